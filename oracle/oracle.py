@@ -1,0 +1,239 @@
+"""ctypes front end of the FP64 CPU oracle (test infrastructure only).
+
+A problem is a plain dict:
+  box         (xmin, xmax, ymin, ymax, zmin, zmax)
+  n           (nx, ny, nz)
+  rho         density, nz*ny*nx values, x fastest
+  kappa, albedo, g         one value per wavelength
+  sources     list of {kind: "point"|"expdisk", pos: (x, y, z), h_r, h_z, lum: [n_lambda]}
+  detectors   list of {distance, incl, azim, pa (degrees), nx, ny, half_x, half_y}
+  n_packages, first_package, seed, w_min, max_scatter, flags
+
+Images come back as an array [comps][n_lambda][sum of ny*nx over frames]
+(comps = 2 with FLAG_SPLIT: direct, scattered).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build_oracle import ensure_built
+
+FLAG_PEEL_EMIT = 1
+FLAG_PEEL_SCAT = 2
+FLAG_ABSORB = 4
+FLAG_SPLIT = 8
+STAT_NAMES = ("emitted", "absorbed", "escaped", "truncated", "x_path", "x_locate", "x_peel", "events", "packages")
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(ensure_built())
+        d, i, u32, u64, i64 = C.c_double, C.c_int, C.c_uint32, C.c_uint64, C.c_int64
+        P = C.c_void_p
+        _lib.oracle_philox.argtypes = [P, P, P]
+        _lib.oracle_uniform.argtypes = [u32]
+        _lib.oracle_uniform.restype = d
+        _lib.oracle_hg_mu.argtypes = [d, d]
+        _lib.oracle_hg_mu.restype = d
+        _lib.oracle_hg_phase.argtypes = [d, d]
+        _lib.oracle_hg_phase.restype = d
+        _lib.oracle_forced_tau.argtypes = [d, d]
+        _lib.oracle_forced_tau.restype = d
+        _lib.oracle_rotate.argtypes = [P, d, d, P]
+        _lib.oracle_emit_position.argtypes = [i, P, P, P]
+        _lib.oracle_emit_direction.argtypes = [P, P]
+        _lib.oracle_detector_basis.argtypes = [P, P]
+        common = [P, P, P, i, P, P, P, i, P, P, P, i, P, P, u64, u64, u64, d, i, C.c_uint]
+        _lib.oracle_run.argtypes = common + [P, P, P, i]
+        _lib.oracle_run.restype = i
+        _lib.oracle_grad.argtypes = common + [P, P, P, P, i]
+        _lib.oracle_grad.restype = i
+        _lib.oracle_reweight.argtypes = [P, P, P, P, i, P, P, P, i, P, P, P, i, P, P, u64, u64, u64, d, i,
+                                         C.c_uint, P, P, i]
+        _lib.oracle_reweight.restype = i
+        _lib.oracle_trace.argtypes = [P, P, P, d, i64, P, P, P, i, P, P, P]
+        _lib.oracle_trace.restype = i64
+        _lib.oracle_peel.argtypes = [P, P, P, d, d, i64, P, P, P, i, P, P, P]
+        _lib.oracle_peel.restype = i
+        _lib.oracle_draw_words.argtypes = [u64, u64, i64, u32, u32, P]
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _i32(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.int32))
+
+
+def philox(counter, key):
+    """Philox4x32-10 of one 128-bit counter under one 64-bit key."""
+    c = np.asarray(counter, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    _load().oracle_philox(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def draw_words(seed, p0, n, lam, c):
+    """Philox words [n][4] of draw c for packages p0..p0+n-1 at wavelength index lam."""
+    out = np.zeros((int(n), 4), dtype=np.uint32)
+    _load().oracle_draw_words(int(seed), int(p0), int(n), int(lam), int(c), _ptr(out))
+    return out
+
+
+def uniform(w):
+    return _load().oracle_uniform(int(w))
+
+
+def hg_mu(g, u):
+    return _load().oracle_hg_mu(float(g), float(u))
+
+
+def hg_phase(g, mu):
+    return _load().oracle_hg_phase(float(g), float(mu))
+
+
+def forced_tau(T, u):
+    return _load().oracle_forced_tau(float(T), float(u))
+
+
+def rotate(k, mu, psi):
+    k = _f64(k)
+    out = np.zeros(3)
+    _load().oracle_rotate(_ptr(k), float(mu), float(psi), _ptr(out))
+    return out
+
+
+def emit_position(kind, par, u):
+    par, u = _f64(par), _f64(u)
+    out = np.zeros(3)
+    _load().oracle_emit_position(int(kind), _ptr(par), _ptr(u), _ptr(out))
+    return out
+
+
+def emit_direction(u):
+    u = _f64(u)
+    out = np.zeros(3)
+    _load().oracle_emit_direction(_ptr(u), _ptr(out))
+    return out
+
+
+def detector_basis(det):
+    par = _f64([det["distance"], det["incl"], det["azim"], det.get("pa", 0.0), det["half_x"], det["half_y"]])
+    out = np.zeros(9)
+    _load().oracle_detector_basis(_ptr(par), _ptr(out))
+    return out[0:3], out[3:6], out[6:9]
+
+
+def _marshal(prob):
+    box = _f64(prob["box"])
+    n = _i32(prob["n"])
+    rho = _f64(prob["rho"]).reshape(-1)
+    assert rho.size == int(n[0]) * int(n[1]) * int(n[2])
+    kappa, albedo, g = _f64(prob["kappa"]), _f64(prob["albedo"]), _f64(prob["g"])
+    nl = kappa.size
+    srcs = prob["sources"]
+    kind = _i32([0 if s["kind"] == "point" else 1 for s in srcs])
+    spar = _f64([[s["pos"][0], s["pos"][1], s["pos"][2], s.get("h_r", 0.0), s.get("h_z", 0.0)] for s in srcs])
+    slum = _f64([np.broadcast_to(np.asarray(s["lum"], dtype=np.float64), (nl,)) for s in srcs])
+    dets = prob["detectors"]
+    dpar = _f64([[d["distance"], d["incl"], d["azim"], d.get("pa", 0.0), d["half_x"], d["half_y"]] for d in dets]
+                if dets else np.zeros((0, 6)))
+    dpix = _i32([[d["nx"], d["ny"]] for d in dets] if dets else np.zeros((0, 2)))
+    npix = int(sum(d["nx"] * d["ny"] for d in dets))
+    keep = (box, n, rho, kappa, albedo, g, kind, spar, slum, dpar, dpix)
+    args = [_ptr(box), _ptr(n), _ptr(rho), nl, _ptr(kappa), _ptr(albedo), _ptr(g), len(srcs), _ptr(kind),
+            _ptr(spar), _ptr(slum), len(dets), _ptr(dpar), _ptr(dpix), int(prob["n_packages"]),
+            int(prob.get("first_package", 0)), int(prob.get("seed", 4357)), float(prob.get("w_min", 1e-4)),
+            int(prob.get("max_scatter", 1000)), int(prob.get("flags", 7))]
+    return args, keep, nl, npix
+
+
+def _comps(prob):
+    return 2 if int(prob.get("flags", 7)) & FLAG_SPLIT else 1
+
+
+def run(prob, threads=1):
+    """Forward run: returns (images[comps][n_lambda][pixels], absorbed[n_lambda][ncell] or None, stats dict)."""
+    args, keep, nl, npix = _marshal(prob)
+    ncell = keep[2].size
+    images = np.zeros((_comps(prob), nl, npix))
+    absorbed = np.zeros((nl, ncell)) if int(prob.get("flags", 7)) & FLAG_ABSORB else None
+    stats = np.zeros(len(STAT_NAMES))
+    rc = _load().oracle_run(*args, _ptr(images), _ptr(absorbed), _ptr(stats), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_run rejected its arguments")
+    return images, absorbed, dict(zip(STAT_NAMES, stats.tolist()))
+
+
+def grad(prob, adj, threads=1):
+    """Detached gradient dL/drho for dL/dI = adj (same layout as the images)."""
+    args, keep, nl, npix = _marshal(prob)
+    ncell = keep[2].size
+    adj = _f64(adj).reshape(_comps(prob), nl, npix)
+    images = np.zeros((_comps(prob), nl, npix))
+    g = np.zeros(ncell)
+    stats = np.zeros(len(STAT_NAMES))
+    rc = _load().oracle_grad(*args, _ptr(adj), _ptr(images), _ptr(g), _ptr(stats), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_grad rejected its arguments")
+    return g, images, dict(zip(STAT_NAMES, stats.tolist()))
+
+
+def reweight(prob, rho_eval, threads=1):
+    """Images of paths sampled at prob['rho'] with weights evaluated at rho_eval."""
+    args, keep, nl, npix = _marshal(prob)
+    rho_eval = _f64(rho_eval).reshape(-1)
+    assert rho_eval.size == keep[2].size
+    images = np.zeros((_comps(prob), nl, npix))
+    stats = np.zeros(len(STAT_NAMES))
+    a = args[:3] + [_ptr(rho_eval)] + args[3:]
+    rc = _load().oracle_reweight(*a, _ptr(images), _ptr(stats), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_reweight rejected its arguments")
+    return images, dict(zip(STAT_NAMES, stats.tolist()))
+
+
+def trace(box, n, rho, kappa, origins, dirs, max_seg=0):
+    """Optical depth along each ray to the grid boundary; with max_seg > 0 also
+    the segment lists.  Returns (tau, total_segments, seg_cell, seg_len, n_seg)."""
+    box, n, rho = _f64(box), _i32(n), _f64(rho).reshape(-1)
+    o, k = _f64(origins).reshape(-1, 3), _f64(dirs).reshape(-1, 3)
+    nr = o.shape[0]
+    tau = np.zeros(nr)
+    nseg = np.zeros(nr, dtype=np.int32)
+    cell = np.zeros((nr, max(max_seg, 1)), dtype=np.int64) if max_seg > 0 else None
+    length = np.zeros((nr, max(max_seg, 1))) if max_seg > 0 else None
+    tot = _load().oracle_trace(_ptr(box), _ptr(n), _ptr(rho), float(kappa), nr, _ptr(o), _ptr(k), _ptr(tau),
+                               int(max_seg), _ptr(cell), _ptr(length), _ptr(nseg))
+    return tau, int(tot), cell, length, nseg
+
+
+def peel(box, n, rho, kappa, g, pos, dir_in, w, detectors):
+    """Peel-off of an event list into the frames of one wavelength (fresh zero images)."""
+    box, n, rho = _f64(box), _i32(n), _f64(rho).reshape(-1)
+    pos = _f64(pos).reshape(-1, 3)
+    din = None if dir_in is None else _f64(dir_in).reshape(-1, 3)
+    w = _f64(w).reshape(-1)
+    dpar = _f64([[d["distance"], d["incl"], d["azim"], d.get("pa", 0.0), d["half_x"], d["half_y"]] for d in detectors])
+    dpix = _i32([[d["nx"], d["ny"]] for d in detectors])
+    images = np.zeros(int(sum(d["nx"] * d["ny"] for d in detectors)))
+    rc = _load().oracle_peel(_ptr(box), _ptr(n), _ptr(rho), float(kappa), float(g), pos.shape[0], _ptr(pos),
+                             _ptr(din), _ptr(w), len(detectors), _ptr(dpar), _ptr(dpix), _ptr(images))
+    if rc != 0:
+        raise ValueError("oracle_peel rejected its arguments")
+    return images
+
+
+def lib_path():
+    return os.path.abspath(ensure_built())

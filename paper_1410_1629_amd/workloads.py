@@ -1,0 +1,301 @@
+"""Seeded synthetic inputs for the photon-package life cycle.
+
+This module only builds inputs: grids, densities, optical properties,
+sources, frames and run options, as plain dicts that both the GPU library
+binding and the CPU oracle accept.  It contains none of the transport
+arithmetic and imports neither side.
+
+Problem dict keys:
+  name, box (xmin, xmax, ymin, ymax, zmin, zmax), n (nx, ny, nz),
+  rho (float64 array [nz, ny, nx]; for precision 1 its values are already
+  float32-representable), kappa / albedo / g (one value per wavelength),
+  sources [{kind, pos, h_r, h_z, lum[n_lambda]}],
+  detectors [{distance, incl, azim, pa, nx, ny, half_x, half_y}],
+  n_packages, first_package, seed, w_min, max_scatter, flags,
+  precision (0: FP64 path; 1: FP32 traversal with FP64 state and tallies).
+
+The five workloads follow the configurations used to measure this path
+(a uniform cube, an edge-on spiral, a multiwavelength disk, a clumpy disk
+and an adjoint problem).  The spiral geometry is the one of the paper's
+worked example (Sect. 2.5: stellar and dust exponential disks, frames at 10
+Mpc); the dust mass is set through the face-on V-band optical depth, which
+is one of the normalisations the paper lists (Sect. 2.2).
+"""
+import numpy as np
+
+FLAG_PEEL_EMIT = 1
+FLAG_PEEL_SCAT = 2
+FLAG_ABSORB = 4
+FLAG_SPLIT = 8
+FLAGS_DEFAULT = FLAG_PEEL_EMIT | FLAG_PEEL_SCAT | FLAG_ABSORB
+
+DEFAULT_SEED = 4357  # the paper's default random seed (Fig. 5)
+
+
+def _centres(lo, hi, n):
+    d = (hi - lo) / n
+    return lo + (np.arange(n) + 0.5) * d
+
+
+def cell_centres(box, n):
+    """Cell-centre coordinates (x, y, z) as broadcastable [nz,ny,nx] arrays."""
+    x = _centres(box[0], box[1], n[0])[None, None, :]
+    y = _centres(box[2], box[3], n[1])[None, :, None]
+    z = _centres(box[4], box[5], n[2])[:, None, None]
+    return x, y, z
+
+
+def exp_disk_density(box, n, rho0, h_r, h_z):
+    """rho0 * exp(-R/h_R - |z|/h_z) sampled at cell centres (float64 [nz,ny,nx])."""
+    x, y, z = cell_centres(box, n)
+    R = np.sqrt(x * x + y * y)
+    return rho0 * np.exp(-R / h_r - np.abs(z) / h_z)
+
+
+def as_f32_values(a):
+    """Rounds to float32 and returns float64 holding exactly those values."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _point(pos=(0.0, 0.0, 0.0), lum=1.0):
+    return {"kind": "point", "pos": tuple(float(v) for v in pos), "h_r": 0.0, "h_z": 0.0, "lum": lum}
+
+
+def _expdisk(h_r, h_z, lum=1.0, pos=(0.0, 0.0, 0.0)):
+    return {"kind": "expdisk", "pos": tuple(float(v) for v in pos), "h_r": float(h_r), "h_z": float(h_z), "lum": lum}
+
+
+def _frame(distance, incl, nx, ny, half_x, half_y, azim=-90.0, pa=0.0):
+    return {"distance": float(distance), "incl": float(incl), "azim": float(azim), "pa": float(pa),
+            "nx": int(nx), "ny": int(ny), "half_x": float(half_x), "half_y": float(half_y)}
+
+
+def _problem(name, box, n, rho, kappa, albedo, g, sources, detectors, n_packages, precision, seed=DEFAULT_SEED,
+             flags=FLAGS_DEFAULT, w_min=1e-4, max_scatter=1000, first_package=0):
+    kappa = np.atleast_1d(np.asarray(kappa, dtype=np.float64))
+    nl = kappa.size
+    for s in sources:
+        s["lum"] = np.broadcast_to(np.asarray(s["lum"], dtype=np.float64), (nl,)).copy()
+    return {"name": name, "box": tuple(float(v) for v in box), "n": tuple(int(v) for v in n),
+            "rho": np.ascontiguousarray(rho, dtype=np.float64), "kappa": kappa,
+            "albedo": np.broadcast_to(np.asarray(albedo, dtype=np.float64), (nl,)).copy(),
+            "g": np.broadcast_to(np.asarray(g, dtype=np.float64), (nl,)).copy(),
+            "sources": sources, "detectors": detectors, "n_packages": int(n_packages),
+            "first_package": int(first_package), "seed": int(seed), "w_min": float(w_min),
+            "max_scatter": int(max_scatter), "flags": int(flags), "precision": int(precision)}
+
+
+def n_pixels(prob):
+    return int(sum(d["nx"] * d["ny"] for d in prob["detectors"]))
+
+
+def split_frames(prob, images_lambda):
+    """Splits one wavelength's flat image block into per-frame [ny, nx] arrays."""
+    out, off = [], 0
+    for d in prob["detectors"]:
+        k = d["nx"] * d["ny"]
+        out.append(np.asarray(images_lambda[off:off + k]).reshape(d["ny"], d["nx"]))
+        off += k
+    return out
+
+
+# --------------------------------------------------------------------------
+# The five measured workloads.
+
+def cube(n_packages=100_000, precision=0, seed=DEFAULT_SEED, flags=FLAGS_DEFAULT):
+    """Uniform cube: 32^3 cells over [-1,1]^3, kappa*rho = 1 (centre-to-edge
+    tau = 1), albedo 0.6, g 0.5, unit point source at the origin, one 64x64
+    frame face-on at distance 10 with half-extent 1."""
+    box, n = (-1, 1, -1, 1, -1, 1), (32, 32, 32)
+    rho = np.ones((32, 32, 32))
+    return _problem("uniform_cube_32", box, n, rho, 1.0, 0.6, 0.5, [_point()],
+                    [_frame(10.0, 0.0, 64, 64, 1.0, 1.0)], n_packages, precision, seed=seed, flags=flags)
+
+
+def spiral(n_packages=10_000_000, precision=1, seed=DEFAULT_SEED, flags=FLAGS_DEFAULT):
+    """Edge-on spiral: stellar exponential disk (h_R 4, h_z 0.4 kpc) and dust
+    exponential disk (h_R 6, h_z 0.25 kpc, face-on V-band tau 1, i.e.
+    kappa*rho0 = tau/(2 h_z) = 2 per kpc) on 256x256x64 cells over
+    +-20 x +-20 x +-2 kpc; albedo 0.6, g 0.6; three 512x512 frames at
+    10 Mpc (1e4 kpc), inclinations 0/60/90 degrees, half-extent 20 kpc."""
+    box, n = (-20, 20, -20, 20, -2, 2), (256, 256, 64)
+    rho = exp_disk_density(box, n, 2.0, 6.0, 0.25)
+    if precision == 1:
+        rho = as_f32_values(rho)
+    dets = [_frame(1e4, inc, 512, 512, 20.0, 20.0) for inc in (0.0, 60.0, 90.0)]
+    return _problem("edge_on_spiral_256x256x64", box, n, rho, 1.0, 0.6, 0.6, [_expdisk(4.0, 0.4)], dets,
+                    n_packages, precision, seed=seed, flags=flags)
+
+
+def multiwavelength(n_packages=1_000_000, precision=1, n_lambda=100, lambdas=None, seed=DEFAULT_SEED,
+                    flags=FLAGS_DEFAULT):
+    """Same disks on 128^3 cells; 100 wavelengths log-spaced 0.1-1000 micron;
+    kappa(lambda) = kappa_V (max(lambda, 0.5)/0.55)^-1.5 (flat below 0.5
+    micron), kappa_V rho0 = 2 per kpc; albedo = g = 0.7 (1 - i/99); unit
+    luminosity per wavelength; one 256x256 edge-on frame.  `lambdas`
+    selects a subset of the wavelength indices."""
+    box, n = (-20, 20, -20, 20, -2, 2), (128, 128, 128)
+    rho = exp_disk_density(box, n, 2.0, 6.0, 0.25)
+    if precision == 1:
+        rho = as_f32_values(rho)
+    i = np.arange(n_lambda, dtype=np.float64)
+    lam = 0.1 * 10.0 ** (4.0 * i / (n_lambda - 1))
+    kappa = (np.maximum(lam, 0.5) / 0.55) ** -1.5
+    alb = 0.7 * (1.0 - i / (n_lambda - 1))
+    if lambdas is not None:
+        sel = np.asarray(lambdas, dtype=np.int64)
+        kappa, alb = kappa[sel], alb[sel]
+    prob = _problem("multiwavelength_128", box, n, rho, kappa, alb, alb.copy(), [_expdisk(4.0, 0.4)],
+                    [_frame(1e4, 90.0, 256, 256, 20.0, 20.0)], n_packages, precision, seed=seed, flags=flags)
+    prob["lambda_um"] = lam if lambdas is None else lam[np.asarray(lambdas)]
+    return prob
+
+
+def clumpy(n_packages=100_000_000, precision=1, n=(512, 512, 512), n_clumps=20_000, seed=DEFAULT_SEED,
+           flags=FLAG_PEEL_EMIT | FLAG_PEEL_SCAT, clump_seed=1):
+    """Clumpy disk: the spiral's dust disk carrying half the mass plus
+    n_clumps Gaussian clumps at uniform random positions in the box (sigma
+    lognormal, median 0.1 kpc, sigma_ln 0.5; equal masses totalling the other
+    half; each clump evaluated at cell centres within 4 sigma and scaled so
+    its cell sum holds its mass); total mass that of the face-on tau 1 disk
+    on this grid; two 1024x1024 frames at 0 and 90 degrees."""
+    box = (-20.0, 20.0, -20.0, 20.0, -2.0, 2.0)
+    smooth = exp_disk_density(box, n, 2.0, 6.0, 0.25)
+    dv = np.prod([(box[2 * a + 1] - box[2 * a]) / n[a] for a in range(3)])
+    mass = smooth.sum() * dv
+    rho = 0.5 * smooth
+    del smooth
+    rng = np.random.default_rng(clump_seed)
+    cen = rng.uniform([box[0], box[2], box[4]], [box[1], box[3], box[5]], size=(n_clumps, 3))
+    sig = 0.1 * np.exp(0.5 * rng.standard_normal(n_clumps))
+    m_clump = 0.5 * mass / n_clumps
+    d = [(box[2 * a + 1] - box[2 * a]) / n[a] for a in range(3)]
+    for c in range(n_clumps):
+        lo_i, hi_i, ax = [], [], []
+        for a in range(3):
+            lo = int(np.floor((cen[c, a] - 4 * sig[c] - box[2 * a]) / d[a]))
+            hi = int(np.floor((cen[c, a] + 4 * sig[c] - box[2 * a]) / d[a])) + 1
+            lo, hi = max(lo, 0), min(hi, n[a])
+            lo_i.append(lo)
+            hi_i.append(hi)
+            x = box[2 * a] + (np.arange(lo, hi) + 0.5) * d[a]
+            ax.append(np.exp(-0.5 * ((x - cen[c, a]) / sig[c]) ** 2))
+        if min(h - l for l, h in zip(lo_i, hi_i)) <= 0:
+            continue
+        blob = ax[2][:, None, None] * ax[1][None, :, None] * ax[0][None, None, :]
+        s = blob.sum() * dv
+        if s <= 0:
+            continue
+        rho[lo_i[2]:hi_i[2], lo_i[1]:hi_i[1], lo_i[0]:hi_i[0]] += blob * (m_clump / s)
+    if precision == 1:
+        rho = as_f32_values(rho)
+    dets = [_frame(1e4, inc, 1024, 1024, 20.0, 20.0) for inc in (0.0, 90.0)]
+    return _problem("clumpy_disk_%dx%dx%d" % tuple(n), box, n, rho, 1.0, 0.6, 0.6, [_expdisk(4.0, 0.4)], dets,
+                    n_packages, precision, seed=seed, flags=flags)
+
+
+def adjoint(n_packages=10_000_000, precision=1, seed=DEFAULT_SEED, n=64, flags=FLAG_PEEL_EMIT | FLAG_PEEL_SCAT):
+    """Adjoint problem: 64^3 cells over [-1,1]^3, rho = exp(z - 1/2) with z
+    i.i.d. standard normal (seed 2), kappa 1, albedo 0.6, g 0.5, unit point
+    source at the origin, one 128x128 face-on frame at distance 10.  The
+    target density is rho * exp(0.1 z') (z' from seed 3); the target image is
+    rendered from it with Philox key 4358."""
+    box, nn = (-1, 1, -1, 1, -1, 1), (n, n, n)
+    z = np.random.default_rng(2).standard_normal((n, n, n))
+    rho = np.exp(z - 0.5)
+    zt = np.random.default_rng(3).standard_normal((n, n, n))
+    rho_t = rho * np.exp(0.1 * zt)
+    if precision == 1:
+        rho, rho_t = as_f32_values(rho), as_f32_values(rho_t)
+    prob = _problem("adjoint_lognormal_%d" % n, box, nn, rho, 1.0, 0.6, 0.5, [_point()],
+                    [_frame(10.0, 0.0, 128, 128, 1.0, 1.0)], n_packages, precision, seed=seed, flags=flags)
+    prob["rho_target"] = rho_t
+    prob["target_seed"] = 4358
+    prob["fd_cells"] = np.random.default_rng(4).choice(n * n * n, size=64, replace=False)
+    return prob
+
+
+CONFIGS = {"cube": cube, "spiral": spiral, "multiwavelength": multiwavelength, "clumpy": clumpy,
+           "adjoint": adjoint}
+
+
+# --------------------------------------------------------------------------
+# Small test inputs.
+
+def small_problem(name="small", n=(8, 8, 8), box=(-1, 1, -1, 1, -1, 1), rho=None, kappa=1.0, albedo=0.6, g=0.5,
+                  sources=None, detectors=None, n_packages=1000, precision=0, seed=DEFAULT_SEED,
+                  flags=FLAGS_DEFAULT, w_min=1e-4, max_scatter=1000, first_package=0):
+    if rho is None:
+        rho = np.ones((n[2], n[1], n[0]))
+    if sources is None:
+        sources = [_point()]
+    if detectors is None:
+        detectors = [_frame(10.0, 0.0, 16, 16, 1.0, 1.0)]
+    return _problem(name, box, n, rho, kappa, albedo, g, sources, detectors, n_packages, precision, seed=seed,
+                    flags=flags, w_min=w_min, max_scatter=max_scatter, first_package=first_package)
+
+
+def lognormal_density(n, sigma_ln=1.0, seed=0, f32=False):
+    z = np.random.default_rng(seed).standard_normal((n[2], n[1], n[0]))
+    rho = np.exp(sigma_ln * z - 0.5 * sigma_ln * sigma_ln)
+    return as_f32_values(rho) if f32 else rho
+
+
+def point(pos=(0.0, 0.0, 0.0), lum=1.0):
+    return _point(pos, lum)
+
+
+def expdisk(h_r, h_z, lum=1.0, pos=(0.0, 0.0, 0.0)):
+    return _expdisk(h_r, h_z, lum, pos)
+
+
+def frame(distance, incl, nx, ny, half_x, half_y, azim=-90.0, pa=0.0):
+    return _frame(distance, incl, nx, ny, half_x, half_y, azim, pa)
+
+
+def random_rays(n_rays, box, seed=0, outside_fraction=0.25, axis_fraction=0.1):
+    """Ray origins and unit directions: most inside the box, some outside it
+    (and aimed roughly at it), some exactly axis-parallel."""
+    rng = np.random.default_rng(seed)
+    lo = np.array([box[0], box[2], box[4]], dtype=np.float64)
+    hi = np.array([box[1], box[3], box[5]], dtype=np.float64)
+    o = rng.uniform(lo, hi, size=(n_rays, 3))
+    mu = rng.uniform(-1, 1, n_rays)
+    ph = rng.uniform(0, 2 * np.pi, n_rays)
+    st = np.sqrt(1 - mu * mu)
+    k = np.stack([st * np.cos(ph), st * np.sin(ph), mu], axis=1)
+    n_out = int(outside_fraction * n_rays)
+    if n_out:
+        c = 0.5 * (lo + hi)
+        span = hi - lo
+        far = c + (rng.uniform(-1, 1, size=(n_out, 3)) * 1.5 * span)
+        tgt = rng.uniform(lo, hi, size=(n_out, 3))
+        dvec = tgt - far
+        o[:n_out] = far
+        k[:n_out] = dvec / np.linalg.norm(dvec, axis=1, keepdims=True)
+    n_ax = int(axis_fraction * n_rays)
+    if n_ax:
+        sl = slice(n_out, n_out + n_ax)
+        axis = rng.integers(0, 3, n_ax)
+        sign = rng.choice([-1.0, 1.0], n_ax)
+        kk = np.zeros((n_ax, 3))
+        kk[np.arange(n_ax), axis] = sign
+        k[sl] = kk
+    return np.ascontiguousarray(o), np.ascontiguousarray(k)
+
+
+def random_events(n_events, box, seed=0, isotropic=False):
+    """Event positions inside the box, incoming unit directions (or None for
+    isotropic emission) and positive weights."""
+    rng = np.random.default_rng(seed)
+    lo = np.array([box[0], box[2], box[4]], dtype=np.float64)
+    hi = np.array([box[1], box[3], box[5]], dtype=np.float64)
+    pos = rng.uniform(lo, hi, size=(n_events, 3))
+    w = rng.uniform(0.1, 1.0, n_events)
+    if isotropic:
+        return np.ascontiguousarray(pos), None, w
+    mu = rng.uniform(-1, 1, n_events)
+    ph = rng.uniform(0, 2 * np.pi, n_events)
+    st = np.sqrt(1 - mu * mu)
+    k = np.stack([st * np.cos(ph), st * np.sin(ph), mu], axis=1)
+    return np.ascontiguousarray(pos), np.ascontiguousarray(k), w
