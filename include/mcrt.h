@@ -1,0 +1,216 @@
+/*
+ * mcrt.h -- C ABI of the MI355X (gfx950) Monte Carlo dust radiative-transfer
+ * library: the photon-package life cycle and its path-replay adjoint.
+ *
+ * Method: Camps & Baes, "SKIRT: an advanced dust radiative transfer code with
+ * a user-friendly architecture" (arXiv:1410.1629).  Sect. 1 names the
+ * techniques (photon packages; peel-off at emission and scattering,
+ * Yusef-Zadeh et al. 1984; continuous absorption, Lucy 1999 and Niccolini et
+ * al. 2003; forced scattering, Cashwell & Everett 1959).  Sect. 2.2 defines
+ * the problem data: a grid of cells with constant density and optical
+ * properties (Table 1(d): regular Cartesian grid), sources with a geometry
+ * and a luminosity per wavelength (Table 1(a): point and exponential disk),
+ * and frame instruments that use parallel projection.  Sect. 2.3 gives the
+ * optical properties: kappa (extinction per unit density), albedo
+ * kappa_sca/kappa_ext and the asymmetry parameter g of the phase function
+ * (Henyey-Greenstein here).  Fig. 4/5 give the instrument parameters and the
+ * package count; Fig. 5 the seeded random generator (default seed 4357).
+ *
+ * Conventions shared by every entry point
+ *  - Cell m = i + nx*(j + ny*k), x fastest.  Cells are half-open along each
+ *    axis; a point on a wall moving towards lower indices belongs to the
+ *    lower cell.
+ *  - Densities live on the device.  precision == MCRT_PREC_FP64: double;
+ *    precision == MCRT_PREC_FP32: float (traversal in FP32, package state
+ *    and every tally in FP64).
+ *  - Images are FP64 flux per pixel (luminosity / distance^2), laid out as
+ *    [comp][lambda][frame pixels], where one wavelength's block is the
+ *    frames one after another, each [ny][nx] row-major; comp is 2 with
+ *    MCRT_SPLIT (0: direct light peeled off at emission, 1: scattered light),
+ *    else 1.
+ *  - Frame geometry: observer direction (sin t cos p, sin t sin p, cos t);
+ *    image axes e_x = (-sin p, cos p, 0), e_y = (-cos t cos p, -cos t sin p,
+ *    sin t), rotated by the position angle; frame [-half_x, half_x] x
+ *    [-half_y, half_y] around the origin; pixels half-open.
+ *  - Random numbers: Philox4x32-10 with key = seed and counter = (package
+ *    index lo, hi, wavelength index, draw index): draw 0 emission position,
+ *    draw 1 emission direction and source choice, draw 2+n scattering n.
+ *    Any package range [first, first + n) therefore reproduces exactly the
+ *    packages of a larger run.
+ *  - Every call is asynchronous on `hip_stream` (a hipStream_t, NULL for the
+ *    default stream) unless it returns statistics, in which case it waits
+ *    for its own work to finish before returning.
+ *  - Ownership: the caller owns every buffer; host structs and arrays are
+ *    read only during the call.  The library keeps no state between calls.
+ *  - Errors: 0 on success; MCRT_EINVAL for invalid arguments (nothing is
+ *    launched), MCRT_EOVERFLOW when a segment buffer was too small,
+ *    MCRT_EHIP for a HIP runtime error.  mcrt_last_error() returns a message
+ *    for the last nonzero return of the calling thread.  No call aborts.
+ */
+#ifndef MCRT_H
+#define MCRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCRT_OK 0
+#define MCRT_EINVAL (-1)
+#define MCRT_EOVERFLOW (-2)
+#define MCRT_EHIP (-3)
+
+#define MCRT_PEEL_EMIT 1u /* peel-off at emission */
+#define MCRT_PEEL_SCAT 2u /* peel-off at every scattering */
+#define MCRT_ABSORB 4u    /* per-cell absorbed-luminosity tally */
+#define MCRT_SPLIT 8u     /* separate direct and scattered images */
+
+#define MCRT_PREC_FP64 0
+#define MCRT_PREC_FP32 1
+
+#define MCRT_SRC_POINT 0
+#define MCRT_SRC_EXPDISK 1
+
+#define MCRT_MAX_SOURCES 8
+#define MCRT_MAX_DETECTORS 8
+#define MCRT_MAX_PACKAGES 20000000000000ULL /* 2e13, the paper's upper bound (Fig. 3) */
+#define MCRT_MAX_SCATTER_LIMIT 1000000
+
+/* Regular Cartesian grid (Table 1(d)): box and cells per axis. */
+typedef struct {
+    double xmin, xmax, ymin, ymax, zmin, zmax;
+    int32_t nx, ny, nz;
+} mcrt_grid;
+
+/* Optical properties per wavelength (Sect. 2.3); host arrays [n_lambda]:
+ * kappa >= 0 (extinction per unit density), 0 <= albedo <= 1, |g| < 1. */
+typedef struct {
+    int32_t n_lambda;
+    const double *kappa, *albedo, *g;
+} mcrt_optics;
+
+/* Source (Table 1(a)): MCRT_SRC_POINT at (x, y, z), or MCRT_SRC_EXPDISK
+ * centred there with density ~ exp(-R/h_r - |z|/h_z), untruncated.
+ * lum: host array [n_lambda] of luminosities >= 0. */
+typedef struct {
+    int32_t kind;
+    double x, y, z, h_r, h_z;
+    const double *lum;
+} mcrt_source;
+
+/* Frame instrument (Fig. 4/5): distance > 0 (enters as 1/distance^2),
+ * inclination, azimuth and position angle in degrees, pixel counts > 0,
+ * half-extents > 0 of the frame. */
+typedef struct {
+    double distance, incl_deg, azim_deg, pa_deg;
+    int32_t nx, ny;
+    double half_x, half_y;
+} mcrt_detector;
+
+/* Run options.  n_packages per wavelength in [1, 2e13]; packages
+ * [first_package, first_package + n_packages) are run; seed is the Philox
+ * key; precision MCRT_PREC_*; a package stops when its weight drops below
+ * w_min times its initial weight or after max_scatter scatterings (the rest
+ * is tallied as truncated); flags MCRT_*.  launch_blocks and event_batch
+ * tune the launch (0 = library choice): blocks per compute unit of the
+ * persistent kernels, and how many lanes of a wavefront wait before the
+ * wavefront processes events. */
+typedef struct {
+    uint64_t n_packages, first_package, seed;
+    int32_t precision;
+    double w_min;
+    int32_t max_scatter;
+    uint32_t flags;
+    int32_t launch_blocks, event_batch;
+} mcrt_opts;
+
+/* Run statistics (FP64 luminosities summed over wavelengths; crossing
+ * counts of positive-length cell segments: pass-1 paths, pass-2 locate
+ * walks, peel-off rays; scattering events; packages; peel-off
+ * contributions that landed in a frame; FP64 read-modify-write deposits into
+ * the per-cell tally: absorbed luminosity forward, gradient in the adjoint).
+ * Crossing counts of the adjoint include both of its walks over each
+ * package.  kernel_ms: duration of the main kernel on the stream, from HIP
+ * events. */
+typedef struct {
+    double emitted, absorbed, escaped, truncated;
+    uint64_t x_path, x_locate, x_peel, events, packages, peels, deposits;
+    double kernel_ms;
+} mcrt_stats;
+
+/* Photon-package life cycle (Sect. 1 techniques, Sect. 2.2 problem data):
+ * for every wavelength and package, emission, peel-off at emission,
+ * then repeated traversal with continuous absorption, forced scattering,
+ * peel-off at scattering and Henyey-Greenstein redirection, until the
+ * weight or scatter limit ends the package.
+ *  rho_dev       device densities [ncell] (double or float, see precision)
+ *  images_dev    device FP64 [comp][n_lambda][frame pixels], overwritten
+ *  absorbed_dev  device FP64 [n_lambda][ncell], overwritten; required with
+ *                MCRT_ABSORB, else ignored (may be NULL)
+ *  stats_host    host mcrt_stats or NULL (non-NULL makes the call wait)
+ * Returns 0 or an MCRT_E* code. */
+int run_photons(const mcrt_grid *grid, const void *rho_dev, const mcrt_optics *optics, int n_src,
+                const mcrt_source *sources, int n_det, const mcrt_detector *detectors, const mcrt_opts *opts,
+                double *images_dev, double *absorbed_dev, mcrt_stats *stats_host, void *hip_stream);
+
+/* Straight-line traversal of the grid (Sect. 2.2: packages move through the
+ * cells), for a batch of rays o + t k, t >= 0, up to the grid boundary.
+ *  origin_dev, dir_dev  device FP64 [n_rays][3]; directions are unit
+ *                        vectors (lengths are in units of t)
+ *  tau_dev              device FP64 [n_rays]: kappa * sum(rho_m * l_m)
+ *  max_seg, seg_cell_dev (int32 [n_rays][max_seg]), seg_len_dev (FP64
+ *    [n_rays][max_seg]), n_seg_dev (int32 [n_rays]): optional segment lists
+ *    (pass NULL to skip); rays with more than max_seg segments store the
+ *    first max_seg, n_seg gets the true count and the call returns
+ *    MCRT_EOVERFLOW after finishing all rays.
+ *  crossings_host       host uint64 or NULL: total segment count (waits)
+ * precision selects the density type and traversal arithmetic. */
+int trace_path(const mcrt_grid *grid, const void *rho_dev, double kappa, int precision, int64_t n_rays,
+               const double *origin_dev, const double *dir_dev, double *tau_dev, int32_t max_seg,
+               int32_t *seg_cell_dev, double *seg_len_dev, int32_t *n_seg_dev, uint64_t *crossings_host,
+               void *hip_stream);
+
+/* Peel-off (Sect. 1, Yusef-Zadeh et al. 1984) of a list of events into
+ * frames of one wavelength: for every event e and frame d whose pixel
+ * contains the projection of pos_e, images[d][pixel] +=
+ *   w_e * phase * exp(-tau(pos_e, k_d)) / distance_d^2,
+ * with phase = 1/(4 pi) when dir_in_dev is NULL (isotropic emission), else
+ * the HG phase function of cos(dir_in_e . k_d) with parameter g.
+ *  pos_dev, dir_in_dev  device FP64 [n_events][3]; w_dev FP64 [n_events]
+ *  images_dev           device FP64 [frame pixels], accumulated (+=) */
+int peel_off(const mcrt_grid *grid, const void *rho_dev, double kappa, double g, int precision, int64_t n_events,
+             const double *pos_dev, const double *dir_in_dev, const double *w_dev, int n_det,
+             const mcrt_detector *detectors, double *images_dev, void *hip_stream);
+
+/* Gradient of an image loss L with respect to every cell density, for the
+ * run that run_photons performs with the same arguments: paths are
+ * re-sampled from the same random numbers (never stored) and the detached
+ * score-function derivative is accumulated,
+ *   dC/drho_m = C [sum_{i<=e} (delta(m, c_i)/rho_m - kappa l_m(leg_i))
+ *                  - kappa l_m(peel ray)],
+ * for every peel-off contribution C of event e, with c_i the cell of
+ * scattering i and leg_i the path from the previous event to it.
+ *  adj_images_dev  device FP64 dL/dI in the image layout of run_photons
+ *  grad_rho_dev    device FP64 [ncell], overwritten with dL/drho
+ *  stats_host      host mcrt_stats or NULL (waits when non-NULL)
+ * The absorbed-luminosity tally has no gradient here; MCRT_ABSORB is
+ * ignored. */
+int backward_density(const mcrt_grid *grid, const void *rho_dev, const mcrt_optics *optics, int n_src,
+                     const mcrt_source *sources, int n_det, const mcrt_detector *detectors, const mcrt_opts *opts,
+                     const double *adj_images_dev, double *grad_rho_dev, mcrt_stats *stats_host,
+                     void *hip_stream);
+
+/* Message for the last nonzero return on the calling thread ("" if none). */
+const char *mcrt_last_error(void);
+
+/* ABI version of this header. */
+int mcrt_abi_version(void);
+
+#define MCRT_ABI_VERSION 1
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCRT_H */

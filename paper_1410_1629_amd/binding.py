@@ -1,0 +1,242 @@
+"""Python binding of the C ABI in include/mcrt.h (argument marshalling only).
+
+Every function here converts Python/torch arguments to the C structs and
+device pointers the library expects and calls the entry point of the same
+name; all work runs in the HIP kernels of libmcrt.so.  Loading fails loudly
+when the library has not been built: there is no fallback.
+
+Problems are the dicts built by `paper_1410_1629_amd.workloads`; device
+buffers are torch tensors on a ROCm device.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcrt.so")
+
+PEEL_EMIT, PEEL_SCAT, ABSORB, SPLIT = 1, 2, 4, 8
+PREC_FP64, PREC_FP32 = 0, 1
+OK, EINVAL, EOVERFLOW, EHIP = 0, -1, -2, -3
+
+
+class McrtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("mcrt error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("xmin", C.c_double), ("xmax", C.c_double), ("ymin", C.c_double), ("ymax", C.c_double),
+                ("zmin", C.c_double), ("zmax", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("nz", C.c_int32)]
+
+
+class Optics(C.Structure):
+    _fields_ = [("n_lambda", C.c_int32), ("kappa", C.POINTER(C.c_double)), ("albedo", C.POINTER(C.c_double)),
+                ("g", C.POINTER(C.c_double))]
+
+
+class Source(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("x", C.c_double), ("y", C.c_double), ("z", C.c_double),
+                ("h_r", C.c_double), ("h_z", C.c_double), ("lum", C.POINTER(C.c_double))]
+
+
+class Detector(C.Structure):
+    _fields_ = [("distance", C.c_double), ("incl_deg", C.c_double), ("azim_deg", C.c_double),
+                ("pa_deg", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32), ("half_x", C.c_double),
+                ("half_y", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("n_packages", C.c_uint64), ("first_package", C.c_uint64), ("seed", C.c_uint64),
+                ("precision", C.c_int32), ("w_min", C.c_double), ("max_scatter", C.c_int32),
+                ("flags", C.c_uint32), ("launch_blocks", C.c_int32), ("event_batch", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("emitted", C.c_double), ("absorbed", C.c_double), ("escaped", C.c_double),
+                ("truncated", C.c_double), ("x_path", C.c_uint64), ("x_locate", C.c_uint64),
+                ("x_peel", C.c_uint64), ("events", C.c_uint64), ("packages", C.c_uint64),
+                ("peels", C.c_uint64), ("deposits", C.c_uint64), ("kernel_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+# Exported symbols of include/mcrt.h.
+SYMBOLS = ("run_photons", "trace_path", "peel_off", "backward_density", "mcrt_last_error", "mcrt_abi_version")
+
+
+def load():
+    """Loads libmcrt.so (raises if it is missing: build it with build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmcrt.so is not built (%s); run `python -m paper_1410_1629_amd.build` or "
+                           "__graft_entry__.build()" % LIB_PATH)
+    lib = C.CDLL(LIB_PATH)
+    P, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    lib.run_photons.argtypes = [C.POINTER(Grid), P, C.POINTER(Optics), C.c_int, C.POINTER(Source), C.c_int,
+                                C.POINTER(Detector), C.POINTER(Opts), P, P, C.POINTER(Stats), P]
+    lib.run_photons.restype = C.c_int
+    lib.backward_density.argtypes = [C.POINTER(Grid), P, C.POINTER(Optics), C.c_int, C.POINTER(Source), C.c_int,
+                                     C.POINTER(Detector), C.POINTER(Opts), P, P, C.POINTER(Stats), P]
+    lib.backward_density.restype = C.c_int
+    lib.trace_path.argtypes = [C.POINTER(Grid), P, d, C.c_int, i64, P, P, P, i32, P, P, P,
+                               C.POINTER(C.c_uint64), P]
+    lib.trace_path.restype = C.c_int
+    lib.peel_off.argtypes = [C.POINTER(Grid), P, d, d, C.c_int, i64, P, P, P, C.c_int, C.POINTER(Detector), P, P]
+    lib.peel_off.restype = C.c_int
+    lib.mcrt_last_error.argtypes = []
+    lib.mcrt_last_error.restype = C.c_char_p
+    lib.mcrt_abi_version.argtypes = []
+    lib.mcrt_abi_version.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise McrtError(rc, load().mcrt_last_error().decode())
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_grid(prob):
+    b, n = prob["box"], prob["n"]
+    return Grid(b[0], b[1], b[2], b[3], b[4], b[5], n[0], n[1], n[2])
+
+
+def make_detectors(dets):
+    arr = (Detector * max(len(dets), 1))()
+    for i, d in enumerate(dets):
+        arr[i] = Detector(d["distance"], d["incl"], d["azim"], d.get("pa", 0.0), d["nx"], d["ny"], d["half_x"],
+                          d["half_y"])
+    return arr
+
+
+class _Problem:
+    """C views of a problem dict; keeps the host arrays alive."""
+
+    def __init__(self, prob, **overrides):
+        self.grid = make_grid(prob)
+        self.kappa = np.ascontiguousarray(prob["kappa"], dtype=np.float64)
+        self.albedo = np.ascontiguousarray(prob["albedo"], dtype=np.float64)
+        self.g = np.ascontiguousarray(prob["g"], dtype=np.float64)
+        dp = C.POINTER(C.c_double)
+        self.optics = Optics(self.kappa.size, self.kappa.ctypes.data_as(dp), self.albedo.ctypes.data_as(dp),
+                             self.g.ctypes.data_as(dp))
+        srcs = prob["sources"]
+        self.lums = [np.ascontiguousarray(np.broadcast_to(np.asarray(s["lum"], dtype=np.float64),
+                                                          (self.kappa.size,))) for s in srcs]
+        self.sources = (Source * len(srcs))()
+        for i, s in enumerate(srcs):
+            self.sources[i] = Source(0 if s["kind"] == "point" else 1, s["pos"][0], s["pos"][1], s["pos"][2],
+                                     s.get("h_r", 0.0), s.get("h_z", 0.0), self.lums[i].ctypes.data_as(dp))
+        self.n_src = len(srcs)
+        self.detectors = make_detectors(prob["detectors"])
+        self.n_det = len(prob["detectors"])
+        o = dict(n_packages=prob["n_packages"], first_package=prob.get("first_package", 0),
+                 seed=prob.get("seed", 4357), precision=prob.get("precision", 0), w_min=prob.get("w_min", 1e-4),
+                 max_scatter=prob.get("max_scatter", 1000), flags=prob.get("flags", 7), launch_blocks=0,
+                 event_batch=0)
+        o.update(overrides)
+        self.opts = Opts(int(o["n_packages"]), int(o["first_package"]), int(o["seed"]), int(o["precision"]),
+                         float(o["w_min"]), int(o["max_scatter"]), int(o["flags"]), int(o["launch_blocks"]),
+                         int(o["event_batch"]))
+
+
+def image_shape(prob):
+    comps = 2 if prob.get("flags", 7) & SPLIT else 1
+    npix = int(sum(d["nx"] * d["ny"] for d in prob["detectors"]))
+    return (comps, len(np.atleast_1d(prob["kappa"])), npix)
+
+
+def density_tensor(prob, device="cuda"):
+    """The problem's density as a device tensor of the precision's type."""
+    import torch
+    dt = torch.float32 if prob.get("precision", 0) == PREC_FP32 else torch.float64
+    return torch.as_tensor(np.ascontiguousarray(prob["rho"]).reshape(-1), dtype=dt).to(device)
+
+
+def run_photons(prob, rho, images, absorbed=None, stats=True, stream=None, **overrides):
+    """run_photons over the problem dict.  rho, images, absorbed: device
+    tensors (images [comps][n_lambda][pixels] FP64, absorbed [n_lambda][ncell]
+    FP64).  Returns the statistics dict (stats=True waits for the kernel)."""
+    lib = load()
+    pr = _Problem(prob, **overrides)
+    st = Stats()
+    _check(lib.run_photons(C.byref(pr.grid), _ptr(rho), C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det,
+                           pr.detectors, C.byref(pr.opts), _ptr(images), _ptr(absorbed),
+                           C.byref(st) if stats else None, _stream(stream)))
+    return st.as_dict() if stats else None
+
+
+def backward_density(prob, rho, adj_images, grad_rho, stats=True, stream=None, **overrides):
+    """backward_density: grad_rho (device FP64 [ncell]) = dL/drho for
+    dL/dI = adj_images (device FP64, image layout of run_photons)."""
+    lib = load()
+    pr = _Problem(prob, **overrides)
+    st = Stats()
+    _check(lib.backward_density(C.byref(pr.grid), _ptr(rho), C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det,
+                                pr.detectors, C.byref(pr.opts), _ptr(adj_images), _ptr(grad_rho),
+                                C.byref(st) if stats else None, _stream(stream)))
+    return st.as_dict() if stats else None
+
+
+def trace_path(grid, rho, kappa, precision, origins, dirs, tau, max_seg=0, seg_cell=None, seg_len=None,
+               n_seg=None, crossings=True, stream=None):
+    """trace_path for device tensors origins/dirs [n][3] FP64 and tau [n]
+    FP64; optional segment lists.  Returns the total crossing count (or
+    None).  `grid` is a problem dict or a Grid."""
+    lib = load()
+    g = grid if isinstance(grid, Grid) else make_grid(grid)
+    n = int(origins.shape[0]) if origins is not None else 0
+    c = C.c_uint64(0)
+    _check(lib.trace_path(C.byref(g), _ptr(rho), float(kappa), int(precision), n, _ptr(origins), _ptr(dirs),
+                          _ptr(tau), int(max_seg), _ptr(seg_cell), _ptr(seg_len), _ptr(n_seg),
+                          C.byref(c) if crossings else None, _stream(stream)))
+    return c.value if crossings else None
+
+
+def peel_off(grid, rho, kappa, g, precision, pos, dir_in, w, detectors, images, stream=None):
+    """peel_off of events (device pos [n][3], dir_in [n][3] or None, w [n])
+    into images (device FP64, frames of one wavelength, accumulated)."""
+    lib = load()
+    gr = grid if isinstance(grid, Grid) else make_grid(grid)
+    dets = make_detectors(detectors)
+    n = int(pos.shape[0]) if pos is not None else 0
+    _check(lib.peel_off(C.byref(gr), _ptr(rho), float(kappa), float(g), int(precision), n, _ptr(pos),
+                        _ptr(dir_in), _ptr(w), len(detectors), dets, _ptr(images), _stream(stream)))
+
+
+def render(prob, device="cuda", rho=None, **overrides):
+    """Allocates outputs and runs the problem: (images, absorbed or None, stats)."""
+    import torch
+    rho = density_tensor(prob, device) if rho is None else rho
+    images = torch.empty(image_shape(prob), dtype=torch.float64, device=device)
+    absorbed = None
+    if prob.get("flags", 7) & ABSORB:
+        absorbed = torch.empty((len(np.atleast_1d(prob["kappa"])), rho.numel()), dtype=torch.float64, device=device)
+    st = run_photons(prob, rho, images, absorbed, **overrides)
+    return images, absorbed, st

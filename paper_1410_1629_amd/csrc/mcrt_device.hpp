@@ -1,0 +1,340 @@
+// mcrt_device.hpp -- lane-level primitives of the photon-package life cycle:
+// counter-based random numbers, the grid walk, sources, the Henyey-Greenstein
+// phase function and the frame projection.
+//
+// Method: Camps & Baes (arXiv:1410.1629).  Sect. 1 names the techniques
+// (photon packages, peel-off, continuous absorption, forced scattering);
+// Sect. 2.2 the grid of constant-property cells, the geometries and the
+// frame instruments with parallel projection; Sect. 2.3 the optical
+// properties and the asymmetry parameter g; Fig. 5 the seeded generator.
+//
+// Precision model.  Package state (position, direction, weight), event
+// sampling and all tallies are FP64.  The walk through the cells -- the
+// per-crossing work -- runs in the type R: double for the FP64 path, float
+// for the FP32 path.  Crossing times are computed per plane from the first
+// plane ahead (t = t0 + j * dt with an integer count j), never accumulated,
+// and the interaction point of forced scattering is recomputed in FP64 from
+// the entry plane of its cell, so FP32 error stays relative to one cell.
+//
+// Everything here is per lane and compiles for host and device (MCRT_HD):
+// the kernels run it on gfx950, and the CPU test harness runs the same code
+// with bounds-checked memory accessors.  Memory is reached only through an
+// accessor object `M` (M.rho(cell) for densities).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#define MCRT_HD __host__ __device__ __forceinline__
+
+namespace mcrt {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxSrc = 8;
+constexpr int kMaxDet = 8;
+// Direction components below this magnitude are treated as parallel to the
+// axis: the ray would need more than 1e20 lengths to reach the next plane,
+// and FP32 crossing times stay finite for any grid up to 1e15 lengths.
+constexpr double kParallel = 1e-20;
+
+// ---------------------------------------------------------------------------
+// Problem data, prepared by the host in FP64.
+
+struct GridDev {
+  double lo[3], hi[3], d[3];
+  int n[3];
+  int stride[3];  // 1, nx, nx*ny
+  int ncell;
+};
+
+struct DetDev {
+  double kd[3], ex[3], ey[3];  // towards the observer; image axes
+  double inv_d2, half_x, half_y, dpx, dpy;
+  int nx, ny;
+  long long off;  // offset of this frame inside one wavelength's image block
+};
+
+struct SrcDev {
+  int kind;  // 0 point, 1 exponential disk
+  double c[3], hr, hz;
+};
+
+struct LamDev {
+  double kappa, albedo, g, w0, ltot;
+  double cum[kMaxSrc];  // cumulative luminosity over sources
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies and xors under a Weyl-incremented 64-bit key.
+
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+MCRT_HD U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = U4{(uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Words of draw number `c` of package p at wavelength index l.
+MCRT_HD U4 draw_words(uint64_t seed, uint64_t p, uint32_t l, uint32_t c) {
+  return philox4x32_10(U4{(uint32_t)p, (uint32_t)(p >> 32), l, c}, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// Uniform deviate strictly inside (0,1): (w + 1/2) 2^-32, exact in FP64.
+MCRT_HD double u01(uint32_t w) { return ((double)w + 0.5) * 2.3283064365386963e-10; }
+
+MCRT_HD void sincos2pi(double u, double* s, double* c) {
+  const double a = 2.0 * kPi * u;
+  *s = sin(a);
+  *c = cos(a);
+}
+
+// ---------------------------------------------------------------------------
+// Henyey-Greenstein phase function and sampling (g sets the phase function,
+// Sect. 2.3), normalised to 1 over the sphere.
+
+MCRT_HD double hg_phase(double g, double mu) {
+  const double x = 1.0 + g * g - 2.0 * g * mu;
+  return (1.0 - g * g) / (4.0 * kPi * x * sqrt(x));
+}
+
+MCRT_HD double hg_sample_mu(double g, double u) {
+  if (fabs(g) < 1e-6) return 2.0 * u - 1.0;
+  const double f = (1.0 - g * g) / (1.0 - g + 2.0 * g * u);
+  const double mu = (1.0 + g * g - f * f) / (2.0 * g);
+  return fmin(1.0, fmax(-1.0, mu));
+}
+
+// Direction at polar cosine mu and azimuth 2 pi u about k, in the
+// branch-free orthonormal basis of Duff et al. (JCGT 2017), renormalised.
+MCRT_HD void turn(double k[3], double mu, double u) {
+  const double s = k[2] >= 0.0 ? 1.0 : -1.0;
+  const double a = -1.0 / (s + k[2]);
+  const double b = k[0] * k[1] * a;
+  const double b1x = 1.0 + s * k[0] * k[0] * a, b1y = s * b, b1z = -s * k[0];
+  const double b2x = b, b2y = s + k[1] * k[1] * a, b2z = -k[1];
+  const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+  double sp, cp;
+  sincos2pi(u, &sp, &cp);
+  const double nx = st * (cp * b1x + sp * b2x) + mu * k[0];
+  const double ny = st * (cp * b1y + sp * b2y) + mu * k[1];
+  const double nz = st * (cp * b1z + sp * b2z) + mu * k[2];
+  const double inv = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
+  k[0] = nx * inv;
+  k[1] = ny * inv;
+  k[2] = nz * inv;
+}
+
+// ---------------------------------------------------------------------------
+// Emission (Table 1(a)): isotropic direction; point or exponential-disk
+// position (R ~ Gamma(2, h_R) from the area element, azimuth uniform, z
+// Laplace with scale h_z).
+
+MCRT_HD void iso_direction(double u0, double u1, double k[3]) {
+  const double mu = 2.0 * u0 - 1.0;
+  const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+  double sp, cp;
+  sincos2pi(u1, &sp, &cp);
+  k[0] = st * cp;
+  k[1] = st * sp;
+  k[2] = mu;
+}
+
+MCRT_HD void source_position(const SrcDev& S, const U4& w, double r[3]) {
+  r[0] = S.c[0];
+  r[1] = S.c[1];
+  r[2] = S.c[2];
+  if (S.kind == 1) {
+    const double u0 = u01(w.x), u1 = u01(w.y), u2 = u01(w.z), u3 = u01(w.w);
+    const double R = -S.hr * log(u0 * u1);
+    double sp, cp;
+    sincos2pi(u2, &sp, &cp);
+    const double z = u3 < 0.5 ? S.hz * log(2.0 * u3) : -S.hz * log(2.0 * (1.0 - u3));
+    r[0] += R * cp;
+    r[1] += R * sp;
+    r[2] += z;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Frame projection (parallel projection, Sect. 2.2): pixel index of r, or -1.
+
+MCRT_HD int frame_pixel(const DetDev& D, const double r[3]) {
+  const double xp = r[0] * D.ex[0] + r[1] * D.ex[1] + r[2] * D.ex[2];
+  const double yp = r[0] * D.ey[0] + r[1] * D.ey[1] + r[2] * D.ey[2];
+  const double fx = floor((xp + D.half_x) / D.dpx);
+  const double fy = floor((yp + D.half_y) / D.dpy);
+  if (!(fx >= 0.0 && fx < (double)D.nx && fy >= 0.0 && fy < (double)D.ny)) return -1;
+  return (int)fy * D.nx + (int)fx;
+}
+
+// ---------------------------------------------------------------------------
+// Grid walk (Amanatides & Woo 1987) in precision R.
+//
+// Times t of the walk are measured from the point where the ray enters the
+// grid (its origin if that lies inside), so their FP32 rounding is relative
+// to the chord, not to the distance from a far origin; `tin` is that entry
+// time in the original parametrisation.  Along each non-parallel axis a,
+// t0[a] is the crossing time of the first plane ahead of the entry point and
+// dt[a] the time between planes, so after j[a] crossings along a the next
+// plane is reached at t = t0[a] + j[a] * dt[a] -- one rounding of a product
+// and a sum, no accumulation and no cancellation against a far anchor.
+// lim[a] is the number of planes ahead before the plane where the ray
+// leaves the grid along a: the walk ends as soon as some j[a] exceeds
+// lim[a], and while every j[a] <= lim[a] the cell is inside the grid.
+// Axes parallel to the ray have t0 = +inf, dt = 0, step 0 and a limit that
+// is never reached.  The current cell is `cell`; its density is prefetched
+// into rho_cur.
+
+template <typename R>
+struct Ray {
+  R t0[3], dt[3];
+  int j[3], lim[3], step[3];
+  int cell;
+  R t, tau, rho_cur;
+  double tin;  // FP64 entry time (0 for rays starting inside)
+  bool active;
+};
+
+MCRT_HD float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
+MCRT_HD double fmaR(double a, double b, double c) { return fma(a, b, c); }
+MCRT_HD int imax3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
+
+// Sets up the walk of o + t k (t >= 0): slab entry for origins outside the
+// grid; cell indices by floor with the lower cell for a coordinate on a wall
+// while moving down; rays missing the grid (or with non-finite data) are
+// left inactive with tau = 0.
+template <typename R, class Mem>
+MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, Mem& M, const double o[3], const double k[3]) {
+  double tin = 0.0, tout = INFINITY;
+  int entry = -1;
+  bool miss = !(std::isfinite(o[0]) && std::isfinite(o[1]) && std::isfinite(o[2]) && std::isfinite(k[0]) &&
+                std::isfinite(k[1]) && std::isfinite(k[2]));
+  bool par[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    par[a] = !(fabs(k[a]) >= kParallel);
+    if (par[a]) {
+      if (!(o[a] >= G.lo[a] && o[a] < G.hi[a])) miss = true;
+    } else {
+      const double ta = (G.lo[a] - o[a]) / k[a];
+      const double tb = (G.hi[a] - o[a]) / k[a];
+      const double tn = fmin(ta, tb), tf = fmax(ta, tb);
+      if (tn > tin) {
+        tin = tn;
+        entry = a;
+      }
+      tout = fmin(tout, tf);
+    }
+  }
+  if (par[0] && par[1] && par[2]) miss = true;
+  if (miss || !(tin < tout)) {
+    ry.active = false;
+    ry.tau = R(0);
+    ry.t = R(0);
+    ry.tin = 0.0;
+    return;
+  }
+  int cell = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int i;
+    if (a == entry) {
+      i = k[a] > 0.0 ? 0 : G.n[a] - 1;
+    } else {
+      const double p = o[a] + tin * k[a];
+      const double x = (p - G.lo[a]) / G.d[a];
+      const double fx = floor(x);
+      i = (int)fmin(fmax(fx, -1.0), (double)G.n[a]);
+      if (!par[a] && k[a] < 0.0 && x == fx) i -= 1;
+      i = i < 0 ? 0 : (i > G.n[a] - 1 ? G.n[a] - 1 : i);
+    }
+    cell += i * G.stride[a];
+    ry.j[a] = 0;
+    if (par[a]) {
+      ry.t0[a] = R(INFINITY);
+      ry.dt[a] = R(0);
+      ry.lim[a] = 1 << 30;
+      ry.step[a] = 0;
+    } else if (k[a] > 0.0) {
+      ry.t0[a] = (R)((G.lo[a] + (double)(i + 1) * G.d[a] - o[a]) / k[a] - tin);
+      ry.dt[a] = (R)(G.d[a] / k[a]);
+      ry.lim[a] = G.n[a] - 1 - i;
+      ry.step[a] = G.stride[a];
+    } else {
+      ry.t0[a] = (R)((G.lo[a] + (double)i * G.d[a] - o[a]) / k[a] - tin);
+      ry.dt[a] = (R)(-G.d[a] / k[a]);
+      ry.lim[a] = i;
+      ry.step[a] = -G.stride[a];
+    }
+  }
+  ry.cell = cell;
+  ry.t = R(0);
+  ry.tin = tin;
+  ry.tau = R(0);
+  ry.rho_cur = M.rho(cell);
+  ry.active = true;
+}
+
+// Crossing time of the next plane ahead along axis a.
+template <typename R>
+MCRT_HD R ray_tplane(const Ray<R>& ry, int a) {
+  return fmaR((R)ry.j[a], ry.dt[a], ry.t0[a]);
+}
+
+// End time of the current segment (the nearest plane ahead).
+template <typename R>
+MCRT_HD R ray_tnext(const Ray<R>& ry) {
+  return fmin(ray_tplane(ry, 0), fmin(ray_tplane(ry, 1), ray_tplane(ry, 2)));
+}
+
+// Moves into the next cell (all axes whose plane is reached at tm advance
+// together); returns true when the walk has left the grid, which is when
+// some axis has crossed more planes than it had ahead inside the grid, or
+// when no axis matched tm (non-finite times).  Prefetches the density of the
+// new cell (of the old one again when leaving, so no load leaves the grid).
+template <typename R, class Mem>
+MCRT_HD bool ray_advance(Ray<R>& ry, R tm, Mem& M) {
+  const bool ax = ray_tplane(ry, 0) == tm;
+  const bool ay = ray_tplane(ry, 1) == tm;
+  const bool az = ray_tplane(ry, 2) == tm;
+  const int old = ry.cell;
+  ry.cell += (ax ? ry.step[0] : 0) + (ay ? ry.step[1] : 0) + (az ? ry.step[2] : 0);
+  ry.j[0] += ax;
+  ry.j[1] += ay;
+  ry.j[2] += az;
+  const bool out = imax3(ry.j[0] - ry.lim[0], ry.j[1] - ry.lim[1], ry.j[2] - ry.lim[2]) > 0 || !(ax || ay || az);
+  ry.rho_cur = M.rho(out ? old : ry.cell);
+  return out;
+}
+
+// FP64 entry time of the current cell, in the original parametrisation of
+// the ray: the latest plane already crossed, or the ray's entry time.  The
+// plane index follows from the crossing count: moving up from start index
+// i0 = n - 1 - lim the last plane crossed is i0 + j; moving down from
+// i0 = lim it is i0 + 1 - j.
+template <typename R>
+MCRT_HD double ray_cell_entry64(const Ray<R>& ry, const GridDev& G, const double o[3], const double k[3]) {
+  double t = ry.tin;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (ry.step[a] == 0 || ry.j[a] == 0) continue;
+    const int p = k[a] > 0.0 ? G.n[a] - 1 - ry.lim[a] + ry.j[a] : ry.lim[a] + 1 - ry.j[a];
+    const double tl = (G.lo[a] + (double)p * G.d[a] - o[a]) / k[a];
+    t = fmax(t, tl);
+  }
+  return t;
+}
+
+}  // namespace mcrt

@@ -1,0 +1,262 @@
+// mcrt_host.hpp -- host-side argument checks and problem tables of the C ABI
+// (include/mcrt.h): grid, frames (observer direction and image axes,
+// Sect. 2.2 / Fig. 4-5), per-wavelength optics and source luminosities
+// (Sect. 2.2-2.3).  No HIP runtime calls: the CPU test harness uses the same
+// preparation as the library.
+#pragma once
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mcrt.h"
+#include "mcrt_lane.hpp"
+
+namespace mcrt {
+namespace host {
+
+inline std::string& last_error() {
+  static thread_local std::string e;
+  return e;
+}
+
+inline int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  last_error() = buf;
+  return code;
+}
+
+inline bool finite(double v) { return std::isfinite(v); }
+
+inline int check_grid(const mcrt_grid* g) {
+  if (!g) return fail(MCRT_EINVAL, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(MCRT_EINVAL, "grid cell counts must be >= 1");
+  if ((long long)g->nx * g->ny * g->nz >= (1ll << 31))
+    return fail(MCRT_EINVAL, "grid has %lld cells; at most 2^31 - 1 are supported",
+                (long long)g->nx * g->ny * g->nz);
+  const double b[6] = {g->xmin, g->xmax, g->ymin, g->ymax, g->zmin, g->zmax};
+  for (int a = 0; a < 3; ++a)
+    if (!finite(b[2 * a]) || !finite(b[2 * a + 1]) || !(b[2 * a + 1] > b[2 * a]))
+      return fail(MCRT_EINVAL, "grid extent along axis %d must be finite and increasing", a);
+  return 0;
+}
+
+inline GridDev make_grid(const mcrt_grid& g) {
+  GridDev G;
+  const double b[6] = {g.xmin, g.xmax, g.ymin, g.ymax, g.zmin, g.zmax};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < 3; ++a) {
+    G.lo[a] = b[2 * a];
+    G.hi[a] = b[2 * a + 1];
+    G.n[a] = n[a];
+    G.d[a] = (G.hi[a] - G.lo[a]) / n[a];
+  }
+  G.stride[0] = 1;
+  G.stride[1] = g.nx;
+  G.stride[2] = g.nx * g.ny;
+  G.ncell = g.nx * g.ny * g.nz;
+  return G;
+}
+
+inline int check_detectors(int n_det, const mcrt_detector* dets, bool allow_zero) {
+  if (n_det < (allow_zero ? 0 : 1) || n_det > MCRT_MAX_DETECTORS)
+    return fail(MCRT_EINVAL, "n_det = %d outside [%d, %d]", n_det, allow_zero ? 0 : 1, MCRT_MAX_DETECTORS);
+  if (n_det > 0 && !dets) return fail(MCRT_EINVAL, "detectors is NULL");
+  for (int d = 0; d < n_det; ++d) {
+    const mcrt_detector& D = dets[d];
+    if (!(D.distance > 0.0) || !finite(D.distance)) return fail(MCRT_EINVAL, "detector %d: distance must be > 0", d);
+    if (!finite(D.incl_deg) || !finite(D.azim_deg) || !finite(D.pa_deg))
+      return fail(MCRT_EINVAL, "detector %d: angles must be finite", d);
+    if (D.nx < 1 || D.ny < 1 || (long long)D.nx * D.ny > (1ll << 30))
+      return fail(MCRT_EINVAL, "detector %d: pixel counts must be >= 1 (at most 2^30 pixels)", d);
+    if (!(D.half_x > 0.0) || !(D.half_y > 0.0) || !finite(D.half_x) || !finite(D.half_y))
+      return fail(MCRT_EINVAL, "detector %d: half-extents must be > 0", d);
+  }
+  return 0;
+}
+
+// Observer direction k_d = (sin t cos p, sin t sin p, cos t), image axes
+// e_x = (-sin p, cos p, 0), e_y = (-cos t cos p, -cos t sin p, sin t)
+// rotated in the image plane by the position angle, pixel sizes.
+inline DetDev make_det(const mcrt_detector& D, long long off) {
+  DetDev R;
+  const double th = D.incl_deg * (kPi / 180.0), ph = D.azim_deg * (kPi / 180.0), om = D.pa_deg * (kPi / 180.0);
+  const double st = std::sin(th), ct = std::cos(th), sp = std::sin(ph), cp = std::cos(ph);
+  const double so = std::sin(om), co = std::cos(om);
+  const double kd[3] = {st * cp, st * sp, ct};
+  const double ex[3] = {-sp, cp, 0.0};
+  const double ey[3] = {-ct * cp, -ct * sp, st};
+  for (int a = 0; a < 3; ++a) {
+    R.kd[a] = kd[a];
+    R.ex[a] = co * ex[a] + so * ey[a];
+    R.ey[a] = -so * ex[a] + co * ey[a];
+  }
+  R.inv_d2 = 1.0 / (D.distance * D.distance);
+  R.half_x = D.half_x;
+  R.half_y = D.half_y;
+  R.dpx = 2.0 * D.half_x / D.nx;
+  R.dpy = 2.0 * D.half_y / D.ny;
+  R.nx = D.nx;
+  R.ny = D.ny;
+  R.off = off;
+  return R;
+}
+
+// Checked run description of run_photons / backward_density.
+struct Prepared {
+  RunParams P;
+  std::vector<LamDev> lam;
+  std::vector<DetDev> det;
+  std::vector<SrcDev> src;
+  long long n_images = 0;  // comps * n_lambda * pixels of all frames
+  double emitted = 0.0;    // sum over wavelengths of n_packages * w0
+};
+
+inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
+                   const mcrt_source* sources, int n_det, const mcrt_detector* detectors, const mcrt_opts* opts,
+                   Prepared& out) {
+  if (int e = check_grid(grid)) return e;
+  if (!rho_dev) return fail(MCRT_EINVAL, "rho_dev is NULL");
+  if (!optics || !optics->kappa || !optics->albedo || !optics->g) return fail(MCRT_EINVAL, "optics incomplete");
+  const int nl = optics->n_lambda;
+  if (nl < 1 || nl > (1 << 20)) return fail(MCRT_EINVAL, "n_lambda = %d outside [1, 2^20]", nl);
+  for (int l = 0; l < nl; ++l) {
+    const double ka = optics->kappa[l], al = optics->albedo[l], gg = optics->g[l];
+    if (!(ka >= 0.0) || !finite(ka)) return fail(MCRT_EINVAL, "kappa[%d] must be finite and >= 0", l);
+    if (!(al >= 0.0 && al <= 1.0)) return fail(MCRT_EINVAL, "albedo[%d] must lie in [0, 1]", l);
+    if (!(std::fabs(gg) < 1.0)) return fail(MCRT_EINVAL, "|g[%d]| must be < 1", l);
+  }
+  if (n_src < 1 || n_src > MCRT_MAX_SOURCES)
+    return fail(MCRT_EINVAL, "n_src = %d outside [1, %d]", n_src, MCRT_MAX_SOURCES);
+  if (!sources) return fail(MCRT_EINVAL, "sources is NULL");
+  for (int s = 0; s < n_src; ++s) {
+    const mcrt_source& S = sources[s];
+    if (S.kind != MCRT_SRC_POINT && S.kind != MCRT_SRC_EXPDISK)
+      return fail(MCRT_EINVAL, "source %d: unknown kind %d", s, S.kind);
+    if (!finite(S.x) || !finite(S.y) || !finite(S.z)) return fail(MCRT_EINVAL, "source %d: position must be finite", s);
+    if (S.kind == MCRT_SRC_EXPDISK && (!(S.h_r > 0.0) || !(S.h_z > 0.0) || !finite(S.h_r) || !finite(S.h_z)))
+      return fail(MCRT_EINVAL, "source %d: scale lengths must be > 0", s);
+    if (!S.lum) return fail(MCRT_EINVAL, "source %d: lum is NULL", s);
+    for (int l = 0; l < nl; ++l)
+      if (!(S.lum[l] >= 0.0) || !finite(S.lum[l])) return fail(MCRT_EINVAL, "source %d: lum[%d] must be >= 0", s, l);
+  }
+  if (int e = check_detectors(n_det, detectors, true)) return e;
+  if (!opts) return fail(MCRT_EINVAL, "opts is NULL");
+  if (opts->n_packages < 1 || opts->n_packages > MCRT_MAX_PACKAGES)
+    return fail(MCRT_EINVAL, "n_packages must lie in [1, 2e13]");
+  if (opts->first_package > (1ull << 62)) return fail(MCRT_EINVAL, "first_package too large");
+  if (opts->n_packages * (unsigned long long)nl > (1ull << 62)) return fail(MCRT_EINVAL, "too many work items");
+  if (opts->precision != MCRT_PREC_FP64 && opts->precision != MCRT_PREC_FP32)
+    return fail(MCRT_EINVAL, "unknown precision %d", opts->precision);
+  if (!(opts->w_min >= 0.0) || !finite(opts->w_min)) return fail(MCRT_EINVAL, "w_min must be finite and >= 0");
+  if (opts->max_scatter < 1 || opts->max_scatter > MCRT_MAX_SCATTER_LIMIT)
+    return fail(MCRT_EINVAL, "max_scatter must lie in [1, %d]", MCRT_MAX_SCATTER_LIMIT);
+  if (opts->flags & ~15u) return fail(MCRT_EINVAL, "unknown flag bits 0x%x", opts->flags);
+  if (opts->launch_blocks < 0 || opts->launch_blocks > 64) return fail(MCRT_EINVAL, "launch_blocks outside [0, 64]");
+  if (opts->event_batch < 0 || opts->event_batch > 64) return fail(MCRT_EINVAL, "event_batch outside [0, 64]");
+
+  RunParams& P = out.P;
+  std::memset(&P, 0, sizeof P);
+  P.G = make_grid(*grid);
+  P.rho = rho_dev;
+  P.n_lambda = nl;
+  P.n_src = n_src;
+  P.n_det = n_det;
+  P.comps = (opts->flags & MCRT_SPLIT) ? 2 : 1;
+  P.first = opts->first_package;
+  P.n_pkg = opts->n_packages;
+  P.seed = opts->seed;
+  P.n_items = opts->n_packages * (unsigned long long)nl;
+  P.w_min = opts->w_min;
+  P.max_scatter = opts->max_scatter;
+  P.flags = opts->flags;
+  P.batch = opts->event_batch > 0 ? opts->event_batch : 16;
+
+  out.lam.assign(nl, LamDev{});
+  out.emitted = 0.0;
+  for (int l = 0; l < nl; ++l) {
+    LamDev& L = out.lam[l];
+    std::memset(&L, 0, sizeof L);
+    L.kappa = optics->kappa[l];
+    L.albedo = optics->albedo[l];
+    L.g = optics->g[l];
+    double cum = 0.0;
+    for (int s = 0; s < n_src; ++s) {
+      cum += sources[s].lum[l];
+      L.cum[s] = cum;
+    }
+    L.ltot = cum;
+    L.w0 = cum / (double)opts->n_packages;
+    out.emitted += L.w0 * (double)opts->n_packages;
+  }
+  out.det.assign(n_det > 0 ? n_det : 1, DetDev{});
+  long long off = 0;
+  for (int d = 0; d < n_det; ++d) {
+    out.det[d] = make_det(detectors[d], off);
+    off += (long long)detectors[d].nx * detectors[d].ny;
+  }
+  P.pix_lambda = off;
+  out.n_images = (long long)P.comps * nl * off;
+  out.src.assign(n_src, SrcDev{});
+  for (int s = 0; s < n_src; ++s) {
+    out.src[s].kind = sources[s].kind;
+    out.src[s].c[0] = sources[s].x;
+    out.src[s].c[1] = sources[s].y;
+    out.src[s].c[2] = sources[s].z;
+    out.src[s].hr = sources[s].h_r;
+    out.src[s].hz = sources[s].h_z;
+  }
+  return 0;
+}
+
+inline int check_trace(const mcrt_grid* grid, const void* rho_dev, double kappa, int precision, int64_t n_rays,
+                       const double* origin_dev, const double* dir_dev, double* tau_dev, int32_t max_seg,
+                       int32_t* seg_cell_dev, double* seg_len_dev) {
+  if (int e = check_grid(grid)) return e;
+  if (!rho_dev) return fail(MCRT_EINVAL, "rho_dev is NULL");
+  if (!(kappa >= 0.0) || !std::isfinite(kappa)) return fail(MCRT_EINVAL, "kappa must be finite and >= 0");
+  if (precision != MCRT_PREC_FP64 && precision != MCRT_PREC_FP32) return fail(MCRT_EINVAL, "unknown precision");
+  if (n_rays < 0) return fail(MCRT_EINVAL, "n_rays < 0");
+  if (n_rays > 0 && (!origin_dev || !dir_dev || !tau_dev)) return fail(MCRT_EINVAL, "ray arrays are NULL");
+  const bool lists = seg_cell_dev || seg_len_dev;
+  if (lists && (!seg_cell_dev || !seg_len_dev)) return fail(MCRT_EINVAL, "seg_cell_dev and seg_len_dev go together");
+  if (lists && max_seg < 1) return fail(MCRT_EINVAL, "max_seg must be >= 1 with segment lists");
+  if (lists && (long long)max_seg * n_rays > (1ll << 40)) return fail(MCRT_EINVAL, "segment lists too large");
+  return 0;
+}
+
+inline int check_peel(const mcrt_grid* grid, const void* rho_dev, double kappa, double g, int precision,
+                      int64_t n_events, const double* pos_dev, const double* w_dev, int n_det,
+                      const mcrt_detector* detectors, double* images_dev) {
+  if (int e = check_grid(grid)) return e;
+  if (!rho_dev) return fail(MCRT_EINVAL, "rho_dev is NULL");
+  if (!(kappa >= 0.0) || !std::isfinite(kappa)) return fail(MCRT_EINVAL, "kappa must be finite and >= 0");
+  if (!(std::fabs(g) < 1.0)) return fail(MCRT_EINVAL, "|g| must be < 1");
+  if (precision != MCRT_PREC_FP64 && precision != MCRT_PREC_FP32) return fail(MCRT_EINVAL, "unknown precision");
+  if (n_events < 0) return fail(MCRT_EINVAL, "n_events < 0");
+  if (int e = check_detectors(n_det, detectors, false)) return e;
+  if (!images_dev) return fail(MCRT_EINVAL, "images_dev is NULL");
+  if (n_events > 0 && (!pos_dev || !w_dev)) return fail(MCRT_EINVAL, "event arrays are NULL");
+  return 0;
+}
+
+inline std::vector<DetDev> make_dets(int n_det, const mcrt_detector* detectors, long long* total_pixels) {
+  std::vector<DetDev> det(n_det > 0 ? n_det : 1);
+  long long off = 0;
+  for (int d = 0; d < n_det; ++d) {
+    det[d] = make_det(detectors[d], off);
+    off += (long long)detectors[d].nx * detectors[d].ny;
+  }
+  if (total_pixels) *total_pixels = off;
+  return det;
+}
+
+}  // namespace host
+}  // namespace mcrt

@@ -1,0 +1,515 @@
+// mcrt_kernels.hip -- gfx950 kernels of the photon-package life cycle and the
+// C ABI that launches them (declared in include/mcrt.h).
+//
+// Method: Camps & Baes (arXiv:1410.1629), Sect. 1 (photon packages; peel-off
+// at emission and scattering; continuous absorption; forced scattering),
+// Sect. 2.1-2.3 (multiple anisotropic scattering; cells of constant
+// properties; geometries; frames; optical properties).
+//
+// Execution model.  One package per lane (mcrt_lane.hpp holds the per-lane
+// state machine and the walk step).  The life-cycle kernel is persistent:
+// every state that needs a walk through the grid sets up a ray, and all rays,
+// whatever they are for (peel-off, pass-1 path, pass-2 locate, adjoint
+// deposit), advance together in one loop, one cell crossing per iteration,
+// so the lanes of a wavefront stay in the walk whatever event their packages
+// are at.  A wavefront leaves the walk to run events only once `batch` of
+// its lanes are waiting (or none is walking).  Lanes that finish a package
+// take the next from a global counter, one atomic per wavefront.  The
+// adjoint kernel runs the same machine twice per package, so paths are
+// recomputed from the random numbers, never stored.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "mcrt.h"
+#include "mcrt_device.hpp"
+#include "mcrt_host.hpp"
+#include "mcrt_lane.hpp"
+
+namespace mcrt {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Wave-level helpers (wave64).
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ void atomic_add_f64(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int src) {
+  const unsigned lo = __shfl((unsigned)v, src), hi = __shfl((unsigned)(v >> 32), src);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// One item for every calling lane, with one atomic per wavefront.
+__device__ __forceinline__ unsigned long long wave_fetch(unsigned long long* counter) {
+  const unsigned long long m = __ballot(1);
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  const int rank = __popcll(m & ((1ull << lane) - 1ull));
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
+  base = shfl_u64(base, leader);
+  return base + (unsigned long long)rank;
+}
+
+// ---------------------------------------------------------------------------
+// Device memory accessors.
+
+template <typename R>
+struct LifeMem {
+  const R* __restrict__ rho_;
+  const RunParams& P;
+  __device__ R rho(int c) const { return rho_[c]; }
+  __device__ const DetDev& det(int d) const { return P.det[d]; }
+  __device__ const LamDev& lam(int l) const { return P.lam[l]; }
+  __device__ const SrcDev& src(int s) const { return P.src[s]; }
+  __device__ double adj(long long i) const { return P.adj[i]; }
+  __device__ void add_image(long long i, double v) const { atomic_add_f64(P.images + i, v); }
+  __device__ void add_absorbed(long long i, double v) const { atomic_add_f64(P.absorbed + i, v); }
+  __device__ void add_grad(int i, double v) const { atomic_add_f64(P.grad + i, v); }
+  __device__ unsigned long long fetch() const { return wave_fetch(P.work); }
+  __device__ void flush_counts(unsigned a, unsigned b, unsigned c, unsigned d) const {
+    atomicAdd(P.xstats + 0, (unsigned long long)a);
+    atomicAdd(P.xstats + 1, (unsigned long long)b);
+    atomicAdd(P.xstats + 2, (unsigned long long)c);
+    atomicAdd(P.xstats + 6, (unsigned long long)d);
+  }
+};
+
+template <typename R>
+struct TraceMem {
+  const R* __restrict__ rho_;
+  const TraceParams& P;
+  __device__ R rho(int c) const { return rho_[c]; }
+  __device__ unsigned long long fetch() const { return wave_fetch(P.work); }
+  __device__ void ray(long long q, double o[3], double k[3]) const {
+    for (int a = 0; a < 3; ++a) {
+      o[a] = P.origin[3 * q + a];
+      k[a] = P.dir[3 * q + a];
+    }
+  }
+  __device__ void set_tau(long long q, double t) const { P.tau[q] = t; }
+  __device__ void set_nseg(long long q, int n) const {
+    if (P.n_seg) P.n_seg[q] = n;
+  }
+  __device__ void store_seg(long long q, int j, int cell, double len) const {
+    P.seg_cell[q * P.max_seg + j] = cell;
+    P.seg_len[q * P.max_seg + j] = len;
+  }
+};
+
+template <typename R>
+struct PeelMem {
+  const R* __restrict__ rho_;
+  const PeelParams& P;
+  __device__ R rho(int c) const { return rho_[c]; }
+  __device__ unsigned long long fetch() const { return wave_fetch(P.work); }
+  __device__ const DetDev& det(int d) const { return P.det[d]; }
+  __device__ void position(long long e, double r[3]) const {
+    for (int a = 0; a < 3; ++a) r[a] = P.pos[3 * e + a];
+  }
+  __device__ bool dir_in(long long e, double k[3]) const {
+    if (!P.dir_in) return false;
+    for (int a = 0; a < 3; ++a) k[a] = P.dir_in[3 * e + a];
+    return true;
+  }
+  __device__ double weight(long long e) const { return P.w[e]; }
+  __device__ void add_image(long long i, double v) const { atomic_add_f64(P.images + i, v); }
+};
+
+// ---------------------------------------------------------------------------
+// Kernels.
+
+template <typename R, bool ADJ>
+__global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
+  LifeMem<R> M{static_cast<const R*>(P.rho), P};
+  Lane<R> L;
+  lane_init(L);
+  for (;;) {
+    lane_events<R, ADJ>(L, P, M);
+    const unsigned long long live = __ballot(!L.done);
+    if (live == 0ull) break;
+    const int n_live = __popcll(live);
+    for (;;) {
+      const int n_act = __popcll(__ballot(L.ry.active));
+      if (n_act == 0 || n_live - n_act >= P.batch) break;
+      if (L.ry.active) lane_step<R, ADJ>(L, P, M);
+    }
+  }
+  const double s_abs = wave_sum(L.s_abs), s_esc = wave_sum(L.s_esc), s_trunc = wave_sum(L.s_trunc);
+  const unsigned long long a0 = wave_sum_u64(L.x_path), a1 = wave_sum_u64(L.x_loc), a2 = wave_sum_u64(L.x_peel),
+                           a3 = wave_sum_u64(L.n_ev), a4 = wave_sum_u64(L.n_pk), a5 = wave_sum_u64(L.n_pl),
+                           a6 = wave_sum_u64(L.n_dep);
+  if (__lane_id() == 0) {
+    atomic_add_f64(P.dstats + 0, s_abs);
+    atomic_add_f64(P.dstats + 1, s_esc);
+    atomic_add_f64(P.dstats + 2, s_trunc);
+    atomicAdd(P.xstats + 0, a0);
+    atomicAdd(P.xstats + 1, a1);
+    atomicAdd(P.xstats + 2, a2);
+    atomicAdd(P.xstats + 3, a3);
+    atomicAdd(P.xstats + 4, a4);
+    atomicAdd(P.xstats + 5, a5);
+    atomicAdd(P.xstats + 6, a6);
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_trace(const TraceParams P) {
+  TraceMem<R> M{static_cast<const R*>(P.rho), P};
+  TraceLane<R> L;
+  trace_init(L);
+  for (;;) {
+    trace_events(L, P, M);
+    const unsigned long long live = __ballot(!L.done);
+    if (live == 0ull) break;
+    const int n_live = __popcll(live);
+    for (;;) {
+      const int n_act = __popcll(__ballot(L.ry.active));
+      if (n_act == 0 || n_live - n_act >= P.batch) break;
+      if (L.ry.active) trace_step(L, P, M);
+    }
+  }
+  const unsigned long long total = wave_sum_u64(L.total), overflow = wave_sum_u64(L.overflow);
+  if (__lane_id() == 0) {
+    atomicAdd(P.counters + 0, total);
+    if (overflow) atomicAdd(P.counters + 1, overflow);
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_peel(const PeelParams P) {
+  PeelMem<R> M{static_cast<const R*>(P.rho), P};
+  PeelLane<R> L;
+  peel_init(L);
+  for (;;) {
+    peel_events(L, P, M);
+    const unsigned long long live = __ballot(!L.done);
+    if (live == 0ull) break;
+    const int n_live = __popcll(live);
+    for (;;) {
+      const int n_act = __popcll(__ballot(L.ry.active));
+      if (n_act == 0 || n_live - n_act >= P.batch) break;
+      if (L.ry.active) peel_step(L, P, M);
+    }
+  }
+}
+
+__global__ void k_zero(double* __restrict__ p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+}  // namespace mcrt
+
+// ===========================================================================
+// Host side: launches.
+
+namespace {
+
+using namespace mcrt;
+using host::fail;
+
+#define HIPCHK(x)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess) return fail(MCRT_EHIP, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <typename K>
+int persistent_grid(K kernel, int blocks_per_cu, int* grid_out) {
+  int dev = 0, cus = 0, nb = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0));
+  if (blocks_per_cu > 0) nb = blocks_per_cu;
+  *grid_out = std::max(1, nb) * std::max(1, cus);
+  return 0;
+}
+
+int zero_fill(double* p, long long n, hipStream_t st) {
+  if (!p || n <= 0) return 0;
+  const long long blocks = std::min<long long>((n + kBlock - 1) / kBlock, 65536);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(kBlock), 0, st, p, n);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+// Device copy of the problem tables plus zeroed counters: one allocation,
+// ordered on the stream, released on the stream when the call returns.
+struct DeviceBlock {
+  unsigned char* ptr = nullptr;
+  hipStream_t st = nullptr;
+  ~DeviceBlock() {
+    if (ptr) (void)hipFreeAsync(ptr, st);
+  }
+};
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+template <typename R, bool ADJ>
+int launch_life(const RunParams& P, int blocks_per_cu, hipStream_t st) {
+  int nblk = 0;
+  if (int e = persistent_grid(k_life<R, ADJ>, blocks_per_cu, &nblk)) return e;
+  hipLaunchKernelGGL((k_life<R, ADJ>), dim3(nblk), dim3(kBlock), 0, st, P);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+// Shared driver of run_photons and backward_density.
+int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
+         const mcrt_source* sources, int n_det, const mcrt_detector* detectors, const mcrt_opts* opts,
+         double* images_dev, double* absorbed_dev, const double* adj_dev, double* grad_dev, mcrt_stats* stats,
+         void* hip_stream) {
+  host::Prepared pr;
+  if (int e = host::prepare(grid, rho_dev, optics, n_src, sources, n_det, detectors, opts, pr)) return e;
+  RunParams& P = pr.P;
+  const bool peel = (opts->flags & (MCRT_PEEL_EMIT | MCRT_PEEL_SCAT)) && n_det > 0;
+  if (!adjoint) {
+    if (peel && !images_dev) return fail(MCRT_EINVAL, "images_dev is NULL");
+    if ((opts->flags & MCRT_ABSORB) && !absorbed_dev) return fail(MCRT_EINVAL, "absorbed_dev is NULL with MCRT_ABSORB");
+    P.images = images_dev;
+    P.absorbed = (opts->flags & MCRT_ABSORB) ? absorbed_dev : nullptr;
+  } else {
+    if (peel && !adj_dev) return fail(MCRT_EINVAL, "adj_images_dev is NULL");
+    if (!grad_dev) return fail(MCRT_EINVAL, "grad_rho_dev is NULL");
+    P.adj = adj_dev;
+    P.grad = grad_dev;
+  }
+  const int nl = P.n_lambda;
+  const size_t off_lam = 0;
+  const size_t off_det = align256(sizeof(LamDev) * nl);
+  const size_t off_src = off_det + align256(sizeof(DetDev) * pr.det.size());
+  const size_t off_cnt = off_src + align256(sizeof(SrcDev) * pr.src.size());
+  const size_t bytes = off_cnt + 256;
+  std::vector<unsigned char> blob(bytes, 0);
+  std::memcpy(blob.data() + off_lam, pr.lam.data(), sizeof(LamDev) * nl);
+  std::memcpy(blob.data() + off_det, pr.det.data(), sizeof(DetDev) * pr.det.size());
+  std::memcpy(blob.data() + off_src, pr.src.data(), sizeof(SrcDev) * pr.src.size());
+
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  DeviceBlock blk;
+  blk.st = st;
+  HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), bytes, st));
+  HIPCHK(hipMemcpyAsync(blk.ptr, blob.data(), bytes, hipMemcpyHostToDevice, st));
+  P.lam = reinterpret_cast<const LamDev*>(blk.ptr + off_lam);
+  P.det = reinterpret_cast<const DetDev*>(blk.ptr + off_det);
+  P.src = reinterpret_cast<const SrcDev*>(blk.ptr + off_src);
+  P.work = reinterpret_cast<unsigned long long*>(blk.ptr + off_cnt);
+  P.dstats = reinterpret_cast<double*>(blk.ptr + off_cnt + 64);
+  P.xstats = reinterpret_cast<unsigned long long*>(blk.ptr + off_cnt + 128);
+  if (!adjoint) {
+    if (int e = zero_fill(P.images, peel ? pr.n_images : 0, st)) return e;
+    if (int e = zero_fill(P.absorbed, P.absorbed ? (long long)nl * P.G.ncell : 0, st)) return e;
+  } else {
+    if (int e = zero_fill(P.grad, P.G.ncell, st)) return e;
+  }
+  EventPair ev;
+  if (stats) {
+    HIPCHK(hipEventCreate(&ev.a));
+    HIPCHK(hipEventCreate(&ev.b));
+    HIPCHK(hipEventRecord(ev.a, st));
+  }
+  const bool f32 = opts->precision == MCRT_PREC_FP32;
+  int rc;
+  if (adjoint)
+    rc = f32 ? launch_life<float, true>(P, opts->launch_blocks, st)
+             : launch_life<double, true>(P, opts->launch_blocks, st);
+  else
+    rc = f32 ? launch_life<float, false>(P, opts->launch_blocks, st)
+             : launch_life<double, false>(P, opts->launch_blocks, st);
+  if (rc) return rc;
+  if (stats) {
+    HIPCHK(hipEventRecord(ev.b, st));
+    double ds[3];
+    unsigned long long xs[7];
+    HIPCHK(hipMemcpyAsync(ds, P.dstats, sizeof ds, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(xs, P.xstats, sizeof xs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ev.a, ev.b) != hipSuccess) ms = -1.0f;
+    stats->emitted = pr.emitted;
+    stats->absorbed = ds[0];
+    stats->escaped = ds[1];
+    stats->truncated = ds[2];
+    stats->x_path = xs[0];
+    stats->x_locate = xs[1];
+    stats->x_peel = xs[2];
+    stats->events = xs[3];
+    stats->packages = xs[4];
+    stats->peels = xs[5];
+    stats->deposits = xs[6];
+    stats->kernel_ms = ms;
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mcrt_abi_version(void) { return MCRT_ABI_VERSION; }
+
+const char* mcrt_last_error(void) { return mcrt::host::last_error().c_str(); }
+
+int run_photons(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
+                const mcrt_source* sources, int n_det, const mcrt_detector* detectors, const mcrt_opts* opts,
+                double* images_dev, double* absorbed_dev, mcrt_stats* stats_host, void* hip_stream) {
+  try {
+    mcrt::host::last_error().clear();
+    return life(false, grid, rho_dev, optics, n_src, sources, n_det, detectors, opts, images_dev, absorbed_dev,
+                nullptr, nullptr, stats_host, hip_stream);
+  } catch (...) {
+    return fail(MCRT_EHIP, "run_photons: host exception");
+  }
+}
+
+int backward_density(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
+                     const mcrt_source* sources, int n_det, const mcrt_detector* detectors, const mcrt_opts* opts,
+                     const double* adj_images_dev, double* grad_rho_dev, mcrt_stats* stats_host,
+                     void* hip_stream) {
+  try {
+    mcrt::host::last_error().clear();
+    mcrt_opts o;
+    if (opts) {
+      o = *opts;
+      o.flags &= ~MCRT_ABSORB;
+    }
+    return life(true, grid, rho_dev, optics, n_src, sources, n_det, detectors, opts ? &o : nullptr, nullptr,
+                nullptr, adj_images_dev, grad_rho_dev, stats_host, hip_stream);
+  } catch (...) {
+    return fail(MCRT_EHIP, "backward_density: host exception");
+  }
+}
+
+int trace_path(const mcrt_grid* grid, const void* rho_dev, double kappa, int precision, int64_t n_rays,
+               const double* origin_dev, const double* dir_dev, double* tau_dev, int32_t max_seg,
+               int32_t* seg_cell_dev, double* seg_len_dev, int32_t* n_seg_dev, uint64_t* crossings_host,
+               void* hip_stream) {
+  try {
+    mcrt::host::last_error().clear();
+    if (int e = host::check_trace(grid, rho_dev, kappa, precision, n_rays, origin_dev, dir_dev, tau_dev, max_seg,
+                                  seg_cell_dev, seg_len_dev))
+      return e;
+    const bool lists = seg_cell_dev != nullptr;
+    if (n_rays == 0) {
+      if (crossings_host) *crossings_host = 0;
+      return 0;
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    TraceParams P;
+    std::memset(&P, 0, sizeof P);
+    P.G = host::make_grid(*grid);
+    P.rho = rho_dev;
+    P.kappa = kappa;
+    P.n_rays = n_rays;
+    P.origin = origin_dev;
+    P.dir = dir_dev;
+    P.tau = tau_dev;
+    P.max_seg = lists ? max_seg : 0;
+    P.seg_cell = lists ? seg_cell_dev : nullptr;
+    P.seg_len = lists ? seg_len_dev : nullptr;
+    P.n_seg = n_seg_dev;
+    P.batch = 16;
+    DeviceBlock blk;
+    blk.st = st;
+    const unsigned long long zeros[3] = {0, 0, 0};
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), 256, st));
+    HIPCHK(hipMemcpyAsync(blk.ptr, zeros, sizeof zeros, hipMemcpyHostToDevice, st));
+    P.work = reinterpret_cast<unsigned long long*>(blk.ptr);
+    P.counters = P.work + 1;
+    int nblk = 0;
+    if (precision == MCRT_PREC_FP32) {
+      if (int e = persistent_grid(k_trace<float>, 0, &nblk)) return e;
+      hipLaunchKernelGGL(k_trace<float>, dim3(nblk), dim3(kBlock), 0, st, P);
+    } else {
+      if (int e = persistent_grid(k_trace<double>, 0, &nblk)) return e;
+      hipLaunchKernelGGL(k_trace<double>, dim3(nblk), dim3(kBlock), 0, st, P);
+    }
+    HIPCHK(hipGetLastError());
+    if (crossings_host || lists) {
+      unsigned long long c[2] = {0, 0};
+      HIPCHK(hipMemcpyAsync(c, P.counters, sizeof c, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (crossings_host) *crossings_host = c[0];
+      if (lists && c[1]) return fail(MCRT_EOVERFLOW, "%llu rays had more than max_seg = %d segments", c[1], max_seg);
+    }
+    return 0;
+  } catch (...) {
+    return fail(MCRT_EHIP, "trace_path: host exception");
+  }
+}
+
+int peel_off(const mcrt_grid* grid, const void* rho_dev, double kappa, double g, int precision, int64_t n_events,
+             const double* pos_dev, const double* dir_in_dev, const double* w_dev, int n_det,
+             const mcrt_detector* detectors, double* images_dev, void* hip_stream) {
+  try {
+    mcrt::host::last_error().clear();
+    if (int e = host::check_peel(grid, rho_dev, kappa, g, precision, n_events, pos_dev, w_dev, n_det, detectors,
+                                 images_dev))
+      return e;
+    if (n_events == 0) return 0;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    std::vector<DetDev> det = host::make_dets(n_det, detectors, nullptr);
+    const size_t off_cnt = align256(sizeof(DetDev) * det.size());
+    const size_t bytes = off_cnt + 256;
+    std::vector<unsigned char> blob(bytes, 0);
+    std::memcpy(blob.data(), det.data(), sizeof(DetDev) * det.size());
+    DeviceBlock blk;
+    blk.st = st;
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), bytes, st));
+    HIPCHK(hipMemcpyAsync(blk.ptr, blob.data(), bytes, hipMemcpyHostToDevice, st));
+    PeelParams P;
+    std::memset(&P, 0, sizeof P);
+    P.G = host::make_grid(*grid);
+    P.rho = rho_dev;
+    P.kappa = kappa;
+    P.g = g;
+    P.n_events = n_events;
+    P.n_det = n_det;
+    P.det = reinterpret_cast<const DetDev*>(blk.ptr);
+    P.pos = pos_dev;
+    P.dir_in = dir_in_dev;
+    P.w = w_dev;
+    P.images = images_dev;
+    P.work = reinterpret_cast<unsigned long long*>(blk.ptr + off_cnt);
+    P.batch = 16;
+    int nblk = 0;
+    if (precision == MCRT_PREC_FP32) {
+      if (int e = persistent_grid(k_peel<float>, 0, &nblk)) return e;
+      hipLaunchKernelGGL(k_peel<float>, dim3(nblk), dim3(kBlock), 0, st, P);
+    } else {
+      if (int e = persistent_grid(k_peel<double>, 0, &nblk)) return e;
+      hipLaunchKernelGGL(k_peel<double>, dim3(nblk), dim3(kBlock), 0, st, P);
+    }
+    HIPCHK(hipGetLastError());
+    return 0;
+  } catch (...) {
+    return fail(MCRT_EHIP, "peel_off: host exception");
+  }
+}
+
+}  // extern "C"

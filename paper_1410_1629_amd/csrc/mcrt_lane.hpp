@@ -1,0 +1,521 @@
+// mcrt_lane.hpp -- per-lane logic of the life-cycle, trace and peel-off
+// kernels: the package state machine and the walk step.
+//
+// Method: Camps & Baes (arXiv:1410.1629), Sect. 1 (photon packages; peel-off
+// at emission and scattering, Yusef-Zadeh et al. 1984; continuous absorption,
+// Lucy 1999, Niccolini et al. 2003; forced scattering, Cashwell & Everett
+// 1959), Sect. 2.1 (multiple anisotropic scattering), Sect. 2.2 (cells of
+// constant properties, geometries, parallel-projection frames, direct and
+// scattered light recorded separately), Sect. 2.3 (kappa, albedo, g).
+//
+// A lane owns one package at a time.  Its state machine (lane_events) runs
+// the events of the package -- emission, peel-off towards each frame, the
+// pass-1 walk with continuous absorption, the pass-2 walk that locates the
+// forced-scattering point, peel-off at the scattering, termination or HG
+// turn -- and stops whenever the next event needs a walk through the grid,
+// leaving a ray set up in `ry`.  lane_step advances that ray by one cell and
+// does the per-crossing work of its mode.  The kernel interleaves the two
+// across the lanes of a wavefront; the CPU test harness runs them lane by
+// lane.  All memory goes through the accessor M:
+//   M.rho(cell)  M.det(d)  M.lam(l)  M.src(s)  M.adj(i)
+//   M.add_image(i, v)  M.add_absorbed(i, v)  M.add_grad(cell, v)
+//   M.fetch()  M.flush_counts(x_path, x_locate, x_peel, deposits)
+//
+// Adjoint (ADJ = true): the detached derivative of C, a peel-off contribution
+// of event e, with respect to the density of cell m is
+//   C [ sum_{i<=e} (delta(m, c_i)/rho_m - kappa l_m(leg_i)) - kappa l_m(peel) ]
+// (c_i: cell of scattering i; leg_i: path from event i-1 to it).  With
+// A = dL/dI at C's pixel and G_e the sum of A C over the frames for event e,
+// the gradient collects, per package, R_i = sum_{e>=i} G_e on leg i and on
+// c_i, and A C on each peel ray.  Pass A replays the package to get
+// R_1 = sum_e G_e; pass B replays it again and deposits, keeping
+// R_i = R_1 - sum_{e<i} G_e; each peel ray is walked once for C and, when
+// A C != 0, a second time to deposit.
+#pragma once
+
+#include "mcrt_device.hpp"
+
+namespace mcrt {
+
+constexpr int kFlagPeelEmit = 1, kFlagPeelScat = 2, kFlagAbsorb = 4, kFlagSplit = 8;
+
+enum RayMode : int { M_PEEL = 0, M_PATH = 1, M_LOCATE = 2, M_PEEL_DEP = 3 };
+enum Phase : int {
+  PH_FETCH = 0,
+  PH_EMIT,
+  PH_PEEL_NEXT,
+  PH_PEEL_END,
+  PH_PEEL_DEP_END,
+  PH_PATH_START,
+  PH_PATH_END,
+  PH_LOCATE_END,
+  PH_TERM,
+  PH_PKG_END
+};
+
+struct RunParams {
+  GridDev G;
+  const void* rho;
+  const LamDev* lam;
+  const DetDev* det;
+  const SrcDev* src;
+  int n_lambda, n_src, n_det, comps;
+  unsigned long long first, n_pkg, seed, n_items;
+  double w_min;
+  int max_scatter;
+  unsigned flags;
+  long long pix_lambda;
+  double* images;
+  double* absorbed;
+  const double* adj;
+  double* grad;
+  unsigned long long* work;    // next work item (wavelength-major)
+  double* dstats;              // absorbed, escaped, truncated
+  unsigned long long* xstats;  // x_path, x_locate, x_peel, events, packages, peels, deposits
+  int batch;
+};
+
+template <typename R>
+struct Lane {
+  Ray<R> ry;
+  int phase;
+  bool done;
+  unsigned long long pkg;
+  int lam, det, n, pix, mode;
+  bool is_emit, found;
+  double r[3], k[3];
+  double W, w0, kap, alb, g, T, tau_s, wabs;
+  R kapR, tau_sR, absf, tau_prev, rho_hit, last_t;
+  unsigned uw1, uw2;
+  int hit_cell, last_cell;
+  long long lam_cell;
+  // adjoint replay
+  int pass;
+  double Rtot, Gacc, Gabs, fac;
+  // statistics
+  double s_abs, s_esc, s_trunc;
+  unsigned x_path, x_loc, x_peel, n_ev, n_pk, n_pl, n_dep;
+};
+
+template <typename R>
+MCRT_HD void lane_init(Lane<R>& L) {
+  L.ry.active = false;
+  L.ry.tau = R(0);
+  L.ry.t = R(0);
+  L.ry.tin = 0.0;
+  L.phase = PH_FETCH;
+  L.done = false;
+  L.pkg = 0;
+  L.lam = L.det = L.n = L.pix = 0;
+  L.mode = M_PEEL;
+  L.is_emit = true;
+  L.found = false;
+  for (int a = 0; a < 3; ++a) L.r[a] = L.k[a] = 0.0;
+  L.k[2] = 1.0;
+  L.W = L.w0 = L.kap = L.alb = L.g = L.T = L.tau_s = L.wabs = 0.0;
+  L.kapR = L.tau_sR = L.absf = L.tau_prev = L.rho_hit = L.last_t = R(0);
+  L.uw1 = L.uw2 = 0;
+  L.hit_cell = L.last_cell = 0;
+  L.lam_cell = 0;
+  L.pass = 0;
+  L.Rtot = L.Gacc = L.Gabs = L.fac = 0.0;
+  L.s_abs = L.s_esc = L.s_trunc = 0.0;
+  L.x_path = L.x_loc = L.x_peel = L.n_ev = L.n_pk = L.n_pl = L.n_dep = 0;
+}
+
+// Runs the lane's events until its next walk is set up (ry.active) or no
+// work is left (done).
+template <typename R, bool ADJ, class Mem>
+MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
+  const GridDev& G = P.G;
+  while (!L.ry.active && !L.done) {
+    switch (L.phase) {
+      case PH_FETCH: {
+        if ((L.x_path | L.x_loc | L.x_peel | L.n_dep) & 0xC0000000u) {  // keep 32-bit counters from wrapping
+          M.flush_counts(L.x_path, L.x_loc, L.x_peel, L.n_dep);
+          L.x_path = L.x_loc = L.x_peel = L.n_dep = 0;
+        }
+        const unsigned long long item = M.fetch();
+        if (item >= P.n_items) {
+          L.done = true;
+          break;
+        }
+        L.lam = (int)(item / P.n_pkg);
+        L.pkg = P.first + (item - (unsigned long long)L.lam * P.n_pkg);
+        L.lam_cell = (long long)L.lam * G.ncell;
+        const LamDev& LD = M.lam(L.lam);
+        L.kap = LD.kappa;
+        L.kapR = (R)L.kap;
+        L.alb = LD.albedo;
+        L.g = LD.g;
+        L.w0 = LD.w0;
+        L.pass = 0;
+        L.Gacc = L.Gabs = 0.0;
+        L.phase = PH_EMIT;
+        break;
+      }
+      case PH_EMIT: {  // also the start of the adjoint replay
+        const LamDev& LD = M.lam(L.lam);
+        const U4 wd = draw_words(P.seed, L.pkg, (unsigned)L.lam, 1u);
+        int s = P.n_src - 1;
+        const double target = u01(wd.z) * LD.ltot;
+        for (int q = 0; q < P.n_src; ++q) {
+          if (target < LD.cum[q]) {
+            s = q;
+            break;
+          }
+        }
+        iso_direction(u01(wd.x), u01(wd.y), L.k);
+        source_position(M.src(s), draw_words(P.seed, L.pkg, (unsigned)L.lam, 0u), L.r);
+        L.W = L.w0;
+        L.n = 0;
+        if (L.pass == 0) ++L.n_pk;
+        L.is_emit = true;
+        L.det = 0;
+        L.phase = (P.flags & kFlagPeelEmit) ? PH_PEEL_NEXT : PH_PATH_START;
+        break;
+      }
+      case PH_PEEL_NEXT: {
+        while (L.det < P.n_det) {
+          L.pix = frame_pixel(M.det(L.det), L.r);
+          if (L.pix >= 0) break;
+          ++L.det;
+        }
+        if (L.det >= P.n_det) {
+          L.phase = L.is_emit ? PH_PATH_START : PH_TERM;
+          break;
+        }
+        ray_begin(L.ry, G, M, L.r, M.det(L.det).kd);
+        L.mode = M_PEEL;
+        L.phase = PH_PEEL_END;
+        break;
+      }
+      case PH_PEEL_END: {
+        const DetDev& D = M.det(L.det);
+        const double ph = L.is_emit ? 1.0 / (4.0 * kPi)
+                                    : hg_phase(L.g, L.k[0] * D.kd[0] + L.k[1] * D.kd[1] + L.k[2] * D.kd[2]);
+        const double C = L.W * ph * exp(-(double)L.ry.tau) * D.inv_d2;
+        const int comp = ((P.flags & kFlagSplit) && !L.is_emit) ? 1 : 0;
+        const long long ii = ((long long)comp * P.n_lambda + L.lam) * P.pix_lambda + D.off + L.pix;
+        L.phase = PH_PEEL_NEXT;
+        if (L.pass == 0) ++L.n_pl;
+        if (!ADJ) {
+          M.add_image(ii, C);
+          ++L.det;
+        } else {
+          const double ac = M.adj(ii) * C;
+          L.Gacc += ac;
+          if (L.pass == 0) {
+            L.Gabs += fabs(ac);
+            ++L.det;
+          } else if (ac != 0.0) {  // second walk of the same ray deposits -A C kappa l
+            L.fac = -ac * L.kap;
+            ray_begin(L.ry, G, M, L.r, D.kd);
+            L.mode = M_PEEL_DEP;
+            L.phase = PH_PEEL_DEP_END;
+          } else {
+            ++L.det;
+          }
+        }
+        break;
+      }
+      case PH_PEEL_DEP_END: {
+        ++L.det;
+        L.phase = PH_PEEL_NEXT;
+        break;
+      }
+      case PH_PATH_START: {
+        ray_begin(L.ry, G, M, L.r, L.k);
+        L.mode = M_PATH;
+        L.absf = R(0);
+        L.wabs = L.W * (1.0 - L.alb);
+        L.phase = PH_PATH_END;
+        break;
+      }
+      case PH_PATH_END: {
+        L.T = (double)L.ry.tau;
+        if (L.T == 0.0) {  // nothing to interact with: the package leaves
+          if (L.pass == 0) L.s_esc += L.W;
+          L.phase = PH_PKG_END;
+          break;
+        }
+        if (L.pass == 0) {
+          L.s_abs += L.wabs * (double)L.absf;
+          L.s_esc += L.W * exp(-L.T);
+        }
+        const U4 ws = draw_words(P.seed, L.pkg, (unsigned)L.lam, 2u + (unsigned)L.n);
+        L.tau_s = -log1p(u01(ws.x) * expm1(-L.T));
+        L.tau_sR = (R)L.tau_s;
+        L.uw1 = ws.y;
+        L.uw2 = ws.z;
+        if (ADJ && L.pass == 1) L.fac = -(L.Rtot - L.Gacc) * L.kap;
+        ray_begin(L.ry, G, M, L.r, L.k);
+        L.mode = M_LOCATE;
+        L.found = false;
+        L.last_cell = L.ry.cell;
+        L.last_t = L.ry.t;
+        L.phase = PH_LOCATE_END;
+        break;
+      }
+      case PH_LOCATE_END: {
+        double s;
+        if (L.found) {
+          const double tp = ray_cell_entry64(L.ry, G, L.r, L.k);
+          s = tp + (L.tau_s - (double)L.tau_prev) / (L.kap * (double)L.rho_hit);
+          if (ADJ && L.pass == 1) {
+            const double Ri = L.Rtot - L.Gacc;
+            M.add_grad(L.hit_cell, Ri / (double)L.rho_hit - Ri * L.kap * (s - tp));
+            ++L.n_dep;
+          }
+        } else {  // tau_s reached the total by rounding: end of the last absorbing segment
+          s = L.ry.tin + (double)L.last_t;
+          if (ADJ && L.pass == 1) {
+            M.add_grad(L.last_cell, (L.Rtot - L.Gacc) / (double)M.rho(L.last_cell));
+            ++L.n_dep;
+          }
+        }
+        L.r[0] += s * L.k[0];
+        L.r[1] += s * L.k[1];
+        L.r[2] += s * L.k[2];
+        L.W *= L.alb * (-expm1(-L.T));
+        ++L.n;
+        if (L.pass == 0) ++L.n_ev;
+        L.is_emit = false;
+        L.det = 0;
+        L.phase = (P.flags & kFlagPeelScat) ? PH_PEEL_NEXT : PH_TERM;
+        break;
+      }
+      case PH_TERM: {
+        if (L.W < P.w_min * L.w0 || L.n >= P.max_scatter) {
+          if (L.pass == 0) L.s_trunc += L.W;
+          L.phase = PH_PKG_END;
+          break;
+        }
+        turn(L.k, hg_sample_mu(L.g, u01(L.uw1)), u01(L.uw2));
+        L.phase = PH_PATH_START;
+        break;
+      }
+      case PH_PKG_END:
+      default: {
+        if (ADJ && L.pass == 0 && L.Gabs != 0.0) {  // replay the package and deposit
+          L.Rtot = L.Gacc;
+          L.Gacc = 0.0;
+          L.pass = 1;
+          L.phase = PH_EMIT;
+        } else {
+          L.phase = PH_FETCH;
+        }
+        break;
+      }
+    }
+  }
+}
+
+// One crossing of the lane's active ray, with the per-crossing work of its
+// mode: pass-1 continuous absorption W (1 - albedo) e^-tau (1 - e^-dtau)
+// into the cell; pass-2 search for the first segment whose optical depth
+// passes tau_s (and, in the adjoint replay, -R kappa l deposits along the
+// leg); peel rays accumulate tau (and, on the deposit walk, -A C kappa l).
+// Zero-length segments are skipped.
+template <typename R, bool ADJ, class Mem>
+MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M) {
+  Ray<R>& ry = L.ry;
+  const R tm = ray_tnext(ry);
+  R seg = tm - ry.t;
+  const bool pos = seg > R(0);
+  seg = pos ? seg : R(0);
+  const R rs = ry.rho_cur;
+  const R dtau = L.kapR * rs * seg;
+  if (L.mode == M_PATH) {
+    L.x_path += pos;
+    if (!ADJ && dtau > R(0)) {
+      const R f = exp(-ry.tau) * (-expm1(-dtau));
+      L.absf += f;
+      if (P.absorbed) {
+        M.add_absorbed(L.lam_cell + ry.cell, L.wabs * (double)f);
+        ++L.n_dep;
+      }
+    }
+  } else if (L.mode == M_LOCATE) {
+    L.x_loc += pos;
+    if (pos && ry.tau + dtau > L.tau_sR) {
+      L.found = true;
+      L.hit_cell = ry.cell;
+      L.tau_prev = ry.tau;
+      L.rho_hit = rs;
+      ry.active = false;
+      return;
+    }
+    if (dtau > R(0)) {
+      L.last_cell = ry.cell;
+      L.last_t = tm;
+    }
+    if (ADJ && L.pass == 1 && pos) {
+      M.add_grad(ry.cell, L.fac * (double)seg);
+      ++L.n_dep;
+    }
+  } else {
+    L.x_peel += pos;
+    if (ADJ && L.mode == M_PEEL_DEP && pos) {
+      M.add_grad(ry.cell, L.fac * (double)seg);
+      ++L.n_dep;
+    }
+  }
+  ry.tau += dtau;
+  if (pos) ry.t = tm;
+  if (ray_advance(ry, tm, M)) ry.active = false;
+}
+
+// ---------------------------------------------------------------------------
+// trace_path and peel_off: one ray per work item.
+
+struct TraceParams {
+  GridDev G;
+  const void* rho;
+  double kappa;
+  long long n_rays;
+  const double* origin;
+  const double* dir;
+  double* tau;
+  int max_seg;
+  int* seg_cell;
+  double* seg_len;
+  int* n_seg;
+  unsigned long long* work;
+  unsigned long long* counters;  // [0] segments, [1] rays over max_seg
+  int batch;
+};
+
+template <typename R>
+struct TraceLane {
+  Ray<R> ry;
+  bool done, pending;
+  long long q;
+  int nseg;
+  unsigned long long total, overflow;
+};
+
+template <typename R>
+MCRT_HD void trace_init(TraceLane<R>& L) {
+  L.ry.active = false;
+  L.ry.tau = R(0);
+  L.done = L.pending = false;
+  L.q = 0;
+  L.nseg = 0;
+  L.total = L.overflow = 0;
+}
+
+// Finishes the lane's ray (if any) and sets up the next one.
+template <typename R, class Mem>
+MCRT_HD void trace_events(TraceLane<R>& L, const TraceParams& P, Mem& M) {
+  while (!L.ry.active && !L.done) {
+    if (L.pending) {
+      M.set_tau(L.q, (double)L.ry.tau);
+      M.set_nseg(L.q, L.nseg);
+      L.total += (unsigned long long)L.nseg;
+      L.overflow += (unsigned long long)(P.seg_cell != nullptr && L.nseg > P.max_seg);
+      L.pending = false;
+    }
+    const unsigned long long item = M.fetch();
+    if (item >= (unsigned long long)P.n_rays) {
+      L.done = true;
+      break;
+    }
+    L.q = (long long)item;
+    double o[3], k[3];
+    M.ray(L.q, o, k);
+    L.nseg = 0;
+    L.pending = true;
+    ray_begin(L.ry, P.G, M, o, k);
+  }
+}
+
+template <typename R, class Mem>
+MCRT_HD void trace_step(TraceLane<R>& L, const TraceParams& P, Mem& M) {
+  Ray<R>& ry = L.ry;
+  const R tm = ray_tnext(ry);
+  R seg = tm - ry.t;
+  const bool pos = seg > R(0);
+  seg = pos ? seg : R(0);
+  if (pos) {
+    if (P.seg_cell != nullptr && L.nseg < P.max_seg) M.store_seg(L.q, L.nseg, ry.cell, (double)seg);
+    ++L.nseg;
+    ry.t = tm;
+  }
+  ry.tau += (R)P.kappa * ry.rho_cur * seg;
+  if (ray_advance(ry, tm, M)) ry.active = false;
+}
+
+struct PeelParams {
+  GridDev G;
+  const void* rho;
+  double kappa, g;
+  long long n_events;
+  int n_det;
+  const DetDev* det;
+  const double* pos;
+  const double* dir_in;
+  const double* w;
+  double* images;
+  unsigned long long* work;
+  int batch;
+};
+
+template <typename R>
+struct PeelLane {
+  Ray<R> ry;
+  bool done, pending;
+  long long e;
+  int d, pix;
+};
+
+template <typename R>
+MCRT_HD void peel_init(PeelLane<R>& L) {
+  L.ry.active = false;
+  L.ry.tau = R(0);
+  L.done = L.pending = false;
+  L.e = 0;
+  L.d = L.pix = 0;
+}
+
+template <typename R, class Mem>
+MCRT_HD void peel_events(PeelLane<R>& L, const PeelParams& P, Mem& M) {
+  const unsigned long long n_items = (unsigned long long)P.n_events * (unsigned long long)P.n_det;
+  while (!L.ry.active && !L.done) {
+    if (L.pending) {
+      const DetDev& D = M.det(L.d);
+      double kin[3];
+      double ph = 1.0 / (4.0 * kPi);
+      if (M.dir_in(L.e, kin)) ph = hg_phase(P.g, kin[0] * D.kd[0] + kin[1] * D.kd[1] + kin[2] * D.kd[2]);
+      M.add_image(D.off + L.pix, M.weight(L.e) * ph * exp(-(double)L.ry.tau) * D.inv_d2);
+      L.pending = false;
+    }
+    const unsigned long long item = M.fetch();
+    if (item >= n_items) {
+      L.done = true;
+      break;
+    }
+    L.e = (long long)(item / (unsigned long long)P.n_det);
+    L.d = (int)(item - (unsigned long long)L.e * P.n_det);
+    double r[3];
+    M.position(L.e, r);
+    L.pix = frame_pixel(M.det(L.d), r);
+    if (L.pix < 0) continue;
+    L.pending = true;
+    ray_begin(L.ry, P.G, M, r, M.det(L.d).kd);
+  }
+}
+
+template <typename R, class Mem>
+MCRT_HD void peel_step(PeelLane<R>& L, const PeelParams& P, Mem& M) {
+  Ray<R>& ry = L.ry;
+  const R tm = ray_tnext(ry);
+  R seg = tm - ry.t;
+  const bool pos = seg > R(0);
+  seg = pos ? seg : R(0);
+  if (pos) ry.t = tm;
+  ry.tau += (R)P.kappa * ry.rho_cur * seg;
+  if (ray_advance(ry, tm, M)) ry.active = false;
+}
+
+}  // namespace mcrt

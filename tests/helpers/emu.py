@@ -1,0 +1,122 @@
+"""ctypes front end of the CPU harness of the HIP library's lane code
+(tests/helpers/mcrt_emu.cpp).  Test infrastructure: builds the harness with
+hipcc as host code, then runs the kernels' per-lane logic on host arrays
+with bounds checks.  Uses the binding's C struct layouts (include/mcrt.h)."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+from paper_1410_1629_amd import binding as B
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+SRC = os.path.join(HERE, "mcrt_emu.cpp")
+CSRC = os.path.join(ROOT, "paper_1410_1629_amd", "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+DEPS = [SRC, os.path.join(INCLUDE, "mcrt.h")] + [os.path.join(CSRC, h) for h in
+                                                ("mcrt_device.hpp", "mcrt_lane.hpp", "mcrt_host.hpp")]
+WAVE = 64
+
+
+class EmuViolation(AssertionError):
+    pass
+
+
+def build(out_dir, csrc=CSRC):
+    lib = os.path.join(out_dir, "libmcrt_emu.so")
+    cmd = ["hipcc", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-x", "hip",
+           "--offload-arch=gfx950", "-I" + INCLUDE, "-I" + csrc, SRC, "-o", lib]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return lib
+
+
+class Emu:
+    def __init__(self, lib_path):
+        lib = C.CDLL(lib_path)
+        P, i64, d = C.c_void_p, C.c_longlong, C.c_double
+        lib.emu_run_photons.argtypes = [C.POINTER(B.Grid), P, C.POINTER(B.Optics), C.c_int, C.POINTER(B.Source),
+                                        C.c_int, C.POINTER(B.Detector), C.POINTER(B.Opts), P, i64, P, i64,
+                                        C.POINTER(B.Stats), C.c_int]
+        lib.emu_backward_density.argtypes = [C.POINTER(B.Grid), P, C.POINTER(B.Optics), C.c_int,
+                                             C.POINTER(B.Source), C.c_int, C.POINTER(B.Detector),
+                                             C.POINTER(B.Opts), P, i64, P, i64, C.POINTER(B.Stats), C.c_int]
+        lib.emu_trace_path.argtypes = [C.POINTER(B.Grid), P, d, C.c_int, C.c_int64, P, P, P, C.c_int32, P, P, P,
+                                       C.POINTER(C.c_uint64), C.c_int]
+        lib.emu_peel_off.argtypes = [C.POINTER(B.Grid), P, d, d, C.c_int, C.c_int64, P, P, P, C.c_int,
+                                     C.POINTER(B.Detector), P, C.c_int]
+        for f in ("emu_run_photons", "emu_backward_density", "emu_trace_path", "emu_peel_off"):
+            getattr(lib, f).restype = C.c_int
+        lib.emu_violation.restype = C.c_char_p
+        lib.emu_last_error.restype = C.c_char_p
+        self.lib = lib
+
+    def _check(self, rc):
+        if rc == -100:
+            raise EmuViolation(self.lib.emu_violation().decode())
+        if rc != 0:
+            raise B.McrtError(rc, self.lib.emu_last_error().decode())
+
+    @staticmethod
+    def _rho(prob):
+        dt = np.float32 if prob.get("precision", 0) == 1 else np.float64
+        return np.ascontiguousarray(np.asarray(prob["rho"]).reshape(-1), dtype=dt)
+
+    @staticmethod
+    def _p(a):
+        return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+    def run(self, prob, wave=WAVE, **overrides):
+        pr = B._Problem(prob, **overrides)
+        rho = self._rho(prob)
+        images = np.zeros(B.image_shape(prob))
+        absorbed = np.zeros((len(np.atleast_1d(prob["kappa"])), rho.size)) if prob.get("flags", 7) & 4 else None
+        st = B.Stats()
+        self._check(self.lib.emu_run_photons(C.byref(pr.grid), self._p(rho), C.byref(pr.optics), pr.n_src,
+                                             pr.sources, pr.n_det, pr.detectors, C.byref(pr.opts), self._p(images),
+                                             images.size, self._p(absorbed), 0 if absorbed is None else absorbed.size,
+                                             C.byref(st), wave))
+        return images, absorbed, st.as_dict()
+
+    def grad(self, prob, adj, wave=WAVE, **overrides):
+        pr = B._Problem(prob, **overrides)
+        rho = self._rho(prob)
+        adj = np.ascontiguousarray(adj, dtype=np.float64).reshape(-1)
+        g = np.zeros(rho.size)
+        st = B.Stats()
+        self._check(self.lib.emu_backward_density(C.byref(pr.grid), self._p(rho), C.byref(pr.optics), pr.n_src,
+                                                  pr.sources, pr.n_det, pr.detectors, C.byref(pr.opts),
+                                                  self._p(adj), adj.size, self._p(g), g.size, C.byref(st), wave))
+        return g, st.as_dict()
+
+    def trace(self, box, n, rho, kappa, prec, origins, dirs, max_seg=0, wave=WAVE):
+        g = B.make_grid({"box": box, "n": n})
+        dt = np.float32 if prec == 1 else np.float64
+        rho = np.ascontiguousarray(np.asarray(rho).reshape(-1), dtype=dt)
+        o = np.ascontiguousarray(origins, dtype=np.float64).reshape(-1, 3)
+        k = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+        nr = o.shape[0]
+        tau = np.zeros(nr)
+        nseg = np.zeros(nr, dtype=np.int32)
+        cell = np.zeros((nr, max_seg), dtype=np.int32) if max_seg else None
+        length = np.zeros((nr, max_seg)) if max_seg else None
+        c = C.c_uint64(0)
+        rc = self.lib.emu_trace_path(C.byref(g), self._p(rho), float(kappa), int(prec), nr, self._p(o), self._p(k),
+                                     self._p(tau), int(max_seg), self._p(cell), self._p(length), self._p(nseg),
+                                     C.byref(c), wave)
+        return rc, tau, c.value, cell, length, nseg
+
+    def peel(self, box, n, rho, kappa, g, prec, pos, dir_in, w, detectors, wave=WAVE):
+        gr = B.make_grid({"box": box, "n": n})
+        dt = np.float32 if prec == 1 else np.float64
+        rho = np.ascontiguousarray(np.asarray(rho).reshape(-1), dtype=dt)
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        din = None if dir_in is None else np.ascontiguousarray(dir_in, dtype=np.float64).reshape(-1, 3)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        dets = B.make_detectors(detectors)
+        images = np.zeros(int(sum(d["nx"] * d["ny"] for d in detectors)))
+        self._check(self.lib.emu_peel_off(C.byref(gr), self._p(rho), float(kappa), float(g), int(prec), pos.shape[0],
+                                          self._p(pos), self._p(din), self._p(w), len(detectors), dets,
+                                          self._p(images), wave))
+        return images

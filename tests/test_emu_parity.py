@@ -1,0 +1,187 @@
+"""The HIP library's per-lane code, run on the CPU by the bounds-checked
+harness (tests/helpers/mcrt_emu.cpp), against the FP64 oracle.
+
+This checks the kernels' logic -- state machine, walk, tallies, adjoint
+replay -- and that no access leaves its buffer, before any GPU run; the
+GPU tests then check the same cases on the device.  Tolerances as for the
+GPU: FP64 1e-10 relative L1, FP32 traversal 1e-5.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.join(os.path.dirname(__file__), "helpers"))
+
+
+def rel_l1(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    den = np.abs(b).sum()
+    return float(np.abs(a - b).sum() / den) if den > 0 else float(np.abs(a).sum())
+
+
+@pytest.fixture(scope="session")
+def E(tmp_path_factory):
+    import emu
+    return emu.Emu(emu.build(str(tmp_path_factory.mktemp("emu"))))
+
+
+TRACE_CASES = [
+    ("uniform32", (-1, 1, -1, 1, -1, 1), (32, 32, 32), None, 1.0),
+    ("lognormal_ragged", (-2.0, 1.0, 0.0, 3.0, -1.0, 0.5), (9, 6, 5), 9, 0.7),
+    ("flat", (-20, 20, -20, 20, -2, 2), (64, 3, 17), 4, 1.3),
+    ("one_cell", (-1, 1, -1, 1, -1, 1), (1, 1, 1), 5, 2.0),
+]
+
+
+@pytest.mark.parametrize("name,box,n,seed,kappa", TRACE_CASES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_trace(E, orc, W, name, box, n, seed, kappa, prec):
+    rho = np.ones(n[::-1]) if seed is None else W.lognormal_density(n, 1.0, seed=seed, f32=(prec == 1))
+    o, k = W.random_rays(3001, box, seed=17)
+    max_seg = int(sum(n)) + 4
+    tau_o, tot_o, cell_o, len_o, nseg_o = orc.trace(box, n, rho, kappa, o, k, max_seg=max_seg)
+    rc, tau, tot, cell, length, nseg = E.trace(box, n, rho, kappa, prec, o, k, max_seg=max_seg)
+    assert rc == 0
+    tol = 1e-12 if prec == 0 else 2e-6
+    np.testing.assert_allclose(tau, tau_o, rtol=tol, atol=tol * max(1.0, tau_o.max()) * 1e-3)
+    same = nseg == nseg_o
+    assert same.mean() > (0.999 if prec == 0 else 0.99), same.mean()
+    for q in np.nonzero(same)[0]:
+        m = nseg[q]
+        if not np.array_equal(cell[q, :m], cell_o[q, :m].astype(np.int32)):
+            assert min(len_o[q, :m].min(), length[q, :m].min()) < 1e-6 * max(box[1] - box[0], 1.0)
+            continue
+        # lengths are differences of crossing times: absolute rounding scales with the box
+        np.testing.assert_allclose(length[q, :m], len_o[q, :m], rtol=tol, atol=tol * max(box[1] - box[0], 1.0))
+    assert abs(tot - tot_o) <= 1e-3 * tot_o + 2
+
+
+def test_trace_edge_cases(E, orc):
+    box, n = (-1, 1, -1, 1, -1, 1), (4, 4, 4)
+    o = np.array([[2.0, 0, 0], [1.0, 0, 0], [-1.0, 0.0, 0.1], [0.0, 0.1, 0.1], [0.0, 0.1, 0.1],
+                  [0.0, 0.0, 0.0], [np.nan, 0, 0], [0.3, -0.2, 0.1]])
+    k = np.array([[1.0, 0, 0], [1.0, 0, 0], [1.0, 0, 0], [-1.0, 0, 0], [1.0, 0, 0],
+                  [1 / np.sqrt(3)] * 3, [1.0, 0, 0], [0.0, 1e-25, 1.0]])
+    rc, tau, tot, cell, length, nseg = E.trace(box, n, np.ones(64), 1.0, 0, o, k, max_seg=2)
+    assert rc == -2  # the wall-plane ray crosses 4 cells
+    tau_o, _, cell_o, _, nseg_o = orc.trace(box, n, np.ones(64), 1.0, o[:6], k[:6], max_seg=4)
+    np.testing.assert_allclose(tau[:6], tau_o, rtol=1e-14, atol=1e-15)
+    np.testing.assert_array_equal(nseg[:6], nseg_o)
+    assert tau[6] == 0.0 and nseg[6] == 0  # non-finite origin: no walk
+    assert abs(tau[7] - 0.9) < 1e-14  # a component below 1e-20 counts as parallel
+    rc, tau, tot, *_ = E.trace(box, n, np.ones(64), 1.0, 0, np.zeros((0, 3)), np.zeros((0, 3)))
+    assert rc == 0 and tot == 0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("iso", [True, False])
+def test_peel(E, orc, W, prec, iso):
+    box, n = (-20, 20, -20, 20, -2, 2), (40, 36, 12)
+    rho = W.exp_disk_density(box, n, 2.0, 6.0, 0.25)
+    if prec:
+        rho = W.as_f32_values(rho)
+    pos, din, w = W.random_events(4011, box, seed=5, isotropic=iso)
+    dets = [W.frame(1e4, inc, 33, 31, 20.0, 20.0) for inc in (0.0, 60.0, 90.0)] + [
+        W.frame(1e4, 37.0, 16, 16, 10.0, 8.0, azim=25.0, pa=30.0)]
+    ref = orc.peel(box, n, rho, 1.1, 0.6, pos, din, w, dets)
+    got = E.peel(box, n, rho, 1.1, 0.6, prec, pos, din, w, dets)
+    assert rel_l1(got, ref) < (1e-12 if prec == 0 else 1e-6)
+    np.testing.assert_array_equal(got != 0, ref != 0)
+
+
+def _compare(E, orc, prob, tol):
+    images, absorbed, st = E.run(prob)
+    img_o, abs_o, st_o = orc.run(prob)
+    assert rel_l1(images, img_o) < tol, rel_l1(images, img_o)
+    if absorbed is not None:
+        assert rel_l1(absorbed, abs_o) < tol, rel_l1(absorbed, abs_o)
+    for key in ("emitted", "absorbed", "escaped", "truncated"):
+        assert abs(st[key] - st_o[key]) <= max(tol, 1e-12) * 10 * st_o["emitted"], (key, st[key], st_o[key])
+    for key in ("packages",):
+        assert st[key] == st_o[key]
+    for key in ("events", "x_path", "x_locate", "x_peel"):
+        assert abs(st[key] - st_o[key]) <= 1e-4 * st_o[key] + 2, (key, st[key], st_o[key])
+    return images, absorbed, st
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_run_cube(E, orc, W, prec):
+    prob = W.cube(n_packages=6000, precision=prec, flags=W.FLAGS_DEFAULT | W.FLAG_SPLIT)
+    images, _, st = _compare(E, orc, prob, 1e-10 if prec == 0 else 1e-5)
+    assert abs(images[0, 0].reshape(64, 64)[32, 32] - np.exp(-1) / (400 * np.pi)) < 1e-6 * 2.93e-4
+    closure = st["absorbed"] + st["escaped"] + st["truncated"] - st["emitted"]
+    assert abs(closure) < (1e-12 if prec == 0 else 1e-6) * st["emitted"]
+
+
+def test_run_multiwavelength_two_sources(E, orc, W):
+    prob = W.small_problem(n=(10, 7, 6), box=(-1.0, 1.5, -1.0, 1.0, -0.8, 0.8),
+                           rho=W.lognormal_density((10, 7, 6), 1.0, seed=4), kappa=[0.5, 1.0, 2.5],
+                           albedo=[0.9, 0.5, 0.0], g=[0.7, 0.0, -0.3],
+                           sources=[W.point((0.2, 0.1, -0.3), [1.0, 2.0, 0.5]), W.expdisk(0.3, 0.1, [3.0, 1.0, 1.0])],
+                           detectors=[W.frame(10.0, 30.0, 24, 20, 1.5, 1.2, azim=10.0),
+                                      W.frame(10.0, 90.0, 17, 9, 1.5, 1.0, pa=20.0)],
+                           n_packages=2003, flags=W.FLAGS_DEFAULT | W.FLAG_SPLIT)
+    _compare(E, orc, prob, 1e-10)
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2, 3, 4, 7])
+def test_run_flags(E, orc, W, flags):
+    prob = W.small_problem(n=(8, 8, 8), rho=W.lognormal_density((8, 8, 8), 0.7, seed=6),
+                           detectors=[W.frame(10.0, 45.0, 16, 16, 1.0, 1.0)], n_packages=1001, flags=flags)
+    _compare(E, orc, prob, 1e-10)
+
+
+def test_run_no_frames_and_empty_medium(E, orc, W):
+    prob = W.small_problem(n=(5, 5, 5), detectors=[], n_packages=500)
+    _compare(E, orc, prob, 1e-10)
+    prob = W.small_problem(n=(5, 5, 5), rho=np.zeros((5, 5, 5)), n_packages=500, sources=[W.expdisk(0.5, 0.2)])
+    images, absorbed, st = _compare(E, orc, prob, 1e-10)
+    assert st["events"] == 0 and st["escaped"] == pytest.approx(st["emitted"], rel=1e-14)
+
+
+def test_run_wave_sizes_and_batches_agree(E, W):
+    prob = W.small_problem(n=(9, 9, 9), rho=W.lognormal_density((9, 9, 9), 1.0, seed=3), n_packages=1500)
+    ref, ref_a, ref_s = E.run(prob)
+    for wave, batch in ((1, 0), (7, 3), (64, 1), (64, 64)):
+        im, ab, st = E.run(prob, wave=wave, event_batch=batch)
+        assert rel_l1(im, ref) < 1e-12 and rel_l1(ab, ref_a) < 1e-12
+        assert st["x_path"] == ref_s["x_path"] and st["events"] == ref_s["events"]
+
+
+def test_run_spiral_full_grid_subset(E, orc, W):
+    prob = W.spiral(n_packages=800, precision=1)
+    prob["first_package"] = 7_654_321
+    _compare(E, orc, prob, 1e-5)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_backward(E, orc, W, prec):
+    n = (10, 10, 10)
+    prob = W.small_problem(n=n, rho=W.lognormal_density(n, 0.8, seed=31, f32=(prec == 1)), kappa=1.2, albedo=0.7,
+                           g=0.45, sources=[W.point((0.13, -0.21, 0.07))],
+                           detectors=[W.frame(10.0, 30.0, 24, 24, 1.0, 1.0, azim=20.0),
+                                      W.frame(10.0, 90.0, 16, 16, 1.2, 1.2)],
+                           n_packages=1200, flags=W.FLAG_PEEL_EMIT | W.FLAG_PEEL_SCAT, w_min=1e-3, max_scatter=50,
+                           precision=prec)
+    img_o, _, _ = orc.run(prob)
+    target = img_o * (1 + 0.3 * np.random.default_rng(5).standard_normal(img_o.shape))
+    adj = 2 * (img_o - target)
+    g_o, _, st_o = orc.grad(prob, adj)
+    g, st = E.grad(prob, adj)
+    assert rel_l1(g, g_o) < (1e-9 if prec == 0 else 1e-5), rel_l1(g, g_o)
+    assert st["packages"] == st_o["packages"]
+    g0, _ = E.grad(prob, np.zeros_like(adj))
+    assert np.all(g0 == 0)
+
+
+def test_backward_split_and_multi_lambda(E, orc, W):
+    prob = W.small_problem(n=(7, 6, 5), rho=W.lognormal_density((7, 6, 5), 0.6, seed=2), kappa=[0.8, 1.5],
+                           albedo=[0.6, 0.3], g=[0.5, -0.2], detectors=[W.frame(10.0, 20.0, 12, 10, 1.0, 1.0)],
+                           n_packages=700, flags=W.FLAG_PEEL_EMIT | W.FLAG_PEEL_SCAT | W.FLAG_SPLIT)
+    img_o, _, _ = orc.run(prob)
+    adj = np.random.default_rng(2).standard_normal(img_o.shape)
+    g_o, _, _ = orc.grad(prob, adj)
+    g, _ = E.grad(prob, adj)
+    assert rel_l1(g, g_o) < 1e-9

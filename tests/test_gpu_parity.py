@@ -1,0 +1,253 @@
+"""Parity of the HIP path (called through the C ABI) with the FP64 CPU
+oracle on the same seeded inputs.
+
+Tolerances: FP64 path 1e-10 relative L1 (differences come from libm ulps
+and the order of FP64 atomic additions); FP32 traversal with FP64 state
+and tallies 1e-5 relative L1 (the FP32 rounding of optical depths and of
+in-cell offsets, about 1e-7 per crossing, plus the rare pixel moves it
+causes).  Pixel and cell indices are compared exactly where they are
+decided in FP64 by both sides.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l1(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    den = np.abs(b).sum()
+    return float(np.abs(a - b).sum() / den) if den > 0 else float(np.abs(a).sum())
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    from paper_1410_1629_amd import binding
+    binding.load()
+    assert torch.cuda.is_available()
+    return binding
+
+
+def _dev(x, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype or torch.float64).cuda()
+
+
+def _say(msg):
+    print("[gpu] " + msg, flush=True)
+
+
+# ------------------------------------------------------------------ trace_path
+
+TRACE_CASES = [
+    ("uniform32", (-1, 1, -1, 1, -1, 1), (32, 32, 32), None, 1.0),
+    ("lognormal_ragged", (-2.0, 1.0, 0.0, 3.0, -1.0, 0.5), (9, 6, 5), 9, 0.7),
+    ("flat", (-20, 20, -20, 20, -2, 2), (64, 3, 17), 4, 1.3),
+    ("one_cell", (-1, 1, -1, 1, -1, 1), (1, 1, 1), 5, 2.0),
+]
+
+
+@pytest.mark.parametrize("name,box,n,seed,kappa", TRACE_CASES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_trace_matches_oracle(B, orc, W, name, box, n, seed, kappa, prec):
+    import torch
+    _say("trace %s prec=%d" % (name, prec))
+    rho = np.ones(n[::-1]) if seed is None else W.lognormal_density(n, 1.0, seed=seed, f32=(prec == 1))
+    o, k = W.random_rays(3001, box, seed=17)
+    max_seg = int(sum(n)) + 4
+    tau_o, tot_o, cell_o, len_o, nseg_o = orc.trace(box, n, rho, kappa, o, k, max_seg=max_seg)
+    prob = {"box": box, "n": n}
+    drho = _dev(rho.reshape(-1), torch.float32 if prec else torch.float64)
+    tau = torch.empty(len(o), dtype=torch.float64, device="cuda")
+    cell = torch.empty((len(o), max_seg), dtype=torch.int32, device="cuda")
+    length = torch.empty((len(o), max_seg), dtype=torch.float64, device="cuda")
+    nseg = torch.empty(len(o), dtype=torch.int32, device="cuda")
+    tot = B.trace_path(prob, drho, kappa, prec, _dev(o), _dev(k), tau, max_seg, cell, length, nseg)
+    tau, cell, length, nseg = tau.cpu().numpy(), cell.cpu().numpy(), length.cpu().numpy(), nseg.cpu().numpy()
+    tol = 1e-12 if prec == 0 else 2e-6
+    np.testing.assert_allclose(tau, tau_o, rtol=tol, atol=tol * max(1.0, tau_o.max()) * 1e-3)
+    # segment lists: identical cells for every ray whose walk has no near-tie
+    same = nseg == nseg_o
+    assert same.mean() > (0.999 if prec == 0 else 0.99), same.mean()
+    for q in np.nonzero(same)[0]:
+        m = nseg[q]
+        if not np.array_equal(cell[q, :m], cell_o[q, :m].astype(np.int32)):
+            # allowed only where the two sides split a tie differently: tiny segments
+            assert min(len_o[q, :m].min(), length[q, :m].min()) < 1e-6 * max(box[1] - box[0], 1.0)
+            continue
+        # lengths are differences of crossing times: absolute rounding scales with the box
+        np.testing.assert_allclose(length[q, :m], len_o[q, :m], rtol=tol, atol=tol * max(box[1] - box[0], 1.0))
+    assert abs(tot - tot_o) <= 1e-3 * tot_o + 2
+
+
+def test_trace_edge_cases(B, orc, W):
+    import torch
+    _say("trace edge cases")
+    prob = {"box": (-1, 1, -1, 1, -1, 1), "n": (4, 4, 4)}
+    rho = _dev(np.ones(64))
+    empty = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    assert B.trace_path(prob, rho, 1.0, 0, empty, empty, torch.empty(0, dtype=torch.float64, device="cuda")) == 0
+    # rays that miss, leave immediately, lie in a wall, start on a wall
+    o = np.array([[2.0, 0, 0], [1.0, 0, 0], [-1.0, 0.0, 0.1], [0.0, 0.1, 0.1], [0.0, 0.1, 0.1]])
+    k = np.array([[1.0, 0, 0], [1.0, 0, 0], [1.0, 0, 0], [-1.0, 0, 0], [1.0, 0, 0]])
+    tau = torch.empty(5, dtype=torch.float64, device="cuda")
+    cell = torch.zeros((5, 2), dtype=torch.int32, device="cuda")
+    length = torch.zeros((5, 2), dtype=torch.float64, device="cuda")
+    nseg = torch.empty(5, dtype=torch.int32, device="cuda")
+    with pytest.raises(B.McrtError) as ei:  # the wall-plane ray crosses 4 cells: overflow of max_seg = 2
+        B.trace_path(prob, rho, 1.0, 0, _dev(o), _dev(k), tau, 2, cell, length, nseg)
+    assert ei.value.code == B.EOVERFLOW
+    tau_o, _, cell_o, _, nseg_o = orc.trace(prob["box"], prob["n"], np.ones(64), 1.0, o, k, max_seg=4)
+    np.testing.assert_allclose(tau.cpu().numpy(), tau_o, rtol=1e-14, atol=1e-15)
+    np.testing.assert_array_equal(nseg.cpu().numpy(), nseg_o)
+    np.testing.assert_array_equal(cell.cpu().numpy()[3:, :2], cell_o[3:, :2])
+
+
+# ------------------------------------------------------------------ peel_off
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("iso", [True, False])
+def test_peel_matches_oracle(B, orc, W, prec, iso):
+    import torch
+    _say("peel prec=%d iso=%s" % (prec, iso))
+    box, n = (-20, 20, -20, 20, -2, 2), (40, 36, 12)
+    rho = W.exp_disk_density(box, n, 2.0, 6.0, 0.25)
+    if prec:
+        rho = W.as_f32_values(rho)
+    pos, din, w = W.random_events(20011, box, seed=5, isotropic=iso)
+    dets = [W.frame(1e4, inc, 33, 31, 20.0, 20.0) for inc in (0.0, 60.0, 90.0)] + [
+        W.frame(1e4, 37.0, 16, 16, 10.0, 8.0, azim=25.0, pa=30.0)]
+    ref = orc.peel(box, n, rho, 1.1, 0.6, pos, din, w, dets)
+    img = torch.zeros(ref.size, dtype=torch.float64, device="cuda")
+    B.peel_off({"box": box, "n": n}, _dev(rho.reshape(-1), torch.float32 if prec else torch.float64), 1.1, 0.6,
+               prec, _dev(pos), None if din is None else _dev(din), _dev(w), dets, img)
+    got = img.cpu().numpy()
+    assert rel_l1(got, ref) < (1e-12 if prec == 0 else 1e-6), rel_l1(got, ref)
+    np.testing.assert_array_equal(got != 0, ref != 0)
+
+
+# ------------------------------------------------------------------ run_photons
+
+def _compare_run(B, orc, prob, tol_img, tol_abs):
+    images, absorbed, st = B.render(prob)
+    img_o, abs_o, st_o = orc.run(prob)
+    e_img = rel_l1(images.cpu().numpy(), img_o)
+    e_abs = rel_l1(absorbed.cpu().numpy(), abs_o) if absorbed is not None else 0.0
+    _say("  rel_L1 images %.3e absorbed %.3e" % (e_img, e_abs))
+    assert e_img < tol_img, e_img
+    assert e_abs < tol_abs, e_abs
+    for key in ("emitted", "absorbed", "escaped", "truncated"):
+        assert abs(st[key] - st_o[key]) <= max(tol_abs, 1e-12) * st_o["emitted"] * 10, (key, st[key], st_o[key])
+    assert st["packages"] == st_o["packages"]
+    for key in ("events", "x_path", "x_locate", "x_peel"):
+        assert abs(st[key] - st_o[key]) <= 1e-4 * st_o[key] + 2, (key, st[key], st_o[key])
+    closure = st["absorbed"] + st["escaped"] + st["truncated"] - st["emitted"]
+    assert abs(closure) < 1e-6 * st["emitted"] if prob["precision"] else abs(closure) < 1e-12 * st["emitted"]
+    return images, absorbed, st, img_o, abs_o
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_run_cube_matches_oracle(B, orc, W, prec):
+    _say("run cube prec=%d" % prec)
+    prob = W.cube(n_packages=20_000, precision=prec, flags=W.FLAGS_DEFAULT | W.FLAG_SPLIT)
+    images, _, st, img_o, _ = _compare_run(B, orc, prob, 1e-10 if prec == 0 else 1e-5, 1e-10 if prec == 0 else 1e-5)
+    direct = images.cpu().numpy()[0, 0].reshape(64, 64)
+    expect = np.exp(-1.0) / (4 * np.pi * 100)
+    assert abs(direct[32, 32] - expect) < (1e-13 if prec == 0 else 1e-6) * expect
+
+
+def test_run_multiwavelength_two_sources(B, orc, W):
+    _say("run multi-lambda two sources")
+    prob = W.small_problem(n=(10, 7, 6), box=(-1.0, 1.5, -1.0, 1.0, -0.8, 0.8),
+                           rho=W.lognormal_density((10, 7, 6), 1.0, seed=4), kappa=[0.5, 1.0, 2.5],
+                           albedo=[0.9, 0.5, 0.0], g=[0.7, 0.0, -0.3],
+                           sources=[W.point((0.2, 0.1, -0.3), [1.0, 2.0, 0.5]), W.expdisk(0.3, 0.1, [3.0, 1.0, 1.0])],
+                           detectors=[W.frame(10.0, 30.0, 24, 20, 1.5, 1.2, azim=10.0),
+                                      W.frame(10.0, 90.0, 17, 9, 1.5, 1.0, pa=20.0)],
+                           n_packages=4003, flags=W.FLAGS_DEFAULT | W.FLAG_SPLIT)
+    _compare_run(B, orc, prob, 1e-10, 1e-10)
+
+
+@pytest.mark.parametrize("flags", [1, 2, 3, 4, 7])
+def test_run_flag_combinations(B, orc, W, flags):
+    _say("run flags=%d" % flags)
+    prob = W.small_problem(n=(8, 8, 8), rho=W.lognormal_density((8, 8, 8), 0.7, seed=6),
+                           detectors=[W.frame(10.0, 45.0, 16, 16, 1.0, 1.0)], n_packages=2001, flags=flags)
+    img_o, abs_o, st_o = orc.run(prob)
+    images, absorbed, st = B.render(prob)
+    if flags & 3:
+        assert rel_l1(images.cpu().numpy(), img_o) < 1e-10
+    if flags & 4:
+        assert rel_l1(absorbed.cpu().numpy(), abs_o) < 1e-10
+    assert abs(st["escaped"] - st_o["escaped"]) < 1e-12 * st_o["emitted"]
+
+
+def test_run_sharding_and_resume(B, W):
+    # packages are identified by their index: [0, N) equals the weighted sum
+    # of [0, M) and [M, N) run separately
+    _say("run sharding")
+    N, M = 6000, 2500
+    prob = W.small_problem(n=(12, 12, 12), rho=W.lognormal_density((12, 12, 12), 1.0, seed=8), n_packages=N)
+    i_all, a_all, s_all = B.render(prob)
+    i_a, a_a, s_a = B.render(dict(prob, n_packages=M))
+    i_b, a_b, s_b = B.render(dict(prob, n_packages=N - M, first_package=M))
+    comb = (M * i_a + (N - M) * i_b) / N
+    assert rel_l1(comb.cpu().numpy(), i_all.cpu().numpy()) < 1e-12
+    assert rel_l1(((M * a_a + (N - M) * a_b) / N).cpu().numpy(), a_all.cpu().numpy()) < 1e-12
+    for key in ("x_path", "x_locate", "x_peel", "events", "packages"):
+        assert s_all[key] == s_a[key] + s_b[key]
+
+
+def test_run_spiral_full_grid_subset(B, orc, W):
+    # the edge-on spiral at its full size (256x256x64 cells, three 512x512
+    # frames, FP32 traversal): a package subset from deep inside the run
+    _say("run spiral full grid subset")
+    prob = W.spiral(n_packages=3000, precision=1)
+    prob["first_package"] = 7_654_321
+    _compare_run(B, orc, prob, 1e-5, 1e-5)
+
+
+def test_run_spiral_full_size_properties(B, W):
+    # full package count in the benchmark's launch configuration: energy
+    # closes, every package is accounted for, images are finite and positive
+    _say("run spiral 1e7 packages")
+    prob = W.spiral(n_packages=10_000_000, precision=1)
+    images, absorbed, st = B.render(prob)
+    assert st["packages"] == 10_000_000
+    closure = st["absorbed"] + st["escaped"] + st["truncated"] - st["emitted"]
+    assert abs(closure) < 1e-6 * st["emitted"], closure
+    assert abs(absorbed.sum().item() - st["absorbed"]) < 1e-9 * st["emitted"]
+    im = images.cpu().numpy()
+    assert np.isfinite(im).all() and (im >= 0).all() and im.sum() > 0
+
+
+# ------------------------------------------------------------------ backward_density
+
+def _adj_problem(W, prec, N=3000):
+    n = (10, 10, 10)
+    rho = W.lognormal_density(n, 0.8, seed=31, f32=(prec == 1))
+    return W.small_problem(n=n, rho=rho, kappa=1.2, albedo=0.7, g=0.45, sources=[W.point((0.13, -0.21, 0.07))],
+                           detectors=[W.frame(10.0, 30.0, 24, 24, 1.0, 1.0, azim=20.0),
+                                      W.frame(10.0, 90.0, 16, 16, 1.2, 1.2)],
+                           n_packages=N, flags=W.FLAG_PEEL_EMIT | W.FLAG_PEEL_SCAT, w_min=1e-3, max_scatter=50,
+                           precision=prec)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_backward_matches_oracle(B, orc, W, prec):
+    import torch
+    _say("backward prec=%d" % prec)
+    prob = _adj_problem(W, prec)
+    img_o, _, _ = orc.run(prob)
+    target = img_o * (1 + 0.3 * np.random.default_rng(5).standard_normal(img_o.shape))
+    adj = 2 * (img_o - target)
+    g_o, _, st_o = orc.grad(prob, adj)
+    rho = B.density_tensor(prob)
+    grad = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
+    st = B.backward_density(prob, rho, _dev(adj), grad)
+    g = grad.cpu().numpy()
+    e = rel_l1(g, g_o)
+    _say("  rel_L1 grad %.3e" % e)
+    assert e < (1e-9 if prec == 0 else 1e-5), e
+    assert st["packages"] == st_o["packages"]
