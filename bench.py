@@ -83,10 +83,15 @@ def cpu_baseline(prob, seconds):
         oracle.grad(p, adj, threads=threads)
         return time.perf_counter() - t0
 
-    n0 = max(200, 50 * threads)
-    t0 = timed(n0)
-    n = int(min(max(n0, n0 * seconds / max(t0, 1e-3)), 2_000_000))
-    t = timed(n)
+    n, t = max(200, 50 * threads), 0.0
+    while True:  # grow the sample until it takes a second, then size it to the target
+        t = timed(n)
+        if t >= 1.0 or n >= 2_000_000:
+            break
+        n *= 4
+    if t < seconds and n < 2_000_000:
+        n = int(min(n * seconds / max(t, 1e-3), 2_000_000))
+        t = timed(n)
     return {"value": n / t, "unit": "packages/s", "cores": threads, "kind": "oracle",
             "sample": "first %d packages of the same workload, FP64 forward run + gradient, %.1f s" % (n, t)}
 

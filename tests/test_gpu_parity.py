@@ -251,3 +251,22 @@ def test_backward_matches_oracle(B, orc, W, prec):
     _say("  rel_L1 grad %.3e" % e)
     assert e < (1e-9 if prec == 0 else 1e-5), e
     assert st["packages"] == st_o["packages"]
+
+
+# ------------------------------------------------------------------ autograd
+
+def test_autograd_function_matches_oracle_gradient(B, orc, W):
+    import torch
+    from paper_1410_1629_amd import autograd
+    _say("autograd RTImage")
+    prob = _adj_problem(W, 0, N=2000)
+    img_o, _, _ = orc.run(prob)
+    target = torch.as_tensor(img_o * 0.8).cuda()
+    rho = B.density_tensor(prob).requires_grad_(True)
+    images = autograd.render(prob, rho)
+    loss = ((images - target) ** 2).sum()
+    loss.backward()
+    adj = 2 * (img_o - img_o * 0.8)
+    g_o, _, _ = orc.grad(prob, adj)
+    assert rel_l1(images.detach().cpu().numpy(), img_o) < 1e-10
+    assert rel_l1(rho.grad.cpu().numpy(), g_o) < 1e-9
