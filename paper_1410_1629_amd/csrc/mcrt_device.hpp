@@ -43,7 +43,7 @@ constexpr double kParallel = 1e-20;
 // Problem data, prepared by the host in FP64.
 
 struct GridDev {
-  double lo[3], hi[3], d[3];
+  double lo[3], hi[3], d[3], inv_d[3];
   int n[3];
   int stride[3];  // 1, nx, nx*ny
   int ncell;
@@ -51,7 +51,7 @@ struct GridDev {
 
 struct DetDev {
   double kd[3], ex[3], ey[3];  // towards the observer; image axes
-  double inv_d2, half_x, half_y, dpx, dpy;
+  double inv_d2, half_x, half_y, inv_dpx, inv_dpy;  // pixels per unit length
   int nx, ny;
   long long off;  // offset of this frame inside one wavelength's image block
 };
@@ -173,8 +173,8 @@ MCRT_HD void source_position(const SrcDev& S, const U4& w, double r[3]) {
 MCRT_HD int frame_pixel(const DetDev& D, const double r[3]) {
   const double xp = r[0] * D.ex[0] + r[1] * D.ex[1] + r[2] * D.ex[2];
   const double yp = r[0] * D.ey[0] + r[1] * D.ey[1] + r[2] * D.ey[2];
-  const double fx = floor((xp + D.half_x) / D.dpx);
-  const double fy = floor((yp + D.half_y) / D.dpy);
+  const double fx = floor((xp + D.half_x) * D.inv_dpx);
+  const double fy = floor((yp + D.half_y) * D.inv_dpy);
   if (!(fx >= 0.0 && fx < (double)D.nx && fy >= 0.0 && fy < (double)D.ny)) return -1;
   return (int)fy * D.nx + (int)fx;
 }
@@ -194,15 +194,14 @@ MCRT_HD int frame_pixel(const DetDev& D, const double r[3]) {
 // leaves the grid along a: the walk ends as soon as some j[a] exceeds
 // lim[a], and while every j[a] <= lim[a] the cell is inside the grid.
 // Axes parallel to the ray have t0 = +inf, dt = 0, step 0 and a limit that
-// is never reached.  The current cell is `cell`; its density is prefetched
-// into rho_cur.
+// is never reached.  The current cell is `cell`.
 
 template <typename R>
 struct Ray {
   R t0[3], dt[3];
   int j[3], lim[3], step[3];
   int cell;
-  R t, tau, rho_cur;
+  R t, tau;
   double tin;  // FP64 entry time (0 for rays starting inside)
   bool active;
 };
@@ -222,14 +221,16 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, Mem& M, const double o[3], 
   bool miss = !(std::isfinite(o[0]) && std::isfinite(o[1]) && std::isfinite(o[2]) && std::isfinite(k[0]) &&
                 std::isfinite(k[1]) && std::isfinite(k[2]));
   bool par[3];
+  double inv[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     par[a] = !(fabs(k[a]) >= kParallel);
+    inv[a] = par[a] ? 0.0 : 1.0 / k[a];
     if (par[a]) {
       if (!(o[a] >= G.lo[a] && o[a] < G.hi[a])) miss = true;
     } else {
-      const double ta = (G.lo[a] - o[a]) / k[a];
-      const double tb = (G.hi[a] - o[a]) / k[a];
+      const double ta = (G.lo[a] - o[a]) * inv[a];
+      const double tb = (G.hi[a] - o[a]) * inv[a];
       const double tn = fmin(ta, tb), tf = fmax(ta, tb);
       if (tn > tin) {
         tin = tn;
@@ -254,7 +255,7 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, Mem& M, const double o[3], 
       i = k[a] > 0.0 ? 0 : G.n[a] - 1;
     } else {
       const double p = o[a] + tin * k[a];
-      const double x = (p - G.lo[a]) / G.d[a];
+      const double x = (p - G.lo[a]) * G.inv_d[a];
       const double fx = floor(x);
       i = (int)fmin(fmax(fx, -1.0), (double)G.n[a]);
       if (!par[a] && k[a] < 0.0 && x == fx) i -= 1;
@@ -268,13 +269,13 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, Mem& M, const double o[3], 
       ry.lim[a] = 1 << 30;
       ry.step[a] = 0;
     } else if (k[a] > 0.0) {
-      ry.t0[a] = (R)((G.lo[a] + (double)(i + 1) * G.d[a] - o[a]) / k[a] - tin);
-      ry.dt[a] = (R)(G.d[a] / k[a]);
+      ry.t0[a] = (R)((G.lo[a] + (double)(i + 1) * G.d[a] - o[a]) * inv[a] - tin);
+      ry.dt[a] = (R)(G.d[a] * inv[a]);
       ry.lim[a] = G.n[a] - 1 - i;
       ry.step[a] = G.stride[a];
     } else {
-      ry.t0[a] = (R)((G.lo[a] + (double)i * G.d[a] - o[a]) / k[a] - tin);
-      ry.dt[a] = (R)(-G.d[a] / k[a]);
+      ry.t0[a] = (R)((G.lo[a] + (double)i * G.d[a] - o[a]) * inv[a] - tin);
+      ry.dt[a] = (R)(-G.d[a] * inv[a]);
       ry.lim[a] = i;
       ry.step[a] = -G.stride[a];
     }
@@ -283,7 +284,6 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, Mem& M, const double o[3], 
   ry.t = R(0);
   ry.tin = tin;
   ry.tau = R(0);
-  ry.rho_cur = M.rho(cell);
   ry.active = true;
 }
 
@@ -299,24 +299,62 @@ MCRT_HD R ray_tnext(const Ray<R>& ry) {
   return fmin(ray_tplane(ry, 0), fmin(ray_tplane(ry, 1), ray_tplane(ry, 2)));
 }
 
-// Moves into the next cell (all axes whose plane is reached at tm advance
-// together); returns true when the walk has left the grid, which is when
-// some axis has crossed more planes than it had ahead inside the grid, or
-// when no axis matched tm (non-finite times).  Prefetches the density of the
-// new cell (of the old one again when leaving, so no load leaves the grid).
-template <typename R, class Mem>
-MCRT_HD bool ray_advance(Ray<R>& ry, R tm, Mem& M) {
-  const bool ax = ray_tplane(ry, 0) == tm;
-  const bool ay = ray_tplane(ry, 1) == tm;
-  const bool az = ray_tplane(ry, 2) == tm;
-  const int old = ry.cell;
-  ry.cell += (ax ? ry.step[0] : 0) + (ay ? ry.step[1] : 0) + (az ? ry.step[2] : 0);
-  ry.j[0] += ax;
-  ry.j[1] += ay;
-  ry.j[2] += az;
-  const bool out = imax3(ry.j[0] - ry.lim[0], ry.j[1] - ry.lim[1], ry.j[2] - ry.lim[2]) > 0 || !(ax || ay || az);
-  ry.rho_cur = M.rho(out ? old : ry.cell);
-  return out;
+// The next D cells of the walk, as a block: their indices, the end times of
+// their segments and their densities.  The cell sequence of a walk does not
+// depend on the densities, so the block first advances the walk D times
+// (pure arithmetic: all axes whose plane is reached at the segment's end
+// advance together) and then issues the D density loads back to back, which
+// keeps D gathers in flight per lane instead of one.  The walk leaves the
+// grid when some axis has crossed more planes than it had ahead inside it,
+// or when no axis matched the end time (non-finite times); sub-steps after
+// that repeat the last valid cell, so no load leaves the grid.  `adv` keeps
+// the axes that advanced at each sub-step (3 bits each) so that a caller
+// stopping inside the block can rewind the plane counts (ray_rewind).
+template <int D, typename R>
+struct WalkBlock {
+  int cell[D];
+  R tend[D];
+  R rho[D];
+  int n;         // valid entries (>= 1 for an active ray)
+  unsigned adv;  // axes advanced at sub-step d: bits 3d .. 3d+2
+  bool out;      // the walk has left the grid after entry n-1
+};
+
+template <int D, typename R, class Mem>
+MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, Mem& M) {
+  b.n = 0;
+  b.adv = 0;
+  b.out = false;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const R tx = ray_tplane(ry, 0), ty = ray_tplane(ry, 1), tz = ray_tplane(ry, 2);
+    const R tm = fmin(tx, fmin(ty, tz));
+    const bool live = !b.out;
+    const bool ax = live && tx == tm, ay = live && ty == tm, az = live && tz == tm;
+    b.cell[d] = live ? ry.cell : b.cell[d > 0 ? d - 1 : 0];
+    b.tend[d] = live ? tm : b.tend[d > 0 ? d - 1 : 0];
+    ry.cell += (ax ? ry.step[0] : 0) + (ay ? ry.step[1] : 0) + (az ? ry.step[2] : 0);
+    ry.j[0] += ax;
+    ry.j[1] += ay;
+    ry.j[2] += az;
+    b.adv |= ((unsigned)ax | ((unsigned)ay << 1) | ((unsigned)az << 2)) << (3 * d);
+    b.n += live;
+    b.out = b.out || imax3(ry.j[0] - ry.lim[0], ry.j[1] - ry.lim[1], ry.j[2] - ry.lim[2]) > 0 || !(ax || ay || az);
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) b.rho[d] = M.rho(b.cell[d]);
+}
+
+// Undoes the plane crossings of sub-steps d .. D-1 of the last block, so the
+// ray's counts again describe the walk inside cell b.cell[d].
+template <int D, typename R>
+MCRT_HD void ray_rewind(Ray<R>& ry, const WalkBlock<D, R>& b, int d) {
+  for (int e = d; e < D; ++e) {
+    const unsigned m = b.adv >> (3 * e);
+    ry.j[0] -= (int)(m & 1u);
+    ry.j[1] -= (int)((m >> 1) & 1u);
+    ry.j[2] -= (int)((m >> 2) & 1u);
+  }
 }
 
 // FP64 entry time of the current cell, in the original parametrisation of

@@ -57,6 +57,7 @@ inline GridDev make_grid(const mcrt_grid& g) {
     G.hi[a] = b[2 * a + 1];
     G.n[a] = n[a];
     G.d[a] = (G.hi[a] - G.lo[a]) / n[a];
+    G.inv_d[a] = 1.0 / G.d[a];
   }
   G.stride[0] = 1;
   G.stride[1] = g.nx;
@@ -101,8 +102,8 @@ inline DetDev make_det(const mcrt_detector& D, long long off) {
   R.inv_d2 = 1.0 / (D.distance * D.distance);
   R.half_x = D.half_x;
   R.half_y = D.half_y;
-  R.dpx = 2.0 * D.half_x / D.nx;
-  R.dpy = 2.0 * D.half_y / D.ny;
+  R.inv_dpx = D.nx / (2.0 * D.half_x);
+  R.inv_dpy = D.ny / (2.0 * D.half_y);
   R.nx = D.nx;
   R.ny = D.ny;
   R.off = off;

@@ -55,16 +55,44 @@ __device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int
   return ((unsigned long long)hi << 32) | lo;
 }
 
-// One item for every calling lane, with one atomic per wavefront.
-__device__ __forceinline__ unsigned long long wave_fetch(unsigned long long* counter) {
+// One work item for every calling lane.  Each wavefront keeps a reservoir
+// [res[0], res[1]) of items in LDS, touched only by its leading calling lane,
+// and refills it with one global atomic per `chunk` items, so the single
+// global counter sees few, large requests.
+__device__ __forceinline__ unsigned long long wave_fetch(unsigned long long* counter, unsigned long long* res,
+                                                         unsigned chunk) {
   const unsigned long long m = __ballot(1);
   const int lane = __lane_id();
   const int leader = __ffsll((long long)m) - 1;
-  const int rank = __popcll(m & ((1ull << lane) - 1ull));
-  unsigned long long base = 0;
-  if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
-  base = shfl_u64(base, leader);
-  return base + (unsigned long long)rank;
+  const unsigned rank = __popcll(m & ((1ull << lane) - 1ull));
+  const unsigned cnt = __popcll(m);
+  unsigned long long a = 0, avail = 0, nb = 0;
+  if (lane == leader) {
+    a = res[0];
+    avail = res[1] - a;
+    if (avail >= cnt) {
+      res[0] = a + cnt;
+    } else {
+      const unsigned long long need = cnt - avail, take = need > chunk ? need : chunk;
+      nb = atomicAdd(counter, take);
+      res[0] = nb + need;
+      res[1] = nb + take;
+    }
+  }
+  a = shfl_u64(a, leader);
+  avail = shfl_u64(avail, leader);
+  nb = shfl_u64(nb, leader);
+  return rank < avail ? a + rank : nb + (rank - avail);
+}
+
+constexpr int kWavesPerBlock = kBlock / 64;
+
+// Per-wavefront reservoir slots in LDS; lane 0 of each wavefront empties its
+// slot before the wavefront's first fetch.
+__device__ __forceinline__ unsigned long long* wave_reservoir(unsigned long long (&slots)[kWavesPerBlock][2]) {
+  unsigned long long* r = slots[threadIdx.x / 64];
+  if (__lane_id() == 0) r[0] = r[1] = 0;
+  return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -74,6 +102,7 @@ template <typename R>
 struct LifeMem {
   const R* __restrict__ rho_;
   const RunParams& P;
+  unsigned long long* res;
   __device__ R rho(int c) const { return rho_[c]; }
   __device__ const DetDev& det(int d) const { return P.det[d]; }
   __device__ const LamDev& lam(int l) const { return P.lam[l]; }
@@ -82,7 +111,7 @@ struct LifeMem {
   __device__ void add_image(long long i, double v) const { atomic_add_f64(P.images + i, v); }
   __device__ void add_absorbed(long long i, double v) const { atomic_add_f64(P.absorbed + i, v); }
   __device__ void add_grad(int i, double v) const { atomic_add_f64(P.grad + i, v); }
-  __device__ unsigned long long fetch() const { return wave_fetch(P.work); }
+  __device__ unsigned long long fetch() const { return wave_fetch(P.work, res, 64); }
   __device__ void flush_counts(unsigned a, unsigned b, unsigned c, unsigned d) const {
     atomicAdd(P.xstats + 0, (unsigned long long)a);
     atomicAdd(P.xstats + 1, (unsigned long long)b);
@@ -95,8 +124,9 @@ template <typename R>
 struct TraceMem {
   const R* __restrict__ rho_;
   const TraceParams& P;
+  unsigned long long* res;
   __device__ R rho(int c) const { return rho_[c]; }
-  __device__ unsigned long long fetch() const { return wave_fetch(P.work); }
+  __device__ unsigned long long fetch() const { return wave_fetch(P.work, res, 256); }
   __device__ void ray(long long q, double o[3], double k[3]) const {
     for (int a = 0; a < 3; ++a) {
       o[a] = P.origin[3 * q + a];
@@ -117,8 +147,9 @@ template <typename R>
 struct PeelMem {
   const R* __restrict__ rho_;
   const PeelParams& P;
+  unsigned long long* res;
   __device__ R rho(int c) const { return rho_[c]; }
-  __device__ unsigned long long fetch() const { return wave_fetch(P.work); }
+  __device__ unsigned long long fetch() const { return wave_fetch(P.work, res, 256); }
   __device__ const DetDev& det(int d) const { return P.det[d]; }
   __device__ void position(long long e, double r[3]) const {
     for (int a = 0; a < 3; ++a) r[a] = P.pos[3 * e + a];
@@ -137,7 +168,8 @@ struct PeelMem {
 
 template <typename R, bool ADJ>
 __global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
-  LifeMem<R> M{static_cast<const R*>(P.rho), P};
+  __shared__ unsigned long long slots[kWavesPerBlock][2];
+  LifeMem<R> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots)};
   Lane<R> L;
   lane_init(L);
   for (;;) {
@@ -171,7 +203,8 @@ __global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
 
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_trace(const TraceParams P) {
-  TraceMem<R> M{static_cast<const R*>(P.rho), P};
+  __shared__ unsigned long long slots[kWavesPerBlock][2];
+  TraceMem<R> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots)};
   TraceLane<R> L;
   trace_init(L);
   for (;;) {
@@ -194,7 +227,8 @@ __global__ void __launch_bounds__(kBlock) k_trace(const TraceParams P) {
 
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_peel(const PeelParams P) {
-  PeelMem<R> M{static_cast<const R*>(P.rho), P};
+  __shared__ unsigned long long slots[kWavesPerBlock][2];
+  PeelMem<R> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots)};
   PeelLane<R> L;
   peel_init(L);
   for (;;) {

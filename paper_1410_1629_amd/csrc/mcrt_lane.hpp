@@ -85,7 +85,7 @@ struct Lane {
   bool is_emit, found;
   double r[3], k[3];
   double W, w0, kap, alb, g, T, tau_s, wabs;
-  R kapR, tau_sR, absf, tau_prev, rho_hit, last_t;
+  R kapR, tau_sR, absf, trans, tau_prev, rho_hit, last_t;
   unsigned uw1, uw2;
   int hit_cell, last_cell;
   long long lam_cell;
@@ -114,6 +114,7 @@ MCRT_HD void lane_init(Lane<R>& L) {
   L.k[2] = 1.0;
   L.W = L.w0 = L.kap = L.alb = L.g = L.T = L.tau_s = L.wabs = 0.0;
   L.kapR = L.tau_sR = L.absf = L.tau_prev = L.rho_hit = L.last_t = R(0);
+  L.trans = R(1);
   L.uw1 = L.uw2 = 0;
   L.hit_cell = L.last_cell = 0;
   L.lam_cell = 0;
@@ -124,22 +125,163 @@ MCRT_HD void lane_init(Lane<R>& L) {
 }
 
 // Runs the lane's events until its next walk is set up (ry.active) or no
-// work is left (done).
+// work is left (done).  Each pass goes once through the phase blocks in the
+// order in which a package usually moves through them -- end of a peel-off
+// walk, end of the pass-1 walk, end of the locate walk, next frame,
+// termination or turn, next pass-1 walk, end of package, new package -- so
+// a lane whose walk just ended normally reaches its next walk within one
+// pass, and the lanes of a wavefront that are at different events share
+// the pass instead of taking turns.  The walk itself is set up once, at the
+// end of the pass, from the origin, direction and mode the blocks chose.
 template <typename R, bool ADJ, class Mem>
 MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
   const GridDev& G = P.G;
   while (!L.ry.active && !L.done) {
-    switch (L.phase) {
-      case PH_FETCH: {
-        if ((L.x_path | L.x_loc | L.x_peel | L.n_dep) & 0xC0000000u) {  // keep 32-bit counters from wrapping
-          M.flush_counts(L.x_path, L.x_loc, L.x_peel, L.n_dep);
-          L.x_path = L.x_loc = L.x_peel = L.n_dep = 0;
+    bool want = false;  // a walk is to be set up at the end of this pass
+    bool to_det = false;  // towards frame L.det (else along the package direction)
+
+    // -- end of a peel-off walk: the contribution, then the next frame
+    if (L.phase == PH_PEEL_END) {
+      const DetDev& D = M.det(L.det);
+      const double ph = L.is_emit ? 1.0 / (4.0 * kPi)
+                                  : hg_phase(L.g, L.k[0] * D.kd[0] + L.k[1] * D.kd[1] + L.k[2] * D.kd[2]);
+      const double C = L.W * ph * exp(-(double)L.ry.tau) * D.inv_d2;
+      const int comp = ((P.flags & kFlagSplit) && !L.is_emit) ? 1 : 0;
+      const long long ii = ((long long)comp * P.n_lambda + L.lam) * P.pix_lambda + D.off + L.pix;
+      if (L.pass == 0) ++L.n_pl;
+      L.phase = PH_PEEL_NEXT;
+      if (!ADJ) {
+        M.add_image(ii, C);
+        ++L.det;
+      } else {
+        const double ac = M.adj(ii) * C;
+        L.Gacc += ac;
+        if (L.pass == 0) L.Gabs += fabs(ac);
+        if (L.pass == 1 && ac != 0.0) {  // a second walk of the same ray deposits -A C kappa l
+          L.fac = -ac * L.kap;
+          want = to_det = true;
+          L.mode = M_PEEL_DEP;
+          L.phase = PH_PEEL_DEP_END;
+        } else {
+          ++L.det;
         }
-        const unsigned long long item = M.fetch();
-        if (item >= P.n_items) {
-          L.done = true;
-          break;
+      }
+    }
+    if (ADJ && L.phase == PH_PEEL_DEP_END && !want) {
+      ++L.det;
+      L.phase = PH_PEEL_NEXT;
+    }
+
+    // -- end of the pass-1 walk: escape and absorption, forced-scattering depth
+    if (L.phase == PH_PATH_END) {
+      L.T = (double)L.ry.tau;
+      if (L.T == 0.0) {  // nothing to interact with: the package leaves
+        if (L.pass == 0) L.s_esc += L.W;
+        L.phase = PH_PKG_END;
+      } else {
+        if (L.pass == 0) {
+          L.s_abs += L.wabs * (double)L.absf;
+          L.s_esc += L.W * exp(-L.T);
         }
+        const U4 ws = draw_words(P.seed, L.pkg, (unsigned)L.lam, 2u + (unsigned)L.n);
+        L.tau_s = -log1p(u01(ws.x) * expm1(-L.T));
+        L.tau_sR = (R)L.tau_s;
+        L.uw1 = ws.y;
+        L.uw2 = ws.z;
+        if (ADJ && L.pass == 1) L.fac = -(L.Rtot - L.Gacc) * L.kap;
+        want = true;
+        L.mode = M_LOCATE;
+        L.found = false;
+        L.phase = PH_LOCATE_END;
+      }
+    }
+
+    // -- end of the locate walk: move to the interaction point, update the weight
+    if (L.phase == PH_LOCATE_END && !want) {
+      double s;
+      if (L.found) {
+        const double tp = ray_cell_entry64(L.ry, G, L.r, L.k);
+        s = tp + (L.tau_s - (double)L.tau_prev) / (L.kap * (double)L.rho_hit);
+        if (ADJ && L.pass == 1) {
+          const double Ri = L.Rtot - L.Gacc;
+          M.add_grad(L.hit_cell, Ri / (double)L.rho_hit - Ri * L.kap * (s - tp));
+          ++L.n_dep;
+        }
+      } else {  // tau_s reached the total by rounding: end of the last absorbing segment
+        s = L.ry.tin + (double)L.last_t;
+        if (ADJ && L.pass == 1) {
+          M.add_grad(L.last_cell, (L.Rtot - L.Gacc) / (double)M.rho(L.last_cell));
+          ++L.n_dep;
+        }
+      }
+      L.r[0] += s * L.k[0];
+      L.r[1] += s * L.k[1];
+      L.r[2] += s * L.k[2];
+      L.W *= L.alb * (-expm1(-L.T));
+      ++L.n;
+      if (L.pass == 0) ++L.n_ev;
+      L.is_emit = false;
+      L.det = 0;
+      L.phase = (P.flags & kFlagPeelScat) ? PH_PEEL_NEXT : PH_TERM;
+    }
+
+    // -- the next frame whose pixel the event projects into
+    if (L.phase == PH_PEEL_NEXT && !want) {
+      while (L.det < P.n_det) {
+        L.pix = frame_pixel(M.det(L.det), L.r);
+        if (L.pix >= 0) break;
+        ++L.det;
+      }
+      if (L.det < P.n_det) {
+        want = to_det = true;
+        L.mode = M_PEEL;
+        L.phase = PH_PEEL_END;
+      } else {
+        L.phase = L.is_emit ? PH_PATH_START : PH_TERM;
+      }
+    }
+
+    // -- termination, or a new direction from the HG phase function
+    if (L.phase == PH_TERM && !want) {
+      if (L.W < P.w_min * L.w0 || L.n >= P.max_scatter) {
+        if (L.pass == 0) L.s_trunc += L.W;
+        L.phase = PH_PKG_END;
+      } else {
+        turn(L.k, hg_sample_mu(L.g, u01(L.uw1)), u01(L.uw2));
+        L.phase = PH_PATH_START;
+      }
+    }
+
+    // -- the pass-1 walk along the package direction
+    if (L.phase == PH_PATH_START && !want) {
+      want = true;
+      L.mode = M_PATH;
+      L.absf = R(0);
+      L.trans = R(1);
+      L.wabs = L.W * (1.0 - L.alb);
+      L.phase = PH_PATH_END;
+    }
+
+    // -- end of the package: replay it for the adjoint, or take the next one
+    if (L.phase == PH_PKG_END && !want) {
+      if (ADJ && L.pass == 0 && L.Gabs != 0.0) {
+        L.Rtot = L.Gacc;
+        L.Gacc = 0.0;
+        L.pass = 1;
+        L.phase = PH_EMIT;
+      } else {
+        L.phase = PH_FETCH;
+      }
+    }
+    if (L.phase == PH_FETCH && !want) {
+      if ((L.x_path | L.x_loc | L.x_peel | L.n_dep) & 0xC0000000u) {  // keep 32-bit counters from wrapping
+        M.flush_counts(L.x_path, L.x_loc, L.x_peel, L.n_dep);
+        L.x_path = L.x_loc = L.x_peel = L.n_dep = 0;
+      }
+      const unsigned long long item = M.fetch();
+      if (item >= P.n_items) {
+        L.done = true;
+      } else {
         L.lam = (int)(item / P.n_pkg);
         L.pkg = P.first + (item - (unsigned long long)L.lam * P.n_pkg);
         L.lam_cell = (long long)L.lam * G.ncell;
@@ -152,218 +294,111 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
         L.pass = 0;
         L.Gacc = L.Gabs = 0.0;
         L.phase = PH_EMIT;
-        break;
       }
-      case PH_EMIT: {  // also the start of the adjoint replay
-        const LamDev& LD = M.lam(L.lam);
-        const U4 wd = draw_words(P.seed, L.pkg, (unsigned)L.lam, 1u);
-        int s = P.n_src - 1;
-        const double target = u01(wd.z) * LD.ltot;
-        for (int q = 0; q < P.n_src; ++q) {
-          if (target < LD.cum[q]) {
-            s = q;
-            break;
-          }
-        }
-        iso_direction(u01(wd.x), u01(wd.y), L.k);
-        source_position(M.src(s), draw_words(P.seed, L.pkg, (unsigned)L.lam, 0u), L.r);
-        L.W = L.w0;
-        L.n = 0;
-        if (L.pass == 0) ++L.n_pk;
-        L.is_emit = true;
-        L.det = 0;
-        L.phase = (P.flags & kFlagPeelEmit) ? PH_PEEL_NEXT : PH_PATH_START;
-        break;
-      }
-      case PH_PEEL_NEXT: {
-        while (L.det < P.n_det) {
-          L.pix = frame_pixel(M.det(L.det), L.r);
-          if (L.pix >= 0) break;
-          ++L.det;
-        }
-        if (L.det >= P.n_det) {
-          L.phase = L.is_emit ? PH_PATH_START : PH_TERM;
+    }
+    // -- emission (also the start of the adjoint replay)
+    if (L.phase == PH_EMIT && !want && !L.done) {
+      const LamDev& LD = M.lam(L.lam);
+      const U4 wd = draw_words(P.seed, L.pkg, (unsigned)L.lam, 1u);
+      int s = P.n_src - 1;
+      const double target = u01(wd.z) * LD.ltot;
+      for (int q = 0; q < P.n_src; ++q) {
+        if (target < LD.cum[q]) {
+          s = q;
           break;
         }
-        ray_begin(L.ry, G, M, L.r, M.det(L.det).kd);
-        L.mode = M_PEEL;
-        L.phase = PH_PEEL_END;
-        break;
       }
-      case PH_PEEL_END: {
-        const DetDev& D = M.det(L.det);
-        const double ph = L.is_emit ? 1.0 / (4.0 * kPi)
-                                    : hg_phase(L.g, L.k[0] * D.kd[0] + L.k[1] * D.kd[1] + L.k[2] * D.kd[2]);
-        const double C = L.W * ph * exp(-(double)L.ry.tau) * D.inv_d2;
-        const int comp = ((P.flags & kFlagSplit) && !L.is_emit) ? 1 : 0;
-        const long long ii = ((long long)comp * P.n_lambda + L.lam) * P.pix_lambda + D.off + L.pix;
-        L.phase = PH_PEEL_NEXT;
-        if (L.pass == 0) ++L.n_pl;
-        if (!ADJ) {
-          M.add_image(ii, C);
-          ++L.det;
-        } else {
-          const double ac = M.adj(ii) * C;
-          L.Gacc += ac;
-          if (L.pass == 0) {
-            L.Gabs += fabs(ac);
-            ++L.det;
-          } else if (ac != 0.0) {  // second walk of the same ray deposits -A C kappa l
-            L.fac = -ac * L.kap;
-            ray_begin(L.ry, G, M, L.r, D.kd);
-            L.mode = M_PEEL_DEP;
-            L.phase = PH_PEEL_DEP_END;
-          } else {
-            ++L.det;
-          }
-        }
-        break;
-      }
-      case PH_PEEL_DEP_END: {
-        ++L.det;
-        L.phase = PH_PEEL_NEXT;
-        break;
-      }
-      case PH_PATH_START: {
-        ray_begin(L.ry, G, M, L.r, L.k);
-        L.mode = M_PATH;
-        L.absf = R(0);
-        L.wabs = L.W * (1.0 - L.alb);
-        L.phase = PH_PATH_END;
-        break;
-      }
-      case PH_PATH_END: {
-        L.T = (double)L.ry.tau;
-        if (L.T == 0.0) {  // nothing to interact with: the package leaves
-          if (L.pass == 0) L.s_esc += L.W;
-          L.phase = PH_PKG_END;
-          break;
-        }
-        if (L.pass == 0) {
-          L.s_abs += L.wabs * (double)L.absf;
-          L.s_esc += L.W * exp(-L.T);
-        }
-        const U4 ws = draw_words(P.seed, L.pkg, (unsigned)L.lam, 2u + (unsigned)L.n);
-        L.tau_s = -log1p(u01(ws.x) * expm1(-L.T));
-        L.tau_sR = (R)L.tau_s;
-        L.uw1 = ws.y;
-        L.uw2 = ws.z;
-        if (ADJ && L.pass == 1) L.fac = -(L.Rtot - L.Gacc) * L.kap;
-        ray_begin(L.ry, G, M, L.r, L.k);
-        L.mode = M_LOCATE;
-        L.found = false;
+      iso_direction(u01(wd.x), u01(wd.y), L.k);
+      source_position(M.src(s), draw_words(P.seed, L.pkg, (unsigned)L.lam, 0u), L.r);
+      L.W = L.w0;
+      L.n = 0;
+      if (L.pass == 0) ++L.n_pk;
+      L.is_emit = true;
+      L.det = 0;
+      L.phase = (P.flags & kFlagPeelEmit) ? PH_PEEL_NEXT : PH_PATH_START;
+    }
+
+    // -- set up the chosen walk (a walk that misses the grid ends at once and
+    //    its end is handled in the next pass)
+    if (want) {
+      const double* d = to_det ? M.det(L.det).kd : L.k;
+      ray_begin(L.ry, G, M, L.r, d);
+      if (L.mode == M_LOCATE) {
         L.last_cell = L.ry.cell;
         L.last_t = L.ry.t;
-        L.phase = PH_LOCATE_END;
-        break;
-      }
-      case PH_LOCATE_END: {
-        double s;
-        if (L.found) {
-          const double tp = ray_cell_entry64(L.ry, G, L.r, L.k);
-          s = tp + (L.tau_s - (double)L.tau_prev) / (L.kap * (double)L.rho_hit);
-          if (ADJ && L.pass == 1) {
-            const double Ri = L.Rtot - L.Gacc;
-            M.add_grad(L.hit_cell, Ri / (double)L.rho_hit - Ri * L.kap * (s - tp));
-            ++L.n_dep;
-          }
-        } else {  // tau_s reached the total by rounding: end of the last absorbing segment
-          s = L.ry.tin + (double)L.last_t;
-          if (ADJ && L.pass == 1) {
-            M.add_grad(L.last_cell, (L.Rtot - L.Gacc) / (double)M.rho(L.last_cell));
-            ++L.n_dep;
-          }
-        }
-        L.r[0] += s * L.k[0];
-        L.r[1] += s * L.k[1];
-        L.r[2] += s * L.k[2];
-        L.W *= L.alb * (-expm1(-L.T));
-        ++L.n;
-        if (L.pass == 0) ++L.n_ev;
-        L.is_emit = false;
-        L.det = 0;
-        L.phase = (P.flags & kFlagPeelScat) ? PH_PEEL_NEXT : PH_TERM;
-        break;
-      }
-      case PH_TERM: {
-        if (L.W < P.w_min * L.w0 || L.n >= P.max_scatter) {
-          if (L.pass == 0) L.s_trunc += L.W;
-          L.phase = PH_PKG_END;
-          break;
-        }
-        turn(L.k, hg_sample_mu(L.g, u01(L.uw1)), u01(L.uw2));
-        L.phase = PH_PATH_START;
-        break;
-      }
-      case PH_PKG_END:
-      default: {
-        if (ADJ && L.pass == 0 && L.Gabs != 0.0) {  // replay the package and deposit
-          L.Rtot = L.Gacc;
-          L.Gacc = 0.0;
-          L.pass = 1;
-          L.phase = PH_EMIT;
-        } else {
-          L.phase = PH_FETCH;
-        }
-        break;
       }
     }
   }
 }
 
-// One crossing of the lane's active ray, with the per-crossing work of its
-// mode: pass-1 continuous absorption W (1 - albedo) e^-tau (1 - e^-dtau)
-// into the cell; pass-2 search for the first segment whose optical depth
-// passes tau_s (and, in the adjoint replay, -R kappa l deposits along the
-// leg); peel rays accumulate tau (and, on the deposit walk, -A C kappa l).
-// Zero-length segments are skipped.
+// Walk block size: crossings per step of a lane, and density loads each
+// lane keeps in flight.
+constexpr int kBlockWalk = 4;
+
+// Up to kBlockWalk crossings of the lane's active ray, with the per-crossing
+// work of its mode: pass-1 continuous absorption W (1 - albedo) e^-tau
+// (1 - e^-dtau) into the cell; pass-2 search for the first segment whose
+// optical depth passes tau_s (and, in the adjoint replay, -R kappa l deposits
+// along the leg); peel rays accumulate tau (and, on the deposit walk,
+// -A C kappa l).  Zero-length segments are skipped.
 template <typename R, bool ADJ, class Mem>
 MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M) {
   Ray<R>& ry = L.ry;
-  const R tm = ray_tnext(ry);
-  R seg = tm - ry.t;
-  const bool pos = seg > R(0);
-  seg = pos ? seg : R(0);
-  const R rs = ry.rho_cur;
-  const R dtau = L.kapR * rs * seg;
-  if (L.mode == M_PATH) {
-    L.x_path += pos;
-    if (!ADJ && dtau > R(0)) {
-      const R f = exp(-ry.tau) * (-expm1(-dtau));
-      L.absf += f;
-      if (P.absorbed) {
-        M.add_absorbed(L.lam_cell + ry.cell, L.wabs * (double)f);
+  WalkBlock<kBlockWalk, R> b;
+  ray_next_block(ry, b, M);
+#pragma unroll
+  for (int d = 0; d < kBlockWalk; ++d) {
+    if (d >= b.n) break;
+    const R tm = b.tend[d];
+    R seg = tm - ry.t;
+    const bool pos = seg > R(0);
+    seg = pos ? seg : R(0);
+    const R rs = b.rho[d];
+    const int cell = b.cell[d];
+    const R dtau = L.kapR * rs * seg;
+    if (L.mode == M_PATH) {
+      L.x_path += pos;
+      if (!ADJ && dtau > R(0)) {
+        // deposit e^-tau (1 - e^-dtau) with e^-tau carried along the walk
+        const R em = expm1(-dtau);
+        const R f = -L.trans * em;
+        L.trans += L.trans * em;
+        L.absf += f;
+        if (P.absorbed) {
+          M.add_absorbed(L.lam_cell + cell, L.wabs * (double)f);
+          ++L.n_dep;
+        }
+      }
+    } else if (L.mode == M_LOCATE) {
+      L.x_loc += pos;
+      if (pos && ry.tau + dtau > L.tau_sR) {
+        L.found = true;
+        L.hit_cell = cell;
+        L.tau_prev = ry.tau;
+        L.rho_hit = rs;
+        ray_rewind(ry, b, d);
+        ry.active = false;
+        return;
+      }
+      if (dtau > R(0)) {
+        L.last_cell = cell;
+        L.last_t = tm;
+      }
+      if (ADJ && L.pass == 1 && pos) {
+        M.add_grad(cell, L.fac * (double)seg);
+        ++L.n_dep;
+      }
+    } else {
+      L.x_peel += pos;
+      if (ADJ && L.mode == M_PEEL_DEP && pos) {
+        M.add_grad(cell, L.fac * (double)seg);
         ++L.n_dep;
       }
     }
-  } else if (L.mode == M_LOCATE) {
-    L.x_loc += pos;
-    if (pos && ry.tau + dtau > L.tau_sR) {
-      L.found = true;
-      L.hit_cell = ry.cell;
-      L.tau_prev = ry.tau;
-      L.rho_hit = rs;
-      ry.active = false;
-      return;
-    }
-    if (dtau > R(0)) {
-      L.last_cell = ry.cell;
-      L.last_t = tm;
-    }
-    if (ADJ && L.pass == 1 && pos) {
-      M.add_grad(ry.cell, L.fac * (double)seg);
-      ++L.n_dep;
-    }
-  } else {
-    L.x_peel += pos;
-    if (ADJ && L.mode == M_PEEL_DEP && pos) {
-      M.add_grad(ry.cell, L.fac * (double)seg);
-      ++L.n_dep;
-    }
+    ry.tau += dtau;
+    if (pos) ry.t = tm;
   }
-  ry.tau += dtau;
-  if (pos) ry.t = tm;
-  if (ray_advance(ry, tm, M)) ry.active = false;
+  if (b.out) ry.active = false;
 }
 
 // ---------------------------------------------------------------------------
@@ -433,17 +468,23 @@ MCRT_HD void trace_events(TraceLane<R>& L, const TraceParams& P, Mem& M) {
 template <typename R, class Mem>
 MCRT_HD void trace_step(TraceLane<R>& L, const TraceParams& P, Mem& M) {
   Ray<R>& ry = L.ry;
-  const R tm = ray_tnext(ry);
-  R seg = tm - ry.t;
-  const bool pos = seg > R(0);
-  seg = pos ? seg : R(0);
-  if (pos) {
-    if (P.seg_cell != nullptr && L.nseg < P.max_seg) M.store_seg(L.q, L.nseg, ry.cell, (double)seg);
-    ++L.nseg;
-    ry.t = tm;
+  WalkBlock<kBlockWalk, R> b;
+  ray_next_block(ry, b, M);
+  const R kap = (R)P.kappa;
+#pragma unroll
+  for (int d = 0; d < kBlockWalk; ++d) {
+    if (d >= b.n) break;
+    R seg = b.tend[d] - ry.t;
+    const bool pos = seg > R(0);
+    seg = pos ? seg : R(0);
+    if (pos) {
+      if (P.seg_cell != nullptr && L.nseg < P.max_seg) M.store_seg(L.q, L.nseg, b.cell[d], (double)seg);
+      ++L.nseg;
+      ry.t = b.tend[d];
+    }
+    ry.tau += kap * b.rho[d] * seg;
   }
-  ry.tau += (R)P.kappa * ry.rho_cur * seg;
-  if (ray_advance(ry, tm, M)) ry.active = false;
+  if (b.out) ry.active = false;
 }
 
 struct PeelParams {
@@ -509,13 +550,19 @@ MCRT_HD void peel_events(PeelLane<R>& L, const PeelParams& P, Mem& M) {
 template <typename R, class Mem>
 MCRT_HD void peel_step(PeelLane<R>& L, const PeelParams& P, Mem& M) {
   Ray<R>& ry = L.ry;
-  const R tm = ray_tnext(ry);
-  R seg = tm - ry.t;
-  const bool pos = seg > R(0);
-  seg = pos ? seg : R(0);
-  if (pos) ry.t = tm;
-  ry.tau += (R)P.kappa * ry.rho_cur * seg;
-  if (ray_advance(ry, tm, M)) ry.active = false;
+  WalkBlock<kBlockWalk, R> b;
+  ray_next_block(ry, b, M);
+  const R kap = (R)P.kappa;
+#pragma unroll
+  for (int d = 0; d < kBlockWalk; ++d) {
+    if (d >= b.n) break;
+    R seg = b.tend[d] - ry.t;
+    const bool pos = seg > R(0);
+    seg = pos ? seg : R(0);
+    if (pos) ry.t = b.tend[d];
+    ry.tau += kap * b.rho[d] * seg;
+  }
+  if (b.out) ry.active = false;
 }
 
 }  // namespace mcrt
