@@ -42,6 +42,9 @@
  *    for its own work to finish before returning.
  *  - Ownership: the caller owns every buffer; host structs and arrays are
  *    read only during the call.  The library keeps no state between calls.
+ *    Each call allocates stream-ordered device memory (hipMallocAsync) for
+ *    its tables, a bricked copy of the densities and, where it has one, a
+ *    bricked tally, and frees it on the stream when its work ends. 
  *  - Errors: 0 on success; MCRT_EINVAL for invalid arguments (nothing is
  *    launched), MCRT_EOVERFLOW when a segment buffer was too small,
  *    MCRT_EHIP for a HIP runtime error.  mcrt_last_error() returns a message
@@ -112,10 +115,14 @@ typedef struct {
  * [first_package, first_package + n_packages) are run; seed is the Philox
  * key; precision MCRT_PREC_*; a package stops when its weight drops below
  * w_min times its initial weight or after max_scatter scatterings (the rest
- * is tallied as truncated); flags MCRT_*.  launch_blocks and event_batch
- * tune the launch (0 = library choice): blocks per compute unit of the
- * persistent kernels, and how many lanes of a wavefront wait before the
- * wavefront processes events. */
+ * is tallied as truncated); flags MCRT_*.  launch_blocks, event_batch and
+ * brick_shape tune the run without changing its results (0 = library
+ * choice): blocks per compute unit of the persistent kernels; how many
+ * lanes of a wavefront wait before the wavefront processes events; and the
+ * brick of the library's internal cell layout, MCRT_BRICK(lx, ly, lz) for
+ * bricks of 2^lx x 2^ly x 2^lz cells (each log2 in [0, 7], at most 2^10
+ * cells).  The default brick fills one 128-byte cache line with the most
+ * compact block of cells in physical units. */
 typedef struct {
     uint64_t n_packages, first_package, seed;
     int32_t precision;
@@ -123,7 +130,10 @@ typedef struct {
     int32_t max_scatter;
     uint32_t flags;
     int32_t launch_blocks, event_batch;
+    int32_t brick_shape;
 } mcrt_opts;
+
+#define MCRT_BRICK(lx, ly, lz) (0x1000 | (lx) | ((ly) << 4) | ((lz) << 8))
 
 /* Run statistics (FP64 luminosities summed over wavelengths; crossing
  * counts of positive-length cell segments: pass-1 paths, pass-2 locate
@@ -207,7 +217,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 1
+#define MCRT_ABI_VERSION 2
 
 #ifdef __cplusplus
 }

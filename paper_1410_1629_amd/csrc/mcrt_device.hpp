@@ -42,12 +42,48 @@ constexpr double kParallel = 1e-20;
 // ---------------------------------------------------------------------------
 // Problem data, prepared by the host in FP64.
 
+// Cells are stored internally in bricks: blocks of 2^lb[0] x 2^lb[1] x
+// 2^lb[2] cells, x fastest inside a brick and bricks x fastest, so that one
+// cache line holds a compact block of neighbouring cells and a walk in any
+// direction reads several cells per line (row-major storage gives one cell
+// per line for every step along y or z).  The caller's arrays stay in the
+// row-major layout of the C ABI; the library converts at the boundary.
 struct GridDev {
   double lo[3], hi[3], d[3], inv_d[3];
   int n[3];
-  int stride[3];  // 1, nx, nx*ny
-  int ncell;
+  int stride[3];  // row-major strides 1, nx, nx*ny
+  int ncell;      // nx*ny*nz
+  int lb[3];      // log2 of the brick size along each axis
+  int nb[3];      // bricks along each axis
+  int bstride[3]; // brick strides in cells: 2^(lb0+lb1+lb2), nb0 of them, nb0*nb1 of them
+  int ncell_pad;  // cells of the bricked arrays (whole bricks)
 };
+
+// Bricked address of cell (i0, i1, i2).
+MCRT_HD int brick_addr(const GridDev& G, const int i[3]) {
+  const int m0 = (1 << G.lb[0]) - 1, m1 = (1 << G.lb[1]) - 1, m2 = (1 << G.lb[2]) - 1;
+  return (i[0] >> G.lb[0]) * G.bstride[0] + (i[1] >> G.lb[1]) * G.bstride[1] + (i[2] >> G.lb[2]) * G.bstride[2] +
+         ((i[0] & m0) | ((i[1] & m1) << G.lb[0]) | ((i[2] & m2) << (G.lb[0] + G.lb[1])));
+}
+
+// Cell indices of bricked address c; false for padding cells.
+MCRT_HD bool brick_cell(const GridDev& G, int c, int i[3]) {
+  const int cb = G.lb[0] + G.lb[1] + G.lb[2];
+  const int b = c >> cb, off = c & ((1 << cb) - 1);
+  const int b0 = b % G.nb[0], t = b / G.nb[0];
+  const int b1 = t % G.nb[1], b2 = t / G.nb[1];
+  i[0] = (b0 << G.lb[0]) | (off & ((1 << G.lb[0]) - 1));
+  i[1] = (b1 << G.lb[1]) | ((off >> G.lb[0]) & ((1 << G.lb[1]) - 1));
+  i[2] = (b2 << G.lb[2]) | (off >> (G.lb[0] + G.lb[1]));
+  return c >= 0 && c < G.ncell_pad && i[0] < G.n[0] && i[1] < G.n[1] && i[2] < G.n[2];
+}
+
+// Row-major index of bricked address c (c must be a grid cell).
+MCRT_HD int brick_to_linear(const GridDev& G, int c) {
+  int i[3];
+  brick_cell(G, c, i);
+  return i[0] + i[1] * G.stride[1] + i[2] * G.stride[2];
+}
 
 struct DetDev {
   double kd[3], ex[3], ey[3];  // towards the observer; image axes
@@ -190,17 +226,14 @@ MCRT_HD int frame_pixel(const DetDev& D, const double r[3]) {
 // dt[a] the time between planes, so after j[a] crossings along a the next
 // plane is reached at t = t0[a] + j[a] * dt[a] -- one rounding of a product
 // and a sum, no accumulation and no cancellation against a far anchor.
-// lim[a] is the number of planes ahead before the plane where the ray
-// leaves the grid along a: the walk ends as soon as some j[a] exceeds
-// lim[a], and while every j[a] <= lim[a] the cell is inside the grid.
-// Axes parallel to the ray have t0 = +inf, dt = 0, step 0 and a limit that
-// is never reached.  The current cell is `cell`.
+// i[a] is the current cell index along a and s[a] its step (+1, -1, or 0
+// for an axis parallel to the ray, whose t0 is +inf and dt 0); the walk
+// ends as soon as some i[a] leaves [0, n[a]).
 
 template <typename R>
 struct Ray {
   R t0[3], dt[3];
-  int j[3], lim[3], step[3];
-  int cell;
+  int j[3], i[3], s[3];
   R t, tau;
   double tin;  // FP64 entry time (0 for rays starting inside)
   bool active;
@@ -208,14 +241,13 @@ struct Ray {
 
 MCRT_HD float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
 MCRT_HD double fmaR(double a, double b, double c) { return fma(a, b, c); }
-MCRT_HD int imax3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
 
 // Sets up the walk of o + t k (t >= 0): slab entry for origins outside the
 // grid; cell indices by floor with the lower cell for a coordinate on a wall
 // while moving down; rays missing the grid (or with non-finite data) are
 // left inactive with tau = 0.
-template <typename R, class Mem>
-MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, Mem& M, const double o[3], const double k[3]) {
+template <typename R>
+MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const double k[3]) {
   double tin = 0.0, tout = INFINITY;
   int entry = -1;
   bool miss = !(std::isfinite(o[0]) && std::isfinite(o[1]) && std::isfinite(o[2]) && std::isfinite(k[0]) &&
@@ -247,7 +279,6 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, Mem& M, const double o[3], 
     ry.tin = 0.0;
     return;
   }
-  int cell = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     int i;
@@ -261,30 +292,32 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, Mem& M, const double o[3], 
       if (!par[a] && k[a] < 0.0 && x == fx) i -= 1;
       i = i < 0 ? 0 : (i > G.n[a] - 1 ? G.n[a] - 1 : i);
     }
-    cell += i * G.stride[a];
+    ry.i[a] = i;
     ry.j[a] = 0;
     if (par[a]) {
       ry.t0[a] = R(INFINITY);
       ry.dt[a] = R(0);
-      ry.lim[a] = 1 << 30;
-      ry.step[a] = 0;
+      ry.s[a] = 0;
     } else if (k[a] > 0.0) {
       ry.t0[a] = (R)((G.lo[a] + (double)(i + 1) * G.d[a] - o[a]) * inv[a] - tin);
       ry.dt[a] = (R)(G.d[a] * inv[a]);
-      ry.lim[a] = G.n[a] - 1 - i;
-      ry.step[a] = G.stride[a];
+      ry.s[a] = 1;
     } else {
       ry.t0[a] = (R)((G.lo[a] + (double)i * G.d[a] - o[a]) * inv[a] - tin);
       ry.dt[a] = (R)(-G.d[a] * inv[a]);
-      ry.lim[a] = i;
-      ry.step[a] = -G.stride[a];
+      ry.s[a] = -1;
     }
   }
-  ry.cell = cell;
   ry.t = R(0);
   ry.tin = tin;
   ry.tau = R(0);
   ry.active = true;
+}
+
+// Bricked address of the ray's current cell.
+template <typename R>
+MCRT_HD int ray_cell(const Ray<R>& ry, const GridDev& G) {
+  return brick_addr(G, ry.i);
 }
 
 // Crossing time of the next plane ahead along axis a.
@@ -299,17 +332,17 @@ MCRT_HD R ray_tnext(const Ray<R>& ry) {
   return fmin(ray_tplane(ry, 0), fmin(ray_tplane(ry, 1), ray_tplane(ry, 2)));
 }
 
-// The next D cells of the walk, as a block: their indices, the end times of
-// their segments and their densities.  The cell sequence of a walk does not
-// depend on the densities, so the block first advances the walk D times
-// (pure arithmetic: all axes whose plane is reached at the segment's end
-// advance together) and then issues the D density loads back to back, which
-// keeps D gathers in flight per lane instead of one.  The walk leaves the
-// grid when some axis has crossed more planes than it had ahead inside it,
-// or when no axis matched the end time (non-finite times); sub-steps after
-// that repeat the last valid cell, so no load leaves the grid.  `adv` keeps
-// the axes that advanced at each sub-step (3 bits each) so that a caller
-// stopping inside the block can rewind the plane counts (ray_rewind).
+// The next D cells of the walk, as a block: their bricked addresses, the end
+// times of their segments and their densities.  The cell sequence of a walk
+// does not depend on the densities, so the block first advances the walk D
+// times (pure arithmetic: all axes whose plane is reached at the segment's
+// end advance together) and then issues the D density loads back to back,
+// which keeps D gathers in flight per lane instead of one.  The walk leaves
+// the grid when some index leaves its range, or when no axis matched the end
+// time (non-finite times); sub-steps after that repeat the last valid cell,
+// so no load leaves the grid.  `adv` keeps the axes that advanced at each
+// sub-step (3 bits each) so that a caller stopping inside the block can
+// rewind the ray (ray_rewind).
 template <int D, typename R>
 struct WalkBlock {
   int cell[D];
@@ -321,7 +354,7 @@ struct WalkBlock {
 };
 
 template <int D, typename R, class Mem>
-MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, Mem& M) {
+MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, const GridDev& G, Mem& M) {
   b.n = 0;
   b.adv = 0;
   b.out = false;
@@ -331,44 +364,49 @@ MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, Mem& M) {
     const R tm = fmin(tx, fmin(ty, tz));
     const bool live = !b.out;
     const bool ax = live && tx == tm, ay = live && ty == tm, az = live && tz == tm;
-    b.cell[d] = live ? ry.cell : b.cell[d > 0 ? d - 1 : 0];
+    b.cell[d] = live ? brick_addr(G, ry.i) : b.cell[d > 0 ? d - 1 : 0];
     b.tend[d] = live ? tm : b.tend[d > 0 ? d - 1 : 0];
-    ry.cell += (ax ? ry.step[0] : 0) + (ay ? ry.step[1] : 0) + (az ? ry.step[2] : 0);
+    ry.i[0] += ax ? ry.s[0] : 0;
+    ry.i[1] += ay ? ry.s[1] : 0;
+    ry.i[2] += az ? ry.s[2] : 0;
     ry.j[0] += ax;
     ry.j[1] += ay;
     ry.j[2] += az;
     b.adv |= ((unsigned)ax | ((unsigned)ay << 1) | ((unsigned)az << 2)) << (3 * d);
     b.n += live;
-    b.out = b.out || imax3(ry.j[0] - ry.lim[0], ry.j[1] - ry.lim[1], ry.j[2] - ry.lim[2]) > 0 || !(ax || ay || az);
+    const bool outside = (unsigned)ry.i[0] >= (unsigned)G.n[0] || (unsigned)ry.i[1] >= (unsigned)G.n[1] ||
+                         (unsigned)ry.i[2] >= (unsigned)G.n[2];
+    b.out = b.out || outside || !(ax || ay || az);
   }
 #pragma unroll
   for (int d = 0; d < D; ++d) b.rho[d] = M.rho(b.cell[d]);
 }
 
 // Undoes the plane crossings of sub-steps d .. D-1 of the last block, so the
-// ray's counts again describe the walk inside cell b.cell[d].
+// ray again describes the walk inside cell b.cell[d].
 template <int D, typename R>
 MCRT_HD void ray_rewind(Ray<R>& ry, const WalkBlock<D, R>& b, int d) {
   for (int e = d; e < D; ++e) {
     const unsigned m = b.adv >> (3 * e);
-    ry.j[0] -= (int)(m & 1u);
-    ry.j[1] -= (int)((m >> 1) & 1u);
-    ry.j[2] -= (int)((m >> 2) & 1u);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int x = (int)((m >> a) & 1u);
+      ry.j[a] -= x;
+      ry.i[a] -= x * ry.s[a];
+    }
   }
 }
 
 // FP64 entry time of the current cell, in the original parametrisation of
-// the ray: the latest plane already crossed, or the ray's entry time.  The
-// plane index follows from the crossing count: moving up from start index
-// i0 = n - 1 - lim the last plane crossed is i0 + j; moving down from
-// i0 = lim it is i0 + 1 - j.
+// the ray: the latest plane already crossed, or the ray's entry time.  Moving
+// up into cell i the last plane crossed is plane i; moving down, plane i + 1.
 template <typename R>
 MCRT_HD double ray_cell_entry64(const Ray<R>& ry, const GridDev& G, const double o[3], const double k[3]) {
   double t = ry.tin;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    if (ry.step[a] == 0 || ry.j[a] == 0) continue;
-    const int p = k[a] > 0.0 ? G.n[a] - 1 - ry.lim[a] + ry.j[a] : ry.lim[a] + 1 - ry.j[a];
+    if (ry.s[a] == 0 || ry.j[a] == 0) continue;
+    const int p = ry.s[a] > 0 ? ry.i[a] : ry.i[a] + 1;
     const double tl = (G.lo[a] + (double)p * G.d[a] - o[a]) / k[a];
     t = fmax(t, tl);
   }

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -48,8 +49,56 @@ inline int check_grid(const mcrt_grid* g) {
   return 0;
 }
 
-inline GridDev make_grid(const mcrt_grid& g) {
-  GridDev G;
+inline int ilog2_ceil(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+// Brick of the internal layout.  By default: 2^cb cells (one 128-byte line
+// of elements of `elem_bytes`), shaped to minimise the brick's surface per
+// volume in physical units -- the rate at which a straight walk in a random
+// direction leaves bricks -- with no side longer than the grid needs; ties
+// go to the longest x, then y.  brick_shape (MCRT_BRICK) overrides.
+inline void choose_brick(const GridDev& G, int elem_bytes, int brick_shape, int lb[3]) {
+  if (brick_shape != 0) {
+    lb[0] = brick_shape & 15;
+    lb[1] = (brick_shape >> 4) & 15;
+    lb[2] = (brick_shape >> 8) & 15;
+    return;
+  }
+  int cb = 0;
+  while ((1 << cb) * elem_bytes < 128) ++cb;
+  const int cap[3] = {ilog2_ceil(G.n[0]), ilog2_ceil(G.n[1]), ilog2_ceil(G.n[2])};
+  const int want = std::min(cb, cap[0] + cap[1] + cap[2]);
+  double best = INFINITY;
+  lb[0] = lb[1] = lb[2] = 0;
+  for (int x = cap[0]; x >= 0; --x)
+    for (int y = cap[1]; y >= 0; --y) {
+      const int z = want - x - y;
+      if (z < 0 || z > cap[2]) continue;
+      const double score = 1.0 / ((1 << x) * G.d[0]) + 1.0 / ((1 << y) * G.d[1]) + 1.0 / ((1 << z) * G.d[2]);
+      if (score < best * (1.0 - 1e-12)) {
+        best = score;
+        lb[0] = x;
+        lb[1] = y;
+        lb[2] = z;
+      }
+    }
+}
+
+inline int check_brick(int brick_shape) {
+  if (brick_shape == 0) return 0;
+  const int lx = brick_shape & 15, ly = (brick_shape >> 4) & 15, lz = (brick_shape >> 8) & 15;
+  if ((brick_shape & ~0x1fff) || !(brick_shape & 0x1000) || lx > 7 || ly > 7 || lz > 7 || lx + ly + lz > 10)
+    return fail(MCRT_EINVAL, "brick_shape 0x%x is not MCRT_BRICK(lx, ly, lz) with log2 sizes in [0, 7] and at most "
+                "2^10 cells", brick_shape);
+  return 0;
+}
+
+// Device grid description: geometry, row-major strides and the bricked
+// layout.  Fails if the bricked arrays would exceed 2^31 - 1 cells.
+inline int make_grid(const mcrt_grid& g, int elem_bytes, int brick_shape, GridDev& G) {
   const double b[6] = {g.xmin, g.xmax, g.ymin, g.ymax, g.zmin, g.zmax};
   const int n[3] = {g.nx, g.ny, g.nz};
   for (int a = 0; a < 3; ++a) {
@@ -63,8 +112,24 @@ inline GridDev make_grid(const mcrt_grid& g) {
   G.stride[1] = g.nx;
   G.stride[2] = g.nx * g.ny;
   G.ncell = g.nx * g.ny * g.nz;
-  return G;
+  if (int e = check_brick(brick_shape)) return e;
+  choose_brick(G, elem_bytes, brick_shape, G.lb);
+  long long pad = 1;
+  for (int a = 0; a < 3; ++a) {
+    G.nb[a] = (n[a] + (1 << G.lb[a]) - 1) >> G.lb[a];
+    pad *= (long long)G.nb[a] << G.lb[a];
+  }
+  if (pad >= (1ll << 31))
+    return fail(MCRT_EINVAL, "bricked grid has %lld cells; at most 2^31 - 1 are supported", pad);
+  const int cpb = 1 << (G.lb[0] + G.lb[1] + G.lb[2]);
+  G.bstride[0] = cpb;
+  G.bstride[1] = G.nb[0] * cpb;
+  G.bstride[2] = G.nb[0] * G.nb[1] * cpb;
+  G.ncell_pad = (int)pad;
+  return 0;
 }
+
+inline int elem_bytes(int precision) { return precision == MCRT_PREC_FP32 ? 4 : 8; }
 
 inline int check_detectors(int n_det, const mcrt_detector* dets, bool allow_zero) {
   if (n_det < (allow_zero ? 0 : 1) || n_det > MCRT_MAX_DETECTORS)
@@ -165,7 +230,7 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
 
   RunParams& P = out.P;
   std::memset(&P, 0, sizeof P);
-  P.G = make_grid(*grid);
+  if (int e = make_grid(*grid, elem_bytes(opts->precision), opts->brick_shape, P.G)) return e;
   P.rho = rho_dev;
   P.n_lambda = nl;
   P.n_src = n_src;

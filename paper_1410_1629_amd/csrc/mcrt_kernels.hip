@@ -138,7 +138,7 @@ struct TraceMem {
     if (P.n_seg) P.n_seg[q] = n;
   }
   __device__ void store_seg(long long q, int j, int cell, double len) const {
-    P.seg_cell[q * P.max_seg + j] = cell;
+    P.seg_cell[q * P.max_seg + j] = brick_to_linear(P.G, cell);
     P.seg_len[q * P.max_seg + j] = len;
   }
 };
@@ -249,6 +249,34 @@ __global__ void k_zero(double* __restrict__ p, long long n) {
     p[i] = 0.0;
 }
 
+// Row-major densities -> bricked layout (padding cells 0); one thread per
+// bricked cell, so the writes are contiguous.
+template <typename R>
+__global__ void k_brick(const R* __restrict__ src, R* __restrict__ dst, const GridDev G) {
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < G.ncell_pad;
+       c += (long long)gridDim.x * blockDim.x) {
+    int i[3];
+    const bool in = brick_cell(G, (int)c, i);
+    dst[c] = in ? src[i[0] + i[1] * G.stride[1] + i[2] * G.stride[2]] : R(0);
+  }
+}
+
+// Bricked tally [n_lambda][ncell_pad] -> row-major [n_lambda][ncell]; one
+// thread per row-major cell.
+__global__ void k_unbrick(const double* __restrict__ src, double* __restrict__ dst, const GridDev G, int n_lambda) {
+  const long long n = (long long)n_lambda * G.ncell;
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+    const long long l = q / G.ncell;
+    const int m = (int)(q - l * G.ncell);
+    int i[3];
+    i[0] = m % G.n[0];
+    const int t = m / G.n[0];
+    i[1] = t % G.n[1];
+    i[2] = t / G.n[1];
+    dst[q] = src[l * G.ncell_pad + brick_addr(G, i)];
+  }
+}
+
 }  // namespace mcrt
 
 // ===========================================================================
@@ -278,16 +306,37 @@ int persistent_grid(K kernel, int blocks_per_cu, int* grid_out) {
   return 0;
 }
 
+unsigned stream_blocks(long long n) { return (unsigned)std::min<long long>((n + kBlock - 1) / kBlock, 16384); }
+
 int zero_fill(double* p, long long n, hipStream_t st) {
   if (!p || n <= 0) return 0;
-  const long long blocks = std::min<long long>((n + kBlock - 1) / kBlock, 65536);
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(kBlock), 0, st, p, n);
+  hipLaunchKernelGGL(k_zero, dim3(stream_blocks(n)), dim3(kBlock), 0, st, p, n);
   HIPCHK(hipGetLastError());
   return 0;
 }
 
-// Device copy of the problem tables plus zeroed counters: one allocation,
-// ordered on the stream, released on the stream when the call returns.
+// Bricked copy of the caller's densities into dst (G.ncell_pad elements).
+int brick_density(const GridDev& G, const void* rho, void* dst, bool f32, hipStream_t st) {
+  if (f32)
+    hipLaunchKernelGGL(k_brick<float>, dim3(stream_blocks(G.ncell_pad)), dim3(kBlock), 0, st,
+                       static_cast<const float*>(rho), static_cast<float*>(dst), G);
+  else
+    hipLaunchKernelGGL(k_brick<double>, dim3(stream_blocks(G.ncell_pad)), dim3(kBlock), 0, st,
+                       static_cast<const double*>(rho), static_cast<double*>(dst), G);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int unbrick_tally(const GridDev& G, const double* src, double* dst, int n_lambda, hipStream_t st) {
+  hipLaunchKernelGGL(k_unbrick, dim3(stream_blocks((long long)n_lambda * G.ncell)), dim3(kBlock), 0, st, src, dst, G,
+                     n_lambda);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+// Per-call device memory (problem tables, zeroed counters, the bricked
+// densities and tally): one allocation, ordered on the stream, released on
+// the stream when the call returns.
 struct DeviceBlock {
   unsigned char* ptr = nullptr;
   hipStream_t st = nullptr;
@@ -334,12 +383,16 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     P.grad = grad_dev;
   }
   const int nl = P.n_lambda;
+  const bool f32 = opts->precision == MCRT_PREC_FP32;
+  const long long n_tally = adjoint ? (long long)P.G.ncell_pad : (P.absorbed ? (long long)nl * P.G.ncell_pad : 0);
   const size_t off_lam = 0;
   const size_t off_det = align256(sizeof(LamDev) * nl);
   const size_t off_src = off_det + align256(sizeof(DetDev) * pr.det.size());
   const size_t off_cnt = off_src + align256(sizeof(SrcDev) * pr.src.size());
-  const size_t bytes = off_cnt + 256;
-  std::vector<unsigned char> blob(bytes, 0);
+  const size_t off_rho = off_cnt + 256;
+  const size_t off_tal = off_rho + align256((size_t)P.G.ncell_pad * (f32 ? 4 : 8));
+  const size_t bytes = off_tal + align256(sizeof(double) * (size_t)n_tally);
+  std::vector<unsigned char> blob(off_rho, 0);
   std::memcpy(blob.data() + off_lam, pr.lam.data(), sizeof(LamDev) * nl);
   std::memcpy(blob.data() + off_det, pr.det.data(), sizeof(DetDev) * pr.det.size());
   std::memcpy(blob.data() + off_src, pr.src.data(), sizeof(SrcDev) * pr.src.size());
@@ -348,26 +401,30 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   DeviceBlock blk;
   blk.st = st;
   HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), bytes, st));
-  HIPCHK(hipMemcpyAsync(blk.ptr, blob.data(), bytes, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(blk.ptr, blob.data(), off_rho, hipMemcpyHostToDevice, st));
+  if (int e = brick_density(P.G, rho_dev, blk.ptr + off_rho, f32, st)) return e;
+  double* const user_tally = adjoint ? P.grad : P.absorbed;
+  double* const tally = n_tally ? reinterpret_cast<double*>(blk.ptr + off_tal) : nullptr;
+  P.rho = blk.ptr + off_rho;
+  if (adjoint)
+    P.grad = tally;
+  else
+    P.absorbed = tally;
   P.lam = reinterpret_cast<const LamDev*>(blk.ptr + off_lam);
   P.det = reinterpret_cast<const DetDev*>(blk.ptr + off_det);
   P.src = reinterpret_cast<const SrcDev*>(blk.ptr + off_src);
   P.work = reinterpret_cast<unsigned long long*>(blk.ptr + off_cnt);
   P.dstats = reinterpret_cast<double*>(blk.ptr + off_cnt + 64);
   P.xstats = reinterpret_cast<unsigned long long*>(blk.ptr + off_cnt + 128);
-  if (!adjoint) {
+  if (!adjoint)
     if (int e = zero_fill(P.images, peel ? pr.n_images : 0, st)) return e;
-    if (int e = zero_fill(P.absorbed, P.absorbed ? (long long)nl * P.G.ncell : 0, st)) return e;
-  } else {
-    if (int e = zero_fill(P.grad, P.G.ncell, st)) return e;
-  }
+  if (int e = zero_fill(tally, n_tally, st)) return e;
   EventPair ev;
   if (stats) {
     HIPCHK(hipEventCreate(&ev.a));
     HIPCHK(hipEventCreate(&ev.b));
     HIPCHK(hipEventRecord(ev.a, st));
   }
-  const bool f32 = opts->precision == MCRT_PREC_FP32;
   int rc;
   if (adjoint)
     rc = f32 ? launch_life<float, true>(P, opts->launch_blocks, st)
@@ -376,8 +433,10 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     rc = f32 ? launch_life<float, false>(P, opts->launch_blocks, st)
              : launch_life<double, false>(P, opts->launch_blocks, st);
   if (rc) return rc;
+  if (stats) HIPCHK(hipEventRecord(ev.b, st));
+  if (tally)
+    if (int e = unbrick_tally(P.G, tally, user_tally, adjoint ? 1 : nl, st)) return e;
   if (stats) {
-    HIPCHK(hipEventRecord(ev.b, st));
     double ds[3];
     unsigned long long xs[7];
     HIPCHK(hipMemcpyAsync(ds, P.dstats, sizeof ds, hipMemcpyDeviceToHost, st));
@@ -456,8 +515,7 @@ int trace_path(const mcrt_grid* grid, const void* rho_dev, double kappa, int pre
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     TraceParams P;
     std::memset(&P, 0, sizeof P);
-    P.G = host::make_grid(*grid);
-    P.rho = rho_dev;
+    if (int e = host::make_grid(*grid, host::elem_bytes(precision), 0, P.G)) return e;
     P.kappa = kappa;
     P.n_rays = n_rays;
     P.origin = origin_dev;
@@ -471,12 +529,15 @@ int trace_path(const mcrt_grid* grid, const void* rho_dev, double kappa, int pre
     DeviceBlock blk;
     blk.st = st;
     const unsigned long long zeros[3] = {0, 0, 0};
-    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), 256, st));
+    const bool f32 = precision == MCRT_PREC_FP32;
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), 256 + (size_t)P.G.ncell_pad * (f32 ? 4 : 8), st));
     HIPCHK(hipMemcpyAsync(blk.ptr, zeros, sizeof zeros, hipMemcpyHostToDevice, st));
+    if (int e = brick_density(P.G, rho_dev, blk.ptr + 256, f32, st)) return e;
+    P.rho = blk.ptr + 256;
     P.work = reinterpret_cast<unsigned long long*>(blk.ptr);
     P.counters = P.work + 1;
     int nblk = 0;
-    if (precision == MCRT_PREC_FP32) {
+    if (f32) {
       if (int e = persistent_grid(k_trace<float>, 0, &nblk)) return e;
       hipLaunchKernelGGL(k_trace<float>, dim3(nblk), dim3(kBlock), 0, st, P);
     } else {
@@ -507,19 +568,22 @@ int peel_off(const mcrt_grid* grid, const void* rho_dev, double kappa, double g,
       return e;
     if (n_events == 0) return 0;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    PeelParams P;
+    std::memset(&P, 0, sizeof P);
+    if (int e = host::make_grid(*grid, host::elem_bytes(precision), 0, P.G)) return e;
+    const bool f32 = precision == MCRT_PREC_FP32;
     std::vector<DetDev> det = host::make_dets(n_det, detectors, nullptr);
     const size_t off_cnt = align256(sizeof(DetDev) * det.size());
-    const size_t bytes = off_cnt + 256;
-    std::vector<unsigned char> blob(bytes, 0);
+    const size_t off_rho = off_cnt + 256;
+    const size_t bytes = off_rho + (size_t)P.G.ncell_pad * (f32 ? 4 : 8);
+    std::vector<unsigned char> blob(off_rho, 0);
     std::memcpy(blob.data(), det.data(), sizeof(DetDev) * det.size());
     DeviceBlock blk;
     blk.st = st;
     HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), bytes, st));
-    HIPCHK(hipMemcpyAsync(blk.ptr, blob.data(), bytes, hipMemcpyHostToDevice, st));
-    PeelParams P;
-    std::memset(&P, 0, sizeof P);
-    P.G = host::make_grid(*grid);
-    P.rho = rho_dev;
+    HIPCHK(hipMemcpyAsync(blk.ptr, blob.data(), off_rho, hipMemcpyHostToDevice, st));
+    if (int e = brick_density(P.G, rho_dev, blk.ptr + off_rho, f32, st)) return e;
+    P.rho = blk.ptr + off_rho;
     P.kappa = kappa;
     P.g = g;
     P.n_events = n_events;
@@ -532,7 +596,7 @@ int peel_off(const mcrt_grid* grid, const void* rho_dev, double kappa, double g,
     P.work = reinterpret_cast<unsigned long long*>(blk.ptr + off_cnt);
     P.batch = 16;
     int nblk = 0;
-    if (precision == MCRT_PREC_FP32) {
+    if (f32) {
       if (int e = persistent_grid(k_peel<float>, 0, &nblk)) return e;
       hipLaunchKernelGGL(k_peel<float>, dim3(nblk), dim3(kBlock), 0, st, P);
     } else {

@@ -20,6 +20,9 @@
 //   M.rho(cell)  M.det(d)  M.lam(l)  M.src(s)  M.adj(i)
 //   M.add_image(i, v)  M.add_absorbed(i, v)  M.add_grad(cell, v)
 //   M.fetch()  M.flush_counts(x_path, x_locate, x_peel, deposits)
+// Cells are bricked addresses (GridDev): densities, the absorbed tally
+// (wavelength-major, ncell_pad per wavelength) and the gradient are all in
+// the bricked layout inside the library.
 //
 // Adjoint (ADJ = true): the detached derivative of C, a peel-off contribution
 // of event e, with respect to the density of cell m is
@@ -284,7 +287,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
       } else {
         L.lam = (int)(item / P.n_pkg);
         L.pkg = P.first + (item - (unsigned long long)L.lam * P.n_pkg);
-        L.lam_cell = (long long)L.lam * G.ncell;
+        L.lam_cell = (long long)L.lam * G.ncell_pad;
         const LamDev& LD = M.lam(L.lam);
         L.kap = LD.kappa;
         L.kapR = (R)L.kap;
@@ -322,9 +325,9 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     //    its end is handled in the next pass)
     if (want) {
       const double* d = to_det ? M.det(L.det).kd : L.k;
-      ray_begin(L.ry, G, M, L.r, d);
+      ray_begin(L.ry, G, L.r, d);
       if (L.mode == M_LOCATE) {
-        L.last_cell = L.ry.cell;
+        L.last_cell = ray_cell(L.ry, G);
         L.last_t = L.ry.t;
       }
     }
@@ -345,7 +348,7 @@ template <typename R, bool ADJ, class Mem>
 MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M) {
   Ray<R>& ry = L.ry;
   WalkBlock<kBlockWalk, R> b;
-  ray_next_block(ry, b, M);
+  ray_next_block(ry, b, P.G, M);
 #pragma unroll
   for (int d = 0; d < kBlockWalk; ++d) {
     if (d >= b.n) break;
@@ -461,7 +464,7 @@ MCRT_HD void trace_events(TraceLane<R>& L, const TraceParams& P, Mem& M) {
     M.ray(L.q, o, k);
     L.nseg = 0;
     L.pending = true;
-    ray_begin(L.ry, P.G, M, o, k);
+    ray_begin(L.ry, P.G, o, k);
   }
 }
 
@@ -469,7 +472,7 @@ template <typename R, class Mem>
 MCRT_HD void trace_step(TraceLane<R>& L, const TraceParams& P, Mem& M) {
   Ray<R>& ry = L.ry;
   WalkBlock<kBlockWalk, R> b;
-  ray_next_block(ry, b, M);
+  ray_next_block(ry, b, P.G, M);
   const R kap = (R)P.kappa;
 #pragma unroll
   for (int d = 0; d < kBlockWalk; ++d) {
@@ -543,7 +546,7 @@ MCRT_HD void peel_events(PeelLane<R>& L, const PeelParams& P, Mem& M) {
     L.pix = frame_pixel(M.det(L.d), r);
     if (L.pix < 0) continue;
     L.pending = true;
-    ray_begin(L.ry, P.G, M, r, M.det(L.d).kd);
+    ray_begin(L.ry, P.G, r, M.det(L.d).kd);
   }
 }
 
@@ -551,7 +554,7 @@ template <typename R, class Mem>
 MCRT_HD void peel_step(PeelLane<R>& L, const PeelParams& P, Mem& M) {
   Ray<R>& ry = L.ry;
   WalkBlock<kBlockWalk, R> b;
-  ray_next_block(ry, b, M);
+  ray_next_block(ry, b, P.G, M);
   const R kap = (R)P.kappa;
 #pragma unroll
   for (int d = 0; d < kBlockWalk; ++d) {

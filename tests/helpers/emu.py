@@ -43,9 +43,9 @@ class Emu:
                                              C.POINTER(B.Source), C.c_int, C.POINTER(B.Detector),
                                              C.POINTER(B.Opts), P, i64, P, i64, C.POINTER(B.Stats), C.c_int]
         lib.emu_trace_path.argtypes = [C.POINTER(B.Grid), P, d, C.c_int, C.c_int64, P, P, P, C.c_int32, P, P, P,
-                                       C.POINTER(C.c_uint64), C.c_int]
+                                       C.POINTER(C.c_uint64), C.c_int, C.c_int]
         lib.emu_peel_off.argtypes = [C.POINTER(B.Grid), P, d, d, C.c_int, C.c_int64, P, P, P, C.c_int,
-                                     C.POINTER(B.Detector), P, C.c_int]
+                                     C.POINTER(B.Detector), P, C.c_int, C.c_int]
         for f in ("emu_run_photons", "emu_backward_density", "emu_trace_path", "emu_peel_off"):
             getattr(lib, f).restype = C.c_int
         lib.emu_violation.restype = C.c_char_p
@@ -90,7 +90,7 @@ class Emu:
                                                   self._p(adj), adj.size, self._p(g), g.size, C.byref(st), wave))
         return g, st.as_dict()
 
-    def trace(self, box, n, rho, kappa, prec, origins, dirs, max_seg=0, wave=WAVE):
+    def trace(self, box, n, rho, kappa, prec, origins, dirs, max_seg=0, wave=WAVE, brick_shape=0):
         g = B.make_grid({"box": box, "n": n})
         dt = np.float32 if prec == 1 else np.float64
         rho = np.ascontiguousarray(np.asarray(rho).reshape(-1), dtype=dt)
@@ -104,10 +104,10 @@ class Emu:
         c = C.c_uint64(0)
         rc = self.lib.emu_trace_path(C.byref(g), self._p(rho), float(kappa), int(prec), nr, self._p(o), self._p(k),
                                      self._p(tau), int(max_seg), self._p(cell), self._p(length), self._p(nseg),
-                                     C.byref(c), wave)
+                                     C.byref(c), int(brick_shape), wave)
         return rc, tau, c.value, cell, length, nseg
 
-    def peel(self, box, n, rho, kappa, g, prec, pos, dir_in, w, detectors, wave=WAVE):
+    def peel(self, box, n, rho, kappa, g, prec, pos, dir_in, w, detectors, wave=WAVE, brick_shape=0):
         gr = B.make_grid({"box": box, "n": n})
         dt = np.float32 if prec == 1 else np.float64
         rho = np.ascontiguousarray(np.asarray(rho).reshape(-1), dtype=dt)
@@ -118,5 +118,5 @@ class Emu:
         images = np.zeros(int(sum(d["nx"] * d["ny"] for d in detectors)))
         self._check(self.lib.emu_peel_off(C.byref(gr), self._p(rho), float(kappa), float(g), int(prec), pos.shape[0],
                                           self._p(pos), self._p(din), self._p(w), len(detectors), dets,
-                                          self._p(images), wave))
+                                          self._p(images), int(brick_shape), wave))
         return images

@@ -35,10 +35,37 @@ struct Violation : std::runtime_error {
                                  " outside [0, " + std::to_string((long long)(lim)) + ")");               \
   } while (0)
 
+// Checks that c is the bricked address of a grid cell (not padding).
+inline void check_cell(const GridDev& G, long long c, const char* what) {
+  int i[3];
+  EMU_CHECK(c >= 0 && c < G.ncell_pad, what, c, G.ncell_pad);
+  EMU_CHECK(brick_cell(G, (int)c, i), (std::string(what) + " (padding cell)").c_str(), c, G.ncell_pad);
+}
+
+// Bricked copy of row-major densities, as the library makes on the device.
+template <typename R>
+std::vector<R> brick_copy(const GridDev& G, const R* rho) {
+  std::vector<R> out((size_t)G.ncell_pad, R(0));
+  for (int c = 0; c < G.ncell_pad; ++c) {
+    int i[3];
+    if (brick_cell(G, c, i)) out[c] = rho[i[0] + i[1] * G.stride[1] + i[2] * G.stride[2]];
+  }
+  return out;
+}
+
+// Bricked tally [n][ncell_pad] -> row-major [n][ncell].
+inline void unbrick(const GridDev& G, const std::vector<double>& src, double* dst, int n) {
+  for (int l = 0; l < n; ++l)
+    for (int m = 0; m < G.ncell; ++m) {
+      int i[3] = {m % G.n[0], (m / G.n[0]) % G.n[1], m / G.n[0] / G.n[1]};
+      dst[(long long)l * G.ncell + m] = src[(size_t)l * G.ncell_pad + brick_addr(G, i)];
+    }
+}
+
 template <typename R>
 struct HostLifeMem {
   const R* rho_;
-  long long ncell;
+  const GridDev& G;
   const host::Prepared& pr;
   double* images;
   long long n_images;
@@ -52,7 +79,7 @@ struct HostLifeMem {
   unsigned long long xs[7] = {0, 0, 0, 0, 0, 0, 0};
 
   R rho(int c) const {
-    EMU_CHECK(c >= 0 && c < ncell, "density", c, ncell);
+    check_cell(G, c, "density");
     return rho_[c];
   }
   const DetDev& det(int d) const {
@@ -77,10 +104,12 @@ struct HostLifeMem {
   }
   void add_absorbed(long long i, double v) {
     EMU_CHECK(i >= 0 && i < n_absorbed, "absorbed tally", i, n_absorbed);
+    check_cell(G, i % G.ncell_pad, "absorbed tally");
     absorbed[i] += v;
   }
   void add_grad(int i, double v) {
     EMU_CHECK(i >= 0 && i < n_grad, "gradient", i, n_grad);
+    check_cell(G, i, "gradient");
     grad[i] += v;
   }
   unsigned long long fetch() { return next++; }
@@ -136,17 +165,23 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   P.grad = grad;
   if (!ADJ && n_images < pr.n_images && (opts->flags & 3) && n_det > 0)
     throw Violation("image buffer smaller than the layout needs");
-  HostLifeMem<R> M{static_cast<const R*>(rho), (long long)P.G.ncell, pr, images, n_images, P.absorbed, n_absorbed,
-                   adj, n_adj, grad, n_grad};
+  if (P.absorbed && n_absorbed < (long long)P.n_lambda * P.G.ncell) throw Violation("absorbed buffer too small");
+  if (ADJ && grad && n_grad < P.G.ncell) throw Violation("gradient buffer too small");
+  const std::vector<R> rho_b = brick_copy(P.G, static_cast<const R*>(rho));
+  std::vector<double> abs_b(P.absorbed ? (size_t)P.n_lambda * P.G.ncell_pad : 0, 0.0);
+  std::vector<double> grad_b(ADJ && grad ? (size_t)P.G.ncell_pad : 0, 0.0);
+  HostLifeMem<R> M{rho_b.data(), P.G, pr, images, n_images, P.absorbed ? abs_b.data() : nullptr,
+                   (long long)abs_b.size(), adj, n_adj, grad_b.data(), (long long)grad_b.size()};
+  P.absorbed = M.absorbed;
   if (images && !ADJ) std::fill(images, images + n_images, 0.0);
-  if (P.absorbed) std::fill(absorbed, absorbed + n_absorbed, 0.0);
-  if (grad) std::fill(grad, grad + n_grad, 0.0);
   std::vector<Lane<R>> lanes(wave);
   for (auto& L : lanes) lane_init(L);
   const long long cap = (long long)P.G.n[0] + P.G.n[1] + P.G.n[2] + 8;
   run_wave(
       lanes, P.batch, [&](Lane<R>& L) { lane_events<R, ADJ>(L, P, M); },
       [&](Lane<R>& L) { lane_step<R, ADJ>(L, P, M); }, cap, 0);
+  if (P.absorbed) unbrick(P.G, abs_b, absorbed, P.n_lambda);
+  if (ADJ && grad) unbrick(P.G, grad_b, grad, 1);
   if (stats) {
     double sa = 0, se = 0, st = 0;
     for (auto& L : lanes) {
@@ -180,12 +215,11 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
 template <typename R>
 struct HostTraceMem {
   const R* rho_;
-  long long ncell;
   const TraceParams& P;
   long long cap_seg;  // entries of seg_cell / seg_len
   unsigned long long next = 0;
   R rho(int c) const {
-    EMU_CHECK(c >= 0 && c < ncell, "density", c, ncell);
+    check_cell(P.G, c, "density");
     return rho_[c];
   }
   unsigned long long fetch() { return next++; }
@@ -207,7 +241,8 @@ struct HostTraceMem {
   void store_seg(long long q, int j, int cell, double len) const {
     const long long i = q * P.max_seg + j;
     EMU_CHECK(j >= 0 && j < P.max_seg && i >= 0 && i < cap_seg, "segment", i, cap_seg);
-    P.seg_cell[i] = cell;
+    check_cell(P.G, cell, "segment cell");
+    P.seg_cell[i] = brick_to_linear(P.G, cell);
     P.seg_len[i] = len;
   }
 };
@@ -215,12 +250,13 @@ struct HostTraceMem {
 template <typename R>
 int emu_trace(const mcrt_grid* grid, const void* rho, double kappa, int64_t n_rays, const double* origin,
               const double* dir, double* tau, int32_t max_seg, int32_t* seg_cell, double* seg_len, int32_t* n_seg,
-              uint64_t* crossings, int wave) {
+              uint64_t* crossings, int brick_shape, int wave) {
   const bool lists = seg_cell != nullptr;
   TraceParams P;
   std::memset(&P, 0, sizeof P);
-  P.G = host::make_grid(*grid);
-  P.rho = rho;
+  if (int e = host::make_grid(*grid, (int)sizeof(R), brick_shape, P.G)) return e;
+  const std::vector<R> rho_b = brick_copy(P.G, static_cast<const R*>(rho));
+  P.rho = rho_b.data();
   P.kappa = kappa;
   P.n_rays = n_rays;
   P.origin = origin;
@@ -231,7 +267,7 @@ int emu_trace(const mcrt_grid* grid, const void* rho, double kappa, int64_t n_ra
   P.seg_len = lists ? seg_len : nullptr;
   P.n_seg = n_seg;
   P.batch = 16;
-  HostTraceMem<R> M{static_cast<const R*>(rho), (long long)P.G.ncell, P, lists ? (long long)max_seg * n_rays : 0};
+  HostTraceMem<R> M{rho_b.data(), P, lists ? (long long)max_seg * n_rays : 0};
   std::vector<TraceLane<R>> lanes(wave);
   for (auto& L : lanes) trace_init(L);
   const long long cap = (long long)P.G.n[0] + P.G.n[1] + P.G.n[2] + 8;
@@ -251,13 +287,12 @@ int emu_trace(const mcrt_grid* grid, const void* rho, double kappa, int64_t n_ra
 template <typename R>
 struct HostPeelMem {
   const R* rho_;
-  long long ncell;
   const PeelParams& P;
   const std::vector<DetDev>& dets;
   long long n_images;
   unsigned long long next = 0;
   R rho(int c) const {
-    EMU_CHECK(c >= 0 && c < ncell, "density", c, ncell);
+    check_cell(P.G, c, "density");
     return rho_[c];
   }
   unsigned long long fetch() { return next++; }
@@ -288,13 +323,14 @@ struct HostPeelMem {
 template <typename R>
 int emu_peel(const mcrt_grid* grid, const void* rho, double kappa, double g, int64_t n_events, const double* pos,
              const double* dir_in, const double* w, int n_det, const mcrt_detector* detectors, double* images,
-             int wave) {
+             int brick_shape, int wave) {
   long long npix = 0;
   std::vector<DetDev> det = host::make_dets(n_det, detectors, &npix);
   PeelParams P;
   std::memset(&P, 0, sizeof P);
-  P.G = host::make_grid(*grid);
-  P.rho = rho;
+  if (int e = host::make_grid(*grid, (int)sizeof(R), brick_shape, P.G)) return e;
+  const std::vector<R> rho_b = brick_copy(P.G, static_cast<const R*>(rho));
+  P.rho = rho_b.data();
   P.kappa = kappa;
   P.g = g;
   P.n_events = n_events;
@@ -304,7 +340,7 @@ int emu_peel(const mcrt_grid* grid, const void* rho, double kappa, double g, int
   P.w = w;
   P.images = images;
   P.batch = 16;
-  HostPeelMem<R> M{static_cast<const R*>(rho), (long long)P.G.ncell, P, det, npix};
+  HostPeelMem<R> M{rho_b.data(), P, det, npix};
   std::vector<PeelLane<R>> lanes(wave);
   for (auto& L : lanes) peel_init(L);
   const long long cap = (long long)P.G.n[0] + P.G.n[1] + P.G.n[2] + 8;
@@ -373,7 +409,7 @@ int emu_backward_density(const mcrt_grid* grid, const void* rho, const mcrt_opti
 
 int emu_trace_path(const mcrt_grid* grid, const void* rho, double kappa, int precision, int64_t n_rays,
                    const double* origin, const double* dir, double* tau, int32_t max_seg, int32_t* seg_cell,
-                   double* seg_len, int32_t* n_seg, uint64_t* crossings, int wave) {
+                   double* seg_len, int32_t* n_seg, uint64_t* crossings, int brick_shape, int wave) {
   try {
     g_violation.clear();
     host::last_error().clear();
@@ -385,9 +421,9 @@ int emu_trace_path(const mcrt_grid* grid, const void* rho, double kappa, int pre
     }
     return precision == MCRT_PREC_FP32
                ? emu_trace<float>(grid, rho, kappa, n_rays, origin, dir, tau, max_seg, seg_cell, seg_len, n_seg,
-                                  crossings, wave)
+                                  crossings, brick_shape, wave)
                : emu_trace<double>(grid, rho, kappa, n_rays, origin, dir, tau, max_seg, seg_cell, seg_len, n_seg,
-                                   crossings, wave);
+                                   crossings, brick_shape, wave);
   } catch (const Violation& v) {
     g_violation = std::string("trace_path: ") + v.what();
     return -100;
@@ -396,7 +432,7 @@ int emu_trace_path(const mcrt_grid* grid, const void* rho, double kappa, int pre
 
 int emu_peel_off(const mcrt_grid* grid, const void* rho, double kappa, double g, int precision, int64_t n_events,
                  const double* pos, const double* dir_in, const double* w, int n_det, const mcrt_detector* detectors,
-                 double* images, int wave) {
+                 double* images, int brick_shape, int wave) {
   try {
     g_violation.clear();
     host::last_error().clear();
@@ -404,8 +440,10 @@ int emu_peel_off(const mcrt_grid* grid, const void* rho, double kappa, double g,
       return e;
     if (n_events == 0) return 0;
     return precision == MCRT_PREC_FP32
-               ? emu_peel<float>(grid, rho, kappa, g, n_events, pos, dir_in, w, n_det, detectors, images, wave)
-               : emu_peel<double>(grid, rho, kappa, g, n_events, pos, dir_in, w, n_det, detectors, images, wave);
+               ? emu_peel<float>(grid, rho, kappa, g, n_events, pos, dir_in, w, n_det, detectors, images,
+                                 brick_shape, wave)
+               : emu_peel<double>(grid, rho, kappa, g, n_events, pos, dir_in, w, n_det, detectors, images,
+                                  brick_shape, wave);
   } catch (const Violation& v) {
     g_violation = std::string("peel_off: ") + v.what();
     return -100;
