@@ -122,7 +122,12 @@ typedef struct {
  * brick of the library's internal cell layout, MCRT_BRICK(lx, ly, lz) for
  * bricks of 2^lx x 2^ly x 2^lz cells (each log2 in [0, 7], at most 2^10
  * cells).  The default brick fills one 128-byte cache line with the most
- * compact block of cells in physical units. */
+ * compact block of cells in physical units.  deposit_queue (backward_density
+ * only) caps the device queue of peel-ray deposit walks, in rays (at most
+ * 2^31): 0 = library choice, -1 = no queue (every deposit ray is walked inline with global
+ * atomics); rays beyond the cap are walked inline.  Queued rays are sorted by
+ * frame and image-plane tile and walked in bundles whose deposits are summed
+ * in LDS before they reach the gradient. */
 typedef struct {
     uint64_t n_packages, first_package, seed;
     int32_t precision;
@@ -131,6 +136,7 @@ typedef struct {
     uint32_t flags;
     int32_t launch_blocks, event_batch;
     int32_t brick_shape;
+    int64_t deposit_queue;
 } mcrt_opts;
 
 #define MCRT_BRICK(lx, ly, lz) (0x1000 | (lx) | ((ly) << 4) | ((lz) << 8))
@@ -217,7 +223,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 2
+#define MCRT_ABI_VERSION 3
 
 #ifdef __cplusplus
 }

@@ -90,7 +90,33 @@ struct DetDev {
   double inv_d2, half_x, half_y, inv_dpx, inv_dpy;  // pixels per unit length
   int nx, ny;
   long long off;  // offset of this frame inside one wavelength's image block
+  // Sort keys of the adjoint's deposit rays: the pixel (coarsened to
+  // 2^tshift x 2^tshift blocks on very large frames) in Morton order,
+  // numbered from key_off.  Rays of one frame whose keys are close land
+  // close together in the image, so they are parallel rays a few cells
+  // apart that cross one narrow bundle of cells.
+  int tshift, key_off;
 };
+
+// Interleaves the low 16 bits of x (even bits) and y (odd bits).
+MCRT_HD unsigned morton2(unsigned x, unsigned y) {
+  unsigned v[2] = {x & 0xffffu, y & 0xffffu};
+  for (int a = 0; a < 2; ++a) {
+    unsigned t = v[a];
+    t = (t | (t << 8)) & 0x00ff00ffu;
+    t = (t | (t << 4)) & 0x0f0f0f0fu;
+    t = (t | (t << 2)) & 0x33333333u;
+    t = (t | (t << 1)) & 0x55555555u;
+    v[a] = t;
+  }
+  return v[0] | (v[1] << 1);
+}
+
+// Sort key of pixel `pix` of frame D.
+MCRT_HD unsigned tile_key(const DetDev& D, int pix) {
+  const int iy = pix / D.nx, ix = pix - iy * D.nx;
+  return (unsigned)D.key_off + morton2((unsigned)ix >> D.tshift, (unsigned)iy >> D.tshift);
+}
 
 struct SrcDev {
   int kind;  // 0 point, 1 exponential disk
@@ -353,7 +379,9 @@ struct WalkBlock {
   bool out;      // the walk has left the grid after entry n-1
 };
 
-template <int D, typename R, class Mem>
+// LOAD = false skips the density loads (walks whose work does not depend on
+// the densities, such as the adjoint's peel-ray deposits).
+template <int D, typename R, class Mem, bool LOAD = true>
 MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, const GridDev& G, Mem& M) {
   b.n = 0;
   b.adv = 0;
@@ -378,8 +406,10 @@ MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, const GridDev& G, Me
                          (unsigned)ry.i[2] >= (unsigned)G.n[2];
     b.out = b.out || outside || !(ax || ay || az);
   }
+  if constexpr (LOAD) {
 #pragma unroll
-  for (int d = 0; d < D; ++d) b.rho[d] = M.rho(b.cell[d]);
+    for (int d = 0; d < D; ++d) b.rho[d] = M.rho(b.cell[d]);
+  }
 }
 
 // Undoes the plane crossings of sub-steps d .. D-1 of the last block, so the

@@ -172,7 +172,27 @@ inline DetDev make_det(const mcrt_detector& D, long long off) {
   R.nx = D.nx;
   R.ny = D.ny;
   R.off = off;
+  R.tshift = 0;
+  R.key_off = 0;
   return R;
+}
+
+// Sort-key ranges of the frames (tile_key): a Morton index over the pixels,
+// or over 2^tshift-pixel blocks when a frame would need more than 2^22
+// keys.  Returns the total number of keys.
+inline long long tile_frames(std::vector<DetDev>& det, int n_det) {
+  long long keys = 0;
+  for (int d = 0; d < n_det; ++d) {
+    DetDev& D = det[d];
+    int k = 0;
+    while ((1 << k) < std::max(D.nx, D.ny)) ++k;
+    int ts = 0;
+    while (2 * (k - ts) > 22) ++ts;
+    D.tshift = ts;
+    D.key_off = (int)keys;
+    keys += 1ll << (2 * (k - ts));
+  }
+  return keys;
 }
 
 // Checked run description of run_photons / backward_density.
@@ -183,6 +203,7 @@ struct Prepared {
   std::vector<SrcDev> src;
   long long n_images = 0;  // comps * n_lambda * pixels of all frames
   double emitted = 0.0;    // sum over wavelengths of n_packages * w0
+  long long n_keys = 0;    // image-plane tiles over all frames
 };
 
 inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
@@ -227,6 +248,8 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
   if (opts->flags & ~15u) return fail(MCRT_EINVAL, "unknown flag bits 0x%x", opts->flags);
   if (opts->launch_blocks < 0 || opts->launch_blocks > 64) return fail(MCRT_EINVAL, "launch_blocks outside [0, 64]");
   if (opts->event_batch < 0 || opts->event_batch > 64) return fail(MCRT_EINVAL, "event_batch outside [0, 64]");
+  if (opts->deposit_queue < -1 || opts->deposit_queue > (1ll << 31))
+    return fail(MCRT_EINVAL, "deposit_queue outside [-1, 2^31]");
 
   RunParams& P = out.P;
   std::memset(&P, 0, sizeof P);
@@ -270,6 +293,7 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
   }
   P.pix_lambda = off;
   out.n_images = (long long)P.comps * nl * off;
+  out.n_keys = tile_frames(out.det, n_det);
   out.src.assign(n_src, SrcDev{});
   for (int s = 0; s < n_src; ++s) {
     out.src[s].kind = sources[s].kind;

@@ -87,6 +87,15 @@ __device__ __forceinline__ unsigned long long wave_fetch(unsigned long long* cou
 
 constexpr int kWavesPerBlock = kBlock / 64;
 
+// Counter block of a life-cycle call (u64 words): [0] next work item,
+// [8..10] FP64 luminosity stats, [16..22] crossing and event counts,
+// [24] next deposit-queue slot, [25] next tile key of the bundle walk.
+constexpr int kJobCounter = 24, kKeyCounter = 25;
+// Deposit-queue slots are reserved per wavefront in chunks (one global
+// atomic per chunk); slots a wavefront reserved but did not fill are marked
+// with kNoKey when it exits, and the sort skips them.
+constexpr unsigned kJobChunk = 256, kNoKey = 0xffffffffu;
+
 // Per-wavefront reservoir slots in LDS; lane 0 of each wavefront empties its
 // slot before the wavefront's first fetch.
 __device__ __forceinline__ unsigned long long* wave_reservoir(unsigned long long (&slots)[kWavesPerBlock][2]) {
@@ -103,6 +112,7 @@ struct LifeMem {
   const R* __restrict__ rho_;
   const RunParams& P;
   unsigned long long* res;
+  unsigned long long* job_res;
   __device__ R rho(int c) const { return rho_[c]; }
   __device__ const DetDev& det(int d) const { return P.det[d]; }
   __device__ const LamDev& lam(int l) const { return P.lam[l]; }
@@ -112,6 +122,18 @@ struct LifeMem {
   __device__ void add_absorbed(long long i, double v) const { atomic_add_f64(P.absorbed + i, v); }
   __device__ void add_grad(int i, double v) const { atomic_add_f64(P.grad + i, v); }
   __device__ unsigned long long fetch() const { return wave_fetch(P.work, res, 64); }
+  __device__ unsigned long long job_slot() const { return wave_fetch(P.work + kJobCounter, job_res, kJobChunk); }
+  __device__ double ev_load(int slot, int e, int k) const { return P.evs[(2ull * e + k) * P.n_slots + slot]; }
+  __device__ void ev_store(int slot, int e, int k, double v) const { P.evs[(2ull * e + k) * P.n_slots + slot] = v; }
+  __device__ void store_job(unsigned long long slot, const double r[3], double w, unsigned key) const {
+    BpJob& J = P.jobs[slot];
+    J.r[0] = r[0];
+    J.r[1] = r[1];
+    J.r[2] = r[2];
+    J.w = w;
+    J.key = key;
+    J.rank = 0;
+  }
   __device__ void flush_counts(unsigned a, unsigned b, unsigned c, unsigned d) const {
     atomicAdd(P.xstats + 0, (unsigned long long)a);
     atomicAdd(P.xstats + 1, (unsigned long long)b);
@@ -168,10 +190,11 @@ struct PeelMem {
 
 template <typename R, bool ADJ>
 __global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
-  __shared__ unsigned long long slots[kWavesPerBlock][2];
-  LifeMem<R> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots)};
+  __shared__ unsigned long long slots[kWavesPerBlock][2], job_slots[kWavesPerBlock][2];
+  LifeMem<R> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots), wave_reservoir(job_slots)};
   Lane<R> L;
   lane_init(L);
+  L.slot = blockIdx.x * kBlock + threadIdx.x;
   for (;;) {
     lane_events<R, ADJ>(L, P, M);
     const unsigned long long live = __ballot(!L.done);
@@ -182,6 +205,10 @@ __global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
       if (n_act == 0 || n_live - n_act >= P.batch) break;
       if (L.ry.active) lane_step<R, ADJ>(L, P, M);
     }
+  }
+  if (ADJ && P.jobs) {  // unfilled reserved queue slots
+    const unsigned long long lo = M.job_res[0], hi = M.job_res[1] < P.job_cap ? M.job_res[1] : P.job_cap;
+    for (unsigned long long q = lo + __lane_id(); q < hi; q += 64) P.jobs[q].key = kNoKey;
   }
   const double s_abs = wave_sum(L.s_abs), s_esc = wave_sum(L.s_esc), s_trunc = wave_sum(L.s_trunc);
   const unsigned long long a0 = wave_sum_u64(L.x_path), a1 = wave_sum_u64(L.x_loc), a2 = wave_sum_u64(L.x_peel),
@@ -241,6 +268,183 @@ __global__ void __launch_bounds__(kBlock) k_peel(const PeelParams P) {
       if (n_act == 0 || n_live - n_act >= P.batch) break;
       if (L.ry.active) peel_step(L, P, M);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint deposit rays, walked in bundles.  The life-cycle kernel queues
+// each peel ray that must deposit -A C kappa l.  A counting sort by key
+// (k_count, k_scan, k_perm) orders the queue by frame and by pixel in Morton
+// order, so any run of consecutive sorted rays is a compact patch of one
+// frame: parallel rays a few cells apart that cross one narrow bundle of
+// cells.  k_bundle hands such runs (chunks) to workgroups, walks them and
+// sums the deposits per cell in an LDS hash table, then adds each distinct
+// cell to the gradient with one global atomic.  Global atomics execute at
+// the memory side at a fixed request rate, so this replaces one atomic per
+// crossing by about one per cell and chunk.
+
+// Queue slots handed out (the counter may have run past the capacity).
+__device__ __forceinline__ unsigned long long queued_jobs(const unsigned long long* ctr, unsigned long long cap) {
+  const unsigned long long n = ctr[kJobCounter];
+  return n < cap ? n : cap;
+}
+
+__global__ void k_count(BpJob* __restrict__ jobs, const unsigned long long* __restrict__ ctr, unsigned long long cap,
+                        unsigned* __restrict__ kcount) {
+  const unsigned long long n = queued_jobs(ctr, cap);
+  for (unsigned long long j = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; j < n;
+       j += (unsigned long long)gridDim.x * blockDim.x) {
+    const unsigned key = jobs[j].key;
+    if (key != kNoKey) jobs[j].rank = atomicAdd(kcount + key, 1u);
+  }
+}
+
+// Exclusive scan of kcount[0, n) into kstart[0, n]; one block of kScanThreads.
+constexpr int kScanThreads = 1024;
+__global__ void __launch_bounds__(kScanThreads) k_scan(const unsigned* __restrict__ kcount, unsigned* __restrict__ kstart,
+                                                       long long n) {
+  __shared__ unsigned part[kScanThreads];
+  const long long per = (n + kScanThreads - 1) / kScanThreads;
+  const long long lo = threadIdx.x * per, hi = lo + per < n ? lo + per : n;
+  unsigned s = 0;
+  for (long long i = lo; i < hi; ++i) s += kcount[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {  // Hillis-Steele inclusive scan
+    const unsigned v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  unsigned run = part[threadIdx.x] - s;
+  for (long long i = lo; i < hi; ++i) {
+    kstart[i] = run;
+    run += kcount[i];
+  }
+  if (threadIdx.x == kScanThreads - 1) kstart[n] = part[kScanThreads - 1];
+}
+
+__global__ void k_perm(const BpJob* __restrict__ jobs, const unsigned long long* __restrict__ ctr,
+                       unsigned long long cap, const unsigned* __restrict__ kstart, unsigned* __restrict__ perm) {
+  const unsigned long long n = queued_jobs(ctr, cap);
+  for (unsigned long long j = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; j < n;
+       j += (unsigned long long)gridDim.x * blockDim.x) {
+    const unsigned key = jobs[j].key;
+    if (key != kNoKey) perm[kstart[key] + jobs[j].rank] = (unsigned)j;
+  }
+}
+
+constexpr int kBundleThreads = 512, kBundleWaves = kBundleThreads / 64;
+constexpr int kTableBits = 13, kTable = 1 << kTableBits, kProbes = 4;
+constexpr unsigned kChunk = 2048;
+
+struct BundleParams {
+  GridDev G;
+  const DetDev* det;
+  int n_det;
+  long long n_keys;
+  const BpJob* jobs;
+  const unsigned* perm;
+  const unsigned* kstart;
+  double* grad;
+  unsigned long long* ctr;  // counter block of the call
+  int batch;
+};
+
+// Deposits into the workgroup's LDS table (open addressing, linear probing
+// over at most kProbes slots); a deposit that finds no slot goes straight
+// to the global tally.
+struct BundleMem {
+  int* tk;
+  double* tv;
+  double* grad;
+  __device__ void deposit(int cell, double v) const {
+    const unsigned h = ((unsigned)cell * 2654435761u) >> (32 - kTableBits);
+    for (int p = 0; p < kProbes; ++p) {
+      const unsigned i = (h + (unsigned)p) & (kTable - 1);
+      int k = __hip_atomic_load(tk + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (k == -1) {
+        k = atomicCAS(tk + i, -1, cell);
+        if (k == -1) k = cell;
+      }
+      if (k == cell) {
+        __hip_atomic_fetch_add(tv + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return;
+      }
+    }
+    atomic_add_f64(grad + cell, v);
+  }
+};
+
+// Frame of a sort key.
+__device__ __forceinline__ int key_frame(const BundleParams& P, unsigned key) {
+  int d = 0;
+  while (d + 1 < P.n_det && (unsigned)P.det[d + 1].key_off <= key) ++d;
+  return d;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBundleThreads) k_bundle(const BundleParams P) {
+  __shared__ int tk[kTable];
+  __shared__ double tv[kTable];
+  __shared__ unsigned s_begin, s_end, s_next;
+  for (int i = threadIdx.x; i < kTable; i += kBundleThreads) {
+    tk[i] = -1;
+    tv[i] = 0.0;
+  }
+  const BundleMem M{tk, tv, P.grad};
+  const unsigned n_jobs = P.kstart[P.n_keys];
+  unsigned long long nx = 0;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const unsigned long long b = atomicAdd(P.ctr + kKeyCounter, 1ull) * kChunk;
+      s_begin = s_next = b < n_jobs ? (unsigned)b : n_jobs;
+      s_end = b + kChunk < n_jobs ? (unsigned)(b + kChunk) : n_jobs;
+    }
+    __syncthreads();
+    const unsigned end = s_end;
+    if (s_begin >= end) break;  // s_begin and s_end change only after the closing barrier
+    // every lane walks rays of the chunk until it is exhausted; a wavefront
+    // takes new rays once `batch` of its lanes are idle
+    Ray<R> ry;
+    ry.active = false;
+    double w = 0.0;
+    bool done = false;
+    for (;;) {
+      while (!ry.active && !done) {
+        const unsigned q = atomicAdd(&s_next, 1u);
+        if (q >= end) {
+          done = true;
+          break;
+        }
+        const BpJob& J = P.jobs[P.perm[q]];
+        w = J.w;
+        ray_begin(ry, P.G, J.r, P.det[key_frame(P, J.key)].kd);
+      }
+      const unsigned long long live = __ballot(!done);
+      if (live == 0ull) break;
+      const int n_live = __popcll(live);
+      for (;;) {
+        const int n_act = __popcll(__ballot(ry.active));
+        if (n_act == 0 || n_live - n_act >= P.batch) break;
+        if (ry.active) nx += bp_step<R>(ry, P.G, w, M);
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTable; i += kBundleThreads) {
+      const int c = tk[i];
+      if (c >= 0) {
+        atomic_add_f64(P.grad + c, tv[i]);
+        tk[i] = -1;
+        tv[i] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  const unsigned long long wsum = wave_sum_u64(nx);
+  if (__lane_id() == 0 && wsum) {
+    atomicAdd(P.ctr + 16 + 2, wsum);  // x_peel
+    atomicAdd(P.ctr + 16 + 6, wsum);  // deposits
   }
 }
 
@@ -308,6 +512,11 @@ int persistent_grid(K kernel, int blocks_per_cu, int* grid_out) {
 
 unsigned stream_blocks(long long n) { return (unsigned)std::min<long long>((n + kBlock - 1) / kBlock, 16384); }
 
+__global__ void k_zero_u32(unsigned* __restrict__ p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 int zero_fill(double* p, long long n, hipStream_t st) {
   if (!p || n <= 0) return 0;
   hipLaunchKernelGGL(k_zero, dim3(stream_blocks(n)), dim3(kBlock), 0, st, p, n);
@@ -353,14 +562,95 @@ struct EventPair {
   }
 };
 
+// Device memory of the adjoint's deposit queue: jobs, their sorted order
+// and the per-key counts and starts.
+struct DepositQueue {
+  unsigned char* ptr = nullptr;
+  hipStream_t st = nullptr;
+  unsigned long long cap = 0;
+  long long n_keys = 0;
+  BpJob* jobs = nullptr;
+  unsigned *perm = nullptr, *kcount = nullptr, *kstart = nullptr;
+  ~DepositQueue() {
+    if (ptr) (void)hipFreeAsync(ptr, st);
+  }
+};
+
+int make_queue(const mcrt_opts& o, const host::Prepared& pr, hipStream_t st, DepositQueue& q) {
+  q.st = st;
+  q.n_keys = pr.n_keys;
+  unsigned long long cap;
+  if (o.deposit_queue > 0) {
+    cap = (unsigned long long)o.deposit_queue;
+  } else {
+    // every event peels off once per frame; 8 events per package covers the
+    // typical package, and the rest is walked inline
+    cap = pr.P.n_items * (unsigned long long)pr.P.n_det * 8ull;
+    cap = std::min(std::max(cap, 1ull << 16), 1ull << 28);
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    cap = std::min<unsigned long long>(cap, free_b / 4 / (sizeof(BpJob) + sizeof(unsigned)));
+    if (cap == 0) return 0;
+  }
+  const size_t off_perm = align256(sizeof(BpJob) * cap);
+  const size_t off_cnt = off_perm + align256(sizeof(unsigned) * cap);
+  const size_t off_start = off_cnt + align256(sizeof(unsigned) * (size_t)q.n_keys);
+  const size_t bytes = off_start + align256(sizeof(unsigned) * (size_t)(q.n_keys + 1));
+  HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&q.ptr), bytes, st));
+  q.cap = cap;
+  q.jobs = reinterpret_cast<BpJob*>(q.ptr);
+  q.perm = reinterpret_cast<unsigned*>(q.ptr + off_perm);
+  q.kcount = reinterpret_cast<unsigned*>(q.ptr + off_cnt);
+  q.kstart = reinterpret_cast<unsigned*>(q.ptr + off_start);
+  hipLaunchKernelGGL(k_zero_u32, dim3(stream_blocks(q.n_keys)), dim3(kBlock), 0, st, q.kcount, q.n_keys);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+// Sorts the queued rays by tile key and walks them in bundles.
+template <typename R>
+int run_queue(const DepositQueue& q, const RunParams& P, unsigned long long* ctr, hipStream_t st) {
+  hipLaunchKernelGGL(k_count, dim3(stream_blocks((long long)q.cap)), dim3(kBlock), 0, st, q.jobs, ctr, q.cap,
+                     q.kcount);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, q.kcount, q.kstart, q.n_keys);
+  hipLaunchKernelGGL(k_perm, dim3(stream_blocks((long long)q.cap)), dim3(kBlock), 0, st, q.jobs, ctr, q.cap,
+                     q.kstart, q.perm);
+  HIPCHK(hipGetLastError());
+  BundleParams B;
+  B.G = P.G;
+  B.det = P.det;
+  B.n_det = P.n_det;
+  B.n_keys = q.n_keys;
+  B.jobs = q.jobs;
+  B.perm = q.perm;
+  B.kstart = q.kstart;
+  B.grad = P.grad;
+  B.ctr = ctr;
+  B.batch = 16;
+  int dev = 0, cus = 0, nb = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bundle<R>, kBundleThreads, 0));
+  hipLaunchKernelGGL(k_bundle<R>, dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0, st, B);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
 template <typename R, bool ADJ>
-int launch_life(const RunParams& P, int blocks_per_cu, hipStream_t st) {
-  int nblk = 0;
-  if (int e = persistent_grid(k_life<R, ADJ>, blocks_per_cu, &nblk)) return e;
+int life_grid(int blocks_per_cu, int* nblk) {
+  return persistent_grid(k_life<R, ADJ>, blocks_per_cu, nblk);
+}
+
+template <typename R, bool ADJ>
+int launch_life(const RunParams& P, int nblk, hipStream_t st) {
   hipLaunchKernelGGL((k_life<R, ADJ>), dim3(nblk), dim3(kBlock), 0, st, P);
   HIPCHK(hipGetLastError());
   return 0;
 }
+
+// Events per package kept in the adjoint's event scratch (more are walked
+// again in pass B).
+constexpr int kEventsKept = 32;
 
 // Shared driver of run_photons and backward_density.
 int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
@@ -384,6 +674,14 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   }
   const int nl = P.n_lambda;
   const bool f32 = opts->precision == MCRT_PREC_FP32;
+  int nblk = 0;
+  if (int e = adjoint ? (f32 ? life_grid<float, true>(opts->launch_blocks, &nblk)
+                             : life_grid<double, true>(opts->launch_blocks, &nblk))
+                      : (f32 ? life_grid<float, false>(opts->launch_blocks, &nblk)
+                             : life_grid<double, false>(opts->launch_blocks, &nblk)))
+    return e;
+  const unsigned long long n_slots = (unsigned long long)nblk * kBlock;
+  const size_t n_evs = adjoint ? (size_t)n_slots * 2 * kEventsKept : 0;
   const long long n_tally = adjoint ? (long long)P.G.ncell_pad : (P.absorbed ? (long long)nl * P.G.ncell_pad : 0);
   const size_t off_lam = 0;
   const size_t off_det = align256(sizeof(LamDev) * nl);
@@ -391,7 +689,8 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const size_t off_cnt = off_src + align256(sizeof(SrcDev) * pr.src.size());
   const size_t off_rho = off_cnt + 256;
   const size_t off_tal = off_rho + align256((size_t)P.G.ncell_pad * (f32 ? 4 : 8));
-  const size_t bytes = off_tal + align256(sizeof(double) * (size_t)n_tally);
+  const size_t off_evs = off_tal + align256(sizeof(double) * (size_t)n_tally);
+  const size_t bytes = off_evs + align256(sizeof(double) * n_evs);
   std::vector<unsigned char> blob(off_rho, 0);
   std::memcpy(blob.data() + off_lam, pr.lam.data(), sizeof(LamDev) * nl);
   std::memcpy(blob.data() + off_det, pr.det.data(), sizeof(DetDev) * pr.det.size());
@@ -410,6 +709,11 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     P.grad = tally;
   else
     P.absorbed = tally;
+  if (adjoint) {
+    P.evs = reinterpret_cast<double*>(blk.ptr + off_evs);
+    P.n_slots = n_slots;
+    P.ev_max = kEventsKept;
+  }
   P.lam = reinterpret_cast<const LamDev*>(blk.ptr + off_lam);
   P.det = reinterpret_cast<const DetDev*>(blk.ptr + off_det);
   P.src = reinterpret_cast<const SrcDev*>(blk.ptr + off_src);
@@ -419,6 +723,13 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   if (!adjoint)
     if (int e = zero_fill(P.images, peel ? pr.n_images : 0, st)) return e;
   if (int e = zero_fill(tally, n_tally, st)) return e;
+  DepositQueue queue;
+  if (adjoint && peel && opts->deposit_queue != -1) {
+    if (int e = make_queue(*opts, pr, st, queue)) return e;
+    P.jobs = queue.cap ? queue.jobs : nullptr;
+    P.job_cap = queue.cap;
+  }
+  unsigned long long* const ctr = reinterpret_cast<unsigned long long*>(blk.ptr + off_cnt);
   EventPair ev;
   if (stats) {
     HIPCHK(hipEventCreate(&ev.a));
@@ -427,12 +738,14 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   }
   int rc;
   if (adjoint)
-    rc = f32 ? launch_life<float, true>(P, opts->launch_blocks, st)
-             : launch_life<double, true>(P, opts->launch_blocks, st);
+    rc = f32 ? launch_life<float, true>(P, nblk, st) : launch_life<double, true>(P, nblk, st);
   else
-    rc = f32 ? launch_life<float, false>(P, opts->launch_blocks, st)
-             : launch_life<double, false>(P, opts->launch_blocks, st);
+    rc = f32 ? launch_life<float, false>(P, nblk, st) : launch_life<double, false>(P, nblk, st);
   if (rc) return rc;
+  if (P.jobs) {
+    rc = f32 ? run_queue<float>(queue, P, ctr, st) : run_queue<double>(queue, P, ctr, st);
+    if (rc) return rc;
+  }
   if (stats) HIPCHK(hipEventRecord(ev.b, st));
   if (tally)
     if (int e = unbrick_tally(P.G, tally, user_tally, adjoint ? 1 : nl, st)) return e;

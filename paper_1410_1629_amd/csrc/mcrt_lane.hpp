@@ -20,6 +20,8 @@
 //   M.rho(cell)  M.det(d)  M.lam(l)  M.src(s)  M.adj(i)
 //   M.add_image(i, v)  M.add_absorbed(i, v)  M.add_grad(cell, v)
 //   M.fetch()  M.flush_counts(x_path, x_locate, x_peel, deposits)
+//   M.job_slot()  M.store_job(slot, r, w, key)   (adjoint deposit queue)
+//   M.ev_load(slot, e, k)  M.ev_store(slot, e, k, v)   (adjoint event scratch)
 // Cells are bricked addresses (GridDev): densities, the absorbed tally
 // (wavelength-major, ncell_pad per wavelength) and the gradient are all in
 // the bricked layout inside the library.
@@ -30,10 +32,14 @@
 // (c_i: cell of scattering i; leg_i: path from event i-1 to it).  With
 // A = dL/dI at C's pixel and G_e the sum of A C over the frames for event e,
 // the gradient collects, per package, R_i = sum_{e>=i} G_e on leg i and on
-// c_i, and A C on each peel ray.  Pass A replays the package to get
-// R_1 = sum_e G_e; pass B replays it again and deposits, keeping
-// R_i = R_1 - sum_{e<i} G_e; each peel ray is walked once for C and, when
-// A C != 0, a second time to deposit.
+// c_i, and A C on each peel ray.  Pass A replays the package: it walks each
+// peel ray for C and, when A C != 0, queues a second walk of the same ray
+// that deposits -A C kappa l (or walks it at once when the queue is full);
+// it keeps G_e and the optical depth T of each leg in the lane's event
+// scratch and sums R_1 = sum_e G_e.  Pass B replays the package again with
+// R_i = R_1 - sum_{e<i} G_e and deposits along the locate walks; it reads
+// G_e and T from the scratch instead of walking peel rays and paths again
+// (events beyond the scratch are walked as in pass A, without deposits).
 #pragma once
 
 #include "mcrt_device.hpp"
@@ -56,6 +62,16 @@ enum Phase : int {
   PH_PKG_END
 };
 
+// A queued adjoint deposit ray: from r towards frame `key`'s observer,
+// depositing w * (segment length) into every cell crossed (w = -A C kappa).
+// key is the image-plane tile key (tile_key), rank the job's place among the
+// jobs of its key (set by the counting pass).
+struct BpJob {
+  double r[3];
+  double w;
+  unsigned key, rank;
+};
+
 struct RunParams {
   GridDev G;
   const void* rho;
@@ -76,6 +92,11 @@ struct RunParams {
   double* dstats;              // absorbed, escaped, truncated
   unsigned long long* xstats;  // x_path, x_locate, x_peel, events, packages, peels, deposits
   int batch;
+  BpJob* jobs;                 // adjoint: queue of peel-ray deposit walks (NULL: walk inline)
+  unsigned long long job_cap;  // its capacity; rays beyond it are walked inline
+  int ev_max;                  // adjoint: events kept per package in the event scratch
+  double* evs;                 // event scratch [ev_max][2][n_slots]: G_e, T of the leg after e
+  unsigned long long n_slots;  // lanes of the launch
 };
 
 template <typename R>
@@ -94,7 +115,9 @@ struct Lane {
   long long lam_cell;
   // adjoint replay
   int pass;
-  double Rtot, Gacc, Gabs, fac;
+  int slot;  // the lane's index in the event scratch
+  double Rtot, Gacc, Gabs, fac, Ge;
+  bool t_kept;  // pass B: T of the next leg is in the scratch
   // statistics
   double s_abs, s_esc, s_trunc;
   unsigned x_path, x_loc, x_peel, n_ev, n_pk, n_pl, n_dep;
@@ -122,9 +145,34 @@ MCRT_HD void lane_init(Lane<R>& L) {
   L.hit_cell = L.last_cell = 0;
   L.lam_cell = 0;
   L.pass = 0;
-  L.Rtot = L.Gacc = L.Gabs = L.fac = 0.0;
+  L.slot = 0;
+  L.Rtot = L.Gacc = L.Gabs = L.fac = L.Ge = 0.0;
+  L.t_kept = false;
   L.s_abs = L.s_esc = L.s_trunc = 0.0;
   L.x_path = L.x_loc = L.x_peel = L.n_ev = L.n_pk = L.n_pl = L.n_dep = 0;
+}
+
+// Adjoint bookkeeping of one event (emission or scattering n = L.n): its
+// peel-off contributions sum to G_e.  Pass A sums them into L.Ge while it
+// walks the peel rays and keeps the sum in the event scratch; pass B takes
+// the kept sum and skips the event's peel-offs.  Events beyond the scratch
+// walk their peel rays in both passes.
+// Called once the event's next phase is set: events without peel-off (the
+// flags exclude it) have G_e = 0 and nothing in the scratch.
+template <typename R, class Mem>
+MCRT_HD void event_start(Lane<R>& L, const RunParams& P, Mem& M) {
+  L.Ge = 0.0;
+  if (L.pass == 1 && L.n < P.ev_max && L.phase == PH_PEEL_NEXT) {
+    L.Ge = M.ev_load(L.slot, L.n, 0);
+    L.det = P.n_det;  // no peel-off walks: PEEL_NEXT goes straight on
+  }
+}
+
+template <typename R, class Mem>
+MCRT_HD void event_done(Lane<R>& L, const RunParams& P, Mem& M) {
+  if (L.pass == 0 && L.n < P.ev_max) M.ev_store(L.slot, L.n, 0, L.Ge);
+  L.Gacc += L.Ge;
+  L.Ge = 0.0;
 }
 
 // Runs the lane's events until its next walk is set up (ry.active) or no
@@ -158,13 +206,20 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
         ++L.det;
       } else {
         const double ac = M.adj(ii) * C;
-        L.Gacc += ac;
+        L.Ge += ac;
         if (L.pass == 0) L.Gabs += fabs(ac);
-        if (L.pass == 1 && ac != 0.0) {  // a second walk of the same ray deposits -A C kappa l
+        if (L.pass == 0 && ac != 0.0) {  // a second walk of the same ray deposits -A C kappa l
           L.fac = -ac * L.kap;
-          want = to_det = true;
-          L.mode = M_PEEL_DEP;
-          L.phase = PH_PEEL_DEP_END;
+          unsigned long long slot = ~0ull;
+          if (P.jobs) slot = M.job_slot();
+          if (slot < P.job_cap) {  // queued: walked later, bundled with parallel neighbours
+            M.store_job(slot, L.r, L.fac, tile_key(D, L.pix));
+            ++L.det;
+          } else {
+            want = to_det = true;
+            L.mode = M_PEEL_DEP;
+            L.phase = PH_PEEL_DEP_END;
+          }
         } else {
           ++L.det;
         }
@@ -177,7 +232,13 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
 
     // -- end of the pass-1 walk: escape and absorption, forced-scattering depth
     if (L.phase == PH_PATH_END) {
-      L.T = (double)L.ry.tau;
+      if (ADJ && L.t_kept) {
+        L.T = M.ev_load(L.slot, L.n, 1);
+        L.t_kept = false;
+      } else {
+        L.T = (double)L.ry.tau;
+        if (ADJ && L.pass == 0 && L.n < P.ev_max) M.ev_store(L.slot, L.n, 1, L.T);
+      }
       if (L.T == 0.0) {  // nothing to interact with: the package leaves
         if (L.pass == 0) L.s_esc += L.W;
         L.phase = PH_PKG_END;
@@ -226,6 +287,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
       L.is_emit = false;
       L.det = 0;
       L.phase = (P.flags & kFlagPeelScat) ? PH_PEEL_NEXT : PH_TERM;
+      if (ADJ) event_start(L, P, M);
     }
 
     // -- the next frame whose pixel the event projects into
@@ -240,6 +302,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
         L.mode = M_PEEL;
         L.phase = PH_PEEL_END;
       } else {
+        if (ADJ) event_done(L, P, M);
         L.phase = L.is_emit ? PH_PATH_START : PH_TERM;
       }
     }
@@ -257,12 +320,16 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
 
     // -- the pass-1 walk along the package direction
     if (L.phase == PH_PATH_START && !want) {
-      want = true;
-      L.mode = M_PATH;
       L.absf = R(0);
       L.trans = R(1);
       L.wabs = L.W * (1.0 - L.alb);
       L.phase = PH_PATH_END;
+      if (ADJ && L.pass == 1 && L.n < P.ev_max) {
+        L.t_kept = true;  // T of this leg is in the scratch: no walk
+        continue;
+      }
+      want = true;
+      L.mode = M_PATH;
     }
 
     // -- end of the package: replay it for the adjoint, or take the next one
@@ -319,6 +386,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
       L.is_emit = true;
       L.det = 0;
       L.phase = (P.flags & kFlagPeelEmit) ? PH_PEEL_NEXT : PH_PATH_START;
+      if (ADJ) event_start(L, P, M);
     }
 
     // -- set up the chosen walk (a walk that misses the grid ends at once and
@@ -402,6 +470,40 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M) {
     if (pos) ry.t = tm;
   }
   if (b.out) ry.active = false;
+}
+
+// ---------------------------------------------------------------------------
+// Queued adjoint deposit rays.  The walk is the one the inline M_PEEL_DEP
+// mode makes (same setup, same blocks, same segments), without density
+// loads: its deposits w * l do not depend on the densities.  Every deposit
+// goes through M.deposit(cell, v).  bp_step advances the ray by one block
+// and returns its positive-length crossings; bp_walk walks a whole job.
+template <typename R, class Mem>
+MCRT_HD unsigned bp_step(Ray<R>& ry, const GridDev& G, double w, Mem& M) {
+  WalkBlock<kBlockWalk, R> b;
+  ray_next_block<kBlockWalk, R, Mem, false>(ry, b, G, M);
+  unsigned n = 0;
+#pragma unroll
+  for (int d = 0; d < kBlockWalk; ++d) {
+    if (d >= b.n) break;
+    const R seg = b.tend[d] - ry.t;
+    if (seg > R(0)) {
+      M.deposit(b.cell[d], w * (double)seg);
+      ++n;
+      ry.t = b.tend[d];
+    }
+  }
+  if (b.out) ry.active = false;
+  return n;
+}
+
+template <typename R, class Mem>
+MCRT_HD unsigned bp_walk(const GridDev& G, const DetDev& D, const BpJob& J, Mem& M) {
+  Ray<R> ry;
+  ray_begin(ry, G, J.r, D.kd);
+  unsigned n = 0;
+  while (ry.active) n += bp_step<R>(ry, G, J.w, M);
+  return n;
 }
 
 // ---------------------------------------------------------------------------

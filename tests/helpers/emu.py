@@ -48,6 +48,8 @@ class Emu:
                                      C.POINTER(B.Detector), P, C.c_int, C.c_int]
         for f in ("emu_run_photons", "emu_backward_density", "emu_trace_path", "emu_peel_off"):
             getattr(lib, f).restype = C.c_int
+        lib.emu_set_events_kept.argtypes = [C.c_int]
+        lib.emu_set_events_kept.restype = None
         lib.emu_violation.restype = C.c_char_p
         lib.emu_last_error.restype = C.c_char_p
         self.lib = lib
@@ -78,6 +80,11 @@ class Emu:
                                              images.size, self._p(absorbed), 0 if absorbed is None else absorbed.size,
                                              C.byref(st), wave))
         return images, absorbed, st.as_dict()
+
+    def set_events_kept(self, n):
+        """Events per package the adjoint keeps in its event scratch (the
+        library keeps 32); later events are walked again in pass B."""
+        self.lib.emu_set_events_kept(int(n))
 
     def grad(self, prob, adj, wave=WAVE, **overrides):
         pr = B._Problem(prob, **overrides)

@@ -24,6 +24,7 @@ using namespace mcrt;
 namespace {
 
 thread_local std::string g_violation;
+int g_events_kept = 32;  // adjoint event scratch per package, as the library keeps
 
 struct Violation : std::runtime_error {
   using std::runtime_error::runtime_error;
@@ -113,6 +114,40 @@ struct HostLifeMem {
     grad[i] += v;
   }
   unsigned long long fetch() { return next++; }
+  // adjoint deposit queue
+  std::vector<BpJob>* jobs = nullptr;
+  unsigned long long job_cap = 0, job_next = 0;
+  long long n_keys = 0;
+  unsigned long long job_slot() { return job_next++; }
+  // adjoint event scratch [ev_max][2][n_slots]
+  std::vector<double>* evs = nullptr;
+  int ev_max = 0, n_slots = 0;
+  std::vector<unsigned char>* ev_set = nullptr;
+  double ev_load(int slot, int e, int k) const {
+    EMU_CHECK(slot >= 0 && slot < n_slots, "event scratch lane", slot, n_slots);
+    EMU_CHECK(e >= 0 && e < ev_max && k >= 0 && k < 2, "event scratch entry", e, ev_max);
+    const size_t i = ((size_t)2 * e + k) * n_slots + slot;
+    EMU_CHECK((*ev_set)[i], "event scratch read before write", e, ev_max);
+    return (*evs)[i];
+  }
+  void ev_store(int slot, int e, int k, double v) {
+    EMU_CHECK(slot >= 0 && slot < n_slots, "event scratch lane", slot, n_slots);
+    EMU_CHECK(e >= 0 && e < ev_max && k >= 0 && k < 2, "event scratch entry", e, ev_max);
+    const size_t i = ((size_t)2 * e + k) * n_slots + slot;
+    (*evs)[i] = v;
+    (*ev_set)[i] = 1;
+  }
+  void store_job(unsigned long long slot, const double r[3], double w, unsigned key) {
+    EMU_CHECK(jobs != nullptr && slot < job_cap, "deposit queue", slot, job_cap);
+    EMU_CHECK(key < (unsigned long long)n_keys, "tile key", key, n_keys);
+    BpJob& J = (*jobs)[slot];
+    J.r[0] = r[0];
+    J.r[1] = r[1];
+    J.r[2] = r[2];
+    J.w = w;
+    J.key = key;
+    J.rank = 0;
+  }
   void flush_counts(unsigned a, unsigned b, unsigned c, unsigned d) {
     xs[0] += a;
     xs[1] += b;
@@ -151,6 +186,42 @@ void run_wave(std::vector<LaneT>& lanes, int batch, Events events, Step step, lo
   }
 }
 
+// Deposits of the bundled walk, straight into the bricked gradient.
+struct HostBundleMem {
+  const GridDev& G;
+  std::vector<double>& grad;
+  void deposit(int cell, double v) {
+    check_cell(G, cell, "bundle deposit");
+    grad[cell] += v;
+  }
+};
+
+// The library's counting sort of the queue by tile key (count with ranks,
+// exclusive scan, permutation), then the bundled walks key by key.
+template <typename R>
+unsigned long long emu_bundles(const GridDev& G, const std::vector<DetDev>& det, int n_det, long long n_keys,
+                               std::vector<BpJob>& jobs, unsigned long long n_jobs, std::vector<double>& grad) {
+  std::vector<unsigned> kcount(n_keys, 0), kstart(n_keys + 1, 0), perm(n_jobs, 0);
+  for (unsigned long long j = 0; j < n_jobs; ++j) {
+    EMU_CHECK(jobs[j].key < (unsigned long long)n_keys, "tile key", jobs[j].key, n_keys);
+    jobs[j].rank = kcount[jobs[j].key]++;
+  }
+  for (long long k = 0; k < n_keys; ++k) kstart[k + 1] = kstart[k] + kcount[k];
+  for (unsigned long long j = 0; j < n_jobs; ++j) {
+    const unsigned long long q = (unsigned long long)kstart[jobs[j].key] + jobs[j].rank;
+    EMU_CHECK(q < n_jobs, "sorted queue", q, n_jobs);
+    perm[q] = (unsigned)j;
+  }
+  HostBundleMem M{G, grad};
+  unsigned long long nx = 0;
+  for (long long key = 0; key < n_keys; ++key) {
+    int d = 0;
+    while (d + 1 < n_det && (long long)det[d + 1].key_off <= key) ++d;
+    for (unsigned q = kstart[key]; q < kstart[key + 1]; ++q) nx += bp_walk<R>(G, det[d], jobs[perm[q]], M);
+  }
+  return nx;
+}
+
 template <typename R, bool ADJ>
 int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, int n_src, const mcrt_source* sources,
              int n_det, const mcrt_detector* detectors, const mcrt_opts* opts, double* images, long long n_images,
@@ -174,12 +245,46 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
                    (long long)abs_b.size(), adj, n_adj, grad_b.data(), (long long)grad_b.size()};
   P.absorbed = M.absorbed;
   if (images && !ADJ) std::fill(images, images + n_images, 0.0);
+  std::vector<BpJob> jobs;
+  const bool peel = (opts->flags & (MCRT_PEEL_EMIT | MCRT_PEEL_SCAT)) && n_det > 0;
+  if (ADJ && peel && opts->deposit_queue != -1) {
+    unsigned long long cap = opts->deposit_queue > 0 ? (unsigned long long)opts->deposit_queue
+                                                     : P.n_items * (unsigned long long)P.n_det * 8ull;
+    if (opts->deposit_queue == 0) cap = std::min(std::max(cap, 1ull << 16), 1ull << 28);
+    jobs.resize(cap);
+    M.jobs = &jobs;
+    M.job_cap = cap;
+    M.n_keys = pr.n_keys;
+    P.jobs = jobs.data();
+    P.job_cap = cap;
+  }
+  std::vector<double> evs;
+  std::vector<unsigned char> ev_set;
+  if (ADJ) {
+    P.ev_max = g_events_kept;
+    P.n_slots = (unsigned long long)wave;
+    evs.assign((size_t)2 * P.ev_max * wave, 0.0);
+    ev_set.assign(evs.size(), 0);
+    M.evs = &evs;
+    M.ev_set = &ev_set;
+    M.ev_max = P.ev_max;
+    M.n_slots = wave;
+  }
   std::vector<Lane<R>> lanes(wave);
-  for (auto& L : lanes) lane_init(L);
+  for (int i = 0; i < wave; ++i) {
+    lane_init(lanes[i]);
+    lanes[i].slot = i;
+  }
   const long long cap = (long long)P.G.n[0] + P.G.n[1] + P.G.n[2] + 8;
   run_wave(
       lanes, P.batch, [&](Lane<R>& L) { lane_events<R, ADJ>(L, P, M); },
       [&](Lane<R>& L) { lane_step<R, ADJ>(L, P, M); }, cap, 0);
+  if (P.jobs) {
+    const unsigned long long nx =
+        emu_bundles<R>(P.G, pr.det, P.n_det, pr.n_keys, jobs, std::min(M.job_next, M.job_cap), grad_b);
+    M.xs[2] += nx;
+    M.xs[6] += nx;
+  }
   if (P.absorbed) unbrick(P.G, abs_b, absorbed, P.n_lambda);
   if (ADJ && grad) unbrick(P.G, grad_b, grad, 1);
   if (stats) {
@@ -365,6 +470,7 @@ int guard(const char* what, int (*f)(void*), void* arg) {
 extern "C" {
 
 const char* emu_violation(void) { return g_violation.c_str(); }
+void emu_set_events_kept(int n) { g_events_kept = n; }
 const char* emu_last_error(void) { return host::last_error().c_str(); }
 
 int emu_run_photons(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, int n_src,

@@ -244,3 +244,51 @@ def test_brick_shape_rejected(E, W):
     for bad in (brick(8, 0, 0), brick(4, 4, 3), 0x2000, 5):
         with pytest.raises(McrtError):
             E.run(prob, brick_shape=bad)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_backward_deposit_queue_modes(E, orc, W, prec):
+    """Peel-ray deposits walked inline, all queued and bundled by tile, or
+    queued until a tiny queue is full: same gradient and crossing counts."""
+    n = (12, 10, 9)
+    prob = W.small_problem(n=n, box=(-1.0, 1.2, -1.0, 1.0, -0.9, 0.9),
+                           rho=W.lognormal_density(n, 0.8, seed=41, f32=(prec == 1)), kappa=1.1, albedo=0.65, g=0.4,
+                           detectors=[W.frame(10.0, 0.0, 20, 20, 1.2, 1.2), W.frame(10.0, 90.0, 24, 16, 1.3, 1.0),
+                                      W.frame(10.0, 55.0, 18, 18, 1.3, 1.3, azim=30.0, pa=15.0)],
+                           n_packages=900, flags=W.FLAG_PEEL_EMIT | W.FLAG_PEEL_SCAT, precision=prec)
+    img_o, _, _ = orc.run(prob)
+    adj = np.random.default_rng(8).standard_normal(img_o.shape)
+    g_o, _, _ = orc.grad(prob, adj)
+    ref = None
+    for q in (-1, 0, 7, 100000):
+        g, st = E.grad(prob, adj, deposit_queue=q)
+        assert rel_l1(g, g_o) < (1e-9 if prec == 0 else 1e-5), (q, rel_l1(g, g_o))
+        if ref is None:
+            ref = (g, st)
+            continue
+        assert rel_l1(g, ref[0]) < 1e-12
+        for key in ("x_path", "x_locate", "x_peel", "deposits", "events", "peels"):
+            assert st[key] == ref[1][key], (q, key)
+
+
+@pytest.mark.parametrize("kept", [0, 1, 3, 32])
+def test_backward_event_scratch_sizes(E, orc, W, kept):
+    """Pass B reads G_e and T of the first `kept` events from the scratch and
+    walks the rest again: the gradient does not depend on how many are kept,
+    and no scratch entry is read before pass A wrote it."""
+    n = (9, 8, 7)
+    prob = W.small_problem(n=n, rho=W.lognormal_density(n, 0.9, seed=43), kappa=1.4, albedo=0.8, g=0.3,
+                           detectors=[W.frame(10.0, 20.0, 16, 16, 1.1, 1.1), W.frame(10.0, 75.0, 12, 20, 1.2, 1.2)],
+                           n_packages=700, flags=W.FLAG_PEEL_EMIT | W.FLAG_PEEL_SCAT, w_min=1e-5, max_scatter=40)
+    img_o, _, _ = orc.run(prob)
+    adj = np.random.default_rng(3).standard_normal(img_o.shape)
+    g_o, _, _ = orc.grad(prob, adj)
+    try:
+        E.set_events_kept(kept)
+        g, st = E.grad(prob, adj)
+        g1, _ = E.grad(dict(prob, flags=W.FLAG_PEEL_SCAT), adj)  # no peel-off at emission
+    finally:
+        E.set_events_kept(32)
+    g1_o, _, _ = orc.grad(dict(prob, flags=W.FLAG_PEEL_SCAT), adj)
+    assert rel_l1(g, g_o) < 1e-9, rel_l1(g, g_o)
+    assert rel_l1(g1, g1_o) < 1e-9, rel_l1(g1, g1_o)

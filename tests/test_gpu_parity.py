@@ -253,6 +253,49 @@ def test_backward_matches_oracle(B, orc, W, prec):
     assert st["packages"] == st_o["packages"]
 
 
+def test_backward_deposit_queue_modes(B, orc, W):
+    # peel-ray deposits walked inline, queued and bundled, or queued until a
+    # tiny queue is full: the same gradient and the same crossing counts
+    import torch
+    _say("backward deposit queue modes")
+    prob = _adj_problem(W, 0)
+    img_o, _, _ = orc.run(prob)
+    adj = np.random.default_rng(12).standard_normal(img_o.shape)
+    g_o, _, _ = orc.grad(prob, adj)
+    rho = B.density_tensor(prob)
+    ref = None
+    for q in (-1, 0, 100, 5000):
+        grad = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
+        st = B.backward_density(prob, rho, _dev(adj), grad, deposit_queue=q)
+        g = grad.cpu().numpy()
+        e = rel_l1(g, g_o)
+        _say("  queue %d: rel_L1 grad %.3e" % (q, e))
+        assert e < 1e-9, (q, e)
+        if ref is None:
+            ref = st
+        for key in ("x_path", "x_locate", "x_peel", "deposits", "events", "peels", "packages"):
+            assert st[key] == ref[key], (q, key, st[key], ref[key])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_backward_spiral_full_grid_subset(B, orc, W, prec):
+    # the spiral's grid and three 512x512 frames, a package subset from deep
+    # inside the run, random image adjoint
+    import torch
+    _say("backward spiral subset prec=%d" % prec)
+    prob = W.spiral(n_packages=1500, precision=prec)
+    prob["first_package"] = 3_141_592
+    img_o, _, _ = orc.run(prob)
+    adj = np.random.default_rng(13).standard_normal(img_o.shape) * 1e9
+    g_o, _, _ = orc.grad(prob, adj)
+    rho = B.density_tensor(prob)
+    grad = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
+    B.backward_density(prob, rho, _dev(adj), grad)
+    e = rel_l1(grad.cpu().numpy(), g_o)
+    _say("  rel_L1 grad %.3e" % e)
+    assert e < (1e-9 if prec == 0 else 1e-5), e
+
+
 # ------------------------------------------------------------------ autograd
 
 def test_autograd_function_matches_oracle_gradient(B, orc, W):
