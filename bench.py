@@ -12,15 +12,24 @@ against a fixed target image (rendered once, before timing, from a
 perturbed density).  Inputs are resident on the device before timing.
 
 Prints one JSON line.  `value` is packages per second of whole steps;
-`roofline` describes the kernel with the longer average duration, from HIP
-events around its launches on the stream it runs on; `cpu_baseline` times
-the FP64 CPU oracle on a bounded package sample of the same workload.
+`roofline` describes the kernel with the longer average duration (HIP
+events around it on the stream it runs on, recorded by the library);
+`traversal` is the walk alone (trace_path on random rays in the same grid);
+`fp64_path` times one step of the plain FP64 GPU path and compares the two
+precisions against the Monte Carlo noise; `cpu_baseline` times the FP64 CPU
+oracle on a bounded package sample of the same workload.
+
+`--collect-profiles DIR` runs this script under rocprofv3 (a kernel-trace
+summary, then FETCH_SIZE and WRITE_SIZE counter passes with a 1 GiB copy
+for calibration) as child processes and writes the summaries to profiles/.
 """
 import argparse
+import csv
 import glob
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -29,12 +38,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "photon packages/sec (with peel-off) and cell-crossings/s vs HBM/L2 roofline"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes: one density value per cell crossing, one FP64
+# Algorithmic bytes (what the method moves, not what line-granular hardware
+# moves): one density value per cell crossing that reads it, one FP64
 # read-modify-write (8 B read + 8 B written) per tally deposit and per
-# peel-off contribution landing in a frame.
+# forward peel-off contribution into a frame, one FP64 read of dL/dI per
+# adjoint peel-off contribution; a traversal ray reads its origin and
+# direction (48 B) and writes its optical depth (8 B).
 BYTES_PER_CROSSING = {0: 8, 1: 4}
 BYTES_PER_DEPOSIT = 16
-BYTES_PER_PEEL = 16
+BYTES_PER_PEEL_FORWARD = 16
+BYTES_PER_PEEL_ADJOINT = 8
+BYTES_PER_RAY = 56
+COPY_BYTES = 1 << 30
+# kernel names as rocprofv3 prints them -> keys of profiles/traffic.json
+KERNELS = {
+    "forward": "void mcrt::k_life<float, false>(mcrt::RunParams)",
+    "adjoint": "void mcrt::k_life<float, true>(mcrt::RunParams)",
+    "bundle": "void mcrt::k_bundle<float>(mcrt::BundleParams)",
+    "trace": "void mcrt::k_trace<float>(mcrt::TraceParams)",
+}
 
 
 def source_hash():
@@ -45,9 +67,9 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel, launches_bytes):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
+def traffic_for(key):
+    """Hardware HBM bytes per launch of a kernel from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -56,15 +78,23 @@ def traffic_for(kernel, launches_bytes):
             rec = json.load(f)
     except ValueError:
         return None
-    k = rec.get("kernels", {}).get(kernel)
+    k = rec.get("kernels", {}).get(key)
     if not k or rec.get("source_hash") != source_hash():
         return None
     return k.get("hbm_bytes_per_launch")
 
 
-def algorithmic_bytes(st, prec):
-    x = st["x_path"] + st["x_locate"] + st["x_peel"]
-    return x * BYTES_PER_CROSSING[prec] + st["deposits"] * BYTES_PER_DEPOSIT + st["peels"] * BYTES_PER_PEEL
+def life_bytes(st, prec, adjoint):
+    """Algorithmic bytes of the life-cycle kernel of one call (the bundled
+    deposit walks of the adjoint run in their own kernel and are excluded)."""
+    x = st["x_path"] + st["x_locate"] + st["x_peel"] - st["x_queue"]
+    peel = BYTES_PER_PEEL_ADJOINT if adjoint else BYTES_PER_PEEL_FORWARD
+    return x * BYTES_PER_CROSSING[prec] + (st["deposits"] - st["x_queue"]) * BYTES_PER_DEPOSIT + st["peels"] * peel
+
+
+def rel_l1(a, b):
+    den = b.abs().sum().item()
+    return (a - b).abs().sum().item() / den if den > 0 else float("nan")
 
 
 def cpu_baseline(prob, seconds):
@@ -96,6 +126,148 @@ def cpu_baseline(prob, seconds):
             "sample": "first %d packages of the same workload, FP64 forward run + gradient, %.1f s" % (n, t)}
 
 
+def traversal(B, prob, n_rays, dev):
+    """trace_path over random rays in the workload's grid: origins uniform in
+    the box, isotropic directions, optical depth only."""
+    import torch
+    g = torch.Generator(device=dev)
+    g.manual_seed(11)
+    box = prob["box"]
+    lo = torch.tensor([box[0], box[2], box[4]], dtype=torch.float64, device=dev)
+    hi = torch.tensor([box[1], box[3], box[5]], dtype=torch.float64, device=dev)
+    o = lo + (hi - lo) * torch.rand((n_rays, 3), generator=g, dtype=torch.float64, device=dev)
+    k = torch.randn((n_rays, 3), generator=g, dtype=torch.float64, device=dev)
+    k /= k.norm(dim=1, keepdim=True)
+    rho = B.density_tensor(prob, dev)
+    tau = torch.empty(n_rays, dtype=torch.float64, device=dev)
+    x = B.trace_path(prob, rho, 1.0, prob["precision"], o, k, tau)
+    reps = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        B.trace_path(prob, rho, 1.0, prob["precision"], o, k, tau, crossings=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    alg = x * BYTES_PER_CROSSING[prob["precision"]] + n_rays * BYTES_PER_RAY
+    achieved = alg / (ms / 1e3) / 1e9
+    hw = traffic_for("trace")
+    out = {"kernel": KERNELS["trace"], "rays": n_rays, "ms": ms, "crossings": x,
+           "crossings_per_s": x / (ms / 1e3), "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": hw,
+           "note": "ms covers the call (bricking the densities plus the walk kernel)"}
+    if hw:
+        out["hardware_gbs"] = hw / (ms / 1e3) / 1e9
+        out["hardware_frac"] = out["hardware_gbs"] / HBM_PEAK_GBS
+    return out
+
+
+def fp64_comparison(B, prob, step_fn, images32, grad32, dev):
+    """One step of the plain FP64 GPU path on the same packages; its
+    difference from the FP32 path next to the Monte Carlo noise of the
+    images (half the relative L1 difference of the two halves of the
+    package range, about the noise of the full run)."""
+    import torch
+    p64 = dict(prob, precision=0)
+    rho64 = B.density_tensor(p64, dev)
+    images = torch.empty_like(images32)
+    grad = torch.empty_like(grad32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sf, sb = step_fn(p64, rho64, images, grad)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    half = prob["n_packages"] // 2
+    ia = torch.empty_like(images32)
+    ib = torch.empty_like(images32)
+    rho32 = B.density_tensor(prob, dev)
+    B.run_photons(dict(prob, n_packages=half), rho32, ia, None, flags=prob["flags"] & ~B.ABSORB)
+    B.run_photons(dict(prob, n_packages=prob["n_packages"] - half, first_package=half), rho32, ib, None,
+                  flags=prob["flags"] & ~B.ABSORB)
+    return {"packages_per_s": prob["n_packages"] / wall, "ms_per_step": wall * 1e3,
+            "forward_ms": sf["kernel_ms"], "adjoint_ms": sb["kernel_ms"],
+            "images_rel_l1_fp32_vs_fp64": rel_l1(images32, images),
+            "gradient_rel_l1_fp32_vs_fp64": rel_l1(grad32, grad),
+            "images_mc_noise_rel_l1": 0.5 * rel_l1(ia, ib)}
+
+
+def collect_profiles(out_dir, prof):
+    """Runs this script under rocprofv3 as child processes (this process
+    never touches the GPU) and writes the summaries to `prof` (profiles/)."""
+    os.makedirs(out_dir, exist_ok=True)
+    me = os.path.abspath(__file__)
+    child = [sys.executable, me, "--steps", "2", "--warmup", "1", "--no-cpu-baseline", "--no-fp64"]
+    runs = {
+        "trace": ["rocprofv3", "--kernel-trace", "--stats", "--output-format", "csv"],
+        "fetch": ["rocprofv3", "--kernel-trace", "--output-format", "csv", "--pmc", "FETCH_SIZE"],
+        "write": ["rocprofv3", "--kernel-trace", "--output-format", "csv", "--pmc", "WRITE_SIZE"],
+    }
+    for name, cmd in runs.items():
+        extra = ["--calibrate-copy"] if name != "trace" else []
+        full = cmd + ["-d", os.path.join(out_dir, name), "-o", name, "--"] + child + extra
+        print("[profile] " + " ".join(full), flush=True)
+        r = subprocess.run(["timeout", "-k", "10", "300"] + full)
+        if r.returncode != 0:
+            print("[profile] %s pass failed with status %d" % (name, r.returncode), flush=True)
+            sys.exit(r.returncode)
+
+    def dispatches(name):
+        f = glob.glob(os.path.join(out_dir, name, "**", "*counter_collection.csv"), recursive=True)[0]
+        agg = {}
+        for r in csv.DictReader(open(f)):
+            key = int(r["Dispatch_Id"])
+            a = agg.setdefault(key, {"kernel": r["Kernel_Name"], "value": 0.0})
+            a["value"] += float(r["Counter_Value"])
+        return [agg[k] for k in sorted(agg)]
+
+    factors = {}
+    per_kernel = {}
+    for name, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        ds = dispatches(name)
+        copy = ds[0]  # the calibration copy is the first kernel of the child process
+        # the copy reads and writes COPY_BYTES once; counters are in KiB
+        factors[counter] = COPY_BYTES / (copy["value"] * 1024.0)
+        for key, kname in KERNELS.items():
+            vals = [d["value"] for d in ds if d["kernel"] == kname]
+            if vals:
+                per_kernel.setdefault(key, {})[counter + "_kib_per_dispatch"] = sum(vals) / len(vals)
+    kernels = {}
+    for key, v in per_kernel.items():
+        if "FETCH_SIZE_kib_per_dispatch" in v and "WRITE_SIZE_kib_per_dispatch" in v:
+            b = 1024.0 * (v["FETCH_SIZE_kib_per_dispatch"] * factors["FETCH_SIZE"] +
+                          v["WRITE_SIZE_kib_per_dispatch"] * factors["WRITE_SIZE"])
+            kernels[key] = dict(v, hbm_bytes_per_launch=b)
+    stats_f = glob.glob(os.path.join(out_dir, "trace", "**", "*kernel_stats.csv"), recursive=True)[0]
+    stats = list(csv.DictReader(open(stats_f)))
+    os.makedirs(prof, exist_ok=True)
+    with open(os.path.join(prof, "traffic.json"), "w") as f:
+        json.dump({"source_hash": source_hash(), "workload": "edge_on_spiral_256x256x64, 1e7 packages, FP32",
+                   "copy_calibration_bytes": COPY_BYTES, "factors": factors, "kernels": kernels,
+                   "command": "python bench.py --collect-profiles " + out_dir}, f, indent=1)
+    with open(os.path.join(prof, "life_kernels_spiral_1e7_fp32.md"), "w") as f:
+        f.write("# Kernel trace and HBM counters: edge-on spiral, 1e7 packages, FP32 path\n\n")
+        f.write("Command (writes this file and traffic.json): `python bench.py --collect-profiles %s`\n\n" % out_dir)
+        f.write("Each pass runs `python bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-fp64` under "
+                "rocprofv3: `--kernel-trace --stats`, then `--pmc FETCH_SIZE` and `--pmc WRITE_SIZE` (the "
+                "counter passes add `--calibrate-copy`: a 1 GiB device copy first, whose counter values give "
+                "the scale factors below).\n\n")
+        f.write("## Kernel durations (rocprofv3 --stats)\n\n| kernel | calls | average ms | total ms |\n|---|---|---|---|\n")
+        for r in stats:
+            n = r.get("Name") or r.get("KernelName") or ""
+            if "mcrt" not in n:
+                continue
+            f.write("| `%s` | %s | %.3f | %.3f |\n" % (n, r["Calls"], float(r["AverageNs"]) / 1e6,
+                                                      float(r["TotalDurationNs"]) / 1e6))
+        f.write("\n## HBM traffic per dispatch (counter KiB x calibration factor)\n\n")
+        f.write("Factors: FETCH_SIZE x %.3f, WRITE_SIZE x %.3f (1 GiB copy).\n\n" % (factors["FETCH_SIZE"],
+                                                                                   factors["WRITE_SIZE"]))
+        f.write("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes per launch |\n|---|---|---|---|\n")
+        for key, v in kernels.items():
+            f.write("| `%s` | %.0f | %.0f | %.4g |\n" % (KERNELS[key], v["FETCH_SIZE_kib_per_dispatch"],
+                                                       v["WRITE_SIZE_kib_per_dispatch"], v["hbm_bytes_per_launch"]))
+    print("[profile] wrote %s/traffic.json and life_kernels_spiral_1e7_fp32.md" % prof, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,11 +276,18 @@ def main():
     ap.add_argument("--packages", type=int, default=10_000_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
+    ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy first (counter scale)")
+    ap.add_argument("--collect-profiles", metavar="DIR", help="run the rocprofv3 passes (raw output in DIR)")
+    ap.add_argument("--profiles-dir", default=os.path.join(ROOT, "profiles"), help="where the summaries go")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.collect_profiles:
+        collect_profiles(args.collect_profiles, args.profiles_dir)
+        return
 
     import numpy as np
     import torch
@@ -119,6 +298,12 @@ def main():
     B.load()
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.add(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
     prob = W.spiral(n_packages=args.packages, precision=1)
     prec = prob["precision"]
     rho = B.density_tensor(prob, dev)
@@ -135,20 +320,20 @@ def main():
     B.run_photons(dict(prob, seed=4358), rho_t, target, absorbed)
     del rho_t
 
-    def step():
-        sf = B.run_photons(prob, rho, images, absorbed)
-        torch.sub(images, target, out=adj)
+    def step_fn(p, r, img, g):
+        sf = B.run_photons(p, r, img, absorbed)
+        torch.sub(img, target, out=adj)
         adj.mul_(2.0)
-        sb = B.backward_density(prob, rho, adj, grad)
+        sb = B.backward_density(p, r, adj, g)
         return sf, sb
 
     for _ in range(args.warmup):
-        step()
+        step_fn(prob, rho, images, grad)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fw, bw = [], []
     for _ in range(args.steps):
-        sf, sb = step()
+        sf, sb = step_fn(prob, rho, images, grad)
         fw.append(sf)
         bw.append(sb)
     torch.cuda.synchronize()
@@ -157,21 +342,26 @@ def main():
     ms_step = 1e3 * wall / args.steps
     n_pkg = prob["n_packages"]
 
-    def summary(sts):
+    def summary(sts, adjoint):
         ms = float(np.mean([s["kernel_ms"] for s in sts]))
+        life_ms = float(np.mean([s["life_ms"] for s in sts]))
         s0 = sts[-1]
         x = s0["x_path"] + s0["x_locate"] + s0["x_peel"]
-        return {"kernel_ms": ms, "packages_per_s": n_pkg / (ms / 1e3), "crossings": x,
-                "crossings_per_s": x / (ms / 1e3), "x_path": s0["x_path"], "x_locate": s0["x_locate"],
-                "x_peel": s0["x_peel"], "events": s0["events"], "peels": s0["peels"], "deposits": s0["deposits"],
-                "algorithmic_bytes": algorithmic_bytes(s0, prec)}
+        out = {"kernel_ms": ms, "life_ms": life_ms, "packages_per_s": n_pkg / (ms / 1e3), "crossings": x,
+               "crossings_per_s": x / (ms / 1e3)}
+        for k in ("x_path", "x_locate", "x_peel", "x_queue", "events", "peels", "deposits"):
+            out[k] = s0[k]
+        out["life_algorithmic_bytes"] = life_bytes(s0, prec, adjoint)
+        if adjoint:
+            out["queue_ms"] = float(np.mean([s["queue_ms"] for s in sts]))
+        return out
 
-    fsum, bsum = summary(fw), summary(bw)
-    kname = {True: "k_life<float, true> (adjoint)", False: "k_life<float, false> (forward)"}
-    dominant_adj = bsum["kernel_ms"] > fsum["kernel_ms"]
+    fsum, bsum = summary(fw, False), summary(bw, True)
+    dominant_adj = bsum["life_ms"] > fsum["life_ms"]
     dom = bsum if dominant_adj else fsum
-    achieved = dom["algorithmic_bytes"] / (dom["kernel_ms"] / 1e3) / 1e9
-    traffic = traffic_for("adjoint" if dominant_adj else "forward", None)
+    achieved = dom["life_algorithmic_bytes"] / (dom["life_ms"] / 1e3) / 1e9
+    key = "adjoint" if dominant_adj else "forward"
+    traffic = traffic_for(key)
     st_f = fw[-1]
     closure = (st_f["absorbed"] + st_f["escaped"] + st_f["truncated"] - st_f["emitted"]) / st_f["emitted"]
     out = {
@@ -197,9 +387,14 @@ def main():
         "forward": fsum,
         "adjoint": bsum,
         "energy_closure": closure,
-        "roofline": {"kernel": kname[dominant_adj], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": KERNELS[key], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
     }
+    if traffic:
+        out["roofline"]["hardware_frac"] = traffic / (dom["life_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
+    out["traversal"] = traversal(B, prob, 4_000_000, dev)
+    if not args.no_fp64:
+        out["fp64_path"] = fp64_comparison(B, prob, step_fn, images, grad, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
