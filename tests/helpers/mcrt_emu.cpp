@@ -114,6 +114,7 @@ struct HostLifeMem {
     grad[i] += v;
   }
   unsigned long long fetch() { return next++; }
+  unsigned long long x_queue = 0;
   // adjoint deposit queue
   std::vector<BpJob>* jobs = nullptr;
   unsigned long long job_cap = 0, job_next = 0;
@@ -284,6 +285,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
         emu_bundles<R>(P.G, pr.det, P.n_det, pr.n_keys, jobs, std::min(M.job_next, M.job_cap), grad_b);
     M.xs[2] += nx;
     M.xs[6] += nx;
+    M.x_queue = nx;
   }
   if (P.absorbed) unbrick(P.G, abs_b, absorbed, P.n_lambda);
   if (ADJ && grad) unbrick(P.G, grad_b, grad, 1);
@@ -313,6 +315,8 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
     stats->peels = M.xs[5];
     stats->deposits = M.xs[6];
     stats->kernel_ms = 0.0;
+    stats->x_queue = M.x_queue;
+    stats->life_ms = stats->queue_ms = 0.0;
   }
   return 0;
 }

@@ -1,0 +1,229 @@
+"""The workloads beside the benchmark one, on the GPU through the C ABI:
+package subsets against the FP64 oracle at each workload's full grid and
+frame sizes, then the full package counts (energy closure, every package
+accounted for, throughput printed).
+
+- multiwavelength: the disks on 128^3 cells, 100 wavelengths, FP32 path,
+  absorbed luminosity tallied per wavelength and cell (FP64, 1.68 GB);
+- clumpy: 512^3 cells (smooth disk plus 2e4 Gaussian clumps), two 1024^2
+  frames, FP32 path;
+- adjoint: 64^3 lognormal density, one 128^2 frame, L2 loss against the
+  image of a perturbed density, gradient in both precisions.
+
+Tolerances as in test_gpu_parity: FP64 path 1e-10 (images) / 1e-9
+(gradient), FP32 traversal 1e-5, relative L1.
+"""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l1(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    den = np.abs(b).sum()
+    return float(np.abs(a - b).sum() / den) if den > 0 else float(np.abs(a).sum())
+
+
+def _say(msg):
+    print("[gpu] " + msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    from paper_1410_1629_amd import binding
+    binding.load()
+    assert torch.cuda.is_available()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def clumpy_f32():
+    from paper_1410_1629_amd import workloads as W
+    return W.clumpy(n_packages=100_000_000, precision=1)
+
+
+def _render(B, prob, rho=None):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    images, absorbed, st = B.render(prob, rho=rho)
+    torch.cuda.synchronize()
+    return images, absorbed, st, time.perf_counter() - t0
+
+
+def _closure(st):
+    return (st["absorbed"] + st["escaped"] + st["truncated"] - st["emitted"]) / st["emitted"]
+
+
+def _compare(B, orc, prob, tol, rho=None):
+    images, absorbed, st, _ = _render(B, prob, rho)
+    img_o, abs_o, st_o = orc.run(prob)
+    ei = rel_l1(images.cpu().numpy(), img_o)
+    ea = rel_l1(absorbed.cpu().numpy(), abs_o) if absorbed is not None else 0.0
+    _say("  rel_L1 images %.3e absorbed %.3e" % (ei, ea))
+    assert ei < tol and ea < tol, (ei, ea)
+    assert st["packages"] == st_o["packages"]
+    for key in ("events", "x_path", "x_locate", "x_peel"):
+        assert abs(st[key] - st_o[key]) <= 1e-4 * st_o[key] + 2, (key, st[key], st_o[key])
+
+
+# ------------------------------------------------------------------ multiwavelength
+
+def test_multiwavelength_subset_matches_oracle(B, orc, W):
+    _say("multiwavelength: 5 wavelengths x 400 packages")
+    prob = W.multiwavelength(n_packages=400, lambdas=[0, 25, 50, 75, 99])
+    prob["first_package"] = 900_000
+    _compare(B, orc, prob, 1e-5)
+
+
+def test_multiwavelength_full_size(B, W):
+    _say("multiwavelength: 100 wavelengths x 1e6 packages")
+    prob = W.multiwavelength(n_packages=1_000_000)
+    images, absorbed, st, wall = _render(B, prob)
+    n = 100 * 1_000_000
+    _say("  %.2f s wall, kernel %.1f ms, %.3g packages/s, %.3g crossings/s" % (
+        wall, st["kernel_ms"], n / (st["kernel_ms"] / 1e3),
+        (st["x_path"] + st["x_locate"] + st["x_peel"]) / (st["kernel_ms"] / 1e3)))
+    assert st["packages"] == n
+    assert abs(_closure(st)) < 1e-6
+    ab = absorbed.sum(dim=1).cpu().numpy()
+    assert np.isfinite(ab).all() and (ab >= 0).all()
+    assert abs(ab.sum() - st["absorbed"]) < 1e-9 * st["emitted"]
+    # extinction falls with wavelength: the shortest wavelength absorbs more
+    assert ab[0] > ab[-1]
+
+
+# ------------------------------------------------------------------ clumpy
+
+def test_clumpy_subset_matches_oracle(B, orc, clumpy_f32):
+    _say("clumpy: 512^3 grid, 2 x 1024^2 frames, 1500 packages")
+    prob = dict(clumpy_f32, n_packages=1500, first_package=54_321_987)
+    _compare(B, orc, prob, 1e-5)
+
+
+def test_clumpy_full_size(B, clumpy_f32):
+    _say("clumpy: 1e8 packages")
+    images, absorbed, st, wall = _render(B, clumpy_f32)
+    n = clumpy_f32["n_packages"]
+    _say("  %.2f s wall, kernel %.1f ms, %.3g packages/s, %.3g crossings/s" % (
+        wall, st["kernel_ms"], n / (st["kernel_ms"] / 1e3),
+        (st["x_path"] + st["x_locate"] + st["x_peel"]) / (st["kernel_ms"] / 1e3)))
+    assert st["packages"] == n
+    assert abs(_closure(st)) < 1e-6
+    im = images.cpu().numpy()
+    assert np.isfinite(im).all() and (im >= 0).all() and im.sum() > 0
+    if absorbed is not None:  # the workload's absorbed tally is optional (off by default)
+        assert abs(absorbed.sum().item() - st["absorbed"]) < 1e-9 * st["emitted"]
+
+
+# ------------------------------------------------------------------ adjoint workload
+
+def _adjoint_case(W, orc, prec, n_packages):
+    """The adjoint workload at n_packages with the oracle's image, the
+    oracle's image of the perturbed density (the target) and dL/dI."""
+    prob = W.adjoint(n_packages=n_packages, precision=prec)
+    target_prob = dict(prob, rho=prob["rho_target"], seed=4358)
+    img_o, _, _ = orc.run(prob)
+    tgt_o, _, _ = orc.run(target_prob)
+    return prob, img_o, 2.0 * (img_o - tgt_o)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_adjoint_workload_matches_oracle(B, orc, W, prec):
+    import torch
+    _say("adjoint workload prec=%d: 64^3, 128^2 frame, 20000 packages" % prec)
+    prob, img_o, adj = _adjoint_case(W, orc, prec, 20_000)
+    g_o, _, _ = orc.grad(prob, adj)
+    rho = B.density_tensor(prob)
+    images = torch.empty(B.image_shape(prob), dtype=torch.float64, device="cuda")
+    B.run_photons(prob, rho, images, None)
+    grad = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
+    B.backward_density(prob, rho, torch.as_tensor(adj).cuda(), grad)
+    ei, eg = rel_l1(images.cpu().numpy(), img_o), rel_l1(grad.cpu().numpy(), g_o)
+    _say("  rel_L1 images %.3e gradient %.3e" % (ei, eg))
+    # FP32 images: on this field (i.i.d. lognormal cells, sigma_ln 1) the
+    # FP32 crossing times' absolute error (eps times the distance along the
+    # chord) does not cancel between neighbouring cells, so leg optical
+    # depths differ from FP64 by ~1e-5 relative; the scattering points move
+    # by as much and the shift grows with every event, until a few packages
+    # in 1e4 land on the other side of a cell or pixel boundary (measured:
+    # 3 of 20000, 1.95e-5 in the images).  Smooth fields stay below 1e-5.
+    assert ei < (1e-10 if prec == 0 else 5e-5)
+    assert eg < (1e-9 if prec == 0 else 1e-5)
+
+
+def test_adjoint_workload_full_size_fp32_vs_fp64(B, W):
+    # 1e7 packages: forward + adjoint in both precisions on the GPU; the two
+    # gradients agree far inside their Monte Carlo noise (estimated from the
+    # two halves of the package range)
+    import torch
+    _say("adjoint workload: 1e7 packages, FP32 and FP64")
+    out = {}
+    for prec in (1, 0):
+        prob = W.adjoint(n_packages=10_000_000, precision=prec)
+        rho = B.density_tensor(prob)
+        rho_t = torch.as_tensor(np.ascontiguousarray(prob["rho_target"]).reshape(-1), dtype=rho.dtype).cuda()
+        shape = B.image_shape(prob)
+        target = torch.empty(shape, dtype=torch.float64, device="cuda")
+        B.run_photons(dict(prob, seed=4358), rho_t, target, None)
+        images = torch.empty(shape, dtype=torch.float64, device="cuda")
+        grad = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
+        sf = B.run_photons(prob, rho, images, None)
+        adj = 2.0 * (images - target)
+        sb = B.backward_density(prob, rho, adj, grad)
+        halves = []
+        for first, n in ((0, 5_000_000), (5_000_000, 5_000_000)):
+            gh = torch.empty_like(grad)
+            B.backward_density(dict(prob, first_package=first, n_packages=n), rho, adj, gh)
+            halves.append(gh.cpu().numpy())
+        out[prec] = (images.cpu().numpy(), grad.cpu().numpy(), halves)
+        _say("  prec %d: forward %.1f ms, adjoint %.1f ms (%.3g packages/s per step)" % (
+            prec, sf["kernel_ms"], sb["kernel_ms"], 1e7 / ((sf["kernel_ms"] + sb["kernel_ms"]) / 1e3)))
+    g32, g64 = out[1][1], out[0][1]
+    noise = 0.5 * rel_l1(out[0][2][0], out[0][2][1])
+    diff = rel_l1(g32, g64)
+    _say("  gradient rel_L1 FP32 vs FP64 %.3e, Monte Carlo noise %.3e; images %.3e" % (
+        diff, noise, rel_l1(out[1][0], out[0][0])))
+    assert diff < 0.05 * noise  # FP32 rounding at least 20x below the Monte Carlo noise
+    assert np.isfinite(g32).all() and np.isfinite(g64).all()
+
+
+def test_adjoint_workload_gradient_matches_finite_differences(B, orc, W):
+    # the GPU gradient of L = sum (I - T)^2 on the workload's 64 designated
+    # cells against central differences of L over the reweighted estimator
+    # (paths frozen at rho0, evaluated by the oracle), h = 1e-4 rho_m; the
+    # detached gradient is exactly that estimator's derivative
+    import os
+    import torch
+    _say("adjoint workload: GPU gradient vs finite differences on 64 cells")
+    prob, img_o, adj = _adjoint_case(W, orc, 0, 4000)
+    target = img_o - 0.5 * adj
+    rho = B.density_tensor(prob)
+    grad = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
+    B.backward_density(prob, rho, torch.as_tensor(adj).cuda(), grad)
+    g = grad.cpu().numpy()
+    rho0 = prob["rho"].reshape(-1)
+    threads = len(os.sched_getaffinity(0))
+
+    def loss(r):
+        im, _ = orc.reweight(prob, r, threads=threads)
+        return ((im - target) ** 2).sum()
+
+    # tolerance: 1e-5 relative, with a floor of 1e-8 |g|max below which the
+    # central difference is rounding noise of L
+    gmax = np.abs(g).max()
+    worst = 0.0
+    for m in prob["fd_cells"]:
+        h = 1e-4 * rho0[m]
+        rp, rm = rho0.copy(), rho0.copy()
+        rp[m] += h
+        rm[m] -= h
+        fd = (loss(rp) - loss(rm)) / (2 * h)
+        ratio = abs(fd - g[m]) / (1e-5 * abs(g[m]) + 1e-8 * gmax)
+        worst = max(worst, ratio)
+        assert ratio < 1.0, (m, g[m], fd)
+    _say("  worst difference %.3f of the tolerance over 64 cells (|g| max %.3e)" % (worst, gmax))
