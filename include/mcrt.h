@@ -144,15 +144,21 @@ typedef struct {
 /* Run statistics (FP64 luminosities summed over wavelengths; crossing
  * counts of positive-length cell segments: pass-1 paths, pass-2 locate
  * walks, peel-off rays; scattering events; packages; peel-off
- * contributions that landed in a frame; FP64 read-modify-write deposits into
- * the per-cell tally: absorbed luminosity forward, gradient in the adjoint).
- * Crossing counts of the adjoint include both of its walks over each
- * package.  kernel_ms: duration of the main kernel on the stream, from HIP
- * events. */
+ * contributions that landed in a frame; deposits into the per-cell tally:
+ * absorbed luminosity forward, gradient in the adjoint).  The adjoint's
+ * counts cover all of its walks: both replays of each package (pass B takes
+ * what pass A kept and walks only its locate legs and the events beyond the
+ * kept ones) and the peel-ray deposit walks; x_queue is the part of x_peel
+ * (and of deposits) walked by the bundled deposit kernel, whose deposits are
+ * summed on chip before they reach the tally.  Durations on the stream from
+ * HIP events: kernel_ms all kernels of the call, life_ms the life-cycle
+ * kernel, queue_ms the sort and bundled walks of the deposit queue. */
 typedef struct {
     double emitted, absorbed, escaped, truncated;
     uint64_t x_path, x_locate, x_peel, events, packages, peels, deposits;
     double kernel_ms;
+    uint64_t x_queue;
+    double life_ms, queue_ms;
 } mcrt_stats;
 
 /* Photon-package life cycle (Sect. 1 techniques, Sect. 2.2 problem data):
@@ -223,7 +229,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 3
+#define MCRT_ABI_VERSION 4
 
 #ifdef __cplusplus
 }

@@ -65,7 +65,8 @@ class Stats(C.Structure):
     _fields_ = [("emitted", C.c_double), ("absorbed", C.c_double), ("escaped", C.c_double),
                 ("truncated", C.c_double), ("x_path", C.c_uint64), ("x_locate", C.c_uint64),
                 ("x_peel", C.c_uint64), ("events", C.c_uint64), ("packages", C.c_uint64),
-                ("peels", C.c_uint64), ("deposits", C.c_uint64), ("kernel_ms", C.c_double)]
+                ("peels", C.c_uint64), ("deposits", C.c_uint64), ("kernel_ms", C.c_double),
+                ("x_queue", C.c_uint64), ("life_ms", C.c_double), ("queue_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -89,8 +89,9 @@ constexpr int kWavesPerBlock = kBlock / 64;
 
 // Counter block of a life-cycle call (u64 words): [0] next work item,
 // [8..10] FP64 luminosity stats, [16..22] crossing and event counts,
-// [24] next deposit-queue slot, [25] next tile key of the bundle walk.
-constexpr int kJobCounter = 24, kKeyCounter = 25;
+// [24] next deposit-queue slot, [25] next chunk of the bundled walk,
+// [26] crossings of the bundled walk.
+constexpr int kJobCounter = 24, kKeyCounter = 25, kQueueCrossings = 26;
 // Deposit-queue slots are reserved per wavefront in chunks (one global
 // atomic per chunk); slots a wavefront reserved but did not fill are marked
 // with kNoKey when it exits, and the sort skips them.
@@ -442,10 +443,7 @@ __global__ void __launch_bounds__(kBundleThreads) k_bundle(const BundleParams P)
     __syncthreads();
   }
   const unsigned long long wsum = wave_sum_u64(nx);
-  if (__lane_id() == 0 && wsum) {
-    atomicAdd(P.ctr + 16 + 2, wsum);  // x_peel
-    atomicAdd(P.ctr + 16 + 6, wsum);  // deposits
-  }
+  if (__lane_id() == 0 && wsum) atomicAdd(P.ctr + kQueueCrossings, wsum);
 }
 
 __global__ void k_zero(double* __restrict__ p, long long n) {
@@ -555,10 +553,11 @@ struct DeviceBlock {
 };
 
 struct EventPair {
-  hipEvent_t a = nullptr, b = nullptr;
+  hipEvent_t a = nullptr, b = nullptr, c = nullptr;
   ~EventPair() {
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
+    if (c) (void)hipEventDestroy(c);
   }
 };
 
@@ -734,6 +733,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   if (stats) {
     HIPCHK(hipEventCreate(&ev.a));
     HIPCHK(hipEventCreate(&ev.b));
+    HIPCHK(hipEventCreate(&ev.c));
     HIPCHK(hipEventRecord(ev.a, st));
   }
   int rc;
@@ -742,33 +742,40 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   else
     rc = f32 ? launch_life<float, false>(P, nblk, st) : launch_life<double, false>(P, nblk, st);
   if (rc) return rc;
+  if (stats) HIPCHK(hipEventRecord(ev.b, st));
   if (P.jobs) {
     rc = f32 ? run_queue<float>(queue, P, ctr, st) : run_queue<double>(queue, P, ctr, st);
     if (rc) return rc;
   }
-  if (stats) HIPCHK(hipEventRecord(ev.b, st));
+  if (stats) HIPCHK(hipEventRecord(ev.c, st));
   if (tally)
     if (int e = unbrick_tally(P.G, tally, user_tally, adjoint ? 1 : nl, st)) return e;
   if (stats) {
     double ds[3];
-    unsigned long long xs[7];
+    unsigned long long xs[7], xq = 0;
     HIPCHK(hipMemcpyAsync(ds, P.dstats, sizeof ds, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(xs, P.xstats, sizeof xs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&xq, ctr + kQueueCrossings, sizeof xq, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, ev.a, ev.b) != hipSuccess) ms = -1.0f;
+    float ms = 0.0f, ms_life = 0.0f, ms_queue = 0.0f;
+    if (hipEventElapsedTime(&ms, ev.a, ev.c) != hipSuccess) ms = -1.0f;
+    if (hipEventElapsedTime(&ms_life, ev.a, ev.b) != hipSuccess) ms_life = -1.0f;
+    if (hipEventElapsedTime(&ms_queue, ev.b, ev.c) != hipSuccess) ms_queue = -1.0f;
     stats->emitted = pr.emitted;
     stats->absorbed = ds[0];
     stats->escaped = ds[1];
     stats->truncated = ds[2];
     stats->x_path = xs[0];
     stats->x_locate = xs[1];
-    stats->x_peel = xs[2];
+    stats->x_peel = xs[2] + xq;
     stats->events = xs[3];
     stats->packages = xs[4];
     stats->peels = xs[5];
-    stats->deposits = xs[6];
+    stats->deposits = xs[6] + xq;
     stats->kernel_ms = ms;
+    stats->x_queue = xq;
+    stats->life_ms = ms_life;
+    stats->queue_ms = ms_queue;
   }
   return 0;
 }
