@@ -97,6 +97,36 @@ constexpr int kJobCounter = 24, kKeyCounter = 25, kQueueCrossings = 26;
 // with kNoKey when it exits, and the sort skips them.
 constexpr unsigned kJobChunk = 256, kNoKey = 0xffffffffu;
 
+// Issues the wavefront's walk-block deposits (one per lane and sub-step)
+// through an LDS transpose: entry 4 * lane + d is lane `lane`'s deposit of
+// sub-step d, and atomic instruction k takes entries 64 k + lane, so the
+// four deposits of one walker -- consecutive cells of its walk, often in one
+// 64-byte segment of the bricked tally -- go out in adjacent lanes of one
+// instruction, which the memory pipeline merges into one request per
+// segment.  Global atomics are executed at the memory side at a fixed
+// request rate, so fewer requests is what counts.  Called by every lane of
+// the wavefront (uniform control flow).
+__device__ __forceinline__ void flush_deposits(const WalkDeposits& dep, double* tally, long long* sidx, double* sval) {
+  static_assert(kBlockWalk == 4, "the transpose assumes four sub-steps per lane");
+  const int lane = __lane_id();
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    sidx[4 * lane + d] = ((dep.on >> d) & 1u) ? dep.idx[d] : -1ll;
+    sval[4 * lane + d] = dep.val[d];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const long long i = sidx[64 * k + lane];
+    if (i >= 0) atomic_add_f64(tally + i, sval[64 * k + lane]);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Per-wavefront reservoir slots in LDS; lane 0 of each wavefront empties its
 // slot before the wavefront's first fetch.
 __device__ __forceinline__ unsigned long long* wave_reservoir(unsigned long long (&slots)[kWavesPerBlock][2]) {
@@ -192,6 +222,9 @@ struct PeelMem {
 template <typename R, bool ADJ>
 __global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2], job_slots[kWavesPerBlock][2];
+  __shared__ long long dep_idx[kWavesPerBlock][64 * kBlockWalk];
+  __shared__ double dep_val[kWavesPerBlock][64 * kBlockWalk];
+  const int wave = threadIdx.x / 64;
   LifeMem<R> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots), wave_reservoir(job_slots)};
   Lane<R> L;
   lane_init(L);
@@ -204,7 +237,10 @@ __global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
     for (;;) {
       const int n_act = __popcll(__ballot(L.ry.active));
       if (n_act == 0 || n_live - n_act >= P.batch) break;
-      if (L.ry.active) lane_step<R, ADJ>(L, P, M);
+      WalkDeposits dep;
+      dep.on = 0;
+      if (L.ry.active) lane_step<R, ADJ>(L, P, M, dep);
+      if (!ADJ && __ballot(dep.on != 0u)) flush_deposits(dep, P.absorbed, dep_idx[wave], dep_val[wave]);
     }
   }
   if (ADJ && P.jobs) {  // unfilled reserved queue slots

@@ -406,6 +406,25 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
 // lane keeps in flight.
 constexpr int kBlockWalk = 4;
 
+// Absorbed-luminosity deposits of one forward walk block: index into the
+// tally, value, and a bit per sub-step that made one.  The kernel issues
+// them for the whole wavefront at once, transposed so that one walker's
+// deposits -- neighbouring cells, often in one 64-byte segment of the
+// bricked tally -- sit in adjacent lanes of one atomic instruction; the CPU
+// harness applies them in order.  (The adjoint's walk deposits, far fewer,
+// go straight to the gradient.)
+struct WalkDeposits {
+  long long idx[kBlockWalk];
+  double val[kBlockWalk];
+  unsigned on;
+};
+
+template <class Mem>
+MCRT_HD void apply_deposits(const WalkDeposits& dep, Mem& M) {
+  for (int d = 0; d < kBlockWalk; ++d)
+    if ((dep.on >> d) & 1u) M.add_absorbed(dep.idx[d], dep.val[d]);
+}
+
 // Up to kBlockWalk crossings of the lane's active ray, with the per-crossing
 // work of its mode: pass-1 continuous absorption W (1 - albedo) e^-tau
 // (1 - e^-dtau) into the cell; pass-2 search for the first segment whose
@@ -413,8 +432,9 @@ constexpr int kBlockWalk = 4;
 // along the leg); peel rays accumulate tau (and, on the deposit walk,
 // -A C kappa l).  Zero-length segments are skipped.
 template <typename R, bool ADJ, class Mem>
-MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M) {
+MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep) {
   Ray<R>& ry = L.ry;
+  dep.on = 0;
   WalkBlock<kBlockWalk, R> b;
   ray_next_block(ry, b, P.G, M);
 #pragma unroll
@@ -436,7 +456,9 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M) {
         L.trans += L.trans * em;
         L.absf += f;
         if (P.absorbed) {
-          M.add_absorbed(L.lam_cell + cell, L.wabs * (double)f);
+          dep.idx[d] = L.lam_cell + cell;
+          dep.val[d] = L.wabs * (double)f;
+          dep.on |= 1u << d;
           ++L.n_dep;
         }
       }

@@ -279,7 +279,12 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   const long long cap = (long long)P.G.n[0] + P.G.n[1] + P.G.n[2] + 8;
   run_wave(
       lanes, P.batch, [&](Lane<R>& L) { lane_events<R, ADJ>(L, P, M); },
-      [&](Lane<R>& L) { lane_step<R, ADJ>(L, P, M); }, cap, 0);
+      [&](Lane<R>& L) {
+        WalkDeposits dep;
+        lane_step<R, ADJ>(L, P, M, dep);
+        apply_deposits(dep, M);
+      },
+      cap, 0);
   if (P.jobs) {
     const unsigned long long nx =
         emu_bundles<R>(P.G, pr.det, P.n_det, pr.n_keys, jobs, std::min(M.job_next, M.job_cap), grad_b);
