@@ -1,0 +1,175 @@
+"""The C ABI of include/mcrt.h on the CPU: the built library exports every
+function the header declares, the Python binding's struct layouts match the
+C compiler's, and invalid arguments are rejected with MCRT_EINVAL and a
+message before anything touches a GPU (argument checks run first, so these
+calls are safe on a machine without one)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcrt.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\([^;{]*\)\s*;", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1410_1629_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libmcrt.so is not built")
+    return binding.load()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1410_1629_amd import binding
+    return binding
+
+
+def test_header_declares_the_four_calls():
+    names = _declared_functions()
+    for n in ("run_photons", "trace_path", "peel_off", "backward_density", "mcrt_last_error", "mcrt_abi_version"):
+        assert n in names, names
+
+
+def test_library_exports_every_declared_function(lib, B):
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], check=True, capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    for n in _declared_functions():
+        assert n in exported, n
+        assert getattr(lib, n) is not None
+    assert set(B.SYMBOLS) == set(_declared_functions())
+
+
+def test_abi_version(lib):
+    m = re.search(r"#define\s+MCRT_ABI_VERSION\s+(\d+)", open(HEADER).read())
+    assert lib.mcrt_abi_version() == int(m.group(1))
+
+
+def test_struct_layouts_match_the_c_compiler(B, tmp_path):
+    structs = {"mcrt_grid": B.Grid, "mcrt_optics": B.Optics, "mcrt_source": B.Source, "mcrt_detector": B.Detector,
+               "mcrt_opts": B.Opts, "mcrt_stats": B.Stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mcrt.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(ln.split() for ln in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                    text=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[cname + "." + f]) == getattr(py, f).offset, (cname, f)
+
+
+def _call_run(lib, B, prob, **over):
+    pr = B._Problem(prob, **over)
+    st = B.Stats()
+    fake = C.c_void_p(0x1000)  # never dereferenced: the checks fail first
+    return lib.run_photons(C.byref(pr.grid), fake, C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det,
+                           pr.detectors, C.byref(pr.opts), fake, fake, C.byref(st), None)
+
+
+@pytest.mark.parametrize("case", ["n_packages", "precision", "flags", "w_min", "max_scatter", "launch_blocks",
+                                  "event_batch", "brick_shape", "deposit_queue", "grid_cells", "grid_extent",
+                                  "albedo", "g", "kappa", "lum", "n_det", "det_pixels", "det_distance",
+                                  "n_src", "src_kind", "src_scale"])
+def test_invalid_arguments_are_rejected(lib, B, W, case):
+    prob = W.small_problem(n=(4, 4, 4), n_packages=100)
+    over = {}
+    if case == "n_packages":
+        over["n_packages"] = 0
+    elif case == "precision":
+        over["precision"] = 7
+    elif case == "flags":
+        over["flags"] = 64
+    elif case == "w_min":
+        over["w_min"] = -1.0
+    elif case == "max_scatter":
+        over["max_scatter"] = 0
+    elif case == "launch_blocks":
+        over["launch_blocks"] = 100
+    elif case == "event_batch":
+        over["event_batch"] = 65
+    elif case == "brick_shape":
+        over["brick_shape"] = B.brick(9, 0, 0)
+    elif case == "deposit_queue":
+        over["deposit_queue"] = -2
+    elif case == "grid_cells":
+        prob["n"] = (0, 4, 4)
+    elif case == "grid_extent":
+        prob["box"] = (1.0, -1.0, -1, 1, -1, 1)
+    elif case == "albedo":
+        prob["albedo"] = np.array([1.5])
+    elif case == "g":
+        prob["g"] = np.array([1.0])
+    elif case == "kappa":
+        prob["kappa"] = np.array([np.nan])
+    elif case == "lum":
+        prob["sources"] = [W.point(lum=-1.0)]
+    elif case == "n_det":
+        prob["detectors"] = [W.frame(10.0, 0.0, 4, 4, 1.0, 1.0)] * 9
+    elif case == "det_pixels":
+        prob["detectors"] = [W.frame(10.0, 0.0, 0, 4, 1.0, 1.0)]
+    elif case == "det_distance":
+        prob["detectors"] = [W.frame(0.0, 0.0, 4, 4, 1.0, 1.0)]
+    elif case == "n_src":
+        prob["sources"] = [W.point()] * 9
+    elif case == "src_kind":
+        prob["sources"] = [dict(W.point(), kind="ring")]
+    elif case == "src_scale":
+        prob["sources"] = [W.expdisk(0.0, 0.1)]
+    if case == "src_kind":
+        # the binding maps kinds to the enum; pass an unknown value directly
+        pr = B._Problem(dict(prob, sources=[W.point()]))
+        pr.sources[0].kind = 5
+        st = B.Stats()
+        fake = C.c_void_p(0x1000)
+        rc = lib.run_photons(C.byref(pr.grid), fake, C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det,
+                             pr.detectors, C.byref(pr.opts), fake, fake, C.byref(st), None)
+    else:
+        rc = _call_run(lib, B, prob, **over)
+    assert rc == B.EINVAL, (case, rc)
+    assert lib.mcrt_last_error().decode(), case
+
+
+def test_null_pointers_are_rejected(lib, B, W):
+    prob = W.small_problem(n=(4, 4, 4), n_packages=100)
+    pr = B._Problem(prob)
+    st = B.Stats()
+    fake = C.c_void_p(0x1000)
+    assert lib.run_photons(None, fake, C.byref(pr.optics), 1, pr.sources, pr.n_det, pr.detectors, C.byref(pr.opts),
+                           fake, fake, C.byref(st), None) == B.EINVAL
+    assert lib.run_photons(C.byref(pr.grid), None, C.byref(pr.optics), 1, pr.sources, pr.n_det, pr.detectors,
+                           C.byref(pr.opts), fake, fake, C.byref(st), None) == B.EINVAL
+    assert lib.run_photons(C.byref(pr.grid), fake, C.byref(pr.optics), 1, pr.sources, pr.n_det, pr.detectors,
+                           None, fake, fake, C.byref(st), None) == B.EINVAL
+    assert lib.run_photons(C.byref(pr.grid), fake, C.byref(pr.optics), 1, pr.sources, pr.n_det, pr.detectors,
+                           C.byref(pr.opts), None, fake, C.byref(st), None) == B.EINVAL  # images with peel-off
+    assert lib.backward_density(C.byref(pr.grid), fake, C.byref(pr.optics), 1, pr.sources, pr.n_det, pr.detectors,
+                                C.byref(pr.opts), fake, None, C.byref(st), None) == B.EINVAL  # no gradient buffer
+    g = B.make_grid(prob)
+    assert lib.trace_path(C.byref(g), fake, 1.0, 0, -1, fake, fake, fake, 0, None, None, None, None,
+                          None) == B.EINVAL
+    assert lib.trace_path(C.byref(g), fake, -1.0, 0, 10, fake, fake, fake, 0, None, None, None, None,
+                          None) == B.EINVAL
+    assert lib.trace_path(C.byref(g), fake, 1.0, 0, 10, fake, fake, fake, 0, fake, None, None, None,
+                          None) == B.EINVAL  # segment lists go together
+    dets = B.make_detectors(prob["detectors"])
+    assert lib.peel_off(C.byref(g), fake, 1.0, 1.0, 0, 10, fake, None, fake, 1, dets, fake, None) == B.EINVAL
+    assert lib.peel_off(C.byref(g), fake, 1.0, 0.5, 0, 10, fake, None, fake, 0, dets, fake, None) == B.EINVAL
+    assert lib.mcrt_last_error().decode()

@@ -147,6 +147,42 @@ def _compare_run(B, orc, prob, tol_img, tol_abs):
     return images, absorbed, st, img_o, abs_o
 
 
+DEGENERATE = {
+    "pure_scattering": dict(albedo=1.0),
+    "pure_absorption": dict(albedo=0.0),
+    "isotropic": dict(g=0.0),
+    "forward_peaked": dict(g=0.95),
+    "backward_peaked": dict(g=-0.9),
+    "source_outside_grid": dict(sources="outside"),
+    "one_pixel_frame": dict(detectors="one_pixel"),
+    "frame_missing_grid": dict(detectors="off_grid"),
+    "single_package": dict(n_packages=1),
+    "last_package_indices": dict(first_package=(1 << 62) - 50),
+    "truncated_by_count": dict(w_min=0.0, max_scatter=3),
+    "optically_thick": dict(kappa=30.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(DEGENERATE))
+@pytest.mark.parametrize("prec", [0, 1])
+def test_run_degenerate_cases_match_oracle(B, orc, W, case, prec):
+    _say("run degenerate %s prec=%d" % (case, prec))
+    kw = dict(n=(9, 8, 7), rho=W.lognormal_density((9, 8, 7), 0.5, seed=14, f32=(prec == 1)), n_packages=1500,
+              precision=prec, flags=W.FLAGS_DEFAULT | W.FLAG_SPLIT,
+              detectors=[W.frame(10.0, 35.0, 20, 18, 1.2, 1.1, azim=15.0), W.frame(10.0, 90.0, 12, 12, 1.3, 1.3)])
+    over = dict(DEGENERATE[case])
+    if over.get("sources") == "outside":
+        over["sources"] = [W.point((2.5, 0.3, -0.2), 2.0)]
+    if over.get("detectors") == "one_pixel":
+        over["detectors"] = [W.frame(10.0, 20.0, 1, 1, 1.5, 1.5)]
+    if over.get("detectors") == "off_grid":
+        over["detectors"] = [W.frame(10.0, 0.0, 8, 8, 0.2, 0.2, pa=0.0), W.frame(10.0, 0.0, 4, 4, 0.1, 0.1, azim=40.0)]
+        over["sources"] = [W.point((0.9, 0.9, 0.0))]
+    kw.update(over)
+    prob = W.small_problem(**kw)
+    _compare_run(B, orc, prob, 1e-10 if prec == 0 else 1e-5, 1e-10 if prec == 0 else 1e-5)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_run_cube_matches_oracle(B, orc, W, prec):
     _say("run cube prec=%d" % prec)
