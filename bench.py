@@ -85,11 +85,11 @@ def traffic_for(key):
 
 
 def life_bytes(st, prec, adjoint):
-    """Algorithmic bytes of the life-cycle kernel of one call (the bundled
-    deposit walks of the adjoint run in their own kernel and are excluded)."""
+    """Algorithmic bytes of the life-cycle kernel of one call (the queued
+    peel-ray walks of the adjoint run in their own kernels and are excluded)."""
     x = st["x_path"] + st["x_locate"] + st["x_peel"] - st["x_queue"]
     peel = BYTES_PER_PEEL_ADJOINT if adjoint else BYTES_PER_PEEL_FORWARD
-    return x * BYTES_PER_CROSSING[prec] + (st["deposits"] - st["x_queue"]) * BYTES_PER_DEPOSIT + st["peels"] * peel
+    return x * BYTES_PER_CROSSING[prec] + (st["deposits"] - st["d_queue"]) * BYTES_PER_DEPOSIT + st["peels"] * peel
 
 
 def rel_l1(a, b):

@@ -123,11 +123,13 @@ typedef struct {
  * bricks of 2^lx x 2^ly x 2^lz cells (each log2 in [0, 7], at most 2^10
  * cells).  The default brick fills one 128-byte cache line with the most
  * compact block of cells in physical units.  deposit_queue (backward_density
- * only) caps the device queue of peel-ray deposit walks, in rays (at most
- * 2^31): 0 = library choice, -1 = no queue (every deposit ray is walked inline with global
- * atomics); rays beyond the cap are walked inline.  Queued rays are sorted by
- * frame and image-plane tile and walked in bundles whose deposits are summed
- * in LDS before they reach the gradient. */
+ * only) caps the device queue of peel rays, in rays per chunk of packages (at
+ * most 2^31): 0 = library choice, -1 = no queue (every peel ray is walked
+ * inline, its deposits with global atomics); rays beyond the cap are walked
+ * inline.  Queued rays are sorted by frame and image-plane tile, walked for
+ * their optical depth by a lean kernel, and walked again for their deposits
+ * in bundles whose deposits are summed in LDS before they reach the
+ * gradient. */
 typedef struct {
     uint64_t n_packages, first_package, seed;
     int32_t precision;
@@ -149,16 +151,19 @@ typedef struct {
  * counts cover all of its walks: both replays of each package (pass B takes
  * what pass A kept and walks only its locate legs and the events beyond the
  * kept ones) and the peel-ray deposit walks; x_queue is the part of x_peel
- * (and of deposits) walked by the bundled deposit kernel, whose deposits are
- * summed on chip before they reach the tally.  Durations on the stream from
- * HIP events: kernel_ms all kernels of the call, life_ms the life-cycle
- * kernel, queue_ms the sort and bundled walks of the deposit queue. */
+ * walked by the queue kernels (each queued peel ray's optical-depth walk,
+ * and its deposit walk when it has one), d_queue the part of deposits made
+ * by those deposit walks, which sum them on chip before they reach the
+ * tally.  Durations on the stream from HIP events: kernel_ms all kernels of
+ * the call, life_ms the life-cycle kernel, queue_ms the sort and the walks
+ * of the peel-ray queue. */
 typedef struct {
     double emitted, absorbed, escaped, truncated;
     uint64_t x_path, x_locate, x_peel, events, packages, peels, deposits;
     double kernel_ms;
     uint64_t x_queue;
     double life_ms, queue_ms;
+    uint64_t d_queue;
 } mcrt_stats;
 
 /* Photon-package life cycle (Sect. 1 techniques, Sect. 2.2 problem data):
@@ -229,7 +234,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 4
+#define MCRT_ABI_VERSION 5
 
 #ifdef __cplusplus
 }

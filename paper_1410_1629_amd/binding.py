@@ -66,7 +66,8 @@ class Stats(C.Structure):
                 ("truncated", C.c_double), ("x_path", C.c_uint64), ("x_locate", C.c_uint64),
                 ("x_peel", C.c_uint64), ("events", C.c_uint64), ("packages", C.c_uint64),
                 ("peels", C.c_uint64), ("deposits", C.c_uint64), ("kernel_ms", C.c_double),
-                ("x_queue", C.c_uint64), ("life_ms", C.c_double), ("queue_ms", C.c_double)]
+                ("x_queue", C.c_uint64), ("life_ms", C.c_double), ("queue_ms", C.c_double),
+                ("d_queue", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,6 +76,7 @@ class Stats(C.Structure):
 _lib = None
 
 # Exported symbols of include/mcrt.h.
+ABI_VERSION = 5  # MCRT_ABI_VERSION of the header these structs follow
 SYMBOLS = ("run_photons", "trace_path", "peel_off", "backward_density", "mcrt_last_error", "mcrt_abi_version")
 
 
@@ -103,6 +105,9 @@ def load():
     lib.mcrt_last_error.restype = C.c_char_p
     lib.mcrt_abi_version.argtypes = []
     lib.mcrt_abi_version.restype = C.c_int
+    if lib.mcrt_abi_version() != ABI_VERSION:
+        raise RuntimeError("libmcrt.so has ABI version %d, the binding expects %d; rebuild it" % (
+            lib.mcrt_abi_version(), ABI_VERSION))
     _lib = lib
     return lib
 

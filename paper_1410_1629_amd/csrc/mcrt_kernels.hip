@@ -89,9 +89,10 @@ constexpr int kWavesPerBlock = kBlock / 64;
 
 // Counter block of a life-cycle call (u64 words): [0] next work item,
 // [8..10] FP64 luminosity stats, [16..22] crossing and event counts,
-// [24] next deposit-queue slot, [25] next chunk of the bundled walk,
-// [26] crossings of the bundled walk.
-constexpr int kJobCounter = 24, kKeyCounter = 25, kQueueCrossings = 26;
+// [24] next peel-job slot, [25] next sorted job of the optical-depth walks,
+// [26] and [27] crossings and deposits of the queued walks, [28] next chunk
+// of the deposit walks.
+constexpr int kJobCounter = 24, kKeyCounter = 25, kQueueCrossings = 26, kDepCounter = 28;
 // Deposit-queue slots are reserved per wavefront in chunks (one global
 // atomic per chunk); slots a wavefront reserved but did not fill are marked
 // with kNoKey when it exits, and the sort skips them.
@@ -154,16 +155,31 @@ struct LifeMem {
   __device__ void add_grad(int i, double v) const { atomic_add_f64(P.grad + i, v); }
   __device__ unsigned long long fetch() const { return wave_fetch(P.work, res, 64); }
   __device__ unsigned long long job_slot() const { return wave_fetch(P.work + kJobCounter, job_res, kJobChunk); }
-  __device__ double ev_load(int slot, int e, int k) const { return P.evs[(2ull * e + k) * P.n_slots + slot]; }
-  __device__ void ev_store(int slot, int e, int k, double v) const { P.evs[(2ull * e + k) * P.n_slots + slot] = v; }
-  __device__ void store_job(unsigned long long slot, const double r[3], double w, unsigned key) const {
-    BpJob& J = P.jobs[slot];
+  // event scratch of the adjoint: [ev_max][ev_k][n_chunk], then [n_chunk]
+  __device__ double ev_load(int slot, int e, int k) const {
+    return P.evs[((size_t)e * P.ev_k + k) * P.n_chunk + slot];
+  }
+  __device__ void ev_store(int slot, int e, int k, double v) const {
+    P.evs[((size_t)e * P.ev_k + k) * P.n_chunk + slot] = v;
+  }
+  __device__ double ev_load_beyond(int slot) const { return P.evs[(size_t)P.ev_max * P.ev_k * P.n_chunk + slot]; }
+  __device__ void ev_add_beyond(int slot, double v) const {
+    atomic_add_f64(P.evs + (size_t)P.ev_max * P.ev_k * P.n_chunk + slot, v);
+  }
+  __device__ void store_job(unsigned long long slot, const double r[3], double v, long long ii, unsigned key,
+                            unsigned item, int e, int d, unsigned lam) const {
+    PeelJob& J = P.jobs[slot];
     J.r[0] = r[0];
     J.r[1] = r[1];
     J.r[2] = r[2];
-    J.w = w;
+    J.v = v;
+    J.ii = ii;
     J.key = key;
     J.rank = 0;
+    J.slot = item;
+    J.e = (unsigned short)e;
+    J.d = (unsigned short)d;
+    J.lam = lam;
   }
   __device__ void flush_counts(unsigned a, unsigned b, unsigned c, unsigned d) const {
     atomicAdd(P.xstats + 0, (unsigned long long)a);
@@ -228,7 +244,6 @@ __global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
   LifeMem<R> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots), wave_reservoir(job_slots)};
   Lane<R> L;
   lane_init(L);
-  L.slot = blockIdx.x * kBlock + threadIdx.x;
   for (;;) {
     lane_events<R, ADJ>(L, P, M);
     const unsigned long long live = __ballot(!L.done);
@@ -309,16 +324,20 @@ __global__ void __launch_bounds__(kBlock) k_peel(const PeelParams P) {
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint deposit rays, walked in bundles.  The life-cycle kernel queues
-// each peel ray that must deposit -A C kappa l.  A counting sort by key
+// Adjoint peel rays, walked in bundles.  Pass A queues each peel ray of each
+// event (origin, W Phi / D^2, pixel, frame).  A counting sort by key
 // (k_count, k_scan, k_perm) orders the queue by frame and by pixel in Morton
 // order, so any run of consecutive sorted rays is a compact patch of one
 // frame: parallel rays a few cells apart that cross one narrow bundle of
-// cells.  k_bundle hands such runs (chunks) to workgroups, walks them and
-// sums the deposits per cell in an LDS hash table, then adds each distinct
-// cell to the gradient with one global atomic.  Global atomics execute at
-// the memory side at a fixed request rate, so this replaces one atomic per
-// crossing by about one per cell and chunk.
+// cells.  k_peeltau walks each ray once for its optical depth, which gives
+// C and q = (dL/dI) C (kept for pass B); k_peeldep hands runs of sorted rays
+// (chunks) to workgroups and walks each ray with q != 0 once more, without
+// density loads, to deposit -q kappa l; the deposits are summed per cell in
+// an LDS hash table and each distinct cell goes to the gradient with one
+// global atomic.
+// Global atomics execute at the memory side at a fixed request rate, so this
+// replaces one atomic per crossing by about one per cell and chunk; and the
+// walks run in a lean kernel, on rays whose neighbours read the same lines.
 
 // Queue slots handed out (the counter may have run past the capacity).
 __device__ __forceinline__ unsigned long long queued_jobs(const unsigned long long* ctr, unsigned long long cap) {
@@ -326,8 +345,8 @@ __device__ __forceinline__ unsigned long long queued_jobs(const unsigned long lo
   return n < cap ? n : cap;
 }
 
-__global__ void k_count(BpJob* __restrict__ jobs, const unsigned long long* __restrict__ ctr, unsigned long long cap,
-                        unsigned* __restrict__ kcount) {
+__global__ void k_count(PeelJob* __restrict__ jobs, const unsigned long long* __restrict__ ctr,
+                        unsigned long long cap, unsigned* __restrict__ kcount) {
   const unsigned long long n = queued_jobs(ctr, cap);
   for (unsigned long long j = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; j < n;
        j += (unsigned long long)gridDim.x * blockDim.x) {
@@ -336,32 +355,75 @@ __global__ void k_count(BpJob* __restrict__ jobs, const unsigned long long* __re
   }
 }
 
-// Exclusive scan of kcount[0, n) into kstart[0, n]; one block of kScanThreads.
-constexpr int kScanThreads = 1024;
-__global__ void __launch_bounds__(kScanThreads) k_scan(const unsigned* __restrict__ kcount, unsigned* __restrict__ kstart,
-                                                       long long n) {
-  __shared__ unsigned part[kScanThreads];
-  const long long per = (n + kScanThreads - 1) / kScanThreads;
-  const long long lo = threadIdx.x * per, hi = lo + per < n ? lo + per : n;
-  unsigned s = 0;
-  for (long long i = lo; i < hi; ++i) s += kcount[i];
-  part[threadIdx.x] = s;
+// Exclusive scan of kcount[0, n) into kstart[0, n] in three launches:
+// k_scan_tiles scans tiles of kScanTile counts within each block and writes
+// the tile totals, k_scan_top scans the totals in one block, k_scan_add adds
+// each tile's offset.
+constexpr int kScanThreads = 256, kScanPer = 8, kScanTile = kScanThreads * kScanPer, kTopThreads = 1024;
+
+__device__ __forceinline__ unsigned block_exclusive_scan(unsigned v, unsigned* lds, unsigned* total) {
+  const int t = threadIdx.x;
+  lds[t] = v;
   __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {  // Hillis-Steele inclusive scan
-    const unsigned v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {  // Hillis-Steele inclusive scan
+    const unsigned u = t >= off ? lds[t - off] : 0u;
     __syncthreads();
-    part[threadIdx.x] += v;
+    lds[t] += u;
     __syncthreads();
   }
-  unsigned run = part[threadIdx.x] - s;
-  for (long long i = lo; i < hi; ++i) {
-    kstart[i] = run;
-    run += kcount[i];
-  }
-  if (threadIdx.x == kScanThreads - 1) kstart[n] = part[kScanThreads - 1];
+  const unsigned incl = lds[t];
+  *total = lds[blockDim.x - 1];
+  __syncthreads();
+  return incl - v;
 }
 
-__global__ void k_perm(const BpJob* __restrict__ jobs, const unsigned long long* __restrict__ ctr,
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const unsigned* __restrict__ kcount,
+                                                             unsigned* __restrict__ kstart, unsigned* __restrict__ tiles,
+                                                             long long n) {
+  __shared__ unsigned lds[kScanThreads];
+  const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanPer;
+  unsigned v[kScanPer], s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    v[i] = base + i < n ? kcount[base + i] : 0u;
+    s += v[i];
+  }
+  unsigned total;
+  unsigned run = block_exclusive_scan(s, lds, &total);
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    if (base + i < n) kstart[base + i] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == 0) tiles[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kTopThreads) k_scan_top(unsigned* __restrict__ tiles, long long n_tiles,
+                                                          unsigned* __restrict__ kstart, long long n) {
+  __shared__ unsigned lds[kTopThreads];
+  const long long per = (n_tiles + kTopThreads - 1) / kTopThreads;
+  const long long lo = threadIdx.x * per, hi = lo + per < n_tiles ? lo + per : n_tiles;
+  unsigned s = 0;
+  for (long long i = lo; i < hi; ++i) s += tiles[i];
+  unsigned total;
+  unsigned run = block_exclusive_scan(s, lds, &total);
+  for (long long i = lo; i < hi; ++i) {
+    const unsigned t = tiles[i];
+    tiles[i] = run;
+    run += t;
+  }
+  if (threadIdx.x == 0) kstart[n] = total;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_add(unsigned* __restrict__ kstart,
+                                                           const unsigned* __restrict__ tiles, long long n) {
+  const long long base = (long long)blockIdx.x * kScanTile;
+  const unsigned off = tiles[blockIdx.x];
+  for (int i = threadIdx.x; i < kScanTile; i += kScanThreads)
+    if (base + i < n) kstart[base + i] += off;
+}
+
+__global__ void k_perm(const PeelJob* __restrict__ jobs, const unsigned long long* __restrict__ ctr,
                        unsigned long long cap, const unsigned* __restrict__ kstart, unsigned* __restrict__ perm) {
   const unsigned long long n = queued_jobs(ctr, cap);
   for (unsigned long long j = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; j < n;
@@ -371,30 +433,40 @@ __global__ void k_perm(const BpJob* __restrict__ jobs, const unsigned long long*
   }
 }
 
-constexpr int kBundleThreads = 512, kBundleWaves = kBundleThreads / 64;
+constexpr int kBundleThreads = 512;
 constexpr int kTableBits = 13, kTable = 1 << kTableBits, kProbes = 4;
 constexpr unsigned kChunk = 2048;
 
-struct BundleParams {
+struct PeelJobParams {
   GridDev G;
+  const void* rho;
   const DetDev* det;
+  const LamDev* lam;
   int n_det;
   long long n_keys;
-  const BpJob* jobs;
+  PeelJob* jobs;  // the optical-depth walks overwrite v with the deposit weight
   const unsigned* perm;
   const unsigned* kstart;
+  const double* adj;
   double* grad;
+  double* evs;  // event scratch of the chunk (see LifeMem)
+  int ev_max, ev_k;
+  unsigned long long n_chunk;
   unsigned long long* ctr;  // counter block of the call
   int batch;
 };
 
-// Deposits into the workgroup's LDS table (open addressing, linear probing
-// over at most kProbes slots); a deposit that finds no slot goes straight
-// to the global tally.
-struct BundleMem {
+// Density loads for the optical-depth walk; deposits of the deposit walk go
+// into the workgroup's LDS table (open addressing, linear probing over at
+// most kProbes slots); a deposit that finds no slot goes straight to the
+// global tally.
+template <typename R>
+struct PeelJobMem {
+  const R* __restrict__ rho_;
   int* tk;
   double* tv;
   double* grad;
+  __device__ R rho(int c) const { return rho_[c]; }
   __device__ void deposit(int cell, double v) const {
     const unsigned h = ((unsigned)cell * 2654435761u) >> (32 - kTableBits);
     for (int p = 0; p < kProbes; ++p) {
@@ -414,14 +486,70 @@ struct BundleMem {
 };
 
 // Frame of a sort key.
-__device__ __forceinline__ int key_frame(const BundleParams& P, unsigned key) {
+__device__ __forceinline__ int key_frame(const PeelJobParams& P, unsigned key) {
   int d = 0;
   while (d + 1 < P.n_det && (unsigned)P.det[d + 1].key_off <= key) ++d;
   return d;
 }
 
+// The optical-depth walks of the sorted queue, one ray per lane in a lean
+// persistent loop (no LDS table, so many waves per SIMD hide the density
+// loads): q = (dL/dI) v e^-tau goes to the event scratch, and the job's v
+// becomes the deposit weight -q kappa (0: no deposit walk).
 template <typename R>
-__global__ void __launch_bounds__(kBundleThreads) k_bundle(const BundleParams P) {
+__global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
+  __shared__ unsigned long long slots[kWavesPerBlock][2];
+  unsigned long long* res = wave_reservoir(slots);
+  const PeelJobMem<R> M{static_cast<const R*>(P.rho), nullptr, nullptr, P.grad};
+  const unsigned n_jobs = P.kstart[P.n_keys];
+  unsigned long long nx = 0;
+  Ray<R> ry;
+  ry.active = false;
+  ry.tau = R(0);
+  bool done = false, pending = false;
+  unsigned job = 0;
+  R kap = R(0);
+  for (;;) {
+    while (!ry.active && !done) {
+      if (pending) {
+        PeelJob& J = P.jobs[job];
+        const double q = P.adj[J.ii] * (J.v * exp(-(double)ry.tau));
+        if (J.e < P.ev_max)
+          P.evs[((size_t)J.e * P.ev_k + 1 + J.d) * P.n_chunk + J.slot] = q;
+        else
+          atomic_add_f64(P.evs + (size_t)P.ev_max * P.ev_k * P.n_chunk + J.slot, q);
+        J.v = -q * P.lam[J.lam].kappa;
+        pending = false;
+      }
+      const unsigned long long qi = wave_fetch(P.ctr + kKeyCounter, res, 256);
+      if (qi >= n_jobs) {
+        done = true;
+        break;
+      }
+      job = P.perm[qi];
+      const PeelJob& J = P.jobs[job];
+      kap = (R)P.lam[J.lam].kappa;
+      ray_begin(ry, P.G, J.r, P.det[key_frame(P, J.key)].kd);
+      pending = true;
+    }
+    const unsigned long long live = __ballot(!done);
+    if (live == 0ull) break;
+    const int n_live = __popcll(live);
+    for (;;) {
+      const int n_act = __popcll(__ballot(ry.active));
+      if (n_act == 0 || n_live - n_act >= P.batch) break;
+      if (ry.active) nx += tau_step<R>(ry, P.G, kap, M);
+    }
+  }
+  const unsigned long long wsum = wave_sum_u64(nx);
+  if (__lane_id() == 0 && wsum) atomicAdd(P.ctr + kQueueCrossings, wsum);
+}
+
+// The deposit walks of the sorted queue: chunks of consecutive sorted jobs
+// per workgroup, deposits summed per cell in the LDS table, one global
+// atomic per distinct cell and chunk.  Jobs whose weight is 0 are skipped.
+template <typename R>
+__global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams P) {
   __shared__ int tk[kTable];
   __shared__ double tv[kTable];
   __shared__ unsigned s_begin, s_end, s_next;
@@ -429,34 +557,32 @@ __global__ void __launch_bounds__(kBundleThreads) k_bundle(const BundleParams P)
     tk[i] = -1;
     tv[i] = 0.0;
   }
-  const BundleMem M{tk, tv, P.grad};
+  const PeelJobMem<R> M{static_cast<const R*>(P.rho), tk, tv, P.grad};
   const unsigned n_jobs = P.kstart[P.n_keys];
-  unsigned long long nx = 0;
+  unsigned long long nd = 0;
   for (;;) {
     if (threadIdx.x == 0) {
-      const unsigned long long b = atomicAdd(P.ctr + kKeyCounter, 1ull) * kChunk;
+      const unsigned long long b = atomicAdd(P.ctr + kDepCounter, 1ull) * kChunk;
       s_begin = s_next = b < n_jobs ? (unsigned)b : n_jobs;
       s_end = b + kChunk < n_jobs ? (unsigned)(b + kChunk) : n_jobs;
     }
     __syncthreads();
     const unsigned end = s_end;
     if (s_begin >= end) break;  // s_begin and s_end change only after the closing barrier
-    // every lane walks rays of the chunk until it is exhausted; a wavefront
-    // takes new rays once `batch` of its lanes are idle
     Ray<R> ry;
     ry.active = false;
-    double w = 0.0;
     bool done = false;
+    double w = 0.0;
     for (;;) {
       while (!ry.active && !done) {
-        const unsigned q = atomicAdd(&s_next, 1u);
-        if (q >= end) {
+        const unsigned qi = atomicAdd(&s_next, 1u);
+        if (qi >= end) {
           done = true;
           break;
         }
-        const BpJob& J = P.jobs[P.perm[q]];
-        w = J.w;
-        ray_begin(ry, P.G, J.r, P.det[key_frame(P, J.key)].kd);
+        const PeelJob& J = P.jobs[P.perm[qi]];
+        w = J.v;
+        if (w != 0.0) ray_begin(ry, P.G, J.r, P.det[key_frame(P, J.key)].kd);
       }
       const unsigned long long live = __ballot(!done);
       if (live == 0ull) break;
@@ -464,7 +590,7 @@ __global__ void __launch_bounds__(kBundleThreads) k_bundle(const BundleParams P)
       for (;;) {
         const int n_act = __popcll(__ballot(ry.active));
         if (n_act == 0 || n_live - n_act >= P.batch) break;
-        if (ry.active) nx += bp_step<R>(ry, P.G, w, M);
+        if (ry.active) nd += bp_step<R>(ry, P.G, w, M);
       }
     }
     __syncthreads();
@@ -478,8 +604,11 @@ __global__ void __launch_bounds__(kBundleThreads) k_bundle(const BundleParams P)
     }
     __syncthreads();
   }
-  const unsigned long long wsum = wave_sum_u64(nx);
-  if (__lane_id() == 0 && wsum) atomicAdd(P.ctr + kQueueCrossings, wsum);
+  const unsigned long long dsum = wave_sum_u64(nd);
+  if (__lane_id() == 0 && dsum) {
+    atomicAdd(P.ctr + kQueueCrossings, dsum);
+    atomicAdd(P.ctr + kQueueCrossings + 1, dsum);
+  }
 }
 
 __global__ void k_zero(double* __restrict__ p, long long n) {
@@ -597,76 +726,99 @@ struct EventPair {
   }
 };
 
-// Device memory of the adjoint's deposit queue: jobs, their sorted order
+// Device memory of the adjoint's peel-job queue: jobs, their sorted order
 // and the per-key counts and starts.
-struct DepositQueue {
+struct PeelQueue {
   unsigned char* ptr = nullptr;
   hipStream_t st = nullptr;
   unsigned long long cap = 0;
   long long n_keys = 0;
-  BpJob* jobs = nullptr;
-  unsigned *perm = nullptr, *kcount = nullptr, *kstart = nullptr;
-  ~DepositQueue() {
+  PeelJob* jobs = nullptr;
+  unsigned *perm = nullptr, *kcount = nullptr, *kstart = nullptr, *tiles = nullptr;
+  ~PeelQueue() {
     if (ptr) (void)hipFreeAsync(ptr, st);
   }
 };
 
-int make_queue(const mcrt_opts& o, const host::Prepared& pr, hipStream_t st, DepositQueue& q) {
+// Capacity per chunk of `chunk` packages: mcrt_opts.deposit_queue, or by
+// default 8 peel rays per package and frame (the typical package has fewer
+// events; rays beyond the capacity are walked in pass A), at most 2^28 and a
+// quarter of the free device memory.
+int make_peel_queue(const mcrt_opts& o, const host::Prepared& pr, unsigned long long chunk, hipStream_t st,
+                    PeelQueue& q) {
   q.st = st;
   q.n_keys = pr.n_keys;
   unsigned long long cap;
   if (o.deposit_queue > 0) {
     cap = (unsigned long long)o.deposit_queue;
   } else {
-    // every event peels off once per frame; 8 events per package covers the
-    // typical package, and the rest is walked inline
-    cap = pr.P.n_items * (unsigned long long)pr.P.n_det * 8ull;
+    cap = chunk * (unsigned long long)pr.P.n_det * 8ull;
     cap = std::min(std::max(cap, 1ull << 16), 1ull << 28);
     size_t free_b = 0, total_b = 0;
     HIPCHK(hipMemGetInfo(&free_b, &total_b));
-    cap = std::min<unsigned long long>(cap, free_b / 4 / (sizeof(BpJob) + sizeof(unsigned)));
+    cap = std::min<unsigned long long>(cap, free_b / 4 / (sizeof(PeelJob) + sizeof(unsigned)));
     if (cap == 0) return 0;
   }
-  const size_t off_perm = align256(sizeof(BpJob) * cap);
+  const size_t off_perm = align256(sizeof(PeelJob) * cap);
   const size_t off_cnt = off_perm + align256(sizeof(unsigned) * cap);
   const size_t off_start = off_cnt + align256(sizeof(unsigned) * (size_t)q.n_keys);
-  const size_t bytes = off_start + align256(sizeof(unsigned) * (size_t)(q.n_keys + 1));
+  const size_t off_tiles = off_start + align256(sizeof(unsigned) * (size_t)(q.n_keys + 1));
+  const size_t bytes = off_tiles + align256(sizeof(unsigned) * (size_t)(q.n_keys / kScanTile + 1));
   HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&q.ptr), bytes, st));
   q.cap = cap;
-  q.jobs = reinterpret_cast<BpJob*>(q.ptr);
+  q.jobs = reinterpret_cast<PeelJob*>(q.ptr);
   q.perm = reinterpret_cast<unsigned*>(q.ptr + off_perm);
   q.kcount = reinterpret_cast<unsigned*>(q.ptr + off_cnt);
   q.kstart = reinterpret_cast<unsigned*>(q.ptr + off_start);
-  hipLaunchKernelGGL(k_zero_u32, dim3(stream_blocks(q.n_keys)), dim3(kBlock), 0, st, q.kcount, q.n_keys);
-  HIPCHK(hipGetLastError());
+  q.tiles = reinterpret_cast<unsigned*>(q.ptr + off_tiles);
   return 0;
 }
 
-// Sorts the queued rays by tile key and walks them in bundles.
+// Zeroes counter words [w, w + n) of the call's counter block.
+int reset_counters(unsigned long long* ctr, int w, int n, hipStream_t st) {
+  return zero_fill(reinterpret_cast<double*>(ctr + w), n, st);
+}
+
+// Sorts the chunk's queued peel rays by key and walks them in bundles.
 template <typename R>
-int run_queue(const DepositQueue& q, const RunParams& P, unsigned long long* ctr, hipStream_t st) {
+int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ctr, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(stream_blocks(q.n_keys)), dim3(kBlock), 0, st, q.kcount, q.n_keys);
   hipLaunchKernelGGL(k_count, dim3(stream_blocks((long long)q.cap)), dim3(kBlock), 0, st, q.jobs, ctr, q.cap,
                      q.kcount);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, q.kcount, q.kstart, q.n_keys);
+  const long long n_tiles = (q.n_keys + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, st, q.kcount, q.kstart, q.tiles,
+                     q.n_keys);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kTopThreads), 0, st, q.tiles, n_tiles, q.kstart, q.n_keys);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, st, q.kstart, q.tiles, q.n_keys);
   hipLaunchKernelGGL(k_perm, dim3(stream_blocks((long long)q.cap)), dim3(kBlock), 0, st, q.jobs, ctr, q.cap,
                      q.kstart, q.perm);
   HIPCHK(hipGetLastError());
-  BundleParams B;
-  B.G = P.G;
-  B.det = P.det;
-  B.n_det = P.n_det;
-  B.n_keys = q.n_keys;
-  B.jobs = q.jobs;
-  B.perm = q.perm;
-  B.kstart = q.kstart;
-  B.grad = P.grad;
-  B.ctr = ctr;
-  B.batch = 16;
+  PeelJobParams J;
+  J.G = P.G;
+  J.rho = P.rho;
+  J.det = P.det;
+  J.lam = P.lam;
+  J.n_det = P.n_det;
+  J.n_keys = q.n_keys;
+  J.jobs = q.jobs;
+  J.perm = q.perm;
+  J.kstart = q.kstart;
+  J.adj = P.adj;
+  J.grad = P.grad;
+  J.evs = P.evs;
+  J.ev_max = P.ev_max;
+  J.ev_k = P.ev_k;
+  J.n_chunk = P.n_chunk;
+  J.ctr = ctr;
+  J.batch = 16;
+  int nblk = 0;
+  if (int e = persistent_grid(k_peeltau<R>, 0, &nblk)) return e;
+  hipLaunchKernelGGL(k_peeltau<R>, dim3(nblk), dim3(kBlock), 0, st, J);
   int dev = 0, cus = 0, nb = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bundle<R>, kBundleThreads, 0));
-  hipLaunchKernelGGL(k_bundle<R>, dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0, st, B);
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peeldep<R>, kBundleThreads, 0));
+  hipLaunchKernelGGL(k_peeldep<R>, dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0, st, J);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -684,8 +836,9 @@ int launch_life(const RunParams& P, int nblk, hipStream_t st) {
 }
 
 // Events per package kept in the adjoint's event scratch (more are walked
-// again in pass B).
+// again in pass B), and the scratch size that bounds a chunk of packages.
 constexpr int kEventsKept = 32;
+constexpr size_t kScratchBytes = size_t(1) << 30;
 
 // Shared driver of run_photons and backward_density.
 int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
@@ -715,8 +868,13 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
                       : (f32 ? life_grid<float, false>(opts->launch_blocks, &nblk)
                              : life_grid<double, false>(opts->launch_blocks, &nblk)))
     return e;
-  const unsigned long long n_slots = (unsigned long long)nblk * kBlock;
-  const size_t n_evs = adjoint ? (size_t)n_slots * 2 * kEventsKept : 0;
+  // the adjoint runs in chunks of packages: its event scratch holds, per
+  // package, T and q per frame for kEventsKept events plus the sum of q beyond
+  const int ev_k = 1 + n_det;
+  const size_t per_item = sizeof(double) * ((size_t)kEventsKept * ev_k + 1);
+  const unsigned long long chunk =
+      adjoint ? std::min<unsigned long long>(P.n_items, std::max<size_t>(1 << 16, kScratchBytes / per_item)) : 0;
+  const size_t n_evs = adjoint ? (size_t)chunk * ((size_t)kEventsKept * ev_k + 1) : 0;
   const long long n_tally = adjoint ? (long long)P.G.ncell_pad : (P.absorbed ? (long long)nl * P.G.ncell_pad : 0);
   const size_t off_lam = 0;
   const size_t off_det = align256(sizeof(LamDev) * nl);
@@ -746,9 +904,11 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     P.absorbed = tally;
   if (adjoint) {
     P.evs = reinterpret_cast<double*>(blk.ptr + off_evs);
-    P.n_slots = n_slots;
     P.ev_max = kEventsKept;
+    P.ev_k = ev_k;
   }
+  P.item0 = 0;
+  P.n_chunk = P.n_items;
   P.lam = reinterpret_cast<const LamDev*>(blk.ptr + off_lam);
   P.det = reinterpret_cast<const DetDev*>(blk.ptr + off_det);
   P.src = reinterpret_cast<const SrcDev*>(blk.ptr + off_src);
@@ -758,60 +918,95 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   if (!adjoint)
     if (int e = zero_fill(P.images, peel ? pr.n_images : 0, st)) return e;
   if (int e = zero_fill(tally, n_tally, st)) return e;
-  DepositQueue queue;
+  PeelQueue queue;
   if (adjoint && peel && opts->deposit_queue != -1) {
-    if (int e = make_queue(*opts, pr, st, queue)) return e;
+    if (int e = make_peel_queue(*opts, pr, chunk, st, queue)) return e;
     P.jobs = queue.cap ? queue.jobs : nullptr;
     P.job_cap = queue.cap;
   }
   unsigned long long* const ctr = reinterpret_cast<unsigned long long*>(blk.ptr + off_cnt);
   EventPair ev;
+  std::vector<hipEvent_t> qev;  // around each chunk's queue phase
+  struct EventsGuard {
+    std::vector<hipEvent_t>& v;
+    ~EventsGuard() {
+      for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    }
+  } qguard{qev};
   if (stats) {
     HIPCHK(hipEventCreate(&ev.a));
-    HIPCHK(hipEventCreate(&ev.b));
     HIPCHK(hipEventCreate(&ev.c));
     HIPCHK(hipEventRecord(ev.a, st));
   }
-  int rc;
-  if (adjoint)
-    rc = f32 ? launch_life<float, true>(P, nblk, st) : launch_life<double, true>(P, nblk, st);
-  else
+  int rc = 0;
+  if (!adjoint) {
     rc = f32 ? launch_life<float, false>(P, nblk, st) : launch_life<double, false>(P, nblk, st);
-  if (rc) return rc;
-  if (stats) HIPCHK(hipEventRecord(ev.b, st));
-  if (P.jobs) {
-    rc = f32 ? run_queue<float>(queue, P, ctr, st) : run_queue<double>(queue, P, ctr, st);
     if (rc) return rc;
+  } else {
+    for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
+      P.item0 = c0;
+      P.n_chunk = std::min(chunk, P.n_items - c0);
+      if (int e = zero_fill(P.evs, (long long)(P.n_chunk * ((unsigned long long)kEventsKept * ev_k + 1)), st))
+        return e;
+      if (int e = reset_counters(ctr, 0, 1, st)) return e;
+      if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
+      if (int e = reset_counters(ctr, kDepCounter, 1, st)) return e;
+      P.split = 1;  // pass A
+      rc = f32 ? launch_life<float, true>(P, nblk, st) : launch_life<double, true>(P, nblk, st);
+      if (rc) return rc;
+      if (P.jobs) {
+        if (stats) {
+          qev.push_back(nullptr);
+          HIPCHK(hipEventCreate(&qev.back()));
+          HIPCHK(hipEventRecord(qev.back(), st));
+        }
+        rc = f32 ? run_peel_jobs<float>(queue, P, ctr, st) : run_peel_jobs<double>(queue, P, ctr, st);
+        if (rc) return rc;
+        if (stats) {
+          qev.push_back(nullptr);
+          HIPCHK(hipEventCreate(&qev.back()));
+          HIPCHK(hipEventRecord(qev.back(), st));
+        }
+      }
+      if (int e = reset_counters(ctr, 0, 1, st)) return e;
+      P.split = 2;  // pass B
+      rc = f32 ? launch_life<float, true>(P, nblk, st) : launch_life<double, true>(P, nblk, st);
+      if (rc) return rc;
+    }
   }
   if (stats) HIPCHK(hipEventRecord(ev.c, st));
   if (tally)
     if (int e = unbrick_tally(P.G, tally, user_tally, adjoint ? 1 : nl, st)) return e;
   if (stats) {
     double ds[3];
-    unsigned long long xs[7], xq = 0;
+    unsigned long long xs[7], xq[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(ds, P.dstats, sizeof ds, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(xs, P.xstats, sizeof xs, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&xq, ctr + kQueueCrossings, sizeof xq, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(xq, ctr + kQueueCrossings, sizeof xq, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    float ms = 0.0f, ms_life = 0.0f, ms_queue = 0.0f;
+    float ms = 0.0f, ms_queue = 0.0f;
     if (hipEventElapsedTime(&ms, ev.a, ev.c) != hipSuccess) ms = -1.0f;
-    if (hipEventElapsedTime(&ms_life, ev.a, ev.b) != hipSuccess) ms_life = -1.0f;
-    if (hipEventElapsedTime(&ms_queue, ev.b, ev.c) != hipSuccess) ms_queue = -1.0f;
+    for (size_t i = 0; i + 1 < qev.size(); i += 2) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, qev[i], qev[i + 1]) == hipSuccess) ms_queue += t;
+    }
+    const float ms_life = ms - ms_queue;
     stats->emitted = pr.emitted;
     stats->absorbed = ds[0];
     stats->escaped = ds[1];
     stats->truncated = ds[2];
     stats->x_path = xs[0];
     stats->x_locate = xs[1];
-    stats->x_peel = xs[2] + xq;
+    stats->x_peel = xs[2] + xq[0];
     stats->events = xs[3];
     stats->packages = xs[4];
     stats->peels = xs[5];
-    stats->deposits = xs[6] + xq;
+    stats->deposits = xs[6] + xq[1];
     stats->kernel_ms = ms;
-    stats->x_queue = xq;
+    stats->x_queue = xq[0];
     stats->life_ms = ms_life;
     stats->queue_ms = ms_queue;
+    stats->d_queue = xq[1];
   }
   return 0;
 }

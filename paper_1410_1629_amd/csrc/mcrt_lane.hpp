@@ -30,16 +30,24 @@
 // of event e, with respect to the density of cell m is
 //   C [ sum_{i<=e} (delta(m, c_i)/rho_m - kappa l_m(leg_i)) - kappa l_m(peel) ]
 // (c_i: cell of scattering i; leg_i: path from event i-1 to it).  With
-// A = dL/dI at C's pixel and G_e the sum of A C over the frames for event e,
-// the gradient collects, per package, R_i = sum_{e>=i} G_e on leg i and on
-// c_i, and A C on each peel ray.  Pass A replays the package: it walks each
-// peel ray for C and, when A C != 0, queues a second walk of the same ray
-// that deposits -A C kappa l (or walks it at once when the queue is full);
-// it keeps G_e and the optical depth T of each leg in the lane's event
-// scratch and sums R_1 = sum_e G_e.  Pass B replays the package again with
-// R_i = R_1 - sum_{e<i} G_e and deposits along the locate walks; it reads
-// G_e and T from the scratch instead of walking peel rays and paths again
-// (events beyond the scratch are walked as in pass A, without deposits).
+// A = dL/dI at C's pixel, q = A C for one peel ray and G_e the sum of q over
+// the frames for event e, the gradient collects, per package,
+// R_i = sum_{e>=i} G_e on leg i and on c_i, and -q kappa l along each peel
+// ray.  The adjoint runs on chunks of packages in two replays of each
+// package, as two launches of the life-cycle kernel (P.split):
+//   split 1 (pass A): the package's events; each peel ray goes to the queue
+//     of peel jobs (or, with the queue full, is walked here: once for C,
+//     and again to deposit -q kappa l); T of every leg and q of every walked
+//     peel ray go to the event scratch;
+//   the peel-job kernel walks the queued rays (sorted into bundles of
+//     parallel neighbours) for C, writes q to the scratch, and walks each
+//     ray with q != 0 again to deposit;
+//   split 2 (pass B): the package again with R_1 = sum of its q and
+//     R_i = R_1 - sum_{e<i} G_e, depositing along the locate walks; G_e and T
+//     come from the scratch (events beyond it walk their peel rays and paths
+//     again, without deposits).
+#pragma once
+
 #pragma once
 
 #include "mcrt_device.hpp"
@@ -62,14 +70,17 @@ enum Phase : int {
   PH_PKG_END
 };
 
-// A queued adjoint deposit ray: from r towards frame `key`'s observer,
-// depositing w * (segment length) into every cell crossed (w = -A C kappa).
-// key is the image-plane tile key (tile_key), rank the job's place among the
-// jobs of its key (set by the counting pass).
-struct BpJob {
+// A queued adjoint peel ray: from r towards frame d of event e of chunk
+// package `slot`, with v = W Phi / D^2 (so C = v e^-tau), ii its index in
+// the image block (for dL/dI) and lam its wavelength.  key is the sort key
+// (tile_key), rank the job's place among the jobs of its key.
+struct PeelJob {
   double r[3];
-  double w;
-  unsigned key, rank;
+  double v;
+  long long ii;
+  unsigned key, rank, slot;
+  unsigned short e, d;
+  unsigned lam;
 };
 
 struct RunParams {
@@ -92,11 +103,14 @@ struct RunParams {
   double* dstats;              // absorbed, escaped, truncated
   unsigned long long* xstats;  // x_path, x_locate, x_peel, events, packages, peels, deposits
   int batch;
-  BpJob* jobs;                 // adjoint: queue of peel-ray deposit walks (NULL: walk inline)
-  unsigned long long job_cap;  // its capacity; rays beyond it are walked inline
-  int ev_max;                  // adjoint: events kept per package in the event scratch
-  double* evs;                 // event scratch [ev_max][2][n_slots]: G_e, T of the leg after e
-  unsigned long long n_slots;  // lanes of the launch
+  // adjoint (ADJ): the launch's role and its chunk of work items
+  int split;                   // 1: pass A, 2: pass B
+  unsigned long long item0, n_chunk;  // work items [item0, item0 + n_chunk)
+  PeelJob* jobs;               // pass A: queue of peel jobs (NULL: walk every peel ray here)
+  unsigned long long job_cap;  // its capacity; rays beyond it are walked here
+  int ev_max;                  // events kept per package in the event scratch
+  int ev_k;                    // doubles per event: T of the leg after it, then q per frame
+  double* evs;                 // event scratch [ev_max][ev_k][n_chunk], then q beyond ev_max [n_chunk]
 };
 
 template <typename R>
@@ -153,26 +167,33 @@ MCRT_HD void lane_init(Lane<R>& L) {
 }
 
 // Adjoint bookkeeping of one event (emission or scattering n = L.n): its
-// peel-off contributions sum to G_e.  Pass A sums them into L.Ge while it
-// walks the peel rays and keeps the sum in the event scratch; pass B takes
-// the kept sum and skips the event's peel-offs.  Events beyond the scratch
-// walk their peel rays in both passes.
-// Called once the event's next phase is set: events without peel-off (the
-// flags exclude it) have G_e = 0 and nothing in the scratch.
+// peel-off contributions q sum to G_e.  Pass B takes the q the scratch holds
+// for the event and skips its peel-offs; events beyond the scratch walk
+// their peel rays again.  Called once the event's next phase is set: events
+// without peel-off (the flags exclude it) have G_e = 0.
 template <typename R, class Mem>
 MCRT_HD void event_start(Lane<R>& L, const RunParams& P, Mem& M) {
   L.Ge = 0.0;
   if (L.pass == 1 && L.n < P.ev_max && L.phase == PH_PEEL_NEXT) {
-    L.Ge = M.ev_load(L.slot, L.n, 0);
+    for (int d = 0; d < P.n_det; ++d) L.Ge += M.ev_load(L.slot, L.n, 1 + d);
     L.det = P.n_det;  // no peel-off walks: PEEL_NEXT goes straight on
   }
 }
 
 template <typename R, class Mem>
 MCRT_HD void event_done(Lane<R>& L, const RunParams& P, Mem& M) {
-  if (L.pass == 0 && L.n < P.ev_max) M.ev_store(L.slot, L.n, 0, L.Ge);
   L.Gacc += L.Ge;
   L.Ge = 0.0;
+}
+
+// Pass A keeps q of a walked peel ray for pass B: per frame for the first
+// ev_max events, summed beyond.
+template <typename R, class Mem>
+MCRT_HD void keep_q(Lane<R>& L, const RunParams& P, Mem& M, double q) {
+  if (L.n < P.ev_max)
+    M.ev_store(L.slot, L.n, 1 + L.det, q);
+  else
+    M.ev_add_beyond(L.slot, q);
 }
 
 // Runs the lane's events until its next walk is set up (ry.active) or no
@@ -207,19 +228,12 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
       } else {
         const double ac = M.adj(ii) * C;
         L.Ge += ac;
-        if (L.pass == 0) L.Gabs += fabs(ac);
+        if (L.pass == 0) keep_q(L, P, M, ac);
         if (L.pass == 0 && ac != 0.0) {  // a second walk of the same ray deposits -A C kappa l
           L.fac = -ac * L.kap;
-          unsigned long long slot = ~0ull;
-          if (P.jobs) slot = M.job_slot();
-          if (slot < P.job_cap) {  // queued: walked later, bundled with parallel neighbours
-            M.store_job(slot, L.r, L.fac, tile_key(D, L.pix));
-            ++L.det;
-          } else {
-            want = to_det = true;
-            L.mode = M_PEEL_DEP;
-            L.phase = PH_PEEL_DEP_END;
-          }
+          want = to_det = true;
+          L.mode = M_PEEL_DEP;
+          L.phase = PH_PEEL_DEP_END;
         } else {
           ++L.det;
         }
@@ -233,11 +247,11 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     // -- end of the pass-1 walk: escape and absorption, forced-scattering depth
     if (L.phase == PH_PATH_END) {
       if (ADJ && L.t_kept) {
-        L.T = M.ev_load(L.slot, L.n, 1);
+        L.T = M.ev_load(L.slot, L.n, 0);
         L.t_kept = false;
       } else {
         L.T = (double)L.ry.tau;
-        if (ADJ && L.pass == 0 && L.n < P.ev_max) M.ev_store(L.slot, L.n, 1, L.T);
+        if (ADJ && L.pass == 0 && L.n < P.ev_max) M.ev_store(L.slot, L.n, 0, L.T);
       }
       if (L.T == 0.0) {  // nothing to interact with: the package leaves
         if (L.pass == 0) L.s_esc += L.W;
@@ -293,8 +307,21 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     // -- the next frame whose pixel the event projects into
     if (L.phase == PH_PEEL_NEXT && !want) {
       while (L.det < P.n_det) {
-        L.pix = frame_pixel(M.det(L.det), L.r);
-        if (L.pix >= 0) break;
+        const DetDev& D = M.det(L.det);
+        L.pix = frame_pixel(D, L.r);
+        if (L.pix >= 0) {
+          if (!ADJ || !P.jobs || L.pass != 0) break;
+          const unsigned long long slot = M.job_slot();
+          if (slot >= P.job_cap) break;  // queue full: walk it here
+          // queued: C = v e^-tau is completed by the peel-job kernel
+          const double ph = L.is_emit ? 1.0 / (4.0 * kPi)
+                                      : hg_phase(L.g, L.k[0] * D.kd[0] + L.k[1] * D.kd[1] + L.k[2] * D.kd[2]);
+          const int comp = ((P.flags & kFlagSplit) && !L.is_emit) ? 1 : 0;
+          const long long ii = ((long long)comp * P.n_lambda + L.lam) * P.pix_lambda + D.off + L.pix;
+          M.store_job(slot, L.r, L.W * ph * D.inv_d2, ii, tile_key(D, L.pix), (unsigned)L.slot, L.n, L.det,
+                      (unsigned)L.lam);
+          ++L.n_pl;
+        }
         ++L.det;
       }
       if (L.det < P.n_det) {
@@ -333,25 +360,18 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     }
 
     // -- end of the package: replay it for the adjoint, or take the next one
-    if (L.phase == PH_PKG_END && !want) {
-      if (ADJ && L.pass == 0 && L.Gabs != 0.0) {
-        L.Rtot = L.Gacc;
-        L.Gacc = 0.0;
-        L.pass = 1;
-        L.phase = PH_EMIT;
-      } else {
-        L.phase = PH_FETCH;
-      }
-    }
+    if (L.phase == PH_PKG_END && !want) L.phase = PH_FETCH;
     if (L.phase == PH_FETCH && !want) {
       if ((L.x_path | L.x_loc | L.x_peel | L.n_dep) & 0xC0000000u) {  // keep 32-bit counters from wrapping
         M.flush_counts(L.x_path, L.x_loc, L.x_peel, L.n_dep);
         L.x_path = L.x_loc = L.x_peel = L.n_dep = 0;
       }
-      const unsigned long long item = M.fetch();
-      if (item >= P.n_items) {
+      const unsigned long long k = M.fetch();
+      if (k >= P.n_chunk) {
         L.done = true;
       } else {
+        const unsigned long long item = P.item0 + k;
+        L.slot = (int)k;
         L.lam = (int)(item / P.n_pkg);
         L.pkg = P.first + (item - (unsigned long long)L.lam * P.n_pkg);
         L.lam_cell = (long long)L.lam * G.ncell_pad;
@@ -364,6 +384,24 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
         L.pass = 0;
         L.Gacc = L.Gabs = 0.0;
         L.phase = PH_EMIT;
+        if (ADJ && P.split == 2) {  // pass B: R_1 is the sum of the package's q; none, no replay
+          double R1 = 0.0, Rabs = 0.0;
+          for (int e = 0; e < P.ev_max; ++e)
+            for (int d = 0; d < P.n_det; ++d) {
+              const double q = M.ev_load(L.slot, e, 1 + d);
+              R1 += q;
+              Rabs += fabs(q);
+            }
+          const double qb = M.ev_load_beyond(L.slot);
+          R1 += qb;
+          Rabs += fabs(qb);
+          L.pass = 1;
+          L.Rtot = R1;
+          if (Rabs == 0.0) {
+            L.phase = PH_FETCH;
+            continue;
+          }
+        }
       }
     }
     // -- emission (also the start of the adjoint replay)
@@ -495,11 +533,32 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
 }
 
 // ---------------------------------------------------------------------------
-// Queued adjoint deposit rays.  The walk is the one the inline M_PEEL_DEP
-// mode makes (same setup, same blocks, same segments), without density
-// loads: its deposits w * l do not depend on the densities.  Every deposit
-// goes through M.deposit(cell, v).  bp_step advances the ray by one block
-// and returns its positive-length crossings; bp_walk walks a whole job.
+// Queued adjoint peel rays (the peel-job kernel).  tau_step is the walk the
+// inline M_PEEL mode makes -- same setup, blocks, segments and optical-depth
+// sum -- and bp_step the walk of the inline M_PEEL_DEP mode without density
+// loads (its deposits w l do not depend on the densities); every deposit
+// goes through M.deposit(cell, v).  Each advances the ray by one block and
+// returns its positive-length crossings.
+template <typename R, class Mem>
+MCRT_HD unsigned tau_step(Ray<R>& ry, const GridDev& G, R kap, Mem& M) {
+  WalkBlock<kBlockWalk, R> b;
+  ray_next_block(ry, b, G, M);
+  unsigned n = 0;
+#pragma unroll
+  for (int d = 0; d < kBlockWalk; ++d) {
+    if (d >= b.n) break;
+    R seg = b.tend[d] - ry.t;
+    const bool pos = seg > R(0);
+    seg = pos ? seg : R(0);
+    const R dtau = kap * b.rho[d] * seg;
+    n += pos;
+    ry.tau += dtau;
+    if (pos) ry.t = b.tend[d];
+  }
+  if (b.out) ry.active = false;
+  return n;
+}
+
 template <typename R, class Mem>
 MCRT_HD unsigned bp_step(Ray<R>& ry, const GridDev& G, double w, Mem& M) {
   WalkBlock<kBlockWalk, R> b;
@@ -516,15 +575,6 @@ MCRT_HD unsigned bp_step(Ray<R>& ry, const GridDev& G, double w, Mem& M) {
     }
   }
   if (b.out) ry.active = false;
-  return n;
-}
-
-template <typename R, class Mem>
-MCRT_HD unsigned bp_walk(const GridDev& G, const DetDev& D, const BpJob& J, Mem& M) {
-  Ray<R> ry;
-  ray_begin(ry, G, J.r, D.kd);
-  unsigned n = 0;
-  while (ry.active) n += bp_step<R>(ry, G, J.w, M);
   return n;
 }
 

@@ -50,6 +50,8 @@ class Emu:
             getattr(lib, f).restype = C.c_int
         lib.emu_set_events_kept.argtypes = [C.c_int]
         lib.emu_set_events_kept.restype = None
+        lib.emu_set_chunk_items.argtypes = [C.c_int]
+        lib.emu_set_chunk_items.restype = None
         lib.emu_violation.restype = C.c_char_p
         lib.emu_last_error.restype = C.c_char_p
         self.lib = lib
@@ -85,6 +87,10 @@ class Emu:
         """Events per package the adjoint keeps in its event scratch (the
         library keeps 32); later events are walked again in pass B."""
         self.lib.emu_set_events_kept(int(n))
+
+    def set_chunk_items(self, n):
+        """Packages per adjoint chunk (0: the library's choice)."""
+        self.lib.emu_set_chunk_items(int(n))
 
     def grad(self, prob, adj, wave=WAVE, **overrides):
         pr = B._Problem(prob, **overrides)

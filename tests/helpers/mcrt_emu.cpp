@@ -25,6 +25,7 @@ namespace {
 
 thread_local std::string g_violation;
 int g_events_kept = 32;  // adjoint event scratch per package, as the library keeps
+int g_chunk_items = 0;   // > 0: smaller adjoint chunks than the library's (tests)
 
 struct Violation : std::runtime_error {
   using std::runtime_error::runtime_error;
@@ -114,40 +115,62 @@ struct HostLifeMem {
     grad[i] += v;
   }
   unsigned long long fetch() { return next++; }
-  unsigned long long x_queue = 0;
-  // adjoint deposit queue
-  std::vector<BpJob>* jobs = nullptr;
+  unsigned long long x_queue = 0, d_queue = 0;
+  // adjoint peel-job queue
+  std::vector<PeelJob>* jobs = nullptr;
   unsigned long long job_cap = 0, job_next = 0;
   long long n_keys = 0;
   unsigned long long job_slot() { return job_next++; }
-  // adjoint event scratch [ev_max][2][n_slots]
+  // adjoint event scratch [ev_max][ev_k][n_chunk], then [n_chunk]; T entries
+  // (k = 0) must be written before they are read, q entries start at zero
   std::vector<double>* evs = nullptr;
-  int ev_max = 0, n_slots = 0;
+  int ev_max = 0, ev_k = 0, n_chunk = 0;
   std::vector<unsigned char>* ev_set = nullptr;
+  size_t ev_index(int slot, int e, int k) const {
+    EMU_CHECK(slot >= 0 && slot < n_chunk, "event scratch package", slot, n_chunk);
+    EMU_CHECK(e >= 0 && e < ev_max, "event scratch event", e, ev_max);
+    EMU_CHECK(k >= 0 && k < ev_k, "event scratch entry", k, ev_k);
+    return ((size_t)e * ev_k + k) * n_chunk + slot;
+  }
   double ev_load(int slot, int e, int k) const {
-    EMU_CHECK(slot >= 0 && slot < n_slots, "event scratch lane", slot, n_slots);
-    EMU_CHECK(e >= 0 && e < ev_max && k >= 0 && k < 2, "event scratch entry", e, ev_max);
-    const size_t i = ((size_t)2 * e + k) * n_slots + slot;
-    EMU_CHECK((*ev_set)[i], "event scratch read before write", e, ev_max);
+    const size_t i = ev_index(slot, e, k);
+    if (k == 0) EMU_CHECK((*ev_set)[i], "event scratch read before write", e, ev_max);
     return (*evs)[i];
   }
   void ev_store(int slot, int e, int k, double v) {
-    EMU_CHECK(slot >= 0 && slot < n_slots, "event scratch lane", slot, n_slots);
-    EMU_CHECK(e >= 0 && e < ev_max && k >= 0 && k < 2, "event scratch entry", e, ev_max);
-    const size_t i = ((size_t)2 * e + k) * n_slots + slot;
+    const size_t i = ev_index(slot, e, k);
     (*evs)[i] = v;
     (*ev_set)[i] = 1;
   }
-  void store_job(unsigned long long slot, const double r[3], double w, unsigned key) {
-    EMU_CHECK(jobs != nullptr && slot < job_cap, "deposit queue", slot, job_cap);
-    EMU_CHECK(key < (unsigned long long)n_keys, "tile key", key, n_keys);
-    BpJob& J = (*jobs)[slot];
+  double ev_load_beyond(int slot) const {
+    EMU_CHECK(slot >= 0 && slot < n_chunk, "event scratch package", slot, n_chunk);
+    return (*evs)[(size_t)ev_max * ev_k * n_chunk + slot];
+  }
+  void ev_add_beyond(int slot, double v) {
+    EMU_CHECK(slot >= 0 && slot < n_chunk, "event scratch package", slot, n_chunk);
+    (*evs)[(size_t)ev_max * ev_k * n_chunk + slot] += v;
+  }
+  void store_job(unsigned long long slot, const double r[3], double v, long long ii, unsigned key, unsigned item,
+                 int e, int d, unsigned lam) {
+    EMU_CHECK(jobs != nullptr && slot < job_cap, "peel-job queue", slot, job_cap);
+    EMU_CHECK(key < (unsigned long long)n_keys, "sort key", key, n_keys);
+    EMU_CHECK(ii >= 0 && ii < n_adj, "job image index", ii, n_adj);
+    EMU_CHECK(item < (unsigned)n_chunk, "job package", item, n_chunk);
+    EMU_CHECK(d >= 0 && d < pr.P.n_det, "job frame", d, pr.P.n_det);
+    EMU_CHECK(lam < (unsigned)pr.P.n_lambda, "job wavelength", lam, pr.P.n_lambda);
+    EMU_CHECK(e >= 0 && e < 65536, "job event", e, 65536);
+    PeelJob& J = (*jobs)[slot];
     J.r[0] = r[0];
     J.r[1] = r[1];
     J.r[2] = r[2];
-    J.w = w;
+    J.v = v;
+    J.ii = ii;
     J.key = key;
     J.rank = 0;
+    J.slot = item;
+    J.e = (unsigned short)e;
+    J.d = (unsigned short)d;
+    J.lam = lam;
   }
   void flush_counts(unsigned a, unsigned b, unsigned c, unsigned d) {
     xs[0] += a;
@@ -197,14 +220,18 @@ struct HostBundleMem {
   }
 };
 
-// The library's counting sort of the queue by tile key (count with ranks,
-// exclusive scan, permutation), then the bundled walks key by key.
+// The library's counting sort of the chunk's queue by key (count with
+// ranks, exclusive scan, permutation), then each job in sorted order: the
+// optical-depth walk, q = (dL/dI) C into the event scratch, and for q != 0
+// the deposit walk.  Returns the crossings; `deps` gets the deposits.
 template <typename R>
-unsigned long long emu_bundles(const GridDev& G, const std::vector<DetDev>& det, int n_det, long long n_keys,
-                               std::vector<BpJob>& jobs, unsigned long long n_jobs, std::vector<double>& grad) {
+unsigned long long emu_peel_jobs(HostLifeMem<R>& M, const RunParams& P, std::vector<PeelJob>& jobs,
+                                 unsigned long long n_jobs, std::vector<double>& grad, unsigned long long& deps,
+                                 long long cap_steps) {
+  const long long n_keys = M.n_keys;
   std::vector<unsigned> kcount(n_keys, 0), kstart(n_keys + 1, 0), perm(n_jobs, 0);
   for (unsigned long long j = 0; j < n_jobs; ++j) {
-    EMU_CHECK(jobs[j].key < (unsigned long long)n_keys, "tile key", jobs[j].key, n_keys);
+    EMU_CHECK(jobs[j].key < (unsigned long long)n_keys, "sort key", jobs[j].key, n_keys);
     jobs[j].rank = kcount[jobs[j].key]++;
   }
   for (long long k = 0; k < n_keys; ++k) kstart[k + 1] = kstart[k] + kcount[k];
@@ -213,12 +240,37 @@ unsigned long long emu_bundles(const GridDev& G, const std::vector<DetDev>& det,
     EMU_CHECK(q < n_jobs, "sorted queue", q, n_jobs);
     perm[q] = (unsigned)j;
   }
-  HostBundleMem M{G, grad};
+  HostBundleMem D{P.G, grad};
   unsigned long long nx = 0;
-  for (long long key = 0; key < n_keys; ++key) {
+  deps = 0;
+  for (unsigned long long qi = 0; qi < n_jobs; ++qi) {
+    const PeelJob& J = jobs[perm[qi]];
     int d = 0;
-    while (d + 1 < n_det && (long long)det[d + 1].key_off <= key) ++d;
-    for (unsigned q = kstart[key]; q < kstart[key + 1]; ++q) nx += bp_walk<R>(G, det[d], jobs[perm[q]], M);
+    while (d + 1 < P.n_det && (unsigned)M.det(d + 1).key_off <= J.key) ++d;
+    EMU_CHECK(d == J.d, "job frame against its key", J.d, P.n_det);
+    Ray<R> ry;
+    ray_begin(ry, P.G, J.r, M.det(d).kd);
+    const R kap = (R)M.lam((int)J.lam).kappa;
+    long long steps = 0;
+    while (ry.active) {
+      nx += tau_step<R>(ry, P.G, kap, M);
+      if (++steps > cap_steps) throw Violation("a peel-job walk exceeded the grid's crossing bound");
+    }
+    const double q = M.adj(J.ii) * (J.v * exp(-(double)ry.tau));
+    if (J.e < P.ev_max)
+      M.ev_store((int)J.slot, J.e, 1 + J.d, q);
+    else
+      M.ev_add_beyond((int)J.slot, q);
+    if (q == 0.0) continue;
+    const double w = -q * M.lam((int)J.lam).kappa;
+    ray_begin(ry, P.G, J.r, M.det(d).kd);
+    steps = 0;
+    while (ry.active) {
+      const unsigned n = bp_step<R>(ry, P.G, w, D);
+      nx += n;
+      deps += n;
+      if (++steps > cap_steps) throw Violation("a deposit walk exceeded the grid's crossing bound");
+    }
   }
   return nx;
 }
@@ -246,56 +298,23 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
                    (long long)abs_b.size(), adj, n_adj, grad_b.data(), (long long)grad_b.size()};
   P.absorbed = M.absorbed;
   if (images && !ADJ) std::fill(images, images + n_images, 0.0);
-  std::vector<BpJob> jobs;
   const bool peel = (opts->flags & (MCRT_PEEL_EMIT | MCRT_PEEL_SCAT)) && n_det > 0;
-  if (ADJ && peel && opts->deposit_queue != -1) {
-    unsigned long long cap = opts->deposit_queue > 0 ? (unsigned long long)opts->deposit_queue
-                                                     : P.n_items * (unsigned long long)P.n_det * 8ull;
-    if (opts->deposit_queue == 0) cap = std::min(std::max(cap, 1ull << 16), 1ull << 28);
-    jobs.resize(cap);
-    M.jobs = &jobs;
-    M.job_cap = cap;
-    M.n_keys = pr.n_keys;
-    P.jobs = jobs.data();
-    P.job_cap = cap;
-  }
-  std::vector<double> evs;
-  std::vector<unsigned char> ev_set;
-  if (ADJ) {
-    P.ev_max = g_events_kept;
-    P.n_slots = (unsigned long long)wave;
-    evs.assign((size_t)2 * P.ev_max * wave, 0.0);
-    ev_set.assign(evs.size(), 0);
-    M.evs = &evs;
-    M.ev_set = &ev_set;
-    M.ev_max = P.ev_max;
-    M.n_slots = wave;
-  }
-  std::vector<Lane<R>> lanes(wave);
-  for (int i = 0; i < wave; ++i) {
-    lane_init(lanes[i]);
-    lanes[i].slot = i;
-  }
   const long long cap = (long long)P.G.n[0] + P.G.n[1] + P.G.n[2] + 8;
-  run_wave(
-      lanes, P.batch, [&](Lane<R>& L) { lane_events<R, ADJ>(L, P, M); },
-      [&](Lane<R>& L) {
-        WalkDeposits dep;
-        lane_step<R, ADJ>(L, P, M, dep);
-        apply_deposits(dep, M);
-      },
-      cap, 0);
-  if (P.jobs) {
-    const unsigned long long nx =
-        emu_bundles<R>(P.G, pr.det, P.n_det, pr.n_keys, jobs, std::min(M.job_next, M.job_cap), grad_b);
-    M.xs[2] += nx;
-    M.xs[6] += nx;
-    M.x_queue = nx;
-  }
-  if (P.absorbed) unbrick(P.G, abs_b, absorbed, P.n_lambda);
-  if (ADJ && grad) unbrick(P.G, grad_b, grad, 1);
-  if (stats) {
-    double sa = 0, se = 0, st = 0;
+  double sa = 0, se = 0, st = 0;
+  // one launch of the life-cycle kernel: fresh lanes, then their statistics
+  auto launch = [&](int split) {
+    P.split = split;
+    M.next = 0;
+    std::vector<Lane<R>> lanes(wave);
+    for (auto& L : lanes) lane_init(L);
+    run_wave(
+        lanes, P.batch, [&](Lane<R>& L) { lane_events<R, ADJ>(L, P, M); },
+        [&](Lane<R>& L) {
+          WalkDeposits dep;
+          lane_step<R, ADJ>(L, P, M, dep);
+          apply_deposits(dep, M);
+        },
+        cap, 0);
     for (auto& L : lanes) {
       sa += L.s_abs;
       se += L.s_esc;
@@ -308,6 +327,61 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
       M.xs[5] += L.n_pl;
       M.xs[6] += L.n_dep;
     }
+  };
+  if (!ADJ) {
+    P.item0 = 0;
+    P.n_chunk = P.n_items;
+    launch(0);
+  } else {
+    // chunks of packages as the library runs them (the library's chunk holds
+    // about 1 GiB of event scratch; g_chunk_items overrides for tests)
+    P.ev_max = g_events_kept;
+    P.ev_k = 1 + P.n_det;
+    const size_t per_item = sizeof(double) * ((size_t)P.ev_max * P.ev_k + 1);
+    unsigned long long chunk = std::min<unsigned long long>(
+        P.n_items, std::max<size_t>(1 << 16, (size_t(1) << 30) / per_item));
+    if (g_chunk_items > 0) chunk = std::min<unsigned long long>(chunk, (unsigned long long)g_chunk_items);
+    std::vector<PeelJob> jobs;
+    if (peel && opts->deposit_queue != -1) {
+      unsigned long long qcap = opts->deposit_queue > 0 ? (unsigned long long)opts->deposit_queue
+                                                        : chunk * (unsigned long long)P.n_det * 8ull;
+      if (opts->deposit_queue == 0) qcap = std::min(std::max(qcap, 1ull << 16), 1ull << 28);
+      jobs.resize(qcap);
+      M.jobs = &jobs;
+      M.job_cap = qcap;
+      M.n_keys = pr.n_keys;
+      P.jobs = jobs.data();
+      P.job_cap = qcap;
+    }
+    std::vector<double> evs;
+    std::vector<unsigned char> ev_set;
+    M.evs = &evs;
+    M.ev_set = &ev_set;
+    M.ev_max = P.ev_max;
+    M.ev_k = P.ev_k;
+    for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
+      P.item0 = c0;
+      P.n_chunk = std::min(chunk, P.n_items - c0);
+      M.n_chunk = (int)P.n_chunk;
+      evs.assign((size_t)P.n_chunk * ((size_t)P.ev_max * P.ev_k + 1), 0.0);
+      ev_set.assign(evs.size(), 0);
+      M.job_next = 0;
+      launch(1);  // pass A
+      if (P.jobs) {
+        unsigned long long deps = 0;
+        const unsigned long long nx =
+            emu_peel_jobs<R>(M, P, jobs, std::min(M.job_next, M.job_cap), grad_b, deps, cap);
+        M.x_queue += nx;
+        M.d_queue += deps;
+      }
+      launch(2);  // pass B
+    }
+    M.xs[2] += M.x_queue;
+    M.xs[6] += M.d_queue;
+  }
+  if (P.absorbed) unbrick(P.G, abs_b, absorbed, P.n_lambda);
+  if (ADJ && grad) unbrick(P.G, grad_b, grad, 1);
+  if (stats) {
     stats->emitted = pr.emitted;
     stats->absorbed = sa;
     stats->escaped = se;
@@ -322,6 +396,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
     stats->kernel_ms = 0.0;
     stats->x_queue = M.x_queue;
     stats->life_ms = stats->queue_ms = 0.0;
+    stats->d_queue = M.d_queue;
   }
   return 0;
 }
@@ -480,6 +555,7 @@ extern "C" {
 
 const char* emu_violation(void) { return g_violation.c_str(); }
 void emu_set_events_kept(int n) { g_events_kept = n; }
+void emu_set_chunk_items(int n) { g_chunk_items = n; }
 const char* emu_last_error(void) { return host::last_error().c_str(); }
 
 int emu_run_photons(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, int n_src,

@@ -50,9 +50,9 @@ def test_library_exports_every_declared_function(lib, B):
     assert set(B.SYMBOLS) == set(_declared_functions())
 
 
-def test_abi_version(lib):
+def test_abi_version(lib, B):
     m = re.search(r"#define\s+MCRT_ABI_VERSION\s+(\d+)", open(HEADER).read())
-    assert lib.mcrt_abi_version() == int(m.group(1))
+    assert lib.mcrt_abi_version() == int(m.group(1)) == B.ABI_VERSION
 
 
 def test_struct_layouts_match_the_c_compiler(B, tmp_path):

@@ -263,6 +263,11 @@ def test_backward_deposit_queue_modes(E, orc, W, prec):
     for q in (-1, 0, 7, 100000):
         g, st = E.grad(prob, adj, deposit_queue=q)
         assert rel_l1(g, g_o) < (1e-9 if prec == 0 else 1e-5), (q, rel_l1(g, g_o))
+        if q == -1:
+            assert st["x_queue"] == 0 and st["d_queue"] == 0
+        else:  # queued rays: an optical-depth walk each, a deposit walk when q != 0
+            assert 0 < st["d_queue"] <= st["x_queue"] - st["d_queue"]
+            assert st["d_queue"] <= st["deposits"]
         if ref is None:
             ref = (g, st)
             continue
@@ -292,3 +297,27 @@ def test_backward_event_scratch_sizes(E, orc, W, kept):
     g1_o, _, _ = orc.grad(dict(prob, flags=W.FLAG_PEEL_SCAT), adj)
     assert rel_l1(g, g_o) < 1e-9, rel_l1(g, g_o)
     assert rel_l1(g1, g1_o) < 1e-9, rel_l1(g1, g1_o)
+
+
+@pytest.mark.parametrize("queue", [-1, 0, 50])
+def test_backward_in_chunks(E, orc, W, queue):
+    """The adjoint runs on chunks of packages (pass A, peel jobs, pass B per
+    chunk): chunks of 97 packages, with and without the peel-job queue, give
+    the unchunked gradient and the oracle's."""
+    n = (9, 9, 8)
+    prob = W.small_problem(n=n, rho=W.lognormal_density(n, 0.7, seed=47), kappa=1.2, albedo=0.7, g=0.5,
+                           detectors=[W.frame(10.0, 25.0, 18, 18, 1.2, 1.2), W.frame(10.0, 80.0, 14, 16, 1.2, 1.2)],
+                           n_packages=700, flags=W.FLAG_PEEL_EMIT | W.FLAG_PEEL_SCAT | W.FLAG_SPLIT)
+    img_o, _, _ = orc.run(prob)
+    adj = np.random.default_rng(4).standard_normal(img_o.shape)
+    g_o, _, _ = orc.grad(prob, adj)
+    g_full, st_full = E.grad(prob, adj, deposit_queue=queue)
+    try:
+        E.set_chunk_items(97)
+        g, st = E.grad(prob, adj, deposit_queue=queue)
+    finally:
+        E.set_chunk_items(0)
+    assert rel_l1(g, g_o) < 1e-9 and rel_l1(g_full, g_o) < 1e-9
+    assert rel_l1(g, g_full) < 1e-12
+    for key in ("x_path", "x_locate", "x_peel", "deposits", "events", "packages", "peels"):
+        assert st[key] == st_full[key], key

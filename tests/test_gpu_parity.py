@@ -307,6 +307,11 @@ def test_backward_deposit_queue_modes(B, orc, W):
         e = rel_l1(g, g_o)
         _say("  queue %d: rel_L1 grad %.3e" % (q, e))
         assert e < 1e-9, (q, e)
+        if q == -1:
+            assert st["x_queue"] == 0 and st["d_queue"] == 0
+        else:  # queued rays: an optical-depth walk each, a deposit walk when q != 0
+            assert 0 < st["d_queue"] <= st["x_queue"] - st["d_queue"]
+            assert st["d_queue"] <= st["deposits"]
         if ref is None:
             ref = st
         for key in ("x_path", "x_locate", "x_peel", "deposits", "events", "peels", "packages"):
