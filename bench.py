@@ -54,7 +54,8 @@ COPY_BYTES = 1 << 30
 KERNELS = {
     "forward": "void mcrt::k_life<float, false>(mcrt::RunParams)",
     "adjoint": "void mcrt::k_life<float, true>(mcrt::RunParams)",
-    "bundle": "void mcrt::k_bundle<float>(mcrt::BundleParams)",
+    "peel_tau": "void mcrt::k_peeltau<float>(mcrt::PeelJobParams)",
+    "peel_deposit": "void mcrt::k_peeldep<float>(mcrt::PeelJobParams)",
     "trace": "void mcrt::k_trace<float>(mcrt::TraceParams)",
 }
 

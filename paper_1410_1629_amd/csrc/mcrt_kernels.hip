@@ -434,8 +434,8 @@ __global__ void k_perm(const PeelJob* __restrict__ jobs, const unsigned long lon
 }
 
 constexpr int kBundleThreads = 512;
-constexpr int kTableBits = 13, kTable = 1 << kTableBits, kProbes = 4;
-constexpr unsigned kChunk = 2048;
+constexpr int kTableBits = 12, kTable = 1 << kTableBits, kProbes = 4;
+constexpr unsigned kChunk = 1024;
 
 struct PeelJobParams {
   GridDev G;
@@ -836,9 +836,10 @@ int launch_life(const RunParams& P, int nblk, hipStream_t st) {
 }
 
 // Events per package kept in the adjoint's event scratch (more are walked
-// again in pass B), and the scratch size that bounds a chunk of packages.
+// again in pass B), and the scratch size that bounds a chunk of packages (at
+// most a quarter of the free device memory).
 constexpr int kEventsKept = 32;
-constexpr size_t kScratchBytes = size_t(1) << 30;
+constexpr size_t kScratchBytes = size_t(1) << 32;
 
 // Shared driver of run_photons and backward_density.
 int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
@@ -872,8 +873,15 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   // package, T and q per frame for kEventsKept events plus the sum of q beyond
   const int ev_k = 1 + n_det;
   const size_t per_item = sizeof(double) * ((size_t)kEventsKept * ev_k + 1);
-  const unsigned long long chunk =
-      adjoint ? std::min<unsigned long long>(P.n_items, std::max<size_t>(1 << 16, kScratchBytes / per_item)) : 0;
+  unsigned long long chunk = 0;
+  if (adjoint) {  // equal chunks, each within the scratch budget
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    const unsigned long long most =
+        std::min<unsigned long long>(P.n_items, std::max<size_t>(1 << 16, std::min(kScratchBytes, free_b / 4) / per_item));
+    const unsigned long long n_chunks = (P.n_items + most - 1) / most;
+    chunk = (P.n_items + n_chunks - 1) / n_chunks;
+  }
   const size_t n_evs = adjoint ? (size_t)chunk * ((size_t)kEventsKept * ev_k + 1) : 0;
   const long long n_tally = adjoint ? (long long)P.G.ncell_pad : (P.absorbed ? (long long)nl * P.G.ncell_pad : 0);
   const size_t off_lam = 0;
