@@ -122,7 +122,7 @@ typedef struct {
  * brick of the library's internal cell layout, MCRT_BRICK(lx, ly, lz) for
  * bricks of 2^lx x 2^ly x 2^lz cells (each log2 in [0, 7], at most 2^10
  * cells).  The default brick fills one 128-byte cache line with the most
- * compact block of cells in physical units.  deposit_queue (backward_density
+ * compact block of cells in physical units.  peel_queue (backward_density
  * only) caps the device queue of peel rays, in rays per chunk of packages (at
  * most 2^31): 0 = library choice, -1 = no queue (every peel ray is walked
  * inline, its deposits with global atomics); rays beyond the cap are walked
@@ -138,7 +138,7 @@ typedef struct {
     uint32_t flags;
     int32_t launch_blocks, event_batch;
     int32_t brick_shape;
-    int64_t deposit_queue;
+    int64_t peel_queue;
 } mcrt_opts;
 
 #define MCRT_BRICK(lx, ly, lz) (0x1000 | (lx) | ((ly) << 4) | ((lz) << 8))
@@ -234,7 +234,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 5
+#define MCRT_ABI_VERSION 6
 
 #ifdef __cplusplus
 }

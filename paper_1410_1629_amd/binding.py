@@ -53,7 +53,7 @@ class Opts(C.Structure):
     _fields_ = [("n_packages", C.c_uint64), ("first_package", C.c_uint64), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("w_min", C.c_double), ("max_scatter", C.c_int32),
                 ("flags", C.c_uint32), ("launch_blocks", C.c_int32), ("event_batch", C.c_int32),
-                ("brick_shape", C.c_int32), ("deposit_queue", C.c_int64)]
+                ("brick_shape", C.c_int32), ("peel_queue", C.c_int64)]
 
 
 def brick(lx, ly, lz):
@@ -76,7 +76,7 @@ class Stats(C.Structure):
 _lib = None
 
 # Exported symbols of include/mcrt.h.
-ABI_VERSION = 5  # MCRT_ABI_VERSION of the header these structs follow
+ABI_VERSION = 6  # MCRT_ABI_VERSION of the header these structs follow
 SYMBOLS = ("run_photons", "trace_path", "peel_off", "backward_density", "mcrt_last_error", "mcrt_abi_version")
 
 
@@ -171,11 +171,11 @@ class _Problem:
         o = dict(n_packages=prob["n_packages"], first_package=prob.get("first_package", 0),
                  seed=prob.get("seed", 4357), precision=prob.get("precision", 0), w_min=prob.get("w_min", 1e-4),
                  max_scatter=prob.get("max_scatter", 1000), flags=prob.get("flags", 7), launch_blocks=0,
-                 event_batch=0, brick_shape=0, deposit_queue=0)
+                 event_batch=0, brick_shape=0, peel_queue=0)
         o.update(overrides)
         self.opts = Opts(int(o["n_packages"]), int(o["first_package"]), int(o["seed"]), int(o["precision"]),
                          float(o["w_min"]), int(o["max_scatter"]), int(o["flags"]), int(o["launch_blocks"]),
-                         int(o["event_batch"]), int(o["brick_shape"]), int(o["deposit_queue"]))
+                         int(o["event_batch"]), int(o["brick_shape"]), int(o["peel_queue"]))
 
 
 def image_shape(prob):

@@ -90,12 +90,13 @@ struct DetDev {
   double inv_d2, half_x, half_y, inv_dpx, inv_dpy;  // pixels per unit length
   int nx, ny;
   long long off;  // offset of this frame inside one wavelength's image block
-  // Sort keys of the adjoint's deposit rays: the pixel (coarsened to
-  // 2^tshift x 2^tshift blocks on very large frames) in Morton order,
-  // numbered from key_off.  Rays of one frame whose keys are close land
-  // close together in the image, so they are parallel rays a few cells
-  // apart that cross one narrow bundle of cells.
-  int tshift, key_off;
+  // Sort keys of queued peel rays: the tile of 2^tshift x 2^tshift pixels
+  // in Morton order, numbered from key_off, then the pixel's Morton index
+  // inside its tile (shifted right by sub_shift to at most 8 bits).  Rays of
+  // one frame whose keys are close land close together in the image, so
+  // they are parallel rays a few cells apart that cross one narrow bundle of
+  // cells.
+  int tshift, key_off, sub_shift;
 };
 
 // Interleaves the low 16 bits of x (even bits) and y (odd bits).
@@ -116,6 +117,13 @@ MCRT_HD unsigned morton2(unsigned x, unsigned y) {
 MCRT_HD unsigned tile_key(const DetDev& D, int pix) {
   const int iy = pix / D.nx, ix = pix - iy * D.nx;
   return (unsigned)D.key_off + morton2((unsigned)ix >> D.tshift, (unsigned)iy >> D.tshift);
+}
+
+// Second sort key of pixel `pix`: its place inside its tile.
+MCRT_HD unsigned tile_sub(const DetDev& D, int pix) {
+  const int iy = pix / D.nx, ix = pix - iy * D.nx;
+  const unsigned m = (1u << D.tshift) - 1u;
+  return morton2((unsigned)ix & m, (unsigned)iy & m) >> D.sub_shift;
 }
 
 struct SrcDev {

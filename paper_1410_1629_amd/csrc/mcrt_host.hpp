@@ -174,21 +174,31 @@ inline DetDev make_det(const mcrt_detector& D, long long off) {
   R.off = off;
   R.tshift = 0;
   R.key_off = 0;
+  R.sub_shift = 0;
   return R;
 }
 
-// Sort-key ranges of the frames (tile_key): a Morton index over the pixels,
-// or over 2^tshift-pixel blocks when a frame would need more than 2^22
-// keys.  Returns the total number of keys.
+// Sort keys of the peel-ray queue, over all frames (the sort keeps one
+// counter per key in LDS), and the parts the sort cuts the queue into.
+constexpr long long kSortKeys = 1 << 14;
+constexpr int kSortBlocks = 512;
+
+// Sort-key ranges of the frames (tile_key): a Morton index over tiles of
+// 2^tshift x 2^tshift pixels, the frames sharing kSortKeys keys (a power of
+// 4 per frame).  Returns the total number of keys.
 inline long long tile_frames(std::vector<DetDev>& det, int n_det) {
+  if (n_det <= 0) return 0;
+  int bits = 0;  // key bits per frame: even, with n_det << bits <= kSortKeys
+  while ((static_cast<long long>(n_det) << (bits + 2)) <= kSortKeys) bits += 2;
   long long keys = 0;
   for (int d = 0; d < n_det; ++d) {
     DetDev& D = det[d];
     int k = 0;
     while ((1 << k) < std::max(D.nx, D.ny)) ++k;
     int ts = 0;
-    while (2 * (k - ts) > 22) ++ts;
+    while (2 * (k - ts) > bits) ++ts;
     D.tshift = ts;
+    D.sub_shift = std::max(0, 2 * ts - 8);
     D.key_off = (int)keys;
     keys += 1ll << (2 * (k - ts));
   }
@@ -248,8 +258,8 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
   if (opts->flags & ~15u) return fail(MCRT_EINVAL, "unknown flag bits 0x%x", opts->flags);
   if (opts->launch_blocks < 0 || opts->launch_blocks > 64) return fail(MCRT_EINVAL, "launch_blocks outside [0, 64]");
   if (opts->event_batch < 0 || opts->event_batch > 64) return fail(MCRT_EINVAL, "event_batch outside [0, 64]");
-  if (opts->deposit_queue < -1 || opts->deposit_queue > (1ll << 31))
-    return fail(MCRT_EINVAL, "deposit_queue outside [-1, 2^31]");
+  if (opts->peel_queue < -1 || opts->peel_queue > (1ll << 31))
+    return fail(MCRT_EINVAL, "peel_queue outside [-1, 2^31]");
 
   RunParams& P = out.P;
   std::memset(&P, 0, sizeof P);

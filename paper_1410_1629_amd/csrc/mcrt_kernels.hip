@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "mcrt.h"
@@ -167,7 +168,7 @@ struct LifeMem {
     atomic_add_f64(P.evs + (size_t)P.ev_max * P.ev_k * P.n_chunk + slot, v);
   }
   __device__ void store_job(unsigned long long slot, const double r[3], double v, long long ii, unsigned key,
-                            unsigned item, int e, int d, unsigned lam) const {
+                            unsigned sub, unsigned item, int e, int d, unsigned lam) const {
     PeelJob& J = P.jobs[slot];
     J.r[0] = r[0];
     J.r[1] = r[1];
@@ -175,11 +176,11 @@ struct LifeMem {
     J.v = v;
     J.ii = ii;
     J.key = key;
-    J.rank = 0;
     J.slot = item;
-    J.e = (unsigned short)e;
-    J.d = (unsigned short)d;
     J.lam = lam;
+    J.e = (unsigned short)e;
+    J.d = (unsigned char)d;
+    J.sub = (unsigned char)sub;
   }
   __device__ void flush_counts(unsigned a, unsigned b, unsigned c, unsigned d) const {
     atomicAdd(P.xstats + 0, (unsigned long long)a);
@@ -235,8 +236,11 @@ struct PeelMem {
 // ---------------------------------------------------------------------------
 // Kernels.
 
+// The life-cycle kernel body; k_life (FP32 walk) and k_life64 (FP64 walk)
+// launch it.  The FP64 kernel asks for two wavefronts per SIMD, which its
+// register use would otherwise just miss.
 template <typename R, bool ADJ>
-__global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
+__device__ __forceinline__ void life_body(const RunParams& P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2], job_slots[kWavesPerBlock][2];
   __shared__ long long dep_idx[kWavesPerBlock][64 * kBlockWalk];
   __shared__ double dep_val[kWavesPerBlock][64 * kBlockWalk];
@@ -258,7 +262,7 @@ __global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
       if (!ADJ && __ballot(dep.on != 0u)) flush_deposits(dep, P.absorbed, dep_idx[wave], dep_val[wave]);
     }
   }
-  if (ADJ && P.jobs) {  // unfilled reserved queue slots
+  if (P.jobs) {  // unfilled reserved queue slots
     const unsigned long long lo = M.job_res[0], hi = M.job_res[1] < P.job_cap ? M.job_res[1] : P.job_cap;
     for (unsigned long long q = lo + __lane_id(); q < hi; q += 64) P.jobs[q].key = kNoKey;
   }
@@ -278,6 +282,16 @@ __global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
     atomicAdd(P.xstats + 5, a5);
     atomicAdd(P.xstats + 6, a6);
   }
+}
+
+template <typename R, bool ADJ>
+__global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
+  life_body<R, ADJ>(P);
+}
+
+template <bool ADJ>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_life64(const RunParams P) {
+  life_body<double, ADJ>(P);
 }
 
 template <typename R>
@@ -324,20 +338,22 @@ __global__ void __launch_bounds__(kBlock) k_peel(const PeelParams P) {
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint peel rays, walked in bundles.  Pass A queues each peel ray of each
-// event (origin, W Phi / D^2, pixel, frame).  A counting sort by key
-// (k_count, k_scan, k_perm) orders the queue by frame and by pixel in Morton
-// order, so any run of consecutive sorted rays is a compact patch of one
-// frame: parallel rays a few cells apart that cross one narrow bundle of
-// cells.  k_peeltau walks each ray once for its optical depth, which gives
-// C and q = (dL/dI) C (kept for pass B); k_peeldep hands runs of sorted rays
-// (chunks) to workgroups and walks each ray with q != 0 once more, without
-// density loads, to deposit -q kappa l; the deposits are summed per cell in
-// an LDS hash table and each distinct cell goes to the gradient with one
-// global atomic.
-// Global atomics execute at the memory side at a fixed request rate, so this
-// replaces one atomic per crossing by about one per cell and chunk; and the
-// walks run in a lean kernel, on rays whose neighbours read the same lines.
+// Queued peel rays.  The life kernel of the forward run and pass A of the
+// adjoint queue each peel ray of each event (origin, W Phi / D^2, pixel,
+// frame) instead of walking it.  A counting sort by key (k_hist, a scan,
+// k_scatter) orders the queue by frame and by image tile in Morton order, so
+// any run of consecutive sorted rays is a compact patch of one frame:
+// parallel rays a few cells apart that cross one narrow bundle of cells.
+// k_peeltau walks each ray once for its optical depth, in a lean kernel with
+// many waves per SIMD whose neighbouring lanes read the same lines, and adds
+// C = v e^-tau to its pixel (forward) or keeps q = (dL/dI) C for pass B
+// (adjoint).  In the adjoint, k_peeldep hands runs of sorted rays (chunks)
+// to workgroups and walks each ray with q != 0 once more, without density
+// loads, to deposit -q kappa l; the deposits are summed per cell in an LDS
+// hash table and each distinct cell goes to the gradient with one global
+// atomic.  Global atomics execute at the memory side at a fixed request
+// rate, so this replaces one atomic per crossing by about one per cell and
+// chunk.
 
 // Queue slots handed out (the counter may have run past the capacity).
 __device__ __forceinline__ unsigned long long queued_jobs(const unsigned long long* ctr, unsigned long long cap) {
@@ -345,17 +361,64 @@ __device__ __forceinline__ unsigned long long queued_jobs(const unsigned long lo
   return n < cap ? n : cap;
 }
 
-__global__ void k_count(PeelJob* __restrict__ jobs, const unsigned long long* __restrict__ ctr,
-                        unsigned long long cap, unsigned* __restrict__ kcount) {
-  const unsigned long long n = queued_jobs(ctr, cap);
-  for (unsigned long long j = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; j < n;
-       j += (unsigned long long)gridDim.x * blockDim.x) {
+// The sort cuts the queue into kSortBlocks equal parts, one per workgroup.
+// k_hist counts each part's tile keys in LDS and writes the counts to
+// column b of the key-major matrix counts[key][kSortBlocks]; the exclusive
+// scan of that matrix gives each (key, part) its first sorted position;
+// k_scatter starts an LDS counter per key there and hands positions out to
+// the part's rays, writing each ray's index and second key.  k_refine then
+// sorts each tile's run by the second key (the pixel inside the tile), one
+// workgroup per tile, the same way.  Slots a wavefront reserved but did not
+// fill (kNoKey) are skipped.  No global atomics: LDS counters do the
+// ranking; the order of rays with equal keys is arbitrary.
+constexpr int kSortThreads = 1024, kSortBlocks = host::kSortBlocks, kRefineThreads = 256, kSubKeys = 256;
+
+__device__ __forceinline__ void sort_part(unsigned long long n, unsigned long long& lo, unsigned long long& hi) {
+  const unsigned long long per = (n + kSortBlocks - 1) / kSortBlocks;
+  lo = blockIdx.x * per;
+  hi = lo + per < n ? lo + per : n;
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_hist(const PeelJob* __restrict__ jobs,
+                                                       const unsigned long long* __restrict__ ctr,
+                                                       unsigned long long cap, int n_keys,
+                                                       unsigned* __restrict__ counts) {
+  __shared__ unsigned h[host::kSortKeys];
+  for (int i = threadIdx.x; i < n_keys; i += kSortThreads) h[i] = 0u;
+  __syncthreads();
+  unsigned long long lo, hi;
+  sort_part(queued_jobs(ctr, cap), lo, hi);
+  for (unsigned long long j = lo + threadIdx.x; j < hi; j += kSortThreads) {
     const unsigned key = jobs[j].key;
-    if (key != kNoKey) jobs[j].rank = atomicAdd(kcount + key, 1u);
+    if (key != kNoKey) atomicAdd(h + key, 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_keys; i += kSortThreads) counts[(size_t)i * kSortBlocks + blockIdx.x] = h[i];
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_scatter(const PeelJob* __restrict__ jobs,
+                                                          const unsigned long long* __restrict__ ctr,
+                                                          unsigned long long cap, int n_keys,
+                                                          const unsigned* __restrict__ starts,
+                                                          unsigned* __restrict__ idx, unsigned char* __restrict__ subs) {
+  __shared__ unsigned h[host::kSortKeys];
+  for (int i = threadIdx.x; i < n_keys; i += kSortThreads) h[i] = starts[(size_t)i * kSortBlocks + blockIdx.x];
+  __syncthreads();
+  unsigned long long lo, hi;
+  sort_part(queued_jobs(ctr, cap), lo, hi);
+  for (unsigned long long j = lo + threadIdx.x; j < hi; j += kSortThreads) {
+    const PeelJob& J = jobs[j];
+    const unsigned key = J.key;
+    if (key != kNoKey) {
+      const unsigned q = atomicAdd(h + key, 1u);
+      idx[q] = (unsigned)j;
+      subs[q] = J.sub;
+    }
   }
 }
 
-// Exclusive scan of kcount[0, n) into kstart[0, n] in three launches:
+// Exclusive scan of counts[0, n) into starts[0, n] (the total in starts[n])
+// in three launches:
 // k_scan_tiles scans tiles of kScanTile counts within each block and writes
 // the tile totals, k_scan_top scans the totals in one block, k_scan_add adds
 // each tile's offset.
@@ -377,29 +440,29 @@ __device__ __forceinline__ unsigned block_exclusive_scan(unsigned v, unsigned* l
   return incl - v;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const unsigned* __restrict__ kcount,
-                                                             unsigned* __restrict__ kstart, unsigned* __restrict__ tiles,
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const unsigned* __restrict__ counts,
+                                                             unsigned* __restrict__ starts, unsigned* __restrict__ tiles,
                                                              long long n) {
   __shared__ unsigned lds[kScanThreads];
   const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanPer;
   unsigned v[kScanPer], s = 0;
 #pragma unroll
   for (int i = 0; i < kScanPer; ++i) {
-    v[i] = base + i < n ? kcount[base + i] : 0u;
+    v[i] = base + i < n ? counts[base + i] : 0u;
     s += v[i];
   }
   unsigned total;
   unsigned run = block_exclusive_scan(s, lds, &total);
 #pragma unroll
   for (int i = 0; i < kScanPer; ++i) {
-    if (base + i < n) kstart[base + i] = run;
+    if (base + i < n) starts[base + i] = run;
     run += v[i];
   }
   if (threadIdx.x == 0) tiles[blockIdx.x] = total;
 }
 
 __global__ void __launch_bounds__(kTopThreads) k_scan_top(unsigned* __restrict__ tiles, long long n_tiles,
-                                                          unsigned* __restrict__ kstart, long long n) {
+                                                          unsigned* __restrict__ starts, long long n) {
   __shared__ unsigned lds[kTopThreads];
   const long long per = (n_tiles + kTopThreads - 1) / kTopThreads;
   const long long lo = threadIdx.x * per, hi = lo + per < n_tiles ? lo + per : n_tiles;
@@ -412,25 +475,40 @@ __global__ void __launch_bounds__(kTopThreads) k_scan_top(unsigned* __restrict__
     tiles[i] = run;
     run += t;
   }
-  if (threadIdx.x == 0) kstart[n] = total;
+  if (threadIdx.x == 0) starts[n] = total;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_add(unsigned* __restrict__ kstart,
+__global__ void __launch_bounds__(kScanThreads) k_scan_add(unsigned* __restrict__ starts,
                                                            const unsigned* __restrict__ tiles, long long n) {
   const long long base = (long long)blockIdx.x * kScanTile;
   const unsigned off = tiles[blockIdx.x];
   for (int i = threadIdx.x; i < kScanTile; i += kScanThreads)
-    if (base + i < n) kstart[base + i] += off;
+    if (base + i < n) starts[base + i] += off;
 }
 
-__global__ void k_perm(const PeelJob* __restrict__ jobs, const unsigned long long* __restrict__ ctr,
-                       unsigned long long cap, const unsigned* __restrict__ kstart, unsigned* __restrict__ perm) {
-  const unsigned long long n = queued_jobs(ctr, cap);
-  for (unsigned long long j = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; j < n;
-       j += (unsigned long long)gridDim.x * blockDim.x) {
-    const unsigned key = jobs[j].key;
-    if (key != kNoKey) perm[kstart[key] + jobs[j].rank] = (unsigned)j;
+// Workgroup k sorts the run [starts of key k, starts of key k + 1) of idx
+// by subs into perm.
+__global__ void __launch_bounds__(kRefineThreads) k_refine(const unsigned* __restrict__ starts,
+                                                           const unsigned* __restrict__ idx,
+                                                           const unsigned char* __restrict__ subs,
+                                                           unsigned* __restrict__ perm) {
+  __shared__ unsigned h[kSubKeys], scan[kRefineThreads];
+  const unsigned lo = starts[(size_t)blockIdx.x * kSortBlocks], hi = starts[(size_t)(blockIdx.x + 1) * kSortBlocks];
+  if (hi - lo <= 1u) {
+    if (hi > lo && threadIdx.x == 0) perm[lo] = idx[lo];
+    return;
   }
+  static_assert(kSubKeys == kRefineThreads, "one counter per thread");
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  for (unsigned i = lo + threadIdx.x; i < hi; i += kRefineThreads) atomicAdd(h + subs[i], 1u);
+  __syncthreads();
+  unsigned total;
+  const unsigned c = h[threadIdx.x];
+  const unsigned ex = block_exclusive_scan(c, scan, &total);
+  h[threadIdx.x] = lo + ex;
+  __syncthreads();
+  for (unsigned i = lo + threadIdx.x; i < hi; i += kRefineThreads) perm[atomicAdd(h + subs[i], 1u)] = idx[i];
 }
 
 constexpr int kBundleThreads = 512;
@@ -443,10 +521,10 @@ struct PeelJobParams {
   const DetDev* det;
   const LamDev* lam;
   int n_det;
-  long long n_keys;
-  PeelJob* jobs;  // the optical-depth walks overwrite v with the deposit weight
-  const unsigned* perm;
-  const unsigned* kstart;
+  PeelJob* jobs;  // the adjoint's optical-depth walks overwrite v with the deposit weight
+  const unsigned* perm;      // sorted order of the queue
+  const unsigned* n_sorted;  // number of sorted rays
+  double* images;            // forward
   const double* adj;
   double* grad;
   double* evs;  // event scratch of the chunk (see LifeMem)
@@ -485,40 +563,62 @@ struct PeelJobMem {
   }
 };
 
-// Frame of a sort key.
-__device__ __forceinline__ int key_frame(const PeelJobParams& P, unsigned key) {
-  int d = 0;
-  while (d + 1 < P.n_det && (unsigned)P.det[d + 1].key_off <= key) ++d;
-  return d;
+// Adds each waiting contribution (has) to its pixel: neighbouring lanes of
+// the sorted queue mostly share a pixel, so the wavefront sums the
+// contributions of each distinct pixel and issues one atomic for it (rather
+// than up to 64 atomics on one address, which the memory side executes one
+// after another).  Called by every lane of the wavefront.
+__device__ __forceinline__ void flush_images(bool& has, long long ii, double c, double* images) {
+  unsigned long long pend = __ballot(has);
+  while (pend) {
+    const int leader = __ffsll((long long)pend) - 1;
+    const long long lii = (long long)shfl_u64((unsigned long long)ii, leader);
+    const bool mine = has && ii == lii;
+    const double s = wave_sum(mine ? c : 0.0);
+    if (__lane_id() == leader) atomic_add_f64(images + lii, s);
+    if (mine) has = false;
+    pend = __ballot(has);
+  }
 }
 
 // The optical-depth walks of the sorted queue, one ray per lane in a lean
 // persistent loop (no LDS table, so many waves per SIMD hide the density
-// loads): q = (dL/dI) v e^-tau goes to the event scratch, and the job's v
+// loads).  Forward: C = v e^-tau goes to the ray's pixel (flush_images).
+// Adjoint: q = (dL/dI) v e^-tau goes to the event scratch, and the job's v
 // becomes the deposit weight -q kappa (0: no deposit walk).
-template <typename R>
+template <typename R, bool ADJ>
 __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2];
   unsigned long long* res = wave_reservoir(slots);
   const PeelJobMem<R> M{static_cast<const R*>(P.rho), nullptr, nullptr, P.grad};
-  const unsigned n_jobs = P.kstart[P.n_keys];
+  const unsigned n_jobs = *P.n_sorted;
   unsigned long long nx = 0;
   Ray<R> ry;
   ry.active = false;
   ry.tau = R(0);
-  bool done = false, pending = false;
+  bool done = false, pending = false, has = false;
   unsigned job = 0;
   R kap = R(0);
+  long long out_ii = 0;
+  double out_c = 0.0;
   for (;;) {
     while (!ry.active && !done) {
       if (pending) {
         PeelJob& J = P.jobs[job];
-        const double q = P.adj[J.ii] * (J.v * exp(-(double)ry.tau));
-        if (J.e < P.ev_max)
-          P.evs[((size_t)J.e * P.ev_k + 1 + J.d) * P.n_chunk + J.slot] = q;
-        else
-          atomic_add_f64(P.evs + (size_t)P.ev_max * P.ev_k * P.n_chunk + J.slot, q);
-        J.v = -q * P.lam[J.lam].kappa;
+        const double C = J.v * exp(-(double)ry.tau);
+        if (!ADJ) {
+          if (has) atomic_add_f64(P.images + out_ii, out_c);  // a second ray ended in this refill
+          out_ii = J.ii;
+          out_c = C;
+          has = true;
+        } else {
+          const double q = P.adj[J.ii] * C;
+          if (J.e < P.ev_max)
+            P.evs[((size_t)J.e * P.ev_k + 1 + J.d) * P.n_chunk + J.slot] = q;
+          else
+            atomic_add_f64(P.evs + (size_t)P.ev_max * P.ev_k * P.n_chunk + J.slot, q);
+          J.v = -q * P.lam[J.lam].kappa;
+        }
         pending = false;
       }
       const unsigned long long qi = wave_fetch(P.ctr + kKeyCounter, res, 256);
@@ -529,9 +629,10 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
       job = P.perm[qi];
       const PeelJob& J = P.jobs[job];
       kap = (R)P.lam[J.lam].kappa;
-      ray_begin(ry, P.G, J.r, P.det[key_frame(P, J.key)].kd);
+      ray_begin(ry, P.G, J.r, P.det[J.d].kd);
       pending = true;
     }
+    if (!ADJ) flush_images(has, out_ii, out_c, P.images);
     const unsigned long long live = __ballot(!done);
     if (live == 0ull) break;
     const int n_live = __popcll(live);
@@ -558,7 +659,7 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
     tv[i] = 0.0;
   }
   const PeelJobMem<R> M{static_cast<const R*>(P.rho), tk, tv, P.grad};
-  const unsigned n_jobs = P.kstart[P.n_keys];
+  const unsigned n_jobs = *P.n_sorted;
   unsigned long long nd = 0;
   for (;;) {
     if (threadIdx.x == 0) {
@@ -582,7 +683,7 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
         }
         const PeelJob& J = P.jobs[P.perm[qi]];
         w = J.v;
-        if (w != 0.0) ray_begin(ry, P.G, J.r, P.det[key_frame(P, J.key)].kd);
+        if (w != 0.0) ray_begin(ry, P.G, J.r, P.det[J.d].kd);
       }
       const unsigned long long live = __ballot(!done);
       if (live == 0ull) break;
@@ -726,50 +827,58 @@ struct EventPair {
   }
 };
 
-// Device memory of the adjoint's peel-job queue: jobs, their sorted order
-// and the per-key counts and starts.
+// Device memory of the peel-ray queue: rays, their sorted order (and the
+// order after the first sort pass with the second keys), the sort's count
+// matrix (keys x kSortBlocks), its scan and the scan's tile totals.
+constexpr size_t kQueueBytesPerRay = sizeof(PeelJob) + 2 * sizeof(unsigned) + 1;
 struct PeelQueue {
   unsigned char* ptr = nullptr;
   hipStream_t st = nullptr;
   unsigned long long cap = 0;
   long long n_keys = 0;
   PeelJob* jobs = nullptr;
-  unsigned *perm = nullptr, *kcount = nullptr, *kstart = nullptr, *tiles = nullptr;
+  unsigned *perm = nullptr, *idx = nullptr, *counts = nullptr, *starts = nullptr, *tiles = nullptr;
+  unsigned char* subs = nullptr;
   ~PeelQueue() {
     if (ptr) (void)hipFreeAsync(ptr, st);
   }
 };
 
-// Capacity per chunk of `chunk` packages: mcrt_opts.deposit_queue, or by
+// Capacity per chunk of `chunk` packages: mcrt_opts.peel_queue, or by
 // default 8 peel rays per package and frame (the typical package has fewer
-// events; rays beyond the capacity are walked in pass A), at most 2^28 and a
+// events; rays beyond the capacity are walked inline), at most 2^28 and a
 // quarter of the free device memory.
 int make_peel_queue(const mcrt_opts& o, const host::Prepared& pr, unsigned long long chunk, hipStream_t st,
                     PeelQueue& q) {
   q.st = st;
   q.n_keys = pr.n_keys;
   unsigned long long cap;
-  if (o.deposit_queue > 0) {
-    cap = (unsigned long long)o.deposit_queue;
+  if (o.peel_queue > 0) {
+    cap = (unsigned long long)o.peel_queue;
   } else {
     cap = chunk * (unsigned long long)pr.P.n_det * 8ull;
     cap = std::min(std::max(cap, 1ull << 16), 1ull << 28);
     size_t free_b = 0, total_b = 0;
     HIPCHK(hipMemGetInfo(&free_b, &total_b));
-    cap = std::min<unsigned long long>(cap, free_b / 4 / (sizeof(PeelJob) + sizeof(unsigned)));
+    cap = std::min<unsigned long long>(cap, free_b / 4 / kQueueBytesPerRay);
     if (cap == 0) return 0;
   }
+  const size_t n_cnt = (size_t)q.n_keys * kSortBlocks;
   const size_t off_perm = align256(sizeof(PeelJob) * cap);
-  const size_t off_cnt = off_perm + align256(sizeof(unsigned) * cap);
-  const size_t off_start = off_cnt + align256(sizeof(unsigned) * (size_t)q.n_keys);
-  const size_t off_tiles = off_start + align256(sizeof(unsigned) * (size_t)(q.n_keys + 1));
-  const size_t bytes = off_tiles + align256(sizeof(unsigned) * (size_t)(q.n_keys / kScanTile + 1));
+  const size_t off_idx = off_perm + align256(sizeof(unsigned) * cap);
+  const size_t off_subs = off_idx + align256(sizeof(unsigned) * cap);
+  const size_t off_cnt = off_subs + align256(cap);
+  const size_t off_start = off_cnt + align256(sizeof(unsigned) * n_cnt);
+  const size_t off_tiles = off_start + align256(sizeof(unsigned) * (n_cnt + 1));
+  const size_t bytes = off_tiles + align256(sizeof(unsigned) * (n_cnt / kScanTile + 1));
   HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&q.ptr), bytes, st));
   q.cap = cap;
   q.jobs = reinterpret_cast<PeelJob*>(q.ptr);
   q.perm = reinterpret_cast<unsigned*>(q.ptr + off_perm);
-  q.kcount = reinterpret_cast<unsigned*>(q.ptr + off_cnt);
-  q.kstart = reinterpret_cast<unsigned*>(q.ptr + off_start);
+  q.idx = reinterpret_cast<unsigned*>(q.ptr + off_idx);
+  q.subs = q.ptr + off_subs;
+  q.counts = reinterpret_cast<unsigned*>(q.ptr + off_cnt);
+  q.starts = reinterpret_cast<unsigned*>(q.ptr + off_start);
   q.tiles = reinterpret_cast<unsigned*>(q.ptr + off_tiles);
   return 0;
 }
@@ -779,19 +888,21 @@ int reset_counters(unsigned long long* ctr, int w, int n, hipStream_t st) {
   return zero_fill(reinterpret_cast<double*>(ctr + w), n, st);
 }
 
-// Sorts the chunk's queued peel rays by key and walks them in bundles.
-template <typename R>
+// Sorts the chunk's queued peel rays by key and walks them: optical depth
+// (and the image, forward), then the adjoint's deposit walks.
+template <typename R, bool ADJ>
 int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ctr, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_u32, dim3(stream_blocks(q.n_keys)), dim3(kBlock), 0, st, q.kcount, q.n_keys);
-  hipLaunchKernelGGL(k_count, dim3(stream_blocks((long long)q.cap)), dim3(kBlock), 0, st, q.jobs, ctr, q.cap,
-                     q.kcount);
-  const long long n_tiles = (q.n_keys + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, st, q.kcount, q.kstart, q.tiles,
-                     q.n_keys);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kTopThreads), 0, st, q.tiles, n_tiles, q.kstart, q.n_keys);
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, st, q.kstart, q.tiles, q.n_keys);
-  hipLaunchKernelGGL(k_perm, dim3(stream_blocks((long long)q.cap)), dim3(kBlock), 0, st, q.jobs, ctr, q.cap,
-                     q.kstart, q.perm);
+  const long long n_cnt = q.n_keys * kSortBlocks;
+  hipLaunchKernelGGL(k_hist, dim3(kSortBlocks), dim3(kSortThreads), 0, st, q.jobs, ctr, q.cap, (int)q.n_keys,
+                     q.counts);
+  const long long n_tiles = (n_cnt + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, st, q.counts, q.starts, q.tiles,
+                     n_cnt);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kTopThreads), 0, st, q.tiles, n_tiles, q.starts, n_cnt);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, st, q.starts, q.tiles, n_cnt);
+  hipLaunchKernelGGL(k_scatter, dim3(kSortBlocks), dim3(kSortThreads), 0, st, q.jobs, ctr, q.cap, (int)q.n_keys,
+                     q.starts, q.idx, q.subs);
+  hipLaunchKernelGGL(k_refine, dim3((unsigned)q.n_keys), dim3(kRefineThreads), 0, st, q.starts, q.idx, q.subs, q.perm);
   HIPCHK(hipGetLastError());
   PeelJobParams J;
   J.G = P.G;
@@ -799,10 +910,10 @@ int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ct
   J.det = P.det;
   J.lam = P.lam;
   J.n_det = P.n_det;
-  J.n_keys = q.n_keys;
   J.jobs = q.jobs;
   J.perm = q.perm;
-  J.kstart = q.kstart;
+  J.n_sorted = q.starts + n_cnt;
+  J.images = P.images;
   J.adj = P.adj;
   J.grad = P.grad;
   J.evs = P.evs;
@@ -812,34 +923,43 @@ int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ct
   J.ctr = ctr;
   J.batch = 16;
   int nblk = 0;
-  if (int e = persistent_grid(k_peeltau<R>, 0, &nblk)) return e;
-  hipLaunchKernelGGL(k_peeltau<R>, dim3(nblk), dim3(kBlock), 0, st, J);
-  int dev = 0, cus = 0, nb = 0;
-  HIPCHK(hipGetDevice(&dev));
-  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peeldep<R>, kBundleThreads, 0));
-  hipLaunchKernelGGL(k_peeldep<R>, dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0, st, J);
+  if (int e = persistent_grid(k_peeltau<R, ADJ>, 0, &nblk)) return e;
+  hipLaunchKernelGGL((k_peeltau<R, ADJ>), dim3(nblk), dim3(kBlock), 0, st, J);
+  if (ADJ) {
+    int dev = 0, cus = 0, nb = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peeldep<R>, kBundleThreads, 0));
+    hipLaunchKernelGGL(k_peeldep<R>, dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0, st, J);
+  }
   HIPCHK(hipGetLastError());
   return 0;
 }
 
 template <typename R, bool ADJ>
 int life_grid(int blocks_per_cu, int* nblk) {
-  return persistent_grid(k_life<R, ADJ>, blocks_per_cu, nblk);
+  if constexpr (std::is_same<R, double>::value)
+    return persistent_grid(k_life64<ADJ>, blocks_per_cu, nblk);
+  else
+    return persistent_grid(k_life<R, ADJ>, blocks_per_cu, nblk);
 }
 
 template <typename R, bool ADJ>
 int launch_life(const RunParams& P, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL((k_life<R, ADJ>), dim3(nblk), dim3(kBlock), 0, st, P);
+  if constexpr (std::is_same<R, double>::value)
+    hipLaunchKernelGGL((k_life64<ADJ>), dim3(nblk), dim3(kBlock), 0, st, P);
+  else
+    hipLaunchKernelGGL((k_life<R, ADJ>), dim3(nblk), dim3(kBlock), 0, st, P);
   HIPCHK(hipGetLastError());
   return 0;
 }
 
 // Events per package kept in the adjoint's event scratch (more are walked
-// again in pass B), and the scratch size that bounds a chunk of packages (at
-// most a quarter of the free device memory).
+// again in pass B), and the sizes of that scratch and of the peel-ray queue
+// that bound a chunk of packages (each at most a quarter of the free device
+// memory).
 constexpr int kEventsKept = 32;
-constexpr size_t kScratchBytes = size_t(1) << 32;
+constexpr size_t kScratchBytes = size_t(1) << 32, kQueueBytes = size_t(1) << 33;
 
 // Shared driver of run_photons and backward_density.
 int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
@@ -869,19 +989,23 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
                       : (f32 ? life_grid<float, false>(opts->launch_blocks, &nblk)
                              : life_grid<double, false>(opts->launch_blocks, &nblk)))
     return e;
-  // the adjoint runs in chunks of packages: its event scratch holds, per
-  // package, T and q per frame for kEventsKept events plus the sum of q beyond
+  // packages run in equal chunks: the adjoint's event scratch holds, per
+  // package, T and q per frame for kEventsKept events plus the sum of q
+  // beyond; the peel-ray queue by default 8 rays per package and frame
   const int ev_k = 1 + n_det;
   const size_t per_item = sizeof(double) * ((size_t)kEventsKept * ev_k + 1);
-  unsigned long long chunk = 0;
-  if (adjoint) {  // equal chunks, each within the scratch budget
-    size_t free_b = 0, total_b = 0;
-    HIPCHK(hipMemGetInfo(&free_b, &total_b));
-    const unsigned long long most =
-        std::min<unsigned long long>(P.n_items, std::max<size_t>(1 << 16, std::min(kScratchBytes, free_b / 4) / per_item));
-    const unsigned long long n_chunks = (P.n_items + most - 1) / most;
-    chunk = (P.n_items + n_chunks - 1) / n_chunks;
-  }
+  const bool queued = peel && opts->peel_queue != -1;
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(hipMemGetInfo(&free_b, &total_b));
+  unsigned long long most = P.n_items;
+  if (adjoint)
+    most = std::min<unsigned long long>(most, std::max<size_t>(1 << 16, std::min(kScratchBytes, free_b / 4) / per_item));
+  if (queued && opts->peel_queue == 0)
+    most = std::min<unsigned long long>(
+        most, std::max<size_t>(1 << 16, std::min(kQueueBytes, free_b / 4) /
+                                            ((size_t)n_det * 8 * kQueueBytesPerRay)));
+  const unsigned long long n_chunks = (P.n_items + most - 1) / most;
+  const unsigned long long chunk = (P.n_items + n_chunks - 1) / n_chunks;
   const size_t n_evs = adjoint ? (size_t)chunk * ((size_t)kEventsKept * ev_k + 1) : 0;
   const long long n_tally = adjoint ? (long long)P.G.ncell_pad : (P.absorbed ? (long long)nl * P.G.ncell_pad : 0);
   const size_t off_lam = 0;
@@ -927,7 +1051,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     if (int e = zero_fill(P.images, peel ? pr.n_images : 0, st)) return e;
   if (int e = zero_fill(tally, n_tally, st)) return e;
   PeelQueue queue;
-  if (adjoint && peel && opts->deposit_queue != -1) {
+  if (queued) {
     if (int e = make_peel_queue(*opts, pr, chunk, st, queue)) return e;
     P.jobs = queue.cap ? queue.jobs : nullptr;
     P.job_cap = queue.cap;
@@ -947,9 +1071,34 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     HIPCHK(hipEventRecord(ev.a, st));
   }
   int rc = 0;
+  auto queue_phase = [&](bool adj) -> int {  // sort and walk the chunk's queued peel rays
+    if (stats) {
+      qev.push_back(nullptr);
+      HIPCHK(hipEventCreate(&qev.back()));
+      HIPCHK(hipEventRecord(qev.back(), st));
+    }
+    const int r = adj ? (f32 ? run_peel_jobs<float, true>(queue, P, ctr, st) : run_peel_jobs<double, true>(queue, P, ctr, st))
+                      : (f32 ? run_peel_jobs<float, false>(queue, P, ctr, st)
+                             : run_peel_jobs<double, false>(queue, P, ctr, st));
+    if (r) return r;
+    if (stats) {
+      qev.push_back(nullptr);
+      HIPCHK(hipEventCreate(&qev.back()));
+      HIPCHK(hipEventRecord(qev.back(), st));
+    }
+    return 0;
+  };
   if (!adjoint) {
-    rc = f32 ? launch_life<float, false>(P, nblk, st) : launch_life<double, false>(P, nblk, st);
-    if (rc) return rc;
+    for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
+      P.item0 = c0;
+      P.n_chunk = std::min(chunk, P.n_items - c0);
+      if (int e = reset_counters(ctr, 0, 1, st)) return e;
+      if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
+      rc = f32 ? launch_life<float, false>(P, nblk, st) : launch_life<double, false>(P, nblk, st);
+      if (rc) return rc;
+      if (P.jobs)
+        if (int e = queue_phase(false)) return e;
+    }
   } else {
     for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
       P.item0 = c0;
@@ -962,20 +1111,8 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
       P.split = 1;  // pass A
       rc = f32 ? launch_life<float, true>(P, nblk, st) : launch_life<double, true>(P, nblk, st);
       if (rc) return rc;
-      if (P.jobs) {
-        if (stats) {
-          qev.push_back(nullptr);
-          HIPCHK(hipEventCreate(&qev.back()));
-          HIPCHK(hipEventRecord(qev.back(), st));
-        }
-        rc = f32 ? run_peel_jobs<float>(queue, P, ctr, st) : run_peel_jobs<double>(queue, P, ctr, st);
-        if (rc) return rc;
-        if (stats) {
-          qev.push_back(nullptr);
-          HIPCHK(hipEventCreate(&qev.back()));
-          HIPCHK(hipEventRecord(qev.back(), st));
-        }
-      }
+      if (P.jobs)
+        if (int e = queue_phase(true)) return e;
       if (int e = reset_counters(ctr, 0, 1, st)) return e;
       P.split = 2;  // pass B
       rc = f32 ? launch_life<float, true>(P, nblk, st) : launch_life<double, true>(P, nblk, st);

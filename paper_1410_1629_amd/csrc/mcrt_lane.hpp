@@ -20,7 +20,7 @@
 //   M.rho(cell)  M.det(d)  M.lam(l)  M.src(s)  M.adj(i)
 //   M.add_image(i, v)  M.add_absorbed(i, v)  M.add_grad(cell, v)
 //   M.fetch()  M.flush_counts(x_path, x_locate, x_peel, deposits)
-//   M.job_slot()  M.store_job(slot, r, w, key)   (adjoint deposit queue)
+//   M.job_slot()  M.store_job(slot, ...)   (peel-ray queue)
 //   M.ev_load(slot, e, k)  M.ev_store(slot, e, k, v)   (adjoint event scratch)
 // Cells are bricked addresses (GridDev): densities, the absorbed tally
 // (wavelength-major, ncell_pad per wavelength) and the gradient are all in
@@ -70,17 +70,19 @@ enum Phase : int {
   PH_PKG_END
 };
 
-// A queued adjoint peel ray: from r towards frame d of event e of chunk
-// package `slot`, with v = W Phi / D^2 (so C = v e^-tau), ii its index in
-// the image block (for dL/dI) and lam its wavelength.  key is the sort key
-// (tile_key), rank the job's place among the jobs of its key.
+// A queued peel ray: from r towards frame d of event e (saturated at
+// kEventSat) of chunk package `slot`, with v = W Phi / D^2 (so its
+// contribution is C = v e^-tau), ii its index in the image block (the pixel
+// it adds to, or the dL/dI it is weighted with) and lam its wavelength.
+// key and sub are its sort keys (tile_key, tile_sub).
+constexpr int kEventSat = 65535;
 struct PeelJob {
   double r[3];
   double v;
   long long ii;
-  unsigned key, rank, slot;
-  unsigned short e, d;
-  unsigned lam;
+  unsigned key, slot, lam;
+  unsigned short e;
+  unsigned char d, sub;
 };
 
 struct RunParams {
@@ -106,7 +108,7 @@ struct RunParams {
   // adjoint (ADJ): the launch's role and its chunk of work items
   int split;                   // 1: pass A, 2: pass B
   unsigned long long item0, n_chunk;  // work items [item0, item0 + n_chunk)
-  PeelJob* jobs;               // pass A: queue of peel jobs (NULL: walk every peel ray here)
+  PeelJob* jobs;               // forward run and pass A: queue of peel rays (NULL: walk every peel ray here)
   unsigned long long job_cap;  // its capacity; rays beyond it are walked here
   int ev_max;                  // events kept per package in the event scratch
   int ev_k;                    // doubles per event: T of the leg after it, then q per frame
@@ -310,15 +312,16 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
         const DetDev& D = M.det(L.det);
         L.pix = frame_pixel(D, L.r);
         if (L.pix >= 0) {
-          if (!ADJ || !P.jobs || L.pass != 0) break;
+          if (!P.jobs || L.pass != 0) break;
           const unsigned long long slot = M.job_slot();
           if (slot >= P.job_cap) break;  // queue full: walk it here
-          // queued: C = v e^-tau is completed by the peel-job kernel
+          // queued: C = v e^-tau is completed by the queue's walk kernel
           const double ph = L.is_emit ? 1.0 / (4.0 * kPi)
                                       : hg_phase(L.g, L.k[0] * D.kd[0] + L.k[1] * D.kd[1] + L.k[2] * D.kd[2]);
           const int comp = ((P.flags & kFlagSplit) && !L.is_emit) ? 1 : 0;
           const long long ii = ((long long)comp * P.n_lambda + L.lam) * P.pix_lambda + D.off + L.pix;
-          M.store_job(slot, L.r, L.W * ph * D.inv_d2, ii, tile_key(D, L.pix), (unsigned)L.slot, L.n, L.det,
+          M.store_job(slot, L.r, L.W * ph * D.inv_d2, ii, tile_key(D, L.pix), tile_sub(D, L.pix), (unsigned)L.slot,
+                      L.n < kEventSat ? L.n : kEventSat, L.det,
                       (unsigned)L.lam);
           ++L.n_pl;
         }

@@ -150,15 +150,16 @@ struct HostLifeMem {
     EMU_CHECK(slot >= 0 && slot < n_chunk, "event scratch package", slot, n_chunk);
     (*evs)[(size_t)ev_max * ev_k * n_chunk + slot] += v;
   }
-  void store_job(unsigned long long slot, const double r[3], double v, long long ii, unsigned key, unsigned item,
-                 int e, int d, unsigned lam) {
+  void store_job(unsigned long long slot, const double r[3], double v, long long ii, unsigned key, unsigned sub,
+                 unsigned item, int e, int d, unsigned lam) {
     EMU_CHECK(jobs != nullptr && slot < job_cap, "peel-job queue", slot, job_cap);
     EMU_CHECK(key < (unsigned long long)n_keys, "sort key", key, n_keys);
-    EMU_CHECK(ii >= 0 && ii < n_adj, "job image index", ii, n_adj);
+    EMU_CHECK(ii >= 0 && ii < (adj_ ? n_adj : n_images), "job image index", ii, adj_ ? n_adj : n_images);
     EMU_CHECK(item < (unsigned)n_chunk, "job package", item, n_chunk);
     EMU_CHECK(d >= 0 && d < pr.P.n_det, "job frame", d, pr.P.n_det);
     EMU_CHECK(lam < (unsigned)pr.P.n_lambda, "job wavelength", lam, pr.P.n_lambda);
-    EMU_CHECK(e >= 0 && e < 65536, "job event", e, 65536);
+    EMU_CHECK(e >= 0 && e <= kEventSat, "job event", e, kEventSat);
+    EMU_CHECK(sub < 256u, "second sort key", sub, 256);
     PeelJob& J = (*jobs)[slot];
     J.r[0] = r[0];
     J.r[1] = r[1];
@@ -166,11 +167,11 @@ struct HostLifeMem {
     J.v = v;
     J.ii = ii;
     J.key = key;
-    J.rank = 0;
     J.slot = item;
-    J.e = (unsigned short)e;
-    J.d = (unsigned short)d;
     J.lam = lam;
+    J.e = (unsigned short)e;
+    J.d = (unsigned char)d;
+    J.sub = (unsigned char)sub;
   }
   void flush_counts(unsigned a, unsigned b, unsigned c, unsigned d) {
     xs[0] += a;
@@ -220,50 +221,95 @@ struct HostBundleMem {
   }
 };
 
-// The library's counting sort of the chunk's queue by key (count with
-// ranks, exclusive scan, permutation), then each job in sorted order: the
-// optical-depth walk, q = (dL/dI) C into the event scratch, and for q != 0
-// the deposit walk.  Returns the crossings; `deps` gets the deposits.
-template <typename R>
+// The library's counting sort of the chunk's queue by key, part by part as
+// its workgroups run it (per-part key counts, exclusive scan of the
+// key-major count matrix, per-part counters handing out positions), then
+// each ray in sorted order: the optical-depth walk; forward, C into its
+// pixel; adjoint, q = (dL/dI) C into the event scratch and, for q != 0, the
+// deposit walk.  Returns the crossings; `deps` gets the deposits.
+template <typename R, bool ADJ>
 unsigned long long emu_peel_jobs(HostLifeMem<R>& M, const RunParams& P, std::vector<PeelJob>& jobs,
                                  unsigned long long n_jobs, std::vector<double>& grad, unsigned long long& deps,
                                  long long cap_steps) {
   const long long n_keys = M.n_keys;
-  std::vector<unsigned> kcount(n_keys, 0), kstart(n_keys + 1, 0), perm(n_jobs, 0);
-  for (unsigned long long j = 0; j < n_jobs; ++j) {
-    EMU_CHECK(jobs[j].key < (unsigned long long)n_keys, "sort key", jobs[j].key, n_keys);
-    jobs[j].rank = kcount[jobs[j].key]++;
+  const int nb = host::kSortBlocks;
+  const unsigned long long per = (n_jobs + nb - 1) / nb;
+  std::vector<unsigned> counts((size_t)n_keys * nb, 0), starts((size_t)n_keys * nb + 1, 0);
+  unsigned long long n_valid = 0;
+  for (int b = 0; b < nb; ++b)
+    for (unsigned long long j = b * per; j < std::min(n_jobs, (b + 1) * per); ++j) {
+      EMU_CHECK(jobs[j].key < (unsigned long long)n_keys, "sort key", jobs[j].key, n_keys);
+      ++counts[(size_t)jobs[j].key * nb + b];
+      ++n_valid;
+    }
+  for (size_t i = 0; i < counts.size(); ++i) starts[i + 1] = starts[i] + counts[i];
+  EMU_CHECK(starts.back() == n_valid, "sorted rays", starts.back(), n_valid);
+  std::vector<unsigned> idx(n_valid, 0), perm(n_valid, 0);
+  std::vector<unsigned char> subs(n_valid, 0), filled(n_valid, 0);
+  for (int b = 0; b < nb; ++b) {
+    std::vector<unsigned> h(n_keys);
+    for (long long k = 0; k < n_keys; ++k) h[k] = starts[(size_t)k * nb + b];
+    for (unsigned long long j = b * per; j < std::min(n_jobs, (b + 1) * per); ++j) {
+      const unsigned q = h[jobs[j].key]++;
+      EMU_CHECK(q < n_valid && !filled[q], "sorted position", q, n_valid);
+      filled[q] = 1;
+      idx[q] = (unsigned)j;
+      subs[q] = jobs[j].sub;
+    }
   }
-  for (long long k = 0; k < n_keys; ++k) kstart[k + 1] = kstart[k] + kcount[k];
-  for (unsigned long long j = 0; j < n_jobs; ++j) {
-    const unsigned long long q = (unsigned long long)kstart[jobs[j].key] + jobs[j].rank;
-    EMU_CHECK(q < n_jobs, "sorted queue", q, n_jobs);
-    perm[q] = (unsigned)j;
+  // second pass: each tile's run by the second key
+  std::fill(filled.begin(), filled.end(), 0);
+  for (long long k = 0; k < n_keys; ++k) {
+    const unsigned lo = starts[(size_t)k * nb], hi = starts[(size_t)(k + 1) * nb];
+    EMU_CHECK(lo <= hi && hi <= n_valid, "tile run", hi, n_valid);
+    unsigned h[256] = {0};
+    for (unsigned i = lo; i < hi; ++i) ++h[subs[i]];
+    unsigned run = lo;
+    for (int c = 0; c < 256; ++c) {
+      const unsigned t = h[c];
+      h[c] = run;
+      run += t;
+    }
+    for (unsigned i = lo; i < hi; ++i) {
+      const unsigned q = h[subs[i]]++;
+      EMU_CHECK(q >= lo && q < hi && !filled[q], "refined position", q, hi);
+      filled[q] = 1;
+      perm[q] = idx[i];
+    }
   }
   HostBundleMem D{P.G, grad};
   unsigned long long nx = 0;
   deps = 0;
-  for (unsigned long long qi = 0; qi < n_jobs; ++qi) {
+  for (unsigned long long qi = 0; qi < n_valid; ++qi) {
     const PeelJob& J = jobs[perm[qi]];
+    if (qi > 0) {
+      const PeelJob& Jp = jobs[perm[qi - 1]];
+      EMU_CHECK(Jp.key < J.key || (Jp.key == J.key && Jp.sub <= J.sub), "sorted order", qi, n_valid);
+    }
     int d = 0;
     while (d + 1 < P.n_det && (unsigned)M.det(d + 1).key_off <= J.key) ++d;
     EMU_CHECK(d == J.d, "job frame against its key", J.d, P.n_det);
     Ray<R> ry;
-    ray_begin(ry, P.G, J.r, M.det(d).kd);
+    ray_begin(ry, P.G, J.r, M.det(J.d).kd);
     const R kap = (R)M.lam((int)J.lam).kappa;
     long long steps = 0;
     while (ry.active) {
       nx += tau_step<R>(ry, P.G, kap, M);
       if (++steps > cap_steps) throw Violation("a peel-job walk exceeded the grid's crossing bound");
     }
-    const double q = M.adj(J.ii) * (J.v * exp(-(double)ry.tau));
+    const double C = J.v * exp(-(double)ry.tau);
+    if (!ADJ) {
+      M.add_image(J.ii, C);
+      continue;
+    }
+    const double q = M.adj(J.ii) * C;
     if (J.e < P.ev_max)
       M.ev_store((int)J.slot, J.e, 1 + J.d, q);
     else
       M.ev_add_beyond((int)J.slot, q);
     if (q == 0.0) continue;
     const double w = -q * M.lam((int)J.lam).kappa;
-    ray_begin(ry, P.G, J.r, M.det(d).kd);
+    ray_begin(ry, P.G, J.r, M.det(J.d).kd);
     steps = 0;
     while (ry.active) {
       const unsigned n = bp_step<R>(ry, P.G, w, D);
@@ -328,57 +374,60 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
       M.xs[6] += L.n_dep;
     }
   };
-  if (!ADJ) {
-    P.item0 = 0;
-    P.n_chunk = P.n_items;
-    launch(0);
-  } else {
-    // chunks of packages as the library runs them (the library's chunk holds
-    // about 1 GiB of event scratch; g_chunk_items overrides for tests)
+  // chunks of packages as the library runs them (the library sizes them by
+  // its event-scratch and queue budgets; g_chunk_items overrides for tests)
+  if (ADJ) {
     P.ev_max = g_events_kept;
     P.ev_k = 1 + P.n_det;
-    const size_t per_item = sizeof(double) * ((size_t)P.ev_max * P.ev_k + 1);
-    unsigned long long chunk = std::min<unsigned long long>(
-        P.n_items, std::max<size_t>(1 << 16, (size_t(1) << 30) / per_item));
-    if (g_chunk_items > 0) chunk = std::min<unsigned long long>(chunk, (unsigned long long)g_chunk_items);
-    std::vector<PeelJob> jobs;
-    if (peel && opts->deposit_queue != -1) {
-      unsigned long long qcap = opts->deposit_queue > 0 ? (unsigned long long)opts->deposit_queue
-                                                        : chunk * (unsigned long long)P.n_det * 8ull;
-      if (opts->deposit_queue == 0) qcap = std::min(std::max(qcap, 1ull << 16), 1ull << 28);
-      jobs.resize(qcap);
-      M.jobs = &jobs;
-      M.job_cap = qcap;
-      M.n_keys = pr.n_keys;
-      P.jobs = jobs.data();
-      P.job_cap = qcap;
-    }
-    std::vector<double> evs;
-    std::vector<unsigned char> ev_set;
-    M.evs = &evs;
-    M.ev_set = &ev_set;
-    M.ev_max = P.ev_max;
-    M.ev_k = P.ev_k;
-    for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
-      P.item0 = c0;
-      P.n_chunk = std::min(chunk, P.n_items - c0);
-      M.n_chunk = (int)P.n_chunk;
-      evs.assign((size_t)P.n_chunk * ((size_t)P.ev_max * P.ev_k + 1), 0.0);
-      ev_set.assign(evs.size(), 0);
-      M.job_next = 0;
-      launch(1);  // pass A
-      if (P.jobs) {
-        unsigned long long deps = 0;
-        const unsigned long long nx =
-            emu_peel_jobs<R>(M, P, jobs, std::min(M.job_next, M.job_cap), grad_b, deps, cap);
-        M.x_queue += nx;
-        M.d_queue += deps;
-      }
-      launch(2);  // pass B
-    }
-    M.xs[2] += M.x_queue;
-    M.xs[6] += M.d_queue;
   }
+  const size_t per_item = sizeof(double) * ((size_t)P.ev_max * P.ev_k + 1);
+  unsigned long long chunk =
+      ADJ ? std::min<unsigned long long>(P.n_items, std::max<size_t>(1 << 16, (size_t(1) << 30) / per_item))
+          : P.n_items;
+  if (g_chunk_items > 0) chunk = std::min<unsigned long long>(chunk, (unsigned long long)g_chunk_items);
+  std::vector<PeelJob> jobs;
+  if (peel && opts->peel_queue != -1) {
+    unsigned long long qcap =
+        opts->peel_queue > 0 ? (unsigned long long)opts->peel_queue : chunk * (unsigned long long)P.n_det * 8ull;
+    if (opts->peel_queue == 0) qcap = std::min(std::max(qcap, 1ull << 16), 1ull << 28);
+    jobs.resize(qcap);
+    M.jobs = &jobs;
+    M.job_cap = qcap;
+    M.n_keys = pr.n_keys;
+    P.jobs = jobs.data();
+    P.job_cap = qcap;
+  }
+  std::vector<double> evs;
+  std::vector<unsigned char> ev_set;
+  M.evs = &evs;
+  M.ev_set = &ev_set;
+  M.ev_max = P.ev_max;
+  M.ev_k = P.ev_k;
+  auto queue_phase = [&]() {
+    unsigned long long deps = 0;
+    const unsigned long long nx =
+        emu_peel_jobs<R, ADJ>(M, P, jobs, std::min(M.job_next, M.job_cap), grad_b, deps, cap);
+    M.x_queue += nx;
+    M.d_queue += deps;
+  };
+  for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
+    P.item0 = c0;
+    P.n_chunk = std::min(chunk, P.n_items - c0);
+    M.n_chunk = (int)P.n_chunk;
+    M.job_next = 0;
+    if (!ADJ) {
+      launch(0);
+      if (P.jobs) queue_phase();
+      continue;
+    }
+    evs.assign((size_t)P.n_chunk * ((size_t)P.ev_max * P.ev_k + 1), 0.0);
+    ev_set.assign(evs.size(), 0);
+    launch(1);  // pass A
+    if (P.jobs) queue_phase();
+    launch(2);  // pass B
+  }
+  M.xs[2] += M.x_queue;
+  M.xs[6] += M.d_queue;
   if (P.absorbed) unbrick(P.G, abs_b, absorbed, P.n_lambda);
   if (ADJ && grad) unbrick(P.G, grad_b, grad, 1);
   if (stats) {

@@ -85,7 +85,7 @@ def _call_run(lib, B, prob, **over):
 
 
 @pytest.mark.parametrize("case", ["n_packages", "precision", "flags", "w_min", "max_scatter", "launch_blocks",
-                                  "event_batch", "brick_shape", "deposit_queue", "grid_cells", "grid_extent",
+                                  "event_batch", "brick_shape", "peel_queue", "grid_cells", "grid_extent",
                                   "albedo", "g", "kappa", "lum", "n_det", "det_pixels", "det_distance",
                                   "n_src", "src_kind", "src_scale"])
 def test_invalid_arguments_are_rejected(lib, B, W, case):
@@ -107,8 +107,8 @@ def test_invalid_arguments_are_rejected(lib, B, W, case):
         over["event_batch"] = 65
     elif case == "brick_shape":
         over["brick_shape"] = B.brick(9, 0, 0)
-    elif case == "deposit_queue":
-        over["deposit_queue"] = -2
+    elif case == "peel_queue":
+        over["peel_queue"] = -2
     elif case == "grid_cells":
         prob["n"] = (0, 4, 4)
     elif case == "grid_extent":

@@ -247,7 +247,7 @@ def test_brick_shape_rejected(E, W):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_backward_deposit_queue_modes(E, orc, W, prec):
+def test_backward_peel_queue_modes(E, orc, W, prec):
     """Peel-ray deposits walked inline, all queued and bundled by tile, or
     queued until a tiny queue is full: same gradient and crossing counts."""
     n = (12, 10, 9)
@@ -261,7 +261,7 @@ def test_backward_deposit_queue_modes(E, orc, W, prec):
     g_o, _, _ = orc.grad(prob, adj)
     ref = None
     for q in (-1, 0, 7, 100000):
-        g, st = E.grad(prob, adj, deposit_queue=q)
+        g, st = E.grad(prob, adj, peel_queue=q)
         assert rel_l1(g, g_o) < (1e-9 if prec == 0 else 1e-5), (q, rel_l1(g, g_o))
         if q == -1:
             assert st["x_queue"] == 0 and st["d_queue"] == 0
@@ -274,6 +274,59 @@ def test_backward_deposit_queue_modes(E, orc, W, prec):
         assert rel_l1(g, ref[0]) < 1e-12
         for key in ("x_path", "x_locate", "x_peel", "deposits", "events", "peels"):
             assert st[key] == ref[1][key], (q, key)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_forward_peel_queue_modes(E, orc, W, prec):
+    """Forward peel rays walked inline, all queued (sorted, walked by the
+    queue kernel, added to their pixels), queued until a tiny queue is full,
+    and queued per chunk of 97 packages: the oracle's images and tallies and
+    the same crossing counts in every mode."""
+    n = (11, 9, 8)
+    prob = W.small_problem(n=n, rho=W.lognormal_density(n, 0.8, seed=51, f32=(prec == 1)), kappa=1.2, albedo=0.7,
+                           g=0.4, detectors=[W.frame(10.0, 0.0, 20, 20, 1.2, 1.2),
+                                             W.frame(10.0, 70.0, 16, 24, 1.3, 1.1, azim=20.0)],
+                           n_packages=800, precision=prec,
+                           flags=W.FLAG_PEEL_EMIT | W.FLAG_PEEL_SCAT | W.FLAG_ABSORB | W.FLAG_SPLIT)
+    img_o, abs_o, _ = orc.run(prob)
+    tol = 1e-10 if prec == 0 else 1e-5
+    ref = None
+    for q, chunk in ((-1, 0), (0, 0), (7, 0), (0, 97)):
+        try:
+            E.set_chunk_items(chunk)
+            images, absorbed, st = E.run(prob, peel_queue=q)
+        finally:
+            E.set_chunk_items(0)
+        assert rel_l1(images, img_o) < tol and rel_l1(absorbed, abs_o) < tol, (q, chunk)
+        if q == -1:
+            assert st["x_queue"] == 0
+        else:
+            assert 0 < st["x_queue"] <= st["x_peel"] and st["d_queue"] == 0
+        if ref is None:
+            ref = (images, st)
+            continue
+        assert rel_l1(images, ref[0]) < 1e-12
+        for key in ("x_path", "x_locate", "x_peel", "deposits", "events", "peels", "packages"):
+            assert st[key] == ref[1][key], (q, chunk, key)
+
+
+def test_backward_events_beyond_the_job_event_field(E, orc, W):
+    """Queued peel rays record their event number in 16 bits: the lane code
+    saturates it (any event past the scratch's kept events is "beyond"), and
+    the harness rejects a stored number past the saturation value.
+    Packages with 70000 scatterings (pure scattering, no weight cut-off)
+    with every ray queued give the oracle's gradient."""
+    prob = W.small_problem(n=(3, 3, 3), kappa=4.0, albedo=1.0, g=0.3, w_min=0.0, max_scatter=70000, n_packages=2,
+                           detectors=[W.frame(10.0, 30.0, 6, 6, 1.2, 1.2)],
+                           flags=W.FLAG_PEEL_EMIT | W.FLAG_PEEL_SCAT)
+    img_o, _, st_o = orc.run(prob)
+    assert st_o["events"] == 2 * 70000
+    adj = np.random.default_rng(9).standard_normal(img_o.shape)
+    g_o, _, _ = orc.grad(prob, adj)
+    for q in (-1, 150000):  # a queue that holds every ray
+        g, st = E.grad(prob, adj, peel_queue=q)
+        assert rel_l1(g, g_o) < 1e-9, (q, rel_l1(g, g_o))
+        assert (st["x_queue"] == 0) == (q == -1)
 
 
 @pytest.mark.parametrize("kept", [0, 1, 3, 32])
@@ -311,10 +364,10 @@ def test_backward_in_chunks(E, orc, W, queue):
     img_o, _, _ = orc.run(prob)
     adj = np.random.default_rng(4).standard_normal(img_o.shape)
     g_o, _, _ = orc.grad(prob, adj)
-    g_full, st_full = E.grad(prob, adj, deposit_queue=queue)
+    g_full, st_full = E.grad(prob, adj, peel_queue=queue)
     try:
         E.set_chunk_items(97)
-        g, st = E.grad(prob, adj, deposit_queue=queue)
+        g, st = E.grad(prob, adj, peel_queue=queue)
     finally:
         E.set_chunk_items(0)
     assert rel_l1(g, g_o) < 1e-9 and rel_l1(g_full, g_o) < 1e-9

@@ -289,7 +289,38 @@ def test_backward_matches_oracle(B, orc, W, prec):
     assert st["packages"] == st_o["packages"]
 
 
-def test_backward_deposit_queue_modes(B, orc, W):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_forward_peel_queue_modes(B, orc, W, prec):
+    # forward peel rays walked inline, all queued (sorted, walked by the
+    # queue kernel), or queued until a tiny queue is full: the oracle's
+    # images and the same crossing counts
+    _say("forward peel queue modes prec=%d" % prec)
+    n = (11, 9, 8)
+    prob = W.small_problem(n=n, rho=W.lognormal_density(n, 0.8, seed=51, f32=(prec == 1)), kappa=1.2, albedo=0.7,
+                           g=0.4, detectors=[W.frame(10.0, 0.0, 20, 20, 1.2, 1.2),
+                                             W.frame(10.0, 70.0, 16, 24, 1.3, 1.1, azim=20.0)],
+                           n_packages=3000, precision=prec,
+                           flags=W.FLAG_PEEL_EMIT | W.FLAG_PEEL_SCAT | W.FLAG_ABSORB | W.FLAG_SPLIT)
+    img_o, abs_o, _ = orc.run(prob)
+    tol = 1e-10 if prec == 0 else 1e-5
+    ref = None
+    for q in (-1, 0, 100, 5000):
+        images, absorbed, st = B.render(prob, peel_queue=q)
+        e_i = rel_l1(images.cpu().numpy(), img_o)
+        e_a = rel_l1(absorbed.cpu().numpy(), abs_o)
+        _say("  queue %d: rel_L1 images %.3e absorbed %.3e" % (q, e_i, e_a))
+        assert e_i < tol and e_a < tol, (q, e_i, e_a)
+        if q == -1:
+            assert st["x_queue"] == 0
+        else:
+            assert 0 < st["x_queue"] <= st["x_peel"] and st["d_queue"] == 0
+        if ref is None:
+            ref = st
+        for key in ("x_path", "x_locate", "x_peel", "deposits", "events", "peels", "packages"):
+            assert st[key] == ref[key], (q, key, st[key], ref[key])
+
+
+def test_backward_peel_queue_modes(B, orc, W):
     # peel-ray deposits walked inline, queued and bundled, or queued until a
     # tiny queue is full: the same gradient and the same crossing counts
     import torch
@@ -302,7 +333,7 @@ def test_backward_deposit_queue_modes(B, orc, W):
     ref = None
     for q in (-1, 0, 100, 5000):
         grad = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
-        st = B.backward_density(prob, rho, _dev(adj), grad, deposit_queue=q)
+        st = B.backward_density(prob, rho, _dev(adj), grad, peel_queue=q)
         g = grad.cpu().numpy()
         e = rel_l1(g, g_o)
         _say("  queue %d: rel_L1 grad %.3e" % (q, e))
