@@ -54,7 +54,8 @@ COPY_BYTES = 1 << 30
 KERNELS = {
     "forward": "void mcrt::k_life<float, false>(mcrt::RunParams)",
     "adjoint": "void mcrt::k_life<float, true>(mcrt::RunParams)",
-    "peel_tau": "void mcrt::k_peeltau<float>(mcrt::PeelJobParams)",
+    "peel_tau_forward": "void mcrt::k_peeltau<float, false>(mcrt::PeelJobParams)",
+    "peel_tau_adjoint": "void mcrt::k_peeltau<float, true>(mcrt::PeelJobParams)",
     "peel_deposit": "void mcrt::k_peeldep<float>(mcrt::PeelJobParams)",
     "trace": "void mcrt::k_trace<float>(mcrt::TraceParams)",
 }
@@ -192,9 +193,10 @@ def fp64_comparison(B, prob, step_fn, images32, grad32, dev):
             "images_mc_noise_rel_l1": 0.5 * rel_l1(ia, ib)}
 
 
-def collect_profiles(out_dir, prof):
+def collect_profiles(out_dir, prof, run=True):
     """Runs this script under rocprofv3 as child processes (this process
-    never touches the GPU) and writes the summaries to `prof` (profiles/)."""
+    never touches the GPU) and writes the summaries to `prof` (profiles/);
+    run=False only summarizes the raw output already in out_dir."""
     os.makedirs(out_dir, exist_ok=True)
     me = os.path.abspath(__file__)
     child = [sys.executable, me, "--steps", "2", "--warmup", "1", "--no-cpu-baseline", "--no-fp64"]
@@ -203,7 +205,7 @@ def collect_profiles(out_dir, prof):
         "fetch": ["rocprofv3", "--kernel-trace", "--output-format", "csv", "--pmc", "FETCH_SIZE"],
         "write": ["rocprofv3", "--kernel-trace", "--output-format", "csv", "--pmc", "WRITE_SIZE"],
     }
-    for name, cmd in runs.items():
+    for name, cmd in (runs.items() if run else ()):
         extra = ["--calibrate-copy"] if name != "trace" else []
         full = cmd + ["-d", os.path.join(out_dir, name), "-o", name, "--"] + child + extra
         print("[profile] " + " ".join(full), flush=True)
@@ -280,14 +282,16 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy first (counter scale)")
     ap.add_argument("--collect-profiles", metavar="DIR", help="run the rocprofv3 passes (raw output in DIR)")
+    ap.add_argument("--summarize-profiles", metavar="DIR", help="only rewrite the summaries from the raw output in DIR")
     ap.add_argument("--profiles-dir", default=os.path.join(ROOT, "profiles"), help="where the summaries go")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
-    if args.collect_profiles:
-        collect_profiles(args.collect_profiles, args.profiles_dir)
+    if args.collect_profiles or args.summarize_profiles:
+        collect_profiles(args.collect_profiles or args.summarize_profiles, args.profiles_dir,
+                         run=bool(args.collect_profiles))
         return
 
     import numpy as np
@@ -349,7 +353,7 @@ def main():
         s0 = sts[-1]
         x = s0["x_path"] + s0["x_locate"] + s0["x_peel"]
         out = {"kernel_ms": ms, "life_ms": life_ms, "packages_per_s": n_pkg / (ms / 1e3), "crossings": x,
-               "crossings_per_s": x / (ms / 1e3)}
+               "crossings_per_s": x / (ms / 1e3), "life_launches": s0["life_launches"]}
         for k in ("x_path", "x_locate", "x_peel", "x_queue", "events", "peels", "deposits"):
             out[k] = s0[k]
         out["life_algorithmic_bytes"] = life_bytes(s0, prec, adjoint)
@@ -360,7 +364,9 @@ def main():
     fsum, bsum = summary(fw, False), summary(bw, True)
     dominant_adj = bsum["life_ms"] > fsum["life_ms"]
     dom = bsum if dominant_adj else fsum
-    achieved = dom["life_algorithmic_bytes"] / (dom["life_ms"] / 1e3) / 1e9
+    # per launch of the life kernel: the call's bytes and time over its launches
+    launch_s = dom["life_ms"] / 1e3 / dom["life_launches"]
+    achieved = dom["life_algorithmic_bytes"] / dom["life_launches"] / launch_s / 1e9
     key = "adjoint" if dominant_adj else "forward"
     traffic = traffic_for(key)
     st_f = fw[-1]
@@ -392,7 +398,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
     }
     if traffic:
-        out["roofline"]["hardware_frac"] = traffic / (dom["life_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
+        out["roofline"]["hardware_frac"] = traffic / launch_s / 1e9 / HBM_PEAK_GBS
     out["traversal"] = traversal(B, prob, 4_000_000, dev)
     if not args.no_fp64:
         out["fp64_path"] = fp64_comparison(B, prob, step_fn, images, grad, dev)

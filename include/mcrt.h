@@ -122,14 +122,16 @@ typedef struct {
  * brick of the library's internal cell layout, MCRT_BRICK(lx, ly, lz) for
  * bricks of 2^lx x 2^ly x 2^lz cells (each log2 in [0, 7], at most 2^10
  * cells).  The default brick fills one 128-byte cache line with the most
- * compact block of cells in physical units.  peel_queue (backward_density
- * only) caps the device queue of peel rays, in rays per chunk of packages (at
- * most 2^31): 0 = library choice, -1 = no queue (every peel ray is walked
- * inline, its deposits with global atomics); rays beyond the cap are walked
- * inline.  Queued rays are sorted by frame and image-plane tile, walked for
- * their optical depth by a lean kernel, and walked again for their deposits
- * in bundles whose deposits are summed in LDS before they reach the
- * gradient. */
+ * compact block of cells in physical units.  peel_queue caps the device
+ * queue of peel rays, in rays per chunk of packages (at most 2^31): 0 =
+ * library choice, -1 = no queue (every peel ray is walked inline by the
+ * life-cycle kernel; in the adjoint its deposits go out as global atomics);
+ * rays beyond the cap are walked inline.  Queued rays are sorted by frame
+ * and image tile, then pixel, and walked for their optical depth by a lean
+ * kernel (forward: the contribution goes to its pixel); the adjoint walks
+ * them again for their deposits in bundles whose deposits are summed in LDS
+ * before they reach the gradient.  The results do not depend on the cap up
+ * to the order of FP64 additions. */
 typedef struct {
     uint64_t n_packages, first_package, seed;
     int32_t precision;
@@ -156,7 +158,9 @@ typedef struct {
  * by those deposit walks, which sum them on chip before they reach the
  * tally.  Durations on the stream from HIP events: kernel_ms all kernels of
  * the call, life_ms the life-cycle kernel, queue_ms the sort and the walks
- * of the peel-ray queue. */
+ * of the peel-ray queue.  life_launches counts the life-cycle kernel's
+ * launches (the call runs its packages in chunks; the adjoint launches the
+ * kernel twice per chunk). */
 typedef struct {
     double emitted, absorbed, escaped, truncated;
     uint64_t x_path, x_locate, x_peel, events, packages, peels, deposits;
@@ -164,6 +168,7 @@ typedef struct {
     uint64_t x_queue;
     double life_ms, queue_ms;
     uint64_t d_queue;
+    uint64_t life_launches;
 } mcrt_stats;
 
 /* Photon-package life cycle (Sect. 1 techniques, Sect. 2.2 problem data):
@@ -234,7 +239,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 6
+#define MCRT_ABI_VERSION 7
 
 #ifdef __cplusplus
 }

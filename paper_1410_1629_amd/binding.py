@@ -67,7 +67,7 @@ class Stats(C.Structure):
                 ("x_peel", C.c_uint64), ("events", C.c_uint64), ("packages", C.c_uint64),
                 ("peels", C.c_uint64), ("deposits", C.c_uint64), ("kernel_ms", C.c_double),
                 ("x_queue", C.c_uint64), ("life_ms", C.c_double), ("queue_ms", C.c_double),
-                ("d_queue", C.c_uint64)]
+                ("d_queue", C.c_uint64), ("life_launches", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -76,7 +76,7 @@ class Stats(C.Structure):
 _lib = None
 
 # Exported symbols of include/mcrt.h.
-ABI_VERSION = 6  # MCRT_ABI_VERSION of the header these structs follow
+ABI_VERSION = 7  # MCRT_ABI_VERSION of the header these structs follow
 SYMBOLS = ("run_photons", "trace_path", "peel_off", "backward_density", "mcrt_last_error", "mcrt_abi_version")
 
 

@@ -1071,6 +1071,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     HIPCHK(hipEventRecord(ev.a, st));
   }
   int rc = 0;
+  unsigned long long launches = 0;  // of the life-cycle kernel
   auto queue_phase = [&](bool adj) -> int {  // sort and walk the chunk's queued peel rays
     if (stats) {
       qev.push_back(nullptr);
@@ -1096,6 +1097,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
       if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
       rc = f32 ? launch_life<float, false>(P, nblk, st) : launch_life<double, false>(P, nblk, st);
       if (rc) return rc;
+      ++launches;
       if (P.jobs)
         if (int e = queue_phase(false)) return e;
     }
@@ -1111,12 +1113,14 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
       P.split = 1;  // pass A
       rc = f32 ? launch_life<float, true>(P, nblk, st) : launch_life<double, true>(P, nblk, st);
       if (rc) return rc;
+      ++launches;
       if (P.jobs)
         if (int e = queue_phase(true)) return e;
       if (int e = reset_counters(ctr, 0, 1, st)) return e;
       P.split = 2;  // pass B
       rc = f32 ? launch_life<float, true>(P, nblk, st) : launch_life<double, true>(P, nblk, st);
       if (rc) return rc;
+      ++launches;
     }
   }
   if (stats) HIPCHK(hipEventRecord(ev.c, st));
@@ -1152,6 +1156,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     stats->life_ms = ms_life;
     stats->queue_ms = ms_queue;
     stats->d_queue = xq[1];
+    stats->life_launches = launches;
   }
   return 0;
 }

@@ -302,6 +302,7 @@ def test_forward_peel_queue_modes(E, orc, W, prec):
             assert st["x_queue"] == 0
         else:
             assert 0 < st["x_queue"] <= st["x_peel"] and st["d_queue"] == 0
+        assert st["life_launches"] == (1 if chunk == 0 else -(-800 // chunk))
         if ref is None:
             ref = (images, st)
             continue
@@ -374,3 +375,4 @@ def test_backward_in_chunks(E, orc, W, queue):
     assert rel_l1(g, g_full) < 1e-12
     for key in ("x_path", "x_locate", "x_peel", "deposits", "events", "packages", "peels"):
         assert st[key] == st_full[key], key
+    assert st_full["life_launches"] == 2 and st["life_launches"] == 2 * -(-700 // 97)

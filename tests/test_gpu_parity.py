@@ -314,6 +314,7 @@ def test_forward_peel_queue_modes(B, orc, W, prec):
             assert st["x_queue"] == 0
         else:
             assert 0 < st["x_queue"] <= st["x_peel"] and st["d_queue"] == 0
+        assert st["life_launches"] == 1  # 3000 packages: one chunk
         if ref is None:
             ref = st
         for key in ("x_path", "x_locate", "x_peel", "deposits", "events", "peels", "packages"):
