@@ -80,10 +80,17 @@ extern "C" {
 #define MCRT_MAX_PACKAGES 20000000000000ULL /* 2e13, the paper's upper bound (Fig. 3) */
 #define MCRT_MAX_SCATTER_LIMIT 1000000
 
-/* Regular Cartesian grid (Table 1(d)): box and cells per axis. */
+/* Cartesian grid of cuboidal cells (Table 1(d)): box and cells per axis.
+ * planes NULL: regularly spaced cells (LinCub).  Otherwise a host array of
+ * the cell-boundary coordinates -- nx + 1 along x, then ny + 1 along y, then
+ * nz + 1 along z -- each run strictly increasing from the box's minimum to
+ * its maximum (equal to them exactly): cells spaced by any rule, such as
+ * the power-law spacing of PowCub (Table 1(d)).  Read only during the call.
+ * Cell m = i + nx (j + ny k) either way. */
 typedef struct {
     double xmin, xmax, ymin, ymax, zmin, zmax;
     int32_t nx, ny, nz;
+    const double *planes;
 } mcrt_grid;
 
 /* Optical properties per wavelength (Sect. 2.3); host arrays [n_lambda]:
@@ -239,7 +246,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 7
+#define MCRT_ABI_VERSION 8
 
 #ifdef __cplusplus
 }

@@ -104,17 +104,50 @@ typedef struct {
     double lo[3], hi[3], d[3];
     int n[3];
     int64_t ncell;
+    const double *pl[3]; /* rectilinear grid: the n[a] + 1 planes of axis a; NULL: regular */
 } grid_t;
 
-static void grid_init(grid_t *G, const double box[6], const int n[3])
+/* planes: NULL for regularly spaced cells (LinCub), else the cell-boundary
+ * coordinates of x, then y, then z (n + 1 each, increasing from the box's
+ * minimum to its maximum): cells spaced by any rule, such as PowCub's
+ * power law (Table 1(d)). */
+static void grid_init(grid_t *G, const double box[6], const int n[3], const double *planes)
 {
+    size_t off = 0;
     for (int a = 0; a < 3; a++) {
         G->lo[a] = box[2 * a];
         G->hi[a] = box[2 * a + 1];
         G->n[a] = n[a];
         G->d[a] = (G->hi[a] - G->lo[a]) / n[a];
+        G->pl[a] = planes ? planes + off : NULL;
+        off += (size_t)n[a] + 1;
     }
     G->ncell = (int64_t)n[0] * n[1] * n[2];
+}
+
+/* Coordinate of plane p (0..n) along axis a. */
+static double plane_at(const grid_t *G, int a, int p)
+{
+    return G->pl[a] ? G->pl[a][p] : G->lo[a] + p * G->d[a];
+}
+
+/* Cell along axis a holding coordinate x, before clamping: -1 below the
+ * grid, n above; *on_plane tells whether x is exactly a plane's coordinate.
+ * Regular grids by floor((x - lo)/d); rectilinear grids by scanning the
+ * planes for the last one at or below x. */
+static int axis_cell(const grid_t *G, int a, double x, int *on_plane)
+{
+    if (!G->pl[a]) {
+        double u = (x - G->lo[a]) / G->d[a];
+        double fu = floor(u);
+        *on_plane = (u == fu);
+        return (int)fu;
+    }
+    int i = -1;
+    for (int p = 0; p <= G->n[a]; p++)
+        if (G->pl[a][p] <= x) i = p;
+    *on_plane = (i >= 0 && G->pl[a][i] == x);
+    return i;
 }
 
 typedef struct {
@@ -188,10 +221,9 @@ static void traverse(const grid_t *G, const double o[3], const double k[3], segb
             continue;
         }
         double p = o[a] + tin * k[a];
-        double x = (p - G->lo[a]) / G->d[a];
-        double fx = floor(x);
-        int i = (int)fx;
-        if (k[a] < 0.0 && x == fx) i -= 1;
+        int on_plane;
+        int i = axis_cell(G, a, p, &on_plane);
+        if (k[a] < 0.0 && on_plane) i -= 1;
         if (i < 0) i = 0;
         if (i > G->n[a] - 1) i = G->n[a] - 1;
         idx[a] = i;
@@ -203,9 +235,9 @@ static void traverse(const grid_t *G, const double o[3], const double k[3], segb
         double tn[3];
         for (int a = 0; a < 3; a++) {
             if (k[a] > 0.0)
-                tn[a] = (G->lo[a] + (idx[a] + 1) * G->d[a] - o[a]) / k[a];
+                tn[a] = (plane_at(G, a, idx[a] + 1) - o[a]) / k[a];
             else if (k[a] < 0.0)
-                tn[a] = (G->lo[a] + idx[a] * G->d[a] - o[a]) / k[a];
+                tn[a] = (plane_at(G, a, idx[a]) - o[a]) / k[a];
             else
                 tn[a] = INFINITY;
         }
@@ -700,13 +732,13 @@ static int setup_problem(problem_t *P, const double box[6], const int n[3], cons
                          const double *kappa, const double *albedo, const double *g, int n_src, const int *src_kind,
                          const double *src_par, const double *src_lum, int n_det, const double *det_par,
                          const int *det_pix, uint64_t n_pkg, uint64_t first, uint64_t seed, double w_min,
-                         int max_scatter, unsigned flags)
+                         int max_scatter, unsigned flags, const double *planes)
 {
     if (n_src < 1 || n_src > MAX_SRC || n_det < 0 || n_det > MAX_DET || n_lambda < 1 || n_pkg < 1) return -1;
     for (int a = 0; a < 3; a++)
         if (n[a] < 1 || !(box[2 * a + 1] > box[2 * a])) return -1;
     memset(P, 0, sizeof *P);
-    grid_init(&P->G, box, n);
+    grid_init(&P->G, box, n, planes);
     P->rho = rho;
     P->n_lambda = n_lambda;
     P->kappa = kappa;
@@ -804,11 +836,11 @@ int oracle_run(const double box[6], const int n[3], const double *rho, int n_lam
                const double *albedo, const double *g, int n_src, const int *src_kind, const double *src_par,
                const double *src_lum, int n_det, const double *det_par, const int *det_pix, uint64_t n_pkg,
                uint64_t first, uint64_t seed, double w_min, int max_scatter, unsigned flags, double *images,
-               double *absorbed, double *stats, int n_threads)
+               double *absorbed, double *stats, int n_threads, const double *planes)
 {
     problem_t P;
     if (setup_problem(&P, box, n, rho, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
-                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags))
+                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes))
         return -1;
     P.mode = MODE_FORWARD;
     return simulate(&P, images, (flags & FLAG_ABSORB) ? absorbed : NULL, NULL, stats, n_threads);
@@ -821,11 +853,11 @@ int oracle_grad(const double box[6], const int n[3], const double *rho, int n_la
                 const double *albedo, const double *g, int n_src, const int *src_kind, const double *src_par,
                 const double *src_lum, int n_det, const double *det_par, const int *det_pix, uint64_t n_pkg,
                 uint64_t first, uint64_t seed, double w_min, int max_scatter, unsigned flags, const double *adj,
-                double *images, double *grad, double *stats, int n_threads)
+                double *images, double *grad, double *stats, int n_threads, const double *planes)
 {
     problem_t P;
     if (setup_problem(&P, box, n, rho, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
-                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags))
+                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes))
         return -1;
     P.mode = MODE_GRAD;
     P.adj = adj;
@@ -839,11 +871,12 @@ int oracle_reweight(const double box[6], const int n[3], const double *rho0, con
                     const double *kappa, const double *albedo, const double *g, int n_src, const int *src_kind,
                     const double *src_par, const double *src_lum, int n_det, const double *det_par,
                     const int *det_pix, uint64_t n_pkg, uint64_t first, uint64_t seed, double w_min,
-                    int max_scatter, unsigned flags, double *images, double *stats, int n_threads)
+                    int max_scatter, unsigned flags, double *images, double *stats, int n_threads,
+                    const double *planes)
 {
     problem_t P;
     if (setup_problem(&P, box, n, rho0, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
-                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags))
+                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes))
         return -1;
     P.mode = MODE_REWEIGHT;
     P.rho_eval = rho;
@@ -855,10 +888,10 @@ int oracle_reweight(const double box[6], const int n[3], const double *rho0, con
  * count.  Returns the total number of segments. */
 int64_t oracle_trace(const double box[6], const int n[3], const double *rho, double kappa, int64_t n_rays,
                      const double *origin, const double *dir, double *tau, int max_seg, int64_t *seg_cell,
-                     double *seg_len, int *n_seg)
+                     double *seg_len, int *n_seg, const double *planes)
 {
     grid_t G;
-    grid_init(&G, box, n);
+    grid_init(&G, box, n, planes);
     segbuf sb = {0};
     int64_t total = 0;
     for (int64_t q = 0; q < n_rays; q++) {
@@ -883,11 +916,11 @@ int64_t oracle_trace(const double box[6], const int n[3], const double *rho, dou
  * means isotropic emission (phase 1/4pi), else HG with parameter g. */
 int oracle_peel(const double box[6], const int n[3], const double *rho, double kappa, double g, int64_t n_events,
                 const double *pos, const double *dir_in, const double *w, int n_det, const double *det_par,
-                const int *det_pix, double *images)
+                const int *det_pix, double *images, const double *planes)
 {
     if (n_det < 1 || n_det > MAX_DET) return -1;
     grid_t G;
-    grid_init(&G, box, n);
+    grid_init(&G, box, n, planes);
     det_t det[MAX_DET];
     size_t off = 0;
     for (int d = 0; d < n_det; d++) {

@@ -3,6 +3,7 @@
 A problem is a plain dict:
   box         (xmin, xmax, ymin, ymax, zmin, zmax)
   n           (nx, ny, nz)
+  planes      optional (x, y, z) cell-boundary coordinates of a rectilinear grid
   rho         density, nz*ny*nx values, x fastest
   kappa, albedo, g         one value per wavelength
   sources     list of {kind: "point"|"expdisk", pos: (x, y, z), h_r, h_z, lum: [n_lambda]}
@@ -48,16 +49,16 @@ def _load():
         _lib.oracle_emit_direction.argtypes = [P, P]
         _lib.oracle_detector_basis.argtypes = [P, P]
         common = [P, P, P, i, P, P, P, i, P, P, P, i, P, P, u64, u64, u64, d, i, C.c_uint]
-        _lib.oracle_run.argtypes = common + [P, P, P, i]
+        _lib.oracle_run.argtypes = common + [P, P, P, i, P]
         _lib.oracle_run.restype = i
-        _lib.oracle_grad.argtypes = common + [P, P, P, P, i]
+        _lib.oracle_grad.argtypes = common + [P, P, P, P, i, P]
         _lib.oracle_grad.restype = i
         _lib.oracle_reweight.argtypes = [P, P, P, P, i, P, P, P, i, P, P, P, i, P, P, u64, u64, u64, d, i,
-                                         C.c_uint, P, P, i]
+                                         C.c_uint, P, P, i, P]
         _lib.oracle_reweight.restype = i
-        _lib.oracle_trace.argtypes = [P, P, P, d, i64, P, P, P, i, P, P, P]
+        _lib.oracle_trace.argtypes = [P, P, P, d, i64, P, P, P, i, P, P, P, P]
         _lib.oracle_trace.restype = i64
-        _lib.oracle_peel.argtypes = [P, P, P, d, d, i64, P, P, P, i, P, P, P]
+        _lib.oracle_peel.argtypes = [P, P, P, d, d, i64, P, P, P, i, P, P, P, P]
         _lib.oracle_peel.restype = i
         _lib.oracle_draw_words.argtypes = [u64, u64, i64, u32, u32, P]
     return _lib
@@ -135,6 +136,16 @@ def detector_basis(det):
     return out[0:3], out[3:6], out[6:9]
 
 
+def _planes(planes, n):
+    """Concatenated plane coordinates of a rectilinear grid (x, y, z; n + 1
+    each), or None for a regular grid."""
+    if planes is None:
+        return None
+    arr = _f64(np.concatenate([np.asarray(p, dtype=np.float64).reshape(-1) for p in planes]))
+    assert arr.size == sum(int(m) + 1 for m in n)
+    return arr
+
+
 def _marshal(prob):
     box = _f64(prob["box"])
     n = _i32(prob["n"])
@@ -151,7 +162,8 @@ def _marshal(prob):
                 if dets else np.zeros((0, 6)))
     dpix = _i32([[d["nx"], d["ny"]] for d in dets] if dets else np.zeros((0, 2)))
     npix = int(sum(d["nx"] * d["ny"] for d in dets))
-    keep = (box, n, rho, kappa, albedo, g, kind, spar, slum, dpar, dpix)
+    planes = _planes(prob.get("planes"), n)
+    keep = (box, n, rho, kappa, albedo, g, kind, spar, slum, dpar, dpix, planes)
     args = [_ptr(box), _ptr(n), _ptr(rho), nl, _ptr(kappa), _ptr(albedo), _ptr(g), len(srcs), _ptr(kind),
             _ptr(spar), _ptr(slum), len(dets), _ptr(dpar), _ptr(dpix), int(prob["n_packages"]),
             int(prob.get("first_package", 0)), int(prob.get("seed", 4357)), float(prob.get("w_min", 1e-4)),
@@ -170,7 +182,7 @@ def run(prob, threads=1):
     images = np.zeros((_comps(prob), nl, npix))
     absorbed = np.zeros((nl, ncell)) if int(prob.get("flags", 7)) & FLAG_ABSORB else None
     stats = np.zeros(len(STAT_NAMES))
-    rc = _load().oracle_run(*args, _ptr(images), _ptr(absorbed), _ptr(stats), int(threads))
+    rc = _load().oracle_run(*args, _ptr(images), _ptr(absorbed), _ptr(stats), int(threads), _ptr(keep[11]))
     if rc != 0:
         raise ValueError("oracle_run rejected its arguments")
     return images, absorbed, dict(zip(STAT_NAMES, stats.tolist()))
@@ -184,7 +196,7 @@ def grad(prob, adj, threads=1):
     images = np.zeros((_comps(prob), nl, npix))
     g = np.zeros(ncell)
     stats = np.zeros(len(STAT_NAMES))
-    rc = _load().oracle_grad(*args, _ptr(adj), _ptr(images), _ptr(g), _ptr(stats), int(threads))
+    rc = _load().oracle_grad(*args, _ptr(adj), _ptr(images), _ptr(g), _ptr(stats), int(threads), _ptr(keep[11]))
     if rc != 0:
         raise ValueError("oracle_grad rejected its arguments")
     return g, images, dict(zip(STAT_NAMES, stats.tolist()))
@@ -198,16 +210,18 @@ def reweight(prob, rho_eval, threads=1):
     images = np.zeros((_comps(prob), nl, npix))
     stats = np.zeros(len(STAT_NAMES))
     a = args[:3] + [_ptr(rho_eval)] + args[3:]
-    rc = _load().oracle_reweight(*a, _ptr(images), _ptr(stats), int(threads))
+    rc = _load().oracle_reweight(*a, _ptr(images), _ptr(stats), int(threads), _ptr(keep[11]))
     if rc != 0:
         raise ValueError("oracle_reweight rejected its arguments")
     return images, dict(zip(STAT_NAMES, stats.tolist()))
 
 
-def trace(box, n, rho, kappa, origins, dirs, max_seg=0):
+def trace(box, n, rho, kappa, origins, dirs, max_seg=0, planes=None):
     """Optical depth along each ray to the grid boundary; with max_seg > 0 also
-    the segment lists.  Returns (tau, total_segments, seg_cell, seg_len, n_seg)."""
+    the segment lists.  Returns (tau, total_segments, seg_cell, seg_len, n_seg).
+    planes: (x, y, z) plane coordinates of a rectilinear grid, or None."""
     box, n, rho = _f64(box), _i32(n), _f64(rho).reshape(-1)
+    pl = _planes(planes, n)
     o, k = _f64(origins).reshape(-1, 3), _f64(dirs).reshape(-1, 3)
     nr = o.shape[0]
     tau = np.zeros(nr)
@@ -215,13 +229,14 @@ def trace(box, n, rho, kappa, origins, dirs, max_seg=0):
     cell = np.zeros((nr, max(max_seg, 1)), dtype=np.int64) if max_seg > 0 else None
     length = np.zeros((nr, max(max_seg, 1))) if max_seg > 0 else None
     tot = _load().oracle_trace(_ptr(box), _ptr(n), _ptr(rho), float(kappa), nr, _ptr(o), _ptr(k), _ptr(tau),
-                               int(max_seg), _ptr(cell), _ptr(length), _ptr(nseg))
+                               int(max_seg), _ptr(cell), _ptr(length), _ptr(nseg), _ptr(pl))
     return tau, int(tot), cell, length, nseg
 
 
-def peel(box, n, rho, kappa, g, pos, dir_in, w, detectors):
+def peel(box, n, rho, kappa, g, pos, dir_in, w, detectors, planes=None):
     """Peel-off of an event list into the frames of one wavelength (fresh zero images)."""
     box, n, rho = _f64(box), _i32(n), _f64(rho).reshape(-1)
+    pl = _planes(planes, n)
     pos = _f64(pos).reshape(-1, 3)
     din = None if dir_in is None else _f64(dir_in).reshape(-1, 3)
     w = _f64(w).reshape(-1)
@@ -229,7 +244,7 @@ def peel(box, n, rho, kappa, g, pos, dir_in, w, detectors):
     dpix = _i32([[d["nx"], d["ny"]] for d in detectors])
     images = np.zeros(int(sum(d["nx"] * d["ny"] for d in detectors)))
     rc = _load().oracle_peel(_ptr(box), _ptr(n), _ptr(rho), float(kappa), float(g), pos.shape[0], _ptr(pos),
-                             _ptr(din), _ptr(w), len(detectors), _ptr(dpar), _ptr(dpix), _ptr(images))
+                             _ptr(din), _ptr(w), len(detectors), _ptr(dpar), _ptr(dpix), _ptr(images), _ptr(pl))
     if rc != 0:
         raise ValueError("oracle_peel rejected its arguments")
     return images

@@ -57,7 +57,28 @@ struct GridDev {
   int nb[3];      // bricks along each axis
   int bstride[3]; // brick strides in cells: 2^(lb0+lb1+lb2), nb0 of them, nb0*nb1 of them
   int ncell_pad;  // cells of the bricked arrays (whole bricks)
+  // Rectilinear grids (rect = 1; cells spaced by any rule, Table 1(d)):
+  // the cell-boundary planes of each axis, n[a] + 1 of them, absolute (pa)
+  // and relative to the first plane (qd), FP64.  Regular grids (rect = 0)
+  // use lo + p d.
+  int rect;
+  const double* pa[3];
+  const double* qd[3];
 };
+
+// Cell along one axis of a rectilinear grid: the largest c in [0, n - 1]
+// with P[c] <= x (0 below the first plane).
+MCRT_HD int rect_cell(const double* P, int n, double x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (P[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
 
 // Bricked address of cell (i0, i1, i2).
 MCRT_HD int brick_addr(const GridDev& G, const int i[3]) {
@@ -264,9 +285,21 @@ MCRT_HD int frame_pixel(const DetDev& D, const double r[3]) {
 // for an axis parallel to the ray, whose t0 is +inf and dt 0); the walk
 // ends as soon as some i[a] leaves [0, n[a]).
 
+//
+// On a rectilinear grid the planes are not evenly spaced: there e[a] is the
+// entry point's coordinate relative to the axis's first plane (FP64), dt[a]
+// is 1 / k[a], and tp[a] = (Q[p] - e[a]) dt[a] is the crossing time of the
+// next plane p ahead (Q the FP64 relative plane table), reloaded each time
+// the walk crosses a plane along a.  The difference is taken in FP64 -- in
+// precision R its rounding would scale with the box, not with t, and rays
+// nearly parallel to an axis would magnify it -- so the FP32 walk's times
+// carry a relative error of a few units of R, as on a regular grid.
+
 template <typename R>
 struct Ray {
   R t0[3], dt[3];
+  R tp[3];       // rectilinear grids only
+  double e[3];   // rectilinear grids only
   int j[3], i[3], s[3];
   R t, tau;
   double tin;  // FP64 entry time (0 for rays starting inside)
@@ -276,11 +309,23 @@ struct Ray {
 MCRT_HD float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
 MCRT_HD double fmaR(double a, double b, double c) { return fma(a, b, c); }
 
+// Crossing time of the next plane ahead along axis a of a rectilinear grid
+// (+inf for an axis parallel to the ray).  The plane index is clamped to the
+// table: after the walk has left the grid the value is never used.
+template <typename R>
+MCRT_HD R rect_tplane(const Ray<R>& ry, const GridDev& G, int a) {
+  if (ry.s[a] == 0) return R(INFINITY);
+  int p = ry.i[a] + (ry.s[a] > 0 ? 1 : 0);
+  p = p < 0 ? 0 : (p > G.n[a] ? G.n[a] : p);
+  return (R)((G.qd[a][p] - ry.e[a]) * (double)ry.dt[a]);
+}
+
 // Sets up the walk of o + t k (t >= 0): slab entry for origins outside the
-// grid; cell indices by floor with the lower cell for a coordinate on a wall
+// grid; cell indices by floor (regular grids) or by search in the plane
+// table (rectilinear grids), with the lower cell for a coordinate on a wall
 // while moving down; rays missing the grid (or with non-finite data) are
 // left inactive with tau = 0.
-template <typename R>
+template <typename R, bool RECT = false>
 MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const double k[3]) {
   double tin = 0.0, tout = INFINITY;
   int entry = -1;
@@ -318,6 +363,11 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const do
     int i;
     if (a == entry) {
       i = k[a] > 0.0 ? 0 : G.n[a] - 1;
+    } else if constexpr (RECT) {
+      const double x = o[a] + tin * k[a];
+      i = rect_cell(G.pa[a], G.n[a], x);
+      if (!par[a] && k[a] < 0.0 && x == G.pa[a][i]) i -= 1;
+      i = i < 0 ? 0 : i;
     } else {
       const double p = o[a] + tin * k[a];
       const double x = (p - G.lo[a]) * G.inv_d[a];
@@ -328,7 +378,13 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const do
     }
     ry.i[a] = i;
     ry.j[a] = 0;
-    if (par[a]) {
+    if constexpr (RECT) {
+      ry.s[a] = par[a] ? 0 : (k[a] > 0.0 ? 1 : -1);
+      ry.e[a] = o[a] + tin * k[a] - G.pa[a][0];
+      ry.t0[a] = R(0);
+      ry.dt[a] = (R)inv[a];
+      ry.tp[a] = rect_tplane(ry, G, a);
+    } else if (par[a]) {
       ry.t0[a] = R(INFINITY);
       ry.dt[a] = R(0);
       ry.s[a] = 0;
@@ -355,15 +411,12 @@ MCRT_HD int ray_cell(const Ray<R>& ry, const GridDev& G) {
 }
 
 // Crossing time of the next plane ahead along axis a.
-template <typename R>
+template <typename R, bool RECT = false>
 MCRT_HD R ray_tplane(const Ray<R>& ry, int a) {
-  return fmaR((R)ry.j[a], ry.dt[a], ry.t0[a]);
-}
-
-// End time of the current segment (the nearest plane ahead).
-template <typename R>
-MCRT_HD R ray_tnext(const Ray<R>& ry) {
-  return fmin(ray_tplane(ry, 0), fmin(ray_tplane(ry, 1), ray_tplane(ry, 2)));
+  if constexpr (RECT)
+    return ry.tp[a];
+  else
+    return fmaR((R)ry.j[a], ry.dt[a], ry.t0[a]);
 }
 
 // The next D cells of the walk, as a block: their bricked addresses, the end
@@ -388,15 +441,17 @@ struct WalkBlock {
 };
 
 // LOAD = false skips the density loads (walks whose work does not depend on
-// the densities, such as the adjoint's peel-ray deposits).
+// the densities, such as the adjoint's peel-ray deposits).  The grid kind
+// comes from the accessor (Mem::kRect).
 template <int D, typename R, class Mem, bool LOAD = true>
 MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, const GridDev& G, Mem& M) {
+  constexpr bool RECT = Mem::kRect;
   b.n = 0;
   b.adv = 0;
   b.out = false;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    const R tx = ray_tplane(ry, 0), ty = ray_tplane(ry, 1), tz = ray_tplane(ry, 2);
+    const R tx = ray_tplane<R, RECT>(ry, 0), ty = ray_tplane<R, RECT>(ry, 1), tz = ray_tplane<R, RECT>(ry, 2);
     const R tm = fmin(tx, fmin(ty, tz));
     const bool live = !b.out;
     const bool ax = live && tx == tm, ay = live && ty == tm, az = live && tz == tm;
@@ -408,6 +463,11 @@ MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, const GridDev& G, Me
     ry.j[0] += ax;
     ry.j[1] += ay;
     ry.j[2] += az;
+    if constexpr (RECT) {
+      if (ax) ry.tp[0] = rect_tplane(ry, G, 0);
+      if (ay) ry.tp[1] = rect_tplane(ry, G, 1);
+      if (az) ry.tp[2] = rect_tplane(ry, G, 2);
+    }
     b.adv |= ((unsigned)ax | ((unsigned)ay << 1) | ((unsigned)az << 2)) << (3 * d);
     b.n += live;
     const bool outside = (unsigned)ry.i[0] >= (unsigned)G.n[0] || (unsigned)ry.i[1] >= (unsigned)G.n[1] ||
@@ -422,8 +482,8 @@ MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, const GridDev& G, Me
 
 // Undoes the plane crossings of sub-steps d .. D-1 of the last block, so the
 // ray again describes the walk inside cell b.cell[d].
-template <int D, typename R>
-MCRT_HD void ray_rewind(Ray<R>& ry, const WalkBlock<D, R>& b, int d) {
+template <int D, typename R, bool RECT = false>
+MCRT_HD void ray_rewind(Ray<R>& ry, const WalkBlock<D, R>& b, int d, const GridDev& G) {
   for (int e = d; e < D; ++e) {
     const unsigned m = b.adv >> (3 * e);
 #pragma unroll
@@ -433,19 +493,28 @@ MCRT_HD void ray_rewind(Ray<R>& ry, const WalkBlock<D, R>& b, int d) {
       ry.i[a] -= x * ry.s[a];
     }
   }
+  if constexpr (RECT) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ry.tp[a] = rect_tplane(ry, G, a);
+  }
 }
 
 // FP64 entry time of the current cell, in the original parametrisation of
 // the ray: the latest plane already crossed, or the ray's entry time.  Moving
 // up into cell i the last plane crossed is plane i; moving down, plane i + 1.
-template <typename R>
+template <typename R, bool RECT = false>
 MCRT_HD double ray_cell_entry64(const Ray<R>& ry, const GridDev& G, const double o[3], const double k[3]) {
   double t = ry.tin;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (ry.s[a] == 0 || ry.j[a] == 0) continue;
     const int p = ry.s[a] > 0 ? ry.i[a] : ry.i[a] + 1;
-    const double tl = (G.lo[a] + (double)p * G.d[a] - o[a]) / k[a];
+    double plane;
+    if constexpr (RECT)
+      plane = G.pa[a][p];
+    else
+      plane = G.lo[a] + (double)p * G.d[a];
+    const double tl = (plane - o[a]) / k[a];
     t = fmax(t, tl);
   }
   return t;

@@ -46,7 +46,51 @@ inline int check_grid(const mcrt_grid* g) {
   for (int a = 0; a < 3; ++a)
     if (!finite(b[2 * a]) || !finite(b[2 * a + 1]) || !(b[2 * a + 1] > b[2 * a]))
       return fail(MCRT_EINVAL, "grid extent along axis %d must be finite and increasing", a);
+  if (g->planes) {
+    const int n[3] = {g->nx, g->ny, g->nz};
+    const double* p = g->planes;
+    for (int a = 0; a < 3; ++a) {
+      if (p[0] != b[2 * a] || p[n[a]] != b[2 * a + 1])
+        return fail(MCRT_EINVAL, "planes along axis %d must start at the box minimum and end at its maximum", a);
+      for (int q = 0; q < n[a]; ++q)
+        if (!finite(p[q + 1]) || !(p[q + 1] > p[q]))
+          return fail(MCRT_EINVAL, "planes along axis %d must be finite and strictly increasing (plane %d)", a, q + 1);
+      p += n[a] + 1;
+    }
+  }
   return 0;
+}
+
+inline size_t align_up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Plane tables of a rectilinear grid (0 bytes for a regular one): absolute,
+// then relative to each axis's first plane, FP64, n + 1 per axis, each table
+// 256-byte aligned.
+inline size_t plane_bytes(const GridDev& G) {
+  if (!G.rect) return 0;
+  const size_t n = (size_t)(G.n[0] + 1) + (G.n[1] + 1) + (G.n[2] + 1);
+  return 2 * align_up256(n * sizeof(double));
+}
+
+// Writes the tables of g at `host` (plane_bytes(G) bytes) and points G at
+// their copy at `dev` (the same bytes in device memory, or `host` itself).
+inline void put_planes(const mcrt_grid& g, GridDev& G, unsigned char* host, const unsigned char* dev) {
+  if (!G.rect) return;
+  const size_t n = (size_t)(G.n[0] + 1) + (G.n[1] + 1) + (G.n[2] + 1);
+  const size_t o_qd = align_up256(n * sizeof(double));
+  double* pa = reinterpret_cast<double*>(host);
+  double* qd = reinterpret_cast<double*>(host + o_qd);
+  size_t o = 0;
+  for (int a = 0; a < 3; ++a) {
+    const double* P = g.planes + o;
+    for (int p = 0; p <= G.n[a]; ++p) {
+      pa[o + p] = P[p];
+      qd[o + p] = P[p] - P[0];
+    }
+    G.pa[a] = reinterpret_cast<const double*>(dev) + o;
+    G.qd[a] = reinterpret_cast<const double*>(dev + o_qd) + o;
+    o += G.n[a] + 1;
+  }
 }
 
 inline int ilog2_ceil(int n) {
@@ -108,6 +152,8 @@ inline int make_grid(const mcrt_grid& g, int elem_bytes, int brick_shape, GridDe
     G.d[a] = (G.hi[a] - G.lo[a]) / n[a];
     G.inv_d[a] = 1.0 / G.d[a];
   }
+  G.rect = g.planes ? 1 : 0;
+  for (int a = 0; a < 3; ++a) G.pa[a] = G.qd[a] = nullptr;
   G.stride[0] = 1;
   G.stride[1] = g.nx;
   G.stride[2] = g.nx * g.ny;

@@ -140,8 +140,9 @@ __device__ __forceinline__ unsigned long long* wave_reservoir(unsigned long long
 // ---------------------------------------------------------------------------
 // Device memory accessors.
 
-template <typename R>
+template <typename R, bool RECT>
 struct LifeMem {
+  static constexpr bool kRect = RECT;
   const R* __restrict__ rho_;
   const RunParams& P;
   unsigned long long* res;
@@ -190,8 +191,9 @@ struct LifeMem {
   }
 };
 
-template <typename R>
+template <typename R, bool RECT>
 struct TraceMem {
+  static constexpr bool kRect = RECT;
   const R* __restrict__ rho_;
   const TraceParams& P;
   unsigned long long* res;
@@ -213,8 +215,9 @@ struct TraceMem {
   }
 };
 
-template <typename R>
+template <typename R, bool RECT>
 struct PeelMem {
+  static constexpr bool kRect = RECT;
   const R* __restrict__ rho_;
   const PeelParams& P;
   unsigned long long* res;
@@ -237,15 +240,16 @@ struct PeelMem {
 // Kernels.
 
 // The life-cycle kernel body; k_life (FP32 walk) and k_life64 (FP64 walk)
-// launch it.  The FP64 kernel asks for two wavefronts per SIMD, which its
-// register use would otherwise just miss.
-template <typename R, bool ADJ>
+// launch it, for regular (RECT = false) or rectilinear grids.  The FP64
+// kernel asks for two wavefronts per SIMD, which its register use would
+// otherwise just miss.
+template <typename R, bool ADJ, bool RECT>
 __device__ __forceinline__ void life_body(const RunParams& P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2], job_slots[kWavesPerBlock][2];
   __shared__ long long dep_idx[kWavesPerBlock][64 * kBlockWalk];
   __shared__ double dep_val[kWavesPerBlock][64 * kBlockWalk];
   const int wave = threadIdx.x / 64;
-  LifeMem<R> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots), wave_reservoir(job_slots)};
+  LifeMem<R, RECT> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots), wave_reservoir(job_slots)};
   Lane<R> L;
   lane_init(L);
   for (;;) {
@@ -284,20 +288,20 @@ __device__ __forceinline__ void life_body(const RunParams& P) {
   }
 }
 
-template <typename R, bool ADJ>
+template <typename R, bool ADJ, bool RECT>
 __global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
-  life_body<R, ADJ>(P);
+  life_body<R, ADJ, RECT>(P);
 }
 
-template <bool ADJ>
+template <bool ADJ, bool RECT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_life64(const RunParams P) {
-  life_body<double, ADJ>(P);
+  life_body<double, ADJ, RECT>(P);
 }
 
-template <typename R>
+template <typename R, bool RECT>
 __global__ void __launch_bounds__(kBlock) k_trace(const TraceParams P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2];
-  TraceMem<R> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots)};
+  TraceMem<R, RECT> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots)};
   TraceLane<R> L;
   trace_init(L);
   for (;;) {
@@ -318,10 +322,10 @@ __global__ void __launch_bounds__(kBlock) k_trace(const TraceParams P) {
   }
 }
 
-template <typename R>
+template <typename R, bool RECT>
 __global__ void __launch_bounds__(kBlock) k_peel(const PeelParams P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2];
-  PeelMem<R> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots)};
+  PeelMem<R, RECT> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots)};
   PeelLane<R> L;
   peel_init(L);
   for (;;) {
@@ -538,8 +542,9 @@ struct PeelJobParams {
 // into the workgroup's LDS table (open addressing, linear probing over at
 // most kProbes slots); a deposit that finds no slot goes straight to the
 // global tally.
-template <typename R>
+template <typename R, bool RECT>
 struct PeelJobMem {
+  static constexpr bool kRect = RECT;
   const R* __restrict__ rho_;
   int* tk;
   double* tv;
@@ -586,11 +591,11 @@ __device__ __forceinline__ void flush_images(bool& has, long long ii, double c, 
 // loads).  Forward: C = v e^-tau goes to the ray's pixel (flush_images).
 // Adjoint: q = (dL/dI) v e^-tau goes to the event scratch, and the job's v
 // becomes the deposit weight -q kappa (0: no deposit walk).
-template <typename R, bool ADJ>
+template <typename R, bool ADJ, bool RECT>
 __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2];
   unsigned long long* res = wave_reservoir(slots);
-  const PeelJobMem<R> M{static_cast<const R*>(P.rho), nullptr, nullptr, P.grad};
+  const PeelJobMem<R, RECT> M{static_cast<const R*>(P.rho), nullptr, nullptr, P.grad};
   const unsigned n_jobs = *P.n_sorted;
   unsigned long long nx = 0;
   Ray<R> ry;
@@ -629,7 +634,7 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
       job = P.perm[qi];
       const PeelJob& J = P.jobs[job];
       kap = (R)P.lam[J.lam].kappa;
-      ray_begin(ry, P.G, J.r, P.det[J.d].kd);
+      ray_begin<R, RECT>(ry, P.G, J.r, P.det[J.d].kd);
       pending = true;
     }
     if (!ADJ) flush_images(has, out_ii, out_c, P.images);
@@ -649,7 +654,7 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
 // The deposit walks of the sorted queue: chunks of consecutive sorted jobs
 // per workgroup, deposits summed per cell in the LDS table, one global
 // atomic per distinct cell and chunk.  Jobs whose weight is 0 are skipped.
-template <typename R>
+template <typename R, bool RECT>
 __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams P) {
   __shared__ int tk[kTable];
   __shared__ double tv[kTable];
@@ -658,7 +663,7 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
     tk[i] = -1;
     tv[i] = 0.0;
   }
-  const PeelJobMem<R> M{static_cast<const R*>(P.rho), tk, tv, P.grad};
+  const PeelJobMem<R, RECT> M{static_cast<const R*>(P.rho), tk, tv, P.grad};
   const unsigned n_jobs = *P.n_sorted;
   unsigned long long nd = 0;
   for (;;) {
@@ -683,7 +688,7 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
         }
         const PeelJob& J = P.jobs[P.perm[qi]];
         w = J.v;
-        if (w != 0.0) ray_begin(ry, P.G, J.r, P.det[J.d].kd);
+        if (w != 0.0) ray_begin<R, RECT>(ry, P.G, J.r, P.det[J.d].kd);
       }
       const unsigned long long live = __ballot(!done);
       if (live == 0ull) break;
@@ -771,6 +776,15 @@ int persistent_grid(K kernel, int blocks_per_cu, int* grid_out) {
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0));
   if (blocks_per_cu > 0) nb = blocks_per_cu;
   *grid_out = std::max(1, nb) * std::max(1, cus);
+  return 0;
+}
+
+// Launches a persistent kernel with a full-occupancy grid of kBlock threads.
+template <typename K, typename Params>
+int launch_persistent(K kernel, const Params& P, hipStream_t st) {
+  int nblk = 0;
+  if (int e = persistent_grid(kernel, 0, &nblk)) return e;
+  hipLaunchKernelGGL(kernel, dim3(nblk), dim3(kBlock), 0, st, P);
   return 0;
 }
 
@@ -888,8 +902,26 @@ int reset_counters(unsigned long long* ctr, int w, int n, hipStream_t st) {
   return zero_fill(reinterpret_cast<double*>(ctr + w), n, st);
 }
 
-// Sorts the chunk's queued peel rays by key and walks them: optical depth
-// (and the image, forward), then the adjoint's deposit walks.
+// The queue's walks: optical depth (and the image, forward), then the
+// adjoint's deposit walks.
+template <typename R, bool ADJ, bool RECT>
+int walk_peel_jobs(const PeelJobParams& J, hipStream_t st) {
+  int nblk = 0;
+  if (int e = persistent_grid(k_peeltau<R, ADJ, RECT>, 0, &nblk)) return e;
+  hipLaunchKernelGGL((k_peeltau<R, ADJ, RECT>), dim3(nblk), dim3(kBlock), 0, st, J);
+  if (ADJ) {
+    int dev = 0, cus = 0, nb = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peeldep<R, RECT>, kBundleThreads, 0));
+    hipLaunchKernelGGL((k_peeldep<R, RECT>), dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0, st,
+                       J);
+  }
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+// Sorts the chunk's queued peel rays by key and walks them.
 template <typename R, bool ADJ>
 int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ctr, hipStream_t st) {
   const long long n_cnt = q.n_keys * kSortBlocks;
@@ -922,34 +954,36 @@ int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ct
   J.n_chunk = P.n_chunk;
   J.ctr = ctr;
   J.batch = 16;
-  int nblk = 0;
-  if (int e = persistent_grid(k_peeltau<R, ADJ>, 0, &nblk)) return e;
-  hipLaunchKernelGGL((k_peeltau<R, ADJ>), dim3(nblk), dim3(kBlock), 0, st, J);
-  if (ADJ) {
-    int dev = 0, cus = 0, nb = 0;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peeldep<R>, kBundleThreads, 0));
-    hipLaunchKernelGGL(k_peeldep<R>, dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0, st, J);
-  }
-  HIPCHK(hipGetLastError());
-  return 0;
+  return P.G.rect ? walk_peel_jobs<R, ADJ, true>(J, st) : walk_peel_jobs<R, ADJ, false>(J, st);
+}
+
+template <typename R, bool ADJ, bool RECT>
+int life_grid_k(int blocks_per_cu, int* nblk) {
+  if constexpr (std::is_same<R, double>::value)
+    return persistent_grid(k_life64<ADJ, RECT>, blocks_per_cu, nblk);
+  else
+    return persistent_grid(k_life<R, ADJ, RECT>, blocks_per_cu, nblk);
 }
 
 template <typename R, bool ADJ>
-int life_grid(int blocks_per_cu, int* nblk) {
+int life_grid(bool rect, int blocks_per_cu, int* nblk) {
+  return rect ? life_grid_k<R, ADJ, true>(blocks_per_cu, nblk) : life_grid_k<R, ADJ, false>(blocks_per_cu, nblk);
+}
+
+template <typename R, bool ADJ, bool RECT>
+void launch_life_k(const RunParams& P, int nblk, hipStream_t st) {
   if constexpr (std::is_same<R, double>::value)
-    return persistent_grid(k_life64<ADJ>, blocks_per_cu, nblk);
+    hipLaunchKernelGGL((k_life64<ADJ, RECT>), dim3(nblk), dim3(kBlock), 0, st, P);
   else
-    return persistent_grid(k_life<R, ADJ>, blocks_per_cu, nblk);
+    hipLaunchKernelGGL((k_life<R, ADJ, RECT>), dim3(nblk), dim3(kBlock), 0, st, P);
 }
 
 template <typename R, bool ADJ>
 int launch_life(const RunParams& P, int nblk, hipStream_t st) {
-  if constexpr (std::is_same<R, double>::value)
-    hipLaunchKernelGGL((k_life64<ADJ>), dim3(nblk), dim3(kBlock), 0, st, P);
+  if (P.G.rect)
+    launch_life_k<R, ADJ, true>(P, nblk, st);
   else
-    hipLaunchKernelGGL((k_life<R, ADJ>), dim3(nblk), dim3(kBlock), 0, st, P);
+    launch_life_k<R, ADJ, false>(P, nblk, st);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -984,10 +1018,11 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const int nl = P.n_lambda;
   const bool f32 = opts->precision == MCRT_PREC_FP32;
   int nblk = 0;
-  if (int e = adjoint ? (f32 ? life_grid<float, true>(opts->launch_blocks, &nblk)
-                             : life_grid<double, true>(opts->launch_blocks, &nblk))
-                      : (f32 ? life_grid<float, false>(opts->launch_blocks, &nblk)
-                             : life_grid<double, false>(opts->launch_blocks, &nblk)))
+  const bool rect = P.G.rect != 0;
+  if (int e = adjoint ? (f32 ? life_grid<float, true>(rect, opts->launch_blocks, &nblk)
+                             : life_grid<double, true>(rect, opts->launch_blocks, &nblk))
+                      : (f32 ? life_grid<float, false>(rect, opts->launch_blocks, &nblk)
+                             : life_grid<double, false>(rect, opts->launch_blocks, &nblk)))
     return e;
   // packages run in equal chunks: the adjoint's event scratch holds, per
   // package, T and q per frame for kEventsKept events plus the sum of q
@@ -1011,7 +1046,8 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const size_t off_lam = 0;
   const size_t off_det = align256(sizeof(LamDev) * nl);
   const size_t off_src = off_det + align256(sizeof(DetDev) * pr.det.size());
-  const size_t off_cnt = off_src + align256(sizeof(SrcDev) * pr.src.size());
+  const size_t off_pl = off_src + align256(sizeof(SrcDev) * pr.src.size());
+  const size_t off_cnt = off_pl + host::plane_bytes(P.G);
   const size_t off_rho = off_cnt + 256;
   const size_t off_tal = off_rho + align256((size_t)P.G.ncell_pad * (f32 ? 4 : 8));
   const size_t off_evs = off_tal + align256(sizeof(double) * (size_t)n_tally);
@@ -1025,6 +1061,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   DeviceBlock blk;
   blk.st = st;
   HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), bytes, st));
+  host::put_planes(*grid, P.G, blob.data() + off_pl, blk.ptr + off_pl);
   HIPCHK(hipMemcpyAsync(blk.ptr, blob.data(), off_rho, hipMemcpyHostToDevice, st));
   if (int e = brick_density(P.G, rho_dev, blk.ptr + off_rho, f32, st)) return e;
   double* const user_tally = adjoint ? P.grad : P.absorbed;
@@ -1229,22 +1266,21 @@ int trace_path(const mcrt_grid* grid, const void* rho_dev, double kappa, int pre
     P.batch = 16;
     DeviceBlock blk;
     blk.st = st;
-    const unsigned long long zeros[3] = {0, 0, 0};
     const bool f32 = precision == MCRT_PREC_FP32;
-    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), 256 + (size_t)P.G.ncell_pad * (f32 ? 4 : 8), st));
-    HIPCHK(hipMemcpyAsync(blk.ptr, zeros, sizeof zeros, hipMemcpyHostToDevice, st));
-    if (int e = brick_density(P.G, rho_dev, blk.ptr + 256, f32, st)) return e;
-    P.rho = blk.ptr + 256;
+    const size_t off_rho = 256 + host::plane_bytes(P.G);  // counters, plane tables, densities
+    std::vector<unsigned char> blob(off_rho, 0);
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), off_rho + (size_t)P.G.ncell_pad * (f32 ? 4 : 8), st));
+    host::put_planes(*grid, P.G, blob.data() + 256, blk.ptr + 256);
+    HIPCHK(hipMemcpyAsync(blk.ptr, blob.data(), off_rho, hipMemcpyHostToDevice, st));
+    if (int e = brick_density(P.G, rho_dev, blk.ptr + off_rho, f32, st)) return e;
+    P.rho = blk.ptr + off_rho;
     P.work = reinterpret_cast<unsigned long long*>(blk.ptr);
     P.counters = P.work + 1;
-    int nblk = 0;
-    if (f32) {
-      if (int e = persistent_grid(k_trace<float>, 0, &nblk)) return e;
-      hipLaunchKernelGGL(k_trace<float>, dim3(nblk), dim3(kBlock), 0, st, P);
-    } else {
-      if (int e = persistent_grid(k_trace<double>, 0, &nblk)) return e;
-      hipLaunchKernelGGL(k_trace<double>, dim3(nblk), dim3(kBlock), 0, st, P);
-    }
+    const int r = f32 ? (P.G.rect ? launch_persistent(k_trace<float, true>, P, st)
+                                  : launch_persistent(k_trace<float, false>, P, st))
+                      : (P.G.rect ? launch_persistent(k_trace<double, true>, P, st)
+                                  : launch_persistent(k_trace<double, false>, P, st));
+    if (r) return r;
     HIPCHK(hipGetLastError());
     if (crossings_host || lists) {
       unsigned long long c[2] = {0, 0};
@@ -1275,13 +1311,15 @@ int peel_off(const mcrt_grid* grid, const void* rho_dev, double kappa, double g,
     const bool f32 = precision == MCRT_PREC_FP32;
     std::vector<DetDev> det = host::make_dets(n_det, detectors, nullptr);
     const size_t off_cnt = align256(sizeof(DetDev) * det.size());
-    const size_t off_rho = off_cnt + 256;
+    const size_t off_pl = off_cnt + 256;
+    const size_t off_rho = off_pl + host::plane_bytes(P.G);
     const size_t bytes = off_rho + (size_t)P.G.ncell_pad * (f32 ? 4 : 8);
     std::vector<unsigned char> blob(off_rho, 0);
     std::memcpy(blob.data(), det.data(), sizeof(DetDev) * det.size());
     DeviceBlock blk;
     blk.st = st;
     HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), bytes, st));
+    host::put_planes(*grid, P.G, blob.data() + off_pl, blk.ptr + off_pl);
     HIPCHK(hipMemcpyAsync(blk.ptr, blob.data(), off_rho, hipMemcpyHostToDevice, st));
     if (int e = brick_density(P.G, rho_dev, blk.ptr + off_rho, f32, st)) return e;
     P.rho = blk.ptr + off_rho;
@@ -1296,14 +1334,11 @@ int peel_off(const mcrt_grid* grid, const void* rho_dev, double kappa, double g,
     P.images = images_dev;
     P.work = reinterpret_cast<unsigned long long*>(blk.ptr + off_cnt);
     P.batch = 16;
-    int nblk = 0;
-    if (f32) {
-      if (int e = persistent_grid(k_peel<float>, 0, &nblk)) return e;
-      hipLaunchKernelGGL(k_peel<float>, dim3(nblk), dim3(kBlock), 0, st, P);
-    } else {
-      if (int e = persistent_grid(k_peel<double>, 0, &nblk)) return e;
-      hipLaunchKernelGGL(k_peel<double>, dim3(nblk), dim3(kBlock), 0, st, P);
-    }
+    const int r = f32 ? (P.G.rect ? launch_persistent(k_peel<float, true>, P, st)
+                                  : launch_persistent(k_peel<float, false>, P, st))
+                      : (P.G.rect ? launch_persistent(k_peel<double, true>, P, st)
+                                  : launch_persistent(k_peel<double, false>, P, st));
+    if (r) return r;
     HIPCHK(hipGetLastError());
     return 0;
   } catch (...) {

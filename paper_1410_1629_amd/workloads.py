@@ -7,6 +7,7 @@ arithmetic and imports neither side.
 
 Problem dict keys:
   name, box (xmin, xmax, ymin, ymax, zmin, zmax), n (nx, ny, nz),
+  optional planes (x, y, z cell boundaries of a rectilinear grid),
   rho (float64 array [nz, ny, nx]; for precision 1 its values are already
   float32-representable), kappa / albedo / g (one value per wavelength),
   sources [{kind, pos, h_r, h_z, lum[n_lambda]}],
@@ -45,11 +46,36 @@ def cell_centres(box, n):
     return x, y, z
 
 
-def exp_disk_density(box, n, rho0, h_r, h_z):
-    """rho0 * exp(-R/h_R - |z|/h_z) sampled at cell centres (float64 [nz,ny,nx])."""
-    x, y, z = cell_centres(box, n)
+def exp_disk_density(box, n, rho0, h_r, h_z, planes=None):
+    """rho0 * exp(-R/h_R - |z|/h_z) sampled at cell centres (float64 [nz,ny,nx]);
+    planes: the (x, y, z) cell boundaries of a rectilinear grid, else regular cells."""
+    if planes is None:
+        x, y, z = cell_centres(box, n)
+    else:
+        x, y, z = plane_centres(planes)
     R = np.sqrt(x * x + y * y)
     return rho0 * np.exp(-R / h_r - np.abs(z) / h_z)
+
+
+def power_law_planes(lo, hi, n, ratio):
+    """Cell boundaries of a power-law mesh on [lo, hi] (the spacing of the
+    PowCub grid, Table 1(d)): n cells whose widths are symmetric about the
+    centre and grow geometrically outward, the outermost `ratio` times as
+    wide as the innermost (ratio 1: regular cells).  Returns n + 1
+    increasing coordinates, the first and last exactly lo and hi."""
+    k = np.abs(np.arange(n) - (n - 1) / 2.0)
+    k = k - k.min()
+    w = np.power(float(ratio), k / k.max()) if n > 2 else np.ones(n)
+    p = lo + (hi - lo) * np.concatenate([[0.0], np.cumsum(w) / w.sum()])
+    p[0], p[-1] = lo, hi
+    assert np.all(np.diff(p) > 0)
+    return p
+
+
+def plane_centres(planes):
+    """Cell-centre coordinates of a rectilinear grid as broadcastable [nz,ny,nx] arrays."""
+    c = [0.5 * (np.asarray(p[1:]) + np.asarray(p[:-1])) for p in planes]
+    return c[0][None, None, :], c[1][:, None][None, :, :], c[2][:, None, None]
 
 
 def as_f32_values(a):
@@ -125,6 +151,24 @@ def spiral(n_packages=10_000_000, precision=1, seed=DEFAULT_SEED, flags=FLAGS_DE
     dets = [_frame(1e4, inc, 512, 512, 20.0, 20.0) for inc in (0.0, 60.0, 90.0)]
     return _problem("edge_on_spiral_256x256x64", box, n, rho, 1.0, 0.6, 0.6, [_expdisk(4.0, 0.4)], dets,
                     n_packages, precision, seed=seed, flags=flags)
+
+
+def powcub_spiral(n_packages=10_000_000, precision=1, seed=DEFAULT_SEED, flags=FLAGS_DEFAULT, ratio=(8.0, 8.0, 16.0)):
+    """The edge-on spiral on a PowCub grid (Table 1(d)): the same box, cell
+    counts, dust and stars, with cells graded geometrically so that they
+    are finest at the disk centre and midplane -- outermost/innermost width
+    8 in x and y, 16 in z -- and the dust sampled at the graded cells'
+    centres."""
+    box, n = (-20, 20, -20, 20, -2, 2), (256, 256, 64)
+    planes = tuple(power_law_planes(box[2 * a], box[2 * a + 1], n[a], ratio[a]) for a in range(3))
+    rho = exp_disk_density(box, n, 2.0, 6.0, 0.25, planes=planes)
+    if precision == 1:
+        rho = as_f32_values(rho)
+    dets = [_frame(1e4, inc, 512, 512, 20.0, 20.0) for inc in (0.0, 60.0, 90.0)]
+    prob = _problem("powcub_spiral_256x256x64", box, n, rho, 1.0, 0.6, 0.6, [_expdisk(4.0, 0.4)], dets,
+                    n_packages, precision, seed=seed, flags=flags)
+    prob["planes"] = planes
+    return prob
 
 
 def multiwavelength(n_packages=1_000_000, precision=1, n_lambda=100, lambdas=None, seed=DEFAULT_SEED,

@@ -39,3 +39,11 @@ def orc():
 def W():
     from paper_1410_1629_amd import workloads
     return workloads
+
+
+@pytest.fixture(scope="session")
+def E(tmp_path_factory):
+    """The CPU harness of the library's lane code (built once per session)."""
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "helpers"))
+    import emu
+    return emu.Emu(emu.build(str(tmp_path_factory.mktemp("emu"))))

@@ -64,8 +64,41 @@ inline void unbrick(const GridDev& G, const std::vector<double>& src, double* ds
     }
 }
 
-template <typename R>
+// Plane tables of a rectilinear grid for the harness: laid out by the
+// library's own routine, checked against the caller's planes, then copied
+// per axis between NaN guards (a read outside a table gives NaN crossing
+// times, which end the walk and break the results the tests compare).
+struct HostPlanes {
+  std::vector<unsigned char> blob;
+  std::vector<double> pa[3], qd[3];
+  void attach(const mcrt_grid& g, GridDev& G) {
+    if (!G.rect) return;
+    blob.assign(host::plane_bytes(G), 0);
+    host::put_planes(g, G, blob.data(), blob.data());
+    const double* P = g.planes;
+    const double nan = std::nan("");
+    for (int a = 0; a < 3; ++a) {
+      const int n = G.n[a];
+      for (int q = 0; q <= n; ++q) {
+        EMU_CHECK(G.pa[a][q] == P[q], "plane table", q, n + 1);
+        EMU_CHECK(G.qd[a][q] == P[q] - P[0], "relative plane table", q, n + 1);
+      }
+      pa[a].assign(n + 3, nan);
+      qd[a].assign(n + 3, nan);
+      for (int q = 0; q <= n; ++q) {
+        pa[a][q + 1] = G.pa[a][q];
+        qd[a][q + 1] = G.qd[a][q];
+      }
+      G.pa[a] = pa[a].data() + 1;
+      G.qd[a] = qd[a].data() + 1;
+      P += n + 1;
+    }
+  }
+};
+
+template <typename R, bool RECT>
 struct HostLifeMem {
+  static constexpr bool kRect = RECT;
   const R* rho_;
   const GridDev& G;
   const host::Prepared& pr;
@@ -212,7 +245,9 @@ void run_wave(std::vector<LaneT>& lanes, int batch, Events events, Step step, lo
 }
 
 // Deposits of the bundled walk, straight into the bricked gradient.
+template <bool RECT>
 struct HostBundleMem {
+  static constexpr bool kRect = RECT;
   const GridDev& G;
   std::vector<double>& grad;
   void deposit(int cell, double v) {
@@ -227,8 +262,8 @@ struct HostBundleMem {
 // each ray in sorted order: the optical-depth walk; forward, C into its
 // pixel; adjoint, q = (dL/dI) C into the event scratch and, for q != 0, the
 // deposit walk.  Returns the crossings; `deps` gets the deposits.
-template <typename R, bool ADJ>
-unsigned long long emu_peel_jobs(HostLifeMem<R>& M, const RunParams& P, std::vector<PeelJob>& jobs,
+template <typename R, bool ADJ, bool RECT>
+unsigned long long emu_peel_jobs(HostLifeMem<R, RECT>& M, const RunParams& P, std::vector<PeelJob>& jobs,
                                  unsigned long long n_jobs, std::vector<double>& grad, unsigned long long& deps,
                                  long long cap_steps) {
   const long long n_keys = M.n_keys;
@@ -277,7 +312,7 @@ unsigned long long emu_peel_jobs(HostLifeMem<R>& M, const RunParams& P, std::vec
       perm[q] = idx[i];
     }
   }
-  HostBundleMem D{P.G, grad};
+  HostBundleMem<RECT> D{P.G, grad};
   unsigned long long nx = 0;
   deps = 0;
   for (unsigned long long qi = 0; qi < n_valid; ++qi) {
@@ -290,7 +325,7 @@ unsigned long long emu_peel_jobs(HostLifeMem<R>& M, const RunParams& P, std::vec
     while (d + 1 < P.n_det && (unsigned)M.det(d + 1).key_off <= J.key) ++d;
     EMU_CHECK(d == J.d, "job frame against its key", J.d, P.n_det);
     Ray<R> ry;
-    ray_begin(ry, P.G, J.r, M.det(J.d).kd);
+    ray_begin<R, RECT>(ry, P.G, J.r, M.det(J.d).kd);
     const R kap = (R)M.lam((int)J.lam).kappa;
     long long steps = 0;
     while (ry.active) {
@@ -309,7 +344,7 @@ unsigned long long emu_peel_jobs(HostLifeMem<R>& M, const RunParams& P, std::vec
       M.ev_add_beyond((int)J.slot, q);
     if (q == 0.0) continue;
     const double w = -q * M.lam((int)J.lam).kappa;
-    ray_begin(ry, P.G, J.r, M.det(J.d).kd);
+    ray_begin<R, RECT>(ry, P.G, J.r, M.det(J.d).kd);
     steps = 0;
     while (ry.active) {
       const unsigned n = bp_step<R>(ry, P.G, w, D);
@@ -321,7 +356,7 @@ unsigned long long emu_peel_jobs(HostLifeMem<R>& M, const RunParams& P, std::vec
   return nx;
 }
 
-template <typename R, bool ADJ>
+template <typename R, bool ADJ, bool RECT>
 int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, int n_src, const mcrt_source* sources,
              int n_det, const mcrt_detector* detectors, const mcrt_opts* opts, double* images, long long n_images,
              double* absorbed, long long n_absorbed, const double* adj, long long n_adj, double* grad, long long n_grad,
@@ -329,6 +364,8 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   host::Prepared pr;
   if (int e = host::prepare(grid, rho, optics, n_src, sources, n_det, detectors, opts, pr)) return e;
   RunParams P = pr.P;
+  HostPlanes planes;
+  planes.attach(*grid, P.G);
   P.images = images;
   P.absorbed = ((opts->flags & MCRT_ABSORB) && !ADJ) ? absorbed : nullptr;
   P.adj = adj;
@@ -340,7 +377,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   const std::vector<R> rho_b = brick_copy(P.G, static_cast<const R*>(rho));
   std::vector<double> abs_b(P.absorbed ? (size_t)P.n_lambda * P.G.ncell_pad : 0, 0.0);
   std::vector<double> grad_b(ADJ && grad ? (size_t)P.G.ncell_pad : 0, 0.0);
-  HostLifeMem<R> M{rho_b.data(), P.G, pr, images, n_images, P.absorbed ? abs_b.data() : nullptr,
+  HostLifeMem<R, RECT> M{rho_b.data(), P.G, pr, images, n_images, P.absorbed ? abs_b.data() : nullptr,
                    (long long)abs_b.size(), adj, n_adj, grad_b.data(), (long long)grad_b.size()};
   P.absorbed = M.absorbed;
   if (images && !ADJ) std::fill(images, images + n_images, 0.0);
@@ -406,7 +443,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   auto queue_phase = [&]() {
     unsigned long long deps = 0;
     const unsigned long long nx =
-        emu_peel_jobs<R, ADJ>(M, P, jobs, std::min(M.job_next, M.job_cap), grad_b, deps, cap);
+        emu_peel_jobs<R, ADJ, RECT>(M, P, jobs, std::min(M.job_next, M.job_cap), grad_b, deps, cap);
     M.x_queue += nx;
     M.d_queue += deps;
   };
@@ -451,8 +488,9 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   return 0;
 }
 
-template <typename R>
+template <typename R, bool RECT>
 struct HostTraceMem {
+  static constexpr bool kRect = RECT;
   const R* rho_;
   const TraceParams& P;
   long long cap_seg;  // entries of seg_cell / seg_len
@@ -486,7 +524,7 @@ struct HostTraceMem {
   }
 };
 
-template <typename R>
+template <typename R, bool RECT>
 int emu_trace(const mcrt_grid* grid, const void* rho, double kappa, int64_t n_rays, const double* origin,
               const double* dir, double* tau, int32_t max_seg, int32_t* seg_cell, double* seg_len, int32_t* n_seg,
               uint64_t* crossings, int brick_shape, int wave) {
@@ -494,6 +532,8 @@ int emu_trace(const mcrt_grid* grid, const void* rho, double kappa, int64_t n_ra
   TraceParams P;
   std::memset(&P, 0, sizeof P);
   if (int e = host::make_grid(*grid, (int)sizeof(R), brick_shape, P.G)) return e;
+  HostPlanes planes;
+  planes.attach(*grid, P.G);
   const std::vector<R> rho_b = brick_copy(P.G, static_cast<const R*>(rho));
   P.rho = rho_b.data();
   P.kappa = kappa;
@@ -506,7 +546,7 @@ int emu_trace(const mcrt_grid* grid, const void* rho, double kappa, int64_t n_ra
   P.seg_len = lists ? seg_len : nullptr;
   P.n_seg = n_seg;
   P.batch = 16;
-  HostTraceMem<R> M{rho_b.data(), P, lists ? (long long)max_seg * n_rays : 0};
+  HostTraceMem<R, RECT> M{rho_b.data(), P, lists ? (long long)max_seg * n_rays : 0};
   std::vector<TraceLane<R>> lanes(wave);
   for (auto& L : lanes) trace_init(L);
   const long long cap = (long long)P.G.n[0] + P.G.n[1] + P.G.n[2] + 8;
@@ -523,8 +563,9 @@ int emu_trace(const mcrt_grid* grid, const void* rho, double kappa, int64_t n_ra
   return 0;
 }
 
-template <typename R>
+template <typename R, bool RECT>
 struct HostPeelMem {
+  static constexpr bool kRect = RECT;
   const R* rho_;
   const PeelParams& P;
   const std::vector<DetDev>& dets;
@@ -559,7 +600,7 @@ struct HostPeelMem {
   }
 };
 
-template <typename R>
+template <typename R, bool RECT>
 int emu_peel(const mcrt_grid* grid, const void* rho, double kappa, double g, int64_t n_events, const double* pos,
              const double* dir_in, const double* w, int n_det, const mcrt_detector* detectors, double* images,
              int brick_shape, int wave) {
@@ -568,6 +609,8 @@ int emu_peel(const mcrt_grid* grid, const void* rho, double kappa, double g, int
   PeelParams P;
   std::memset(&P, 0, sizeof P);
   if (int e = host::make_grid(*grid, (int)sizeof(R), brick_shape, P.G)) return e;
+  HostPlanes planes;
+  planes.attach(*grid, P.G);
   const std::vector<R> rho_b = brick_copy(P.G, static_cast<const R*>(rho));
   P.rho = rho_b.data();
   P.kappa = kappa;
@@ -579,7 +622,7 @@ int emu_peel(const mcrt_grid* grid, const void* rho, double kappa, double g, int
   P.w = w;
   P.images = images;
   P.batch = 16;
-  HostPeelMem<R> M{rho_b.data(), P, det, npix};
+  HostPeelMem<R, RECT> M{rho_b.data(), P, det, npix};
   std::vector<PeelLane<R>> lanes(wave);
   for (auto& L : lanes) peel_init(L);
   const long long cap = (long long)P.G.n[0] + P.G.n[1] + P.G.n[2] + 8;
@@ -587,6 +630,25 @@ int emu_peel(const mcrt_grid* grid, const void* rho, double kappa, double g, int
       lanes, P.batch, [&](PeelLane<R>& L) { peel_events(L, P, M); }, [&](PeelLane<R>& L) { peel_step(L, P, M); },
       cap, 0);
   return 0;
+}
+
+// Precision and grid kind of a call, as the library dispatches its kernels.
+template <bool ADJ, typename... A>
+int life_dispatch(bool f32, bool rect, A... args) {
+  if (f32) return rect ? emu_life<float, ADJ, true>(args...) : emu_life<float, ADJ, false>(args...);
+  return rect ? emu_life<double, ADJ, true>(args...) : emu_life<double, ADJ, false>(args...);
+}
+
+template <typename... A>
+int trace_dispatch(bool f32, bool rect, A... args) {
+  if (f32) return rect ? emu_trace<float, true>(args...) : emu_trace<float, false>(args...);
+  return rect ? emu_trace<double, true>(args...) : emu_trace<double, false>(args...);
+}
+
+template <typename... A>
+int peel_dispatch(bool f32, bool rect, A... args) {
+  if (f32) return rect ? emu_peel<float, true>(args...) : emu_peel<float, false>(args...);
+  return rect ? emu_peel<double, true>(args...) : emu_peel<double, false>(args...);
 }
 
 int guard(const char* what, int (*f)(void*), void* arg) {
@@ -616,11 +678,9 @@ int emu_run_photons(const mcrt_grid* grid, const void* rho, const mcrt_optics* o
     g_violation.clear();
     host::last_error().clear();
     if (!opts) return host::fail(MCRT_EINVAL, "opts is NULL");
-    return opts->precision == MCRT_PREC_FP32
-               ? emu_life<float, false>(grid, rho, optics, n_src, sources, n_det, detectors, opts, images, n_images,
-                                        absorbed, n_absorbed, nullptr, 0, nullptr, 0, stats, wave)
-               : emu_life<double, false>(grid, rho, optics, n_src, sources, n_det, detectors, opts, images, n_images,
-                                         absorbed, n_absorbed, nullptr, 0, nullptr, 0, stats, wave);
+    return life_dispatch<false>(opts->precision == MCRT_PREC_FP32, grid && grid->planes, grid, rho, optics, n_src,
+                                sources, n_det, detectors, opts, images, n_images, absorbed, n_absorbed,
+                                (const double*)nullptr, 0ll, (double*)nullptr, 0ll, stats, wave);
   } catch (const Violation& v) {
     g_violation = std::string("run_photons: ") + v.what();
     return -100;
@@ -637,11 +697,9 @@ int emu_backward_density(const mcrt_grid* grid, const void* rho, const mcrt_opti
     if (!opts) return host::fail(MCRT_EINVAL, "opts is NULL");
     mcrt_opts o = *opts;
     o.flags &= ~MCRT_ABSORB;
-    return o.precision == MCRT_PREC_FP32
-               ? emu_life<float, true>(grid, rho, optics, n_src, sources, n_det, detectors, &o, nullptr, 0, nullptr,
-                                       0, adj, n_adj, grad, n_grad, stats, wave)
-               : emu_life<double, true>(grid, rho, optics, n_src, sources, n_det, detectors, &o, nullptr, 0, nullptr,
-                                        0, adj, n_adj, grad, n_grad, stats, wave);
+    return life_dispatch<true>(o.precision == MCRT_PREC_FP32, grid && grid->planes, grid, rho, optics, n_src, sources,
+                               n_det, detectors, (const mcrt_opts*)&o, (double*)nullptr, 0ll, (double*)nullptr, 0ll,
+                               adj, n_adj, grad, n_grad, stats, wave);
   } catch (const Violation& v) {
     g_violation = std::string("backward_density: ") + v.what();
     return -100;
@@ -660,11 +718,8 @@ int emu_trace_path(const mcrt_grid* grid, const void* rho, double kappa, int pre
       if (crossings) *crossings = 0;
       return 0;
     }
-    return precision == MCRT_PREC_FP32
-               ? emu_trace<float>(grid, rho, kappa, n_rays, origin, dir, tau, max_seg, seg_cell, seg_len, n_seg,
-                                  crossings, brick_shape, wave)
-               : emu_trace<double>(grid, rho, kappa, n_rays, origin, dir, tau, max_seg, seg_cell, seg_len, n_seg,
-                                   crossings, brick_shape, wave);
+    return trace_dispatch(precision == MCRT_PREC_FP32, grid->planes != nullptr, grid, rho, kappa, n_rays, origin, dir,
+                          tau, max_seg, seg_cell, seg_len, n_seg, crossings, brick_shape, wave);
   } catch (const Violation& v) {
     g_violation = std::string("trace_path: ") + v.what();
     return -100;
@@ -680,11 +735,8 @@ int emu_peel_off(const mcrt_grid* grid, const void* rho, double kappa, double g,
     if (int e = host::check_peel(grid, rho, kappa, g, precision, n_events, pos, w, n_det, detectors, images))
       return e;
     if (n_events == 0) return 0;
-    return precision == MCRT_PREC_FP32
-               ? emu_peel<float>(grid, rho, kappa, g, n_events, pos, dir_in, w, n_det, detectors, images,
-                                 brick_shape, wave)
-               : emu_peel<double>(grid, rho, kappa, g, n_events, pos, dir_in, w, n_det, detectors, images,
-                                  brick_shape, wave);
+    return peel_dispatch(precision == MCRT_PREC_FP32, grid->planes != nullptr, grid, rho, kappa, g, n_events, pos,
+                         dir_in, w, n_det, detectors, images, brick_shape, wave);
   } catch (const Violation& v) {
     g_violation = std::string("peel_off: ") + v.what();
     return -100;

@@ -86,6 +86,7 @@ def _call_run(lib, B, prob, **over):
 
 @pytest.mark.parametrize("case", ["n_packages", "precision", "flags", "w_min", "max_scatter", "launch_blocks",
                                   "event_batch", "brick_shape", "peel_queue", "grid_cells", "grid_extent",
+                                  "planes_order", "planes_ends", "planes_nan",
                                   "albedo", "g", "kappa", "lum", "n_det", "det_pixels", "det_distance",
                                   "n_src", "src_kind", "src_scale"])
 def test_invalid_arguments_are_rejected(lib, B, W, case):
@@ -113,6 +114,15 @@ def test_invalid_arguments_are_rejected(lib, B, W, case):
         prob["n"] = (0, 4, 4)
     elif case == "grid_extent":
         prob["box"] = (1.0, -1.0, -1, 1, -1, 1)
+    elif case in ("planes_order", "planes_ends", "planes_nan"):
+        pl = [np.linspace(-1.0, 1.0, 5) for _ in range(3)]
+        if case == "planes_order":
+            pl[1][2] = pl[1][1]  # not strictly increasing
+        elif case == "planes_ends":
+            pl[2][-1] = 1.5  # does not end at the box maximum
+        else:
+            pl[0][3] = np.nan
+        prob["planes"] = tuple(pl)
     elif case == "albedo":
         prob["albedo"] = np.array([1.5])
     elif case == "g":

@@ -21,12 +21,6 @@ def rel_l1(a, b):
     return float(np.abs(a - b).sum() / den) if den > 0 else float(np.abs(a).sum())
 
 
-@pytest.fixture(scope="session")
-def E(tmp_path_factory):
-    import emu
-    return emu.Emu(emu.build(str(tmp_path_factory.mktemp("emu"))))
-
-
 TRACE_CASES = [
     ("uniform32", (-1, 1, -1, 1, -1, 1), (32, 32, 32), None, 1.0),
     ("lognormal_ragged", (-2.0, 1.0, 0.0, 3.0, -1.0, 0.5), (9, 6, 5), 9, 0.7),
