@@ -16,8 +16,10 @@ Prints one JSON line.  `value` is packages per second of whole steps;
 events around it on the stream it runs on, recorded by the library);
 `traversal` is the walk alone (trace_path on random rays in the same grid);
 `fp64_path` times one step of the plain FP64 GPU path and compares the two
-precisions against the Monte Carlo noise; `cpu_baseline` times the FP64 CPU
-oracle on a bounded package sample of the same workload.
+precisions against the Monte Carlo noise; `powcub_grid` times one step of
+the same model on a PowCub grid (rectilinear, cells graded towards the
+centre); `cpu_baseline` times the FP64 CPU oracle on a bounded package
+sample of the same workload.
 
 `--collect-profiles DIR` runs this script under rocprofv3 (a kernel-trace
 summary, then FETCH_SIZE and WRITE_SIZE counter passes with a 1 GiB copy
@@ -52,12 +54,12 @@ BYTES_PER_RAY = 56
 COPY_BYTES = 1 << 30
 # kernel names as rocprofv3 prints them -> keys of profiles/traffic.json
 KERNELS = {
-    "forward": "void mcrt::k_life<float, false>(mcrt::RunParams)",
-    "adjoint": "void mcrt::k_life<float, true>(mcrt::RunParams)",
-    "peel_tau_forward": "void mcrt::k_peeltau<float, false>(mcrt::PeelJobParams)",
-    "peel_tau_adjoint": "void mcrt::k_peeltau<float, true>(mcrt::PeelJobParams)",
-    "peel_deposit": "void mcrt::k_peeldep<float>(mcrt::PeelJobParams)",
-    "trace": "void mcrt::k_trace<float>(mcrt::TraceParams)",
+    "forward": "void mcrt::k_life<float, false, false>(mcrt::RunParams)",
+    "adjoint": "void mcrt::k_life<float, true, false>(mcrt::RunParams)",
+    "peel_tau_forward": "void mcrt::k_peeltau<float, false, false>(mcrt::PeelJobParams)",
+    "peel_tau_adjoint": "void mcrt::k_peeltau<float, true, false>(mcrt::PeelJobParams)",
+    "peel_deposit": "void mcrt::k_peeldep<float, false>(mcrt::PeelJobParams)",
+    "trace": "void mcrt::k_trace<float, false>(mcrt::TraceParams)",
 }
 
 
@@ -193,13 +195,32 @@ def fp64_comparison(B, prob, step_fn, images32, grad32, dev):
             "images_mc_noise_rel_l1": 0.5 * rel_l1(ia, ib)}
 
 
+def powcub_leg(B, W, step_fn, images, grad, dev, n_pkg):
+    """One step (forward + adjoint) of the same model on a PowCub grid
+    (cells graded towards the disk centre and midplane, Table 1(d)), after
+    one untimed step: the rectilinear-grid kernels at the benchmark size."""
+    import torch
+    p = W.powcub_spiral(n_packages=n_pkg, precision=1)
+    rho = B.density_tensor(p, dev)
+    step_fn(p, rho, images, grad)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sf, sb = step_fn(p, rho, images, grad)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    x = sf["x_path"] + sf["x_locate"] + sf["x_peel"] + sb["x_path"] + sb["x_locate"] + sb["x_peel"]
+    return {"workload": p["name"] + ", power-law cell widths (outermost/innermost 8, 8, 16), %d packages" % n_pkg,
+            "packages_per_s": n_pkg / wall, "ms_per_step": wall * 1e3, "forward_ms": sf["kernel_ms"],
+            "adjoint_ms": sb["kernel_ms"], "crossings_per_s": x / wall}
+
+
 def collect_profiles(out_dir, prof, run=True):
     """Runs this script under rocprofv3 as child processes (this process
     never touches the GPU) and writes the summaries to `prof` (profiles/);
     run=False only summarizes the raw output already in out_dir."""
     os.makedirs(out_dir, exist_ok=True)
     me = os.path.abspath(__file__)
-    child = [sys.executable, me, "--steps", "2", "--warmup", "1", "--no-cpu-baseline", "--no-fp64"]
+    child = [sys.executable, me, "--steps", "2", "--warmup", "1", "--no-cpu-baseline", "--no-fp64", "--no-powcub"]
     runs = {
         "trace": ["rocprofv3", "--kernel-trace", "--stats", "--output-format", "csv"],
         "fetch": ["rocprofv3", "--kernel-trace", "--output-format", "csv", "--pmc", "FETCH_SIZE"],
@@ -250,7 +271,7 @@ def collect_profiles(out_dir, prof, run=True):
     with open(os.path.join(prof, "life_kernels_spiral_1e7_fp32.md"), "w") as f:
         f.write("# Kernel trace and HBM counters: edge-on spiral, 1e7 packages, FP32 path\n\n")
         f.write("Command (writes this file and traffic.json): `python bench.py --collect-profiles %s`\n\n" % out_dir)
-        f.write("Each pass runs `python bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-fp64` under "
+        f.write("Each pass runs `python bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-fp64 --no-powcub` under "
                 "rocprofv3: `--kernel-trace --stats`, then `--pmc FETCH_SIZE` and `--pmc WRITE_SIZE` (the "
                 "counter passes add `--calibrate-copy`: a 1 GiB device copy first, whose counter values give "
                 "the scale factors below).\n\n")
@@ -280,6 +301,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
+    ap.add_argument("--no-powcub", action="store_true", help="skip the PowCub-grid step")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy first (counter scale)")
     ap.add_argument("--collect-profiles", metavar="DIR", help="run the rocprofv3 passes (raw output in DIR)")
     ap.add_argument("--summarize-profiles", metavar="DIR", help="only rewrite the summaries from the raw output in DIR")
@@ -402,6 +424,8 @@ def main():
     out["traversal"] = traversal(B, prob, 4_000_000, dev)
     if not args.no_fp64:
         out["fp64_path"] = fp64_comparison(B, prob, step_fn, images, grad, dev)
+    if not args.no_powcub:
+        out["powcub_grid"] = powcub_leg(B, W, step_fn, images, grad, dev, n_pkg)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
