@@ -85,12 +85,29 @@ extern "C" {
  * the cell-boundary coordinates -- nx + 1 along x, then ny + 1 along y, then
  * nz + 1 along z -- each run strictly increasing from the box's minimum to
  * its maximum (equal to them exactly): cells spaced by any rule, such as
- * the power-law spacing of PowCub (Table 1(d)).  Read only during the call.
- * Cell m = i + nx (j + ny k) either way. */
+ * the power-law spacing of PowCub (Table 1(d)).  Cell m = i + nx (j + ny k)
+ * either way.
+ *
+ * tree_nodes > 0 (planes NULL): a tree grid (Table 1(d): k-d tree; an
+ * octree is three binary levels per octree level, Sect. 2.4), host arrays
+ * of tree_nodes entries.  Node 0 is the box.  Node q with tree_axis[q] in
+ * {0, 1, 2} is split along that axis at tree_split[q], strictly inside the
+ * node, into the nodes tree_child[q] (the lower side) and tree_child[q] + 1
+ * (the upper side), both numbered above q; tree_axis[q] = -1 marks a leaf,
+ * and tree_child[q] is then its cell index.  The cells are the leaves:
+ * nx * ny * nz of them, each index used by one leaf; every node is reached
+ * from node 0 exactly once; depth at most 64.  A point on a split plane
+ * belongs to the side the ray moves to (the upper side when it moves
+ * parallel to the plane).  brick_shape does not apply.  All arrays are read
+ * only during the call. */
 typedef struct {
     double xmin, xmax, ymin, ymax, zmin, zmax;
     int32_t nx, ny, nz;
     const double *planes;
+    int32_t tree_nodes;
+    const int32_t *tree_axis;
+    const double *tree_split;
+    const int32_t *tree_child;
 } mcrt_grid;
 
 /* Optical properties per wavelength (Sect. 2.3); host arrays [n_lambda]:
@@ -246,7 +263,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 8
+#define MCRT_ABI_VERSION 9
 
 #ifdef __cplusplus
 }

@@ -105,13 +105,22 @@ typedef struct {
     int n[3];
     int64_t ncell;
     const double *pl[3]; /* rectilinear grid: the n[a] + 1 planes of axis a; NULL: regular */
+    int tree;            /* tree grid: the cells are leaves with boxes leaf_lo/hi[cell] */
+    double *leaf_lo, *leaf_hi;
 } grid_t;
 
 /* planes: NULL for regularly spaced cells (LinCub), else the cell-boundary
  * coordinates of x, then y, then z (n + 1 each, increasing from the box's
  * minimum to its maximum): cells spaced by any rule, such as PowCub's
  * power law (Table 1(d)). */
-static void grid_init(grid_t *G, const double box[6], const int n[3], const double *planes)
+static void grid_free(grid_t *G);
+
+/* tree: NULL, or a tree grid (Table 1(d): k-d tree; an octree is three
+ * binary levels per level) as doubles: the node count, then per node
+ * (axis, split, child) -- axis -1 marks a leaf whose cell is `child`, else
+ * the node splits along `axis` at `split` into nodes child (lower side) and
+ * child + 1 (upper side).  Returns 0, or -1 for a malformed tree. */
+static int grid_init(grid_t *G, const double box[6], const int n[3], const double *planes, const double *tree)
 {
     size_t off = 0;
     for (int a = 0; a < 3; a++) {
@@ -123,6 +132,69 @@ static void grid_init(grid_t *G, const double box[6], const int n[3], const doub
         off += (size_t)n[a] + 1;
     }
     G->ncell = (int64_t)n[0] * n[1] * n[2];
+    G->tree = tree != NULL;
+    G->leaf_lo = G->leaf_hi = NULL;
+    if (!tree) return 0;
+    /* leaf boxes: each node's box from its parent's, children numbered above it */
+    int64_t nn = (int64_t)tree[0];
+    const double *nd = tree + 1;
+    double *lo = (double *)malloc(sizeof(double) * 3 * nn), *hi = (double *)malloc(sizeof(double) * 3 * nn);
+    G->leaf_lo = (double *)calloc(3 * G->ncell, sizeof(double));
+    G->leaf_hi = (double *)calloc(3 * G->ncell, sizeof(double));
+    int ok = nn >= 1;
+    for (int a = 0; a < 3 && ok; a++) {
+        lo[a] = G->lo[a];
+        hi[a] = G->hi[a];
+    }
+    for (int64_t q = 0; q < nn && ok; q++) {
+        int axis = (int)nd[3 * q];
+        int64_t child = (int64_t)nd[3 * q + 2];
+        if (axis < 0) {
+            if (child < 0 || child >= G->ncell) { ok = 0; break; }
+            for (int a = 0; a < 3; a++) {
+                G->leaf_lo[3 * child + a] = lo[3 * q + a];
+                G->leaf_hi[3 * child + a] = hi[3 * q + a];
+            }
+            continue;
+        }
+        if (child <= q || child + 1 >= nn || axis > 2) { ok = 0; break; }
+        for (int side = 0; side < 2; side++) {
+            for (int a = 0; a < 3; a++) {
+                lo[3 * (child + side) + a] = lo[3 * q + a];
+                hi[3 * (child + side) + a] = hi[3 * q + a];
+            }
+        }
+        hi[3 * child + axis] = nd[3 * q + 1];
+        lo[3 * (child + 1) + axis] = nd[3 * q + 1];
+    }
+    free(lo);
+    free(hi);
+    if (!ok) grid_free(G);
+    return ok ? 0 : -1;
+}
+
+static void grid_free(grid_t *G)
+{
+    free(G->leaf_lo);
+    free(G->leaf_hi);
+    G->leaf_lo = G->leaf_hi = NULL;
+}
+
+/* Leaf of a tree grid holding point p for a ray of direction k, by testing
+ * every leaf: along each axis the leaf holds lo <= p < hi when the ray moves
+ * up or parallel, lo < p <= hi when it moves down (a point on a face belongs
+ * to the leaf the ray moves into).  -1 if none. */
+static int64_t tree_locate(const grid_t *G, const double p[3], const double k[3])
+{
+    for (int64_t c = 0; c < G->ncell; c++) {
+        int in = 1;
+        for (int a = 0; a < 3 && in; a++) {
+            double lo = G->leaf_lo[3 * c + a], hi = G->leaf_hi[3 * c + a];
+            in = k[a] < 0.0 ? (lo < p[a] && p[a] <= hi) : (lo <= p[a] && p[a] < hi);
+        }
+        if (in) return c;
+    }
+    return -1;
 }
 
 /* Coordinate of plane p (0..n) along axis a. */
@@ -213,6 +285,45 @@ static void traverse(const grid_t *G, const double o[3], const double k[3], segb
         if (tf < tout) tout = tf;
     }
     if (!(tin < tout)) return;
+
+    if (G->tree) {
+        /* tree grid: from the entry point, the leaf holding the point, left
+         * through its nearest face; the exit faces' coordinates are set to
+         * the faces exactly, the others advance along k */
+        double p[3];
+        for (int a = 0; a < 3; a++)
+            p[a] = a == entry ? (k[a] > 0.0 ? G->lo[a] : G->hi[a]) : o[a] + tin * k[a];
+        double t = tin;
+        for (int64_t guard = 0; guard < 4 * G->ncell + 8; guard++) {
+            int64_t c = tree_locate(G, p, k);
+            if (c < 0) break;
+            double tx[3], tm = INFINITY;
+            for (int a = 0; a < 3; a++) {
+                if (k[a] > 0.0)
+                    tx[a] = (G->leaf_hi[3 * c + a] - p[a]) / k[a];
+                else if (k[a] < 0.0)
+                    tx[a] = (G->leaf_lo[3 * c + a] - p[a]) / k[a];
+                else
+                    tx[a] = INFINITY;
+                if (tx[a] < tm) tm = tx[a];
+            }
+            if (!(tm < INFINITY)) break;
+            if (tm > 0.0) sb_push(out, c, t, t + tm);
+            int leaves_box = 0;
+            for (int a = 0; a < 3; a++) {
+                if (tx[a] == tm) {
+                    double f = k[a] > 0.0 ? G->leaf_hi[3 * c + a] : G->leaf_lo[3 * c + a];
+                    if (f == (k[a] > 0.0 ? G->hi[a] : G->lo[a])) leaves_box = 1;
+                    p[a] = f;
+                } else {
+                    p[a] += tm * k[a];
+                }
+            }
+            t += tm;
+            if (leaves_box) break;
+        }
+        return;
+    }
 
     int idx[3];
     for (int a = 0; a < 3; a++) {
@@ -732,13 +843,13 @@ static int setup_problem(problem_t *P, const double box[6], const int n[3], cons
                          const double *kappa, const double *albedo, const double *g, int n_src, const int *src_kind,
                          const double *src_par, const double *src_lum, int n_det, const double *det_par,
                          const int *det_pix, uint64_t n_pkg, uint64_t first, uint64_t seed, double w_min,
-                         int max_scatter, unsigned flags, const double *planes)
+                         int max_scatter, unsigned flags, const double *planes, const double *tree)
 {
     if (n_src < 1 || n_src > MAX_SRC || n_det < 0 || n_det > MAX_DET || n_lambda < 1 || n_pkg < 1) return -1;
     for (int a = 0; a < 3; a++)
         if (n[a] < 1 || !(box[2 * a + 1] > box[2 * a])) return -1;
     memset(P, 0, sizeof *P);
-    grid_init(&P->G, box, n, planes);
+    if (grid_init(&P->G, box, n, planes, tree)) return -1;
     P->rho = rho;
     P->n_lambda = n_lambda;
     P->kappa = kappa;
@@ -836,14 +947,16 @@ int oracle_run(const double box[6], const int n[3], const double *rho, int n_lam
                const double *albedo, const double *g, int n_src, const int *src_kind, const double *src_par,
                const double *src_lum, int n_det, const double *det_par, const int *det_pix, uint64_t n_pkg,
                uint64_t first, uint64_t seed, double w_min, int max_scatter, unsigned flags, double *images,
-               double *absorbed, double *stats, int n_threads, const double *planes)
+               double *absorbed, double *stats, int n_threads, const double *planes, const double *tree)
 {
     problem_t P;
     if (setup_problem(&P, box, n, rho, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
-                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes))
+                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes, tree))
         return -1;
     P.mode = MODE_FORWARD;
-    return simulate(&P, images, (flags & FLAG_ABSORB) ? absorbed : NULL, NULL, stats, n_threads);
+    int rc = simulate(&P, images, (flags & FLAG_ABSORB) ? absorbed : NULL, NULL, stats, n_threads);
+    grid_free(&P.G);
+    return rc;
 }
 
 /* Gradient of L with respect to every cell density, given adj = dL/dI in
@@ -853,15 +966,18 @@ int oracle_grad(const double box[6], const int n[3], const double *rho, int n_la
                 const double *albedo, const double *g, int n_src, const int *src_kind, const double *src_par,
                 const double *src_lum, int n_det, const double *det_par, const int *det_pix, uint64_t n_pkg,
                 uint64_t first, uint64_t seed, double w_min, int max_scatter, unsigned flags, const double *adj,
-                double *images, double *grad, double *stats, int n_threads, const double *planes)
+                double *images, double *grad, double *stats, int n_threads, const double *planes,
+                const double *tree)
 {
     problem_t P;
     if (setup_problem(&P, box, n, rho, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
-                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes))
+                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes, tree))
         return -1;
     P.mode = MODE_GRAD;
     P.adj = adj;
-    return simulate(&P, images, NULL, grad, stats, n_threads);
+    int rc = simulate(&P, images, NULL, grad, stats, n_threads);
+    grid_free(&P.G);
+    return rc;
 }
 
 /* Images of the estimator whose paths are sampled at rho0 and whose weights
@@ -872,15 +988,17 @@ int oracle_reweight(const double box[6], const int n[3], const double *rho0, con
                     const double *src_par, const double *src_lum, int n_det, const double *det_par,
                     const int *det_pix, uint64_t n_pkg, uint64_t first, uint64_t seed, double w_min,
                     int max_scatter, unsigned flags, double *images, double *stats, int n_threads,
-                    const double *planes)
+                    const double *planes, const double *tree)
 {
     problem_t P;
     if (setup_problem(&P, box, n, rho0, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
-                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes))
+                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes, tree))
         return -1;
     P.mode = MODE_REWEIGHT;
     P.rho_eval = rho;
-    return simulate(&P, images, NULL, NULL, stats, n_threads);
+    int rc = simulate(&P, images, NULL, NULL, stats, n_threads);
+    grid_free(&P.G);
+    return rc;
 }
 
 /* Per-ray optical depth to the grid boundary, and optionally the segment
@@ -888,10 +1006,10 @@ int oracle_reweight(const double box[6], const int n[3], const double *rho0, con
  * count.  Returns the total number of segments. */
 int64_t oracle_trace(const double box[6], const int n[3], const double *rho, double kappa, int64_t n_rays,
                      const double *origin, const double *dir, double *tau, int max_seg, int64_t *seg_cell,
-                     double *seg_len, int *n_seg, const double *planes)
+                     double *seg_len, int *n_seg, const double *planes, const double *tree)
 {
     grid_t G;
-    grid_init(&G, box, n, planes);
+    if (grid_init(&G, box, n, planes, tree)) return -1;
     segbuf sb = {0};
     int64_t total = 0;
     for (int64_t q = 0; q < n_rays; q++) {
@@ -908,6 +1026,7 @@ int64_t oracle_trace(const double box[6], const int n[3], const double *rho, dou
         }
     }
     sb_free(&sb);
+    grid_free(&G);
     return total;
 }
 
@@ -916,11 +1035,11 @@ int64_t oracle_trace(const double box[6], const int n[3], const double *rho, dou
  * means isotropic emission (phase 1/4pi), else HG with parameter g. */
 int oracle_peel(const double box[6], const int n[3], const double *rho, double kappa, double g, int64_t n_events,
                 const double *pos, const double *dir_in, const double *w, int n_det, const double *det_par,
-                const int *det_pix, double *images, const double *planes)
+                const int *det_pix, double *images, const double *planes, const double *tree)
 {
     if (n_det < 1 || n_det > MAX_DET) return -1;
     grid_t G;
-    grid_init(&G, box, n, planes);
+    if (grid_init(&G, box, n, planes, tree)) return -1;
     det_t det[MAX_DET];
     size_t off = 0;
     for (int d = 0; d < n_det; d++) {
@@ -944,6 +1063,7 @@ int oracle_peel(const double box[6], const int n[3], const double *rho, double k
         }
     }
     sb_free(&sb);
+    grid_free(&G);
     return 0;
 }
 

@@ -4,6 +4,7 @@ A problem is a plain dict:
   box         (xmin, xmax, ymin, ymax, zmin, zmax)
   n           (nx, ny, nz)
   planes      optional (x, y, z) cell-boundary coordinates of a rectilinear grid
+  tree        optional tree grid {axis, split, child} per node (n = (cells, 1, 1))
   rho         density, nz*ny*nx values, x fastest
   kappa, albedo, g         one value per wavelength
   sources     list of {kind: "point"|"expdisk", pos: (x, y, z), h_r, h_z, lum: [n_lambda]}
@@ -49,16 +50,16 @@ def _load():
         _lib.oracle_emit_direction.argtypes = [P, P]
         _lib.oracle_detector_basis.argtypes = [P, P]
         common = [P, P, P, i, P, P, P, i, P, P, P, i, P, P, u64, u64, u64, d, i, C.c_uint]
-        _lib.oracle_run.argtypes = common + [P, P, P, i, P]
+        _lib.oracle_run.argtypes = common + [P, P, P, i, P, P]
         _lib.oracle_run.restype = i
-        _lib.oracle_grad.argtypes = common + [P, P, P, P, i, P]
+        _lib.oracle_grad.argtypes = common + [P, P, P, P, i, P, P]
         _lib.oracle_grad.restype = i
         _lib.oracle_reweight.argtypes = [P, P, P, P, i, P, P, P, i, P, P, P, i, P, P, u64, u64, u64, d, i,
-                                         C.c_uint, P, P, i, P]
+                                         C.c_uint, P, P, i, P, P]
         _lib.oracle_reweight.restype = i
-        _lib.oracle_trace.argtypes = [P, P, P, d, i64, P, P, P, i, P, P, P, P]
+        _lib.oracle_trace.argtypes = [P, P, P, d, i64, P, P, P, i, P, P, P, P, P]
         _lib.oracle_trace.restype = i64
-        _lib.oracle_peel.argtypes = [P, P, P, d, d, i64, P, P, P, i, P, P, P, P]
+        _lib.oracle_peel.argtypes = [P, P, P, d, d, i64, P, P, P, i, P, P, P, P, P]
         _lib.oracle_peel.restype = i
         _lib.oracle_draw_words.argtypes = [u64, u64, i64, u32, u32, P]
     return _lib
@@ -146,6 +147,17 @@ def _planes(planes, n):
     return arr
 
 
+def _tree(tree):
+    """A tree grid {"axis", "split", "child"} packed as doubles (node count,
+    then axis, split, child per node), or None."""
+    if tree is None:
+        return None
+    ax = np.asarray(tree["axis"], dtype=np.float64)
+    sp = np.asarray(tree["split"], dtype=np.float64)
+    ch = np.asarray(tree["child"], dtype=np.float64)
+    return _f64(np.concatenate([[ax.size], np.stack([ax, sp, ch], axis=1).reshape(-1)]))
+
+
 def _marshal(prob):
     box = _f64(prob["box"])
     n = _i32(prob["n"])
@@ -163,7 +175,8 @@ def _marshal(prob):
     dpix = _i32([[d["nx"], d["ny"]] for d in dets] if dets else np.zeros((0, 2)))
     npix = int(sum(d["nx"] * d["ny"] for d in dets))
     planes = _planes(prob.get("planes"), n)
-    keep = (box, n, rho, kappa, albedo, g, kind, spar, slum, dpar, dpix, planes)
+    tree = _tree(prob.get("tree"))
+    keep = (box, n, rho, kappa, albedo, g, kind, spar, slum, dpar, dpix, planes, tree)
     args = [_ptr(box), _ptr(n), _ptr(rho), nl, _ptr(kappa), _ptr(albedo), _ptr(g), len(srcs), _ptr(kind),
             _ptr(spar), _ptr(slum), len(dets), _ptr(dpar), _ptr(dpix), int(prob["n_packages"]),
             int(prob.get("first_package", 0)), int(prob.get("seed", 4357)), float(prob.get("w_min", 1e-4)),
@@ -182,7 +195,8 @@ def run(prob, threads=1):
     images = np.zeros((_comps(prob), nl, npix))
     absorbed = np.zeros((nl, ncell)) if int(prob.get("flags", 7)) & FLAG_ABSORB else None
     stats = np.zeros(len(STAT_NAMES))
-    rc = _load().oracle_run(*args, _ptr(images), _ptr(absorbed), _ptr(stats), int(threads), _ptr(keep[11]))
+    rc = _load().oracle_run(*args, _ptr(images), _ptr(absorbed), _ptr(stats), int(threads), _ptr(keep[11]),
+                            _ptr(keep[12]))
     if rc != 0:
         raise ValueError("oracle_run rejected its arguments")
     return images, absorbed, dict(zip(STAT_NAMES, stats.tolist()))
@@ -196,7 +210,8 @@ def grad(prob, adj, threads=1):
     images = np.zeros((_comps(prob), nl, npix))
     g = np.zeros(ncell)
     stats = np.zeros(len(STAT_NAMES))
-    rc = _load().oracle_grad(*args, _ptr(adj), _ptr(images), _ptr(g), _ptr(stats), int(threads), _ptr(keep[11]))
+    rc = _load().oracle_grad(*args, _ptr(adj), _ptr(images), _ptr(g), _ptr(stats), int(threads), _ptr(keep[11]),
+                            _ptr(keep[12]))
     if rc != 0:
         raise ValueError("oracle_grad rejected its arguments")
     return g, images, dict(zip(STAT_NAMES, stats.tolist()))
@@ -210,18 +225,20 @@ def reweight(prob, rho_eval, threads=1):
     images = np.zeros((_comps(prob), nl, npix))
     stats = np.zeros(len(STAT_NAMES))
     a = args[:3] + [_ptr(rho_eval)] + args[3:]
-    rc = _load().oracle_reweight(*a, _ptr(images), _ptr(stats), int(threads), _ptr(keep[11]))
+    rc = _load().oracle_reweight(*a, _ptr(images), _ptr(stats), int(threads), _ptr(keep[11]),
+                            _ptr(keep[12]))
     if rc != 0:
         raise ValueError("oracle_reweight rejected its arguments")
     return images, dict(zip(STAT_NAMES, stats.tolist()))
 
 
-def trace(box, n, rho, kappa, origins, dirs, max_seg=0, planes=None):
+def trace(box, n, rho, kappa, origins, dirs, max_seg=0, planes=None, tree=None):
     """Optical depth along each ray to the grid boundary; with max_seg > 0 also
     the segment lists.  Returns (tau, total_segments, seg_cell, seg_len, n_seg).
-    planes: (x, y, z) plane coordinates of a rectilinear grid, or None."""
+    planes: (x, y, z) plane coordinates of a rectilinear grid, or None; tree:
+    a tree grid {"axis", "split", "child"}, or None."""
     box, n, rho = _f64(box), _i32(n), _f64(rho).reshape(-1)
-    pl = _planes(planes, n)
+    pl, tr = _planes(planes, n), _tree(tree)
     o, k = _f64(origins).reshape(-1, 3), _f64(dirs).reshape(-1, 3)
     nr = o.shape[0]
     tau = np.zeros(nr)
@@ -229,14 +246,14 @@ def trace(box, n, rho, kappa, origins, dirs, max_seg=0, planes=None):
     cell = np.zeros((nr, max(max_seg, 1)), dtype=np.int64) if max_seg > 0 else None
     length = np.zeros((nr, max(max_seg, 1))) if max_seg > 0 else None
     tot = _load().oracle_trace(_ptr(box), _ptr(n), _ptr(rho), float(kappa), nr, _ptr(o), _ptr(k), _ptr(tau),
-                               int(max_seg), _ptr(cell), _ptr(length), _ptr(nseg), _ptr(pl))
+                               int(max_seg), _ptr(cell), _ptr(length), _ptr(nseg), _ptr(pl), _ptr(tr))
     return tau, int(tot), cell, length, nseg
 
 
-def peel(box, n, rho, kappa, g, pos, dir_in, w, detectors, planes=None):
+def peel(box, n, rho, kappa, g, pos, dir_in, w, detectors, planes=None, tree=None):
     """Peel-off of an event list into the frames of one wavelength (fresh zero images)."""
     box, n, rho = _f64(box), _i32(n), _f64(rho).reshape(-1)
-    pl = _planes(planes, n)
+    pl, tr = _planes(planes, n), _tree(tree)
     pos = _f64(pos).reshape(-1, 3)
     din = None if dir_in is None else _f64(dir_in).reshape(-1, 3)
     w = _f64(w).reshape(-1)
@@ -244,7 +261,8 @@ def peel(box, n, rho, kappa, g, pos, dir_in, w, detectors, planes=None):
     dpix = _i32([[d["nx"], d["ny"]] for d in detectors])
     images = np.zeros(int(sum(d["nx"] * d["ny"] for d in detectors)))
     rc = _load().oracle_peel(_ptr(box), _ptr(n), _ptr(rho), float(kappa), float(g), pos.shape[0], _ptr(pos),
-                             _ptr(din), _ptr(w), len(detectors), _ptr(dpar), _ptr(dpix), _ptr(images), _ptr(pl))
+                             _ptr(din), _ptr(w), len(detectors), _ptr(dpar), _ptr(dpix), _ptr(images), _ptr(pl),
+                             _ptr(tr))
     if rc != 0:
         raise ValueError("oracle_peel rejected its arguments")
     return images

@@ -30,7 +30,9 @@ class McrtError(RuntimeError):
 class Grid(C.Structure):
     _fields_ = [("xmin", C.c_double), ("xmax", C.c_double), ("ymin", C.c_double), ("ymax", C.c_double),
                 ("zmin", C.c_double), ("zmax", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32),
-                ("nz", C.c_int32), ("planes", C.POINTER(C.c_double))]
+                ("nz", C.c_int32), ("planes", C.POINTER(C.c_double)), ("tree_nodes", C.c_int32),
+                ("tree_axis", C.POINTER(C.c_int32)), ("tree_split", C.POINTER(C.c_double)),
+                ("tree_child", C.POINTER(C.c_int32))]
 
 
 class Optics(C.Structure):
@@ -76,7 +78,7 @@ class Stats(C.Structure):
 _lib = None
 
 # Exported symbols of include/mcrt.h.
-ABI_VERSION = 8  # MCRT_ABI_VERSION of the header these structs follow
+ABI_VERSION = 9  # MCRT_ABI_VERSION of the header these structs follow
 SYMBOLS = ("run_photons", "trace_path", "peel_off", "backward_density", "mcrt_last_error", "mcrt_abi_version")
 
 
@@ -136,14 +138,25 @@ def _stream(stream):
 
 def make_grid(prob):
     """The grid of a problem dict: box, cells per axis and, for a
-    rectilinear grid, prob["planes"] = (x planes, y planes, z planes)."""
+    rectilinear grid, prob["planes"] = (x planes, y planes, z planes), for a
+    tree grid prob["tree"] = {"axis", "split", "child"} per node."""
     b, n = prob["box"], prob["n"]
-    g = Grid(b[0], b[1], b[2], b[3], b[4], b[5], n[0], n[1], n[2], None)
+    g = Grid(b[0], b[1], b[2], b[3], b[4], b[5], n[0], n[1], n[2], None, 0, None, None, None)
     planes = prob.get("planes")
     if planes is not None:
         arr = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.float64).reshape(-1) for p in planes]))
         g._planes = arr  # kept alive with the struct
         g.planes = arr.ctypes.data_as(C.POINTER(C.c_double))
+    tree = prob.get("tree")
+    if tree is not None:
+        ax = np.ascontiguousarray(tree["axis"], dtype=np.int32)
+        sp = np.ascontiguousarray(tree["split"], dtype=np.float64)
+        ch = np.ascontiguousarray(tree["child"], dtype=np.int32)
+        g._tree = (ax, sp, ch)
+        g.tree_nodes = ax.size
+        g.tree_axis = ax.ctypes.data_as(C.POINTER(C.c_int32))
+        g.tree_split = sp.ctypes.data_as(C.POINTER(C.c_double))
+        g.tree_child = ch.ctypes.data_as(C.POINTER(C.c_int32))
     return g
 
 

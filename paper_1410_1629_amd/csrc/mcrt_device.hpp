@@ -39,6 +39,23 @@ constexpr int kMaxDet = 8;
 // and FP32 crossing times stay finite for any grid up to 1e15 lengths.
 constexpr double kParallel = 1e-20;
 
+// Grid kinds (Table 1(d)): regular Cartesian cells (LinCub), rectilinear
+// cells spaced by any rule per axis (PowCub and others), and the leaves of
+// a binary space partition (k-d tree; an octree is three binary levels per
+// octree level).  Each kernel is compiled once per kind.
+constexpr int kGridRegular = 0, kGridRect = 1, kGridTree = 2;
+// Deepest tree accepted (the host rejects deeper ones).
+constexpr int kMaxTreeDepth = 64;
+
+// A node of a tree grid: split along `axis` at `split` into children
+// `child` (lower side) and `child + 1` (upper side), or a leaf (axis < 0)
+// whose cell index is `child`.
+struct TreeNode {
+  double split;
+  int axis;
+  int child;
+};
+
 // ---------------------------------------------------------------------------
 // Problem data, prepared by the host in FP64.
 
@@ -57,14 +74,39 @@ struct GridDev {
   int nb[3];      // bricks along each axis
   int bstride[3]; // brick strides in cells: 2^(lb0+lb1+lb2), nb0 of them, nb0*nb1 of them
   int ncell_pad;  // cells of the bricked arrays (whole bricks)
-  // Rectilinear grids (rect = 1; cells spaced by any rule, Table 1(d)):
-  // the cell-boundary planes of each axis, n[a] + 1 of them, absolute (pa)
-  // and relative to the first plane (qd), FP64.  Regular grids (rect = 0)
-  // use lo + p d.
-  int rect;
+  // Grid kind (kGrid*).  Rectilinear grids: the cell-boundary planes of
+  // each axis, n[a] + 1 of them, absolute (pa) and relative to the first
+  // plane (qd), FP64; regular grids use lo + p d.  Tree grids: the nodes,
+  // node 0 the box; the cells are the leaves, stored as a one-dimensional
+  // array (n = {cells, 1, 1}, no bricks).
+  int kind;
   const double* pa[3];
   const double* qd[3];
+  const TreeNode* nodes;
+  const double* leaf_box;  // tree grids: per cell lo x y z, hi x y z
+  const int* ropes;        // tree grids: per cell and face (-x +x -y +y -z +z) the node across it, -1 outside
 };
+
+// Leaf below node q of a tree grid holding point (px, py, pz), for a ray
+// with direction signs (sx, sy, sz): at each split a point on the plane goes
+// to the side the ray moves to (the upper side when it moves parallel to
+// the plane), the rule of the regular grid's walls.  Returns the leaf's cell
+// (-1 for a path deeper than kMaxTreeDepth, which the host rejects).  The
+// side is decided on all three axes and then picked by the node's axis, so
+// nothing is indexed by a runtime axis.
+MCRT_HD int tree_find(const GridDev& G, int q, double px, double py, double pz, int sx, int sy, int sz) {
+  for (int depth = 0; depth <= kMaxTreeDepth; ++depth) {
+    const TreeNode nd = G.nodes[q];
+    if (nd.axis < 0) return nd.child;
+    const double sp = nd.split;
+    const bool u0 = px > sp || (px == sp && sx >= 0);
+    const bool u1 = py > sp || (py == sp && sy >= 0);
+    const bool u2 = pz > sp || (pz == sp && sz >= 0);
+    const bool up = (nd.axis == 0 && u0) || (nd.axis == 1 && u1) || (nd.axis == 2 && u2);
+    q = nd.child + (up ? 1 : 0);
+  }
+  return -1;
+}
 
 // Cell along one axis of a rectilinear grid: the largest c in [0, n - 1]
 // with P[c] <= x (0 below the first plane).
@@ -295,11 +337,20 @@ MCRT_HD int frame_pixel(const DetDev& D, const double r[3]) {
 // nearly parallel to an axis would magnify it -- so the FP32 walk's times
 // carry a relative error of a few units of R, as on a regular grid.
 
+//
+// On a tree grid the walk carries, in FP64, the current point e (the start
+// of the current segment), the direction k and the segment's start time tc
+// (from the entry), and i[0] is the current cell; each crossing leaves that
+// leaf through its nearest face, with the exit faces' coordinates set to
+// the faces' planes exactly, and finds the neighbour through the face's rope
+// (tree_cross).
+
 template <typename R>
 struct Ray {
   R t0[3], dt[3];
   R tp[3];       // rectilinear grids only
-  double e[3];   // rectilinear grids only
+  double e[3];   // rectilinear and tree grids
+  double k[3], tc;  // tree grids only
   int j[3], i[3], s[3];
   R t, tau;
   double tin;  // FP64 entry time (0 for rays starting inside)
@@ -325,7 +376,7 @@ MCRT_HD R rect_tplane(const Ray<R>& ry, const GridDev& G, int a) {
 // table (rectilinear grids), with the lower cell for a coordinate on a wall
 // while moving down; rays missing the grid (or with non-finite data) are
 // left inactive with tau = 0.
-template <typename R, bool RECT = false>
+template <typename R, int GK = kGridRegular>
 MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const double k[3]) {
   double tin = 0.0, tout = INFINITY;
   int entry = -1;
@@ -358,12 +409,29 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const do
     ry.tin = 0.0;
     return;
   }
+  if constexpr (GK == kGridTree) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      ry.s[a] = par[a] ? 0 : (k[a] > 0.0 ? 1 : -1);
+      ry.k[a] = par[a] ? 0.0 : k[a];
+      ry.e[a] = a == entry ? (k[a] > 0.0 ? G.lo[a] : G.hi[a]) : o[a] + tin * k[a];
+      ry.j[a] = 0;
+      ry.i[a] = 0;
+    }
+    ry.i[0] = tree_find(G, 0, ry.e[0], ry.e[1], ry.e[2], ry.s[0], ry.s[1], ry.s[2]);
+    ry.tc = 0.0;
+    ry.t = R(0);
+    ry.tin = tin;
+    ry.tau = R(0);
+    ry.active = ry.i[0] >= 0;
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     int i;
     if (a == entry) {
       i = k[a] > 0.0 ? 0 : G.n[a] - 1;
-    } else if constexpr (RECT) {
+    } else if constexpr (GK == kGridRect) {
       const double x = o[a] + tin * k[a];
       i = rect_cell(G.pa[a], G.n[a], x);
       if (!par[a] && k[a] < 0.0 && x == G.pa[a][i]) i -= 1;
@@ -378,7 +446,7 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const do
     }
     ry.i[a] = i;
     ry.j[a] = 0;
-    if constexpr (RECT) {
+    if constexpr (GK == kGridRect) {
       ry.s[a] = par[a] ? 0 : (k[a] > 0.0 ? 1 : -1);
       ry.e[a] = o[a] + tin * k[a] - G.pa[a][0];
       ry.t0[a] = R(0);
@@ -411,9 +479,9 @@ MCRT_HD int ray_cell(const Ray<R>& ry, const GridDev& G) {
 }
 
 // Crossing time of the next plane ahead along axis a.
-template <typename R, bool RECT = false>
+template <typename R, int GK = kGridRegular>
 MCRT_HD R ray_tplane(const Ray<R>& ry, int a) {
-  if constexpr (RECT)
+  if constexpr (GK == kGridRect)
     return ry.tp[a];
   else
     return fmaR((R)ry.j[a], ry.dt[a], ry.t0[a]);
@@ -438,20 +506,100 @@ struct WalkBlock {
   int n;         // valid entries (>= 1 for an active ray)
   unsigned adv;  // axes advanced at sub-step d: bits 3d .. 3d+2
   bool out;      // the walk has left the grid after entry n-1
+  double tc0, tend64[D];  // tree grids: FP64 start of the block and segment ends
 };
+
+// One crossing of a tree grid: the current leaf (i[0], verified to hold the
+// ray's point, else found from the root), its exit time (FP64, from the
+// grid entry) and whether the exit face is the box's; moves the point to the
+// exit -- the exit faces' coordinates set to the faces' planes exactly, the
+// others advanced along k -- and finds the next leaf: across a single face,
+// by descending from the face's rope (the deepest node covering the face),
+// across an edge or corner, from the root.  A non-finite or negative exit
+// time also ends the walk.
+template <typename R>
+MCRT_HD void tree_cross(Ray<R>& ry, const GridDev& G, int& cell, double& tend, bool& out) {
+  const double px = ry.e[0], py = ry.e[1], pz = ry.e[2];
+  const int sx = ry.s[0], sy = ry.s[1], sz = ry.s[2];
+  int c = ry.i[0];
+  double l0 = 0, l1 = 0, l2 = 0, h0 = -1, h1 = -1, h2 = -1;
+  if (c >= 0) {
+    const double* bx = G.leaf_box + 6 * (long long)c;
+    l0 = bx[0], l1 = bx[1], l2 = bx[2], h0 = bx[3], h1 = bx[4], h2 = bx[5];
+  }
+  if (!(px >= l0 && px <= h0 && py >= l1 && py <= h1 && pz >= l2 && pz <= h2)) {
+    c = tree_find(G, 0, px, py, pz, sx, sy, sz);
+    if (c >= 0) {
+      const double* bx = G.leaf_box + 6 * (long long)c;
+      l0 = bx[0], l1 = bx[1], l2 = bx[2], h0 = bx[3], h1 = bx[4], h2 = bx[5];
+    }
+  }
+  cell = c;
+  const double tx = sx > 0 ? (h0 - px) / ry.k[0] : (sx < 0 ? (l0 - px) / ry.k[0] : INFINITY);
+  const double ty = sy > 0 ? (h1 - py) / ry.k[1] : (sy < 0 ? (l1 - py) / ry.k[1] : INFINITY);
+  const double tz = sz > 0 ? (h2 - pz) / ry.k[2] : (sz < 0 ? (l2 - pz) / ry.k[2] : INFINITY);
+  const double tm = fmin(tx, fmin(ty, tz));
+  const bool valid = c >= 0 && tm >= 0.0 && tm < INFINITY;
+  const bool ex = tx == tm, ey = ty == tm, ez = tz == tm;
+  const double fx = sx > 0 ? h0 : l0, fy = sy > 0 ? h1 : l1, fz = sz > 0 ? h2 : l2;
+  const bool boundary = (ex && fx == (sx > 0 ? G.hi[0] : G.lo[0])) || (ey && fy == (sy > 0 ? G.hi[1] : G.lo[1])) ||
+                        (ez && fz == (sz > 0 ? G.hi[2] : G.lo[2]));
+  const double nx = ex ? fx : px + tm * ry.k[0];
+  const double ny = ey ? fy : py + tm * ry.k[1];
+  const double nz = ez ? fz : pz + tm * ry.k[2];
+  out = !valid || boundary;
+  if (valid) {
+    ry.e[0] = nx;
+    ry.e[1] = ny;
+    ry.e[2] = nz;
+    ry.tc += tm;
+  }
+  tend = ry.tc;
+  if (out) return;
+  const int n_exit = (int)ex + (int)ey + (int)ez;
+  const int face = ex ? (sx > 0 ? 1 : 0) : (ey ? (sy > 0 ? 3 : 2) : (sz > 0 ? 5 : 4));
+  const int r = n_exit == 1 ? G.ropes[6 * (long long)c + face] : 0;
+  ry.i[0] = tree_find(G, r < 0 ? 0 : r, nx, ny, nz, sx, sy, sz);
+}
 
 // LOAD = false skips the density loads (walks whose work does not depend on
 // the densities, such as the adjoint's peel-ray deposits).  The grid kind
-// comes from the accessor (Mem::kRect).
+// comes from the accessor (Mem::kGrid).
 template <int D, typename R, class Mem, bool LOAD = true>
 MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, const GridDev& G, Mem& M) {
-  constexpr bool RECT = Mem::kRect;
+  constexpr int GK = Mem::kGrid;
   b.n = 0;
   b.adv = 0;
   b.out = false;
+  if constexpr (GK == kGridTree) {
+    b.tc0 = ry.tc;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (!b.out) {
+        int cell;
+        double te;
+        bool out;
+        tree_cross(ry, G, cell, te, out);
+        b.cell[d] = cell < 0 ? 0 : cell;
+        b.tend64[d] = te;
+        b.tend[d] = (R)te;
+        b.n += 1;
+        b.out = out;
+      } else {
+        b.cell[d] = b.cell[d > 0 ? d - 1 : 0];
+        b.tend64[d] = b.tend64[d > 0 ? d - 1 : 0];
+        b.tend[d] = b.tend[d > 0 ? d - 1 : 0];
+      }
+    }
+    if constexpr (LOAD) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) b.rho[d] = M.rho(b.cell[d]);
+    }
+    return;
+  }
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    const R tx = ray_tplane<R, RECT>(ry, 0), ty = ray_tplane<R, RECT>(ry, 1), tz = ray_tplane<R, RECT>(ry, 2);
+    const R tx = ray_tplane<R, GK>(ry, 0), ty = ray_tplane<R, GK>(ry, 1), tz = ray_tplane<R, GK>(ry, 2);
     const R tm = fmin(tx, fmin(ty, tz));
     const bool live = !b.out;
     const bool ax = live && tx == tm, ay = live && ty == tm, az = live && tz == tm;
@@ -463,7 +611,7 @@ MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, const GridDev& G, Me
     ry.j[0] += ax;
     ry.j[1] += ay;
     ry.j[2] += az;
-    if constexpr (RECT) {
+    if constexpr (GK == kGridRect) {
       if (ax) ry.tp[0] = rect_tplane(ry, G, 0);
       if (ay) ry.tp[1] = rect_tplane(ry, G, 1);
       if (az) ry.tp[2] = rect_tplane(ry, G, 2);
@@ -482,8 +630,20 @@ MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, const GridDev& G, Me
 
 // Undoes the plane crossings of sub-steps d .. D-1 of the last block, so the
 // ray again describes the walk inside cell b.cell[d].
-template <int D, typename R, bool RECT = false>
+template <int D, typename R, int GK = kGridRegular>
 MCRT_HD void ray_rewind(Ray<R>& ry, const WalkBlock<D, R>& b, int d, const GridDev& G) {
+  if constexpr (GK == kGridTree) {  // back to the start of segment d (only its entry time is used)
+    double tc = b.tc0;
+    int cell = b.cell[0];
+#pragma unroll
+    for (int e = 1; e < D; ++e) {
+      tc = e == d ? b.tend64[e - 1] : tc;
+      cell = e == d ? b.cell[e] : cell;
+    }
+    ry.tc = tc;
+    ry.i[0] = cell;
+    return;
+  }
   for (int e = d; e < D; ++e) {
     const unsigned m = b.adv >> (3 * e);
 #pragma unroll
@@ -493,7 +653,7 @@ MCRT_HD void ray_rewind(Ray<R>& ry, const WalkBlock<D, R>& b, int d, const GridD
       ry.i[a] -= x * ry.s[a];
     }
   }
-  if constexpr (RECT) {
+  if constexpr (GK == kGridRect) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) ry.tp[a] = rect_tplane(ry, G, a);
   }
@@ -502,15 +662,16 @@ MCRT_HD void ray_rewind(Ray<R>& ry, const WalkBlock<D, R>& b, int d, const GridD
 // FP64 entry time of the current cell, in the original parametrisation of
 // the ray: the latest plane already crossed, or the ray's entry time.  Moving
 // up into cell i the last plane crossed is plane i; moving down, plane i + 1.
-template <typename R, bool RECT = false>
+template <typename R, int GK = kGridRegular>
 MCRT_HD double ray_cell_entry64(const Ray<R>& ry, const GridDev& G, const double o[3], const double k[3]) {
+  if constexpr (GK == kGridTree) return ry.tin + ry.tc;
   double t = ry.tin;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (ry.s[a] == 0 || ry.j[a] == 0) continue;
     const int p = ry.s[a] > 0 ? ry.i[a] : ry.i[a] + 1;
     double plane;
-    if constexpr (RECT)
+    if constexpr (GK == kGridRect)
       plane = G.pa[a][p];
     else
       plane = G.lo[a] + (double)p * G.d[a];

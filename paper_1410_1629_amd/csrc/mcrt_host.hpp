@@ -36,6 +36,58 @@ inline int fail(int code, const char* fmt, ...) {
 
 inline bool finite(double v) { return std::isfinite(v); }
 
+// Tree grid checks: the nodes form a tree rooted at node 0 whose splits lie
+// strictly inside their nodes, with the leaves numbering the cells once each.
+inline int check_tree(const mcrt_grid& g) {
+  const long long nn = g.tree_nodes, ncell = (long long)g.nx * g.ny * g.nz;
+  if (nn < 1) return fail(MCRT_EINVAL, "tree_nodes = %lld must be >= 1", nn);
+  if (!g.tree_axis || !g.tree_split || !g.tree_child) return fail(MCRT_EINVAL, "tree arrays are NULL");
+  std::vector<double> lo(3 * nn), hi(3 * nn);
+  std::vector<int> depth(nn, -1);
+  std::vector<char> cell_used(ncell, 0);
+  const double box[6] = {g.xmin, g.xmax, g.ymin, g.ymax, g.zmin, g.zmax};
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = box[2 * a];
+    hi[a] = box[2 * a + 1];
+  }
+  depth[0] = 0;
+  long long leaves = 0;
+  for (long long q = 0; q < nn; ++q) {  // children are numbered above their parent
+    if (depth[q] < 0) return fail(MCRT_EINVAL, "tree node %lld is not reached from node 0", q);
+    const int ax = g.tree_axis[q];
+    const int c = g.tree_child[q];
+    if (ax < 0) {
+      if (ax != -1 || c < 0 || c >= ncell || cell_used[c])
+        return fail(MCRT_EINVAL, "tree leaf %lld has cell %d (axis %d): cells must be 0..%lld, once each", q, c, ax,
+                    ncell - 1);
+      cell_used[c] = 1;
+      ++leaves;
+      continue;
+    }
+    const double sp = g.tree_split[q];
+    if (ax > 2 || !finite(sp) || !(sp > lo[3 * q + ax] && sp < hi[3 * q + ax]))
+      return fail(MCRT_EINVAL, "tree node %lld: axis %d, split %g not strictly inside the node", q, ax, sp);
+    if (c <= q || (long long)c + 1 >= nn) return fail(MCRT_EINVAL, "tree node %lld: children %d, %d out of order", q, c,
+                                                       c + 1);
+    if (depth[q] + 1 > kMaxTreeDepth) return fail(MCRT_EINVAL, "tree deeper than %d levels", kMaxTreeDepth);
+    for (int side = 0; side < 2; ++side) {
+      const long long ch = c + side;
+      if (depth[ch] >= 0) return fail(MCRT_EINVAL, "tree node %lld is reached twice", ch);
+      depth[ch] = depth[q] + 1;
+      for (int a = 0; a < 3; ++a) {
+        lo[3 * ch + a] = lo[3 * q + a];
+        hi[3 * ch + a] = hi[3 * q + a];
+      }
+      if (side == 0)
+        hi[3 * ch + ax] = sp;
+      else
+        lo[3 * ch + ax] = sp;
+    }
+  }
+  if (leaves != ncell) return fail(MCRT_EINVAL, "tree has %lld leaves for %lld cells", leaves, ncell);
+  return 0;
+}
+
 inline int check_grid(const mcrt_grid* g) {
   if (!g) return fail(MCRT_EINVAL, "grid is NULL");
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(MCRT_EINVAL, "grid cell counts must be >= 1");
@@ -46,6 +98,10 @@ inline int check_grid(const mcrt_grid* g) {
   for (int a = 0; a < 3; ++a)
     if (!finite(b[2 * a]) || !finite(b[2 * a + 1]) || !(b[2 * a + 1] > b[2 * a]))
       return fail(MCRT_EINVAL, "grid extent along axis %d must be finite and increasing", a);
+  if (g->tree_nodes != 0) {
+    if (g->planes) return fail(MCRT_EINVAL, "a grid has planes or a tree, not both");
+    if (int e = check_tree(*g)) return e;
+  }
   if (g->planes) {
     const int n[3] = {g->nx, g->ny, g->nz};
     const double* p = g->planes;
@@ -63,19 +119,93 @@ inline int check_grid(const mcrt_grid* g) {
 
 inline size_t align_up256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Plane tables of a rectilinear grid (0 bytes for a regular one): absolute,
-// then relative to each axis's first plane, FP64, n + 1 per axis, each table
-// 256-byte aligned.
-inline size_t plane_bytes(const GridDev& G) {
-  if (!G.rect) return 0;
+// Leaf tables of a tree grid (checked by check_tree): the box of each cell
+// (lo x y z, hi x y z) and its ropes (Popov, Guenther, Seidel & Slusallek,
+// "Stackless KD-tree traversal", Eurographics 2007): for each face (-x, +x,
+// -y, +y, -z, +z) the deepest node whose region covers everything across
+// that face, -1 on the box's faces.  Built top-down: a split gives each
+// child its parent's ropes plus its sibling across the split plane, and
+// every rope is pushed down while one child of the rope node still covers
+// the whole face.
+inline void tree_leaf_tables(const mcrt_grid& g, double* box, int* ropes) {
+  const size_t nn = (size_t)g.tree_nodes;
+  std::vector<double> lo(3 * nn), hi(3 * nn);
+  std::vector<int> rp(6 * nn, -1);
+  const double b[6] = {g.xmin, g.xmax, g.ymin, g.ymax, g.zmin, g.zmax};
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = b[2 * a];
+    hi[a] = b[2 * a + 1];
+  }
+  for (size_t q = 0; q < nn; ++q) {
+    const int ax = g.tree_axis[q];
+    if (ax < 0) {
+      const int c = g.tree_child[q];
+      for (int a = 0; a < 3; ++a) {
+        box[6 * (size_t)c + a] = lo[3 * q + a];
+        box[6 * (size_t)c + 3 + a] = hi[3 * q + a];
+      }
+      for (int f = 0; f < 6; ++f) ropes[6 * (size_t)c + f] = rp[6 * q + f];
+      continue;
+    }
+    const size_t c0 = (size_t)g.tree_child[q];
+    for (int side = 0; side < 2; ++side) {
+      const size_t ch = c0 + side;
+      for (int a = 0; a < 3; ++a) {
+        lo[3 * ch + a] = lo[3 * q + a];
+        hi[3 * ch + a] = hi[3 * q + a];
+      }
+      (side == 0 ? hi : lo)[3 * ch + ax] = g.tree_split[q];
+      for (int f = 0; f < 6; ++f) rp[6 * ch + f] = rp[6 * q + f];
+      rp[6 * ch + 2 * ax + (side == 0 ? 1 : 0)] = (int)(c0 + 1 - side);
+      for (int f = 0; f < 6; ++f) {  // push the rope down
+        int r = rp[6 * ch + f];
+        const int fa = f / 2;
+        const bool up = f % 2 == 1;
+        while (r >= 0 && g.tree_axis[r] >= 0) {
+          const int ra = g.tree_axis[r];
+          const double rs = g.tree_split[r];
+          if (ra == fa)
+            r = g.tree_child[r] + (up ? 0 : 1);
+          else if (hi[3 * ch + ra] <= rs)
+            r = g.tree_child[r];
+          else if (lo[3 * ch + ra] >= rs)
+            r = g.tree_child[r] + 1;
+          else
+            break;
+        }
+        rp[6 * ch + f] = r;
+      }
+    }
+  }
+}
+
+// Tables of a rectilinear grid (absolute planes, then relative to each
+// axis's first plane, FP64, n + 1 per axis, 256-byte aligned) or of a tree
+// grid (the nodes); 0 bytes for a regular grid.
+inline size_t plane_bytes(const GridDev& G, const mcrt_grid& g) {
+  if (G.kind == kGridTree)
+    return align_up256(sizeof(TreeNode) * (size_t)g.tree_nodes) + align_up256(sizeof(double) * 6 * (size_t)G.ncell) +
+           align_up256(sizeof(int) * 6 * (size_t)G.ncell);
+  if (G.kind != kGridRect) return 0;
   const size_t n = (size_t)(G.n[0] + 1) + (G.n[1] + 1) + (G.n[2] + 1);
   return 2 * align_up256(n * sizeof(double));
 }
 
-// Writes the tables of g at `host` (plane_bytes(G) bytes) and points G at
-// their copy at `dev` (the same bytes in device memory, or `host` itself).
+// Writes the tables of g at `host` (plane_bytes bytes) and points G at their
+// copy at `dev` (the same bytes in device memory, or `host` itself).
 inline void put_planes(const mcrt_grid& g, GridDev& G, unsigned char* host, const unsigned char* dev) {
-  if (!G.rect) return;
+  if (G.kind == kGridTree) {
+    const size_t nn = (size_t)g.tree_nodes, o_box = align_up256(sizeof(TreeNode) * nn),
+                 o_rope = o_box + align_up256(sizeof(double) * 6 * (size_t)G.ncell);
+    TreeNode* nodes = reinterpret_cast<TreeNode*>(host);
+    for (size_t q = 0; q < nn; ++q) nodes[q] = TreeNode{g.tree_split[q], g.tree_axis[q], g.tree_child[q]};
+    tree_leaf_tables(g, reinterpret_cast<double*>(host + o_box), reinterpret_cast<int*>(host + o_rope));
+    G.nodes = reinterpret_cast<const TreeNode*>(dev);
+    G.leaf_box = reinterpret_cast<const double*>(dev + o_box);
+    G.ropes = reinterpret_cast<const int*>(dev + o_rope);
+    return;
+  }
+  if (G.kind != kGridRect) return;
   const size_t n = (size_t)(G.n[0] + 1) + (G.n[1] + 1) + (G.n[2] + 1);
   const size_t o_qd = align_up256(n * sizeof(double));
   double* pa = reinterpret_cast<double*>(host);
@@ -152,8 +282,24 @@ inline int make_grid(const mcrt_grid& g, int elem_bytes, int brick_shape, GridDe
     G.d[a] = (G.hi[a] - G.lo[a]) / n[a];
     G.inv_d[a] = 1.0 / G.d[a];
   }
-  G.rect = g.planes ? 1 : 0;
+  G.kind = g.tree_nodes > 0 ? kGridTree : (g.planes ? kGridRect : kGridRegular);
   for (int a = 0; a < 3; ++a) G.pa[a] = G.qd[a] = nullptr;
+  G.nodes = nullptr;
+  if (G.kind == kGridTree) {  // the leaves as a one-dimensional array, no bricks
+    const int nc = g.nx * g.ny * g.nz;
+    for (int a = 0; a < 3; ++a) {
+      G.n[a] = a == 0 ? nc : 1;
+      G.lb[a] = 0;
+      G.nb[a] = G.n[a];
+    }
+    G.stride[0] = 1;
+    G.stride[1] = G.stride[2] = nc;
+    G.ncell = nc;
+    G.bstride[0] = 1;
+    G.bstride[1] = G.bstride[2] = nc;
+    G.ncell_pad = nc;
+    return 0;
+  }
   G.stride[0] = 1;
   G.stride[1] = g.nx;
   G.stride[2] = g.nx * g.ny;

@@ -140,9 +140,9 @@ __device__ __forceinline__ unsigned long long* wave_reservoir(unsigned long long
 // ---------------------------------------------------------------------------
 // Device memory accessors.
 
-template <typename R, bool RECT>
+template <typename R, int GK>
 struct LifeMem {
-  static constexpr bool kRect = RECT;
+  static constexpr int kGrid = GK;
   const R* __restrict__ rho_;
   const RunParams& P;
   unsigned long long* res;
@@ -191,9 +191,9 @@ struct LifeMem {
   }
 };
 
-template <typename R, bool RECT>
+template <typename R, int GK>
 struct TraceMem {
-  static constexpr bool kRect = RECT;
+  static constexpr int kGrid = GK;
   const R* __restrict__ rho_;
   const TraceParams& P;
   unsigned long long* res;
@@ -215,9 +215,9 @@ struct TraceMem {
   }
 };
 
-template <typename R, bool RECT>
+template <typename R, int GK>
 struct PeelMem {
-  static constexpr bool kRect = RECT;
+  static constexpr int kGrid = GK;
   const R* __restrict__ rho_;
   const PeelParams& P;
   unsigned long long* res;
@@ -240,16 +240,16 @@ struct PeelMem {
 // Kernels.
 
 // The life-cycle kernel body; k_life (FP32 walk) and k_life64 (FP64 walk)
-// launch it, for regular (RECT = false) or rectilinear grids.  The FP64
+// launch it, once per grid kind (GK, kGrid*).  The FP64
 // kernel asks for two wavefronts per SIMD, which its register use would
 // otherwise just miss.
-template <typename R, bool ADJ, bool RECT>
+template <typename R, bool ADJ, int GK>
 __device__ __forceinline__ void life_body(const RunParams& P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2], job_slots[kWavesPerBlock][2];
   __shared__ long long dep_idx[kWavesPerBlock][64 * kBlockWalk];
   __shared__ double dep_val[kWavesPerBlock][64 * kBlockWalk];
   const int wave = threadIdx.x / 64;
-  LifeMem<R, RECT> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots), wave_reservoir(job_slots)};
+  LifeMem<R, GK> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots), wave_reservoir(job_slots)};
   Lane<R> L;
   lane_init(L);
   for (;;) {
@@ -288,20 +288,20 @@ __device__ __forceinline__ void life_body(const RunParams& P) {
   }
 }
 
-template <typename R, bool ADJ, bool RECT>
+template <typename R, bool ADJ, int GK>
 __global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
-  life_body<R, ADJ, RECT>(P);
+  life_body<R, ADJ, GK>(P);
 }
 
-template <bool ADJ, bool RECT>
+template <bool ADJ, int GK>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_life64(const RunParams P) {
-  life_body<double, ADJ, RECT>(P);
+  life_body<double, ADJ, GK>(P);
 }
 
-template <typename R, bool RECT>
+template <typename R, int GK>
 __global__ void __launch_bounds__(kBlock) k_trace(const TraceParams P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2];
-  TraceMem<R, RECT> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots)};
+  TraceMem<R, GK> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots)};
   TraceLane<R> L;
   trace_init(L);
   for (;;) {
@@ -322,10 +322,10 @@ __global__ void __launch_bounds__(kBlock) k_trace(const TraceParams P) {
   }
 }
 
-template <typename R, bool RECT>
+template <typename R, int GK>
 __global__ void __launch_bounds__(kBlock) k_peel(const PeelParams P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2];
-  PeelMem<R, RECT> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots)};
+  PeelMem<R, GK> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots)};
   PeelLane<R> L;
   peel_init(L);
   for (;;) {
@@ -542,9 +542,9 @@ struct PeelJobParams {
 // into the workgroup's LDS table (open addressing, linear probing over at
 // most kProbes slots); a deposit that finds no slot goes straight to the
 // global tally.
-template <typename R, bool RECT>
+template <typename R, int GK>
 struct PeelJobMem {
-  static constexpr bool kRect = RECT;
+  static constexpr int kGrid = GK;
   const R* __restrict__ rho_;
   int* tk;
   double* tv;
@@ -591,11 +591,11 @@ __device__ __forceinline__ void flush_images(bool& has, long long ii, double c, 
 // loads).  Forward: C = v e^-tau goes to the ray's pixel (flush_images).
 // Adjoint: q = (dL/dI) v e^-tau goes to the event scratch, and the job's v
 // becomes the deposit weight -q kappa (0: no deposit walk).
-template <typename R, bool ADJ, bool RECT>
+template <typename R, bool ADJ, int GK>
 __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2];
   unsigned long long* res = wave_reservoir(slots);
-  const PeelJobMem<R, RECT> M{static_cast<const R*>(P.rho), nullptr, nullptr, P.grad};
+  const PeelJobMem<R, GK> M{static_cast<const R*>(P.rho), nullptr, nullptr, P.grad};
   const unsigned n_jobs = *P.n_sorted;
   unsigned long long nx = 0;
   Ray<R> ry;
@@ -634,7 +634,7 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
       job = P.perm[qi];
       const PeelJob& J = P.jobs[job];
       kap = (R)P.lam[J.lam].kappa;
-      ray_begin<R, RECT>(ry, P.G, J.r, P.det[J.d].kd);
+      ray_begin<R, GK>(ry, P.G, J.r, P.det[J.d].kd);
       pending = true;
     }
     if (!ADJ) flush_images(has, out_ii, out_c, P.images);
@@ -654,7 +654,7 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
 // The deposit walks of the sorted queue: chunks of consecutive sorted jobs
 // per workgroup, deposits summed per cell in the LDS table, one global
 // atomic per distinct cell and chunk.  Jobs whose weight is 0 are skipped.
-template <typename R, bool RECT>
+template <typename R, int GK>
 __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams P) {
   __shared__ int tk[kTable];
   __shared__ double tv[kTable];
@@ -663,7 +663,7 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
     tk[i] = -1;
     tv[i] = 0.0;
   }
-  const PeelJobMem<R, RECT> M{static_cast<const R*>(P.rho), tk, tv, P.grad};
+  const PeelJobMem<R, GK> M{static_cast<const R*>(P.rho), tk, tv, P.grad};
   const unsigned n_jobs = *P.n_sorted;
   unsigned long long nd = 0;
   for (;;) {
@@ -688,7 +688,7 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
         }
         const PeelJob& J = P.jobs[P.perm[qi]];
         w = J.v;
-        if (w != 0.0) ray_begin<R, RECT>(ry, P.G, J.r, P.det[J.d].kd);
+        if (w != 0.0) ray_begin<R, GK>(ry, P.G, J.r, P.det[J.d].kd);
       }
       const unsigned long long live = __ballot(!done);
       if (live == 0ull) break;
@@ -786,6 +786,12 @@ int launch_persistent(K kernel, const Params& P, hipStream_t st) {
   if (int e = persistent_grid(kernel, 0, &nblk)) return e;
   hipLaunchKernelGGL(kernel, dim3(nblk), dim3(kBlock), 0, st, P);
   return 0;
+}
+
+// Launches the grid kind's variant of a persistent kernel.
+template <typename Params, typename R, typename K>
+int launch_by_kind(const Params& P, hipStream_t st, K regular, K rect, K tree) {
+  return launch_persistent(P.G.kind == kGridRect ? rect : (P.G.kind == kGridTree ? tree : regular), P, st);
 }
 
 unsigned stream_blocks(long long n) { return (unsigned)std::min<long long>((n + kBlock - 1) / kBlock, 16384); }
@@ -904,17 +910,17 @@ int reset_counters(unsigned long long* ctr, int w, int n, hipStream_t st) {
 
 // The queue's walks: optical depth (and the image, forward), then the
 // adjoint's deposit walks.
-template <typename R, bool ADJ, bool RECT>
+template <typename R, bool ADJ, int GK>
 int walk_peel_jobs(const PeelJobParams& J, hipStream_t st) {
   int nblk = 0;
-  if (int e = persistent_grid(k_peeltau<R, ADJ, RECT>, 0, &nblk)) return e;
-  hipLaunchKernelGGL((k_peeltau<R, ADJ, RECT>), dim3(nblk), dim3(kBlock), 0, st, J);
+  if (int e = persistent_grid(k_peeltau<R, ADJ, GK>, 0, &nblk)) return e;
+  hipLaunchKernelGGL((k_peeltau<R, ADJ, GK>), dim3(nblk), dim3(kBlock), 0, st, J);
   if (ADJ) {
     int dev = 0, cus = 0, nb = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peeldep<R, RECT>, kBundleThreads, 0));
-    hipLaunchKernelGGL((k_peeldep<R, RECT>), dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0, st,
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peeldep<R, GK>, kBundleThreads, 0));
+    hipLaunchKernelGGL((k_peeldep<R, GK>), dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0, st,
                        J);
   }
   HIPCHK(hipGetLastError());
@@ -954,36 +960,46 @@ int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ct
   J.n_chunk = P.n_chunk;
   J.ctr = ctr;
   J.batch = 16;
-  return P.G.rect ? walk_peel_jobs<R, ADJ, true>(J, st) : walk_peel_jobs<R, ADJ, false>(J, st);
+  switch (P.G.kind) {
+    case kGridRect: return walk_peel_jobs<R, ADJ, kGridRect>(J, st);
+    case kGridTree: return walk_peel_jobs<R, ADJ, kGridTree>(J, st);
+    default: return walk_peel_jobs<R, ADJ, kGridRegular>(J, st);
+  }
 }
 
-template <typename R, bool ADJ, bool RECT>
+template <typename R, bool ADJ, int GK>
 int life_grid_k(int blocks_per_cu, int* nblk) {
   if constexpr (std::is_same<R, double>::value)
-    return persistent_grid(k_life64<ADJ, RECT>, blocks_per_cu, nblk);
+    return persistent_grid(k_life64<ADJ, GK>, blocks_per_cu, nblk);
   else
-    return persistent_grid(k_life<R, ADJ, RECT>, blocks_per_cu, nblk);
+    return persistent_grid(k_life<R, ADJ, GK>, blocks_per_cu, nblk);
 }
 
 template <typename R, bool ADJ>
-int life_grid(bool rect, int blocks_per_cu, int* nblk) {
-  return rect ? life_grid_k<R, ADJ, true>(blocks_per_cu, nblk) : life_grid_k<R, ADJ, false>(blocks_per_cu, nblk);
+int life_grid(int kind, int blocks_per_cu, int* nblk) {
+  switch (kind) {
+    case kGridRect: return life_grid_k<R, ADJ, kGridRect>(blocks_per_cu, nblk);
+    case kGridTree: return life_grid_k<R, ADJ, kGridTree>(blocks_per_cu, nblk);
+    default: return life_grid_k<R, ADJ, kGridRegular>(blocks_per_cu, nblk);
+  }
 }
 
-template <typename R, bool ADJ, bool RECT>
+template <typename R, bool ADJ, int GK>
 void launch_life_k(const RunParams& P, int nblk, hipStream_t st) {
   if constexpr (std::is_same<R, double>::value)
-    hipLaunchKernelGGL((k_life64<ADJ, RECT>), dim3(nblk), dim3(kBlock), 0, st, P);
+    hipLaunchKernelGGL((k_life64<ADJ, GK>), dim3(nblk), dim3(kBlock), 0, st, P);
   else
-    hipLaunchKernelGGL((k_life<R, ADJ, RECT>), dim3(nblk), dim3(kBlock), 0, st, P);
+    hipLaunchKernelGGL((k_life<R, ADJ, GK>), dim3(nblk), dim3(kBlock), 0, st, P);
 }
 
 template <typename R, bool ADJ>
 int launch_life(const RunParams& P, int nblk, hipStream_t st) {
-  if (P.G.rect)
-    launch_life_k<R, ADJ, true>(P, nblk, st);
+  if (P.G.kind == kGridRect)
+    launch_life_k<R, ADJ, kGridRect>(P, nblk, st);
+  else if (P.G.kind == kGridTree)
+    launch_life_k<R, ADJ, kGridTree>(P, nblk, st);
   else
-    launch_life_k<R, ADJ, false>(P, nblk, st);
+    launch_life_k<R, ADJ, kGridRegular>(P, nblk, st);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -1018,11 +1034,11 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const int nl = P.n_lambda;
   const bool f32 = opts->precision == MCRT_PREC_FP32;
   int nblk = 0;
-  const bool rect = P.G.rect != 0;
-  if (int e = adjoint ? (f32 ? life_grid<float, true>(rect, opts->launch_blocks, &nblk)
-                             : life_grid<double, true>(rect, opts->launch_blocks, &nblk))
-                      : (f32 ? life_grid<float, false>(rect, opts->launch_blocks, &nblk)
-                             : life_grid<double, false>(rect, opts->launch_blocks, &nblk)))
+  const int kind = P.G.kind;
+  if (int e = adjoint ? (f32 ? life_grid<float, true>(kind, opts->launch_blocks, &nblk)
+                             : life_grid<double, true>(kind, opts->launch_blocks, &nblk))
+                      : (f32 ? life_grid<float, false>(kind, opts->launch_blocks, &nblk)
+                             : life_grid<double, false>(kind, opts->launch_blocks, &nblk)))
     return e;
   // packages run in equal chunks: the adjoint's event scratch holds, per
   // package, T and q per frame for kEventsKept events plus the sum of q
@@ -1047,7 +1063,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const size_t off_det = align256(sizeof(LamDev) * nl);
   const size_t off_src = off_det + align256(sizeof(DetDev) * pr.det.size());
   const size_t off_pl = off_src + align256(sizeof(SrcDev) * pr.src.size());
-  const size_t off_cnt = off_pl + host::plane_bytes(P.G);
+  const size_t off_cnt = off_pl + host::plane_bytes(P.G, *grid);
   const size_t off_rho = off_cnt + 256;
   const size_t off_tal = off_rho + align256((size_t)P.G.ncell_pad * (f32 ? 4 : 8));
   const size_t off_evs = off_tal + align256(sizeof(double) * (size_t)n_tally);
@@ -1267,7 +1283,7 @@ int trace_path(const mcrt_grid* grid, const void* rho_dev, double kappa, int pre
     DeviceBlock blk;
     blk.st = st;
     const bool f32 = precision == MCRT_PREC_FP32;
-    const size_t off_rho = 256 + host::plane_bytes(P.G);  // counters, plane tables, densities
+    const size_t off_rho = 256 + host::plane_bytes(P.G, *grid);  // counters, plane tables, densities
     std::vector<unsigned char> blob(off_rho, 0);
     HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), off_rho + (size_t)P.G.ncell_pad * (f32 ? 4 : 8), st));
     host::put_planes(*grid, P.G, blob.data() + 256, blk.ptr + 256);
@@ -1276,10 +1292,10 @@ int trace_path(const mcrt_grid* grid, const void* rho_dev, double kappa, int pre
     P.rho = blk.ptr + off_rho;
     P.work = reinterpret_cast<unsigned long long*>(blk.ptr);
     P.counters = P.work + 1;
-    const int r = f32 ? (P.G.rect ? launch_persistent(k_trace<float, true>, P, st)
-                                  : launch_persistent(k_trace<float, false>, P, st))
-                      : (P.G.rect ? launch_persistent(k_trace<double, true>, P, st)
-                                  : launch_persistent(k_trace<double, false>, P, st));
+    const int r = f32 ? launch_by_kind<TraceParams, float>(P, st, k_trace<float, kGridRegular>,
+                                                           k_trace<float, kGridRect>, k_trace<float, kGridTree>)
+                      : launch_by_kind<TraceParams, double>(P, st, k_trace<double, kGridRegular>,
+                                                            k_trace<double, kGridRect>, k_trace<double, kGridTree>);
     if (r) return r;
     HIPCHK(hipGetLastError());
     if (crossings_host || lists) {
@@ -1312,7 +1328,7 @@ int peel_off(const mcrt_grid* grid, const void* rho_dev, double kappa, double g,
     std::vector<DetDev> det = host::make_dets(n_det, detectors, nullptr);
     const size_t off_cnt = align256(sizeof(DetDev) * det.size());
     const size_t off_pl = off_cnt + 256;
-    const size_t off_rho = off_pl + host::plane_bytes(P.G);
+    const size_t off_rho = off_pl + host::plane_bytes(P.G, *grid);
     const size_t bytes = off_rho + (size_t)P.G.ncell_pad * (f32 ? 4 : 8);
     std::vector<unsigned char> blob(off_rho, 0);
     std::memcpy(blob.data(), det.data(), sizeof(DetDev) * det.size());
@@ -1334,10 +1350,10 @@ int peel_off(const mcrt_grid* grid, const void* rho_dev, double kappa, double g,
     P.images = images_dev;
     P.work = reinterpret_cast<unsigned long long*>(blk.ptr + off_cnt);
     P.batch = 16;
-    const int r = f32 ? (P.G.rect ? launch_persistent(k_peel<float, true>, P, st)
-                                  : launch_persistent(k_peel<float, false>, P, st))
-                      : (P.G.rect ? launch_persistent(k_peel<double, true>, P, st)
-                                  : launch_persistent(k_peel<double, false>, P, st));
+    const int r = f32 ? launch_by_kind<PeelParams, float>(P, st, k_peel<float, kGridRegular>,
+                                                          k_peel<float, kGridRect>, k_peel<float, kGridTree>)
+                      : launch_by_kind<PeelParams, double>(P, st, k_peel<double, kGridRegular>,
+                                                           k_peel<double, kGridRect>, k_peel<double, kGridTree>);
     if (r) return r;
     HIPCHK(hipGetLastError());
     return 0;

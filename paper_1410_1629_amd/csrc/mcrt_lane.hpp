@@ -280,7 +280,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     if (L.phase == PH_LOCATE_END && !want) {
       double s;
       if (L.found) {
-        const double tp = ray_cell_entry64<R, Mem::kRect>(L.ry, G, L.r, L.k);
+        const double tp = ray_cell_entry64<R, Mem::kGrid>(L.ry, G, L.r, L.k);
         s = tp + (L.tau_s - (double)L.tau_prev) / (L.kap * (double)L.rho_hit);
         if (ADJ && L.pass == 1) {
           const double Ri = L.Rtot - L.Gacc;
@@ -434,7 +434,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     //    its end is handled in the next pass)
     if (want) {
       const double* d = to_det ? M.det(L.det).kd : L.k;
-      ray_begin<R, Mem::kRect>(L.ry, G, L.r, d);
+      ray_begin<R, Mem::kGrid>(L.ry, G, L.r, d);
       if (L.mode == M_LOCATE) {
         L.last_cell = ray_cell(L.ry, G);
         L.last_t = L.ry.t;
@@ -510,7 +510,7 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
         L.hit_cell = cell;
         L.tau_prev = ry.tau;
         L.rho_hit = rs;
-        ray_rewind<kBlockWalk, R, Mem::kRect>(ry, b, d, P.G);
+        ray_rewind<kBlockWalk, R, Mem::kGrid>(ry, b, d, P.G);
         ry.active = false;
         return;
       }
@@ -641,7 +641,7 @@ MCRT_HD void trace_events(TraceLane<R>& L, const TraceParams& P, Mem& M) {
     M.ray(L.q, o, k);
     L.nseg = 0;
     L.pending = true;
-    ray_begin<R, Mem::kRect>(L.ry, P.G, o, k);
+    ray_begin<R, Mem::kGrid>(L.ry, P.G, o, k);
   }
 }
 
@@ -723,7 +723,7 @@ MCRT_HD void peel_events(PeelLane<R>& L, const PeelParams& P, Mem& M) {
     L.pix = frame_pixel(M.det(L.d), r);
     if (L.pix < 0) continue;
     L.pending = true;
-    ray_begin<R, Mem::kRect>(L.ry, P.G, r, M.det(L.d).kd);
+    ray_begin<R, Mem::kGrid>(L.ry, P.G, r, M.det(L.d).kd);
   }
 }
 

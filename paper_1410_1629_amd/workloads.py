@@ -8,6 +8,7 @@ arithmetic and imports neither side.
 Problem dict keys:
   name, box (xmin, xmax, ymin, ymax, zmin, zmax), n (nx, ny, nz),
   optional planes (x, y, z cell boundaries of a rectilinear grid),
+  optional tree ({axis, split, child} per node of a tree grid; n = (cells, 1, 1)),
   rho (float64 array [nz, ny, nx]; for precision 1 its values are already
   float32-representable), kappa / albedo / g (one value per wavelength),
   sources [{kind, pos, h_r, h_z, lum[n_lambda]}],
@@ -169,6 +170,162 @@ def powcub_spiral(n_packages=10_000_000, precision=1, seed=DEFAULT_SEED, flags=F
                     n_packages, precision, seed=seed, flags=flags)
     prob["planes"] = planes
     return prob
+
+
+class TreeGrid:
+    """Node lists of a tree grid (Table 1(d)), built level by level: node 0
+    is the box; a level's splits append their children in pairs at the end,
+    so children are numbered above their parent.  axis[q] = -1 marks a leaf
+    whose cell is child[q]; lo/hi hold each node's box."""
+
+    def __init__(self, axis, split, child, lo, hi, n_cells):
+        self.axis, self.split, self.child, self.lo, self.hi, self.n_cells = axis, split, child, lo, hi, n_cells
+
+    def tree(self):
+        return {"axis": self.axis.astype(np.int32), "split": self.split.astype(np.float64),
+                "child": self.child.astype(np.int32)}
+
+    def leaf_boxes(self):
+        """Boxes (lo, hi) of the cells, indexed by cell."""
+        leaf = self.axis < 0
+        lo = np.zeros((self.n_cells, 3))
+        hi = np.zeros((self.n_cells, 3))
+        lo[self.child[leaf]] = self.lo[leaf]
+        hi[self.child[leaf]] = self.hi[leaf]
+        return lo, hi
+
+
+def _grow(box, decide, cell_of=None):
+    """Builds a tree level by level.  decide(lo, hi, state) gets the boxes
+    and per-node state of a level and returns (axis, child_state): the split
+    axis per node (-1: leaf) and the state of its children.  cell_of(lo, hi)
+    numbers the leaves (default: in the order they are closed)."""
+    b_lo, b_hi = np.array(box[0::2], dtype=np.float64), np.array(box[1::2], dtype=np.float64)
+    axis, split, child = [np.array([-1])], [np.array([0.0])], [np.array([0])]
+    los, his = [b_lo[None, :]], [b_hi[None, :]]
+    ids, lo, hi, state = np.array([0]), b_lo[None, :], b_hi[None, :], np.zeros(1, dtype=np.int64)
+    n_nodes, n_cells = 1, 0
+    AX, SP, CH = {0: -1}, {0: 0.0}, {0: 0}
+    ax_all, sp_all, ch_all = np.full(1, -1), np.zeros(1), np.zeros(1, dtype=np.int64)
+    while ids.size:
+        ax, cstate = decide(lo, hi, state)
+        leaf = ax < 0
+        nl = int(leaf.sum())
+        cells = cell_of(lo[leaf], hi[leaf]) if cell_of else np.arange(n_cells, n_cells + nl)
+        n_cells += nl
+        sp_ids = ids[~leaf]
+        a = ax[~leaf]
+        lo_s, hi_s = lo[~leaf], hi[~leaf]
+        k = np.arange(sp_ids.size)
+        mid = 0.5 * (lo_s[k, a] + hi_s[k, a])
+        first = n_nodes + 2 * k
+        # grow the global arrays
+        new_n = n_nodes + 2 * sp_ids.size
+        ax_all = np.concatenate([ax_all, np.full(new_n - n_nodes, -1)])
+        sp_all = np.concatenate([sp_all, np.zeros(new_n - n_nodes)])
+        ch_all = np.concatenate([ch_all, np.zeros(new_n - n_nodes, dtype=np.int64)])
+        ch_all[ids[leaf]] = cells
+        ax_all[sp_ids] = a
+        sp_all[sp_ids] = mid
+        ch_all[sp_ids] = first
+        lo_c = np.repeat(lo_s, 2, axis=0)
+        hi_c = np.repeat(hi_s, 2, axis=0)
+        kk = np.repeat(k, 2)
+        side = np.tile([0, 1], sp_ids.size)
+        aa = np.repeat(a, 2)
+        hi_c[np.arange(kk.size)[side == 0], aa[side == 0]] = np.repeat(mid, 2)[side == 0]
+        lo_c[np.arange(kk.size)[side == 1], aa[side == 1]] = np.repeat(mid, 2)[side == 1]
+        los.append(lo_c)
+        his.append(hi_c)
+        ids = np.arange(n_nodes, new_n)
+        lo, hi, state = lo_c, hi_c, np.repeat(cstate[~leaf], 2)
+        n_nodes = new_n
+    return TreeGrid(ax_all, sp_all, ch_all, np.concatenate(los), np.concatenate(his), n_cells)
+
+
+def regular_tree(box, levels):
+    """A k-d tree that halves the box levels[a] times along each axis (x, y,
+    z in turn): the regular 2^lx x 2^ly x 2^lz grid as a tree, each leaf
+    numbered with the regular grid's cell index i + nx (j + ny k)."""
+    n = np.array([1 << L for L in levels])
+    b_lo = np.array(box[0::2], dtype=np.float64)
+    d = (np.array(box[1::2], dtype=np.float64) - b_lo) / n
+    lv = np.array(levels)
+
+    def decide(lo, hi, state):  # state: halvings done so far, x + 100 y + 10000 z
+        done = np.stack([state % 100, (state // 100) % 100, state // 10000], axis=1)
+        left = lv[None, :] - done
+        ax = np.where(left.max(axis=1) > 0, np.argmax(left > 0, axis=1), -1)
+        inc = np.where(ax == 0, 1, np.where(ax == 1, 100, 10000))
+        return ax, state + inc
+
+    def cell_of(lo, hi):
+        ijk = np.floor((lo - b_lo) / d + 0.5).astype(np.int64)
+        return ijk[:, 0] + n[0] * (ijk[:, 1] + n[1] * ijk[:, 2])
+
+    return _grow(box, decide, cell_of)
+
+
+def adaptive_tree(box, density, max_mass, max_depth, octree=False, samples=2):
+    """A tree grid adapted to a density field: a node is divided while its
+    mass (the density averaged over samples^3 points times the volume) is
+    above max_mass and its depth (in binary levels) below max_depth.  k-d
+    tree: halve the longest side; octree: halve x, then y, then z (one octree
+    level, three binary levels)."""
+    u = (np.arange(samples) + 0.5) / samples
+
+    def mass(lo, hi):
+        pts = [lo[:, a, None] + (hi - lo)[:, a, None] * u[None, :] for a in range(3)]
+        x = pts[0][:, None, None, :]
+        y = pts[1][:, None, :, None]
+        z = pts[2][:, :, None, None]
+        return density(x, y, z).reshape(lo.shape[0], -1).mean(axis=1) * np.prod(hi - lo, axis=1)
+
+    def decide(lo, hi, state):  # state: depth * 4 + octree phase (0: an octree node)
+        depth, phase = state // 4, state % 4
+        if octree:
+            refine = (phase != 0) | ((depth + 3 <= max_depth) & (mass(lo, hi) > max_mass))
+            ax = np.where(refine, phase, -1)
+            return ax, (depth + 1) * 4 + (phase + 1) % 3
+        refine = (depth + 1 <= max_depth) & (mass(lo, hi) > max_mass)
+        ax = np.where(refine, np.argmax(hi - lo, axis=1), -1)
+        return ax, (depth + 1) * 4
+
+    return _grow(box, decide)
+
+
+def tree_problem(name, box, builder, density, kappa, albedo, g, sources, detectors, n_packages, precision,
+                 seed=DEFAULT_SEED, flags=FLAGS_DEFAULT, **kw):
+    """A problem on a tree grid: the density sampled at the leaves' centres."""
+    lo, hi = builder.leaf_boxes()
+    c = 0.5 * (lo + hi)
+    rho = density(c[:, 0], c[:, 1], c[:, 2])
+    if precision == 1:
+        rho = as_f32_values(rho)
+    n = (builder.n_cells, 1, 1)
+    p = _problem(name, box, n, rho.reshape(1, 1, -1), kappa, albedo, g, sources, detectors, n_packages, precision,
+                 seed=seed, flags=flags, **kw)
+    p["tree"] = builder.tree()
+    return p
+
+
+def spiral_dust(x, y, z):
+    """The spiral's dust: kappa*rho = 2 exp(-R/6 - |z|/0.25) per kpc."""
+    return 2.0 * np.exp(-np.sqrt(x * x + y * y) / 6.0 - np.abs(z) / 0.25)
+
+
+def kdtree_spiral(n_packages=10_000_000, precision=1, seed=DEFAULT_SEED, flags=FLAGS_DEFAULT, max_mass=3e-4,
+                  max_depth=30):
+    """The edge-on spiral on a k-d tree grid (Table 1(d), Sect. 2.4) adapted
+    to the dust: a node is halved along its longest side while its dust mass
+    exceeds max_mass (kappa-weighted, kpc^2 units), down to 30 levels; the
+    dust is sampled at the leaves' centres.  Same box, stars and frames as
+    the regular spiral."""
+    box = (-20, 20, -20, 20, -2, 2)
+    B = adaptive_tree(box, spiral_dust, max_mass, max_depth)
+    dets = [_frame(1e4, inc, 512, 512, 20.0, 20.0) for inc in (0.0, 60.0, 90.0)]
+    return tree_problem("kdtree_spiral_%d_cells" % B.n_cells, box, B, spiral_dust, 1.0, 0.6, 0.6,
+                        [_expdisk(4.0, 0.4)], dets, n_packages, precision, seed=seed, flags=flags)
 
 
 def multiwavelength(n_packages=1_000_000, precision=1, n_lambda=100, lambdas=None, seed=DEFAULT_SEED,

@@ -103,8 +103,9 @@ class Emu:
                                                   self._p(adj), adj.size, self._p(g), g.size, C.byref(st), wave))
         return g, st.as_dict()
 
-    def trace(self, box, n, rho, kappa, prec, origins, dirs, max_seg=0, wave=WAVE, brick_shape=0, planes=None):
-        g = B.make_grid({"box": box, "n": n, "planes": planes})
+    def trace(self, box, n, rho, kappa, prec, origins, dirs, max_seg=0, wave=WAVE, brick_shape=0, planes=None,
+              tree=None):
+        g = B.make_grid({"box": box, "n": n, "planes": planes, "tree": tree})
         dt = np.float32 if prec == 1 else np.float64
         rho = np.ascontiguousarray(np.asarray(rho).reshape(-1), dtype=dt)
         o = np.ascontiguousarray(origins, dtype=np.float64).reshape(-1, 3)
@@ -120,8 +121,9 @@ class Emu:
                                      C.byref(c), int(brick_shape), wave)
         return rc, tau, c.value, cell, length, nseg
 
-    def peel(self, box, n, rho, kappa, g, prec, pos, dir_in, w, detectors, wave=WAVE, brick_shape=0, planes=None):
-        gr = B.make_grid({"box": box, "n": n, "planes": planes})
+    def peel(self, box, n, rho, kappa, g, prec, pos, dir_in, w, detectors, wave=WAVE, brick_shape=0, planes=None,
+             tree=None):
+        gr = B.make_grid({"box": box, "n": n, "planes": planes, "tree": tree})
         dt = np.float32 if prec == 1 else np.float64
         rho = np.ascontiguousarray(np.asarray(rho).reshape(-1), dtype=dt)
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)

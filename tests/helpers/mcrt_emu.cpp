@@ -72,9 +72,17 @@ struct HostPlanes {
   std::vector<unsigned char> blob;
   std::vector<double> pa[3], qd[3];
   void attach(const mcrt_grid& g, GridDev& G) {
-    if (!G.rect) return;
-    blob.assign(host::plane_bytes(G), 0);
+    if (G.kind == kGridRegular) return;
+    blob.assign(host::plane_bytes(G, g), 0);
     host::put_planes(g, G, blob.data(), blob.data());
+    if (G.kind == kGridTree) {  // the nodes as the library lays them out, checked
+      for (int q = 0; q < g.tree_nodes; ++q) {
+        EMU_CHECK(G.nodes[q].axis == g.tree_axis[q] && G.nodes[q].child == g.tree_child[q] &&
+                      (G.nodes[q].axis < 0 || G.nodes[q].split == g.tree_split[q]),
+                  "tree node table", q, g.tree_nodes);
+      }
+      return;
+    }
     const double* P = g.planes;
     const double nan = std::nan("");
     for (int a = 0; a < 3; ++a) {
@@ -96,9 +104,9 @@ struct HostPlanes {
   }
 };
 
-template <typename R, bool RECT>
+template <typename R, int GK>
 struct HostLifeMem {
-  static constexpr bool kRect = RECT;
+  static constexpr int kGrid = GK;
   const R* rho_;
   const GridDev& G;
   const host::Prepared& pr;
@@ -245,9 +253,9 @@ void run_wave(std::vector<LaneT>& lanes, int batch, Events events, Step step, lo
 }
 
 // Deposits of the bundled walk, straight into the bricked gradient.
-template <bool RECT>
+template <int GK>
 struct HostBundleMem {
-  static constexpr bool kRect = RECT;
+  static constexpr int kGrid = GK;
   const GridDev& G;
   std::vector<double>& grad;
   void deposit(int cell, double v) {
@@ -262,8 +270,8 @@ struct HostBundleMem {
 // each ray in sorted order: the optical-depth walk; forward, C into its
 // pixel; adjoint, q = (dL/dI) C into the event scratch and, for q != 0, the
 // deposit walk.  Returns the crossings; `deps` gets the deposits.
-template <typename R, bool ADJ, bool RECT>
-unsigned long long emu_peel_jobs(HostLifeMem<R, RECT>& M, const RunParams& P, std::vector<PeelJob>& jobs,
+template <typename R, bool ADJ, int GK>
+unsigned long long emu_peel_jobs(HostLifeMem<R, GK>& M, const RunParams& P, std::vector<PeelJob>& jobs,
                                  unsigned long long n_jobs, std::vector<double>& grad, unsigned long long& deps,
                                  long long cap_steps) {
   const long long n_keys = M.n_keys;
@@ -312,7 +320,7 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, RECT>& M, const RunParams& P, st
       perm[q] = idx[i];
     }
   }
-  HostBundleMem<RECT> D{P.G, grad};
+  HostBundleMem<GK> D{P.G, grad};
   unsigned long long nx = 0;
   deps = 0;
   for (unsigned long long qi = 0; qi < n_valid; ++qi) {
@@ -325,7 +333,7 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, RECT>& M, const RunParams& P, st
     while (d + 1 < P.n_det && (unsigned)M.det(d + 1).key_off <= J.key) ++d;
     EMU_CHECK(d == J.d, "job frame against its key", J.d, P.n_det);
     Ray<R> ry;
-    ray_begin<R, RECT>(ry, P.G, J.r, M.det(J.d).kd);
+    ray_begin<R, GK>(ry, P.G, J.r, M.det(J.d).kd);
     const R kap = (R)M.lam((int)J.lam).kappa;
     long long steps = 0;
     while (ry.active) {
@@ -344,7 +352,7 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, RECT>& M, const RunParams& P, st
       M.ev_add_beyond((int)J.slot, q);
     if (q == 0.0) continue;
     const double w = -q * M.lam((int)J.lam).kappa;
-    ray_begin<R, RECT>(ry, P.G, J.r, M.det(J.d).kd);
+    ray_begin<R, GK>(ry, P.G, J.r, M.det(J.d).kd);
     steps = 0;
     while (ry.active) {
       const unsigned n = bp_step<R>(ry, P.G, w, D);
@@ -356,7 +364,7 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, RECT>& M, const RunParams& P, st
   return nx;
 }
 
-template <typename R, bool ADJ, bool RECT>
+template <typename R, bool ADJ, int GK>
 int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, int n_src, const mcrt_source* sources,
              int n_det, const mcrt_detector* detectors, const mcrt_opts* opts, double* images, long long n_images,
              double* absorbed, long long n_absorbed, const double* adj, long long n_adj, double* grad, long long n_grad,
@@ -377,7 +385,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   const std::vector<R> rho_b = brick_copy(P.G, static_cast<const R*>(rho));
   std::vector<double> abs_b(P.absorbed ? (size_t)P.n_lambda * P.G.ncell_pad : 0, 0.0);
   std::vector<double> grad_b(ADJ && grad ? (size_t)P.G.ncell_pad : 0, 0.0);
-  HostLifeMem<R, RECT> M{rho_b.data(), P.G, pr, images, n_images, P.absorbed ? abs_b.data() : nullptr,
+  HostLifeMem<R, GK> M{rho_b.data(), P.G, pr, images, n_images, P.absorbed ? abs_b.data() : nullptr,
                    (long long)abs_b.size(), adj, n_adj, grad_b.data(), (long long)grad_b.size()};
   P.absorbed = M.absorbed;
   if (images && !ADJ) std::fill(images, images + n_images, 0.0);
@@ -443,7 +451,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   auto queue_phase = [&]() {
     unsigned long long deps = 0;
     const unsigned long long nx =
-        emu_peel_jobs<R, ADJ, RECT>(M, P, jobs, std::min(M.job_next, M.job_cap), grad_b, deps, cap);
+        emu_peel_jobs<R, ADJ, GK>(M, P, jobs, std::min(M.job_next, M.job_cap), grad_b, deps, cap);
     M.x_queue += nx;
     M.d_queue += deps;
   };
@@ -488,9 +496,9 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   return 0;
 }
 
-template <typename R, bool RECT>
+template <typename R, int GK>
 struct HostTraceMem {
-  static constexpr bool kRect = RECT;
+  static constexpr int kGrid = GK;
   const R* rho_;
   const TraceParams& P;
   long long cap_seg;  // entries of seg_cell / seg_len
@@ -524,7 +532,7 @@ struct HostTraceMem {
   }
 };
 
-template <typename R, bool RECT>
+template <typename R, int GK>
 int emu_trace(const mcrt_grid* grid, const void* rho, double kappa, int64_t n_rays, const double* origin,
               const double* dir, double* tau, int32_t max_seg, int32_t* seg_cell, double* seg_len, int32_t* n_seg,
               uint64_t* crossings, int brick_shape, int wave) {
@@ -546,7 +554,7 @@ int emu_trace(const mcrt_grid* grid, const void* rho, double kappa, int64_t n_ra
   P.seg_len = lists ? seg_len : nullptr;
   P.n_seg = n_seg;
   P.batch = 16;
-  HostTraceMem<R, RECT> M{rho_b.data(), P, lists ? (long long)max_seg * n_rays : 0};
+  HostTraceMem<R, GK> M{rho_b.data(), P, lists ? (long long)max_seg * n_rays : 0};
   std::vector<TraceLane<R>> lanes(wave);
   for (auto& L : lanes) trace_init(L);
   const long long cap = (long long)P.G.n[0] + P.G.n[1] + P.G.n[2] + 8;
@@ -563,9 +571,9 @@ int emu_trace(const mcrt_grid* grid, const void* rho, double kappa, int64_t n_ra
   return 0;
 }
 
-template <typename R, bool RECT>
+template <typename R, int GK>
 struct HostPeelMem {
-  static constexpr bool kRect = RECT;
+  static constexpr int kGrid = GK;
   const R* rho_;
   const PeelParams& P;
   const std::vector<DetDev>& dets;
@@ -600,7 +608,7 @@ struct HostPeelMem {
   }
 };
 
-template <typename R, bool RECT>
+template <typename R, int GK>
 int emu_peel(const mcrt_grid* grid, const void* rho, double kappa, double g, int64_t n_events, const double* pos,
              const double* dir_in, const double* w, int n_det, const mcrt_detector* detectors, double* images,
              int brick_shape, int wave) {
@@ -622,7 +630,7 @@ int emu_peel(const mcrt_grid* grid, const void* rho, double kappa, double g, int
   P.w = w;
   P.images = images;
   P.batch = 16;
-  HostPeelMem<R, RECT> M{rho_b.data(), P, det, npix};
+  HostPeelMem<R, GK> M{rho_b.data(), P, det, npix};
   std::vector<PeelLane<R>> lanes(wave);
   for (auto& L : lanes) peel_init(L);
   const long long cap = (long long)P.G.n[0] + P.G.n[1] + P.G.n[2] + 8;
@@ -633,22 +641,44 @@ int emu_peel(const mcrt_grid* grid, const void* rho, double kappa, double g, int
 }
 
 // Precision and grid kind of a call, as the library dispatches its kernels.
+inline int grid_kind(const mcrt_grid* g) {
+  return !g ? kGridRegular : (g->tree_nodes > 0 ? kGridTree : (g->planes ? kGridRect : kGridRegular));
+}
+
+template <bool ADJ, typename R, typename... A>
+int life_kind(int kind, A... args) {
+  if (kind == kGridRect) return emu_life<R, ADJ, kGridRect>(args...);
+  if (kind == kGridTree) return emu_life<R, ADJ, kGridTree>(args...);
+  return emu_life<R, ADJ, kGridRegular>(args...);
+}
+
 template <bool ADJ, typename... A>
-int life_dispatch(bool f32, bool rect, A... args) {
-  if (f32) return rect ? emu_life<float, ADJ, true>(args...) : emu_life<float, ADJ, false>(args...);
-  return rect ? emu_life<double, ADJ, true>(args...) : emu_life<double, ADJ, false>(args...);
+int life_dispatch(bool f32, int kind, A... args) {
+  return f32 ? life_kind<ADJ, float>(kind, args...) : life_kind<ADJ, double>(kind, args...);
+}
+
+template <typename R, typename... A>
+int trace_kind(int kind, A... args) {
+  if (kind == kGridRect) return emu_trace<R, kGridRect>(args...);
+  if (kind == kGridTree) return emu_trace<R, kGridTree>(args...);
+  return emu_trace<R, kGridRegular>(args...);
 }
 
 template <typename... A>
-int trace_dispatch(bool f32, bool rect, A... args) {
-  if (f32) return rect ? emu_trace<float, true>(args...) : emu_trace<float, false>(args...);
-  return rect ? emu_trace<double, true>(args...) : emu_trace<double, false>(args...);
+int trace_dispatch(bool f32, int kind, A... args) {
+  return f32 ? trace_kind<float>(kind, args...) : trace_kind<double>(kind, args...);
+}
+
+template <typename R, typename... A>
+int peel_kind(int kind, A... args) {
+  if (kind == kGridRect) return emu_peel<R, kGridRect>(args...);
+  if (kind == kGridTree) return emu_peel<R, kGridTree>(args...);
+  return emu_peel<R, kGridRegular>(args...);
 }
 
 template <typename... A>
-int peel_dispatch(bool f32, bool rect, A... args) {
-  if (f32) return rect ? emu_peel<float, true>(args...) : emu_peel<float, false>(args...);
-  return rect ? emu_peel<double, true>(args...) : emu_peel<double, false>(args...);
+int peel_dispatch(bool f32, int kind, A... args) {
+  return f32 ? peel_kind<float>(kind, args...) : peel_kind<double>(kind, args...);
 }
 
 int guard(const char* what, int (*f)(void*), void* arg) {
@@ -678,7 +708,7 @@ int emu_run_photons(const mcrt_grid* grid, const void* rho, const mcrt_optics* o
     g_violation.clear();
     host::last_error().clear();
     if (!opts) return host::fail(MCRT_EINVAL, "opts is NULL");
-    return life_dispatch<false>(opts->precision == MCRT_PREC_FP32, grid && grid->planes, grid, rho, optics, n_src,
+    return life_dispatch<false>(opts->precision == MCRT_PREC_FP32, grid_kind(grid), grid, rho, optics, n_src,
                                 sources, n_det, detectors, opts, images, n_images, absorbed, n_absorbed,
                                 (const double*)nullptr, 0ll, (double*)nullptr, 0ll, stats, wave);
   } catch (const Violation& v) {
@@ -697,7 +727,7 @@ int emu_backward_density(const mcrt_grid* grid, const void* rho, const mcrt_opti
     if (!opts) return host::fail(MCRT_EINVAL, "opts is NULL");
     mcrt_opts o = *opts;
     o.flags &= ~MCRT_ABSORB;
-    return life_dispatch<true>(o.precision == MCRT_PREC_FP32, grid && grid->planes, grid, rho, optics, n_src, sources,
+    return life_dispatch<true>(o.precision == MCRT_PREC_FP32, grid_kind(grid), grid, rho, optics, n_src, sources,
                                n_det, detectors, (const mcrt_opts*)&o, (double*)nullptr, 0ll, (double*)nullptr, 0ll,
                                adj, n_adj, grad, n_grad, stats, wave);
   } catch (const Violation& v) {
@@ -718,7 +748,7 @@ int emu_trace_path(const mcrt_grid* grid, const void* rho, double kappa, int pre
       if (crossings) *crossings = 0;
       return 0;
     }
-    return trace_dispatch(precision == MCRT_PREC_FP32, grid->planes != nullptr, grid, rho, kappa, n_rays, origin, dir,
+    return trace_dispatch(precision == MCRT_PREC_FP32, grid_kind(grid), grid, rho, kappa, n_rays, origin, dir,
                           tau, max_seg, seg_cell, seg_len, n_seg, crossings, brick_shape, wave);
   } catch (const Violation& v) {
     g_violation = std::string("trace_path: ") + v.what();
@@ -735,7 +765,7 @@ int emu_peel_off(const mcrt_grid* grid, const void* rho, double kappa, double g,
     if (int e = host::check_peel(grid, rho, kappa, g, precision, n_events, pos, w, n_det, detectors, images))
       return e;
     if (n_events == 0) return 0;
-    return peel_dispatch(precision == MCRT_PREC_FP32, grid->planes != nullptr, grid, rho, kappa, g, n_events, pos,
+    return peel_dispatch(precision == MCRT_PREC_FP32, grid_kind(grid), grid, rho, kappa, g, n_events, pos,
                          dir_in, w, n_det, detectors, images, brick_shape, wave);
   } catch (const Violation& v) {
     g_violation = std::string("peel_off: ") + v.what();

@@ -86,7 +86,8 @@ def _call_run(lib, B, prob, **over):
 
 @pytest.mark.parametrize("case", ["n_packages", "precision", "flags", "w_min", "max_scatter", "launch_blocks",
                                   "event_batch", "brick_shape", "peel_queue", "grid_cells", "grid_extent",
-                                  "planes_order", "planes_ends", "planes_nan",
+                                  "planes_order", "planes_ends", "planes_nan", "tree_unreached", "tree_twice",
+                                  "tree_split_outside", "tree_cell_twice", "tree_and_planes", "tree_leaf_count",
                                   "albedo", "g", "kappa", "lum", "n_det", "det_pixels", "det_distance",
                                   "n_src", "src_kind", "src_scale"])
 def test_invalid_arguments_are_rejected(lib, B, W, case):
@@ -123,6 +124,26 @@ def test_invalid_arguments_are_rejected(lib, B, W, case):
         else:
             pl[0][3] = np.nan
         prob["planes"] = tuple(pl)
+    elif case.startswith("tree"):
+        # x halved, then its upper half halved: 3 leaves -> cells 0, 1, 2
+        tree = {"axis": np.array([0, -1, 0, -1, -1]), "split": np.array([0.0, 0, 0.5, 0, 0]),
+                "child": np.array([1, 0, 3, 1, 2])}
+        prob["n"] = (3, 1, 1)
+        prob["rho"] = np.ones((1, 1, 3))
+        if case == "tree_unreached":
+            tree = {k: np.concatenate([v, v[-1:]]) for k, v in tree.items()}  # node 5 hangs loose
+        elif case == "tree_twice":
+            tree["child"][2] = 1  # node 2's children are nodes 1 and 2
+        elif case == "tree_split_outside":
+            tree["split"][2] = -0.5  # outside node 2, which is x in [0, 1]
+        elif case == "tree_cell_twice":
+            tree["child"][4] = 1
+        elif case == "tree_and_planes":
+            prob["planes"] = tuple(np.linspace(-1.0, 1.0, m + 1) for m in (3, 1, 1))
+        else:
+            prob["n"] = (4, 1, 1)
+            prob["rho"] = np.ones((1, 1, 4))
+        prob["tree"] = tree
     elif case == "albedo":
         prob["albedo"] = np.array([1.5])
     elif case == "g":
@@ -155,6 +176,18 @@ def test_invalid_arguments_are_rejected(lib, B, W, case):
         rc = _call_run(lib, B, prob, **over)
     assert rc == B.EINVAL, (case, rc)
     assert lib.mcrt_last_error().decode(), case
+
+
+def test_well_formed_tree_is_accepted_before_any_device_work(lib, B, W):
+    # the tree of the rejection cases, unchanged, passes the argument checks:
+    # the call then fails only on the fake device pointers' stream work, not
+    # with MCRT_EINVAL -- checked through the host-side preparation alone
+    prob = W.small_problem(n=(3, 1, 1), n_packages=10)
+    prob["rho"] = np.ones((1, 1, 3))
+    prob["tree"] = {"axis": np.array([0, -1, 0, -1, -1]), "split": np.array([0.0, 0, 0.5, 0, 0]),
+                    "child": np.array([1, 0, 3, 1, 2])}
+    g = B.make_grid(prob)
+    assert g.tree_nodes == 5
 
 
 def test_null_pointers_are_rejected(lib, B, W):
