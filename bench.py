@@ -16,10 +16,11 @@ Prints one JSON line.  `value` is packages per second of whole steps;
 events around it on the stream it runs on, recorded by the library);
 `traversal` is the walk alone (trace_path on random rays in the same grid);
 `fp64_path` times one step of the plain FP64 GPU path and compares the two
-precisions against the Monte Carlo noise; `powcub_grid` times one step of
-the same model on a PowCub grid (rectilinear, cells graded towards the
-centre); `cpu_baseline` times the FP64 CPU oracle on a bounded package
-sample of the same workload.
+precisions against the Monte Carlo noise; `powcub_grid` and `kdtree_grid`
+time one step of the same model on a PowCub grid (rectilinear, cells graded
+towards the centre) and on a k-d tree grid adapted to the dust;
+`cpu_baseline` times the FP64 CPU oracle on a bounded package sample of the
+same workload.
 
 `--collect-profiles DIR` runs this script under rocprofv3 (a kernel-trace
 summary, then FETCH_SIZE and WRITE_SIZE counter passes with a 1 GiB copy
@@ -195,21 +196,33 @@ def fp64_comparison(B, prob, step_fn, images32, grad32, dev):
             "images_mc_noise_rel_l1": 0.5 * rel_l1(ia, ib)}
 
 
-def powcub_leg(B, W, step_fn, images, grad, dev, n_pkg):
-    """One step (forward + adjoint) of the same model on a PowCub grid
-    (cells graded towards the disk centre and midplane, Table 1(d)), after
-    one untimed step: the rectilinear-grid kernels at the benchmark size."""
+def grid_leg(B, prob, target, dev, note):
+    """One step (forward + adjoint against the benchmark's target image) of
+    the same model on another grid kind, after one untimed step: the
+    rectilinear- or tree-grid kernels at the benchmark's package count."""
     import torch
-    p = W.powcub_spiral(n_packages=n_pkg, precision=1)
-    rho = B.density_tensor(p, dev)
-    step_fn(p, rho, images, grad)
+    rho = B.density_tensor(prob, dev)
+    images = torch.empty_like(target)
+    adj = torch.empty_like(target)
+    absorbed = torch.empty((1, rho.numel()), dtype=torch.float64, device=dev)
+    grad = torch.empty(rho.numel(), dtype=torch.float64, device=dev)
+
+    def step():
+        sf = B.run_photons(prob, rho, images, absorbed)
+        torch.sub(images, target, out=adj)
+        adj.mul_(2.0)
+        sb = B.backward_density(prob, rho, adj, grad)
+        return sf, sb
+
+    step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sf, sb = step_fn(p, rho, images, grad)
+    sf, sb = step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    n_pkg = prob["n_packages"]
     x = sf["x_path"] + sf["x_locate"] + sf["x_peel"] + sb["x_path"] + sb["x_locate"] + sb["x_peel"]
-    return {"workload": p["name"] + ", power-law cell widths (outermost/innermost 8, 8, 16), %d packages" % n_pkg,
+    return {"workload": "%s, %s, %d packages" % (prob["name"], note, n_pkg), "cells": int(rho.numel()),
             "packages_per_s": n_pkg / wall, "ms_per_step": wall * 1e3, "forward_ms": sf["kernel_ms"],
             "adjoint_ms": sb["kernel_ms"], "crossings_per_s": x / wall}
 
@@ -301,7 +314,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
-    ap.add_argument("--no-powcub", action="store_true", help="skip the PowCub-grid step")
+    ap.add_argument("--no-powcub", action="store_true", help="skip the PowCub- and k-d-tree-grid steps")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy first (counter scale)")
     ap.add_argument("--collect-profiles", metavar="DIR", help="run the rocprofv3 passes (raw output in DIR)")
     ap.add_argument("--summarize-profiles", metavar="DIR", help="only rewrite the summaries from the raw output in DIR")
@@ -425,7 +438,10 @@ def main():
     if not args.no_fp64:
         out["fp64_path"] = fp64_comparison(B, prob, step_fn, images, grad, dev)
     if not args.no_powcub:
-        out["powcub_grid"] = powcub_leg(B, W, step_fn, images, grad, dev, n_pkg)
+        out["powcub_grid"] = grid_leg(B, W.powcub_spiral(n_packages=n_pkg, precision=1), target, dev,
+                                      "power-law cell widths (outermost/innermost 8, 8, 16)")
+        out["kdtree_grid"] = grid_leg(B, W.kdtree_spiral(n_packages=n_pkg, precision=1), target, dev,
+                                      "leaves halved along their longest side while their dust mass exceeds 3e-4")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
