@@ -74,6 +74,7 @@ extern "C" {
 
 #define MCRT_SRC_POINT 0
 #define MCRT_SRC_EXPDISK 1
+#define MCRT_SRC_CELLS 2
 
 #define MCRT_MAX_SOURCES 8
 #define MCRT_MAX_DETECTORS 8
@@ -119,11 +120,20 @@ typedef struct {
 
 /* Source (Table 1(a)): MCRT_SRC_POINT at (x, y, z), or MCRT_SRC_EXPDISK
  * centred there with density ~ exp(-R/h_r - |z|/h_z), untruncated.
- * lum: host array [n_lambda] of luminosities >= 0. */
+ * lum: host array [n_lambda] of luminosities >= 0.
+ * MCRT_SRC_CELLS: the grid's cells emit (dust emission, Sect. 1 and 2.1):
+ * cell_lum is a device array [n_lambda][cell] of luminosities >= 0 (cell m
+ * as in mcrt_grid), for instance the output of dust_emission; a package of
+ * wavelength l starts in a cell drawn with probability proportional to
+ * cell_lum[l][m], at a uniform position inside it, in an isotropic
+ * direction; lum and (x, y, z, h_r, h_z) are ignored.  At most one cell
+ * source per call; the call then waits for the per-wavelength totals of
+ * cell_lum and fails with MCRT_EINVAL if one is negative or not finite. */
 typedef struct {
     int32_t kind;
     double x, y, z, h_r, h_z;
     const double *lum;
+    const double *cell_lum;
 } mcrt_source;
 
 /* Frame instrument (Fig. 4/5): distance > 0 (enters as 1/distance^2),
@@ -199,7 +209,8 @@ typedef struct {
  * for every wavelength and package, emission, peel-off at emission,
  * then repeated traversal with continuous absorption, forced scattering,
  * peel-off at scattering and Henyey-Greenstein redirection, until the
- * weight or scatter limit ends the package.
+ * weight or scatter limit ends the package.  At a wavelength where the
+ * sources emit nothing the packages end unborn (counted, no events).
  *  rho_dev       device densities [ncell] (double or float, see precision)
  *  images_dev    device FP64 [comp][n_lambda][frame pixels], overwritten
  *  absorbed_dev  device FP64 [n_lambda][ncell], overwritten; required with
@@ -257,13 +268,40 @@ int backward_density(const mcrt_grid *grid, const void *rho_dev, const mcrt_opti
                      const double *adj_images_dev, double *grad_rho_dev, mcrt_stats *stats_host,
                      void *hip_stream);
 
+/* Dust emission (Sect. 1: absorption and re-emission by the dust; Sect. 2.1:
+ * panchromatic simulations): the equilibrium temperature and the emission
+ * spectrum of every cell from the luminosity it absorbed.  The grains are
+ * modified black bodies: cell m of dust mass M_m = rho_m V_m (V_m its
+ * volume) at temperature T emits
+ *   E_m(T) = emissivity * M_m * sum_i kappa_abs[i] B(lambda[i], T) dlambda[i],
+ *   B(lambda, T) = lambda^-5 / (exp(c2 / (lambda T)) - 1),  c2 = 14387.77 um K,
+ * and T_m solves E_m(T_m) = L_m, L_m the cell's absorbed luminosity summed
+ * over the n_abs rows of absorbed_dev [n_abs][cell] (the absorbed tally of
+ * run_photons); T_m is that root within [1, 1e5] K, held at the nearer end
+ * when the root lies outside (L_m = 0 or M_m = 0: T_m = 0 and no emission).
+ * emission_dev [n_lambda][cell] receives
+ *   L_m * kappa_abs[i] B(lambda[i], T_m) dlambda[i]
+ *       / sum_j kappa_abs[j] B(lambda[j], T_m) dlambda[j],
+ * so every cell re-emits exactly what it absorbed (nothing where that sum
+ * underflows to 0).  lambda (um), dlambda
+ * (bin widths, um), kappa_abs (absorption opacity per unit density): host
+ * arrays [n_lambda], > 0; emissivity > 0 sets the temperature scale only.
+ * rho_dev: densities [cell] (double, or float with MCRT_PREC_FP32);
+ * temperature_dev [cell] may be NULL.  Cells are numbered as in
+ * mcrt_grid.  Device arrays belong to the caller; the call runs on
+ * hip_stream without waiting.  Returns 0, MCRT_EINVAL (with a message)
+ * for invalid arguments before any device work, or MCRT_EHIP. */
+int dust_emission(const mcrt_grid *grid, const void *rho_dev, int precision, int n_abs, const double *absorbed_dev,
+                  int n_lambda, const double *lambda, const double *dlambda, const double *kappa_abs,
+                  double emissivity, double *temperature_dev, double *emission_dev, void *hip_stream);
+
 /* Message for the last nonzero return on the calling thread ("" if none). */
 const char *mcrt_last_error(void);
 
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 9
+#define MCRT_ABI_VERSION 10
 
 #ifdef __cplusplus
 }

@@ -483,7 +483,7 @@ void oracle_rotate(const double k[3], double mu, double psi, double out[3])
  * follows a Laplace law with scale h_z.  Check: moments E[R] = 2 h_R,
  * E[|z|] = h_z, and the dust-free face-on image of the disk. */
 
-enum { SRC_POINT = 0, SRC_EXPDISK = 1 };
+enum { SRC_POINT = 0, SRC_EXPDISK = 1, SRC_CELLS = 2 };
 
 typedef struct {
     int kind;
@@ -516,6 +516,47 @@ void oracle_emit_direction(const double u[4], double k[3])
     k[2] = mu;
 }
 
+/* Box of cell c: along each axis between consecutive planes (regular and
+ * rectilinear grids, c = i + nx (j + ny k)), or the leaf's box (tree grids). */
+static void cell_bounds(const grid_t *G, int64_t c, double lo[3], double hi[3])
+{
+    if (G->tree) {
+        for (int a = 0; a < 3; a++) {
+            lo[a] = G->leaf_lo[3 * c + a];
+            hi[a] = G->leaf_hi[3 * c + a];
+        }
+        return;
+    }
+    int64_t i[3] = {c % G->n[0], (c / G->n[0]) % G->n[1], c / ((int64_t)G->n[0] * G->n[1])};
+    for (int a = 0; a < 3; a++) {
+        lo[a] = plane_at(G, a, (int)i[a]);
+        hi[a] = plane_at(G, a, (int)i[a] + 1);
+    }
+}
+
+/* Emission point of a cell source (the grid's cells emit: dust emission,
+ * Sect. 1 and 2.1).  cum[0..ncell] are the exclusive prefix sums of the
+ * cells' luminosities at this wavelength; the cell is the last c with
+ * cum[c] <= u0 cum[ncell], so it is drawn with probability proportional to
+ * its luminosity (and never with zero luminosity); the point is
+ * lo + u (hi - lo) in its box from u1, u2, u3.  Check: the cell counts and
+ * the positions inside a cell against their laws, with no dust on the way. */
+static void cell_emit_position(const grid_t *G, const double *cum, const double u[4], double r[3])
+{
+    double target = u[0] * cum[G->ncell];
+    int64_t lo = 0, hi = G->ncell - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) / 2;
+        if (cum[mid] <= target)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    double bl[3], bh[3];
+    cell_bounds(G, lo, bl, bh);
+    for (int a = 0; a < 3; a++) r[a] = bl[a] + u[1 + a] * (bh[a] - bl[a]);
+}
+
 /* Forced scattering (Sect. 1, Cashwell & Everett 1959): the optical depth of
  * the interaction point is drawn from exp(-tau) truncated to [0, T]:
  * tau_s = -ln(1 - u (1 - e^-T)).  Check: the histogram against the
@@ -540,7 +581,10 @@ typedef struct {
     const double *kappa, *albedo, *g;
     int n_src;
     src_t src[MAX_SRC];
-    const double *lum; /* [n_src][n_lambda] */
+    const double *lum; /* [n_src][n_lambda]; a cell source's row holds its per-wavelength totals */
+    double *lum_own;   /* the copy of the source luminosities that lum points to */
+    int cell_src;      /* index of the cell source, -1 if none */
+    double *cell_cum;  /* cell source: [n_lambda][ncell + 1] exclusive prefix sums of its luminosities */
     int n_det;
     det_t det[MAX_DET];
     size_t pix_lambda; /* pixels of all frames for one wavelength */
@@ -700,6 +744,10 @@ static void run_package(const problem_t *P, accum_t *A, uint64_t p, int l)
     double ltot = 0.0;
     for (int s = 0; s < P->n_src; s++) ltot += P->lum[(size_t)s * P->n_lambda + l];
     const double w0 = ltot / (double)P->n_pkg;
+    if (ltot == 0.0) { /* nothing is emitted at this wavelength: no package is launched */
+        A->stats[ST_PACKAGES] += 1.0;
+        return;
+    }
 
     /* 1. emission */
     double r[3], k[3];
@@ -720,7 +768,10 @@ static void run_package(const problem_t *P, accum_t *A, uint64_t p, int l)
     {
         const src_t *S = &P->src[sidx];
         double par[5] = {S->c[0], S->c[1], S->c[2], S->hr, S->hz};
-        oracle_emit_position(S->kind, par, u, r);
+        if (S->kind == SRC_CELLS)
+            cell_emit_position(G, P->cell_cum + (size_t)l * (G->ncell + 1), u, r);
+        else
+            oracle_emit_position(S->kind, par, u, r);
     }
     double w = w0, w_eval = w0;
     A->stats[ST_EMITTED] += w0;
@@ -843,7 +894,8 @@ static int setup_problem(problem_t *P, const double box[6], const int n[3], cons
                          const double *kappa, const double *albedo, const double *g, int n_src, const int *src_kind,
                          const double *src_par, const double *src_lum, int n_det, const double *det_par,
                          const int *det_pix, uint64_t n_pkg, uint64_t first, uint64_t seed, double w_min,
-                         int max_scatter, unsigned flags, const double *planes, const double *tree)
+                         int max_scatter, unsigned flags, const double *planes, const double *tree,
+                         const double *cell_lum)
 {
     if (n_src < 1 || n_src > MAX_SRC || n_det < 0 || n_det > MAX_DET || n_lambda < 1 || n_pkg < 1) return -1;
     for (int a = 0; a < 3; a++)
@@ -856,13 +908,37 @@ static int setup_problem(problem_t *P, const double box[6], const int n[3], cons
     P->albedo = albedo;
     P->g = g;
     P->n_src = n_src;
+    P->cell_src = -1;
     for (int s = 0; s < n_src; s++) {
         P->src[s].kind = src_kind[s];
         for (int a = 0; a < 3; a++) P->src[s].c[a] = src_par[5 * s + a];
         P->src[s].hr = src_par[5 * s + 3];
         P->src[s].hz = src_par[5 * s + 4];
+        if (src_kind[s] == SRC_CELLS) {
+            if (P->cell_src >= 0 || !cell_lum) {
+                grid_free(&P->G);
+                return -1;
+            }
+            P->cell_src = s;
+        }
     }
-    P->lum = src_lum;
+    /* a cell source's luminosity at each wavelength is the sum over its cells */
+    P->lum_own = (double *)malloc(sizeof(double) * (size_t)n_src * n_lambda);
+    memcpy(P->lum_own, src_lum, sizeof(double) * (size_t)n_src * n_lambda);
+    if (P->cell_src >= 0) {
+        int64_t nc = P->G.ncell;
+        P->cell_cum = (double *)malloc(sizeof(double) * (size_t)n_lambda * (nc + 1));
+        for (int l = 0; l < n_lambda; l++) {
+            double *cum = P->cell_cum + (size_t)l * (nc + 1), acc = 0.0;
+            for (int64_t m = 0; m < nc; m++) {
+                cum[m] = acc;
+                acc += cell_lum[(size_t)l * nc + m];
+            }
+            cum[nc] = acc;
+            P->lum_own[(size_t)P->cell_src * n_lambda + l] = acc;
+        }
+    }
+    P->lum = P->lum_own;
     P->n_det = n_det;
     size_t off = 0;
     for (int d = 0; d < n_det; d++) {
@@ -878,6 +954,14 @@ static int setup_problem(problem_t *P, const double box[6], const int n[3], cons
     P->max_scatter = max_scatter;
     P->flags = flags;
     return 0;
+}
+
+static void problem_free(problem_t *P)
+{
+    free(P->lum_own);
+    free(P->cell_cum);
+    P->lum_own = P->cell_cum = NULL;
+    grid_free(&P->G);
 }
 
 /* Runs packages [first, first + n_pkg) for every wavelength.  Each thread
@@ -947,15 +1031,16 @@ int oracle_run(const double box[6], const int n[3], const double *rho, int n_lam
                const double *albedo, const double *g, int n_src, const int *src_kind, const double *src_par,
                const double *src_lum, int n_det, const double *det_par, const int *det_pix, uint64_t n_pkg,
                uint64_t first, uint64_t seed, double w_min, int max_scatter, unsigned flags, double *images,
-               double *absorbed, double *stats, int n_threads, const double *planes, const double *tree)
+               double *absorbed, double *stats, int n_threads, const double *planes, const double *tree,
+               const double *cell_lum)
 {
     problem_t P;
     if (setup_problem(&P, box, n, rho, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
-                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes, tree))
+                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes, tree, cell_lum))
         return -1;
     P.mode = MODE_FORWARD;
     int rc = simulate(&P, images, (flags & FLAG_ABSORB) ? absorbed : NULL, NULL, stats, n_threads);
-    grid_free(&P.G);
+    problem_free(&P);
     return rc;
 }
 
@@ -967,16 +1052,16 @@ int oracle_grad(const double box[6], const int n[3], const double *rho, int n_la
                 const double *src_lum, int n_det, const double *det_par, const int *det_pix, uint64_t n_pkg,
                 uint64_t first, uint64_t seed, double w_min, int max_scatter, unsigned flags, const double *adj,
                 double *images, double *grad, double *stats, int n_threads, const double *planes,
-                const double *tree)
+                const double *tree, const double *cell_lum)
 {
     problem_t P;
     if (setup_problem(&P, box, n, rho, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
-                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes, tree))
+                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes, tree, cell_lum))
         return -1;
     P.mode = MODE_GRAD;
     P.adj = adj;
     int rc = simulate(&P, images, NULL, grad, stats, n_threads);
-    grid_free(&P.G);
+    problem_free(&P);
     return rc;
 }
 
@@ -988,16 +1073,16 @@ int oracle_reweight(const double box[6], const int n[3], const double *rho0, con
                     const double *src_par, const double *src_lum, int n_det, const double *det_par,
                     const int *det_pix, uint64_t n_pkg, uint64_t first, uint64_t seed, double w_min,
                     int max_scatter, unsigned flags, double *images, double *stats, int n_threads,
-                    const double *planes, const double *tree)
+                    const double *planes, const double *tree, const double *cell_lum)
 {
     problem_t P;
     if (setup_problem(&P, box, n, rho0, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
-                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes, tree))
+                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes, tree, cell_lum))
         return -1;
     P.mode = MODE_REWEIGHT;
     P.rho_eval = rho;
     int rc = simulate(&P, images, NULL, NULL, stats, n_threads);
-    grid_free(&P.G);
+    problem_free(&P);
     return rc;
 }
 
@@ -1093,4 +1178,72 @@ void oracle_draw_words(uint64_t seed, uint64_t p0, int64_t n, uint32_t l, uint32
         uint32_t ctr[4] = {(uint32_t)p, (uint32_t)(p >> 32), l, c};
         oracle_philox(ctr, key, out + 4 * q);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dust emission (Sect. 1: the dust absorbs and re-emits; Sect. 2.1:
+ * panchromatic simulations).  Reading: the grains are modified black bodies
+ * in radiative equilibrium.  A cell of dust mass M = rho V at temperature T
+ * emits emissivity * M * sum_i kappa_abs_i B(lambda_i, T) dlambda_i with
+ * B(lambda, T) = lambda^-5 / (exp(c2 / (lambda T)) - 1), c2 = hc/k =
+ * 14387.77 um K (lambda in um), and its temperature is the one at which it
+ * emits what it absorbed.  Checks: the closed form for one wavelength, the
+ * Stefan-Boltzmann-type integrals of grey and lambda^-2 dust, Wien's
+ * displacement law, and energy conservation per cell. */
+
+#define OR_C2 14387.77
+
+double oracle_mbb_sum(int nl, const double *lambda, const double *dlambda, const double *kabs, double T)
+{
+    double s = 0.0;
+    for (int i = 0; i < nl; i++) {
+        double l = lambda[i];
+        s += kabs[i] * dlambda[i] / (l * l * l * l * l * expm1(OR_C2 / (l * T)));
+    }
+    return s;
+}
+
+/* Per cell: L = the cell's absorbed luminosity (sum of the n_abs rows),
+ * M = rho V.  L <= 0 or M <= 0: T = 0 and no emission.  Else T solves
+ * mbb_sum(T) = L / (emissivity M), by bisection in ln T over [ln 1, ln 1e5]
+ * until no double lies strictly between the ends (a root outside the range
+ * ends at its nearer end), and the cell emits L kappa_abs_i B(lambda_i, T)
+ * dlambda_i / mbb_sum(T) at wavelength i (nothing if that sum is 0). */
+int oracle_dust_emission(const double box[6], const int n[3], const double *planes, const double *tree,
+                         const double *rho, int n_abs, const double *absorbed, int nl, const double *lambda,
+                         const double *dlambda, const double *kabs, double emissivity, double *T_out,
+                         double *emission)
+{
+    grid_t G;
+    if (n_abs < 1 || nl < 1 || !(emissivity > 0.0)) return -1;
+    if (grid_init(&G, box, n, planes, tree)) return -1;
+    for (int64_t m = 0; m < G.ncell; m++) {
+        double L = 0.0;
+        for (int r = 0; r < n_abs; r++) L += absorbed[(size_t)r * G.ncell + m];
+        double lo[3], hi[3];
+        cell_bounds(&G, m, lo, hi);
+        double M = rho[m] * (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+        double T = 0.0, S = 0.0;
+        if (L > 0.0 && M > 0.0) {
+            double y = L / (emissivity * M), a = 0.0, b = log(1e5);
+            for (;;) {
+                double mid = 0.5 * (a + b);
+                if (!(mid > a && mid < b)) break;
+                if (oracle_mbb_sum(nl, lambda, dlambda, kabs, exp(mid)) < y)
+                    a = mid;
+                else
+                    b = mid;
+            }
+            T = exp(a);
+            S = oracle_mbb_sum(nl, lambda, dlambda, kabs, T);
+        }
+        T_out[m] = T;
+        for (int i = 0; i < nl; i++) {
+            double l = lambda[i];
+            emission[(size_t)i * G.ncell + m] =
+                S > 0.0 ? L * (kabs[i] * dlambda[i] / (l * l * l * l * l * expm1(OR_C2 / (l * T)))) / S : 0.0;
+        }
+    }
+    grid_free(&G);
+    return 0;
 }

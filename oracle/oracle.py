@@ -7,7 +7,8 @@ A problem is a plain dict:
   tree        optional tree grid {axis, split, child} per node (n = (cells, 1, 1))
   rho         density, nz*ny*nx values, x fastest
   kappa, albedo, g         one value per wavelength
-  sources     list of {kind: "point"|"expdisk", pos: (x, y, z), h_r, h_z, lum: [n_lambda]}
+  sources     list of {kind: "point"|"expdisk", pos: (x, y, z), h_r, h_z, lum: [n_lambda]}, or
+              {kind: "cells", cell_lum: [n_lambda][ncell]} (the grid's cells emit; at most one)
   detectors   list of {distance, incl, azim, pa (degrees), nx, ny, half_x, half_y}
   n_packages, first_package, seed, w_min, max_scatter, flags
 
@@ -50,18 +51,22 @@ def _load():
         _lib.oracle_emit_direction.argtypes = [P, P]
         _lib.oracle_detector_basis.argtypes = [P, P]
         common = [P, P, P, i, P, P, P, i, P, P, P, i, P, P, u64, u64, u64, d, i, C.c_uint]
-        _lib.oracle_run.argtypes = common + [P, P, P, i, P, P]
+        _lib.oracle_run.argtypes = common + [P, P, P, i, P, P, P]
         _lib.oracle_run.restype = i
-        _lib.oracle_grad.argtypes = common + [P, P, P, P, i, P, P]
+        _lib.oracle_grad.argtypes = common + [P, P, P, P, i, P, P, P]
         _lib.oracle_grad.restype = i
         _lib.oracle_reweight.argtypes = [P, P, P, P, i, P, P, P, i, P, P, P, i, P, P, u64, u64, u64, d, i,
-                                         C.c_uint, P, P, i, P, P]
+                                         C.c_uint, P, P, i, P, P, P]
         _lib.oracle_reweight.restype = i
         _lib.oracle_trace.argtypes = [P, P, P, d, i64, P, P, P, i, P, P, P, P, P]
         _lib.oracle_trace.restype = i64
         _lib.oracle_peel.argtypes = [P, P, P, d, d, i64, P, P, P, i, P, P, P, P, P]
         _lib.oracle_peel.restype = i
         _lib.oracle_draw_words.argtypes = [u64, u64, i64, u32, u32, P]
+        _lib.oracle_dust_emission.argtypes = [P, P, P, P, P, i, P, i, P, P, P, d, P, P]
+        _lib.oracle_dust_emission.restype = i
+        _lib.oracle_mbb_sum.argtypes = [i, P, P, P, d]
+        _lib.oracle_mbb_sum.restype = d
     return _lib
 
 
@@ -166,8 +171,15 @@ def _marshal(prob):
     kappa, albedo, g = _f64(prob["kappa"]), _f64(prob["albedo"]), _f64(prob["g"])
     nl = kappa.size
     srcs = prob["sources"]
-    kind = _i32([0 if s["kind"] == "point" else 1 for s in srcs])
-    spar = _f64([[s["pos"][0], s["pos"][1], s["pos"][2], s.get("h_r", 0.0), s.get("h_z", 0.0)] for s in srcs])
+    kind = _i32([{"point": 0, "expdisk": 1, "cells": 2}[s["kind"]] for s in srcs])
+    spar = _f64([list(s.get("pos", (0.0, 0.0, 0.0))) + [s.get("h_r", 0.0), s.get("h_z", 0.0)] for s in srcs])
+    cells = [s for s in srcs if s["kind"] == "cells"]
+    cell_lum = None
+    if cells:
+        c = cells[0]["cell_lum"]
+        c = c if isinstance(c, np.ndarray) else np.asarray(c.detach().cpu().numpy() if hasattr(c, "detach") else c)
+        cell_lum = _f64(c).reshape(-1)
+        assert cell_lum.size == nl * rho.size
     slum = _f64([np.broadcast_to(np.asarray(s["lum"], dtype=np.float64), (nl,)) for s in srcs])
     dets = prob["detectors"]
     dpar = _f64([[d["distance"], d["incl"], d["azim"], d.get("pa", 0.0), d["half_x"], d["half_y"]] for d in dets]
@@ -176,7 +188,7 @@ def _marshal(prob):
     npix = int(sum(d["nx"] * d["ny"] for d in dets))
     planes = _planes(prob.get("planes"), n)
     tree = _tree(prob.get("tree"))
-    keep = (box, n, rho, kappa, albedo, g, kind, spar, slum, dpar, dpix, planes, tree)
+    keep = (box, n, rho, kappa, albedo, g, kind, spar, slum, dpar, dpix, planes, tree, cell_lum)
     args = [_ptr(box), _ptr(n), _ptr(rho), nl, _ptr(kappa), _ptr(albedo), _ptr(g), len(srcs), _ptr(kind),
             _ptr(spar), _ptr(slum), len(dets), _ptr(dpar), _ptr(dpix), int(prob["n_packages"]),
             int(prob.get("first_package", 0)), int(prob.get("seed", 4357)), float(prob.get("w_min", 1e-4)),
@@ -196,7 +208,7 @@ def run(prob, threads=1):
     absorbed = np.zeros((nl, ncell)) if int(prob.get("flags", 7)) & FLAG_ABSORB else None
     stats = np.zeros(len(STAT_NAMES))
     rc = _load().oracle_run(*args, _ptr(images), _ptr(absorbed), _ptr(stats), int(threads), _ptr(keep[11]),
-                            _ptr(keep[12]))
+                            _ptr(keep[12]), _ptr(keep[13]))
     if rc != 0:
         raise ValueError("oracle_run rejected its arguments")
     return images, absorbed, dict(zip(STAT_NAMES, stats.tolist()))
@@ -211,7 +223,7 @@ def grad(prob, adj, threads=1):
     g = np.zeros(ncell)
     stats = np.zeros(len(STAT_NAMES))
     rc = _load().oracle_grad(*args, _ptr(adj), _ptr(images), _ptr(g), _ptr(stats), int(threads), _ptr(keep[11]),
-                            _ptr(keep[12]))
+                            _ptr(keep[12]), _ptr(keep[13]))
     if rc != 0:
         raise ValueError("oracle_grad rejected its arguments")
     return g, images, dict(zip(STAT_NAMES, stats.tolist()))
@@ -226,7 +238,7 @@ def reweight(prob, rho_eval, threads=1):
     stats = np.zeros(len(STAT_NAMES))
     a = args[:3] + [_ptr(rho_eval)] + args[3:]
     rc = _load().oracle_reweight(*a, _ptr(images), _ptr(stats), int(threads), _ptr(keep[11]),
-                            _ptr(keep[12]))
+                            _ptr(keep[12]), _ptr(keep[13]))
     if rc != 0:
         raise ValueError("oracle_reweight rejected its arguments")
     return images, dict(zip(STAT_NAMES, stats.tolist()))
@@ -266,6 +278,30 @@ def peel(box, n, rho, kappa, g, pos, dir_in, w, detectors, planes=None, tree=Non
     if rc != 0:
         raise ValueError("oracle_peel rejected its arguments")
     return images
+
+
+def dust_emission(box, n, rho, absorbed, lam, dlam, kappa_abs, emissivity, planes=None, tree=None):
+    """Equilibrium temperature [ncell] and emission spectrum [n_lambda][ncell]
+    of every cell from its absorbed luminosity (absorbed: [n_abs][ncell],
+    rows summed)."""
+    box, n, rho = _f64(box), _i32(n), _f64(rho).reshape(-1)
+    pl, tr = _planes(planes, n), _tree(tree)
+    absorbed = _f64(absorbed).reshape(-1, rho.size)
+    lam, dlam, ka = _f64(np.atleast_1d(lam)), _f64(np.atleast_1d(dlam)), _f64(np.atleast_1d(kappa_abs))
+    T = np.zeros(rho.size)
+    em = np.zeros((lam.size, rho.size))
+    rc = _load().oracle_dust_emission(_ptr(box), _ptr(n), _ptr(pl), _ptr(tr), _ptr(rho), absorbed.shape[0],
+                                      _ptr(absorbed), lam.size, _ptr(lam), _ptr(dlam), _ptr(ka), float(emissivity),
+                                      _ptr(T), _ptr(em))
+    if rc != 0:
+        raise ValueError("oracle_dust_emission rejected its arguments")
+    return T, em
+
+
+def mbb_sum(lam, dlam, kappa_abs, T):
+    """sum_i kappa_abs_i B(lambda_i, T) dlambda_i, B = lambda^-5 / (exp(c2 / (lambda T)) - 1)."""
+    lam, dlam, ka = _f64(np.atleast_1d(lam)), _f64(np.atleast_1d(dlam)), _f64(np.atleast_1d(kappa_abs))
+    return _load().oracle_mbb_sum(lam.size, _ptr(lam), _ptr(dlam), _ptr(ka), float(T))
 
 
 def lib_path():

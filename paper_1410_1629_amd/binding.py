@@ -42,7 +42,8 @@ class Optics(C.Structure):
 
 class Source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("x", C.c_double), ("y", C.c_double), ("z", C.c_double),
-                ("h_r", C.c_double), ("h_z", C.c_double), ("lum", C.POINTER(C.c_double))]
+                ("h_r", C.c_double), ("h_z", C.c_double), ("lum", C.POINTER(C.c_double)),
+                ("cell_lum", C.c_void_p)]
 
 
 class Detector(C.Structure):
@@ -78,8 +79,9 @@ class Stats(C.Structure):
 _lib = None
 
 # Exported symbols of include/mcrt.h.
-ABI_VERSION = 9  # MCRT_ABI_VERSION of the header these structs follow
-SYMBOLS = ("run_photons", "trace_path", "peel_off", "backward_density", "mcrt_last_error", "mcrt_abi_version")
+ABI_VERSION = 10  # MCRT_ABI_VERSION of the header these structs follow
+SYMBOLS = ("run_photons", "trace_path", "peel_off", "backward_density", "dust_emission", "mcrt_last_error",
+           "mcrt_abi_version")
 
 
 def load():
@@ -103,6 +105,9 @@ def load():
     lib.trace_path.restype = C.c_int
     lib.peel_off.argtypes = [C.POINTER(Grid), P, d, d, C.c_int, i64, P, P, P, C.c_int, C.POINTER(Detector), P, P]
     lib.peel_off.restype = C.c_int
+    lib.dust_emission.argtypes = [C.POINTER(Grid), P, C.c_int, C.c_int, P, C.c_int, C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double), d, P, P, P]
+    lib.dust_emission.restype = C.c_int
     lib.mcrt_last_error.argtypes = []
     lib.mcrt_last_error.restype = C.c_char_p
     lib.mcrt_abi_version.argtypes = []
@@ -168,10 +173,39 @@ def make_detectors(dets):
     return arr
 
 
-class _Problem:
-    """C views of a problem dict; keeps the host arrays alive."""
+SOURCE_KINDS = {"point": 0, "expdisk": 1, "cells": 2}
 
-    def __init__(self, prob, **overrides):
+
+def n_cells(prob):
+    """Cells of the problem's grid (a tree grid's problem has n = (cells, 1, 1))."""
+    return int(np.prod(prob["n"]))
+
+
+def _cell_lum(src, nl, ncell, on_device):
+    """The cell source's luminosities [n_lambda][ncell] FP64 as the call
+    takes them: a device tensor (library) or a host array (CPU harness)."""
+    a = src["cell_lum"]
+    if on_device:
+        import torch
+        t = a if isinstance(a, torch.Tensor) else torch.as_tensor(np.asarray(a, dtype=np.float64))
+        t = t.to(device="cuda", dtype=torch.float64).contiguous()
+        if t.numel() != nl * ncell:
+            raise ValueError("cell_lum has %d values, expected n_lambda x cells = %d" % (t.numel(), nl * ncell))
+        return t, C.c_void_p(t.data_ptr())
+    if not isinstance(a, np.ndarray):
+        a = a.detach().cpu().numpy()
+    h = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+    if h.size != nl * ncell:
+        raise ValueError("cell_lum has %d values, expected n_lambda x cells = %d" % (h.size, nl * ncell))
+    return h, h.ctypes.data_as(C.c_void_p)
+
+
+class _Problem:
+    """C views of a problem dict; keeps the host arrays alive.  A cell
+    source's luminosities go to the device unless cells_on_device is False
+    (the CPU harness)."""
+
+    def __init__(self, prob, cells_on_device=True, **overrides):
         self.grid = make_grid(prob)
         self.kappa = np.ascontiguousarray(prob["kappa"], dtype=np.float64)
         self.albedo = np.ascontiguousarray(prob["albedo"], dtype=np.float64)
@@ -183,9 +217,15 @@ class _Problem:
         self.lums = [np.ascontiguousarray(np.broadcast_to(np.asarray(s["lum"], dtype=np.float64),
                                                           (self.kappa.size,))) for s in srcs]
         self.sources = (Source * len(srcs))()
+        self.keep = []
         for i, s in enumerate(srcs):
-            self.sources[i] = Source(0 if s["kind"] == "point" else 1, s["pos"][0], s["pos"][1], s["pos"][2],
-                                     s.get("h_r", 0.0), s.get("h_z", 0.0), self.lums[i].ctypes.data_as(dp))
+            cell = None
+            if s["kind"] == "cells":
+                arr, cell = _cell_lum(s, self.kappa.size, n_cells(prob), cells_on_device)
+                self.keep.append(arr)
+            pos = s.get("pos", (0.0, 0.0, 0.0))
+            self.sources[i] = Source(SOURCE_KINDS[s["kind"]], pos[0], pos[1], pos[2], s.get("h_r", 0.0),
+                                     s.get("h_z", 0.0), self.lums[i].ctypes.data_as(dp), cell)
         self.n_src = len(srcs)
         self.detectors = make_detectors(prob["detectors"])
         self.n_det = len(prob["detectors"])
@@ -273,3 +313,20 @@ def render(prob, device="cuda", rho=None, **overrides):
         absorbed = torch.empty((len(np.atleast_1d(prob["kappa"])), rho.numel()), dtype=torch.float64, device=device)
     st = run_photons(prob, rho, images, absorbed, **overrides)
     return images, absorbed, st
+
+
+def dust_emission(grid, rho, precision, absorbed, lam, dlam, kappa_abs, emissivity, emission, temperature=None,
+                  stream=None):
+    """dust_emission: per cell the equilibrium temperature (device FP64
+    [ncell], optional) and the emission spectrum (device FP64 [n_lambda]
+    [ncell]) of the luminosity in absorbed (device FP64 [n_abs][ncell]);
+    lam, dlam, kappa_abs: host arrays [n_lambda].  `grid` is a problem dict
+    or a Grid."""
+    lib = load()
+    g = grid if isinstance(grid, Grid) else make_grid(grid)
+    lam, dlam, ka = (np.ascontiguousarray(np.atleast_1d(v), dtype=np.float64) for v in (lam, dlam, kappa_abs))
+    dp = C.POINTER(C.c_double)
+    n_abs = int(absorbed.shape[0]) if absorbed is not None and absorbed.dim() == 2 else 1
+    _check(lib.dust_emission(C.byref(g), _ptr(rho), int(precision), n_abs, _ptr(absorbed), lam.size,
+                             lam.ctypes.data_as(dp), dlam.ctypes.data_as(dp), ka.ctypes.data_as(dp),
+                             float(emissivity), _ptr(temperature), _ptr(emission), _stream(stream)))

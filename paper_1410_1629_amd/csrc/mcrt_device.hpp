@@ -190,8 +190,11 @@ MCRT_HD unsigned tile_sub(const DetDev& D, int pix) {
 }
 
 struct SrcDev {
-  int kind;  // 0 point, 1 exponential disk
+  int kind;  // 0 point, 1 exponential disk, 2 the grid's cells
   double c[3], hr, hz;
+  // cells: per wavelength the exclusive prefix sums of the cells'
+  // luminosities, ncell + 1 entries (the last one the total)
+  const double* cum;
 };
 
 struct LamDev {
@@ -298,6 +301,161 @@ MCRT_HD void source_position(const SrcDev& S, const U4& w, double r[3]) {
     r[1] += R * sp;
     r[2] += z;
   }
+}
+
+// Box of cell m (m = i + nx (j + ny k) on regular and rectilinear grids, the
+// leaf's cell on tree grids).
+template <int GK>
+MCRT_HD void cell_box(const GridDev& G, int m, double lo[3], double hi[3]) {
+  if constexpr (GK == kGridTree) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = G.leaf_box[6 * (long long)m + a];
+      hi[a] = G.leaf_box[6 * (long long)m + 3 + a];
+    }
+  } else {
+    const int i[3] = {m % G.n[0], (m / G.n[0]) % G.n[1], m / G.n[0] / G.n[1]};
+    for (int a = 0; a < 3; ++a) {
+      if constexpr (GK == kGridRect) {
+        lo[a] = G.pa[a][i[a]];
+        hi[a] = G.pa[a][i[a] + 1];
+      } else {
+        lo[a] = G.lo[a] + (double)i[a] * G.d[a];
+        hi[a] = G.lo[a] + (double)(i[a] + 1) * G.d[a];
+      }
+    }
+  }
+}
+
+// Emission point of the cell source at wavelength l: the cell c with
+// cum[c] <= u0 * total < cum[c + 1] (binary search; cells of zero luminosity
+// are never drawn), then the point lo + u (hi - lo) of its box.
+template <int GK>
+MCRT_HD void cell_source_position(const SrcDev& S, const GridDev& G, int l, const U4& w, double r[3]) {
+  const double* cum = S.cum + (long long)l * (G.ncell + 1);
+  const double target = u01(w.x) * cum[G.ncell];
+  int lo = 0, hi = G.ncell - 1;  // the last c with cum[c] <= target
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cum[mid] <= target)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  double bl[3], bh[3];
+  cell_box<GK>(G, lo, bl, bh);
+  const double u[3] = {u01(w.y), u01(w.z), u01(w.w)};
+  for (int a = 0; a < 3; ++a) r[a] = bl[a] + u[a] * (bh[a] - bl[a]);
+}
+
+// ---------------------------------------------------------------------------
+// Dust emission: grains as modified black bodies in radiative equilibrium.
+// With a_i = kappa_abs_i dlambda_i lambda_i^-5 and b_i = c2 / lambda_i (c2
+// the second radiation constant in um K), a cell of mass M at temperature T
+// emits emissivity * M * P(T), P(T) = sum_i a_i / (exp(b_i / T) - 1); P
+// rises strictly with T.  The temperature solves P(T) = y, y = L /
+// (emissivity M), on [kDustTmin, kDustTmax]: Newton's method on
+// ln P(e^x) = ln y, x = ln T, kept inside a bracket taken from a table of
+// ln P at kDustTable + 1 equally spaced x (a step that leaves the bracket
+// bisects it instead).
+
+constexpr double kC2 = 14387.77;
+constexpr double kDustTmin = 1.0, kDustTmax = 1e5;
+constexpr int kDustTable = 512;
+
+struct DustDev {
+  int nl;
+  const double* a;    // [nl]
+  const double* b;    // [nl]
+  const double* lnP;  // [kDustTable + 1]: ln P(exp(k h)), h = ln(kDustTmax) / kDustTable
+};
+
+MCRT_HD double dust_step() { return log(kDustTmax) / kDustTable; }
+
+// P(T) and dP/dlnT.
+MCRT_HD void dust_sum(const DustDev& D, double T, double& P, double& dP) {
+  P = 0.0;
+  dP = 0.0;
+  for (int i = 0; i < D.nl; ++i) {
+    const double u = D.b[i] / T, em = expm1(u), t = D.a[i] / em;
+    P += t;
+    dP += t * u * (1.0 + 1.0 / em);
+  }
+}
+
+// Equilibrium temperature for y > 0 (kDustTmin or kDustTmax where the root
+// lies outside).
+MCRT_HD double dust_temperature(const DustDev& D, double y) {
+  const double ly = log(y), h = dust_step();
+  if (!(ly > D.lnP[0])) return kDustTmin;
+  if (!(ly < D.lnP[kDustTable])) return kDustTmax;
+  int k = 0, hi_k = kDustTable - 1;  // the last k with lnP[k] < ly
+  while (k < hi_k) {
+    const int mid = (k + hi_k + 1) >> 1;
+    if (D.lnP[mid] < ly)
+      k = mid;
+    else
+      hi_k = mid - 1;
+  }
+  double lo = k * h, hi = (k + 1) * h;
+  const double p0 = D.lnP[k], p1 = D.lnP[k + 1];
+  double x = std::isfinite(p0) ? lo + (ly - p0) / (p1 - p0) * h : 0.5 * (lo + hi);
+  if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+  for (int it = 0; it < 64; ++it) {
+    double P, dP;
+    dust_sum(D, exp(x), P, dP);
+    const double f = log(P) - ly;
+    if (f == 0.0) break;
+    if (f < 0.0)
+      lo = x;
+    else
+      hi = x;
+    double xn = x - f * P / dP;
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    const bool last = fabs(xn - x) <= 1e-15 * (1.0 + x) || hi - lo <= 1e-15 * (1.0 + hi);
+    x = xn;
+    if (last) break;
+  }
+  return exp(x);
+}
+
+MCRT_HD double dust_table_entry(const DustDev& D, int k) {
+  double P, dP;
+  dust_sum(D, exp(k * dust_step()), P, dP);
+  return log(P);
+}
+
+struct DustParams {
+  GridDev G;
+  DustDev D;
+  const void* rho;         // [ncell], R
+  const double* absorbed;  // [n_abs][ncell]
+  int n_abs;
+  double emissivity;
+  double* temperature;  // [ncell] or null
+  double* emission;     // [nl][ncell]
+};
+
+// Cell m (row-major, as the caller's arrays): L = its absorbed luminosity,
+// M = rho V; T solves emissivity M P(T) = L (T = 0 and no emission if L or
+// M is 0), and wavelength i receives L a_i / (exp(b_i / T) - 1) / P(T).
+template <typename R, int GK>
+MCRT_HD void dust_cell(const DustParams& P, int m) {
+  const int nc = P.G.ncell;
+  double L = 0.0;
+  for (int r = 0; r < P.n_abs; ++r) L += P.absorbed[(long long)r * nc + m];
+  double lo[3], hi[3];
+  cell_box<GK>(P.G, m, lo, hi);
+  const double M = (double)static_cast<const R*>(P.rho)[m] * ((hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]));
+  double T = 0.0, scale = 0.0;
+  if (L > 0.0 && M > 0.0) {
+    T = dust_temperature(P.D, L / (P.emissivity * M));
+    double S, dS;
+    dust_sum(P.D, T, S, dS);
+    scale = S > 0.0 ? L / S : 0.0;
+  }
+  if (P.temperature) P.temperature[m] = T;
+  for (int i = 0; i < P.D.nl; ++i)
+    P.emission[(long long)i * nc + m] = scale > 0.0 ? scale * (P.D.a[i] / expm1(P.D.b[i] / T)) : 0.0;
 }
 
 // ---------------------------------------------------------------------------

@@ -406,7 +406,27 @@ struct Prepared {
   long long n_images = 0;  // comps * n_lambda * pixels of all frames
   double emitted = 0.0;    // sum over wavelengths of n_packages * w0
   long long n_keys = 0;    // image-plane tiles over all frames
+  int cell_src = -1;       // index of the cell source, -1 if none
 };
+
+// Per wavelength: the sources' cumulative luminosities, the total and the
+// package weight; the cell source (if any) with its totals cell_totals[l]
+// (none yet: 0).
+inline void set_luminosities(Prepared& out, int n_src, const mcrt_source* sources, const double* cell_totals,
+                             unsigned long long n_packages) {
+  out.emitted = 0.0;
+  for (size_t l = 0; l < out.lam.size(); ++l) {
+    LamDev& L = out.lam[l];
+    double cum = 0.0;
+    for (int s = 0; s < n_src; ++s) {
+      cum += s == out.cell_src ? (cell_totals ? cell_totals[l] : 0.0) : sources[s].lum[l];
+      L.cum[s] = cum;
+    }
+    L.ltot = cum;
+    L.w0 = cum / (double)n_packages;
+    out.emitted += L.w0 * (double)n_packages;
+  }
+}
 
 inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
                    const mcrt_source* sources, int n_det, const mcrt_detector* detectors, const mcrt_opts* opts,
@@ -425,8 +445,15 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
   if (n_src < 1 || n_src > MCRT_MAX_SOURCES)
     return fail(MCRT_EINVAL, "n_src = %d outside [1, %d]", n_src, MCRT_MAX_SOURCES);
   if (!sources) return fail(MCRT_EINVAL, "sources is NULL");
+  int cell_src = -1;
   for (int s = 0; s < n_src; ++s) {
     const mcrt_source& S = sources[s];
+    if (S.kind == MCRT_SRC_CELLS) {
+      if (cell_src >= 0) return fail(MCRT_EINVAL, "source %d: at most one cell source per call", s);
+      if (!S.cell_lum) return fail(MCRT_EINVAL, "source %d: cell_lum is NULL", s);
+      cell_src = s;
+      continue;
+    }
     if (S.kind != MCRT_SRC_POINT && S.kind != MCRT_SRC_EXPDISK)
       return fail(MCRT_EINVAL, "source %d: unknown kind %d", s, S.kind);
     if (!finite(S.x) || !finite(S.y) || !finite(S.z)) return fail(MCRT_EINVAL, "source %d: position must be finite", s);
@@ -471,22 +498,15 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
   P.batch = opts->event_batch > 0 ? opts->event_batch : 16;
 
   out.lam.assign(nl, LamDev{});
-  out.emitted = 0.0;
   for (int l = 0; l < nl; ++l) {
     LamDev& L = out.lam[l];
     std::memset(&L, 0, sizeof L);
     L.kappa = optics->kappa[l];
     L.albedo = optics->albedo[l];
     L.g = optics->g[l];
-    double cum = 0.0;
-    for (int s = 0; s < n_src; ++s) {
-      cum += sources[s].lum[l];
-      L.cum[s] = cum;
-    }
-    L.ltot = cum;
-    L.w0 = cum / (double)opts->n_packages;
-    out.emitted += L.w0 * (double)opts->n_packages;
   }
+  out.cell_src = cell_src;
+  set_luminosities(out, n_src, sources, nullptr, opts->n_packages);
   out.det.assign(n_det > 0 ? n_det : 1, DetDev{});
   long long off = 0;
   for (int d = 0; d < n_det; ++d) {
@@ -548,6 +568,37 @@ inline std::vector<DetDev> make_dets(int n_det, const mcrt_detector* detectors, 
   }
   if (total_pixels) *total_pixels = off;
   return det;
+}
+
+inline int check_dust(const mcrt_grid* grid, const void* rho_dev, int precision, int n_abs, const double* absorbed_dev,
+                      int n_lambda, const double* lambda, const double* dlambda, const double* kappa_abs,
+                      double emissivity, const double* emission_dev) {
+  if (int e = check_grid(grid)) return e;
+  if (!rho_dev) return fail(MCRT_EINVAL, "rho_dev is NULL");
+  if (precision != MCRT_PREC_FP64 && precision != MCRT_PREC_FP32)
+    return fail(MCRT_EINVAL, "unknown precision %d", precision);
+  if (n_abs < 1 || n_abs > (1 << 20)) return fail(MCRT_EINVAL, "n_abs = %d outside [1, 2^20]", n_abs);
+  if (!absorbed_dev) return fail(MCRT_EINVAL, "absorbed_dev is NULL");
+  if (n_lambda < 1 || n_lambda > (1 << 20)) return fail(MCRT_EINVAL, "n_lambda = %d outside [1, 2^20]", n_lambda);
+  if (!lambda || !dlambda || !kappa_abs) return fail(MCRT_EINVAL, "lambda, dlambda or kappa_abs is NULL");
+  for (int i = 0; i < n_lambda; ++i)
+    if (!(lambda[i] > 0.0) || !finite(lambda[i]) || !(dlambda[i] > 0.0) || !finite(dlambda[i]) ||
+        !(kappa_abs[i] > 0.0) || !finite(kappa_abs[i]))
+      return fail(MCRT_EINVAL, "lambda, dlambda and kappa_abs must be finite and > 0 (index %d)", i);
+  if (!(emissivity > 0.0) || !finite(emissivity)) return fail(MCRT_EINVAL, "emissivity must be finite and > 0");
+  if (!emission_dev) return fail(MCRT_EINVAL, "emission_dev is NULL");
+  return 0;
+}
+
+// Per-wavelength constants of the dust emission: a_i = kappa_abs_i
+// dlambda_i / lambda_i^5 and b_i = c2 / lambda_i.
+inline void dust_constants(int n_lambda, const double* lambda, const double* dlambda, const double* kappa_abs,
+                           double* a, double* b) {
+  for (int i = 0; i < n_lambda; ++i) {
+    const double l = lambda[i];
+    a[i] = kappa_abs[i] * dlambda[i] / (l * l * l * l * l);
+    b[i] = kC2 / l;
+  }
 }
 
 }  // namespace host

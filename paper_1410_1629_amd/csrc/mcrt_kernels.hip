@@ -750,6 +750,105 @@ __global__ void k_unbrick(const double* __restrict__ src, double* __restrict__ d
   }
 }
 
+// ---------------------------------------------------------------------------
+// Cell-source CDF: per wavelength row the exclusive prefix sums of the
+// cells' luminosities x[row][0..n) into cum[row][0..n], cum[row][n] the
+// total.  Tiles of kCdfTile cells; each thread sums kCdfPer consecutive cells
+// in order, one thread of the tile adds the threads' sums in order, and one
+// thread per row adds the tiles' sums in order.  Every entry is an offset
+// plus a partial sum that the next entry extends by the cell's own
+// luminosity, so cum never decreases and a cell of zero luminosity has
+// cum[m + 1] == cum[m] exactly: it can never be drawn.  The tile kernel also
+// flags a negative or non-finite luminosity.
+constexpr int kCdfThreads = 256, kCdfPer = 8, kCdfTile = kCdfThreads * kCdfPer;
+
+struct CdfTile {
+  double part[kCdfPer];  // exclusive sums of the thread's cells
+  double base;           // exclusive sum of the tile's earlier threads
+  double total;          // sum of the tile
+};
+
+__device__ void cdf_tile(const double* __restrict__ row, long long n, long long tile, CdfTile& c, int* bad) {
+  __shared__ double ts[kCdfThreads];
+  __shared__ double tb[kCdfThreads + 1];
+  const long long i0 = tile * kCdfTile + (long long)threadIdx.x * kCdfPer;
+  double s = 0.0;
+  bool ok = true;
+  for (int k = 0; k < kCdfPer; ++k) {
+    c.part[k] = s;
+    const double v = i0 + k < n ? row[i0 + k] : 0.0;
+    ok = ok && v >= 0.0 && v < INFINITY;
+    s += v;
+  }
+  if (!ok) atomicOr(bad, 1);
+  ts[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int t = 0; t < kCdfThreads; ++t) {
+      tb[t] = acc;
+      acc += ts[t];
+    }
+    tb[kCdfThreads] = acc;
+  }
+  __syncthreads();
+  c.base = tb[threadIdx.x];
+  c.total = tb[kCdfThreads];
+}
+
+// One workgroup per (row, tile), blockIdx.x = row * n_tiles + tile.
+__global__ void __launch_bounds__(kCdfThreads) k_cdf_tiles(const double* __restrict__ x, long long n, int n_tiles,
+                                                           double* __restrict__ tile_sum, int* bad) {
+  const long long row = blockIdx.x / n_tiles, tile = blockIdx.x - row * n_tiles;
+  CdfTile c;
+  cdf_tile(x + row * n, n, tile, c, bad);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = c.total;
+}
+
+// One thread per row: tile sums -> exclusive tile offsets, and the total.
+__global__ void k_cdf_top(double* __restrict__ tile_sum, int n_tiles, int rows, double* __restrict__ cum, long long n,
+                          double* __restrict__ totals) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= rows) return;
+  double acc = 0.0;
+  double* t = tile_sum + (long long)row * n_tiles;
+  for (int q = 0; q < n_tiles; ++q) {
+    const double v = t[q];
+    t[q] = acc;
+    acc += v;
+  }
+  cum[(long long)row * (n + 1) + n] = acc;
+  totals[row] = acc;
+}
+
+__global__ void __launch_bounds__(kCdfThreads) k_cdf_apply(const double* __restrict__ x, long long n, int n_tiles,
+                                                           const double* __restrict__ tile_off,
+                                                           double* __restrict__ cum, int* bad) {
+  const long long row = blockIdx.x / n_tiles, tile = blockIdx.x - row * n_tiles;
+  CdfTile c;
+  cdf_tile(x + row * n, n, tile, c, bad);
+  const double off = tile_off[blockIdx.x];
+  const long long i0 = tile * kCdfTile + (long long)threadIdx.x * kCdfPer;
+  double* out = cum + row * (n + 1);
+  for (int k = 0; k < kCdfPer; ++k)
+    if (i0 + k < n) out[i0 + k] = off + (c.base + c.part[k]);
+}
+
+// ---------------------------------------------------------------------------
+// Dust emission, one thread per cell; the table kernel fills ln P at the
+// kDustTable + 1 points first.
+
+__global__ void k_dust_table(DustDev D, double* __restrict__ lnP) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k <= kDustTable) lnP[k] = dust_table_entry(D, k);
+}
+
+template <typename R, int GK>
+__global__ void __launch_bounds__(kBlock) k_dust_emission(DustParams P) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < P.G.ncell) dust_cell<R, GK>(P, m);
+}
+
 }  // namespace mcrt
 
 // ===========================================================================
@@ -824,6 +923,31 @@ int unbrick_tally(const GridDev& G, const double* src, double* dst, int n_lambda
   hipLaunchKernelGGL(k_unbrick, dim3(stream_blocks((long long)n_lambda * G.ncell)), dim3(kBlock), 0, st, src, dst, G,
                      n_lambda);
   HIPCHK(hipGetLastError());
+  return 0;
+}
+
+// CDF of the cell source's luminosities cell_lum [n_lambda][ncell] (device)
+// into cum [n_lambda][ncell + 1]; then the per-wavelength totals come to
+// the host (the call waits for them) and set the package weights in pr.
+int cell_cdf(const double* cell_lum, int nl, int ncell, double* cum, double* tile_sum, int n_tiles, double* totals,
+             hipStream_t st, host::Prepared* pr, int n_src, const mcrt_source* sources, const mcrt_opts* opts) {
+  int* bad = reinterpret_cast<int*>(totals + nl);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(bad), 1ll);
+  const unsigned blocks = (unsigned)((long long)nl * n_tiles);
+  hipLaunchKernelGGL(k_cdf_tiles, dim3(blocks), dim3(kCdfThreads), 0, st, cell_lum, (long long)ncell, n_tiles,
+                     tile_sum, bad);
+  hipLaunchKernelGGL(k_cdf_top, dim3((nl + 255) / 256), dim3(256), 0, st, tile_sum, n_tiles, nl, cum,
+                     (long long)ncell, totals);
+  hipLaunchKernelGGL(k_cdf_apply, dim3(blocks), dim3(kCdfThreads), 0, st, cell_lum, (long long)ncell, n_tiles,
+                     tile_sum, cum, bad);
+  HIPCHK(hipGetLastError());
+  std::vector<double> tot(nl + 1);
+  HIPCHK(hipMemcpyAsync(tot.data(), totals, sizeof(double) * nl + sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int flag = 0;
+  std::memcpy(&flag, tot.data() + nl, sizeof flag);
+  if (flag) return fail(MCRT_EINVAL, "cell_lum holds a negative or non-finite luminosity");
+  host::set_luminosities(*pr, n_src, sources, tot.data(), opts->n_packages);
   return 0;
 }
 
@@ -1067,16 +1191,33 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const size_t off_rho = off_cnt + 256;
   const size_t off_tal = off_rho + align256((size_t)P.G.ncell_pad * (f32 ? 4 : 8));
   const size_t off_evs = off_tal + align256(sizeof(double) * (size_t)n_tally);
-  const size_t bytes = off_evs + align256(sizeof(double) * n_evs);
-  std::vector<unsigned char> blob(off_rho, 0);
-  std::memcpy(blob.data() + off_lam, pr.lam.data(), sizeof(LamDev) * nl);
-  std::memcpy(blob.data() + off_det, pr.det.data(), sizeof(DetDev) * pr.det.size());
-  std::memcpy(blob.data() + off_src, pr.src.data(), sizeof(SrcDev) * pr.src.size());
+  // a cell source: its CDF [n_lambda][ncell + 1], the scan's tile sums, the
+  // per-wavelength totals and a flag for bad luminosities
+  const bool cells = pr.cell_src >= 0;
+  const long long cdf_tiles = cells ? ((long long)P.G.ncell + kCdfTile - 1) / kCdfTile : 0;
+  if (cells && (long long)nl * cdf_tiles * kCdfThreads >= (1ll << 32))
+    return fail(MCRT_EINVAL, "cell source: n_lambda x cells too large");
+  const size_t off_cum = off_evs + align256(sizeof(double) * n_evs);
+  const size_t off_cts = off_cum + align256(cells ? sizeof(double) * (size_t)nl * (P.G.ncell + 1) : 0);
+  const size_t off_ctot = off_cts + align256(sizeof(double) * (size_t)(nl * cdf_tiles));
+  const size_t bytes = off_ctot + (cells ? align256(sizeof(double) * nl + 8) : 0);
 
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   DeviceBlock blk;
   blk.st = st;
   HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), bytes, st));
+  if (cells) {
+    double* cum = reinterpret_cast<double*>(blk.ptr + off_cum);
+    if (int e = cell_cdf(static_cast<const double*>(sources[pr.cell_src].cell_lum), nl, P.G.ncell, cum,
+                         reinterpret_cast<double*>(blk.ptr + off_cts), (int)cdf_tiles,
+                         reinterpret_cast<double*>(blk.ptr + off_ctot), st, &pr, n_src, sources, opts))
+      return e;
+    pr.src[pr.cell_src].cum = cum;
+  }
+  std::vector<unsigned char> blob(off_rho, 0);
+  std::memcpy(blob.data() + off_lam, pr.lam.data(), sizeof(LamDev) * nl);
+  std::memcpy(blob.data() + off_det, pr.det.data(), sizeof(DetDev) * pr.det.size());
+  std::memcpy(blob.data() + off_src, pr.src.data(), sizeof(SrcDev) * pr.src.size());
   host::put_planes(*grid, P.G, blob.data() + off_pl, blk.ptr + off_pl);
   HIPCHK(hipMemcpyAsync(blk.ptr, blob.data(), off_rho, hipMemcpyHostToDevice, st));
   if (int e = brick_density(P.G, rho_dev, blk.ptr + off_rho, f32, st)) return e;
@@ -1359,6 +1500,60 @@ int peel_off(const mcrt_grid* grid, const void* rho_dev, double kappa, double g,
     return 0;
   } catch (...) {
     return fail(MCRT_EHIP, "peel_off: host exception");
+  }
+}
+
+int dust_emission(const mcrt_grid* grid, const void* rho_dev, int precision, int n_abs, const double* absorbed_dev,
+                  int n_lambda, const double* lambda, const double* dlambda, const double* kappa_abs,
+                  double emissivity, double* temperature_dev, double* emission_dev, void* hip_stream) {
+  try {
+    mcrt::host::last_error().clear();
+    if (int e = host::check_dust(grid, rho_dev, precision, n_abs, absorbed_dev, n_lambda, lambda, dlambda, kappa_abs,
+                                 emissivity, emission_dev))
+      return e;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    DustParams P;
+    std::memset(&P, 0, sizeof P);
+    if (int e = host::make_grid(*grid, host::elem_bytes(precision), 0, P.G)) return e;
+    // plane or tree tables, a, b, the ln P table
+    const size_t off_a = host::plane_bytes(P.G, *grid), off_b = off_a + align256(sizeof(double) * n_lambda),
+                 off_t = off_b + align256(sizeof(double) * n_lambda),
+                 bytes = off_t + align256(sizeof(double) * (kDustTable + 1));
+    std::vector<unsigned char> blob(off_t, 0);
+    DeviceBlock blk;
+    blk.st = st;
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), bytes, st));
+    host::put_planes(*grid, P.G, blob.data(), blk.ptr);
+    host::dust_constants(n_lambda, lambda, dlambda, kappa_abs, reinterpret_cast<double*>(blob.data() + off_a),
+                         reinterpret_cast<double*>(blob.data() + off_b));
+    HIPCHK(hipMemcpyAsync(blk.ptr, blob.data(), off_t, hipMemcpyHostToDevice, st));
+    P.D.nl = n_lambda;
+    P.D.a = reinterpret_cast<const double*>(blk.ptr + off_a);
+    P.D.b = reinterpret_cast<const double*>(blk.ptr + off_b);
+    P.D.lnP = reinterpret_cast<const double*>(blk.ptr + off_t);
+    hipLaunchKernelGGL(k_dust_table, dim3((kDustTable + 256) / 256), dim3(256), 0, st, P.D,
+                       reinterpret_cast<double*>(blk.ptr + off_t));
+    P.rho = rho_dev;
+    P.absorbed = absorbed_dev;
+    P.n_abs = n_abs;
+    P.emissivity = emissivity;
+    P.temperature = temperature_dev;
+    P.emission = emission_dev;
+    const dim3 g((unsigned)((P.G.ncell + kBlock - 1) / kBlock)), b(kBlock);
+    const bool f32 = precision == MCRT_PREC_FP32;
+    const int kind = P.G.kind;
+    void (*kern)(DustParams) =
+        f32 ? (kind == kGridRect   ? k_dust_emission<float, kGridRect>
+               : kind == kGridTree ? k_dust_emission<float, kGridTree>
+                                   : k_dust_emission<float, kGridRegular>)
+            : (kind == kGridRect   ? k_dust_emission<double, kGridRect>
+               : kind == kGridTree ? k_dust_emission<double, kGridTree>
+                                   : k_dust_emission<double, kGridRegular>);
+    hipLaunchKernelGGL(kern, g, b, 0, st, P);
+    HIPCHK(hipGetLastError());
+    return 0;
+  } catch (...) {
+    return fail(MCRT_EHIP, "dust_emission: host exception");
   }
 }
 

@@ -405,6 +405,11 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
             continue;
           }
         }
+        if (LD.ltot == 0.0) {  // nothing is emitted at this wavelength: the package ends unborn
+          if (L.pass == 0) ++L.n_pk;
+          L.phase = PH_FETCH;
+          continue;
+        }
       }
     }
     // -- emission (also the start of the adjoint replay)
@@ -420,7 +425,12 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
         }
       }
       iso_direction(u01(wd.x), u01(wd.y), L.k);
-      source_position(M.src(s), draw_words(P.seed, L.pkg, (unsigned)L.lam, 0u), L.r);
+      const SrcDev& S = M.src(s);
+      const U4 wp = draw_words(P.seed, L.pkg, (unsigned)L.lam, 0u);
+      if (S.kind == 2)
+        cell_source_position<Mem::kGrid>(S, G, L.lam, wp, L.r);
+      else
+        source_position(S, wp, L.r);
       L.W = L.w0;
       L.n = 0;
       if (L.pass == 0) ++L.n_pk;

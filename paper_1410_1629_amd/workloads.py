@@ -11,7 +11,8 @@ Problem dict keys:
   optional tree ({axis, split, child} per node of a tree grid; n = (cells, 1, 1)),
   rho (float64 array [nz, ny, nx]; for precision 1 its values are already
   float32-representable), kappa / albedo / g (one value per wavelength),
-  sources [{kind, pos, h_r, h_z, lum[n_lambda]}],
+  sources [{kind, pos, h_r, h_z, lum[n_lambda]}] (kind "cells": the grid's
+  cells emit cell_lum[n_lambda][ncell], e.g. dust emission),
   detectors [{distance, incl, azim, pa, nx, ny, half_x, half_y}],
   n_packages, first_package, seed, w_min, max_scatter, flags,
   precision (0: FP64 path; 1: FP32 traversal with FP64 state and tallies).
@@ -448,6 +449,56 @@ def point(pos=(0.0, 0.0, 0.0), lum=1.0):
 
 def expdisk(h_r, h_z, lum=1.0, pos=(0.0, 0.0, 0.0)):
     return _expdisk(h_r, h_z, lum, pos)
+
+
+def cells(cell_lum):
+    """A cell source: the grid's cells emit cell_lum [n_lambda][ncell]
+    (host array or device tensor), for instance dust emission."""
+    return {"kind": "cells", "cell_lum": cell_lum, "lum": 0.0}
+
+
+def log_bin_widths(lam):
+    """Widths of wavelength bins around increasing centres lam: edges at the
+    geometric means of neighbours, the end bins mirrored."""
+    lam = np.asarray(lam, dtype=np.float64)
+    if lam.size == 1:
+        return np.array([0.1 * lam[0]])
+    mid = np.sqrt(lam[1:] * lam[:-1])
+    edges = np.concatenate([[lam[0] ** 2 / mid[0]], mid, [lam[-1] ** 2 / mid[-1]]])
+    return np.diff(edges)
+
+
+# Grain emission of the panchromatic workload: emissivity in the units of the
+# multiwavelength disk (luminosity per unit density x kpc^3 and per unit of
+# sum_i kappa_abs B dlambda) that puts its median dust near 20 K.
+PANCHROMATIC_EMISSIVITY = 1.1e12
+
+
+def panchromatic(n_packages=1_000_000, precision=1, n_lambda=100, seed=DEFAULT_SEED):
+    """The multiwavelength disk (128^3 cells, 100 wavelengths 0.1-1000
+    micron) as a panchromatic problem: the stellar run with the absorbed
+    tally, then the dust's re-emission on the same wavelengths.  Returns
+    (stellar problem, dust dict {lambda, dlambda, kappa_abs, emissivity});
+    kappa_abs = kappa (1 - albedo)."""
+    prob = multiwavelength(n_packages=n_packages, precision=precision, n_lambda=n_lambda, seed=seed,
+                           flags=FLAGS_DEFAULT)
+    prob["name"] = "panchromatic_128"
+    lam = prob["lambda_um"]
+    dust = {"lambda": lam, "dlambda": log_bin_widths(lam), "kappa_abs": prob["kappa"] * (1.0 - prob["albedo"]),
+            "emissivity": PANCHROMATIC_EMISSIVITY}
+    return prob, dust
+
+
+def dust_problem(stellar, emission, n_packages=None, flags=FLAG_PEEL_EMIT | FLAG_PEEL_SCAT | FLAG_ABSORB):
+    """The re-emission run of a panchromatic problem: the stellar problem's
+    grid, optics and frames with the cells as the only source."""
+    p = dict(stellar)
+    p["sources"] = [cells(emission)]
+    p["flags"] = int(flags)
+    if n_packages is not None:
+        p["n_packages"] = int(n_packages)
+    p["name"] = stellar["name"] + "_dust"
+    return p
 
 
 def frame(distance, incl, nx, ny, half_x, half_y, azim=-90.0, pa=0.0):

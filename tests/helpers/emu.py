@@ -46,7 +46,8 @@ class Emu:
                                        C.POINTER(C.c_uint64), C.c_int, C.c_int]
         lib.emu_peel_off.argtypes = [C.POINTER(B.Grid), P, d, d, C.c_int, C.c_int64, P, P, P, C.c_int,
                                      C.POINTER(B.Detector), P, C.c_int, C.c_int]
-        for f in ("emu_run_photons", "emu_backward_density", "emu_trace_path", "emu_peel_off"):
+        lib.emu_dust_emission.argtypes = [C.POINTER(B.Grid), P, C.c_int, C.c_int, P, C.c_int, P, P, P, d, P, P]
+        for f in ("emu_run_photons", "emu_backward_density", "emu_trace_path", "emu_peel_off", "emu_dust_emission"):
             getattr(lib, f).restype = C.c_int
         lib.emu_set_events_kept.argtypes = [C.c_int]
         lib.emu_set_events_kept.restype = None
@@ -72,7 +73,7 @@ class Emu:
         return None if a is None else a.ctypes.data_as(C.c_void_p)
 
     def run(self, prob, wave=WAVE, **overrides):
-        pr = B._Problem(prob, **overrides)
+        pr = B._Problem(prob, cells_on_device=False, **overrides)
         rho = self._rho(prob)
         images = np.zeros(B.image_shape(prob))
         absorbed = np.zeros((len(np.atleast_1d(prob["kappa"])), rho.size)) if prob.get("flags", 7) & 4 else None
@@ -93,7 +94,7 @@ class Emu:
         self.lib.emu_set_chunk_items(int(n))
 
     def grad(self, prob, adj, wave=WAVE, **overrides):
-        pr = B._Problem(prob, **overrides)
+        pr = B._Problem(prob, cells_on_device=False, **overrides)
         rho = self._rho(prob)
         adj = np.ascontiguousarray(adj, dtype=np.float64).reshape(-1)
         g = np.zeros(rho.size)
@@ -135,3 +136,16 @@ class Emu:
                                           self._p(pos), self._p(din), self._p(w), len(detectors), dets,
                                           self._p(images), int(brick_shape), wave))
         return images
+
+    def dust_emission(self, box, n, rho, prec, absorbed, lam, dlam, kappa_abs, emissivity, planes=None, tree=None):
+        gr = B.make_grid({"box": box, "n": n, "planes": planes, "tree": tree})
+        dt = np.float32 if prec == 1 else np.float64
+        rho = np.ascontiguousarray(np.asarray(rho).reshape(-1), dtype=dt)
+        absorbed = np.ascontiguousarray(absorbed, dtype=np.float64).reshape(-1, rho.size)
+        lam, dlam, ka = (np.ascontiguousarray(np.atleast_1d(v), dtype=np.float64) for v in (lam, dlam, kappa_abs))
+        T = np.zeros(rho.size)
+        em = np.zeros((lam.size, rho.size))
+        self._check(self.lib.emu_dust_emission(C.byref(gr), self._p(rho), int(prec), absorbed.shape[0],
+                                               self._p(absorbed), lam.size, self._p(lam), self._p(dlam),
+                                               self._p(ka), float(emissivity), self._p(T), self._p(em)))
+        return T, em

@@ -371,9 +371,31 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
              mcrt_stats* stats, int wave) {
   host::Prepared pr;
   if (int e = host::prepare(grid, rho, optics, n_src, sources, n_det, detectors, opts, pr)) return e;
-  RunParams P = pr.P;
   HostPlanes planes;
-  planes.attach(*grid, P.G);
+  planes.attach(*grid, pr.P.G);
+  // a cell source: per wavelength the prefix sums of its cells'
+  // luminosities (host array here), NaN-fenced, and the totals
+  std::vector<double> cum;
+  if (pr.cell_src >= 0) {
+    const int nl = pr.P.n_lambda, nc = pr.P.G.ncell;
+    const double* x = sources[pr.cell_src].cell_lum;
+    cum.assign((size_t)nl * (nc + 1) + 2, std::nan(""));
+    std::vector<double> tot(nl);
+    for (int l = 0; l < nl; ++l) {
+      double acc = 0.0;
+      for (int m = 0; m < nc; ++m) {
+        const double v = x[(size_t)l * nc + m];
+        if (!(v >= 0.0 && v < INFINITY)) return host::fail(MCRT_EINVAL, "cell_lum holds a negative or non-finite luminosity");
+        cum[1 + (size_t)l * (nc + 1) + m] = acc;
+        acc += v;
+      }
+      cum[1 + (size_t)l * (nc + 1) + nc] = acc;
+      tot[l] = acc;
+    }
+    host::set_luminosities(pr, n_src, sources, tot.data(), opts->n_packages);
+    pr.src[pr.cell_src].cum = cum.data() + 1;
+  }
+  RunParams P = pr.P;
   P.images = images;
   P.absorbed = ((opts->flags & MCRT_ABSORB) && !ADJ) ? absorbed : nullptr;
   P.adj = adj;
@@ -769,6 +791,49 @@ int emu_peel_off(const mcrt_grid* grid, const void* rho, double kappa, double g,
                          dir_in, w, n_det, detectors, images, brick_shape, wave);
   } catch (const Violation& v) {
     g_violation = std::string("peel_off: ") + v.what();
+    return -100;
+  }
+}
+
+int emu_dust_emission(const mcrt_grid* grid, const void* rho, int precision, int n_abs, const double* absorbed,
+                      int n_lambda, const double* lambda, const double* dlambda, const double* kappa_abs,
+                      double emissivity, double* temperature, double* emission) {
+  try {
+    g_violation.clear();
+    host::last_error().clear();
+    if (int e = host::check_dust(grid, rho, precision, n_abs, absorbed, n_lambda, lambda, dlambda, kappa_abs,
+                                 emissivity, emission))
+      return e;
+    DustParams P;
+    std::memset(&P, 0, sizeof P);
+    if (int e = host::make_grid(*grid, host::elem_bytes(precision), 0, P.G)) return e;
+    HostPlanes planes;
+    planes.attach(*grid, P.G);
+    std::vector<double> a(n_lambda), b(n_lambda), lnP(kDustTable + 1);
+    host::dust_constants(n_lambda, lambda, dlambda, kappa_abs, a.data(), b.data());
+    P.D.nl = n_lambda;
+    P.D.a = a.data();
+    P.D.b = b.data();
+    for (int k = 0; k <= kDustTable; ++k) lnP[k] = dust_table_entry(P.D, k);
+    P.D.lnP = lnP.data();
+    P.rho = rho;
+    P.absorbed = absorbed;
+    P.n_abs = n_abs;
+    P.emissivity = emissivity;
+    P.temperature = temperature;
+    P.emission = emission;
+    const bool f32 = precision == MCRT_PREC_FP32;
+    for (int m = 0; m < P.G.ncell; ++m) {
+      if (P.G.kind == kGridTree)
+        f32 ? dust_cell<float, kGridTree>(P, m) : dust_cell<double, kGridTree>(P, m);
+      else if (P.G.kind == kGridRect)
+        f32 ? dust_cell<float, kGridRect>(P, m) : dust_cell<double, kGridRect>(P, m);
+      else
+        f32 ? dust_cell<float, kGridRegular>(P, m) : dust_cell<double, kGridRegular>(P, m);
+    }
+    return 0;
+  } catch (const Violation& v) {
+    g_violation = std::string("dust_emission: ") + v.what();
     return -100;
   }
 }

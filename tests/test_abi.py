@@ -178,6 +178,61 @@ def test_invalid_arguments_are_rejected(lib, B, W, case):
     assert lib.mcrt_last_error().decode(), case
 
 
+@pytest.mark.parametrize("case", ["cell_lum_null", "two_cell_sources"])
+def test_invalid_cell_sources_are_rejected(lib, B, W, case):
+    prob = W.small_problem(n=(4, 4, 4), n_packages=100)
+    pr = B._Problem(prob)
+    fake = C.c_void_p(0x1000)
+    srcs = (B.Source * 2)()
+    srcs[0] = pr.sources[0]
+    srcs[0].kind = 2
+    srcs[0].cell_lum = None if case == "cell_lum_null" else fake
+    srcs[1] = srcs[0]
+    st = B.Stats()
+    rc = lib.run_photons(C.byref(pr.grid), fake, C.byref(pr.optics), 1 if case == "cell_lum_null" else 2, srcs,
+                         pr.n_det, pr.detectors, C.byref(pr.opts), fake, fake, C.byref(st), None)
+    assert rc == B.EINVAL
+    assert "cell" in lib.mcrt_last_error().decode()
+
+
+@pytest.mark.parametrize("case", ["n_abs", "absorbed", "n_lambda", "lambda", "dlambda", "kappa_abs", "emissivity",
+                                  "emission", "precision", "rho", "grid"])
+def test_invalid_dust_emission_arguments_are_rejected(lib, B, case):
+    g = B.make_grid({"box": (-1, 1, -1, 1, -1, 1), "n": (4, 4, 4)})
+    fake = C.c_void_p(0x1000)
+    lam, dlam, ka = np.array([10.0, 100.0]), np.array([1.0, 10.0]), np.array([1.0, 0.1])
+    args = dict(grid=C.byref(g), rho=fake, precision=0, n_abs=1, absorbed=fake, n_lambda=2, lam=lam, dlam=dlam,
+                ka=ka, eps=1.0, temp=None, emission=fake)
+    if case == "n_abs":
+        args["n_abs"] = 0
+    elif case == "absorbed":
+        args["absorbed"] = None
+    elif case == "n_lambda":
+        args["n_lambda"] = 0
+    elif case == "lambda":
+        args["lam"] = np.array([10.0, -1.0])
+    elif case == "dlambda":
+        args["dlam"] = np.array([0.0, 1.0])
+    elif case == "kappa_abs":
+        args["ka"] = np.array([1.0, np.nan])
+    elif case == "emissivity":
+        args["eps"] = 0.0
+    elif case == "emission":
+        args["emission"] = None
+    elif case == "precision":
+        args["precision"] = 3
+    elif case == "rho":
+        args["rho"] = None
+    elif case == "grid":
+        g.nx = 0
+    dp = C.POINTER(C.c_double)
+    rc = lib.dust_emission(args["grid"], args["rho"], args["precision"], args["n_abs"], args["absorbed"],
+                           args["n_lambda"], args["lam"].ctypes.data_as(dp), args["dlam"].ctypes.data_as(dp),
+                           args["ka"].ctypes.data_as(dp), args["eps"], args["temp"], args["emission"], None)
+    assert rc == B.EINVAL, case
+    assert lib.mcrt_last_error().decode(), case
+
+
 def test_well_formed_tree_is_accepted_before_any_device_work(lib, B, W):
     # the tree of the rejection cases, unchanged, passes the argument checks:
     # the call then fails only on the fake device pointers' stream work, not
