@@ -19,6 +19,9 @@ events around it on the stream it runs on, recorded by the library);
 precisions against the Monte Carlo noise; `powcub_grid` and `kdtree_grid`
 time one step of the same model on a PowCub grid (rectilinear, cells graded
 towards the centre) and on a k-d tree grid adapted to the dust;
+`panchromatic` times one panchromatic step of the multiwavelength disk (the
+stellar run over 100 wavelengths with the absorbed tally, the dust's
+equilibrium temperatures and re-emission, the dust run from the cells);
 `cpu_baseline` times the FP64 CPU oracle on a bounded package sample of the
 same workload.
 
@@ -227,13 +230,59 @@ def grid_leg(B, prob, target, dev, note):
             "adjoint_ms": sb["kernel_ms"], "crossings_per_s": x / wall}
 
 
+def panchromatic_leg(B, dev, n_per_lambda=1_000_000):
+    """One panchromatic step, after one untimed step: stellar run with the
+    absorbed tally -> dust_emission -> dust run from the cells, all 100
+    wavelengths, n_per_lambda packages per wavelength in each run."""
+    import numpy as np
+    import torch
+    from paper_1410_1629_amd import workloads as W
+    prob, dust = W.panchromatic(n_packages=n_per_lambda)
+    rho = B.density_tensor(prob, dev)
+    ncell, nl = rho.numel(), len(prob["kappa"])
+    images = torch.empty(B.image_shape(prob), dtype=torch.float64, device=dev)
+    absorbed = torch.empty((nl, ncell), dtype=torch.float64, device=dev)
+    em = torch.empty((nl, ncell), dtype=torch.float64, device=dev)
+    T = torch.empty(ncell, dtype=torch.float64, device=dev)
+    dprob = W.dust_problem(prob, em)
+    dimages = torch.empty(B.image_shape(dprob), dtype=torch.float64, device=dev)
+    dabs = torch.empty((nl, ncell), dtype=torch.float64, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def step():
+        s1 = B.run_photons(prob, rho, images, absorbed)
+        ev[0].record()
+        B.dust_emission(prob, rho, prob["precision"], absorbed, dust["lambda"], dust["dlambda"], dust["kappa_abs"],
+                        dust["emissivity"], em, T)
+        ev[1].record()
+        s2 = B.run_photons(dprob, rho, dimages, dabs)
+        return s1, s2
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s1, s2 = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    Tn = T.cpu().numpy()
+    items = s1["packages"] + s2["packages"]
+    return {"workload": "%s: stellar run, dust emission (modified black bodies), dust run; %d wavelengths, %d packages "
+                        "per wavelength per run" % (prob["name"], nl, n_per_lambda),
+            "cells": int(ncell), "packages_per_s": items / wall, "ms_per_step": wall * 1e3,
+            "stellar_ms": s1["kernel_ms"], "dust_emission_ms": ev[0].elapsed_time(ev[1]), "dust_run_ms": s2["kernel_ms"],
+            "absorbed_fraction": s1["absorbed"] / s1["emitted"],
+            "reemitted_over_absorbed": s2["emitted"] / s1["absorbed"],
+            "dust_T_median_K": float(np.median(Tn[Tn > 0])), "dust_T_max_K": float(Tn.max())}
+
+
 def collect_profiles(out_dir, prof, run=True):
     """Runs this script under rocprofv3 as child processes (this process
     never touches the GPU) and writes the summaries to `prof` (profiles/);
     run=False only summarizes the raw output already in out_dir."""
     os.makedirs(out_dir, exist_ok=True)
     me = os.path.abspath(__file__)
-    child = [sys.executable, me, "--steps", "2", "--warmup", "1", "--no-cpu-baseline", "--no-fp64", "--no-powcub"]
+    child = [sys.executable, me, "--steps", "2", "--warmup", "1", "--no-cpu-baseline", "--no-fp64", "--no-powcub",
+             "--no-panchromatic"]
     runs = {
         "trace": ["rocprofv3", "--kernel-trace", "--stats", "--output-format", "csv"],
         "fetch": ["rocprofv3", "--kernel-trace", "--output-format", "csv", "--pmc", "FETCH_SIZE"],
@@ -284,8 +333,8 @@ def collect_profiles(out_dir, prof, run=True):
     with open(os.path.join(prof, "life_kernels_spiral_1e7_fp32.md"), "w") as f:
         f.write("# Kernel trace and HBM counters: edge-on spiral, 1e7 packages, FP32 path\n\n")
         f.write("Command (writes this file and traffic.json): `python bench.py --collect-profiles %s`\n\n" % out_dir)
-        f.write("Each pass runs `python bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-fp64 --no-powcub` under "
-                "rocprofv3: `--kernel-trace --stats`, then `--pmc FETCH_SIZE` and `--pmc WRITE_SIZE` (the "
+        f.write("Each pass runs `python bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-fp64 --no-powcub "
+                "--no-panchromatic` under rocprofv3: `--kernel-trace --stats`, then `--pmc FETCH_SIZE` and `--pmc WRITE_SIZE` (the "
                 "counter passes add `--calibrate-copy`: a 1 GiB device copy first, whose counter values give "
                 "the scale factors below).\n\n")
         f.write("## Kernel durations (rocprofv3 --stats)\n\n| kernel | calls | average ms | total ms |\n|---|---|---|---|\n")
@@ -315,6 +364,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
     ap.add_argument("--no-powcub", action="store_true", help="skip the PowCub- and k-d-tree-grid steps")
+    ap.add_argument("--no-panchromatic", action="store_true", help="skip the panchromatic step")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy first (counter scale)")
     ap.add_argument("--collect-profiles", metavar="DIR", help="run the rocprofv3 passes (raw output in DIR)")
     ap.add_argument("--summarize-profiles", metavar="DIR", help="only rewrite the summaries from the raw output in DIR")
@@ -442,6 +492,8 @@ def main():
                                       "power-law cell widths (outermost/innermost 8, 8, 16)")
         out["kdtree_grid"] = grid_leg(B, W.kdtree_spiral(n_packages=n_pkg, precision=1), target, dev,
                                       "leaves halved along their longest side while their dust mass exceeds 3e-4")
+    if not args.no_panchromatic:
+        out["panchromatic"] = panchromatic_leg(B, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
