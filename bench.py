@@ -265,13 +265,14 @@ def panchromatic_leg(B, dev, n_per_lambda=1_000_000):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     Tn = T.cpu().numpy()
+    tally = absorbed.sum().item()
     items = s1["packages"] + s2["packages"]
     return {"workload": "%s: stellar run, dust emission (modified black bodies), dust run; %d wavelengths, %d packages "
                         "per wavelength per run" % (prob["name"], nl, n_per_lambda),
             "cells": int(ncell), "packages_per_s": items / wall, "ms_per_step": wall * 1e3,
             "stellar_ms": s1["kernel_ms"], "dust_emission_ms": ev[0].elapsed_time(ev[1]), "dust_run_ms": s2["kernel_ms"],
             "absorbed_fraction": s1["absorbed"] / s1["emitted"],
-            "reemitted_over_absorbed": s2["emitted"] / s1["absorbed"],
+            "reemitted_over_absorbed_tally": s2["emitted"] / tally,
             "dust_T_median_K": float(np.median(Tn[Tn > 0])), "dust_T_max_K": float(Tn.max())}
 
 
