@@ -12,8 +12,9 @@ against a fixed target image (rendered once, before timing, from a
 perturbed density).  Inputs are resident on the device before timing.
 
 Prints one JSON line.  `value` is packages per second of whole steps;
-`roofline` describes the kernel with the longer average duration (HIP
-events around it on the stream it runs on, recorded by the library);
+`roofline` describes the life-cycle kernel (forward or adjoint) that takes
+the larger share of the step, per launch (HIP events around it on the
+stream it runs on, recorded by the library); `rooflines` gives both;
 `traversal` is the walk alone (trace_path on random rays in the same grid);
 `fp64_path` times one step of the plain FP64 GPU path and compares the two
 precisions against the Monte Carlo noise; `powcub_grid` and `kdtree_grid`
@@ -60,9 +61,9 @@ COPY_BYTES = 1 << 30
 KERNELS = {
     "forward": "void mcrt::k_life<float, false, 0>(mcrt::RunParams)",
     "adjoint": "void mcrt::k_life<float, true, 0>(mcrt::RunParams)",
-    "peel_tau_forward": "void mcrt::k_peeltau<float, false, 0>(mcrt::PeelJobParams)",
-    "peel_tau_adjoint": "void mcrt::k_peeltau<float, true, 0>(mcrt::PeelJobParams)",
-    "peel_deposit": "void mcrt::k_peeldep<float, 0>(mcrt::PeelJobParams)",
+    "peel_tau_forward": "void mcrt::k_peeltau<float, false, 0, false>(mcrt::PeelJobParams)",
+    "peel_tau_adjoint": "void mcrt::k_peeltau<float, true, 0, false>(mcrt::PeelJobParams)",
+    "peel_deposit": "void mcrt::k_peeldep<float, 0, false>(mcrt::PeelJobParams)",
     "trace": "void mcrt::k_trace<float, 0>(mcrt::TraceParams)",
 }
 
@@ -448,13 +449,23 @@ def main():
         return out
 
     fsum, bsum = summary(fw, False), summary(bw, True)
-    dominant_adj = bsum["life_ms"] > fsum["life_ms"]
-    dom = bsum if dominant_adj else fsum
-    # per launch of the life kernel: the call's bytes and time over its launches
-    launch_s = dom["life_ms"] / 1e3 / dom["life_launches"]
-    achieved = dom["life_algorithmic_bytes"] / dom["life_launches"] / launch_s / 1e9
-    key = "adjoint" if dominant_adj else "forward"
-    traffic = traffic_for(key)
+
+    def life_roofline(sm, key):
+        # per launch of the life kernel: the call's bytes and time over its launches
+        launch_s = sm["life_ms"] / 1e3 / sm["life_launches"]
+        achieved = sm["life_algorithmic_bytes"] / sm["life_launches"] / launch_s / 1e9
+        traffic = traffic_for(key)
+        r = {"kernel": KERNELS[key], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "launch_ms": launch_s * 1e3,
+             "step_share": sm["life_ms"] / ms_step}
+        if traffic:
+            r["hardware_frac"] = traffic / launch_s / 1e9 / HBM_PEAK_GBS
+        return r
+
+    # the dominant kernel: the life kernel with the larger share of the step
+    # (forward and adjoint are close; both are reported)
+    rooflines = {"forward": life_roofline(fsum, "forward"), "adjoint": life_roofline(bsum, "adjoint")}
+    key = "adjoint" if bsum["life_ms"] > fsum["life_ms"] else "forward"
     st_f = fw[-1]
     closure = (st_f["absorbed"] + st_f["escaped"] + st_f["truncated"] - st_f["emitted"]) / st_f["emitted"]
     out = {
@@ -480,11 +491,9 @@ def main():
         "forward": fsum,
         "adjoint": bsum,
         "energy_closure": closure,
-        "roofline": {"kernel": KERNELS[key], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "roofline": rooflines[key],
+        "rooflines": rooflines,
     }
-    if traffic:
-        out["roofline"]["hardware_frac"] = traffic / launch_s / 1e9 / HBM_PEAK_GBS
     out["traversal"] = traversal(B, prob, 4_000_000, dev)
     if not args.no_fp64:
         out["fp64_path"] = fp64_comparison(B, prob, step_fn, images, grad, dev)

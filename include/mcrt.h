@@ -10,7 +10,8 @@
  * the problem data: a grid of cells with constant density and optical
  * properties (Table 1(d): regular Cartesian grid), sources with a geometry
  * and a luminosity per wavelength (Table 1(a): point and exponential disk),
- * and frame instruments that use parallel projection.  Sect. 2.3 gives the
+ * and instruments: frames and SEDs seen by a distant observer (parallel
+ * projection) and perspective cameras placed anywhere.  Sect. 2.3 gives the
  * optical properties: kappa (extinction per unit density), albedo
  * kappa_sca/kappa_ext and the asymmetry parameter g of the phase function
  * (Henyey-Greenstein here).  Fig. 4/5 give the instrument parameters and the
@@ -28,7 +29,8 @@
  *    frames one after another, each [ny][nx] row-major; comp is 2 with
  *    MCRT_SPLIT (0: direct light peeled off at emission, 1: scattered light),
  *    else 1.
- *  - Frame geometry: observer direction (sin t cos p, sin t sin p, cos t);
+ *  - Frame geometry (distant instruments): observer direction
+ *    (sin t cos p, sin t sin p, cos t);
  *    image axes e_x = (-sin p, cos p, 0), e_y = (-cos t cos p, -cos t sin p,
  *    sin t), rotated by the position angle; frame [-half_x, half_x] x
  *    [-half_y, half_y] around the origin; pixels half-open.
@@ -136,13 +138,41 @@ typedef struct {
     const double *cell_lum;
 } mcrt_source;
 
-/* Frame instrument (Fig. 4/5): distance > 0 (enters as 1/distance^2),
- * inclination, azimuth and position angle in degrees, pixel counts > 0,
- * half-extents > 0 of the frame. */
+/* Instruments (Sect. 2.2: instruments record the flux received at a
+ * viewpoint; Fig. 4/5).  kind:
+ *  MCRT_DET_FRAME: a distant observer (parallel projection) at distance > 0
+ *    (enters as 1/distance^2) in the direction given by inclination and
+ *    azimuth, image rotated by the position angle (degrees); nx x ny pixels
+ *    over the half-extents half_x, half_y > 0 of the model's projection.
+ *  MCRT_DET_SED: the same distant observer recording only the total flux
+ *    per wavelength (the spectral energy distribution): nx = ny = 1, every
+ *    package counts whatever its projected position; pa, half_x and
+ *    half_y are ignored.
+ *  MCRT_DET_PERSPECTIVE: a pinhole camera anywhere, also inside the model:
+ *    at eye, looking along w = (target - eye) / |target - eye| (target !=
+ *    eye); image axes e_y = up made perpendicular to w and normalised (up
+ *    not parallel to w) and e_x = w x e_y; nx x ny pixels over
+ *    [-half_x, half_x] x [-half_y, half_y] of the plane through target
+ *    perpendicular to w.  A point r with d = r - eye and d.w > 0 is seen at
+ *    (x, y) = |target - eye| (d.e_x, d.e_y) / (d.w) in that plane (points
+ *    behind or at the eye are not seen); its peel-off travels from r to the
+ *    eye (optical depth along that segment only) and counts 1 / |d|^2.
+ *    Pixels record flux; for surface brightness divide by the pixel's
+ *    solid angle at the eye, F(a2, b2) - F(a1, b2) - F(a2, b1) + F(a1, b1)
+ *    with F(a, b) = atan(a b / sqrt(1 + a^2 + b^2)) for the pixel spanning
+ *    [a1, a2] x [b1, b2] in units of |target - eye|.  distance and the
+ *    angles are ignored.
+ * Every kind has nx x ny pixels in the image layout (SED: one). */
+#define MCRT_DET_FRAME 0
+#define MCRT_DET_SED 1
+#define MCRT_DET_PERSPECTIVE 2
+
 typedef struct {
     double distance, incl_deg, azim_deg, pa_deg;
     int32_t nx, ny;
     double half_x, half_y;
+    int32_t kind;
+    double eye[3], target[3], up[3];
 } mcrt_detector;
 
 /* Run options.  n_packages per wavelength in [1, 2e13]; packages
@@ -301,7 +331,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 10
+#define MCRT_ABI_VERSION 11
 
 #ifdef __cplusplus
 }

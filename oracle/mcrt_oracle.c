@@ -246,6 +246,18 @@ static void sb_push(segbuf *b, int64_t cell, double t0, double t1)
     b->n++;
 }
 
+/* Keeps the part of a segment list with t < len (the walk to a camera
+ * inside the model stops at the camera). */
+static void sb_clip(segbuf *b, double len)
+{
+    size_t n = 0;
+    while (n < b->n && b->v[n].t0 < len) {
+        if (b->v[n].t1 > len) b->v[n].t1 = len;
+        n++;
+    }
+    b->n = n;
+}
+
 static void sb_free(segbuf *b)
 {
     free(b->v);
@@ -390,16 +402,37 @@ static double seg_tau(const segbuf *s, const double *rho, double kappa)
  * instrument named "xz" in Fig. 4; omega rotates (e_x, e_y) in the image
  * plane; the extents are half-widths of the frame around the origin;
  * parallel projection, so the distance enters only as 1/D^2; a pixel holds
- * flux (luminosity / D^2). */
+ * flux (luminosity / D^2).
+ *
+ * SED instrument (Sect. 2.2: the spectral energy distribution of the
+ * received flux): the same distant observer with a single pixel that every
+ * point falls in.
+ *
+ * Perspective instrument (Sect. 2.2: placed anywhere, even inside the
+ * model).  Reading: a pinhole camera at `eye` looking at `target`; the image
+ * plane passes through the target perpendicular to the view axis, with
+ * e_y along `up` made perpendicular to the view axis and e_x = view x e_y;
+ * a point is imaged where the line from the eye through it meets that plane
+ * (points behind the eye are not seen); the peel-off ray runs from the
+ * event to the eye -- optical depth along that segment only -- and counts
+ * 1 / (distance to the eye)^2.  Check: the flux of a point source seen from
+ * inside a uniform medium, and the image positions of points at known
+ * angles. */
+
+enum { DET_FRAME = 0, DET_SED = 1, DET_PERSPECTIVE = 2 };
 
 typedef struct {
+    int kind;
     double kd[3], ex[3], ey[3];
     double inv_d2, half_x, half_y, dpx, dpy;
+    double eye[3], view[3], focal; /* perspective: eye, unit view axis, distance eye-target */
     int nx, ny;
     size_t off; /* offset of this frame inside one wavelength's image block */
 } det_t;
 
-static void det_init(det_t *D, const double par[6], const int pix[2])
+/* par[16]: distance, inclination, azimuth, position angle, half_x, half_y,
+ * kind, eye[3], target[3], up[3]. */
+static void det_init(det_t *D, const double par[16], const int pix[2])
 {
     double th = par[1] * (OR_PI / 180.0), ph = par[2] * (OR_PI / 180.0), om = par[3] * (OR_PI / 180.0);
     double st = sin(th), ct = cos(th), sp = sin(ph), cp = cos(ph);
@@ -419,13 +452,67 @@ static void det_init(det_t *D, const double par[6], const int pix[2])
     D->ny = pix[1];
     D->dpx = 2.0 * par[4] / pix[0];
     D->dpy = 2.0 * par[5] / pix[1];
+    D->kind = (int)par[6];
+    if (D->kind == DET_PERSPECTIVE) {
+        const double *eye = par + 7, *target = par + 10, *up = par + 13;
+        double v[3], n = 0.0, uv = 0.0, m = 0.0;
+        for (int a = 0; a < 3; a++) {
+            D->eye[a] = eye[a];
+            v[a] = target[a] - eye[a];
+            n += v[a] * v[a];
+        }
+        D->focal = sqrt(n);
+        for (int a = 0; a < 3; a++) {
+            D->view[a] = v[a] / D->focal;
+            uv += up[a] * D->view[a];
+        }
+        for (int a = 0; a < 3; a++) {
+            D->ey[a] = up[a] - uv * D->view[a];
+            m += D->ey[a] * D->ey[a];
+        }
+        for (int a = 0; a < 3; a++) D->ey[a] /= sqrt(m);
+        D->ex[0] = D->view[1] * D->ey[2] - D->view[2] * D->ey[1];
+        D->ex[1] = D->view[2] * D->ey[0] - D->view[0] * D->ey[2];
+        D->ex[2] = D->view[0] * D->ey[1] - D->view[1] * D->ey[0];
+    }
 }
 
-/* Pixel hit by the parallel projection of r, or -1 if outside the frame. */
+/* Direction, 1/distance^2 and length of the peel-off ray from r to
+ * instrument D (distant instruments: to the grid's boundary). */
+static void det_peel_ray(const det_t *D, const double r[3], double kd[3], double *inv_d2, double *len)
+{
+    if (D->kind == DET_PERSPECTIVE) {
+        double v[3], n = 0.0;
+        for (int a = 0; a < 3; a++) {
+            v[a] = D->eye[a] - r[a];
+            n += v[a] * v[a];
+        }
+        *len = sqrt(n);
+        for (int a = 0; a < 3; a++) kd[a] = v[a] / *len;
+        *inv_d2 = 1.0 / n;
+        return;
+    }
+    for (int a = 0; a < 3; a++) kd[a] = D->kd[a];
+    *inv_d2 = D->inv_d2;
+    *len = INFINITY;
+}
+
+/* Pixel hit by the projection of r (parallel, or through the eye), or -1
+ * if outside the frame. */
 static int64_t det_pixel(const det_t *D, const double r[3])
 {
-    double xp = r[0] * D->ex[0] + r[1] * D->ex[1] + r[2] * D->ex[2];
-    double yp = r[0] * D->ey[0] + r[1] * D->ey[1] + r[2] * D->ey[2];
+    if (D->kind == DET_SED) return 0;
+    double xp, yp;
+    if (D->kind == DET_PERSPECTIVE) {
+        double d[3] = {r[0] - D->eye[0], r[1] - D->eye[1], r[2] - D->eye[2]};
+        double z = d[0] * D->view[0] + d[1] * D->view[1] + d[2] * D->view[2];
+        if (!(z > 0.0)) return -1;
+        xp = D->focal * (d[0] * D->ex[0] + d[1] * D->ex[1] + d[2] * D->ex[2]) / z;
+        yp = D->focal * (d[0] * D->ey[0] + d[1] * D->ey[1] + d[2] * D->ey[2]) / z;
+    } else {
+        xp = r[0] * D->ex[0] + r[1] * D->ex[1] + r[2] * D->ex[2];
+        yp = r[0] * D->ey[0] + r[1] * D->ey[1] + r[2] * D->ey[2];
+    }
     double fx = floor((xp + D->half_x) / D->dpx);
     double fy = floor((yp + D->half_y) / D->dpy);
     if (!(fx >= 0.0 && fx < D->nx && fy >= 0.0 && fy < D->ny)) return -1;
@@ -659,18 +746,21 @@ static void peel_event(const problem_t *P, accum_t *A, int l, int event, const d
         const det_t *D = &P->det[d];
         int64_t pix = det_pixel(D, r);
         if (pix < 0) continue;
-        double phase = k_in ? hg_phase(g, k_in[0] * D->kd[0] + k_in[1] * D->kd[1] + k_in[2] * D->kd[2])
+        double kd[3], inv_d2, len;
+        det_peel_ray(D, r, kd, &inv_d2, &len);
+        double phase = k_in ? hg_phase(g, k_in[0] * kd[0] + k_in[1] * kd[1] + k_in[2] * kd[2])
                             : 1.0 / (4.0 * OR_PI);
         sb_clear(&A->peel);
-        traverse(&P->G, r, D->kd, &A->peel);
+        traverse(&P->G, r, kd, &A->peel);
+        sb_clip(&A->peel, len);
         A->stats[ST_XPEEL] += (double)A->peel.n;
         size_t ii = image_index(P, comp, l, d, pix);
         if (P->mode == MODE_REWEIGHT) {
             double tau = seg_tau(&A->peel, P->rho_eval, kappa);
-            A->images[ii] += w_eval * phase * exp(-tau) * D->inv_d2;
+            A->images[ii] += w_eval * phase * exp(-tau) * inv_d2;
         } else {
             double tau = seg_tau(&A->peel, P->rho, kappa);
-            double c = w * phase * exp(-tau) * D->inv_d2;
+            double c = w * phase * exp(-tau) * inv_d2;
             A->images[ii] += c;
             if (P->mode == MODE_GRAD) {
                 contrib_t *C = grad_new_contrib(A);
@@ -942,7 +1032,7 @@ static int setup_problem(problem_t *P, const double box[6], const int n[3], cons
     P->n_det = n_det;
     size_t off = 0;
     for (int d = 0; d < n_det; d++) {
-        det_init(&P->det[d], det_par + 6 * d, det_pix + 2 * d);
+        det_init(&P->det[d], det_par + 16 * d, det_pix + 2 * d);
         P->det[d].off = off;
         off += (size_t)det_pix[2 * d] * det_pix[2 * d + 1];
     }
@@ -1016,10 +1106,12 @@ static int simulate(problem_t *P, double *images, double *absorbed, double *grad
  *   box[6]      xmin,xmax,ymin,ymax,zmin,zmax;  n[3] cells per axis
  *   rho[ncell]  density, cell m = i + nx (j + ny k)
  *   kappa, albedo, g [n_lambda]
- *   src_kind[n_src] (0 point, 1 exponential disk); src_par[n_src][5]
- *     = x, y, z, h_R, h_z;  src_lum[n_src][n_lambda]
- *   det_par[n_det][6] = distance, inclination, azimuth, position angle (deg),
- *     half-extent x, half-extent y;  det_pix[n_det][2] = nx, ny
+ *   src_kind[n_src] (0 point, 1 exponential disk, 2 cells); src_par[n_src][5]
+ *     = x, y, z, h_R, h_z;  src_lum[n_src][n_lambda]; cell_lum [n_lambda][ncell]
+ *     of the cell source or NULL
+ *   det_par[n_det][16] = distance, inclination, azimuth, position angle (deg),
+ *     half-extent x, half-extent y, kind (0 frame, 1 SED, 2 perspective),
+ *     eye[3], target[3], up[3];  det_pix[n_det][2] = nx, ny
  *   images [comps][n_lambda][sum over frames of ny*nx], comps = 2 with the
  *     split flag (0 direct, 1 scattered), else 1
  *   absorbed [n_lambda][ncell] or NULL
@@ -1128,7 +1220,7 @@ int oracle_peel(const double box[6], const int n[3], const double *rho, double k
     det_t det[MAX_DET];
     size_t off = 0;
     for (int d = 0; d < n_det; d++) {
-        det_init(&det[d], det_par + 6 * d, det_pix + 2 * d);
+        det_init(&det[d], det_par + 16 * d, det_pix + 2 * d);
         det[d].off = off;
         off += (size_t)det_pix[2 * d] * det_pix[2 * d + 1];
     }
@@ -1139,12 +1231,14 @@ int oracle_peel(const double box[6], const int n[3], const double *rho, double k
             int64_t pix = det_pixel(&det[d], r);
             if (pix < 0) continue;
             const double *kin = dir_in ? dir_in + 3 * e : NULL;
-            double phase = kin ? hg_phase(g, kin[0] * det[d].kd[0] + kin[1] * det[d].kd[1] + kin[2] * det[d].kd[2])
-                               : 1.0 / (4.0 * OR_PI);
+            double kd[3], inv_d2, len;
+            det_peel_ray(&det[d], r, kd, &inv_d2, &len);
+            double phase = kin ? hg_phase(g, kin[0] * kd[0] + kin[1] * kd[1] + kin[2] * kd[2]) : 1.0 / (4.0 * OR_PI);
             sb_clear(&sb);
-            traverse(&G, r, det[d].kd, &sb);
+            traverse(&G, r, kd, &sb);
+            sb_clip(&sb, len);
             double tau = seg_tau(&sb, rho, kappa);
-            images[det[d].off + (size_t)pix] += w[e] * phase * exp(-tau) * det[d].inv_d2;
+            images[det[d].off + (size_t)pix] += w[e] * phase * exp(-tau) * inv_d2;
         }
     }
     sb_free(&sb);
@@ -1152,14 +1246,15 @@ int oracle_peel(const double box[6], const int n[3], const double *rho, double k
     return 0;
 }
 
-/* Detector geometry, exposed for the geometry checks: kd, ex, ey [9]. */
-void oracle_detector_basis(const double par[6], double out[9])
+/* Detector geometry, exposed for the geometry checks: kd, ex, ey [9]
+ * (perspective: the view axis, ex, ey). */
+void oracle_detector_basis(const double par[16], double out[9])
 {
     det_t D;
     int pix[2] = {1, 1};
     det_init(&D, par, pix);
     for (int a = 0; a < 3; a++) {
-        out[a] = D.kd[a];
+        out[a] = D.kind == DET_PERSPECTIVE ? D.view[a] : D.kd[a];
         out[3 + a] = D.ex[a];
         out[6 + a] = D.ey[a];
     }

@@ -9,7 +9,9 @@ A problem is a plain dict:
   kappa, albedo, g         one value per wavelength
   sources     list of {kind: "point"|"expdisk", pos: (x, y, z), h_r, h_z, lum: [n_lambda]}, or
               {kind: "cells", cell_lum: [n_lambda][ncell]} (the grid's cells emit; at most one)
-  detectors   list of {distance, incl, azim, pa (degrees), nx, ny, half_x, half_y}
+  detectors   list of {distance, incl, azim, pa (degrees), nx, ny, half_x, half_y}, optionally
+              kind "frame" (default), "sed" (nx = ny = 1) or "perspective" (eye, target, up,
+              nx, ny, half_x, half_y)
   n_packages, first_package, seed, w_min, max_scatter, flags
 
 Images come back as an array [comps][n_lambda][sum of ny*nx over frames]
@@ -135,8 +137,18 @@ def emit_direction(u):
     return out
 
 
+DET_KINDS = {"frame": 0, "sed": 1, "perspective": 2}
+
+
+def _det_par(d):
+    """The 16 instrument parameters of the oracle's entry points."""
+    return ([d.get("distance", 1.0), d.get("incl", 0.0), d.get("azim", 0.0), d.get("pa", 0.0), d.get("half_x", 1.0),
+             d.get("half_y", 1.0), DET_KINDS[d.get("kind", "frame")]] + list(d.get("eye", (0.0, 0.0, 0.0)))
+            + list(d.get("target", (0.0, 0.0, 0.0))) + list(d.get("up", (0.0, 0.0, 0.0))))
+
+
 def detector_basis(det):
-    par = _f64([det["distance"], det["incl"], det["azim"], det.get("pa", 0.0), det["half_x"], det["half_y"]])
+    par = _f64(_det_par(det))
     out = np.zeros(9)
     _load().oracle_detector_basis(_ptr(par), _ptr(out))
     return out[0:3], out[3:6], out[6:9]
@@ -182,8 +194,7 @@ def _marshal(prob):
         assert cell_lum.size == nl * rho.size
     slum = _f64([np.broadcast_to(np.asarray(s["lum"], dtype=np.float64), (nl,)) for s in srcs])
     dets = prob["detectors"]
-    dpar = _f64([[d["distance"], d["incl"], d["azim"], d.get("pa", 0.0), d["half_x"], d["half_y"]] for d in dets]
-                if dets else np.zeros((0, 6)))
+    dpar = _f64([_det_par(d) for d in dets] if dets else np.zeros((0, 16)))
     dpix = _i32([[d["nx"], d["ny"]] for d in dets] if dets else np.zeros((0, 2)))
     npix = int(sum(d["nx"] * d["ny"] for d in dets))
     planes = _planes(prob.get("planes"), n)
@@ -269,7 +280,7 @@ def peel(box, n, rho, kappa, g, pos, dir_in, w, detectors, planes=None, tree=Non
     pos = _f64(pos).reshape(-1, 3)
     din = None if dir_in is None else _f64(dir_in).reshape(-1, 3)
     w = _f64(w).reshape(-1)
-    dpar = _f64([[d["distance"], d["incl"], d["azim"], d.get("pa", 0.0), d["half_x"], d["half_y"]] for d in detectors])
+    dpar = _f64([_det_par(d) for d in detectors])
     dpix = _i32([[d["nx"], d["ny"]] for d in detectors])
     images = np.zeros(int(sum(d["nx"] * d["ny"] for d in detectors)))
     rc = _load().oracle_peel(_ptr(box), _ptr(n), _ptr(rho), float(kappa), float(g), pos.shape[0], _ptr(pos),

@@ -49,7 +49,11 @@ class Source(C.Structure):
 class Detector(C.Structure):
     _fields_ = [("distance", C.c_double), ("incl_deg", C.c_double), ("azim_deg", C.c_double),
                 ("pa_deg", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32), ("half_x", C.c_double),
-                ("half_y", C.c_double)]
+                ("half_y", C.c_double), ("kind", C.c_int32), ("eye", C.c_double * 3), ("target", C.c_double * 3),
+                ("up", C.c_double * 3)]
+
+
+DETECTOR_KINDS = {"frame": 0, "sed": 1, "perspective": 2}
 
 
 class Opts(C.Structure):
@@ -79,7 +83,7 @@ class Stats(C.Structure):
 _lib = None
 
 # Exported symbols of include/mcrt.h.
-ABI_VERSION = 10  # MCRT_ABI_VERSION of the header these structs follow
+ABI_VERSION = 11  # MCRT_ABI_VERSION of the header these structs follow
 SYMBOLS = ("run_photons", "trace_path", "peel_off", "backward_density", "dust_emission", "mcrt_last_error",
            "mcrt_abi_version")
 
@@ -166,10 +170,15 @@ def make_grid(prob):
 
 
 def make_detectors(dets):
+    """Instrument structs of detector dicts (kind "frame" by default, "sed"
+    or "perspective" with eye, target and up)."""
     arr = (Detector * max(len(dets), 1))()
+    v3 = C.c_double * 3
     for i, d in enumerate(dets):
-        arr[i] = Detector(d["distance"], d["incl"], d["azim"], d.get("pa", 0.0), d["nx"], d["ny"], d["half_x"],
-                          d["half_y"])
+        arr[i] = Detector(d.get("distance", 1.0), d.get("incl", 0.0), d.get("azim", 0.0), d.get("pa", 0.0), d["nx"],
+                          d["ny"], d.get("half_x", 1.0), d.get("half_y", 1.0), DETECTOR_KINDS[d.get("kind", "frame")],
+                          v3(*d.get("eye", (0.0, 0.0, 0.0))), v3(*d.get("target", (0.0, 0.0, 0.0))),
+                          v3(*d.get("up", (0.0, 0.0, 0.0))))
     return arr
 
 

@@ -148,9 +148,17 @@ MCRT_HD int brick_to_linear(const GridDev& G, int c) {
   return i[0] + i[1] * G.stride[1] + i[2] * G.stride[2];
 }
 
+// Instrument kinds.
+constexpr int kDetFrame = 0, kDetSed = 1, kDetPerspective = 2;
+
 struct DetDev {
-  double kd[3], ex[3], ey[3];  // towards the observer; image axes
-  double inv_d2, half_x, half_y, inv_dpx, inv_dpy;  // pixels per unit length
+  // frame and SED: kd towards the distant observer; perspective: kd the
+  // view axis from the eye towards the target, and half_x, half_y the
+  // tangents of the half field of view.  ex, ey: image axes.
+  double kd[3], ex[3], ey[3];
+  double inv_d2, half_x, half_y, inv_dpx, inv_dpy;  // pixels per unit length (per unit tangent)
+  double eye[3];
+  int kind;
   int nx, ny;
   long long off;  // offset of this frame inside one wavelength's image block
   // Sort keys of queued peel rays: the tile of 2^tshift x 2^tshift pixels
@@ -160,6 +168,11 @@ struct DetDev {
   // they are parallel rays a few cells apart that cross one narrow bundle of
   // cells.
   int tshift, key_off, sub_shift;
+  // Width of the grid of sort-key pixels: the image's nx, or for an SED
+  // instrument (one image pixel) a virtual kn x kn grid over the projection
+  // of the model box (half_x, half_y and inv_dpx, inv_dpy describe it), so
+  // that its rays spread over many keys.
+  int kn;
 };
 
 // Interleaves the low 16 bits of x (even bits) and y (odd bits).
@@ -176,15 +189,15 @@ MCRT_HD unsigned morton2(unsigned x, unsigned y) {
   return v[0] | (v[1] << 1);
 }
 
-// Sort key of pixel `pix` of frame D.
-MCRT_HD unsigned tile_key(const DetDev& D, int pix) {
-  const int iy = pix / D.nx, ix = pix - iy * D.nx;
+// Sort key of key pixel `kp` of frame D (key_pixel).
+MCRT_HD unsigned tile_key(const DetDev& D, int kp) {
+  const int iy = kp / D.kn, ix = kp - iy * D.kn;
   return (unsigned)D.key_off + morton2((unsigned)ix >> D.tshift, (unsigned)iy >> D.tshift);
 }
 
-// Second sort key of pixel `pix`: its place inside its tile.
-MCRT_HD unsigned tile_sub(const DetDev& D, int pix) {
-  const int iy = pix / D.nx, ix = pix - iy * D.nx;
+// Second sort key of key pixel `kp`: its place inside its tile.
+MCRT_HD unsigned tile_sub(const DetDev& D, int kp) {
+  const int iy = kp / D.kn, ix = kp - iy * D.kn;
   const unsigned m = (1u << D.tshift) - 1u;
   return morton2((unsigned)ix & m, (unsigned)iy & m) >> D.sub_shift;
 }
@@ -462,12 +475,55 @@ MCRT_HD void dust_cell(const DustParams& P, int m) {
 // Frame projection (parallel projection, Sect. 2.2): pixel index of r, or -1.
 
 MCRT_HD int frame_pixel(const DetDev& D, const double r[3]) {
-  const double xp = r[0] * D.ex[0] + r[1] * D.ex[1] + r[2] * D.ex[2];
-  const double yp = r[0] * D.ey[0] + r[1] * D.ey[1] + r[2] * D.ey[2];
+  if (D.kind == kDetSed) return 0;  // the whole sky of the observer
+  double xp, yp;
+  if (D.kind == kDetPerspective) {  // central projection through the eye
+    const double d[3] = {r[0] - D.eye[0], r[1] - D.eye[1], r[2] - D.eye[2]};
+    const double z = d[0] * D.kd[0] + d[1] * D.kd[1] + d[2] * D.kd[2];
+    if (!(z > 0.0)) return -1;
+    xp = (d[0] * D.ex[0] + d[1] * D.ex[1] + d[2] * D.ex[2]) / z;
+    yp = (d[0] * D.ey[0] + d[1] * D.ey[1] + d[2] * D.ey[2]) / z;
+  } else {
+    xp = r[0] * D.ex[0] + r[1] * D.ex[1] + r[2] * D.ex[2];
+    yp = r[0] * D.ey[0] + r[1] * D.ey[1] + r[2] * D.ey[2];
+  }
   const double fx = floor((xp + D.half_x) * D.inv_dpx);
   const double fy = floor((yp + D.half_y) * D.inv_dpy);
   if (!(fx >= 0.0 && fx < (double)D.nx && fy >= 0.0 && fy < (double)D.ny)) return -1;
   return (int)fy * D.nx + (int)fx;
+}
+
+// Key pixel of an event at r seen in image pixel pix: pix itself, or for an
+// SED instrument the virtual pixel of its parallel projection (clamped to
+// the virtual grid).
+MCRT_HD int key_pixel(const DetDev& D, const double r[3], int pix) {
+  if (D.kind != kDetSed) return pix;
+  const double xp = r[0] * D.ex[0] + r[1] * D.ex[1] + r[2] * D.ex[2];
+  const double yp = r[0] * D.ey[0] + r[1] * D.ey[1] + r[2] * D.ey[2];
+  const double last = (double)(D.kn - 1);
+  const double fx = fmin(fmax(floor((xp + D.half_x) * D.inv_dpx), 0.0), last);
+  const double fy = fmin(fmax(floor((yp + D.half_y) * D.inv_dpy), 0.0), last);
+  return (int)fy * D.kn + (int)fx;
+}
+
+// Peel-off geometry of instrument D for an event at r: the direction of the
+// peel ray, the 1/distance^2 factor and the length of the walk -- the
+// distant instruments' direction and distance with a walk to the grid's
+// boundary, or for a perspective camera the direction to the eye, its
+// distance and a walk that stops at the eye.
+MCRT_HD void peel_geometry(const DetDev& D, const double r[3], double kd[3], double& inv_d2, double& tmax) {
+  if (D.kind == kDetPerspective) {
+    const double v[3] = {D.eye[0] - r[0], D.eye[1] - r[1], D.eye[2] - r[2]};
+    const double d2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double inv = 1.0 / sqrt(d2);
+    for (int a = 0; a < 3; ++a) kd[a] = v[a] * inv;
+    inv_d2 = inv * inv;
+    tmax = d2 * inv;
+  } else {
+    for (int a = 0; a < 3; ++a) kd[a] = D.kd[a];
+    inv_d2 = D.inv_d2;
+    tmax = INFINITY;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -511,6 +567,7 @@ struct Ray {
   double k[3], tc;  // tree grids only
   int j[3], i[3], s[3];
   R t, tau;
+  R tmax;      // the walk stops here (time from the entry; +inf: at the boundary)
   double tin;  // FP64 entry time (0 for rays starting inside)
   bool active;
 };
@@ -529,13 +586,14 @@ MCRT_HD R rect_tplane(const Ray<R>& ry, const GridDev& G, int a) {
   return (R)((G.qd[a][p] - ry.e[a]) * (double)ry.dt[a]);
 }
 
-// Sets up the walk of o + t k (t >= 0): slab entry for origins outside the
-// grid; cell indices by floor (regular grids) or by search in the plane
-// table (rectilinear grids), with the lower cell for a coordinate on a wall
-// while moving down; rays missing the grid (or with non-finite data) are
-// left inactive with tau = 0.
+// Sets up the walk of o + t k (0 <= t <= tmax): slab entry for origins
+// outside the grid; cell indices by floor (regular grids) or by search in
+// the plane table (rectilinear grids), with the lower cell for a coordinate
+// on a wall while moving down; rays missing the grid (or with non-finite
+// data, or ending before the grid) are left inactive with tau = 0.
 template <typename R, int GK = kGridRegular>
-MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const double k[3]) {
+MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const double k[3],
+                       double tmax = INFINITY) {
   double tin = 0.0, tout = INFINITY;
   int entry = -1;
   bool miss = !(std::isfinite(o[0]) && std::isfinite(o[1]) && std::isfinite(o[2]) && std::isfinite(k[0]) &&
@@ -560,13 +618,14 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const do
     }
   }
   if (par[0] && par[1] && par[2]) miss = true;
-  if (miss || !(tin < tout)) {
+  if (miss || !(tin < tout) || !(tin < tmax)) {
     ry.active = false;
     ry.tau = R(0);
     ry.t = R(0);
     ry.tin = 0.0;
     return;
   }
+  ry.tmax = (R)(tmax - tin);
   if constexpr (GK == kGridTree) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {

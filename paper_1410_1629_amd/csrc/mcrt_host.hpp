@@ -323,19 +323,61 @@ inline int make_grid(const mcrt_grid& g, int elem_bytes, int brick_shape, GridDe
 
 inline int elem_bytes(int precision) { return precision == MCRT_PREC_FP32 ? 4 : 8; }
 
+// Perspective camera axes: w from the eye towards the target, e_y = up made
+// perpendicular to w, e_x = w x e_y; false if they are degenerate.
+inline bool camera_axes(const mcrt_detector& D, double w[3], double ex[3], double ey[3], double* dist) {
+  double n2 = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    w[a] = D.target[a] - D.eye[a];
+    n2 += w[a] * w[a];
+  }
+  if (!(n2 > 0.0) || !finite(n2)) return false;
+  *dist = std::sqrt(n2);
+  for (int a = 0; a < 3; ++a) w[a] /= *dist;
+  const double uw = D.up[0] * w[0] + D.up[1] * w[1] + D.up[2] * w[2];
+  double m2 = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    ey[a] = D.up[a] - uw * w[a];
+    m2 += ey[a] * ey[a];
+  }
+  const double u2 = D.up[0] * D.up[0] + D.up[1] * D.up[1] + D.up[2] * D.up[2];
+  if (!(m2 > 1e-20 * u2) || !finite(m2)) return false;  // up (nearly) along the view axis
+  const double m = std::sqrt(m2);
+  for (int a = 0; a < 3; ++a) ey[a] /= m;
+  ex[0] = w[1] * ey[2] - w[2] * ey[1];
+  ex[1] = w[2] * ey[0] - w[0] * ey[2];
+  ex[2] = w[0] * ey[1] - w[1] * ey[0];
+  return true;
+}
+
 inline int check_detectors(int n_det, const mcrt_detector* dets, bool allow_zero) {
   if (n_det < (allow_zero ? 0 : 1) || n_det > MCRT_MAX_DETECTORS)
     return fail(MCRT_EINVAL, "n_det = %d outside [%d, %d]", n_det, allow_zero ? 0 : 1, MCRT_MAX_DETECTORS);
   if (n_det > 0 && !dets) return fail(MCRT_EINVAL, "detectors is NULL");
   for (int d = 0; d < n_det; ++d) {
     const mcrt_detector& D = dets[d];
-    if (!(D.distance > 0.0) || !finite(D.distance)) return fail(MCRT_EINVAL, "detector %d: distance must be > 0", d);
-    if (!finite(D.incl_deg) || !finite(D.azim_deg) || !finite(D.pa_deg))
-      return fail(MCRT_EINVAL, "detector %d: angles must be finite", d);
+    if (D.kind != MCRT_DET_FRAME && D.kind != MCRT_DET_SED && D.kind != MCRT_DET_PERSPECTIVE)
+      return fail(MCRT_EINVAL, "detector %d: unknown kind %d", d, D.kind);
     if (D.nx < 1 || D.ny < 1 || (long long)D.nx * D.ny > (1ll << 30))
       return fail(MCRT_EINVAL, "detector %d: pixel counts must be >= 1 (at most 2^30 pixels)", d);
-    if (!(D.half_x > 0.0) || !(D.half_y > 0.0) || !finite(D.half_x) || !finite(D.half_y))
+    if (D.kind == MCRT_DET_PERSPECTIVE) {
+      for (int a = 0; a < 3; ++a)
+        if (!finite(D.eye[a]) || !finite(D.target[a]) || !finite(D.up[a]))
+          return fail(MCRT_EINVAL, "detector %d: eye, target and up must be finite", d);
+      double w[3], ex[3], ey[3], dist;
+      if (!camera_axes(D, w, ex, ey, &dist))
+        return fail(MCRT_EINVAL, "detector %d: target must differ from eye and up must not be parallel to the view", d);
+    } else {
+      if (!(D.distance > 0.0) || !finite(D.distance))
+        return fail(MCRT_EINVAL, "detector %d: distance must be > 0", d);
+      if (!finite(D.incl_deg) || !finite(D.azim_deg) || !finite(D.pa_deg))
+        return fail(MCRT_EINVAL, "detector %d: angles must be finite", d);
+    }
+    if (D.kind == MCRT_DET_SED) {
+      if (D.nx != 1 || D.ny != 1) return fail(MCRT_EINVAL, "detector %d: an SED instrument has 1 x 1 pixels", d);
+    } else if (!(D.half_x > 0.0) || !(D.half_y > 0.0) || !finite(D.half_x) || !finite(D.half_y)) {
       return fail(MCRT_EINVAL, "detector %d: half-extents must be > 0", d);
+    }
   }
   return 0;
 }
@@ -359,8 +401,28 @@ inline DetDev make_det(const mcrt_detector& D, long long off) {
   R.inv_d2 = 1.0 / (D.distance * D.distance);
   R.half_x = D.half_x;
   R.half_y = D.half_y;
-  R.inv_dpx = D.nx / (2.0 * D.half_x);
-  R.inv_dpy = D.ny / (2.0 * D.half_y);
+  R.kind = D.kind;
+  for (int a = 0; a < 3; ++a) R.eye[a] = 0.0;
+  if (D.kind == MCRT_DET_PERSPECTIVE) {  // view axis, camera axes, tangents of the half field
+    double w[3], ex[3], ey[3], dist = 1.0;
+    camera_axes(D, w, ex, ey, &dist);
+    for (int a = 0; a < 3; ++a) {
+      R.kd[a] = w[a];
+      R.ex[a] = ex[a];
+      R.ey[a] = ey[a];
+      R.eye[a] = D.eye[a];
+    }
+    R.inv_d2 = 0.0;
+    R.half_x = D.half_x / dist;
+    R.half_y = D.half_y / dist;
+  }
+  R.kn = D.nx;
+  if (D.kind == MCRT_DET_SED) {  // sort keys only: set by sed_key_grid
+    R.half_x = R.half_y = 1.0;
+    R.kn = 1;
+  }
+  R.inv_dpx = R.kn / (2.0 * R.half_x);
+  R.inv_dpy = (D.kind == MCRT_DET_SED ? 1 : D.ny) / (2.0 * R.half_y);
   R.nx = D.nx;
   R.ny = D.ny;
   R.off = off;
@@ -375,6 +437,24 @@ inline DetDev make_det(const mcrt_detector& D, long long off) {
 constexpr long long kSortKeys = 1 << 14;
 constexpr int kSortBlocks = 512;
 
+// Virtual key grid of an SED instrument: kSedKeys x kSedKeys pixels over
+// the parallel projection of the model box, so that its peel rays sort by
+// where they start, as a frame's do.
+constexpr int kSedKeys = 256;
+inline void sed_key_grid(DetDev& D, const GridDev& G) {
+  double hx = 0.0, hy = 0.0;
+  for (int c = 0; c < 8; ++c) {
+    const double p[3] = {(c & 1) ? G.hi[0] : G.lo[0], (c & 2) ? G.hi[1] : G.lo[1], (c & 4) ? G.hi[2] : G.lo[2]};
+    hx = std::max(hx, std::fabs(p[0] * D.ex[0] + p[1] * D.ex[1] + p[2] * D.ex[2]));
+    hy = std::max(hy, std::fabs(p[0] * D.ey[0] + p[1] * D.ey[1] + p[2] * D.ey[2]));
+  }
+  D.kn = kSedKeys;
+  D.half_x = hx > 0.0 ? hx : 1.0;
+  D.half_y = hy > 0.0 ? hy : 1.0;
+  D.inv_dpx = kSedKeys / (2.0 * D.half_x);
+  D.inv_dpy = kSedKeys / (2.0 * D.half_y);
+}
+
 // Sort-key ranges of the frames (tile_key): a Morton index over tiles of
 // 2^tshift x 2^tshift pixels, the frames sharing kSortKeys keys (a power of
 // 4 per frame).  Returns the total number of keys.
@@ -386,7 +466,7 @@ inline long long tile_frames(std::vector<DetDev>& det, int n_det) {
   for (int d = 0; d < n_det; ++d) {
     DetDev& D = det[d];
     int k = 0;
-    while ((1 << k) < std::max(D.nx, D.ny)) ++k;
+    while ((1 << k) < (D.kind == kDetSed ? D.kn : std::max(D.nx, D.ny))) ++k;
     int ts = 0;
     while (2 * (k - ts) > bits) ++ts;
     D.tshift = ts;
@@ -515,6 +595,8 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
   }
   P.pix_lambda = off;
   out.n_images = (long long)P.comps * nl * off;
+  for (int d = 0; d < n_det; ++d)
+    if (out.det[d].kind == kDetSed) sed_key_grid(out.det[d], P.G);
   out.n_keys = tile_frames(out.det, n_det);
   out.src.assign(n_src, SrcDev{});
   for (int s = 0; s < n_src; ++s) {

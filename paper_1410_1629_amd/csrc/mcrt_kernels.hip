@@ -591,7 +591,7 @@ __device__ __forceinline__ void flush_images(bool& has, long long ii, double c, 
 // loads).  Forward: C = v e^-tau goes to the ray's pixel (flush_images).
 // Adjoint: q = (dL/dI) v e^-tau goes to the event scratch, and the job's v
 // becomes the deposit weight -q kappa (0: no deposit walk).
-template <typename R, bool ADJ, int GK>
+template <typename R, bool ADJ, int GK, bool CAM>
 __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2];
   unsigned long long* res = wave_reservoir(slots);
@@ -634,7 +634,13 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
       job = P.perm[qi];
       const PeelJob& J = P.jobs[job];
       kap = (R)P.lam[J.lam].kappa;
-      ray_begin<R, GK>(ry, P.G, J.r, P.det[J.d].kd);
+      if constexpr (CAM) {
+        double kd[3], inv_d2, tmax;
+        peel_geometry(P.det[J.d], J.r, kd, inv_d2, tmax);
+        ray_begin<R, GK>(ry, P.G, J.r, kd, tmax);
+      } else {
+        ray_begin<R, GK>(ry, P.G, J.r, P.det[J.d].kd);
+      }
       pending = true;
     }
     if (!ADJ) flush_images(has, out_ii, out_c, P.images);
@@ -644,7 +650,7 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
     for (;;) {
       const int n_act = __popcll(__ballot(ry.active));
       if (n_act == 0 || n_live - n_act >= P.batch) break;
-      if (ry.active) nx += tau_step<R>(ry, P.G, kap, M);
+      if (ry.active) nx += tau_step<R, decltype(M), CAM>(ry, P.G, kap, M);
     }
   }
   const unsigned long long wsum = wave_sum_u64(nx);
@@ -654,7 +660,7 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
 // The deposit walks of the sorted queue: chunks of consecutive sorted jobs
 // per workgroup, deposits summed per cell in the LDS table, one global
 // atomic per distinct cell and chunk.  Jobs whose weight is 0 are skipped.
-template <typename R, int GK>
+template <typename R, int GK, bool CAM>
 __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams P) {
   __shared__ int tk[kTable];
   __shared__ double tv[kTable];
@@ -688,7 +694,15 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
         }
         const PeelJob& J = P.jobs[P.perm[qi]];
         w = J.v;
-        if (w != 0.0) ray_begin<R, GK>(ry, P.G, J.r, P.det[J.d].kd);
+        if (w != 0.0) {
+          if constexpr (CAM) {
+            double kd[3], inv_d2, tmax;
+            peel_geometry(P.det[J.d], J.r, kd, inv_d2, tmax);
+            ray_begin<R, GK>(ry, P.G, J.r, kd, tmax);
+          } else {
+            ray_begin<R, GK>(ry, P.G, J.r, P.det[J.d].kd);
+          }
+        }
       }
       const unsigned long long live = __ballot(!done);
       if (live == 0ull) break;
@@ -696,7 +710,7 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
       for (;;) {
         const int n_act = __popcll(__ballot(ry.active));
         if (n_act == 0 || n_live - n_act >= P.batch) break;
-        if (ry.active) nd += bp_step<R>(ry, P.G, w, M);
+        if (ry.active) nd += bp_step<R, decltype(M), CAM>(ry, P.G, w, M);
       }
     }
     __syncthreads();
@@ -1034,18 +1048,18 @@ int reset_counters(unsigned long long* ctr, int w, int n, hipStream_t st) {
 
 // The queue's walks: optical depth (and the image, forward), then the
 // adjoint's deposit walks.
-template <typename R, bool ADJ, int GK>
+template <typename R, bool ADJ, int GK, bool CAM>
 int walk_peel_jobs(const PeelJobParams& J, hipStream_t st) {
   int nblk = 0;
-  if (int e = persistent_grid(k_peeltau<R, ADJ, GK>, 0, &nblk)) return e;
-  hipLaunchKernelGGL((k_peeltau<R, ADJ, GK>), dim3(nblk), dim3(kBlock), 0, st, J);
+  if (int e = persistent_grid(k_peeltau<R, ADJ, GK, CAM>, 0, &nblk)) return e;
+  hipLaunchKernelGGL((k_peeltau<R, ADJ, GK, CAM>), dim3(nblk), dim3(kBlock), 0, st, J);
   if (ADJ) {
     int dev = 0, cus = 0, nb = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peeldep<R, GK>, kBundleThreads, 0));
-    hipLaunchKernelGGL((k_peeldep<R, GK>), dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0, st,
-                       J);
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peeldep<R, GK, CAM>, kBundleThreads, 0));
+    hipLaunchKernelGGL((k_peeldep<R, GK, CAM>), dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0,
+                       st, J);
   }
   HIPCHK(hipGetLastError());
   return 0;
@@ -1053,7 +1067,7 @@ int walk_peel_jobs(const PeelJobParams& J, hipStream_t st) {
 
 // Sorts the chunk's queued peel rays by key and walks them.
 template <typename R, bool ADJ>
-int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ctr, hipStream_t st) {
+int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ctr, bool cam, hipStream_t st) {
   const long long n_cnt = q.n_keys * kSortBlocks;
   hipLaunchKernelGGL(k_hist, dim3(kSortBlocks), dim3(kSortThreads), 0, st, q.jobs, ctr, q.cap, (int)q.n_keys,
                      q.counts);
@@ -1084,10 +1098,17 @@ int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ct
   J.n_chunk = P.n_chunk;
   J.ctr = ctr;
   J.batch = 16;
+  if (cam) {  // a perspective instrument: walks that stop at its eye
+    switch (P.G.kind) {
+      case kGridRect: return walk_peel_jobs<R, ADJ, kGridRect, true>(J, st);
+      case kGridTree: return walk_peel_jobs<R, ADJ, kGridTree, true>(J, st);
+      default: return walk_peel_jobs<R, ADJ, kGridRegular, true>(J, st);
+    }
+  }
   switch (P.G.kind) {
-    case kGridRect: return walk_peel_jobs<R, ADJ, kGridRect>(J, st);
-    case kGridTree: return walk_peel_jobs<R, ADJ, kGridTree>(J, st);
-    default: return walk_peel_jobs<R, ADJ, kGridRegular>(J, st);
+    case kGridRect: return walk_peel_jobs<R, ADJ, kGridRect, false>(J, st);
+    case kGridTree: return walk_peel_jobs<R, ADJ, kGridTree, false>(J, st);
+    default: return walk_peel_jobs<R, ADJ, kGridRegular, false>(J, st);
   }
 }
 
@@ -1266,15 +1287,18 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   }
   int rc = 0;
   unsigned long long launches = 0;  // of the life-cycle kernel
+  bool cam = false;                 // a perspective instrument among the frames
+  for (int d = 0; d < n_det; ++d) cam = cam || pr.det[d].kind == kDetPerspective;
   auto queue_phase = [&](bool adj) -> int {  // sort and walk the chunk's queued peel rays
     if (stats) {
       qev.push_back(nullptr);
       HIPCHK(hipEventCreate(&qev.back()));
       HIPCHK(hipEventRecord(qev.back(), st));
     }
-    const int r = adj ? (f32 ? run_peel_jobs<float, true>(queue, P, ctr, st) : run_peel_jobs<double, true>(queue, P, ctr, st))
-                      : (f32 ? run_peel_jobs<float, false>(queue, P, ctr, st)
-                             : run_peel_jobs<double, false>(queue, P, ctr, st));
+    const int r = adj ? (f32 ? run_peel_jobs<float, true>(queue, P, ctr, cam, st)
+                             : run_peel_jobs<double, true>(queue, P, ctr, cam, st))
+                      : (f32 ? run_peel_jobs<float, false>(queue, P, ctr, cam, st)
+                             : run_peel_jobs<double, false>(queue, P, ctr, cam, st));
     if (r) return r;
     if (stats) {
       qev.push_back(nullptr);

@@ -217,9 +217,11 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     // -- end of a peel-off walk: the contribution, then the next frame
     if (L.phase == PH_PEEL_END) {
       const DetDev& D = M.det(L.det);
+      double kd[3], inv_d2, tmax;
+      peel_geometry(D, L.r, kd, inv_d2, tmax);
       const double ph = L.is_emit ? 1.0 / (4.0 * kPi)
-                                  : hg_phase(L.g, L.k[0] * D.kd[0] + L.k[1] * D.kd[1] + L.k[2] * D.kd[2]);
-      const double C = L.W * ph * exp(-(double)L.ry.tau) * D.inv_d2;
+                                  : hg_phase(L.g, L.k[0] * kd[0] + L.k[1] * kd[1] + L.k[2] * kd[2]);
+      const double C = L.W * ph * exp(-(double)L.ry.tau) * inv_d2;
       const int comp = ((P.flags & kFlagSplit) && !L.is_emit) ? 1 : 0;
       const long long ii = ((long long)comp * P.n_lambda + L.lam) * P.pix_lambda + D.off + L.pix;
       if (L.pass == 0) ++L.n_pl;
@@ -316,11 +318,14 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
           const unsigned long long slot = M.job_slot();
           if (slot >= P.job_cap) break;  // queue full: walk it here
           // queued: C = v e^-tau is completed by the queue's walk kernel
+          double kd[3], inv_d2, tmax;
+          peel_geometry(D, L.r, kd, inv_d2, tmax);
           const double ph = L.is_emit ? 1.0 / (4.0 * kPi)
-                                      : hg_phase(L.g, L.k[0] * D.kd[0] + L.k[1] * D.kd[1] + L.k[2] * D.kd[2]);
+                                      : hg_phase(L.g, L.k[0] * kd[0] + L.k[1] * kd[1] + L.k[2] * kd[2]);
           const int comp = ((P.flags & kFlagSplit) && !L.is_emit) ? 1 : 0;
           const long long ii = ((long long)comp * P.n_lambda + L.lam) * P.pix_lambda + D.off + L.pix;
-          M.store_job(slot, L.r, L.W * ph * D.inv_d2, ii, tile_key(D, L.pix), tile_sub(D, L.pix), (unsigned)L.slot,
+          const int kp = key_pixel(D, L.r, L.pix);
+          M.store_job(slot, L.r, L.W * ph * inv_d2, ii, tile_key(D, kp), tile_sub(D, kp), (unsigned)L.slot,
                       L.n < kEventSat ? L.n : kEventSat, L.det,
                       (unsigned)L.lam);
           ++L.n_pl;
@@ -443,8 +448,9 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     // -- set up the chosen walk (a walk that misses the grid ends at once and
     //    its end is handled in the next pass)
     if (want) {
-      const double* d = to_det ? M.det(L.det).kd : L.k;
-      ray_begin<R, Mem::kGrid>(L.ry, G, L.r, d);
+      double kd[3], inv_d2, tmax = INFINITY;
+      if (to_det) peel_geometry(M.det(L.det), L.r, kd, inv_d2, tmax);
+      ray_begin<R, Mem::kGrid>(L.ry, G, L.r, to_det ? kd : L.k, tmax);
       if (L.mode == M_LOCATE) {
         L.last_cell = ray_cell(L.ry, G);
         L.last_t = L.ry.t;
@@ -491,7 +497,7 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
 #pragma unroll
   for (int d = 0; d < kBlockWalk; ++d) {
     if (d >= b.n) break;
-    const R tm = b.tend[d];
+    const R tm = b.tend[d] > ry.tmax ? ry.tmax : b.tend[d];  // a peel walk to a camera stops there
     R seg = tm - ry.t;
     const bool pos = seg > R(0);
     seg = pos ? seg : R(0);
@@ -542,7 +548,7 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
     ry.tau += dtau;
     if (pos) ry.t = tm;
   }
-  if (b.out) ry.active = false;
+  if (b.out || ry.t >= ry.tmax) ry.active = false;
 }
 
 // ---------------------------------------------------------------------------
@@ -551,8 +557,9 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
 // sum -- and bp_step the walk of the inline M_PEEL_DEP mode without density
 // loads (its deposits w l do not depend on the densities); every deposit
 // goes through M.deposit(cell, v).  Each advances the ray by one block and
-// returns its positive-length crossings.
-template <typename R, class Mem>
+// returns its positive-length crossings.  CAM = false compiles out the stop
+// at a camera inside the grid (no perspective instrument in the call).
+template <typename R, class Mem, bool CAM = true>
 MCRT_HD unsigned tau_step(Ray<R>& ry, const GridDev& G, R kap, Mem& M) {
   WalkBlock<kBlockWalk, R> b;
   ray_next_block(ry, b, G, M);
@@ -560,19 +567,20 @@ MCRT_HD unsigned tau_step(Ray<R>& ry, const GridDev& G, R kap, Mem& M) {
 #pragma unroll
   for (int d = 0; d < kBlockWalk; ++d) {
     if (d >= b.n) break;
-    R seg = b.tend[d] - ry.t;
+    const R tm = (CAM && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];
+    R seg = tm - ry.t;
     const bool pos = seg > R(0);
     seg = pos ? seg : R(0);
     const R dtau = kap * b.rho[d] * seg;
     n += pos;
     ry.tau += dtau;
-    if (pos) ry.t = b.tend[d];
+    if (pos) ry.t = tm;
   }
-  if (b.out) ry.active = false;
+  if (b.out || (CAM && ry.t >= ry.tmax)) ry.active = false;
   return n;
 }
 
-template <typename R, class Mem>
+template <typename R, class Mem, bool CAM = true>
 MCRT_HD unsigned bp_step(Ray<R>& ry, const GridDev& G, double w, Mem& M) {
   WalkBlock<kBlockWalk, R> b;
   ray_next_block<kBlockWalk, R, Mem, false>(ry, b, G, M);
@@ -580,14 +588,15 @@ MCRT_HD unsigned bp_step(Ray<R>& ry, const GridDev& G, double w, Mem& M) {
 #pragma unroll
   for (int d = 0; d < kBlockWalk; ++d) {
     if (d >= b.n) break;
-    const R seg = b.tend[d] - ry.t;
+    const R tm = (CAM && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];
+    const R seg = tm - ry.t;
     if (seg > R(0)) {
       M.deposit(b.cell[d], w * (double)seg);
       ++n;
-      ry.t = b.tend[d];
+      ry.t = tm;
     }
   }
-  if (b.out) ry.active = false;
+  if (b.out || (CAM && ry.t >= ry.tmax)) ry.active = false;
   return n;
 }
 
@@ -715,10 +724,12 @@ MCRT_HD void peel_events(PeelLane<R>& L, const PeelParams& P, Mem& M) {
   while (!L.ry.active && !L.done) {
     if (L.pending) {
       const DetDev& D = M.det(L.d);
-      double kin[3];
+      double r[3], kd[3], inv_d2, tmax, kin[3];
+      M.position(L.e, r);
+      peel_geometry(D, r, kd, inv_d2, tmax);
       double ph = 1.0 / (4.0 * kPi);
-      if (M.dir_in(L.e, kin)) ph = hg_phase(P.g, kin[0] * D.kd[0] + kin[1] * D.kd[1] + kin[2] * D.kd[2]);
-      M.add_image(D.off + L.pix, M.weight(L.e) * ph * exp(-(double)L.ry.tau) * D.inv_d2);
+      if (M.dir_in(L.e, kin)) ph = hg_phase(P.g, kin[0] * kd[0] + kin[1] * kd[1] + kin[2] * kd[2]);
+      M.add_image(D.off + L.pix, M.weight(L.e) * ph * exp(-(double)L.ry.tau) * inv_d2);
       L.pending = false;
     }
     const unsigned long long item = M.fetch();
@@ -733,7 +744,9 @@ MCRT_HD void peel_events(PeelLane<R>& L, const PeelParams& P, Mem& M) {
     L.pix = frame_pixel(M.det(L.d), r);
     if (L.pix < 0) continue;
     L.pending = true;
-    ray_begin<R, Mem::kGrid>(L.ry, P.G, r, M.det(L.d).kd);
+    double kd[3], inv_d2, tmax;
+    peel_geometry(M.det(L.d), r, kd, inv_d2, tmax);
+    ray_begin<R, Mem::kGrid>(L.ry, P.G, r, kd, tmax);
   }
 }
 
@@ -746,13 +759,14 @@ MCRT_HD void peel_step(PeelLane<R>& L, const PeelParams& P, Mem& M) {
 #pragma unroll
   for (int d = 0; d < kBlockWalk; ++d) {
     if (d >= b.n) break;
-    R seg = b.tend[d] - ry.t;
+    const R tm = b.tend[d] > ry.tmax ? ry.tmax : b.tend[d];
+    R seg = tm - ry.t;
     const bool pos = seg > R(0);
     seg = pos ? seg : R(0);
-    if (pos) ry.t = b.tend[d];
+    if (pos) ry.t = tm;
     ry.tau += kap * b.rho[d] * seg;
   }
-  if (b.out) ry.active = false;
+  if (b.out || ry.t >= ry.tmax) ry.active = false;
 }
 
 }  // namespace mcrt

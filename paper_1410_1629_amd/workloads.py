@@ -13,7 +13,9 @@ Problem dict keys:
   float32-representable), kappa / albedo / g (one value per wavelength),
   sources [{kind, pos, h_r, h_z, lum[n_lambda]}] (kind "cells": the grid's
   cells emit cell_lum[n_lambda][ncell], e.g. dust emission),
-  detectors [{distance, incl, azim, pa, nx, ny, half_x, half_y}],
+  detectors [{distance, incl, azim, pa, nx, ny, half_x, half_y}] (frames;
+  kind "sed": the distant observer's total flux, nx = ny = 1; kind
+  "perspective": a camera with eye, target, up, nx, ny, half_x, half_y),
   n_packages, first_package, seed, w_min, max_scatter, flags,
   precision (0: FP64 path; 1: FP32 traversal with FP64 state and tallies).
 
@@ -499,6 +501,21 @@ def dust_problem(stellar, emission, n_packages=None, flags=FLAG_PEEL_EMIT | FLAG
         p["n_packages"] = int(n_packages)
     p["name"] = stellar["name"] + "_dust"
     return p
+
+
+def sed(distance, incl, azim=-90.0):
+    """SED instrument: the total flux per wavelength seen by a distant
+    observer in the direction (incl, azim)."""
+    return {"kind": "sed", "distance": float(distance), "incl": float(incl), "azim": float(azim), "pa": 0.0,
+            "nx": 1, "ny": 1, "half_x": 1.0, "half_y": 1.0}
+
+
+def perspective(eye, target, up, nx, ny, half_x, half_y):
+    """Perspective camera at `eye` looking at `target`, image y along `up`;
+    nx x ny pixels over +-half_x x +-half_y of the plane through target."""
+    return {"kind": "perspective", "eye": tuple(float(v) for v in eye), "target": tuple(float(v) for v in target),
+            "up": tuple(float(v) for v in up), "nx": int(nx), "ny": int(ny), "half_x": float(half_x),
+            "half_y": float(half_y)}
 
 
 def frame(distance, incl, nx, ny, half_x, half_y, azim=-90.0, pa=0.0):

@@ -333,7 +333,11 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, GK>& M, const RunParams& P, std:
     while (d + 1 < P.n_det && (unsigned)M.det(d + 1).key_off <= J.key) ++d;
     EMU_CHECK(d == J.d, "job frame against its key", J.d, P.n_det);
     Ray<R> ry;
-    ray_begin<R, GK>(ry, P.G, J.r, M.det(J.d).kd);
+    {
+      double kd[3], inv_d2, tmax;
+      peel_geometry(M.det(J.d), J.r, kd, inv_d2, tmax);
+      ray_begin<R, GK>(ry, P.G, J.r, kd, tmax);
+    }
     const R kap = (R)M.lam((int)J.lam).kappa;
     long long steps = 0;
     while (ry.active) {
@@ -352,7 +356,11 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, GK>& M, const RunParams& P, std:
       M.ev_add_beyond((int)J.slot, q);
     if (q == 0.0) continue;
     const double w = -q * M.lam((int)J.lam).kappa;
-    ray_begin<R, GK>(ry, P.G, J.r, M.det(J.d).kd);
+    {
+      double kd[3], inv_d2, tmax;
+      peel_geometry(M.det(J.d), J.r, kd, inv_d2, tmax);
+      ray_begin<R, GK>(ry, P.G, J.r, kd, tmax);
+    }
     steps = 0;
     while (ry.active) {
       const unsigned n = bp_step<R>(ry, P.G, w, D);

@@ -178,6 +178,30 @@ def test_invalid_arguments_are_rejected(lib, B, W, case):
     assert lib.mcrt_last_error().decode(), case
 
 
+@pytest.mark.parametrize("case", ["kind", "sed_pixels", "eye_is_target", "up_along_view", "eye_nan", "persp_extent"])
+def test_invalid_instruments_are_rejected(lib, B, W, case):
+    prob = W.small_problem(n=(4, 4, 4), n_packages=100)
+    if case == "sed_pixels":
+        prob["detectors"] = [dict(W.sed(10.0, 30.0), nx=2)]
+    elif case == "eye_is_target":
+        prob["detectors"] = [W.perspective((0.5, 0.5, 0.5), (0.5, 0.5, 0.5), (0, 0, 1), 4, 4, 1.0, 1.0)]
+    elif case == "up_along_view":
+        prob["detectors"] = [W.perspective((0, 0, 3), (0, 0, 0), (0, 0, 2), 4, 4, 1.0, 1.0)]
+    elif case == "eye_nan":
+        prob["detectors"] = [W.perspective((0, np.nan, 3), (0, 0, 0), (0, 1, 0), 4, 4, 1.0, 1.0)]
+    elif case == "persp_extent":
+        prob["detectors"] = [W.perspective((0, 0, 3), (0, 0, 0), (0, 1, 0), 4, 4, 0.0, 1.0)]
+    pr = B._Problem(prob)
+    if case == "kind":
+        pr.detectors[0].kind = 7
+    st = B.Stats()
+    fake = C.c_void_p(0x1000)
+    rc = lib.run_photons(C.byref(pr.grid), fake, C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det,
+                         pr.detectors, C.byref(pr.opts), fake, fake, C.byref(st), None)
+    assert rc == B.EINVAL, case
+    assert "detector 0" in lib.mcrt_last_error().decode(), case
+
+
 @pytest.mark.parametrize("case", ["cell_lum_null", "two_cell_sources"])
 def test_invalid_cell_sources_are_rejected(lib, B, W, case):
     prob = W.small_problem(n=(4, 4, 4), n_packages=100)
