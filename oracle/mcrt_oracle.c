@@ -530,6 +530,10 @@ static double hg_phase(double g, double mu)
 }
 
 /* Inverse-CDF sample of the HG scattering cosine; isotropic below |g| 1e-6. */
+/* d ln Phi / dg of the HG phase function at cosine mu:
+ * -2g / (1 - g^2) - 3 (g - mu) / (1 + g^2 - 2 g mu). */
+static double hg_dlng(double g, double mu) { return -2.0 * g / (1.0 - g * g) - 3.0 * (g - mu) / (1.0 + g * g - 2.0 * g * mu); }
+
 double oracle_hg_mu(double g, double u)
 {
     if (fabs(g) < 1e-6) return 2.0 * u - 1.0;
@@ -681,12 +685,17 @@ typedef struct {
     unsigned flags;
     int mode;
     const double *adj; /* GRAD: dL/dI, same layout as the images */
+    /* REWEIGHT: albedo [n_lambda], g [n_lambda] and source luminosities
+     * [n_src][n_lambda] at which weights are evaluated (NULL: the sampling
+     * values) */
+    const double *alb_eval, *g_eval, *lum_eval;
 } problem_t;
 
 /* One recorded peel-off contribution (GRAD mode). */
 typedef struct {
     int event;    /* 0 = emission, i >= 1 = scattering i */
     double a_c;   /* dL/dI at the pixel times the contribution */
+    double dlng;  /* d ln(contribution) / dg: scores of the sampled directions and the peel phase */
     size_t beg, end; /* peel segments inside the peel buffer */
 } contrib_t;
 
@@ -695,6 +704,7 @@ typedef struct {
     double *absorbed; /* [ncell] slice of the current wavelength, or NULL */
     double *grad;     /* [ncell] or NULL */
     double stats[ST_N];
+    double gopt[2 + MAX_SRC]; /* GRAD: dL/d albedo, dL/d g, dL/d L_s of the current wavelength */
     segbuf path, peel, legs, gpeel;
     /* GRAD bookkeeping of the current package */
     size_t *leg_beg, *leg_end;
@@ -738,7 +748,7 @@ static contrib_t *grad_new_contrib(accum_t *A)
  * w_eval / rho_eval: REWEIGHT mode evaluates the contribution at another
  * density along the same geometry. */
 static void peel_event(const problem_t *P, accum_t *A, int l, int event, const double r[3],
-                       const double *k_in, double w, double w_eval)
+                       const double *k_in, double w, double w_eval, double score)
 {
     int comp = (P->flags & FLAG_SPLIT) && event > 0 ? 1 : 0;
     double kappa = P->kappa[l], g = P->g[l];
@@ -757,7 +767,9 @@ static void peel_event(const problem_t *P, accum_t *A, int l, int event, const d
         size_t ii = image_index(P, comp, l, d, pix);
         if (P->mode == MODE_REWEIGHT) {
             double tau = seg_tau(&A->peel, P->rho_eval, kappa);
-            A->images[ii] += w_eval * phase * exp(-tau) * inv_d2;
+            double phase_eval = phase;
+            if (k_in && P->g_eval) phase_eval = hg_phase(P->g_eval[l], k_in[0] * kd[0] + k_in[1] * kd[1] + k_in[2] * kd[2]);
+            A->images[ii] += w_eval * phase_eval * exp(-tau) * inv_d2;
         } else {
             double tau = seg_tau(&A->peel, P->rho, kappa);
             double c = w * phase * exp(-tau) * inv_d2;
@@ -766,6 +778,7 @@ static void peel_event(const problem_t *P, accum_t *A, int l, int event, const d
                 contrib_t *C = grad_new_contrib(A);
                 C->event = event;
                 C->a_c = P->adj[ii] * c;
+                C->dlng = k_in ? score + hg_dlng(g, k_in[0] * kd[0] + k_in[1] * kd[1] + k_in[2] * kd[2]) : 0.0;
                 C->beg = A->gpeel.n;
                 for (size_t j = 0; j < A->peel.n; j++)
                     sb_push(&A->gpeel, A->peel.v[j].cell, A->peel.v[j].t0, A->peel.v[j].t1);
@@ -788,12 +801,18 @@ static void peel_event(const problem_t *P, accum_t *A, int l, int event, const d
  * out plainly, without the suffix-sum reorganisation the GPU uses.
  * Check: finite differences of the reweighted estimator, and the closed form
  * for a non-scattering medium. */
-static void grad_flush_package(const problem_t *P, accum_t *A, int l)
+static void grad_flush_package(const problem_t *P, accum_t *A, int l, int src)
 {
-    double kappa = P->kappa[l];
+    double kappa = P->kappa[l], alb = P->albedo[l], lum = P->lum[(size_t)src * P->n_lambda + l];
     for (int q = 0; q < A->ncon; q++) {
         const contrib_t *C = &A->con[q];
         if (C->a_c == 0.0) continue;
+        /* optics and luminosity: a contribution after n scatterings scales as
+         * albedo^n, with the scores of its sampled directions and its peel
+         * phase in g, and as the luminosity of its package's source */
+        if (alb > 0.0) A->gopt[0] += C->a_c * C->event / alb;
+        A->gopt[1] += C->a_c * C->dlng;
+        if (lum > 0.0) A->gopt[2 + src] += C->a_c / lum;
         for (int i = 1; i <= C->event; i++) {
             int64_t c = A->leg_cell[i];
             A->grad[c] += C->a_c / P->rho[c];
@@ -863,7 +882,9 @@ static void run_package(const problem_t *P, accum_t *A, uint64_t p, int l)
         else
             oracle_emit_position(S->kind, par, u, r);
     }
-    double w = w0, w_eval = w0;
+    double w = w0, w_eval = w0, score = 0.0;
+    if (P->mode == MODE_REWEIGHT && P->lum_eval)
+        w_eval = w0 * P->lum_eval[(size_t)sidx * P->n_lambda + l] / P->lum[(size_t)sidx * P->n_lambda + l];
     A->stats[ST_EMITTED] += w0;
     A->stats[ST_PACKAGES] += 1.0;
 
@@ -875,7 +896,7 @@ static void run_package(const problem_t *P, accum_t *A, uint64_t p, int l)
     }
 
     /* 2. peel-off at emission */
-    if (P->flags & FLAG_PEEL_EMIT) peel_event(P, A, l, 0, r, NULL, w, w_eval);
+    if (P->flags & FLAG_PEEL_EMIT) peel_event(P, A, l, 0, r, NULL, w, w_eval, 0.0);
 
     /* 3. scattering loop */
     for (int n = 0;; n++) {
@@ -943,13 +964,14 @@ static void run_package(const problem_t *P, accum_t *A, uint64_t p, int l)
                 dtau_leg += kappa * (P->rho_eval[s->cell] - P->rho[s->cell]) * (s->t1 - s->t0);
             }
             dtau_leg += kappa * (P->rho_eval[c_hit] - P->rho[c_hit]) * (s_hit - A->path.v[j_hit].t0);
-            w_eval *= alb * (-expm1(-T)) * (P->rho_eval[c_hit] / P->rho[c_hit]) * exp(-dtau_leg);
+            w_eval *= (P->alb_eval ? P->alb_eval[l] : alb) * (-expm1(-T)) * (P->rho_eval[c_hit] / P->rho[c_hit]) *
+                      exp(-dtau_leg);
         }
 
         for (int a = 0; a < 3; a++) r[a] += s_hit * k[a];
         w *= alb * (-expm1(-T));
 
-        if (P->flags & FLAG_PEEL_SCAT) peel_event(P, A, l, n + 1, r, k, w, w_eval);
+        if (P->flags & FLAG_PEEL_SCAT) peel_event(P, A, l, n + 1, r, k, w, w_eval, score);
 
         if (w < P->w_min * w0 || n + 1 >= P->max_scatter) {
             A->stats[ST_TRUNCATED] += w;
@@ -957,6 +979,8 @@ static void run_package(const problem_t *P, accum_t *A, uint64_t p, int l)
         }
         /* new direction: HG polar cosine and uniform azimuth */
         double mu = oracle_hg_mu(g, u[1]);
+        score += hg_dlng(g, mu);
+        if (P->mode == MODE_REWEIGHT && P->g_eval) w_eval *= hg_phase(P->g_eval[l], mu) / hg_phase(g, mu);
         double psi = 2.0 * OR_PI * u[2];
         double kn[3];
         oracle_rotate(k, mu, psi, kn);
@@ -965,7 +989,7 @@ static void run_package(const problem_t *P, accum_t *A, uint64_t p, int l)
         k[2] = kn[2];
     }
 
-    if (P->mode == MODE_GRAD) grad_flush_package(P, A, l);
+    if (P->mode == MODE_GRAD) grad_flush_package(P, A, l, sidx);
 }
 
 static void accum_free(accum_t *A)
@@ -1057,7 +1081,8 @@ static void problem_free(problem_t *P)
 /* Runs packages [first, first + n_pkg) for every wavelength.  Each thread
  * works on its own accumulators; the wavelength slices are summed in thread
  * order afterwards, so a single thread gives the plain serial sums. */
-static int simulate(problem_t *P, double *images, double *absorbed, double *grad, double stats[ST_N], int n_threads)
+static int simulate(problem_t *P, double *images, double *absorbed, double *grad, double *grad_opt, double stats[ST_N],
+                    int n_threads)
 {
     int comps = (P->flags & FLAG_SPLIT) ? 2 : 1;
     size_t nimg = (size_t)comps * P->n_lambda * P->pix_lambda;
@@ -1065,6 +1090,7 @@ static int simulate(problem_t *P, double *images, double *absorbed, double *grad
     memset(images, 0, nimg * sizeof(double));
     if (absorbed) memset(absorbed, 0, (size_t)P->n_lambda * ncell * sizeof(double));
     if (grad) memset(grad, 0, (size_t)ncell * sizeof(double));
+    if (grad_opt) memset(grad_opt, 0, (size_t)(2 + P->n_src) * P->n_lambda * sizeof(double));
     for (int i = 0; i < ST_N; i++) stats[i] = 0.0;
     if (n_threads < 1) n_threads = 1;
 
@@ -1091,6 +1117,8 @@ static int simulate(problem_t *P, double *images, double *absorbed, double *grad
             if (grad)
                 for (int64_t m = 0; m < ncell; m++) grad[m] += acc[t].grad[m];
             for (int i = 0; i < ST_N; i++) stats[i] += acc[t].stats[i];
+            if (grad_opt)
+                for (int i = 0; i < 2 + P->n_src; i++) grad_opt[(size_t)i * P->n_lambda + l] += acc[t].gopt[i];
             free(acc[t].images);
             free(acc[t].absorbed);
             free(acc[t].grad);
@@ -1131,20 +1159,30 @@ int oracle_run(const double box[6], const int n[3], const double *rho, int n_lam
                       det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes, tree, cell_lum))
         return -1;
     P.mode = MODE_FORWARD;
-    int rc = simulate(&P, images, (flags & FLAG_ABSORB) ? absorbed : NULL, NULL, stats, n_threads);
+    int rc = simulate(&P, images, (flags & FLAG_ABSORB) ? absorbed : NULL, NULL, NULL, stats, n_threads);
     problem_free(&P);
     return rc;
 }
 
 /* Gradient of L with respect to every cell density, given adj = dL/dI in
  * the image layout of oracle_run with the same flags.  Also returns the
- * images of the same run. */
+ * images of the same run, and (grad_opt non-NULL, [2 + n_src][n_lambda])
+ * the gradients with respect to the albedo, g and each source's luminosity
+ * per wavelength.  Reading: the same detached derivative with paths held
+ * fixed.  A contribution after n scatterings scales as albedo^n
+ * (d/dalbedo = n C / albedo; reported 0 at albedo = 0); in g it carries
+ * the log-derivative of the HG density of each direction sampled before it
+ * and of its peel phase (the scores of a fixed path); and it scales as the
+ * luminosity of its package's source (weight L_total / N times choice
+ * probability L_s / L_total; d/dL_s = C / L_s, reported 0 for a dark
+ * source).  Check: finite differences of the reweighted estimator in each
+ * parameter, and the linear cases (one scattering at most; one source). */
 int oracle_grad(const double box[6], const int n[3], const double *rho, int n_lambda, const double *kappa,
                 const double *albedo, const double *g, int n_src, const int *src_kind, const double *src_par,
                 const double *src_lum, int n_det, const double *det_par, const int *det_pix, uint64_t n_pkg,
                 uint64_t first, uint64_t seed, double w_min, int max_scatter, unsigned flags, const double *adj,
                 double *images, double *grad, double *stats, int n_threads, const double *planes,
-                const double *tree, const double *cell_lum)
+                const double *tree, const double *cell_lum, double *grad_opt)
 {
     problem_t P;
     if (setup_problem(&P, box, n, rho, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
@@ -1152,20 +1190,25 @@ int oracle_grad(const double box[6], const int n[3], const double *rho, int n_la
         return -1;
     P.mode = MODE_GRAD;
     P.adj = adj;
-    int rc = simulate(&P, images, NULL, grad, stats, n_threads);
+    int rc = simulate(&P, images, NULL, grad, grad_opt, stats, n_threads);
     problem_free(&P);
     return rc;
 }
 
 /* Images of the estimator whose paths are sampled at rho0 and whose weights
  * are evaluated at rho (reweighting; a smooth function of rho whose
- * derivative at rho = rho0 is oracle_grad). */
+ * derivative at rho = rho0 is oracle_grad); likewise at the albedos, g and
+ * source luminosities alb_eval, g_eval, lum_eval when given (NULL: the
+ * sampling values): weights carry (albedo_eval)^n, the ratios of the HG
+ * densities of the sampled directions and the peel phase at g_eval, and
+ * the ratio of the package source's luminosities. */
 int oracle_reweight(const double box[6], const int n[3], const double *rho0, const double *rho, int n_lambda,
                     const double *kappa, const double *albedo, const double *g, int n_src, const int *src_kind,
                     const double *src_par, const double *src_lum, int n_det, const double *det_par,
                     const int *det_pix, uint64_t n_pkg, uint64_t first, uint64_t seed, double w_min,
                     int max_scatter, unsigned flags, double *images, double *stats, int n_threads,
-                    const double *planes, const double *tree, const double *cell_lum)
+                    const double *planes, const double *tree, const double *cell_lum, const double *alb_eval,
+                    const double *g_eval, const double *lum_eval)
 {
     problem_t P;
     if (setup_problem(&P, box, n, rho0, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
@@ -1173,7 +1216,10 @@ int oracle_reweight(const double box[6], const int n[3], const double *rho0, con
         return -1;
     P.mode = MODE_REWEIGHT;
     P.rho_eval = rho;
-    int rc = simulate(&P, images, NULL, NULL, stats, n_threads);
+    P.alb_eval = alb_eval;
+    P.g_eval = g_eval;
+    P.lum_eval = lum_eval;
+    int rc = simulate(&P, images, NULL, NULL, NULL, stats, n_threads);
     problem_free(&P);
     return rc;
 }

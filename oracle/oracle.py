@@ -55,10 +55,10 @@ def _load():
         common = [P, P, P, i, P, P, P, i, P, P, P, i, P, P, u64, u64, u64, d, i, C.c_uint]
         _lib.oracle_run.argtypes = common + [P, P, P, i, P, P, P]
         _lib.oracle_run.restype = i
-        _lib.oracle_grad.argtypes = common + [P, P, P, P, i, P, P, P]
+        _lib.oracle_grad.argtypes = common + [P, P, P, P, i, P, P, P, P]
         _lib.oracle_grad.restype = i
         _lib.oracle_reweight.argtypes = [P, P, P, P, i, P, P, P, i, P, P, P, i, P, P, u64, u64, u64, d, i,
-                                         C.c_uint, P, P, i, P, P, P]
+                                         C.c_uint, P, P, i, P, P, P, P, P, P]
         _lib.oracle_reweight.restype = i
         _lib.oracle_trace.argtypes = [P, P, P, d, i64, P, P, P, i, P, P, P, P, P]
         _lib.oracle_trace.restype = i64
@@ -225,31 +225,42 @@ def run(prob, threads=1):
     return images, absorbed, dict(zip(STAT_NAMES, stats.tolist()))
 
 
-def grad(prob, adj, threads=1):
-    """Detached gradient dL/drho for dL/dI = adj (same layout as the images)."""
+def grad(prob, adj, threads=1, optics=False):
+    """Detached gradient dL/drho for dL/dI = adj (same layout as the images).
+    optics=True also returns {"albedo": [n_lambda], "g": [n_lambda],
+    "lum": [n_src][n_lambda]} as a fourth value."""
     args, keep, nl, npix = _marshal(prob)
     ncell = keep[2].size
     adj = _f64(adj).reshape(_comps(prob), nl, npix)
     images = np.zeros((_comps(prob), nl, npix))
     g = np.zeros(ncell)
     stats = np.zeros(len(STAT_NAMES))
+    n_src = len(prob["sources"])
+    gopt = np.zeros((2 + n_src, nl)) if optics else None
     rc = _load().oracle_grad(*args, _ptr(adj), _ptr(images), _ptr(g), _ptr(stats), int(threads), _ptr(keep[11]),
-                            _ptr(keep[12]), _ptr(keep[13]))
+                            _ptr(keep[12]), _ptr(keep[13]), _ptr(gopt))
     if rc != 0:
         raise ValueError("oracle_grad rejected its arguments")
+    if optics:
+        return g, images, dict(zip(STAT_NAMES, stats.tolist())), {"albedo": gopt[0], "g": gopt[1], "lum": gopt[2:]}
     return g, images, dict(zip(STAT_NAMES, stats.tolist()))
 
 
-def reweight(prob, rho_eval, threads=1):
-    """Images of paths sampled at prob['rho'] with weights evaluated at rho_eval."""
+def reweight(prob, rho_eval, threads=1, albedo_eval=None, g_eval=None, lum_eval=None):
+    """Images of paths sampled at prob's parameters with weights evaluated at
+    rho_eval (and at albedo_eval, g_eval [n_lambda], lum_eval [n_src][n_lambda]
+    when given)."""
     args, keep, nl, npix = _marshal(prob)
     rho_eval = _f64(rho_eval).reshape(-1)
     assert rho_eval.size == keep[2].size
     images = np.zeros((_comps(prob), nl, npix))
     stats = np.zeros(len(STAT_NAMES))
     a = args[:3] + [_ptr(rho_eval)] + args[3:]
+    ae = None if albedo_eval is None else _f64(albedo_eval).reshape(nl)
+    ge = None if g_eval is None else _f64(g_eval).reshape(nl)
+    le = None if lum_eval is None else _f64(lum_eval).reshape(len(prob["sources"]), nl)
     rc = _load().oracle_reweight(*a, _ptr(images), _ptr(stats), int(threads), _ptr(keep[11]),
-                            _ptr(keep[12]), _ptr(keep[13]))
+                                 _ptr(keep[12]), _ptr(keep[13]), _ptr(ae), _ptr(ge), _ptr(le))
     if rc != 0:
         raise ValueError("oracle_reweight rejected its arguments")
     return images, dict(zip(STAT_NAMES, stats.tolist()))
