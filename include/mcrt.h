@@ -298,6 +298,29 @@ int backward_density(const mcrt_grid *grid, const void *rho_dev, const mcrt_opti
                      const double *adj_images_dev, double *grad_rho_dev, mcrt_stats *stats_host,
                      void *hip_stream);
 
+/* Gradients of the same image loss with respect to the densities and to
+ * the optical properties and source luminosities of every wavelength
+ * (Sect. 2.3: albedo and g; Sect. 2.2: luminosities), in one replay.  The
+ * same detached derivative with paths held fixed: a contribution C after n
+ * scatterings scales as albedo^n, so dC/dalbedo = n C / albedo; in g it
+ * carries the score of every direction sampled before it and of its peel
+ * phase, dC/dg = C [sum_i dln Phi(mu_i)/dg + dln Phi(mu_peel)/dg] with
+ * dln Phi/dg = -2g/(1 - g^2) - 3(g - mu)/(1 + g^2 - 2 g mu) for HG; and it
+ * scales as the luminosity of its package's source (weight L_total / N
+ * times choice probability L_s / L_total), dC/dL_s = C / L_s for packages
+ * of source s (a cell source: L_s is its total, the derivative that of a
+ * uniform scaling of its cells).  Derivatives at albedo = 0 or at a dark
+ * source are reported as 0 (no contribution carries them).  Device FP64
+ * outputs, each overwritten, each NULL when not wanted:
+ *   rho [ncell], albedo [n_lambda], g [n_lambda], lum [n_src][n_lambda]. */
+typedef struct {
+    double *rho, *albedo, *g, *lum;
+} mcrt_grads;
+
+int backward(const mcrt_grid *grid, const void *rho_dev, const mcrt_optics *optics, int n_src,
+             const mcrt_source *sources, int n_det, const mcrt_detector *detectors, const mcrt_opts *opts,
+             const double *adj_images_dev, const mcrt_grads *grads, mcrt_stats *stats_host, void *hip_stream);
+
 /* Dust emission (Sect. 1: absorption and re-emission by the dust; Sect. 2.1:
  * panchromatic simulations): the equilibrium temperature and the emission
  * spectrum of every cell from the luminosity it absorbed.  The grains are
@@ -331,7 +354,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 11
+#define MCRT_ABI_VERSION 12
 
 #ifdef __cplusplus
 }

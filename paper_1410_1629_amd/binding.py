@@ -68,6 +68,10 @@ def brick(lx, ly, lz):
     return 0x1000 | lx | (ly << 4) | (lz << 8)
 
 
+class Grads(C.Structure):
+    _fields_ = [("rho", C.c_void_p), ("albedo", C.c_void_p), ("g", C.c_void_p), ("lum", C.c_void_p)]
+
+
 class Stats(C.Structure):
     _fields_ = [("emitted", C.c_double), ("absorbed", C.c_double), ("escaped", C.c_double),
                 ("truncated", C.c_double), ("x_path", C.c_uint64), ("x_locate", C.c_uint64),
@@ -83,9 +87,9 @@ class Stats(C.Structure):
 _lib = None
 
 # Exported symbols of include/mcrt.h.
-ABI_VERSION = 11  # MCRT_ABI_VERSION of the header these structs follow
-SYMBOLS = ("run_photons", "trace_path", "peel_off", "backward_density", "dust_emission", "mcrt_last_error",
-           "mcrt_abi_version")
+ABI_VERSION = 12  # MCRT_ABI_VERSION of the header these structs follow
+SYMBOLS = ("run_photons", "trace_path", "peel_off", "backward_density", "backward", "dust_emission",
+           "mcrt_last_error", "mcrt_abi_version")
 
 
 def load():
@@ -109,6 +113,9 @@ def load():
     lib.trace_path.restype = C.c_int
     lib.peel_off.argtypes = [C.POINTER(Grid), P, d, d, C.c_int, i64, P, P, P, C.c_int, C.POINTER(Detector), P, P]
     lib.peel_off.restype = C.c_int
+    lib.backward.argtypes = [C.POINTER(Grid), P, C.POINTER(Optics), C.c_int, C.POINTER(Source), C.c_int,
+                             C.POINTER(Detector), C.POINTER(Opts), P, C.POINTER(Grads), C.POINTER(Stats), P]
+    lib.backward.restype = C.c_int
     lib.dust_emission.argtypes = [C.POINTER(Grid), P, C.c_int, C.c_int, P, C.c_int, C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), C.POINTER(C.c_double), d, P, P, P]
     lib.dust_emission.restype = C.c_int
@@ -283,6 +290,22 @@ def backward_density(prob, rho, adj_images, grad_rho, stats=True, stream=None, *
     _check(lib.backward_density(C.byref(pr.grid), _ptr(rho), C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det,
                                 pr.detectors, C.byref(pr.opts), _ptr(adj_images), _ptr(grad_rho),
                                 C.byref(st) if stats else None, _stream(stream)))
+    return st.as_dict() if stats else None
+
+
+def backward(prob, rho, adj_images, grad_rho=None, grad_albedo=None, grad_g=None, grad_lum=None, stats=True,
+             stream=None, **overrides):
+    """backward: the gradients of the image loss with dL/dI = adj_images with
+    respect to the densities (device FP64 [ncell]), the albedo and g
+    ([n_lambda]) and the source luminosities ([n_src][n_lambda]); each
+    output is a device FP64 tensor or None (not computed)."""
+    lib = load()
+    pr = _Problem(prob, **overrides)
+    st = Stats()
+    g = Grads(_ptr(grad_rho), _ptr(grad_albedo), _ptr(grad_g), _ptr(grad_lum))
+    _check(lib.backward(C.byref(pr.grid), _ptr(rho), C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det,
+                        pr.detectors, C.byref(pr.opts), _ptr(adj_images), C.byref(g), C.byref(st) if stats else None,
+                        _stream(stream)))
     return st.as_dict() if stats else None
 
 

@@ -493,6 +493,27 @@ MCRT_HD int frame_pixel(const DetDev& D, const double r[3]) {
   return (int)fy * D.nx + (int)fx;
 }
 
+// d ln Phi / dg of the Henyey-Greenstein phase function at cosine mu (the
+// score in g of a direction drawn from it).
+MCRT_HD double hg_dlng(double g, double mu) {
+  return -2.0 * g / (1.0 - g * g) - 3.0 * (g - mu) / (1.0 + g * g - 2.0 * g * mu);
+}
+
+// The optics and luminosity gradients of wavelength l from the pass-B sums
+// of its packages (sum q n, sum q score, sum q per source): dL/dalbedo =
+// sum q n / albedo, dL/dg = sum q score, dL/dL_s = sum_{source s} q / L_s
+// (0 where albedo or L_s is 0).
+MCRT_HD void optics_finish(double sa, double sg, const double* sl, int n_src, double albedo, const double* lum_l,
+                           long long lum_stride, double* g_alb, double* g_g, double* g_lum, int l, int nl) {
+  if (g_alb) g_alb[l] += albedo > 0.0 ? sa / albedo : 0.0;
+  if (g_g) g_g[l] += sg;
+  if (g_lum)
+    for (int s = 0; s < n_src; ++s) {
+      const double L = lum_l[s * lum_stride];
+      g_lum[(long long)s * nl + l] += L > 0.0 ? sl[s] / L : 0.0;
+    }
+}
+
 // Key pixel of an event at r seen in image pixel pix: pix itself, or for an
 // SED instrument the virtual pixel of its parallel projection (clamped to
 // the virtual grid).

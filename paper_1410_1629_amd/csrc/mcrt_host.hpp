@@ -487,6 +487,7 @@ struct Prepared {
   double emitted = 0.0;    // sum over wavelengths of n_packages * w0
   long long n_keys = 0;    // image-plane tiles over all frames
   int cell_src = -1;       // index of the cell source, -1 if none
+  std::vector<double> lums;  // [n_src][n_lambda] luminosity of each source (a cell source: its total)
 };
 
 // Per wavelength: the sources' cumulative luminosities, the total and the
@@ -495,11 +496,15 @@ struct Prepared {
 inline void set_luminosities(Prepared& out, int n_src, const mcrt_source* sources, const double* cell_totals,
                              unsigned long long n_packages) {
   out.emitted = 0.0;
-  for (size_t l = 0; l < out.lam.size(); ++l) {
+  const size_t nl = out.lam.size();
+  out.lums.assign((size_t)n_src * nl, 0.0);
+  for (size_t l = 0; l < nl; ++l) {
     LamDev& L = out.lam[l];
     double cum = 0.0;
     for (int s = 0; s < n_src; ++s) {
-      cum += s == out.cell_src ? (cell_totals ? cell_totals[l] : 0.0) : sources[s].lum[l];
+      const double ls = s == out.cell_src ? (cell_totals ? cell_totals[l] : 0.0) : sources[s].lum[l];
+      out.lums[(size_t)s * nl + l] = ls;
+      cum += ls;
       L.cum[s] = cum;
     }
     L.ltot = cum;

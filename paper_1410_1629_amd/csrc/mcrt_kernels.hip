@@ -165,6 +165,12 @@ struct LifeMem {
     P.evs[((size_t)e * P.ev_k + k) * P.n_chunk + slot] = v;
   }
   __device__ double ev_load_beyond(int slot) const { return P.evs[(size_t)P.ev_max * P.ev_k * P.n_chunk + slot]; }
+  __device__ void opt_store(int slot, double ga, double gg, double gl, int src) const {
+    P.gpart[slot] = ga;
+    P.gpart[P.n_chunk + slot] = gg;
+    P.gpart[2 * P.n_chunk + slot] = gl;
+    P.gpart[3 * P.n_chunk + slot] = (double)src;
+  }
   __device__ void ev_add_beyond(int slot, double v) const {
     atomic_add_f64(P.evs + (size_t)P.ev_max * P.ev_k * P.n_chunk + slot, v);
   }
@@ -765,6 +771,49 @@ __global__ void k_unbrick(const double* __restrict__ src, double* __restrict__ d
 }
 
 // ---------------------------------------------------------------------------
+// Optics and luminosity gradients of a chunk: one workgroup per wavelength
+// whose packages the chunk holds (block b: wavelength item0 / n_pkg + b)
+// sums the pass-B sums of its packages (gpart [4][n_chunk]: sum q n, sum q
+// score, sum q, source) and adds the gradients (optics_finish).
+constexpr int kOptThreads = 256;
+
+__global__ void __launch_bounds__(kOptThreads) k_grad_optics(const double* __restrict__ gpart,
+                                                             unsigned long long item0, unsigned long long n_chunk,
+                                                             unsigned long long n_pkg, int n_src,
+                                                             const LamDev* __restrict__ lam,
+                                                             const double* __restrict__ lums, int nl,
+                                                             double* g_alb, double* g_g, double* g_lum) {
+  const unsigned long long l = item0 / n_pkg + blockIdx.x;
+  const unsigned long long b = l * n_pkg > item0 ? l * n_pkg : item0;
+  const unsigned long long e = (l + 1) * n_pkg < item0 + n_chunk ? (l + 1) * n_pkg : item0 + n_chunk;
+  double v[2 + MCRT_MAX_SOURCES];
+  for (int q = 0; q < 2 + MCRT_MAX_SOURCES; ++q) v[q] = 0.0;
+  for (unsigned long long it = b + threadIdx.x; it < e; it += kOptThreads) {
+    const unsigned long long slot = it - item0;
+    v[0] += gpart[slot];
+    v[1] += gpart[n_chunk + slot];
+    const double gl = gpart[2 * n_chunk + slot];
+    const int src = (int)gpart[3 * n_chunk + slot];
+#pragma unroll
+    for (int q = 0; q < MCRT_MAX_SOURCES; ++q) v[2 + q] += q == src ? gl : 0.0;
+  }
+  __shared__ double red[kOptThreads];
+  __shared__ double tot[2 + MCRT_MAX_SOURCES];
+  for (int q = 0; q < 2 + n_src; ++q) {
+    red[threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = kOptThreads / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) tot[q] = red[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    optics_finish(tot[0], tot[1], tot + 2, n_src, lam[l].albedo, lums + l, nl, g_alb, g_g, g_lum, (int)l, nl);
+}
+
+// ---------------------------------------------------------------------------
 // Cell-source CDF: per wavelength row the exclusive prefix sums of the
 // cells' luminosities x[row][0..n) into cum[row][0..n], cum[row][n] the
 // total.  Tiles of kCdfTile cells; each thread sums kCdfPer consecutive cells
@@ -1159,8 +1208,8 @@ constexpr size_t kScratchBytes = size_t(1) << 32, kQueueBytes = size_t(1) << 33;
 // Shared driver of run_photons and backward_density.
 int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
          const mcrt_source* sources, int n_det, const mcrt_detector* detectors, const mcrt_opts* opts,
-         double* images_dev, double* absorbed_dev, const double* adj_dev, double* grad_dev, mcrt_stats* stats,
-         void* hip_stream) {
+         double* images_dev, double* absorbed_dev, const double* adj_dev, const mcrt_grads* grads,
+         mcrt_stats* stats, void* hip_stream) {
   host::Prepared pr;
   if (int e = host::prepare(grid, rho_dev, optics, n_src, sources, n_det, detectors, opts, pr)) return e;
   RunParams& P = pr.P;
@@ -1172,9 +1221,10 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     P.absorbed = (opts->flags & MCRT_ABSORB) ? absorbed_dev : nullptr;
   } else {
     if (peel && !adj_dev) return fail(MCRT_EINVAL, "adj_images_dev is NULL");
-    if (!grad_dev) return fail(MCRT_EINVAL, "grad_rho_dev is NULL");
+    if (!grads) return fail(MCRT_EINVAL, "grads is NULL");
+    if (!grads->rho && !grads->albedo && !grads->g && !grads->lum) return fail(MCRT_EINVAL, "no gradient requested");
     P.adj = adj_dev;
-    P.grad = grad_dev;
+    P.grad = grads->rho;
   }
   const int nl = P.n_lambda;
   const bool f32 = opts->precision == MCRT_PREC_FP32;
@@ -1189,7 +1239,8 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   // package, T and q per frame for kEventsKept events plus the sum of q
   // beyond; the peel-ray queue by default 8 rays per package and frame
   const int ev_k = 1 + n_det;
-  const size_t per_item = sizeof(double) * ((size_t)kEventsKept * ev_k + 1);
+  const bool optg = adjoint && (grads->albedo || grads->g || grads->lum);
+  const size_t per_item = sizeof(double) * ((size_t)kEventsKept * ev_k + 1 + (optg ? 4 : 0));
   const bool queued = peel && opts->peel_queue != -1;
   size_t free_b = 0, total_b = 0;
   HIPCHK(hipMemGetInfo(&free_b, &total_b));
@@ -1202,7 +1253,8 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
                                             ((size_t)n_det * 8 * kQueueBytesPerRay)));
   const unsigned long long n_chunks = (P.n_items + most - 1) / most;
   const unsigned long long chunk = (P.n_items + n_chunks - 1) / n_chunks;
-  const size_t n_evs = adjoint ? (size_t)chunk * ((size_t)kEventsKept * ev_k + 1) : 0;
+  // the adjoint's event scratch, then (optics gradients) the pass-B sums
+  const size_t n_evs = adjoint ? (size_t)chunk * ((size_t)kEventsKept * ev_k + 1 + (optg ? 4 : 0)) : 0;
   const long long n_tally = adjoint ? (long long)P.G.ncell_pad : (P.absorbed ? (long long)nl * P.G.ncell_pad : 0);
   const size_t off_lam = 0;
   const size_t off_det = align256(sizeof(LamDev) * nl);
@@ -1221,7 +1273,8 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const size_t off_cum = off_evs + align256(sizeof(double) * n_evs);
   const size_t off_cts = off_cum + align256(cells ? sizeof(double) * (size_t)nl * (P.G.ncell + 1) : 0);
   const size_t off_ctot = off_cts + align256(sizeof(double) * (size_t)(nl * cdf_tiles));
-  const size_t bytes = off_ctot + (cells ? align256(sizeof(double) * nl + 8) : 0);
+  const size_t off_lums = off_ctot + (cells ? align256(sizeof(double) * nl + 8) : 0);
+  const size_t bytes = off_lums + (optg ? align256(sizeof(double) * pr.lums.size()) : 0);
 
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   DeviceBlock blk;
@@ -1253,6 +1306,13 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     P.evs = reinterpret_cast<double*>(blk.ptr + off_evs);
     P.ev_max = kEventsKept;
     P.ev_k = ev_k;
+  }
+  double* const lums = optg ? reinterpret_cast<double*>(blk.ptr + off_lums) : nullptr;
+  if (optg) {  // the sources' luminosities (known once the cell CDF is); gradients start at 0
+    HIPCHK(hipMemcpyAsync(lums, pr.lums.data(), sizeof(double) * pr.lums.size(), hipMemcpyHostToDevice, st));
+    if (int e = zero_fill(grads->albedo, grads->albedo ? nl : 0, st)) return e;
+    if (int e = zero_fill(grads->g, grads->g ? nl : 0, st)) return e;
+    if (int e = zero_fill(grads->lum, grads->lum ? (long long)n_src * nl : 0, st)) return e;
   }
   P.item0 = 0;
   P.n_chunk = P.n_items;
@@ -1323,8 +1383,10 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
       P.item0 = c0;
       P.n_chunk = std::min(chunk, P.n_items - c0);
-      if (int e = zero_fill(P.evs, (long long)(P.n_chunk * ((unsigned long long)kEventsKept * ev_k + 1)), st))
+      if (int e = zero_fill(P.evs, (long long)(P.n_chunk * ((unsigned long long)kEventsKept * ev_k + 1 + (optg ? 4 : 0))),
+                            st))
         return e;
+      P.gpart = optg ? P.evs + P.n_chunk * ((unsigned long long)kEventsKept * ev_k + 1) : nullptr;
       if (int e = reset_counters(ctr, 0, 1, st)) return e;
       if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
       if (int e = reset_counters(ctr, kDepCounter, 1, st)) return e;
@@ -1339,10 +1401,16 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
       rc = f32 ? launch_life<float, true>(P, nblk, st) : launch_life<double, true>(P, nblk, st);
       if (rc) return rc;
       ++launches;
+      if (optg) {
+        const unsigned nb = (unsigned)((P.item0 + P.n_chunk - 1) / P.n_pkg - P.item0 / P.n_pkg + 1);
+        hipLaunchKernelGGL(k_grad_optics, dim3(nb), dim3(kOptThreads), 0, st, P.gpart, P.item0, P.n_chunk, P.n_pkg,
+                           n_src, P.lam, lums, nl, grads->albedo, grads->g, grads->lum);
+        HIPCHK(hipGetLastError());
+      }
     }
   }
   if (stats) HIPCHK(hipEventRecord(ev.c, st));
-  if (tally)
+  if (tally && user_tally)
     if (int e = unbrick_tally(P.G, tally, user_tally, adjoint ? 1 : nl, st)) return e;
   if (stats) {
     double ds[3];
@@ -1410,10 +1478,29 @@ int backward_density(const mcrt_grid* grid, const void* rho_dev, const mcrt_opti
       o = *opts;
       o.flags &= ~MCRT_ABSORB;
     }
+    mcrt_grads g = {grad_rho_dev, nullptr, nullptr, nullptr};
+    if (!grad_rho_dev) return fail(MCRT_EINVAL, "grad_rho_dev is NULL");
     return life(true, grid, rho_dev, optics, n_src, sources, n_det, detectors, opts ? &o : nullptr, nullptr,
-                nullptr, adj_images_dev, grad_rho_dev, stats_host, hip_stream);
+                nullptr, adj_images_dev, &g, stats_host, hip_stream);
   } catch (...) {
     return fail(MCRT_EHIP, "backward_density: host exception");
+  }
+}
+
+int backward(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
+             const mcrt_source* sources, int n_det, const mcrt_detector* detectors, const mcrt_opts* opts,
+             const double* adj_images_dev, const mcrt_grads* grads, mcrt_stats* stats_host, void* hip_stream) {
+  try {
+    mcrt::host::last_error().clear();
+    mcrt_opts o;
+    if (opts) {
+      o = *opts;
+      o.flags &= ~MCRT_ABSORB;
+    }
+    return life(true, grid, rho_dev, optics, n_src, sources, n_det, detectors, opts ? &o : nullptr, nullptr,
+                nullptr, adj_images_dev, grads, stats_host, hip_stream);
+  } catch (...) {
+    return fail(MCRT_EHIP, "backward: host exception");
   }
 }
 

@@ -22,6 +22,7 @@
 //   M.fetch()  M.flush_counts(x_path, x_locate, x_peel, deposits)
 //   M.job_slot()  M.store_job(slot, ...)   (peel-ray queue)
 //   M.ev_load(slot, e, k)  M.ev_store(slot, e, k, v)   (adjoint event scratch)
+//   M.opt_store(slot, ga, gg, gl, src)   (pass B sums for the optics gradients)
 // Cells are bricked addresses (GridDev): densities, the absorbed tally
 // (wavelength-major, ncell_pad per wavelength) and the gradient are all in
 // the bricked layout inside the library.
@@ -113,6 +114,10 @@ struct RunParams {
   int ev_max;                  // events kept per package in the event scratch
   int ev_k;                    // doubles per event: T of the leg after it, then q per frame
   double* evs;                 // event scratch [ev_max][ev_k][n_chunk], then q beyond ev_max [n_chunk]
+  // pass B, when the optics and luminosity gradients are wanted: per package
+  // of the chunk sum q n, sum q (score in g), sum q and its source index,
+  // [4][n_chunk] (null: not wanted)
+  double* gpart;
 };
 
 template <typename R>
@@ -134,6 +139,8 @@ struct Lane {
   int slot;  // the lane's index in the event scratch
   double Rtot, Gacc, Gabs, fac, Ge;
   bool t_kept;  // pass B: T of the next leg is in the scratch
+  int src;      // source of the package
+  double Sg, Ga, Gg, GL;  // pass B, optics gradients: score of the sampled directions; sums over q
   // statistics
   double s_abs, s_esc, s_trunc;
   unsigned x_path, x_loc, x_peel, n_ev, n_pk, n_pl, n_dep;
@@ -164,6 +171,8 @@ MCRT_HD void lane_init(Lane<R>& L) {
   L.slot = 0;
   L.Rtot = L.Gacc = L.Gabs = L.fac = L.Ge = 0.0;
   L.t_kept = false;
+  L.src = 0;
+  L.Sg = L.Ga = L.Gg = L.GL = 0.0;
   L.s_abs = L.s_esc = L.s_trunc = 0.0;
   L.x_path = L.x_loc = L.x_peel = L.n_ev = L.n_pk = L.n_pl = L.n_dep = 0;
 }
@@ -173,11 +182,30 @@ MCRT_HD void lane_init(Lane<R>& L) {
 // for the event and skips its peel-offs; events beyond the scratch walk
 // their peel rays again.  Called once the event's next phase is set: events
 // without peel-off (the flags exclude it) have G_e = 0.
+// Pass B of a run with optics gradients: a peel-off contribution q of the
+// current event towards frame d.  The event's scattering count n, its
+// direction scores so far and its peel phase give q's factors: n (albedo),
+// the score in g, and 1 (the source's luminosity).
+template <typename R, class Mem>
+MCRT_HD void optics_add(Lane<R>& L, Mem& M, int d, double q) {
+  L.Ga += q * (double)L.n;
+  L.GL += q;
+  if (!L.is_emit) {
+    double kd[3], inv_d2, tmax;
+    peel_geometry(M.det(d), L.r, kd, inv_d2, tmax);
+    L.Gg += q * (L.Sg + hg_dlng(L.g, L.k[0] * kd[0] + L.k[1] * kd[1] + L.k[2] * kd[2]));
+  }
+}
+
 template <typename R, class Mem>
 MCRT_HD void event_start(Lane<R>& L, const RunParams& P, Mem& M) {
   L.Ge = 0.0;
   if (L.pass == 1 && L.n < P.ev_max && L.phase == PH_PEEL_NEXT) {
-    for (int d = 0; d < P.n_det; ++d) L.Ge += M.ev_load(L.slot, L.n, 1 + d);
+    for (int d = 0; d < P.n_det; ++d) {
+      const double q = M.ev_load(L.slot, L.n, 1 + d);
+      L.Ge += q;
+      if (P.gpart && q != 0.0) optics_add(L, M, d, q);
+    }
     L.det = P.n_det;  // no peel-off walks: PEEL_NEXT goes straight on
   }
 }
@@ -233,6 +261,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
         const double ac = M.adj(ii) * C;
         L.Ge += ac;
         if (L.pass == 0) keep_q(L, P, M, ac);
+        if (L.pass == 1 && P.gpart && ac != 0.0) optics_add(L, M, L.det, ac);
         if (L.pass == 0 && ac != 0.0) {  // a second walk of the same ray deposits -A C kappa l
           L.fac = -ac * L.kap;
           want = to_det = true;
@@ -348,7 +377,9 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
         if (L.pass == 0) L.s_trunc += L.W;
         L.phase = PH_PKG_END;
       } else {
-        turn(L.k, hg_sample_mu(L.g, u01(L.uw1)), u01(L.uw2));
+        const double mu = hg_sample_mu(L.g, u01(L.uw1));
+        if (ADJ && L.pass == 1 && P.gpart) L.Sg += hg_dlng(L.g, mu);
+        turn(L.k, mu, u01(L.uw2));
         L.phase = PH_PATH_START;
       }
     }
@@ -368,7 +399,12 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     }
 
     // -- end of the package: replay it for the adjoint, or take the next one
-    if (L.phase == PH_PKG_END && !want) L.phase = PH_FETCH;
+    if (L.phase == PH_PKG_END && !want) {
+      if (ADJ && L.pass == 1 && P.gpart) {  // the package's sums for the optics gradients
+        M.opt_store(L.slot, L.Ga, L.Gg, L.GL, L.src);
+      }
+      L.phase = PH_FETCH;
+    }
     if (L.phase == PH_FETCH && !want) {
       if ((L.x_path | L.x_loc | L.x_peel | L.n_dep) & 0xC0000000u) {  // keep 32-bit counters from wrapping
         M.flush_counts(L.x_path, L.x_loc, L.x_peel, L.n_dep);
@@ -431,6 +467,8 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
       }
       iso_direction(u01(wd.x), u01(wd.y), L.k);
       const SrcDev& S = M.src(s);
+      L.src = s;
+      if (ADJ) L.Sg = L.Ga = L.Gg = L.GL = 0.0;
       const U4 wp = draw_words(P.seed, L.pkg, (unsigned)L.lam, 0u);
       if (S.kind == 2)
         cell_source_position<Mem::kGrid>(S, G, L.lam, wp, L.r);

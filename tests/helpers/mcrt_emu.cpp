@@ -165,6 +165,7 @@ struct HostLifeMem {
   // adjoint event scratch [ev_max][ev_k][n_chunk], then [n_chunk]; T entries
   // (k = 0) must be written before they are read, q entries start at zero
   std::vector<double>* evs = nullptr;
+  std::vector<double>* gpart = nullptr;  // pass B sums for the optics gradients [4][n_chunk]
   int ev_max = 0, ev_k = 0, n_chunk = 0;
   std::vector<unsigned char>* ev_set = nullptr;
   size_t ev_index(int slot, int e, int k) const {
@@ -182,6 +183,16 @@ struct HostLifeMem {
     const size_t i = ev_index(slot, e, k);
     (*evs)[i] = v;
     (*ev_set)[i] = 1;
+  }
+  void opt_store(int slot, double ga, double gg, double gl, int src) {
+    EMU_CHECK(gpart != nullptr, "optics sums without their buffer", slot, n_chunk);
+    EMU_CHECK(slot >= 0 && slot < n_chunk, "optics sums package", slot, n_chunk);
+    EMU_CHECK(src >= 0 && src < pr.P.n_src, "optics sums source", src, pr.P.n_src);
+    double* g = gpart->data();
+    g[slot] = ga;
+    g[n_chunk + slot] = gg;
+    g[2 * n_chunk + slot] = gl;
+    g[3 * n_chunk + slot] = (double)src;
   }
   double ev_load_beyond(int slot) const {
     EMU_CHECK(slot >= 0 && slot < n_chunk, "event scratch package", slot, n_chunk);
@@ -376,7 +387,7 @@ template <typename R, bool ADJ, int GK>
 int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, int n_src, const mcrt_source* sources,
              int n_det, const mcrt_detector* detectors, const mcrt_opts* opts, double* images, long long n_images,
              double* absorbed, long long n_absorbed, const double* adj, long long n_adj, double* grad, long long n_grad,
-             mcrt_stats* stats, int wave) {
+             double* gopt, mcrt_stats* stats, int wave) {
   host::Prepared pr;
   if (int e = host::prepare(grid, rho, optics, n_src, sources, n_det, detectors, opts, pr)) return e;
   HostPlanes planes;
@@ -472,8 +483,10 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
     P.jobs = jobs.data();
     P.job_cap = qcap;
   }
-  std::vector<double> evs;
+  std::vector<double> evs, gpart;
   std::vector<unsigned char> ev_set;
+  const int nl = P.n_lambda, ns = P.n_src;
+  if (gopt) std::fill(gopt, gopt + (size_t)(2 + ns) * nl, 0.0);
   M.evs = &evs;
   M.ev_set = &ev_set;
   M.ev_max = P.ev_max;
@@ -497,9 +510,31 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
     }
     evs.assign((size_t)P.n_chunk * ((size_t)P.ev_max * P.ev_k + 1), 0.0);
     ev_set.assign(evs.size(), 0);
+    if (gopt) {
+      gpart.assign(4 * (size_t)P.n_chunk, 0.0);
+      M.gpart = &gpart;
+      P.gpart = gpart.data();  // only tested against null by the lanes; the stores go through M
+    }
     launch(1);  // pass A
     if (P.jobs) queue_phase();
     launch(2);  // pass B
+    if (gopt) {  // per wavelength of the chunk: sums over its packages, then the gradients
+      const unsigned long long nc = P.n_chunk;
+      for (unsigned long long l = P.item0 / P.n_pkg; l <= (P.item0 + nc - 1) / P.n_pkg; ++l) {
+        const unsigned long long b = std::max(l * P.n_pkg, P.item0), e = std::min((l + 1) * P.n_pkg, P.item0 + nc);
+        double sa = 0.0, sg = 0.0, sl[MCRT_MAX_SOURCES] = {0};
+        for (unsigned long long it = b; it < e; ++it) {
+          const unsigned long long q = it - P.item0;
+          sa += gpart[q];
+          sg += gpart[nc + q];
+          const int src = (int)gpart[3 * nc + q];
+          EMU_CHECK(src >= 0 && src < ns, "optics sums source", src, ns);
+          sl[src] += gpart[2 * nc + q];
+        }
+        optics_finish(sa, sg, sl, ns, pr.lam[l].albedo, pr.lums.data() + l, nl, gopt, gopt + nl, gopt + 2 * nl,
+                      (int)l, nl);
+      }
+    }
   }
   M.xs[2] += M.x_queue;
   M.xs[6] += M.d_queue;
@@ -740,7 +775,7 @@ int emu_run_photons(const mcrt_grid* grid, const void* rho, const mcrt_optics* o
     if (!opts) return host::fail(MCRT_EINVAL, "opts is NULL");
     return life_dispatch<false>(opts->precision == MCRT_PREC_FP32, grid_kind(grid), grid, rho, optics, n_src,
                                 sources, n_det, detectors, opts, images, n_images, absorbed, n_absorbed,
-                                (const double*)nullptr, 0ll, (double*)nullptr, 0ll, stats, wave);
+                                (const double*)nullptr, 0ll, (double*)nullptr, 0ll, (double*)nullptr, stats, wave);
   } catch (const Violation& v) {
     g_violation = std::string("run_photons: ") + v.what();
     return -100;
@@ -749,8 +784,8 @@ int emu_run_photons(const mcrt_grid* grid, const void* rho, const mcrt_optics* o
 
 int emu_backward_density(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, int n_src,
                          const mcrt_source* sources, int n_det, const mcrt_detector* detectors, const mcrt_opts* opts,
-                         const double* adj, long long n_adj, double* grad, long long n_grad, mcrt_stats* stats,
-                         int wave) {
+                         const double* adj, long long n_adj, double* grad, long long n_grad, double* gopt,
+                         mcrt_stats* stats, int wave) {
   try {
     g_violation.clear();
     host::last_error().clear();
@@ -759,7 +794,7 @@ int emu_backward_density(const mcrt_grid* grid, const void* rho, const mcrt_opti
     o.flags &= ~MCRT_ABSORB;
     return life_dispatch<true>(o.precision == MCRT_PREC_FP32, grid_kind(grid), grid, rho, optics, n_src, sources,
                                n_det, detectors, (const mcrt_opts*)&o, (double*)nullptr, 0ll, (double*)nullptr, 0ll,
-                               adj, n_adj, grad, n_grad, stats, wave);
+                               adj, n_adj, grad, n_grad, gopt, stats, wave);
   } catch (const Violation& v) {
     g_violation = std::string("backward_density: ") + v.what();
     return -100;

@@ -57,7 +57,7 @@ def test_abi_version(lib, B):
 
 def test_struct_layouts_match_the_c_compiler(B, tmp_path):
     structs = {"mcrt_grid": B.Grid, "mcrt_optics": B.Optics, "mcrt_source": B.Source, "mcrt_detector": B.Detector,
-               "mcrt_opts": B.Opts, "mcrt_stats": B.Stats}
+               "mcrt_opts": B.Opts, "mcrt_stats": B.Stats, "mcrt_grads": B.Grads}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mcrt.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
@@ -176,6 +176,19 @@ def test_invalid_arguments_are_rejected(lib, B, W, case):
         rc = _call_run(lib, B, prob, **over)
     assert rc == B.EINVAL, (case, rc)
     assert lib.mcrt_last_error().decode(), case
+
+
+def test_backward_rejects_missing_gradients(lib, B, W):
+    prob = W.small_problem(n=(4, 4, 4), n_packages=100)
+    pr = B._Problem(prob)
+    fake = C.c_void_p(0x1000)
+    st = B.Stats()
+    none = B.Grads(None, None, None, None)
+    for grads in (None, C.byref(none)):
+        rc = lib.backward(C.byref(pr.grid), fake, C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det, pr.detectors,
+                          C.byref(pr.opts), fake, grads, C.byref(st), None)
+        assert rc == B.EINVAL
+        assert lib.mcrt_last_error().decode()
 
 
 @pytest.mark.parametrize("case", ["kind", "sed_pixels", "eye_is_target", "up_along_view", "eye_nan", "persp_extent"])

@@ -1,0 +1,95 @@
+"""The HIP path's gradients with respect to the albedo, g and the source
+luminosities (with the densities, in one replay) through the C ABI, against
+the FP64 oracle on mixed instruments and sources, tree grids and cell
+sources, in both precisions and queue modes; then the adjoint workload at
+full size: the optics gradients' cost beside the density-only replay, and
+the single-source luminosity gradient against the image it scales."""
+import time
+
+import numpy as np
+import pytest
+
+from test_emu_optics_grad import problems
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l1(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    den = np.abs(b).sum()
+    return float(np.abs(a - b).sum() / den) if den > 0 else float(np.abs(a).sum())
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    from paper_1410_1629_amd import binding
+    binding.load()
+    assert torch.cuda.is_available()
+    return binding
+
+
+def _dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).cuda()
+
+
+def _say(msg):
+    print("[gpu] " + msg, flush=True)
+
+
+def _outputs(B, p, n_cells):
+    import torch
+    nl, ns = len(np.atleast_1d(p["kappa"])), len(p["sources"])
+    z = lambda *s: torch.empty(s, dtype=torch.float64, device="cuda")  # noqa: E731
+    return z(n_cells), z(nl), z(nl), z(ns, nl)
+
+
+@pytest.mark.parametrize("name", ["mixed", "tree", "cells"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_optics_gradients_match_oracle(B, orc, W, name, prec):
+    _say("optics gradients %s prec=%d" % (name, prec))
+    p = problems(W, name, prec)
+    p["n_packages"] = 3000
+    img_o, _, _ = orc.run(p, threads=8)
+    adj = np.random.default_rng(8).standard_normal(img_o.shape)
+    g_o, _, _, go = orc.grad(p, adj, threads=8, optics=True)
+    rho = B.density_tensor(p)
+    tol = 1e-9 if prec == 0 else 1e-5
+    for q in (-1, 0):
+        gr, ga, gg, gl = _outputs(B, p, rho.numel())
+        B.backward(p, rho, _dev(adj), gr, ga, gg, gl, peel_queue=q)
+        errs = [rel_l1(gr.cpu().numpy(), g_o)] + [rel_l1(t.cpu().numpy(), go[k]) for t, k in
+                                                  ((ga, "albedo"), (gg, "g"), (gl, "lum"))]
+        _say("  queue %d: rel_L1 rho %.2e albedo %.2e g %.2e lum %.2e" % ((q,) + tuple(errs)))
+        assert max(errs) < tol
+
+
+def test_adjoint_workload_with_optics_gradients(B, W):
+    import torch
+    _say("adjoint workload, 1e7 packages: density-only replay vs all gradients")
+    p = W.adjoint()
+    rho = B.density_tensor(p)
+    images = torch.empty(B.image_shape(p), dtype=torch.float64, device="cuda")
+    B.run_photons(p, rho, images)
+    adj = torch.randn(images.shape, generator=torch.Generator(device="cuda").manual_seed(3), dtype=torch.float64,
+                      device="cuda")
+    gr, ga, gg, gl = _outputs(B, p, rho.numel())
+    gr2 = torch.empty_like(gr)
+    B.backward_density(p, rho, adj, gr2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s1 = B.backward_density(p, rho, adj, gr2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s2 = B.backward(p, rho, adj, gr, ga, gg, gl)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    assert torch.equal(gr, gr2) or rel_l1(gr.cpu().numpy(), gr2.cpu().numpy()) < 1e-12
+    # one source: its luminosity gradient is sum(adj * image) / L exactly
+    want = (adj * images).sum().item() / p["sources"][0]["lum"][0]
+    assert abs(gl[0, 0].item() / want - 1.0) < 1e-9, (gl[0, 0].item(), want)
+    _say("  density only %.1f ms (kernel %.1f); with albedo, g, luminosity %.1f ms (kernel %.1f); dL/dalbedo %.4e "
+         "dL/dg %.4e dL/dL %.4e" % ((t1 - t0) * 1e3, s1["kernel_ms"], (t2 - t1) * 1e3, s2["kernel_ms"],
+                                    ga[0].item(), gg[0].item(), gl[0, 0].item()))
+    assert np.isfinite([ga[0].item(), gg[0].item()]).all()
