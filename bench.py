@@ -59,8 +59,8 @@ BYTES_PER_RAY = 56
 COPY_BYTES = 1 << 30
 # kernel names as rocprofv3 prints them -> keys of profiles/traffic.json
 KERNELS = {
-    "forward": "void mcrt::k_life<float, false, 0>(mcrt::RunParams)",
-    "adjoint": "void mcrt::k_life<float, true, 0>(mcrt::RunParams)",
+    "forward": "void mcrt::k_life<float, false, 0, false>(mcrt::RunParams)",
+    "adjoint": "void mcrt::k_life<float, true, 0, false>(mcrt::RunParams)",
     "peel_tau_forward": "void mcrt::k_peeltau<float, false, 0, false>(mcrt::PeelJobParams)",
     "peel_tau_adjoint": "void mcrt::k_peeltau<float, true, 0, false>(mcrt::PeelJobParams)",
     "peel_deposit": "void mcrt::k_peeldep<float, 0, false>(mcrt::PeelJobParams)",
