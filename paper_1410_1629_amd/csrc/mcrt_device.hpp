@@ -472,12 +472,15 @@ MCRT_HD void dust_cell(const DustParams& P, int m) {
 }
 
 // ---------------------------------------------------------------------------
-// Frame projection (parallel projection, Sect. 2.2): pixel index of r, or -1.
-
+// Instrument projection (Sect. 2.2): pixel index of r, or -1 -- parallel
+// projection for frames, the single pixel of an SED instrument, central
+// projection through a camera's eye.  INST = false (frames only) compiles
+// out the other kinds: the life kernel's event code is sensitive to its size.
+template <bool INST = true>
 MCRT_HD int frame_pixel(const DetDev& D, const double r[3]) {
-  if (D.kind == kDetSed) return 0;  // the whole sky of the observer
+  if (INST && D.kind == kDetSed) return 0;  // the whole sky of the observer
   double xp, yp;
-  if (D.kind == kDetPerspective) {  // central projection through the eye
+  if (INST && D.kind == kDetPerspective) {  // central projection through the eye
     const double d[3] = {r[0] - D.eye[0], r[1] - D.eye[1], r[2] - D.eye[2]};
     const double z = d[0] * D.kd[0] + d[1] * D.kd[1] + d[2] * D.kd[2];
     if (!(z > 0.0)) return -1;
@@ -517,8 +520,9 @@ MCRT_HD void optics_finish(double sa, double sg, const double* sl, int n_src, do
 // Key pixel of an event at r seen in image pixel pix: pix itself, or for an
 // SED instrument the virtual pixel of its parallel projection (clamped to
 // the virtual grid).
+template <bool INST = true>
 MCRT_HD int key_pixel(const DetDev& D, const double r[3], int pix) {
-  if (D.kind != kDetSed) return pix;
+  if (!INST || D.kind != kDetSed) return pix;
   const double xp = r[0] * D.ex[0] + r[1] * D.ex[1] + r[2] * D.ex[2];
   const double yp = r[0] * D.ey[0] + r[1] * D.ey[1] + r[2] * D.ey[2];
   const double last = (double)(D.kn - 1);

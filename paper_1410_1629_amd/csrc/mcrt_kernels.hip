@@ -140,9 +140,10 @@ __device__ __forceinline__ unsigned long long* wave_reservoir(unsigned long long
 // ---------------------------------------------------------------------------
 // Device memory accessors.
 
-template <typename R, int GK>
+template <typename R, int GK, bool INST>
 struct LifeMem {
   static constexpr int kGrid = GK;
+  static constexpr bool kInst = INST;  // instruments other than frames (SED, camera)
   const R* __restrict__ rho_;
   const RunParams& P;
   unsigned long long* res;
@@ -246,16 +247,17 @@ struct PeelMem {
 // Kernels.
 
 // The life-cycle kernel body; k_life (FP32 walk) and k_life64 (FP64 walk)
-// launch it, once per grid kind (GK, kGrid*).  The FP64
-// kernel asks for two wavefronts per SIMD, which its register use would
-// otherwise just miss.
-template <typename R, bool ADJ, int GK>
+// launch it, once per grid kind (GK, kGrid*) and with or without the
+// handling of instruments other than frames -- SED instruments, cameras and
+// their walks to the eye (INST).  The FP64 kernel asks for two wavefronts
+// per SIMD, which its register use would otherwise just miss.
+template <typename R, bool ADJ, int GK, bool INST>
 __device__ __forceinline__ void life_body(const RunParams& P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2], job_slots[kWavesPerBlock][2];
   __shared__ long long dep_idx[kWavesPerBlock][64 * kBlockWalk];
   __shared__ double dep_val[kWavesPerBlock][64 * kBlockWalk];
   const int wave = threadIdx.x / 64;
-  LifeMem<R, GK> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots), wave_reservoir(job_slots)};
+  LifeMem<R, GK, INST> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots), wave_reservoir(job_slots)};
   Lane<R> L;
   lane_init(L);
   for (;;) {
@@ -294,14 +296,14 @@ __device__ __forceinline__ void life_body(const RunParams& P) {
   }
 }
 
-template <typename R, bool ADJ, int GK>
+template <typename R, bool ADJ, int GK, bool INST>
 __global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
-  life_body<R, ADJ, GK>(P);
+  life_body<R, ADJ, GK, INST>(P);
 }
 
-template <bool ADJ, int GK>
+template <bool ADJ, int GK, bool INST>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_life64(const RunParams P) {
-  life_body<double, ADJ, GK>(P);
+  life_body<double, ADJ, GK, INST>(P);
 }
 
 template <typename R, int GK>
@@ -597,7 +599,7 @@ __device__ __forceinline__ void flush_images(bool& has, long long ii, double c, 
 // loads).  Forward: C = v e^-tau goes to the ray's pixel (flush_images).
 // Adjoint: q = (dL/dI) v e^-tau goes to the event scratch, and the job's v
 // becomes the deposit weight -q kappa (0: no deposit walk).
-template <typename R, bool ADJ, int GK, bool CAM>
+template <typename R, bool ADJ, int GK, bool INST>
 __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2];
   unsigned long long* res = wave_reservoir(slots);
@@ -640,7 +642,7 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
       job = P.perm[qi];
       const PeelJob& J = P.jobs[job];
       kap = (R)P.lam[J.lam].kappa;
-      if constexpr (CAM) {
+      if constexpr (INST) {
         double kd[3], inv_d2, tmax;
         peel_geometry(P.det[J.d], J.r, kd, inv_d2, tmax);
         ray_begin<R, GK>(ry, P.G, J.r, kd, tmax);
@@ -656,7 +658,7 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
     for (;;) {
       const int n_act = __popcll(__ballot(ry.active));
       if (n_act == 0 || n_live - n_act >= P.batch) break;
-      if (ry.active) nx += tau_step<R, decltype(M), CAM>(ry, P.G, kap, M);
+      if (ry.active) nx += tau_step<R, decltype(M), INST>(ry, P.G, kap, M);
     }
   }
   const unsigned long long wsum = wave_sum_u64(nx);
@@ -666,7 +668,7 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
 // The deposit walks of the sorted queue: chunks of consecutive sorted jobs
 // per workgroup, deposits summed per cell in the LDS table, one global
 // atomic per distinct cell and chunk.  Jobs whose weight is 0 are skipped.
-template <typename R, int GK, bool CAM>
+template <typename R, int GK, bool INST>
 __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams P) {
   __shared__ int tk[kTable];
   __shared__ double tv[kTable];
@@ -701,7 +703,7 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
         const PeelJob& J = P.jobs[P.perm[qi]];
         w = J.v;
         if (w != 0.0) {
-          if constexpr (CAM) {
+          if constexpr (INST) {
             double kd[3], inv_d2, tmax;
             peel_geometry(P.det[J.d], J.r, kd, inv_d2, tmax);
             ray_begin<R, GK>(ry, P.G, J.r, kd, tmax);
@@ -716,7 +718,7 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
       for (;;) {
         const int n_act = __popcll(__ballot(ry.active));
         if (n_act == 0 || n_live - n_act >= P.batch) break;
-        if (ry.active) nd += bp_step<R, decltype(M), CAM>(ry, P.G, w, M);
+        if (ry.active) nd += bp_step<R, decltype(M), INST>(ry, P.G, w, M);
       }
     }
     __syncthreads();
@@ -1097,17 +1099,17 @@ int reset_counters(unsigned long long* ctr, int w, int n, hipStream_t st) {
 
 // The queue's walks: optical depth (and the image, forward), then the
 // adjoint's deposit walks.
-template <typename R, bool ADJ, int GK, bool CAM>
+template <typename R, bool ADJ, int GK, bool INST>
 int walk_peel_jobs(const PeelJobParams& J, hipStream_t st) {
   int nblk = 0;
-  if (int e = persistent_grid(k_peeltau<R, ADJ, GK, CAM>, 0, &nblk)) return e;
-  hipLaunchKernelGGL((k_peeltau<R, ADJ, GK, CAM>), dim3(nblk), dim3(kBlock), 0, st, J);
+  if (int e = persistent_grid(k_peeltau<R, ADJ, GK, INST>, 0, &nblk)) return e;
+  hipLaunchKernelGGL((k_peeltau<R, ADJ, GK, INST>), dim3(nblk), dim3(kBlock), 0, st, J);
   if (ADJ) {
     int dev = 0, cus = 0, nb = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peeldep<R, GK, CAM>, kBundleThreads, 0));
-    hipLaunchKernelGGL((k_peeldep<R, GK, CAM>), dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0,
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peeldep<R, GK, INST>, kBundleThreads, 0));
+    hipLaunchKernelGGL((k_peeldep<R, GK, INST>), dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0,
                        st, J);
   }
   HIPCHK(hipGetLastError());
@@ -1116,7 +1118,7 @@ int walk_peel_jobs(const PeelJobParams& J, hipStream_t st) {
 
 // Sorts the chunk's queued peel rays by key and walks them.
 template <typename R, bool ADJ>
-int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ctr, bool cam, hipStream_t st) {
+int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ctr, bool inst, hipStream_t st) {
   const long long n_cnt = q.n_keys * kSortBlocks;
   hipLaunchKernelGGL(k_hist, dim3(kSortBlocks), dim3(kSortThreads), 0, st, q.jobs, ctr, q.cap, (int)q.n_keys,
                      q.counts);
@@ -1147,7 +1149,7 @@ int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ct
   J.n_chunk = P.n_chunk;
   J.ctr = ctr;
   J.batch = 16;
-  if (cam) {  // a perspective instrument: walks that stop at its eye
+  if (inst) {  // instruments other than frames: walks that stop at a camera's eye
     switch (P.G.kind) {
       case kGridRect: return walk_peel_jobs<R, ADJ, kGridRect, true>(J, st);
       case kGridTree: return walk_peel_jobs<R, ADJ, kGridTree, true>(J, st);
@@ -1161,39 +1163,53 @@ int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ct
   }
 }
 
-template <typename R, bool ADJ, int GK>
+template <typename R, bool ADJ, int GK, bool INST>
 int life_grid_k(int blocks_per_cu, int* nblk) {
   if constexpr (std::is_same<R, double>::value)
-    return persistent_grid(k_life64<ADJ, GK>, blocks_per_cu, nblk);
+    return persistent_grid(k_life64<ADJ, GK, INST>, blocks_per_cu, nblk);
   else
-    return persistent_grid(k_life<R, ADJ, GK>, blocks_per_cu, nblk);
+    return persistent_grid(k_life<R, ADJ, GK, INST>, blocks_per_cu, nblk);
 }
 
-template <typename R, bool ADJ>
-int life_grid(int kind, int blocks_per_cu, int* nblk) {
+template <typename R, bool ADJ, bool INST>
+int life_grid_c(int kind, int blocks_per_cu, int* nblk) {
   switch (kind) {
-    case kGridRect: return life_grid_k<R, ADJ, kGridRect>(blocks_per_cu, nblk);
-    case kGridTree: return life_grid_k<R, ADJ, kGridTree>(blocks_per_cu, nblk);
-    default: return life_grid_k<R, ADJ, kGridRegular>(blocks_per_cu, nblk);
+    case kGridRect: return life_grid_k<R, ADJ, kGridRect, INST>(blocks_per_cu, nblk);
+    case kGridTree: return life_grid_k<R, ADJ, kGridTree, INST>(blocks_per_cu, nblk);
+    default: return life_grid_k<R, ADJ, kGridRegular, INST>(blocks_per_cu, nblk);
   }
 }
 
-template <typename R, bool ADJ, int GK>
+template <typename R, bool ADJ>
+int life_grid(int kind, bool inst, int blocks_per_cu, int* nblk) {
+  return inst ? life_grid_c<R, ADJ, true>(kind, blocks_per_cu, nblk)
+             : life_grid_c<R, ADJ, false>(kind, blocks_per_cu, nblk);
+}
+
+template <typename R, bool ADJ, int GK, bool INST>
 void launch_life_k(const RunParams& P, int nblk, hipStream_t st) {
   if constexpr (std::is_same<R, double>::value)
-    hipLaunchKernelGGL((k_life64<ADJ, GK>), dim3(nblk), dim3(kBlock), 0, st, P);
+    hipLaunchKernelGGL((k_life64<ADJ, GK, INST>), dim3(nblk), dim3(kBlock), 0, st, P);
   else
-    hipLaunchKernelGGL((k_life<R, ADJ, GK>), dim3(nblk), dim3(kBlock), 0, st, P);
+    hipLaunchKernelGGL((k_life<R, ADJ, GK, INST>), dim3(nblk), dim3(kBlock), 0, st, P);
+}
+
+template <typename R, bool ADJ, bool INST>
+void launch_life_c(const RunParams& P, int nblk, hipStream_t st) {
+  if (P.G.kind == kGridRect)
+    launch_life_k<R, ADJ, kGridRect, INST>(P, nblk, st);
+  else if (P.G.kind == kGridTree)
+    launch_life_k<R, ADJ, kGridTree, INST>(P, nblk, st);
+  else
+    launch_life_k<R, ADJ, kGridRegular, INST>(P, nblk, st);
 }
 
 template <typename R, bool ADJ>
-int launch_life(const RunParams& P, int nblk, hipStream_t st) {
-  if (P.G.kind == kGridRect)
-    launch_life_k<R, ADJ, kGridRect>(P, nblk, st);
-  else if (P.G.kind == kGridTree)
-    launch_life_k<R, ADJ, kGridTree>(P, nblk, st);
+int launch_life(const RunParams& P, bool inst, int nblk, hipStream_t st) {
+  if (inst)
+    launch_life_c<R, ADJ, true>(P, nblk, st);
   else
-    launch_life_k<R, ADJ, kGridRegular>(P, nblk, st);
+    launch_life_c<R, ADJ, false>(P, nblk, st);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -1201,9 +1217,11 @@ int launch_life(const RunParams& P, int nblk, hipStream_t st) {
 // Events per package kept in the adjoint's event scratch (more are walked
 // again in pass B), and the sizes of that scratch and of the peel-ray queue
 // that bound a chunk of packages (each at most a quarter of the free device
-// memory).
+// memory).  Every chunk costs its launches' tails (a persistent kernel ends
+// with few waves busy), so the budgets are large: the 1e7-package spiral
+// runs in one chunk of each.
 constexpr int kEventsKept = 32;
-constexpr size_t kScratchBytes = size_t(1) << 32, kQueueBytes = size_t(1) << 33;
+constexpr size_t kScratchBytes = size_t(1) << 34, kQueueBytes = size_t(1) << 34;
 
 // Shared driver of run_photons and backward_density.
 int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
@@ -1230,10 +1248,12 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const bool f32 = opts->precision == MCRT_PREC_FP32;
   int nblk = 0;
   const int kind = P.G.kind;
-  if (int e = adjoint ? (f32 ? life_grid<float, true>(kind, opts->launch_blocks, &nblk)
-                             : life_grid<double, true>(kind, opts->launch_blocks, &nblk))
-                      : (f32 ? life_grid<float, false>(kind, opts->launch_blocks, &nblk)
-                             : life_grid<double, false>(kind, opts->launch_blocks, &nblk)))
+  bool inst = false;  // instruments other than frames (SED, camera): the kernels that handle them
+  for (int d = 0; d < n_det; ++d) inst = inst || pr.det[d].kind != kDetFrame;
+  if (int e = adjoint ? (f32 ? life_grid<float, true>(kind, inst, opts->launch_blocks, &nblk)
+                             : life_grid<double, true>(kind, inst, opts->launch_blocks, &nblk))
+                      : (f32 ? life_grid<float, false>(kind, inst, opts->launch_blocks, &nblk)
+                             : life_grid<double, false>(kind, inst, opts->launch_blocks, &nblk)))
     return e;
   // packages run in equal chunks: the adjoint's event scratch holds, per
   // package, T and q per frame for kEventsKept events plus the sum of q
@@ -1347,18 +1367,16 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   }
   int rc = 0;
   unsigned long long launches = 0;  // of the life-cycle kernel
-  bool cam = false;                 // a perspective instrument among the frames
-  for (int d = 0; d < n_det; ++d) cam = cam || pr.det[d].kind == kDetPerspective;
   auto queue_phase = [&](bool adj) -> int {  // sort and walk the chunk's queued peel rays
     if (stats) {
       qev.push_back(nullptr);
       HIPCHK(hipEventCreate(&qev.back()));
       HIPCHK(hipEventRecord(qev.back(), st));
     }
-    const int r = adj ? (f32 ? run_peel_jobs<float, true>(queue, P, ctr, cam, st)
-                             : run_peel_jobs<double, true>(queue, P, ctr, cam, st))
-                      : (f32 ? run_peel_jobs<float, false>(queue, P, ctr, cam, st)
-                             : run_peel_jobs<double, false>(queue, P, ctr, cam, st));
+    const int r = adj ? (f32 ? run_peel_jobs<float, true>(queue, P, ctr, inst, st)
+                             : run_peel_jobs<double, true>(queue, P, ctr, inst, st))
+                      : (f32 ? run_peel_jobs<float, false>(queue, P, ctr, inst, st)
+                             : run_peel_jobs<double, false>(queue, P, ctr, inst, st));
     if (r) return r;
     if (stats) {
       qev.push_back(nullptr);
@@ -1373,7 +1391,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
       P.n_chunk = std::min(chunk, P.n_items - c0);
       if (int e = reset_counters(ctr, 0, 1, st)) return e;
       if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
-      rc = f32 ? launch_life<float, false>(P, nblk, st) : launch_life<double, false>(P, nblk, st);
+      rc = f32 ? launch_life<float, false>(P, inst, nblk, st) : launch_life<double, false>(P, inst, nblk, st);
       if (rc) return rc;
       ++launches;
       if (P.jobs)
@@ -1391,14 +1409,14 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
       if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
       if (int e = reset_counters(ctr, kDepCounter, 1, st)) return e;
       P.split = 1;  // pass A
-      rc = f32 ? launch_life<float, true>(P, nblk, st) : launch_life<double, true>(P, nblk, st);
+      rc = f32 ? launch_life<float, true>(P, inst, nblk, st) : launch_life<double, true>(P, inst, nblk, st);
       if (rc) return rc;
       ++launches;
       if (P.jobs)
         if (int e = queue_phase(true)) return e;
       if (int e = reset_counters(ctr, 0, 1, st)) return e;
       P.split = 2;  // pass B
-      rc = f32 ? launch_life<float, true>(P, nblk, st) : launch_life<double, true>(P, nblk, st);
+      rc = f32 ? launch_life<float, true>(P, inst, nblk, st) : launch_life<double, true>(P, inst, nblk, st);
       if (rc) return rc;
       ++launches;
       if (optg) {

@@ -182,6 +182,20 @@ MCRT_HD void lane_init(Lane<R>& L) {
 // for the event and skips its peel-offs; events beyond the scratch walk
 // their peel rays again.  Called once the event's next phase is set: events
 // without peel-off (the flags exclude it) have G_e = 0.
+// Peel-off geometry for accessor Mem: the camera path only where the run
+// has instruments other than frames (Mem::kInst), else the distant
+// observer's.
+template <class Mem>
+MCRT_HD void peel_geom(const DetDev& D, const double r[3], double kd[3], double& inv_d2, double& tmax) {
+  if constexpr (Mem::kInst) {
+    peel_geometry(D, r, kd, inv_d2, tmax);
+  } else {
+    for (int a = 0; a < 3; ++a) kd[a] = D.kd[a];
+    inv_d2 = D.inv_d2;
+    tmax = INFINITY;
+  }
+}
+
 // Pass B of a run with optics gradients: a peel-off contribution q of the
 // current event towards frame d.  The event's scattering count n, its
 // direction scores so far and its peel phase give q's factors: n (albedo),
@@ -192,7 +206,7 @@ MCRT_HD void optics_add(Lane<R>& L, Mem& M, int d, double q) {
   L.GL += q;
   if (!L.is_emit) {
     double kd[3], inv_d2, tmax;
-    peel_geometry(M.det(d), L.r, kd, inv_d2, tmax);
+    peel_geom<Mem>(M.det(d), L.r, kd, inv_d2, tmax);
     L.Gg += q * (L.Sg + hg_dlng(L.g, L.k[0] * kd[0] + L.k[1] * kd[1] + L.k[2] * kd[2]));
   }
 }
@@ -246,7 +260,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     if (L.phase == PH_PEEL_END) {
       const DetDev& D = M.det(L.det);
       double kd[3], inv_d2, tmax;
-      peel_geometry(D, L.r, kd, inv_d2, tmax);
+      peel_geom<Mem>(D, L.r, kd, inv_d2, tmax);
       const double ph = L.is_emit ? 1.0 / (4.0 * kPi)
                                   : hg_phase(L.g, L.k[0] * kd[0] + L.k[1] * kd[1] + L.k[2] * kd[2]);
       const double C = L.W * ph * exp(-(double)L.ry.tau) * inv_d2;
@@ -341,19 +355,19 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     if (L.phase == PH_PEEL_NEXT && !want) {
       while (L.det < P.n_det) {
         const DetDev& D = M.det(L.det);
-        L.pix = frame_pixel(D, L.r);
+        L.pix = frame_pixel<Mem::kInst>(D, L.r);
         if (L.pix >= 0) {
           if (!P.jobs || L.pass != 0) break;
           const unsigned long long slot = M.job_slot();
           if (slot >= P.job_cap) break;  // queue full: walk it here
           // queued: C = v e^-tau is completed by the queue's walk kernel
           double kd[3], inv_d2, tmax;
-          peel_geometry(D, L.r, kd, inv_d2, tmax);
+          peel_geom<Mem>(D, L.r, kd, inv_d2, tmax);
           const double ph = L.is_emit ? 1.0 / (4.0 * kPi)
                                       : hg_phase(L.g, L.k[0] * kd[0] + L.k[1] * kd[1] + L.k[2] * kd[2]);
           const int comp = ((P.flags & kFlagSplit) && !L.is_emit) ? 1 : 0;
           const long long ii = ((long long)comp * P.n_lambda + L.lam) * P.pix_lambda + D.off + L.pix;
-          const int kp = key_pixel(D, L.r, L.pix);
+          const int kp = key_pixel<Mem::kInst>(D, L.r, L.pix);
           M.store_job(slot, L.r, L.W * ph * inv_d2, ii, tile_key(D, kp), tile_sub(D, kp), (unsigned)L.slot,
                       L.n < kEventSat ? L.n : kEventSat, L.det,
                       (unsigned)L.lam);
@@ -487,7 +501,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     //    its end is handled in the next pass)
     if (want) {
       double kd[3], inv_d2, tmax = INFINITY;
-      if (to_det) peel_geometry(M.det(L.det), L.r, kd, inv_d2, tmax);
+      if (to_det) peel_geom<Mem>(M.det(L.det), L.r, kd, inv_d2, tmax);
       ray_begin<R, Mem::kGrid>(L.ry, G, L.r, to_det ? kd : L.k, tmax);
       if (L.mode == M_LOCATE) {
         L.last_cell = ray_cell(L.ry, G);
@@ -535,7 +549,7 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
 #pragma unroll
   for (int d = 0; d < kBlockWalk; ++d) {
     if (d >= b.n) break;
-    const R tm = b.tend[d] > ry.tmax ? ry.tmax : b.tend[d];  // a peel walk to a camera stops there
+    const R tm = (Mem::kInst && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];  // a peel walk to a camera stops there
     R seg = tm - ry.t;
     const bool pos = seg > R(0);
     seg = pos ? seg : R(0);
@@ -586,7 +600,7 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
     ry.tau += dtau;
     if (pos) ry.t = tm;
   }
-  if (b.out || ry.t >= ry.tmax) ry.active = false;
+  if (b.out || (Mem::kInst && ry.t >= ry.tmax)) ry.active = false;
 }
 
 // ---------------------------------------------------------------------------
@@ -595,9 +609,9 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
 // sum -- and bp_step the walk of the inline M_PEEL_DEP mode without density
 // loads (its deposits w l do not depend on the densities); every deposit
 // goes through M.deposit(cell, v).  Each advances the ray by one block and
-// returns its positive-length crossings.  CAM = false compiles out the stop
-// at a camera inside the grid (no perspective instrument in the call).
-template <typename R, class Mem, bool CAM = true>
+// returns its positive-length crossings.  INST = false (frames only)
+// compiles out the stop at a camera inside the grid.
+template <typename R, class Mem, bool INST = true>
 MCRT_HD unsigned tau_step(Ray<R>& ry, const GridDev& G, R kap, Mem& M) {
   WalkBlock<kBlockWalk, R> b;
   ray_next_block(ry, b, G, M);
@@ -605,7 +619,7 @@ MCRT_HD unsigned tau_step(Ray<R>& ry, const GridDev& G, R kap, Mem& M) {
 #pragma unroll
   for (int d = 0; d < kBlockWalk; ++d) {
     if (d >= b.n) break;
-    const R tm = (CAM && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];
+    const R tm = (INST && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];
     R seg = tm - ry.t;
     const bool pos = seg > R(0);
     seg = pos ? seg : R(0);
@@ -614,11 +628,11 @@ MCRT_HD unsigned tau_step(Ray<R>& ry, const GridDev& G, R kap, Mem& M) {
     ry.tau += dtau;
     if (pos) ry.t = tm;
   }
-  if (b.out || (CAM && ry.t >= ry.tmax)) ry.active = false;
+  if (b.out || (INST && ry.t >= ry.tmax)) ry.active = false;
   return n;
 }
 
-template <typename R, class Mem, bool CAM = true>
+template <typename R, class Mem, bool INST = true>
 MCRT_HD unsigned bp_step(Ray<R>& ry, const GridDev& G, double w, Mem& M) {
   WalkBlock<kBlockWalk, R> b;
   ray_next_block<kBlockWalk, R, Mem, false>(ry, b, G, M);
@@ -626,7 +640,7 @@ MCRT_HD unsigned bp_step(Ray<R>& ry, const GridDev& G, double w, Mem& M) {
 #pragma unroll
   for (int d = 0; d < kBlockWalk; ++d) {
     if (d >= b.n) break;
-    const R tm = (CAM && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];
+    const R tm = (INST && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];
     const R seg = tm - ry.t;
     if (seg > R(0)) {
       M.deposit(b.cell[d], w * (double)seg);
@@ -634,7 +648,7 @@ MCRT_HD unsigned bp_step(Ray<R>& ry, const GridDev& G, double w, Mem& M) {
       ry.t = tm;
     }
   }
-  if (b.out || (CAM && ry.t >= ry.tmax)) ry.active = false;
+  if (b.out || (INST && ry.t >= ry.tmax)) ry.active = false;
   return n;
 }
 

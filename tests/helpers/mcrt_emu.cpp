@@ -104,9 +104,10 @@ struct HostPlanes {
   }
 };
 
-template <typename R, int GK>
+template <typename R, int GK, bool INST>
 struct HostLifeMem {
   static constexpr int kGrid = GK;
+  static constexpr bool kInst = INST;
   const R* rho_;
   const GridDev& G;
   const host::Prepared& pr;
@@ -281,8 +282,8 @@ struct HostBundleMem {
 // each ray in sorted order: the optical-depth walk; forward, C into its
 // pixel; adjoint, q = (dL/dI) C into the event scratch and, for q != 0, the
 // deposit walk.  Returns the crossings; `deps` gets the deposits.
-template <typename R, bool ADJ, int GK>
-unsigned long long emu_peel_jobs(HostLifeMem<R, GK>& M, const RunParams& P, std::vector<PeelJob>& jobs,
+template <typename R, bool ADJ, int GK, bool INST>
+unsigned long long emu_peel_jobs(HostLifeMem<R, GK, INST>& M, const RunParams& P, std::vector<PeelJob>& jobs,
                                  unsigned long long n_jobs, std::vector<double>& grad, unsigned long long& deps,
                                  long long cap_steps) {
   const long long n_keys = M.n_keys;
@@ -346,13 +347,13 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, GK>& M, const RunParams& P, std:
     Ray<R> ry;
     {
       double kd[3], inv_d2, tmax;
-      peel_geometry(M.det(J.d), J.r, kd, inv_d2, tmax);
+      peel_geom<HostLifeMem<R, GK, INST>>(M.det(J.d), J.r, kd, inv_d2, tmax);
       ray_begin<R, GK>(ry, P.G, J.r, kd, tmax);
     }
     const R kap = (R)M.lam((int)J.lam).kappa;
     long long steps = 0;
     while (ry.active) {
-      nx += tau_step<R>(ry, P.G, kap, M);
+      nx += tau_step<R, HostLifeMem<R, GK, INST>, INST>(ry, P.G, kap, M);
       if (++steps > cap_steps) throw Violation("a peel-job walk exceeded the grid's crossing bound");
     }
     const double C = J.v * exp(-(double)ry.tau);
@@ -369,12 +370,12 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, GK>& M, const RunParams& P, std:
     const double w = -q * M.lam((int)J.lam).kappa;
     {
       double kd[3], inv_d2, tmax;
-      peel_geometry(M.det(J.d), J.r, kd, inv_d2, tmax);
+      peel_geom<HostLifeMem<R, GK, INST>>(M.det(J.d), J.r, kd, inv_d2, tmax);
       ray_begin<R, GK>(ry, P.G, J.r, kd, tmax);
     }
     steps = 0;
     while (ry.active) {
-      const unsigned n = bp_step<R>(ry, P.G, w, D);
+      const unsigned n = bp_step<R, HostBundleMem<GK>, INST>(ry, P.G, w, D);
       nx += n;
       deps += n;
       if (++steps > cap_steps) throw Violation("a deposit walk exceeded the grid's crossing bound");
@@ -383,7 +384,7 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, GK>& M, const RunParams& P, std:
   return nx;
 }
 
-template <typename R, bool ADJ, int GK>
+template <typename R, bool ADJ, int GK, bool INST>
 int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, int n_src, const mcrt_source* sources,
              int n_det, const mcrt_detector* detectors, const mcrt_opts* opts, double* images, long long n_images,
              double* absorbed, long long n_absorbed, const double* adj, long long n_adj, double* grad, long long n_grad,
@@ -426,7 +427,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   const std::vector<R> rho_b = brick_copy(P.G, static_cast<const R*>(rho));
   std::vector<double> abs_b(P.absorbed ? (size_t)P.n_lambda * P.G.ncell_pad : 0, 0.0);
   std::vector<double> grad_b(ADJ && grad ? (size_t)P.G.ncell_pad : 0, 0.0);
-  HostLifeMem<R, GK> M{rho_b.data(), P.G, pr, images, n_images, P.absorbed ? abs_b.data() : nullptr,
+  HostLifeMem<R, GK, INST> M{rho_b.data(), P.G, pr, images, n_images, P.absorbed ? abs_b.data() : nullptr,
                    (long long)abs_b.size(), adj, n_adj, grad_b.data(), (long long)grad_b.size()};
   P.absorbed = M.absorbed;
   if (images && !ADJ) std::fill(images, images + n_images, 0.0);
@@ -494,7 +495,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   auto queue_phase = [&]() {
     unsigned long long deps = 0;
     const unsigned long long nx =
-        emu_peel_jobs<R, ADJ, GK>(M, P, jobs, std::min(M.job_next, M.job_cap), grad_b, deps, cap);
+        emu_peel_jobs<R, ADJ, GK, INST>(M, P, jobs, std::min(M.job_next, M.job_cap), grad_b, deps, cap);
     M.x_queue += nx;
     M.d_queue += deps;
   };
@@ -710,16 +711,21 @@ inline int grid_kind(const mcrt_grid* g) {
   return !g ? kGridRegular : (g->tree_nodes > 0 ? kGridTree : (g->planes ? kGridRect : kGridRegular));
 }
 
-template <bool ADJ, typename R, typename... A>
+template <bool ADJ, typename R, bool INST, typename... A>
 int life_kind(int kind, A... args) {
-  if (kind == kGridRect) return emu_life<R, ADJ, kGridRect>(args...);
-  if (kind == kGridTree) return emu_life<R, ADJ, kGridTree>(args...);
-  return emu_life<R, ADJ, kGridRegular>(args...);
+  if (kind == kGridRect) return emu_life<R, ADJ, kGridRect, INST>(args...);
+  if (kind == kGridTree) return emu_life<R, ADJ, kGridTree, INST>(args...);
+  return emu_life<R, ADJ, kGridRegular, INST>(args...);
 }
 
+// As the library: the variant of the kernels that handles SED instruments
+// and cameras only when one is among the frames.
 template <bool ADJ, typename... A>
-int life_dispatch(bool f32, int kind, A... args) {
-  return f32 ? life_kind<ADJ, float>(kind, args...) : life_kind<ADJ, double>(kind, args...);
+int life_dispatch(bool f32, int kind, int n_det, const mcrt_detector* dets, A... args) {
+  bool inst = false;
+  for (int d = 0; d < n_det && dets; ++d) inst = inst || dets[d].kind != MCRT_DET_FRAME;
+  if (inst) return f32 ? life_kind<ADJ, float, true>(kind, args...) : life_kind<ADJ, double, true>(kind, args...);
+  return f32 ? life_kind<ADJ, float, false>(kind, args...) : life_kind<ADJ, double, false>(kind, args...);
 }
 
 template <typename R, typename... A>
@@ -773,7 +779,8 @@ int emu_run_photons(const mcrt_grid* grid, const void* rho, const mcrt_optics* o
     g_violation.clear();
     host::last_error().clear();
     if (!opts) return host::fail(MCRT_EINVAL, "opts is NULL");
-    return life_dispatch<false>(opts->precision == MCRT_PREC_FP32, grid_kind(grid), grid, rho, optics, n_src,
+    return life_dispatch<false>(opts->precision == MCRT_PREC_FP32, grid_kind(grid), n_det, detectors, grid, rho,
+                                optics, n_src,
                                 sources, n_det, detectors, opts, images, n_images, absorbed, n_absorbed,
                                 (const double*)nullptr, 0ll, (double*)nullptr, 0ll, (double*)nullptr, stats, wave);
   } catch (const Violation& v) {
@@ -792,7 +799,8 @@ int emu_backward_density(const mcrt_grid* grid, const void* rho, const mcrt_opti
     if (!opts) return host::fail(MCRT_EINVAL, "opts is NULL");
     mcrt_opts o = *opts;
     o.flags &= ~MCRT_ABSORB;
-    return life_dispatch<true>(o.precision == MCRT_PREC_FP32, grid_kind(grid), grid, rho, optics, n_src, sources,
+    return life_dispatch<true>(o.precision == MCRT_PREC_FP32, grid_kind(grid), n_det, detectors, grid, rho, optics,
+                               n_src, sources,
                                n_det, detectors, (const mcrt_opts*)&o, (double*)nullptr, 0ll, (double*)nullptr, 0ll,
                                adj, n_adj, grad, n_grad, gopt, stats, wave);
   } catch (const Violation& v) {
