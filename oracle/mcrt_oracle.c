@@ -685,6 +685,7 @@ typedef struct {
     unsigned flags;
     int mode;
     const double *adj; /* GRAD: dL/dI, same layout as the images */
+    const double *adj_abs; /* GRAD: dL/dA of the absorbed tally [n_lambda][ncell], or NULL */
     /* REWEIGHT: albedo [n_lambda], g [n_lambda] and source luminosities
      * [n_src][n_lambda] at which weights are evaluated (NULL: the sampling
      * values) */
@@ -696,6 +697,7 @@ typedef struct {
     int event;    /* 0 = emission, i >= 1 = scattering i */
     double a_c;   /* dL/dI at the pixel times the contribution */
     double dlng;  /* d ln(contribution) / dg: scores of the sampled directions and the peel phase */
+    int absorbed; /* 1: the absorbed-tally term of the path after the event (images' optics gradients skip it) */
     size_t beg, end; /* peel segments inside the peel buffer */
 } contrib_t;
 
@@ -779,6 +781,7 @@ static void peel_event(const problem_t *P, accum_t *A, int l, int event, const d
                 C->event = event;
                 C->a_c = P->adj[ii] * c;
                 C->dlng = k_in ? score + hg_dlng(g, k_in[0] * kd[0] + k_in[1] * kd[1] + k_in[2] * kd[2]) : 0.0;
+                C->absorbed = 0;
                 C->beg = A->gpeel.n;
                 for (size_t j = 0; j < A->peel.n; j++)
                     sb_push(&A->gpeel, A->peel.v[j].cell, A->peel.v[j].t0, A->peel.v[j].t1);
@@ -807,12 +810,14 @@ static void grad_flush_package(const problem_t *P, accum_t *A, int l, int src)
     for (int q = 0; q < A->ncon; q++) {
         const contrib_t *C = &A->con[q];
         if (C->a_c == 0.0) continue;
+        if (C->absorbed) goto legs; /* the optics gradients are those of the image loss */
         /* optics and luminosity: a contribution after n scatterings scales as
          * albedo^n, with the scores of its sampled directions and its peel
          * phase in g, and as the luminosity of its package's source */
         if (alb > 0.0) A->gopt[0] += C->a_c * C->event / alb;
         A->gopt[1] += C->a_c * C->dlng;
         if (lum > 0.0) A->gopt[2 + src] += C->a_c / lum;
+    legs:
         for (int i = 1; i <= C->event; i++) {
             int64_t c = A->leg_cell[i];
             A->grad[c] += C->a_c / P->rho[c];
@@ -910,16 +915,60 @@ static void run_package(const problem_t *P, accum_t *A, uint64_t p, int l)
         }
         /* continuous absorption along the whole path */
         {
-            double tau = 0.0;
+            double tau = 0.0, tau_eval = 0.0;
             for (size_t j = 0; j < A->path.n; j++) {
                 const seg_t *s = &A->path.v[j];
                 double dtau = kappa * P->rho[s->cell] * (s->t1 - s->t0);
                 double dep = w * (1.0 - alb) * exp(-tau) * (-expm1(-dtau));
                 A->stats[ST_ABSORBED] += dep;
-                if (A->absorbed) A->absorbed[s->cell] += dep;
+                if (A->absorbed && P->mode != MODE_REWEIGHT) A->absorbed[s->cell] += dep;
+                if (A->absorbed && P->mode == MODE_REWEIGHT) { /* the same deposits at rho_eval, weight w_eval */
+                    double dte = kappa * P->rho_eval[s->cell] * (s->t1 - s->t0);
+                    A->absorbed[s->cell] += w_eval * (1.0 - (P->alb_eval ? P->alb_eval[l] : alb)) * exp(-tau_eval) *
+                                            (-expm1(-dte));
+                    tau_eval += dte;
+                }
                 tau += dtau;
             }
             A->stats[ST_ESCAPED] += w * exp(-T);
+        }
+        /* the absorbed tally's adjoint (GRAD with adj_abs): the path's deposits
+         * dep_j = w (1 - albedo) e^-tau_{j-1} (1 - e^-dtau_j) weighted by
+         * b = dL/dA of their cells sum to B; with paths held fixed, B carries
+         * the density dependence of the weight w (the legs up to this event,
+         * as a contribution of this event does), and each deposit that of its
+         * own factor: -kappa l_k for every cell k crossed before it and
+         * kappa l_j e^-dtau_j / (1 - e^-dtau_j) for its own cell.  Summed over
+         * the path: cell k of segment j_k gets -kappa l_k (B - P_k), P_k the
+         * sum of b dep up to and including segment j_k, plus
+         * b_k w (1 - albedo) e^-tau_{j_k - 1} e^-dtau_k kappa l_k. */
+        if (P->mode == MODE_GRAD && P->adj_abs) {
+            const double *b = P->adj_abs + (size_t)l * G->ncell;
+            double B = 0.0, tau = 0.0;
+            for (size_t j = 0; j < A->path.n; j++) {
+                const seg_t *s = &A->path.v[j];
+                double dtau = kappa * P->rho[s->cell] * (s->t1 - s->t0);
+                B += b[s->cell] * w * (1.0 - alb) * exp(-tau) * (-expm1(-dtau));
+                tau += dtau;
+            }
+            double Pk = 0.0;
+            tau = 0.0;
+            for (size_t j = 0; j < A->path.n; j++) {
+                const seg_t *s = &A->path.v[j];
+                double len = s->t1 - s->t0, dtau = kappa * P->rho[s->cell] * len;
+                Pk += b[s->cell] * w * (1.0 - alb) * exp(-tau) * (-expm1(-dtau));
+                A->grad[s->cell] += -kappa * len * (B - Pk) +
+                                    b[s->cell] * w * (1.0 - alb) * exp(-tau) * exp(-dtau) * kappa * len;
+                tau += dtau;
+            }
+            if (B != 0.0) {
+                contrib_t *C = grad_new_contrib(A);
+                C->event = n;
+                C->a_c = B;
+                C->dlng = 0.0;
+                C->absorbed = 1;
+                C->beg = C->end = A->gpeel.n;
+            }
         }
         /* forced scattering: interaction point */
         draw(P->seed, p, (uint32_t)l, 2u + (uint32_t)n, u);
@@ -1176,13 +1225,16 @@ int oracle_run(const double box[6], const int n[3], const double *rho, int n_lam
  * luminosity of its package's source (weight L_total / N times choice
  * probability L_s / L_total; d/dL_s = C / L_s, reported 0 for a dark
  * source).  Check: finite differences of the reweighted estimator in each
- * parameter, and the linear cases (one scattering at most; one source). */
+ * parameter, and the linear cases (one scattering at most; one source).
+ * adj_abs non-NULL ([n_lambda][ncell], dL/dA): the loss also has a term in
+ * the absorbed tally, and the density gradient includes it (the optics
+ * gradients stay those of the images). */
 int oracle_grad(const double box[6], const int n[3], const double *rho, int n_lambda, const double *kappa,
                 const double *albedo, const double *g, int n_src, const int *src_kind, const double *src_par,
                 const double *src_lum, int n_det, const double *det_par, const int *det_pix, uint64_t n_pkg,
                 uint64_t first, uint64_t seed, double w_min, int max_scatter, unsigned flags, const double *adj,
                 double *images, double *grad, double *stats, int n_threads, const double *planes,
-                const double *tree, const double *cell_lum, double *grad_opt)
+                const double *tree, const double *cell_lum, double *grad_opt, const double *adj_abs)
 {
     problem_t P;
     if (setup_problem(&P, box, n, rho, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
@@ -1190,6 +1242,7 @@ int oracle_grad(const double box[6], const int n[3], const double *rho, int n_la
         return -1;
     P.mode = MODE_GRAD;
     P.adj = adj;
+    P.adj_abs = adj_abs;
     int rc = simulate(&P, images, NULL, grad, grad_opt, stats, n_threads);
     problem_free(&P);
     return rc;
@@ -1201,14 +1254,15 @@ int oracle_grad(const double box[6], const int n[3], const double *rho, int n_la
  * source luminosities alb_eval, g_eval, lum_eval when given (NULL: the
  * sampling values): weights carry (albedo_eval)^n, the ratios of the HG
  * densities of the sampled directions and the peel phase at g_eval, and
- * the ratio of the package source's luminosities. */
+ * the ratio of the package source's luminosities.  absorbed non-NULL
+ * ([n_lambda][ncell]): the absorbed tally of the same estimator. */
 int oracle_reweight(const double box[6], const int n[3], const double *rho0, const double *rho, int n_lambda,
                     const double *kappa, const double *albedo, const double *g, int n_src, const int *src_kind,
                     const double *src_par, const double *src_lum, int n_det, const double *det_par,
                     const int *det_pix, uint64_t n_pkg, uint64_t first, uint64_t seed, double w_min,
                     int max_scatter, unsigned flags, double *images, double *stats, int n_threads,
                     const double *planes, const double *tree, const double *cell_lum, const double *alb_eval,
-                    const double *g_eval, const double *lum_eval)
+                    const double *g_eval, const double *lum_eval, double *absorbed)
 {
     problem_t P;
     if (setup_problem(&P, box, n, rho0, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
@@ -1219,7 +1273,7 @@ int oracle_reweight(const double box[6], const int n[3], const double *rho0, con
     P.alb_eval = alb_eval;
     P.g_eval = g_eval;
     P.lum_eval = lum_eval;
-    int rc = simulate(&P, images, NULL, NULL, NULL, stats, n_threads);
+    int rc = simulate(&P, images, absorbed, NULL, NULL, stats, n_threads);
     problem_free(&P);
     return rc;
 }

@@ -55,10 +55,10 @@ def _load():
         common = [P, P, P, i, P, P, P, i, P, P, P, i, P, P, u64, u64, u64, d, i, C.c_uint]
         _lib.oracle_run.argtypes = common + [P, P, P, i, P, P, P]
         _lib.oracle_run.restype = i
-        _lib.oracle_grad.argtypes = common + [P, P, P, P, i, P, P, P, P]
+        _lib.oracle_grad.argtypes = common + [P, P, P, P, i, P, P, P, P, P]
         _lib.oracle_grad.restype = i
         _lib.oracle_reweight.argtypes = [P, P, P, P, i, P, P, P, i, P, P, P, i, P, P, u64, u64, u64, d, i,
-                                         C.c_uint, P, P, i, P, P, P, P, P, P]
+                                         C.c_uint, P, P, i, P, P, P, P, P, P, P]
         _lib.oracle_reweight.restype = i
         _lib.oracle_trace.argtypes = [P, P, P, d, i64, P, P, P, i, P, P, P, P, P]
         _lib.oracle_trace.restype = i64
@@ -225,10 +225,11 @@ def run(prob, threads=1):
     return images, absorbed, dict(zip(STAT_NAMES, stats.tolist()))
 
 
-def grad(prob, adj, threads=1, optics=False):
-    """Detached gradient dL/drho for dL/dI = adj (same layout as the images).
-    optics=True also returns {"albedo": [n_lambda], "g": [n_lambda],
-    "lum": [n_src][n_lambda]} as a fourth value."""
+def grad(prob, adj, threads=1, optics=False, adj_absorbed=None):
+    """Detached gradient dL/drho for dL/dI = adj (same layout as the images)
+    and, if given, dL/dA = adj_absorbed [n_lambda][ncell] on the absorbed
+    tally.  optics=True also returns {"albedo": [n_lambda], "g": [n_lambda],
+    "lum": [n_src][n_lambda]} (of the image term) as a fourth value."""
     args, keep, nl, npix = _marshal(prob)
     ncell = keep[2].size
     adj = _f64(adj).reshape(_comps(prob), nl, npix)
@@ -237,8 +238,9 @@ def grad(prob, adj, threads=1, optics=False):
     stats = np.zeros(len(STAT_NAMES))
     n_src = len(prob["sources"])
     gopt = np.zeros((2 + n_src, nl)) if optics else None
+    aa = None if adj_absorbed is None else _f64(adj_absorbed).reshape(nl, ncell)
     rc = _load().oracle_grad(*args, _ptr(adj), _ptr(images), _ptr(g), _ptr(stats), int(threads), _ptr(keep[11]),
-                            _ptr(keep[12]), _ptr(keep[13]), _ptr(gopt))
+                            _ptr(keep[12]), _ptr(keep[13]), _ptr(gopt), _ptr(aa))
     if rc != 0:
         raise ValueError("oracle_grad rejected its arguments")
     if optics:
@@ -246,10 +248,11 @@ def grad(prob, adj, threads=1, optics=False):
     return g, images, dict(zip(STAT_NAMES, stats.tolist()))
 
 
-def reweight(prob, rho_eval, threads=1, albedo_eval=None, g_eval=None, lum_eval=None):
+def reweight(prob, rho_eval, threads=1, albedo_eval=None, g_eval=None, lum_eval=None, absorbed=False):
     """Images of paths sampled at prob's parameters with weights evaluated at
     rho_eval (and at albedo_eval, g_eval [n_lambda], lum_eval [n_src][n_lambda]
-    when given)."""
+    when given); absorbed=True returns (images, absorbed [n_lambda][ncell],
+    stats)."""
     args, keep, nl, npix = _marshal(prob)
     rho_eval = _f64(rho_eval).reshape(-1)
     assert rho_eval.size == keep[2].size
@@ -259,10 +262,13 @@ def reweight(prob, rho_eval, threads=1, albedo_eval=None, g_eval=None, lum_eval=
     ae = None if albedo_eval is None else _f64(albedo_eval).reshape(nl)
     ge = None if g_eval is None else _f64(g_eval).reshape(nl)
     le = None if lum_eval is None else _f64(lum_eval).reshape(len(prob["sources"]), nl)
+    ab = np.zeros((nl, keep[2].size)) if absorbed else None
     rc = _load().oracle_reweight(*a, _ptr(images), _ptr(stats), int(threads), _ptr(keep[11]),
-                                 _ptr(keep[12]), _ptr(keep[13]), _ptr(ae), _ptr(ge), _ptr(le))
+                                 _ptr(keep[12]), _ptr(keep[13]), _ptr(ae), _ptr(ge), _ptr(le), _ptr(ab))
     if rc != 0:
         raise ValueError("oracle_reweight rejected its arguments")
+    if absorbed:
+        return images, ab, dict(zip(STAT_NAMES, stats.tolist()))
     return images, dict(zip(STAT_NAMES, stats.tolist()))
 
 

@@ -1,13 +1,14 @@
 """torch.autograd interface of the life cycle: images as a differentiable
-function of the cell densities.
+function of the cell densities (RTImage), and of the densities, albedo, g
+and source luminosities (RTImageOptics).
 
-Forward calls run_photons; backward calls backward_density, which replays
-every package from its random numbers and accumulates the detached
-(score-function) derivative of the images with respect to the density of
-each cell (the derivative of the reweighted estimator whose paths are held
-fixed).  Both run entirely in the HIP kernels.  The absorbed-luminosity
-tally is not differentiated.
+Forward calls run_photons; backward calls backward_density (or backward),
+which replays every package from its random numbers and accumulates the
+detached (score-function) derivative of the images -- the derivative of the
+reweighted estimator whose paths are held fixed.  Both run entirely in the
+HIP kernels.  The absorbed-luminosity tally is not differentiated.
 """
+import numpy as np
 import torch
 
 from . import binding
@@ -40,3 +41,43 @@ class RTImage(torch.autograd.Function):
 def render(prob, rho):
     """Differentiable images of the problem at density `rho`."""
     return RTImage.apply(rho, prob)
+
+
+class RTImageOptics(torch.autograd.Function):
+    """images = RTImageOptics.apply(rho, albedo, g, lum, prob): rho as in
+    RTImage; albedo and g [n_lambda] and lum [n_src][n_lambda] FP64 tensors
+    (their values replace the problem's; the library reads them on the
+    host).  Gradients flow to every input that requires them, from one
+    replay."""
+
+    @staticmethod
+    def forward(ctx, rho, albedo, g, lum, prob):
+        lum_h = lum.detach().to("cpu", torch.float64).numpy()
+        p = dict(prob, flags=int(prob.get("flags", 7)) & ~binding.ABSORB,
+                 albedo=albedo.detach().to("cpu", torch.float64).numpy().copy(),
+                 g=g.detach().to("cpu", torch.float64).numpy().copy(),
+                 sources=[dict(s, lum=np.array(lum_h[i])) for i, s in enumerate(prob["sources"])])
+        images = torch.empty(binding.image_shape(p), dtype=torch.float64, device=rho.device)
+        binding.run_photons(p, rho.contiguous(), images, None, stats=False)
+        ctx.prob = p
+        ctx.save_for_backward(rho, albedo, g, lum)
+        return images
+
+    @staticmethod
+    def backward(ctx, grad_images):
+        rho, albedo, g, lum = ctx.saved_tensors
+        need = ctx.needs_input_grad
+        dev = rho.device
+        outs = [torch.empty(t.numel(), dtype=torch.float64, device=dev) if need[i] else None
+                for i, t in enumerate((rho, albedo, g, lum))]
+        if not any(o is not None for o in outs):
+            return None, None, None, None, None
+        binding.backward(ctx.prob, rho.contiguous(), grad_images.contiguous().to(torch.float64), *outs, stats=False)
+        res = [None if o is None else o.to(t.dtype).view_as(t).to(t.device) for o, t in zip(outs, (rho, albedo, g, lum))]
+        return res[0], res[1], res[2], res[3], None
+
+
+def render_optics(prob, rho, albedo, g, lum):
+    """Differentiable images of the problem at density `rho`, albedo and g
+    per wavelength and source luminosities `lum` [n_src][n_lambda]."""
+    return RTImageOptics.apply(rho, albedo, g, lum, prob)

@@ -93,3 +93,32 @@ def test_adjoint_workload_with_optics_gradients(B, W):
          "dL/dg %.4e dL/dL %.4e" % ((t1 - t0) * 1e3, s1["kernel_ms"], (t2 - t1) * 1e3, s2["kernel_ms"],
                                     ga[0].item(), gg[0].item(), gl[0, 0].item()))
     assert np.isfinite([ga[0].item(), gg[0].item()]).all()
+
+
+def test_autograd_optics_matches_oracle(B, orc, W):
+    import torch
+    from paper_1410_1629_amd import autograd
+    _say("autograd RTImageOptics")
+    p = problems(W, "mixed", 0)
+    p["n_packages"] = 2000
+    img_o, _, _ = orc.run(p, threads=8)
+    target = torch.as_tensor(img_o * 0.7).cuda()
+    rho = B.density_tensor(p).requires_grad_(True)
+    albedo = torch.as_tensor(p["albedo"], dtype=torch.float64).requires_grad_(True)
+    g = torch.as_tensor(p["g"], dtype=torch.float64).requires_grad_(True)
+    lum = torch.as_tensor(np.stack([s["lum"] for s in p["sources"]]), dtype=torch.float64).requires_grad_(True)
+    images = autograd.render_optics(p, rho, albedo, g, lum)
+    loss = ((images - target) ** 2).sum()
+    loss.backward()
+    adj = 2 * (img_o - img_o * 0.7)
+    g_o, _, _, go = orc.grad(p, adj, threads=8, optics=True)
+    assert rel_l1(images.detach().cpu().numpy(), img_o) < 1e-10
+    assert rel_l1(rho.grad.cpu().numpy(), g_o) < 1e-9
+    assert rel_l1(albedo.grad.numpy(), go["albedo"]) < 1e-9
+    assert rel_l1(g.grad.numpy(), go["g"]) < 1e-9
+    assert rel_l1(lum.grad.numpy(), go["lum"]) < 1e-9
+    # only some inputs requiring gradients
+    albedo2 = albedo.detach().requires_grad_(True)
+    img2 = autograd.render_optics(p, rho.detach(), albedo2, g.detach(), lum.detach())
+    ((img2 - target) ** 2).sum().backward()
+    assert rel_l1(albedo2.grad.numpy(), go["albedo"]) < 1e-9
