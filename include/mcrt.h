@@ -312,14 +312,24 @@ int backward_density(const mcrt_grid *grid, const void *rho_dev, const mcrt_opti
  * uniform scaling of its cells).  Derivatives at albedo = 0 or at a dark
  * source are reported as 0 (no contribution carries them).  Device FP64
  * outputs, each overwritten, each NULL when not wanted:
- *   rho [ncell], albedo [n_lambda], g [n_lambda], lum [n_src][n_lambda]. */
+ *   rho [ncell], albedo [n_lambda], g [n_lambda], lum [n_src][n_lambda].
+ * adj_absorbed_dev (device FP64 [n_lambda][ncell], or NULL) adds a term
+ * sum b A to the loss, A the absorbed-luminosity tally of run_photons and b
+ * = dL/dA: every path's deposits dep_j = W (1 - albedo) e^-tau_{j-1}
+ * (1 - e^-dtau_j) (Sect. 1, continuous absorption) carry, with paths held
+ * fixed, the density dependence of their weight W (the legs before the
+ * path, as a peel-off contribution of the path's event does) and of their
+ * own factor: -kappa l_k for each cell k crossed before them and kappa l_j
+ * e^-dtau_j / (1 - e^-dtau_j) for their own cell.  It requires rho; the
+ * optics gradients stay those of the image term. */
 typedef struct {
     double *rho, *albedo, *g, *lum;
 } mcrt_grads;
 
 int backward(const mcrt_grid *grid, const void *rho_dev, const mcrt_optics *optics, int n_src,
              const mcrt_source *sources, int n_det, const mcrt_detector *detectors, const mcrt_opts *opts,
-             const double *adj_images_dev, const mcrt_grads *grads, mcrt_stats *stats_host, void *hip_stream);
+             const double *adj_images_dev, const double *adj_absorbed_dev, const mcrt_grads *grads,
+             mcrt_stats *stats_host, void *hip_stream);
 
 /* Dust emission (Sect. 1: absorption and re-emission by the dust; Sect. 2.1:
  * panchromatic simulations): the equilibrium temperature and the emission
@@ -354,7 +364,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 12
+#define MCRT_ABI_VERSION 13
 
 #ifdef __cplusplus
 }

@@ -87,7 +87,7 @@ class Stats(C.Structure):
 _lib = None
 
 # Exported symbols of include/mcrt.h.
-ABI_VERSION = 12  # MCRT_ABI_VERSION of the header these structs follow
+ABI_VERSION = 13  # MCRT_ABI_VERSION of the header these structs follow
 SYMBOLS = ("run_photons", "trace_path", "peel_off", "backward_density", "backward", "dust_emission",
            "mcrt_last_error", "mcrt_abi_version")
 
@@ -114,7 +114,7 @@ def load():
     lib.peel_off.argtypes = [C.POINTER(Grid), P, d, d, C.c_int, i64, P, P, P, C.c_int, C.POINTER(Detector), P, P]
     lib.peel_off.restype = C.c_int
     lib.backward.argtypes = [C.POINTER(Grid), P, C.POINTER(Optics), C.c_int, C.POINTER(Source), C.c_int,
-                             C.POINTER(Detector), C.POINTER(Opts), P, C.POINTER(Grads), C.POINTER(Stats), P]
+                             C.POINTER(Detector), C.POINTER(Opts), P, P, C.POINTER(Grads), C.POINTER(Stats), P]
     lib.backward.restype = C.c_int
     lib.dust_emission.argtypes = [C.POINTER(Grid), P, C.c_int, C.c_int, P, C.c_int, C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), C.POINTER(C.c_double), d, P, P, P]
@@ -294,8 +294,9 @@ def backward_density(prob, rho, adj_images, grad_rho, stats=True, stream=None, *
 
 
 def backward(prob, rho, adj_images, grad_rho=None, grad_albedo=None, grad_g=None, grad_lum=None, stats=True,
-             stream=None, **overrides):
-    """backward: the gradients of the image loss with dL/dI = adj_images with
+             stream=None, adj_absorbed=None, **overrides):
+    """backward: the gradients of the loss with dL/dI = adj_images (and dL/dA
+    = adj_absorbed [n_lambda][ncell] on the absorbed tally, if given) with
     respect to the densities (device FP64 [ncell]), the albedo and g
     ([n_lambda]) and the source luminosities ([n_src][n_lambda]); each
     output is a device FP64 tensor or None (not computed)."""
@@ -304,8 +305,8 @@ def backward(prob, rho, adj_images, grad_rho=None, grad_albedo=None, grad_g=None
     st = Stats()
     g = Grads(_ptr(grad_rho), _ptr(grad_albedo), _ptr(grad_g), _ptr(grad_lum))
     _check(lib.backward(C.byref(pr.grid), _ptr(rho), C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det,
-                        pr.detectors, C.byref(pr.opts), _ptr(adj_images), C.byref(g), C.byref(st) if stats else None,
-                        _stream(stream)))
+                        pr.detectors, C.byref(pr.opts), _ptr(adj_images), _ptr(adj_absorbed), C.byref(g),
+                        C.byref(st) if stats else None, _stream(stream)))
     return st.as_dict() if stats else None
 
 

@@ -153,6 +153,7 @@ struct LifeMem {
   __device__ const LamDev& lam(int l) const { return P.lam[l]; }
   __device__ const SrcDev& src(int s) const { return P.src[s]; }
   __device__ double adj(long long i) const { return P.adj[i]; }
+  __device__ double adj_abs(long long i) const { return P.adj_abs[i]; }
   __device__ void add_image(long long i, double v) const { atomic_add_f64(P.images + i, v); }
   __device__ void add_absorbed(long long i, double v) const { atomic_add_f64(P.absorbed + i, v); }
   __device__ void add_grad(int i, double v) const { atomic_add_f64(P.grad + i, v); }
@@ -1226,8 +1227,8 @@ constexpr size_t kScratchBytes = size_t(1) << 34, kQueueBytes = size_t(1) << 34;
 // Shared driver of run_photons and backward_density.
 int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
          const mcrt_source* sources, int n_det, const mcrt_detector* detectors, const mcrt_opts* opts,
-         double* images_dev, double* absorbed_dev, const double* adj_dev, const mcrt_grads* grads,
-         mcrt_stats* stats, void* hip_stream) {
+         double* images_dev, double* absorbed_dev, const double* adj_dev, const double* adj_abs_dev,
+         const mcrt_grads* grads, mcrt_stats* stats, void* hip_stream) {
   host::Prepared pr;
   if (int e = host::prepare(grid, rho_dev, optics, n_src, sources, n_det, detectors, opts, pr)) return e;
   RunParams& P = pr.P;
@@ -1258,7 +1259,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   // packages run in equal chunks: the adjoint's event scratch holds, per
   // package, T and q per frame for kEventsKept events plus the sum of q
   // beyond; the peel-ray queue by default 8 rays per package and frame
-  const int ev_k = 1 + n_det;
+  const int ev_k = 1 + n_det + (adjoint && adj_abs_dev ? 1 : 0);  // T, q per frame, then B of the path
   const bool optg = adjoint && (grads->albedo || grads->g || grads->lum);
   const size_t per_item = sizeof(double) * ((size_t)kEventsKept * ev_k + 1 + (optg ? 4 : 0));
   const bool queued = peel && opts->peel_queue != -1;
@@ -1294,7 +1295,9 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const size_t off_cts = off_cum + align256(cells ? sizeof(double) * (size_t)nl * (P.G.ncell + 1) : 0);
   const size_t off_ctot = off_cts + align256(sizeof(double) * (size_t)(nl * cdf_tiles));
   const size_t off_lums = off_ctot + (cells ? align256(sizeof(double) * nl + 8) : 0);
-  const size_t bytes = off_lums + (optg ? align256(sizeof(double) * pr.lums.size()) : 0);
+  const size_t off_aab = off_lums + (optg ? align256(sizeof(double) * pr.lums.size()) : 0);
+  const bool aabs = adjoint && adj_abs_dev;  // a loss on the absorbed tally: its adjoint, bricked
+  const size_t bytes = off_aab + (aabs ? align256(sizeof(double) * (size_t)nl * P.G.ncell_pad) : 0);
 
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   DeviceBlock blk;
@@ -1328,6 +1331,13 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     P.ev_k = ev_k;
   }
   double* const lums = optg ? reinterpret_cast<double*>(blk.ptr + off_lums) : nullptr;
+  if (aabs) {
+    double* aab = reinterpret_cast<double*>(blk.ptr + off_aab);
+    for (int l = 0; l < nl; ++l)
+      if (int e = brick_density(P.G, adj_abs_dev + (size_t)l * P.G.ncell, aab + (size_t)l * P.G.ncell_pad, false, st))
+        return e;
+    P.adj_abs = aab;
+  }
   if (optg) {  // the sources' luminosities (known once the cell CDF is); gradients start at 0
     HIPCHK(hipMemcpyAsync(lums, pr.lums.data(), sizeof(double) * pr.lums.size(), hipMemcpyHostToDevice, st));
     if (int e = zero_fill(grads->albedo, grads->albedo ? nl : 0, st)) return e;
@@ -1479,7 +1489,7 @@ int run_photons(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* o
   try {
     mcrt::host::last_error().clear();
     return life(false, grid, rho_dev, optics, n_src, sources, n_det, detectors, opts, images_dev, absorbed_dev,
-                nullptr, nullptr, stats_host, hip_stream);
+                nullptr, nullptr, nullptr, stats_host, hip_stream);
   } catch (...) {
     return fail(MCRT_EHIP, "run_photons: host exception");
   }
@@ -1499,7 +1509,7 @@ int backward_density(const mcrt_grid* grid, const void* rho_dev, const mcrt_opti
     mcrt_grads g = {grad_rho_dev, nullptr, nullptr, nullptr};
     if (!grad_rho_dev) return fail(MCRT_EINVAL, "grad_rho_dev is NULL");
     return life(true, grid, rho_dev, optics, n_src, sources, n_det, detectors, opts ? &o : nullptr, nullptr,
-                nullptr, adj_images_dev, &g, stats_host, hip_stream);
+                nullptr, adj_images_dev, nullptr, &g, stats_host, hip_stream);
   } catch (...) {
     return fail(MCRT_EHIP, "backward_density: host exception");
   }
@@ -1507,7 +1517,8 @@ int backward_density(const mcrt_grid* grid, const void* rho_dev, const mcrt_opti
 
 int backward(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* optics, int n_src,
              const mcrt_source* sources, int n_det, const mcrt_detector* detectors, const mcrt_opts* opts,
-             const double* adj_images_dev, const mcrt_grads* grads, mcrt_stats* stats_host, void* hip_stream) {
+             const double* adj_images_dev, const double* adj_absorbed_dev, const mcrt_grads* grads,
+             mcrt_stats* stats_host, void* hip_stream) {
   try {
     mcrt::host::last_error().clear();
     mcrt_opts o;
@@ -1515,8 +1526,10 @@ int backward(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics* opti
       o = *opts;
       o.flags &= ~MCRT_ABSORB;
     }
+    if (adj_absorbed_dev && grads && !grads->rho)
+      return fail(MCRT_EINVAL, "adj_absorbed_dev needs grads->rho (its optics gradients are not computed)");
     return life(true, grid, rho_dev, optics, n_src, sources, n_det, detectors, opts ? &o : nullptr, nullptr,
-                nullptr, adj_images_dev, grads, stats_host, hip_stream);
+                nullptr, adj_images_dev, adj_absorbed_dev, grads, stats_host, hip_stream);
   } catch (...) {
     return fail(MCRT_EHIP, "backward: host exception");
   }

@@ -118,6 +118,9 @@ struct RunParams {
   // of the chunk sum q n, sum q (score in g), sum q and its source index,
   // [4][n_chunk] (null: not wanted)
   double* gpart;
+  // adjoint of a loss on the absorbed tally: dL/dA, bricked [n_lambda][ncell_pad]
+  // (null: none); its path sums B sit in the event scratch's last entry
+  const double* adj_abs;
 };
 
 template <typename R>
@@ -141,6 +144,8 @@ struct Lane {
   bool t_kept;  // pass B: T of the next leg is in the scratch
   int src;      // source of the package
   double Sg, Ga, Gg, GL;  // pass B, optics gradients: score of the sampled directions; sums over q
+  double Babs, Pabs;      // absorbed-tally adjoint: B of the current path, its running part P
+  bool abs_dep;           // pass B: this path walk deposits the absorbed-tally terms
   // statistics
   double s_abs, s_esc, s_trunc;
   unsigned x_path, x_loc, x_peel, n_ev, n_pk, n_pl, n_dep;
@@ -173,6 +178,8 @@ MCRT_HD void lane_init(Lane<R>& L) {
   L.t_kept = false;
   L.src = 0;
   L.Sg = L.Ga = L.Gg = L.GL = 0.0;
+  L.Babs = L.Pabs = 0.0;
+  L.abs_dep = false;
   L.s_abs = L.s_esc = L.s_trunc = 0.0;
   L.x_path = L.x_loc = L.x_peel = L.n_ev = L.n_pk = L.n_pl = L.n_dep = 0;
 }
@@ -292,7 +299,23 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     }
 
     // -- end of the pass-1 walk: escape and absorption, forced-scattering depth
-    if (L.phase == PH_PATH_END) {
+    if (ADJ && L.phase == PH_PATH_END && P.adj_abs && !want) {
+      if (L.pass == 0) {  // keep the path's B for pass B
+        if (L.n < P.ev_max)
+          M.ev_store(L.slot, L.n, P.ev_k - 1, L.Babs);
+        else if (L.Babs != 0.0)
+          M.ev_add_beyond(L.slot, L.Babs);
+      } else if (!L.abs_dep && L.Babs != 0.0) {  // beyond the scratch: B known now, walk again to deposit
+        L.abs_dep = true;
+        L.Pabs = 0.0;
+        L.absf = R(0);
+        L.trans = R(1);
+        want = true;
+        L.mode = M_PATH;
+      }
+    }
+    if (L.phase == PH_PATH_END && !want) {
+      if (ADJ && L.pass == 1) L.Gacc += L.Babs;  // the path's B joins this event's contributions
       if (ADJ && L.t_kept) {
         L.T = M.ev_load(L.slot, L.n, 0);
         L.t_kept = false;
@@ -404,9 +427,14 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
       L.trans = R(1);
       L.wabs = L.W * (1.0 - L.alb);
       L.phase = PH_PATH_END;
+      if (ADJ) {  // absorbed-tally adjoint: pass A sums B; pass B deposits with B known
+        L.Babs = (P.adj_abs && L.pass == 1 && L.n < P.ev_max) ? M.ev_load(L.slot, L.n, P.ev_k - 1) : 0.0;
+        L.Pabs = 0.0;
+        L.abs_dep = L.Babs != 0.0;
+      }
       if (ADJ && L.pass == 1 && L.n < P.ev_max) {
-        L.t_kept = true;  // T of this leg is in the scratch: no walk
-        continue;
+        L.t_kept = true;  // T of this leg is in the scratch: no walk unless it deposits
+        if (!L.abs_dep) continue;
       }
       want = true;
       L.mode = M_PATH;
@@ -447,6 +475,12 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
           for (int e = 0; e < P.ev_max; ++e)
             for (int d = 0; d < P.n_det; ++d) {
               const double q = M.ev_load(L.slot, e, 1 + d);
+              R1 += q;
+              Rabs += fabs(q);
+            }
+          if (P.adj_abs)
+            for (int e = 0; e < P.ev_max; ++e) {
+              const double q = M.ev_load(L.slot, e, P.ev_k - 1);
               R1 += q;
               Rabs += fabs(q);
             }
@@ -558,6 +592,22 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
     const R dtau = L.kapR * rs * seg;
     if (L.mode == M_PATH) {
       L.x_path += pos;
+      if (ADJ && P.adj_abs && dtau > R(0)) {
+        // absorbed-tally adjoint: deposit dep = W (1 - albedo) e^-tau (1 - e^-dtau) weighted by b;
+        // pass B also deposits -kappa l (B - P) + b W (1 - albedo) e^-tau e^-dtau kappa l
+        const R em = expm1(-dtau);
+        const double bj = M.adj_abs(L.lam_cell + cell);
+        const double dep = L.wabs * (double)(-L.trans * em);
+        if (L.abs_dep) {
+          L.Pabs += bj * dep;
+          const double kl = L.kap * (double)seg;
+          M.add_grad(cell, -kl * (L.Babs - L.Pabs) + bj * L.wabs * (double)(L.trans * (R(1) + em)) * kl);
+          ++L.n_dep;
+        } else {
+          L.Babs += bj * dep;
+        }
+        L.trans += L.trans * em;
+      }
       if (!ADJ && dtau > R(0)) {
         // deposit e^-tau (1 - e^-dtau) with e^-tau carried along the walk
         const R em = expm1(-dtau);

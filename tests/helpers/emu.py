@@ -41,7 +41,7 @@ class Emu:
                                         C.POINTER(B.Stats), C.c_int]
         lib.emu_backward_density.argtypes = [C.POINTER(B.Grid), P, C.POINTER(B.Optics), C.c_int,
                                              C.POINTER(B.Source), C.c_int, C.POINTER(B.Detector),
-                                             C.POINTER(B.Opts), P, i64, P, i64, P, C.POINTER(B.Stats), C.c_int]
+                                             C.POINTER(B.Opts), P, i64, P, i64, P, P, C.POINTER(B.Stats), C.c_int]
         lib.emu_trace_path.argtypes = [C.POINTER(B.Grid), P, d, C.c_int, C.c_int64, P, P, P, C.c_int32, P, P, P,
                                        C.POINTER(C.c_uint64), C.c_int, C.c_int]
         lib.emu_peel_off.argtypes = [C.POINTER(B.Grid), P, d, d, C.c_int, C.c_int64, P, P, P, C.c_int,
@@ -93,20 +93,22 @@ class Emu:
         """Packages per adjoint chunk (0: the library's choice)."""
         self.lib.emu_set_chunk_items(int(n))
 
-    def grad(self, prob, adj, wave=WAVE, optics=False, **overrides):
+    def grad(self, prob, adj, wave=WAVE, optics=False, adj_absorbed=None, **overrides):
         """(dL/drho, stats), or with optics=True (dL/drho, stats, {"albedo",
-        "g", "lum"})."""
+        "g", "lum"}); adj_absorbed [n_lambda][ncell] adds a loss term on the
+        absorbed tally."""
         pr = B._Problem(prob, cells_on_device=False, **overrides)
         rho = self._rho(prob)
         adj = np.ascontiguousarray(adj, dtype=np.float64).reshape(-1)
         g = np.zeros(rho.size)
         nl = len(np.atleast_1d(prob["kappa"]))
         gopt = np.zeros((2 + pr.n_src, nl)) if optics else None
+        aa = None if adj_absorbed is None else np.ascontiguousarray(adj_absorbed, dtype=np.float64).reshape(-1)
         st = B.Stats()
         self._check(self.lib.emu_backward_density(C.byref(pr.grid), self._p(rho), C.byref(pr.optics), pr.n_src,
                                                   pr.sources, pr.n_det, pr.detectors, C.byref(pr.opts),
                                                   self._p(adj), adj.size, self._p(g), g.size, self._p(gopt),
-                                                  C.byref(st), wave))
+                                                  self._p(aa), C.byref(st), wave))
         if optics:
             return g, st.as_dict(), {"albedo": gopt[0], "g": gopt[1], "lum": gopt[2:]}
         return g, st.as_dict()

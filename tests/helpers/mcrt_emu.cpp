@@ -142,6 +142,13 @@ struct HostLifeMem {
     EMU_CHECK(i >= 0 && i < n_adj, "adjoint image", i, n_adj);
     return adj_[i];
   }
+  const std::vector<double>* adj_abs_b = nullptr;  // bricked dL/dA [n_lambda][ncell_pad]
+  double adj_abs(long long i) const {
+    EMU_CHECK(adj_abs_b != nullptr, "absorbed adjoint without its buffer", i, 0);
+    EMU_CHECK(i >= 0 && i < (long long)adj_abs_b->size(), "absorbed adjoint", i, (long long)adj_abs_b->size());
+    check_cell(G, i % G.ncell_pad, "absorbed adjoint");
+    return (*adj_abs_b)[i];
+  }
   void add_image(long long i, double v) {
     EMU_CHECK(i >= 0 && i < n_images, "image", i, n_images);
     images[i] += v;
@@ -388,7 +395,7 @@ template <typename R, bool ADJ, int GK, bool INST>
 int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, int n_src, const mcrt_source* sources,
              int n_det, const mcrt_detector* detectors, const mcrt_opts* opts, double* images, long long n_images,
              double* absorbed, long long n_absorbed, const double* adj, long long n_adj, double* grad, long long n_grad,
-             double* gopt, mcrt_stats* stats, int wave) {
+             double* gopt, const double* adj_abs, mcrt_stats* stats, int wave) {
   host::Prepared pr;
   if (int e = host::prepare(grid, rho, optics, n_src, sources, n_det, detectors, opts, pr)) return e;
   HostPlanes planes;
@@ -463,9 +470,19 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   };
   // chunks of packages as the library runs them (the library sizes them by
   // its event-scratch and queue budgets; g_chunk_items overrides for tests)
+  std::vector<double> aab;  // the absorbed tally's adjoint, bricked as the library does
+  if (ADJ && adj_abs) {
+    aab.assign((size_t)P.n_lambda * P.G.ncell_pad, 0.0);
+    for (int l = 0; l < P.n_lambda; ++l) {
+      const std::vector<double> row = brick_copy(P.G, adj_abs + (size_t)l * P.G.ncell);
+      std::copy(row.begin(), row.end(), aab.begin() + (size_t)l * P.G.ncell_pad);
+    }
+    M.adj_abs_b = &aab;
+    P.adj_abs = aab.data();  // only tested against null by the lanes; the loads go through M
+  }
   if (ADJ) {
     P.ev_max = g_events_kept;
-    P.ev_k = 1 + P.n_det;
+    P.ev_k = 1 + P.n_det + (adj_abs ? 1 : 0);
   }
   const size_t per_item = sizeof(double) * ((size_t)P.ev_max * P.ev_k + 1);
   unsigned long long chunk =
@@ -782,7 +799,8 @@ int emu_run_photons(const mcrt_grid* grid, const void* rho, const mcrt_optics* o
     return life_dispatch<false>(opts->precision == MCRT_PREC_FP32, grid_kind(grid), n_det, detectors, grid, rho,
                                 optics, n_src,
                                 sources, n_det, detectors, opts, images, n_images, absorbed, n_absorbed,
-                                (const double*)nullptr, 0ll, (double*)nullptr, 0ll, (double*)nullptr, stats, wave);
+                                (const double*)nullptr, 0ll, (double*)nullptr, 0ll, (double*)nullptr,
+                                (const double*)nullptr, stats, wave);
   } catch (const Violation& v) {
     g_violation = std::string("run_photons: ") + v.what();
     return -100;
@@ -792,7 +810,7 @@ int emu_run_photons(const mcrt_grid* grid, const void* rho, const mcrt_optics* o
 int emu_backward_density(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, int n_src,
                          const mcrt_source* sources, int n_det, const mcrt_detector* detectors, const mcrt_opts* opts,
                          const double* adj, long long n_adj, double* grad, long long n_grad, double* gopt,
-                         mcrt_stats* stats, int wave) {
+                         const double* adj_abs, mcrt_stats* stats, int wave) {
   try {
     g_violation.clear();
     host::last_error().clear();
@@ -802,7 +820,7 @@ int emu_backward_density(const mcrt_grid* grid, const void* rho, const mcrt_opti
     return life_dispatch<true>(o.precision == MCRT_PREC_FP32, grid_kind(grid), n_det, detectors, grid, rho, optics,
                                n_src, sources,
                                n_det, detectors, (const mcrt_opts*)&o, (double*)nullptr, 0ll, (double*)nullptr, 0ll,
-                               adj, n_adj, grad, n_grad, gopt, stats, wave);
+                               adj, n_adj, grad, n_grad, gopt, adj_abs, stats, wave);
   } catch (const Violation& v) {
     g_violation = std::string("backward_density: ") + v.what();
     return -100;

@@ -186,9 +186,14 @@ def test_backward_rejects_missing_gradients(lib, B, W):
     none = B.Grads(None, None, None, None)
     for grads in (None, C.byref(none)):
         rc = lib.backward(C.byref(pr.grid), fake, C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det, pr.detectors,
-                          C.byref(pr.opts), fake, grads, C.byref(st), None)
+                          C.byref(pr.opts), fake, None, grads, C.byref(st), None)
         assert rc == B.EINVAL
         assert lib.mcrt_last_error().decode()
+    # a loss on the absorbed tally needs the density gradient
+    only_albedo = B.Grads(None, fake, None, None)
+    rc = lib.backward(C.byref(pr.grid), fake, C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det, pr.detectors,
+                      C.byref(pr.opts), fake, fake, C.byref(only_albedo), C.byref(st), None)
+    assert rc == B.EINVAL and "adj_absorbed" in lib.mcrt_last_error().decode()
 
 
 @pytest.mark.parametrize("case", ["kind", "sed_pixels", "eye_is_target", "up_along_view", "eye_nan", "persp_extent"])
