@@ -143,7 +143,9 @@ __device__ __forceinline__ unsigned long long* wave_reservoir(unsigned long long
 template <typename R, int GK, bool INST>
 struct LifeMem {
   static constexpr int kGrid = GK;
-  static constexpr bool kInst = INST;  // instruments other than frames (SED, camera)
+  // the full variant: instruments other than frames (SED, camera) and the
+  // optics and absorbed-tally gradients; the lean one compiles them out
+  static constexpr bool kInst = INST;
   const R* __restrict__ rho_;
   const RunParams& P;
   unsigned long long* res;
@@ -250,7 +252,8 @@ struct PeelMem {
 // The life-cycle kernel body; k_life (FP32 walk) and k_life64 (FP64 walk)
 // launch it, once per grid kind (GK, kGrid*) and with or without the
 // handling of instruments other than frames -- SED instruments, cameras and
-// their walks to the eye (INST).  The FP64 kernel asks for two wavefronts
+// their walks to the eye -- and of the adjoint's optics and absorbed-tally
+// gradients (INST).  The FP64 kernel asks for two wavefronts
 // per SIMD, which its register use would otherwise just miss.
 template <typename R, bool ADJ, int GK, bool INST>
 __device__ __forceinline__ void life_body(const RunParams& P) {
@@ -1249,18 +1252,20 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const bool f32 = opts->precision == MCRT_PREC_FP32;
   int nblk = 0;
   const int kind = P.G.kind;
-  bool inst = false;  // instruments other than frames (SED, camera): the kernels that handle them
+  bool inst = false;  // instruments other than frames (SED, camera)
   for (int d = 0; d < n_det; ++d) inst = inst || pr.det[d].kind != kDetFrame;
-  if (int e = adjoint ? (f32 ? life_grid<float, true>(kind, inst, opts->launch_blocks, &nblk)
-                             : life_grid<double, true>(kind, inst, opts->launch_blocks, &nblk))
-                      : (f32 ? life_grid<float, false>(kind, inst, opts->launch_blocks, &nblk)
-                             : life_grid<double, false>(kind, inst, opts->launch_blocks, &nblk)))
+  const bool optg = adjoint && (grads->albedo || grads->g || grads->lum);
+  // the life kernels' full variant also carries the optics and absorbed-tally gradients
+  const bool full = inst || optg || (adjoint && adj_abs_dev);
+  if (int e = adjoint ? (f32 ? life_grid<float, true>(kind, full, opts->launch_blocks, &nblk)
+                             : life_grid<double, true>(kind, full, opts->launch_blocks, &nblk))
+                      : (f32 ? life_grid<float, false>(kind, full, opts->launch_blocks, &nblk)
+                             : life_grid<double, false>(kind, full, opts->launch_blocks, &nblk)))
     return e;
   // packages run in equal chunks: the adjoint's event scratch holds, per
   // package, T and q per frame for kEventsKept events plus the sum of q
   // beyond; the peel-ray queue by default 8 rays per package and frame
   const int ev_k = 1 + n_det + (adjoint && adj_abs_dev ? 1 : 0);  // T, q per frame, then B of the path
-  const bool optg = adjoint && (grads->albedo || grads->g || grads->lum);
   const size_t per_item = sizeof(double) * ((size_t)kEventsKept * ev_k + 1 + (optg ? 4 : 0));
   const bool queued = peel && opts->peel_queue != -1;
   size_t free_b = 0, total_b = 0;
@@ -1401,7 +1406,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
       P.n_chunk = std::min(chunk, P.n_items - c0);
       if (int e = reset_counters(ctr, 0, 1, st)) return e;
       if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
-      rc = f32 ? launch_life<float, false>(P, inst, nblk, st) : launch_life<double, false>(P, inst, nblk, st);
+      rc = f32 ? launch_life<float, false>(P, full, nblk, st) : launch_life<double, false>(P, full, nblk, st);
       if (rc) return rc;
       ++launches;
       if (P.jobs)
@@ -1419,14 +1424,14 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
       if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
       if (int e = reset_counters(ctr, kDepCounter, 1, st)) return e;
       P.split = 1;  // pass A
-      rc = f32 ? launch_life<float, true>(P, inst, nblk, st) : launch_life<double, true>(P, inst, nblk, st);
+      rc = f32 ? launch_life<float, true>(P, full, nblk, st) : launch_life<double, true>(P, full, nblk, st);
       if (rc) return rc;
       ++launches;
       if (P.jobs)
         if (int e = queue_phase(true)) return e;
       if (int e = reset_counters(ctr, 0, 1, st)) return e;
       P.split = 2;  // pass B
-      rc = f32 ? launch_life<float, true>(P, inst, nblk, st) : launch_life<double, true>(P, inst, nblk, st);
+      rc = f32 ? launch_life<float, true>(P, full, nblk, st) : launch_life<double, true>(P, full, nblk, st);
       if (rc) return rc;
       ++launches;
       if (optg) {

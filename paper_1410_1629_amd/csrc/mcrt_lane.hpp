@@ -225,7 +225,7 @@ MCRT_HD void event_start(Lane<R>& L, const RunParams& P, Mem& M) {
     for (int d = 0; d < P.n_det; ++d) {
       const double q = M.ev_load(L.slot, L.n, 1 + d);
       L.Ge += q;
-      if (P.gpart && q != 0.0) optics_add(L, M, d, q);
+      if (Mem::kInst && P.gpart && q != 0.0) optics_add(L, M, d, q);
     }
     L.det = P.n_det;  // no peel-off walks: PEEL_NEXT goes straight on
   }
@@ -282,7 +282,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
         const double ac = M.adj(ii) * C;
         L.Ge += ac;
         if (L.pass == 0) keep_q(L, P, M, ac);
-        if (L.pass == 1 && P.gpart && ac != 0.0) optics_add(L, M, L.det, ac);
+        if (Mem::kInst && L.pass == 1 && P.gpart && ac != 0.0) optics_add(L, M, L.det, ac);
         if (L.pass == 0 && ac != 0.0) {  // a second walk of the same ray deposits -A C kappa l
           L.fac = -ac * L.kap;
           want = to_det = true;
@@ -299,7 +299,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
     }
 
     // -- end of the pass-1 walk: escape and absorption, forced-scattering depth
-    if (ADJ && L.phase == PH_PATH_END && P.adj_abs && !want) {
+    if (ADJ && Mem::kInst && L.phase == PH_PATH_END && P.adj_abs && !want) {
       if (L.pass == 0) {  // keep the path's B for pass B
         if (L.n < P.ev_max)
           M.ev_store(L.slot, L.n, P.ev_k - 1, L.Babs);
@@ -415,7 +415,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
         L.phase = PH_PKG_END;
       } else {
         const double mu = hg_sample_mu(L.g, u01(L.uw1));
-        if (ADJ && L.pass == 1 && P.gpart) L.Sg += hg_dlng(L.g, mu);
+        if (ADJ && Mem::kInst && L.pass == 1 && P.gpart) L.Sg += hg_dlng(L.g, mu);
         turn(L.k, mu, u01(L.uw2));
         L.phase = PH_PATH_START;
       }
@@ -428,7 +428,8 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
       L.wabs = L.W * (1.0 - L.alb);
       L.phase = PH_PATH_END;
       if (ADJ) {  // absorbed-tally adjoint: pass A sums B; pass B deposits with B known
-        L.Babs = (P.adj_abs && L.pass == 1 && L.n < P.ev_max) ? M.ev_load(L.slot, L.n, P.ev_k - 1) : 0.0;
+        L.Babs = (Mem::kInst && P.adj_abs && L.pass == 1 && L.n < P.ev_max) ? M.ev_load(L.slot, L.n, P.ev_k - 1)
+                                                                              : 0.0;
         L.Pabs = 0.0;
         L.abs_dep = L.Babs != 0.0;
       }
@@ -442,7 +443,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
 
     // -- end of the package: replay it for the adjoint, or take the next one
     if (L.phase == PH_PKG_END && !want) {
-      if (ADJ && L.pass == 1 && P.gpart) {  // the package's sums for the optics gradients
+      if (ADJ && Mem::kInst && L.pass == 1 && P.gpart) {  // the package's sums for the optics gradients
         M.opt_store(L.slot, L.Ga, L.Gg, L.GL, L.src);
       }
       L.phase = PH_FETCH;
@@ -478,7 +479,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
               R1 += q;
               Rabs += fabs(q);
             }
-          if (P.adj_abs)
+          if (Mem::kInst && P.adj_abs)
             for (int e = 0; e < P.ev_max; ++e) {
               const double q = M.ev_load(L.slot, e, P.ev_k - 1);
               R1 += q;
@@ -592,7 +593,7 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
     const R dtau = L.kapR * rs * seg;
     if (L.mode == M_PATH) {
       L.x_path += pos;
-      if (ADJ && P.adj_abs && dtau > R(0)) {
+      if (ADJ && Mem::kInst && P.adj_abs && dtau > R(0)) {
         // absorbed-tally adjoint: deposit dep = W (1 - albedo) e^-tau (1 - e^-dtau) weighted by b;
         // pass B also deposits -kappa l (B - P) + b W (1 - albedo) e^-tau e^-dtau kappa l
         const R em = expm1(-dtau);

@@ -735,11 +735,11 @@ int life_kind(int kind, A... args) {
   return emu_life<R, ADJ, kGridRegular, INST>(args...);
 }
 
-// As the library: the variant of the kernels that handles SED instruments
-// and cameras only when one is among the frames.
+// As the library: the full variant of the kernels (SED instruments,
+// cameras, optics and absorbed-tally gradients) only when one is used.
 template <bool ADJ, typename... A>
-int life_dispatch(bool f32, int kind, int n_det, const mcrt_detector* dets, A... args) {
-  bool inst = false;
+int life_dispatch(bool f32, int kind, int n_det, const mcrt_detector* dets, bool extras, A... args) {
+  bool inst = extras;  // optics or absorbed-tally gradients take the full variant too
   for (int d = 0; d < n_det && dets; ++d) inst = inst || dets[d].kind != MCRT_DET_FRAME;
   if (inst) return f32 ? life_kind<ADJ, float, true>(kind, args...) : life_kind<ADJ, double, true>(kind, args...);
   return f32 ? life_kind<ADJ, float, false>(kind, args...) : life_kind<ADJ, double, false>(kind, args...);
@@ -796,9 +796,9 @@ int emu_run_photons(const mcrt_grid* grid, const void* rho, const mcrt_optics* o
     g_violation.clear();
     host::last_error().clear();
     if (!opts) return host::fail(MCRT_EINVAL, "opts is NULL");
-    return life_dispatch<false>(opts->precision == MCRT_PREC_FP32, grid_kind(grid), n_det, detectors, grid, rho,
-                                optics, n_src,
-                                sources, n_det, detectors, opts, images, n_images, absorbed, n_absorbed,
+    return life_dispatch<false>(opts->precision == MCRT_PREC_FP32, grid_kind(grid), n_det, detectors, false, grid,
+                                rho, optics, n_src, sources, n_det, detectors, opts, images, n_images, absorbed,
+                                n_absorbed,
                                 (const double*)nullptr, 0ll, (double*)nullptr, 0ll, (double*)nullptr,
                                 (const double*)nullptr, stats, wave);
   } catch (const Violation& v) {
@@ -817,7 +817,8 @@ int emu_backward_density(const mcrt_grid* grid, const void* rho, const mcrt_opti
     if (!opts) return host::fail(MCRT_EINVAL, "opts is NULL");
     mcrt_opts o = *opts;
     o.flags &= ~MCRT_ABSORB;
-    return life_dispatch<true>(o.precision == MCRT_PREC_FP32, grid_kind(grid), n_det, detectors, grid, rho, optics,
+    return life_dispatch<true>(o.precision == MCRT_PREC_FP32, grid_kind(grid), n_det, detectors,
+                               gopt != nullptr || adj_abs != nullptr, grid, rho, optics,
                                n_src, sources,
                                n_det, detectors, (const mcrt_opts*)&o, (double*)nullptr, 0ll, (double*)nullptr, 0ll,
                                adj, n_adj, grad, n_grad, gopt, adj_abs, stats, wave);
