@@ -99,30 +99,41 @@ constexpr int kJobCounter = 24, kKeyCounter = 25, kQueueCrossings = 26, kDepCoun
 // with kNoKey when it exits, and the sort skips them.
 constexpr unsigned kJobChunk = 256, kNoKey = 0xffffffffu;
 
-// Issues the wavefront's walk-block deposits (one per lane and sub-step)
-// through an LDS transpose: entry 4 * lane + d is lane `lane`'s deposit of
-// sub-step d, and atomic instruction k takes entries 64 k + lane, so the
-// four deposits of one walker -- consecutive cells of its walk, often in one
-// 64-byte segment of the bricked tally -- go out in adjacent lanes of one
-// instruction, which the memory pipeline merges into one request per
-// segment.  Global atomics are executed at the memory side at a fixed
-// request rate, so fewer requests is what counts.  Called by every lane of
-// the wavefront (uniform control flow).
-__device__ __forceinline__ void flush_deposits(const WalkDeposits& dep, double* tally, long long* sidx, double* sval) {
-  static_assert(kBlockWalk == 4, "the transpose assumes four sub-steps per lane");
-  const int lane = __lane_id();
+// The forward's absorbed-light deposits leave through an LDS transpose.  The
+// deposits of kDepBlocks walk blocks are staged per wavefront first: entry
+// kDepPer * lane + kBlockWalk * b + d holds lane `lane`'s deposit of sub-step d
+// of staged block b.  The flush's atomic instruction k then takes entries
+// 64 k + lane, so the kDepPer deposits of one walker -- consecutive cells of
+// its walk, often in one segment of the bricked tally -- go out in adjacent
+// lanes of one instruction, which the memory pipeline merges into one request
+// per segment.  Global atomics are executed at the memory side at a fixed
+// request rate, so fewer requests is what counts, and a longer run of one
+// walker's cells splits into fewer segments per deposit.  Both calls are made
+// by every lane of the wavefront (uniform control flow).
+constexpr int kDepBlocks = 4, kDepPer = kDepBlocks * kBlockWalk;
+static_assert(64 % kDepPer == 0, "a flush instruction holds whole walkers");
+
+__device__ __forceinline__ void stage_deposits(const WalkDeposits& dep, int b, long long* sidx, double* sval) {
+  const int base = kDepPer * __lane_id() + kBlockWalk * b;
 #pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    sidx[4 * lane + d] = ((dep.on >> d) & 1u) ? dep.idx[d] : -1ll;
-    sval[4 * lane + d] = dep.val[d];
+  for (int d = 0; d < kBlockWalk; ++d) {
+    sidx[base + d] = ((dep.on >> d) & 1u) ? dep.idx[d] : -1ll;
+    sval[base + d] = dep.val[d];
   }
+}
+
+// Issues the nb staged blocks (entries of later blocks are stale and skipped:
+// entry 64 k + lane is deposit (lane mod kDepPer) of its walker).
+__device__ __forceinline__ void flush_deposits(int nb, double* tally, long long* sidx, double* sval) {
+  const int lane = __lane_id();
+  const bool fresh = (lane % kDepPer) < nb * kBlockWalk;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kDepPer; ++k) {
     const long long i = sidx[64 * k + lane];
-    if (i >= 0) atomic_add_f64(tally + i, sval[64 * k + lane]);
+    if (fresh && i >= 0) atomic_add_f64(tally + i, sval[64 * k + lane]);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -253,17 +264,20 @@ struct PeelMem {
 // launch it, once per grid kind (GK, kGrid*) and with or without the
 // handling of instruments other than frames -- SED instruments, cameras and
 // their walks to the eye -- and of the adjoint's optics and absorbed-tally
-// gradients (INST).  The FP64 kernel asks for two wavefronts
-// per SIMD, which its register use would otherwise just miss.
+// gradients (INST).  The FP64 kernel and the full FP32 variants ask for two
+// wavefronts per SIMD, which their register use would otherwise just miss
+// (one accumulation register beyond 256 halves the occupancy); the lean FP32
+// variants fit without the request, and run faster without it.
 template <typename R, bool ADJ, int GK, bool INST>
 __device__ __forceinline__ void life_body(const RunParams& P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2], job_slots[kWavesPerBlock][2];
-  __shared__ long long dep_idx[kWavesPerBlock][64 * kBlockWalk];
-  __shared__ double dep_val[kWavesPerBlock][64 * kBlockWalk];
+  __shared__ long long dep_idx[kWavesPerBlock][64 * kDepPer];
+  __shared__ double dep_val[kWavesPerBlock][64 * kDepPer];
   const int wave = threadIdx.x / 64;
   LifeMem<R, GK, INST> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots), wave_reservoir(job_slots)};
   Lane<R> L;
   lane_init(L);
+  int staged = 0;  // walk blocks of deposits staged in LDS (wavefront-uniform)
   for (;;) {
     lane_events<R, ADJ>(L, P, M);
     const unsigned long long live = __ballot(!L.done);
@@ -275,9 +289,16 @@ __device__ __forceinline__ void life_body(const RunParams& P) {
       WalkDeposits dep;
       dep.on = 0;
       if (L.ry.active) lane_step<R, ADJ>(L, P, M, dep);
-      if (!ADJ && __ballot(dep.on != 0u)) flush_deposits(dep, P.absorbed, dep_idx[wave], dep_val[wave]);
+      if (!ADJ && __ballot(dep.on != 0u)) {
+        stage_deposits(dep, staged, dep_idx[wave], dep_val[wave]);
+        if (++staged == kDepBlocks) {
+          flush_deposits(staged, P.absorbed, dep_idx[wave], dep_val[wave]);
+          staged = 0;
+        }
+      }
     }
   }
+  if (!ADJ && staged) flush_deposits(staged, P.absorbed, dep_idx[wave], dep_val[wave]);
   if (P.jobs) {  // unfilled reserved queue slots
     const unsigned long long lo = M.job_res[0], hi = M.job_res[1] < P.job_cap ? M.job_res[1] : P.job_cap;
     for (unsigned long long q = lo + __lane_id(); q < hi; q += 64) P.jobs[q].key = kNoKey;
@@ -301,7 +322,7 @@ __device__ __forceinline__ void life_body(const RunParams& P) {
 }
 
 template <typename R, bool ADJ, int GK, bool INST>
-__global__ void __launch_bounds__(kBlock) k_life(const RunParams P) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(INST ? 2 : 1))) k_life(const RunParams P) {
   life_body<R, ADJ, GK, INST>(P);
 }
 
