@@ -99,28 +99,21 @@ constexpr int kJobCounter = 24, kKeyCounter = 25, kQueueCrossings = 26, kDepCoun
 // with kNoKey when it exits, and the sort skips them.
 constexpr unsigned kJobChunk = 256, kNoKey = 0xffffffffu;
 
-// The forward's absorbed-light deposits leave through an LDS transpose.  The
-// deposits of kDepBlocks walk blocks are staged per wavefront first: entry
-// kDepPer * lane + kBlockWalk * b + d holds lane `lane`'s deposit of sub-step d
-// of staged block b.  The flush's atomic instruction k then takes entries
-// 64 k + lane, so the kDepPer deposits of one walker -- consecutive cells of
-// its walk, often in one segment of the bricked tally -- go out in adjacent
-// lanes of one instruction, which the memory pipeline merges into one request
-// per segment.  Global atomics are executed at the memory side at a fixed
-// request rate, so fewer requests is what counts, and a longer run of one
-// walker's cells splits into fewer segments per deposit.  Both calls are made
-// by every lane of the wavefront (uniform control flow).
+// The walk deposits -- the forward's absorbed light, the adjoint's gradient
+// terms -- leave through an LDS transpose.  The deposits of kDepBlocks walk
+// blocks are staged per wavefront first: entry kDepPer * lane + kBlockWalk * b
+// + d holds lane `lane`'s deposit of sub-step d of staged block b (index -1:
+// none), written by the walk itself (LifeMem::walk_deposit).  The
+// flush's atomic instruction k then takes entries 64 k + lane, so the kDepPer
+// deposits of one walker -- consecutive cells of its walk, often in one
+// segment of the bricked array -- go out in adjacent lanes of one
+// instruction, which the memory pipeline merges into one request per
+// segment.  Global atomics are executed at the memory side at a fixed request
+// rate, so fewer requests is what counts, and a longer run of one walker's
+// cells splits into fewer segments per deposit.  Called by every lane of the
+// wavefront (uniform control flow).
 constexpr int kDepBlocks = 4, kDepPer = kDepBlocks * kBlockWalk;
 static_assert(64 % kDepPer == 0, "a flush instruction holds whole walkers");
-
-__device__ __forceinline__ void stage_deposits(const WalkDeposits& dep, int b, long long* sidx, double* sval) {
-  const int base = kDepPer * __lane_id() + kBlockWalk * b;
-#pragma unroll
-  for (int d = 0; d < kBlockWalk; ++d) {
-    sidx[base + d] = ((dep.on >> d) & 1u) ? dep.idx[d] : -1ll;
-    sval[base + d] = dep.val[d];
-  }
-}
 
 // Issues the nb staged blocks (entries of later blocks are stale and skipped:
 // entry 64 k + lane is deposit (lane mod kDepPer) of its walker).
@@ -170,6 +163,20 @@ struct LifeMem {
   __device__ void add_image(long long i, double v) const { atomic_add_f64(P.images + i, v); }
   __device__ void add_absorbed(long long i, double v) const { atomic_add_f64(P.absorbed + i, v); }
   __device__ void add_grad(int i, double v) const { atomic_add_f64(P.grad + i, v); }
+  // walk deposits: this lane's LDS staging entries of the current walk block
+  long long* sidx;
+  double* sval;
+  int dbase;
+  __device__ void stage_clear(int b) {
+    dbase = kDepPer * __lane_id() + kBlockWalk * b;
+#pragma unroll
+    for (int d = 0; d < kBlockWalk; ++d) sidx[dbase + d] = -1ll;
+  }
+  template <bool ADJ>
+  __device__ void walk_deposit(int d, long long i, double v) const {
+    sidx[dbase + d] = i;
+    sval[dbase + d] = v;
+  }
   __device__ unsigned long long fetch() const { return wave_fetch(P.work, res, 64); }
   __device__ unsigned long long job_slot() const { return wave_fetch(P.work + kJobCounter, job_res, kJobChunk); }
   // event scratch of the adjoint: [ev_max][ev_k][n_chunk], then [n_chunk]
@@ -274,10 +281,12 @@ __device__ __forceinline__ void life_body(const RunParams& P) {
   __shared__ long long dep_idx[kWavesPerBlock][64 * kDepPer];
   __shared__ double dep_val[kWavesPerBlock][64 * kDepPer];
   const int wave = threadIdx.x / 64;
-  LifeMem<R, GK, INST> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots), wave_reservoir(job_slots)};
+  LifeMem<R, GK, INST> M{static_cast<const R*>(P.rho), P, wave_reservoir(slots), wave_reservoir(job_slots),
+                         dep_idx[wave], dep_val[wave], 0};
   Lane<R> L;
   lane_init(L);
   int staged = 0;  // walk blocks of deposits staged in LDS (wavefront-uniform)
+  double* const tally = ADJ ? P.grad : P.absorbed;
   for (;;) {
     lane_events<R, ADJ>(L, P, M);
     const unsigned long long live = __ballot(!L.done);
@@ -286,19 +295,17 @@ __device__ __forceinline__ void life_body(const RunParams& P) {
     for (;;) {
       const int n_act = __popcll(__ballot(L.ry.active));
       if (n_act == 0 || n_live - n_act >= P.batch) break;
-      WalkDeposits dep;
-      dep.on = 0;
-      if (L.ry.active) lane_step<R, ADJ>(L, P, M, dep);
-      if (!ADJ && __ballot(dep.on != 0u)) {
-        stage_deposits(dep, staged, dep_idx[wave], dep_val[wave]);
+      M.stage_clear(staged);
+      const bool put = L.ry.active && lane_step<R, ADJ>(L, P, M);
+      if (__ballot(put)) {
         if (++staged == kDepBlocks) {
-          flush_deposits(staged, P.absorbed, dep_idx[wave], dep_val[wave]);
+          flush_deposits(staged, tally, dep_idx[wave], dep_val[wave]);
           staged = 0;
         }
       }
     }
   }
-  if (!ADJ && staged) flush_deposits(staged, P.absorbed, dep_idx[wave], dep_val[wave]);
+  if (staged) flush_deposits(staged, tally, dep_idx[wave], dep_val[wave]);
   if (P.jobs) {  // unfilled reserved queue slots
     const unsigned long long lo = M.job_res[0], hi = M.job_res[1] < P.job_cap ? M.job_res[1] : P.job_cap;
     for (unsigned long long q = lo + __lane_id(); q < hi; q += 64) P.jobs[q].key = kNoKey;

@@ -19,6 +19,7 @@
 // lane.  All memory goes through the accessor M:
 //   M.rho(cell)  M.det(d)  M.lam(l)  M.src(s)  M.adj(i)
 //   M.add_image(i, v)  M.add_absorbed(i, v)  M.add_grad(cell, v)
+//   M.walk_deposit<ADJ>(d, i, v)   (sub-step d's deposit of a walk block)
 //   M.fetch()  M.flush_counts(x_path, x_locate, x_peel, deposits)
 //   M.job_slot()  M.store_job(slot, ...)   (peel-ray queue)
 //   M.ev_load(slot, e, k)  M.ev_store(slot, e, k, v)   (adjoint event scratch)
@@ -550,35 +551,26 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
 // lane keeps in flight.
 constexpr int kBlockWalk = 4;
 
-// Absorbed-luminosity deposits of one forward walk block: index into the
-// tally, value, and a bit per sub-step that made one.  The kernel issues
-// them for the whole wavefront at once, transposed so that one walker's
-// deposits -- neighbouring cells, often in one 64-byte segment of the
-// bricked tally -- sit in adjacent lanes of one atomic instruction; the CPU
-// harness applies them in order.  (The adjoint's walk deposits, far fewer,
-// go straight to the gradient.)
-struct WalkDeposits {
-  long long idx[kBlockWalk];
-  double val[kBlockWalk];
-  unsigned on;
-};
-
-template <class Mem>
-MCRT_HD void apply_deposits(const WalkDeposits& dep, Mem& M) {
-  for (int d = 0; d < kBlockWalk; ++d)
-    if ((dep.on >> d) & 1u) M.add_absorbed(dep.idx[d], dep.val[d]);
-}
+// A walk block's deposits -- forward: absorbed luminosity into the tally;
+// adjoint: the walk's gradient terms (the locate leg's -R kappa l, an inline
+// peel ray's -A C kappa l, the absorbed-tally terms) into the gradient -- go
+// through M.walk_deposit<ADJ>(d, i, v), one per sub-step d at most.  The
+// kernel stages them in LDS and issues them for the whole wavefront at once,
+// transposed so that one walker's deposits -- neighbouring cells, often in
+// one segment of the bricked array -- sit in adjacent lanes of one atomic
+// instruction; the CPU harness applies them at once, in order.
 
 // Up to kBlockWalk crossings of the lane's active ray, with the per-crossing
 // work of its mode: pass-1 continuous absorption W (1 - albedo) e^-tau
 // (1 - e^-dtau) into the cell; pass-2 search for the first segment whose
 // optical depth passes tau_s (and, in the adjoint replay, -R kappa l deposits
 // along the leg); peel rays accumulate tau (and, on the deposit walk,
-// -A C kappa l).  Zero-length segments are skipped.
+// -A C kappa l).  Zero-length segments are skipped.  Returns whether the block
+// made a deposit.
 template <typename R, bool ADJ, class Mem>
-MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep) {
+MCRT_HD bool lane_step(Lane<R>& L, const RunParams& P, Mem& M) {
   Ray<R>& ry = L.ry;
-  dep.on = 0;
+  bool put = false;
   WalkBlock<kBlockWalk, R> b;
   ray_next_block(ry, b, P.G, M);
 #pragma unroll
@@ -598,14 +590,15 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
         // pass B also deposits -kappa l (B - P) + b W (1 - albedo) e^-tau e^-dtau kappa l
         const R em = expm1(-dtau);
         const double bj = M.adj_abs(L.lam_cell + cell);
-        const double dep = L.wabs * (double)(-L.trans * em);
+        const double da = L.wabs * (double)(-L.trans * em);
         if (L.abs_dep) {
-          L.Pabs += bj * dep;
+          L.Pabs += bj * da;
           const double kl = L.kap * (double)seg;
-          M.add_grad(cell, -kl * (L.Babs - L.Pabs) + bj * L.wabs * (double)(L.trans * (R(1) + em)) * kl);
+          M.template walk_deposit<ADJ>(d, cell, -kl * (L.Babs - L.Pabs) + bj * L.wabs * (double)(L.trans * (R(1) + em)) * kl);
+          put = true;
           ++L.n_dep;
         } else {
-          L.Babs += bj * dep;
+          L.Babs += bj * da;
         }
         L.trans += L.trans * em;
       }
@@ -616,9 +609,8 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
         L.trans += L.trans * em;
         L.absf += f;
         if (P.absorbed) {
-          dep.idx[d] = L.lam_cell + cell;
-          dep.val[d] = L.wabs * (double)f;
-          dep.on |= 1u << d;
+          M.template walk_deposit<ADJ>(d, L.lam_cell + cell, L.wabs * (double)f);
+          put = true;
           ++L.n_dep;
         }
       }
@@ -631,20 +623,22 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
         L.rho_hit = rs;
         ray_rewind<kBlockWalk, R, Mem::kGrid>(ry, b, d, P.G);
         ry.active = false;
-        return;
+        return put;
       }
       if (dtau > R(0)) {
         L.last_cell = cell;
         L.last_t = tm;
       }
       if (ADJ && L.pass == 1 && pos) {
-        M.add_grad(cell, L.fac * (double)seg);
+        M.template walk_deposit<ADJ>(d, cell, L.fac * (double)seg);
+        put = true;
         ++L.n_dep;
       }
     } else {
       L.x_peel += pos;
       if (ADJ && L.mode == M_PEEL_DEP && pos) {
-        M.add_grad(cell, L.fac * (double)seg);
+        M.template walk_deposit<ADJ>(d, cell, L.fac * (double)seg);
+        put = true;
         ++L.n_dep;
       }
     }
@@ -652,6 +646,7 @@ MCRT_HD void lane_step(Lane<R>& L, const RunParams& P, Mem& M, WalkDeposits& dep
     if (pos) ry.t = tm;
   }
   if (b.out || (Mem::kInst && ry.t >= ry.tmax)) ry.active = false;
+  return put;
 }
 
 // ---------------------------------------------------------------------------

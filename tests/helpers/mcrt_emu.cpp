@@ -163,6 +163,14 @@ struct HostLifeMem {
     check_cell(G, i, "gradient");
     grad[i] += v;
   }
+  template <bool ADJ>
+  void walk_deposit(int d, long long i, double v) {
+    EMU_CHECK(d >= 0 && d < kBlockWalk, "walk-block sub-step", d, kBlockWalk);
+    if (ADJ)
+      add_grad((int)i, v);
+    else
+      add_absorbed(i, v);
+  }
   unsigned long long fetch() { return next++; }
   unsigned long long x_queue = 0, d_queue = 0;
   // adjoint peel-job queue
@@ -449,11 +457,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
     for (auto& L : lanes) lane_init(L);
     run_wave(
         lanes, P.batch, [&](Lane<R>& L) { lane_events<R, ADJ>(L, P, M); },
-        [&](Lane<R>& L) {
-          WalkDeposits dep;
-          lane_step<R, ADJ>(L, P, M, dep);
-          apply_deposits(dep, M);
-        },
+        [&](Lane<R>& L) { lane_step<R, ADJ>(L, P, M); },
         cap, 0);
     for (auto& L : lanes) {
       sa += L.s_abs;
