@@ -580,7 +580,7 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
   P.w_min = opts->w_min;
   P.max_scatter = opts->max_scatter;
   P.flags = opts->flags;
-  P.batch = opts->event_batch > 0 ? opts->event_batch : 16;
+  P.batch = opts->event_batch > 0 ? opts->event_batch : kBatchForward;
 
   out.lam.assign(nl, LamDev{});
   for (int l = 0; l < nl; ++l) {

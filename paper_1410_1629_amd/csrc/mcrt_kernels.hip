@@ -1180,7 +1180,7 @@ int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ct
   J.ev_k = P.ev_k;
   J.n_chunk = P.n_chunk;
   J.ctr = ctr;
-  J.batch = 16;
+  J.batch = kBatchQueue;
   if (inst) {  // instruments other than frames: walks that stop at a camera's eye
     switch (P.G.kind) {
       case kGridRect: return walk_peel_jobs<R, ADJ, kGridRect, true>(J, st);
@@ -1452,6 +1452,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
       if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
       if (int e = reset_counters(ctr, kDepCounter, 1, st)) return e;
       P.split = 1;  // pass A
+      if (opts->event_batch == 0) P.batch = kBatchPassA;
       rc = f32 ? launch_life<float, true>(P, full, nblk, st) : launch_life<double, true>(P, full, nblk, st);
       if (rc) return rc;
       ++launches;
@@ -1459,6 +1460,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
         if (int e = queue_phase(true)) return e;
       if (int e = reset_counters(ctr, 0, 1, st)) return e;
       P.split = 2;  // pass B
+      if (opts->event_batch == 0) P.batch = kBatchPassB;
       rc = f32 ? launch_life<float, true>(P, full, nblk, st) : launch_life<double, true>(P, full, nblk, st);
       if (rc) return rc;
       ++launches;
