@@ -66,10 +66,11 @@ struct TreeNode {
 // workloads (1e7 packages): forward 32 (PowCub -7%, k-d tree -11%, spiral
 // unchanged against 16); adjoint 32 / 48 (-19% to -28% against 16 / 16).
 constexpr int kBatchForward = 32, kBatchPassA = 32, kBatchPassB = 48;
-// The peel-queue walks (optical depth, deposit walks) refill a lane with the
-// next sorted ray once this many of the wavefront's lanes have finished:
-// measured on the spiral, 48 against 16 saves 4 ms of the forward's queue
-// kernels and 6 ms of the adjoint's.
+// The ray kernels -- the peel-queue walks (optical depth, deposit walks) and
+// the trace and peel-off entry points -- refill a lane with the next ray once
+// this many of the wavefront's lanes have finished: measured on the spiral,
+// 48 against 16 saves 4 ms of the forward's queue kernels, 6 ms of the
+// adjoint's, and 6% of a trace over 4e6 random rays.
 constexpr int kBatchQueue = 48;
 
 // ---------------------------------------------------------------------------

@@ -1597,7 +1597,7 @@ int trace_path(const mcrt_grid* grid, const void* rho_dev, double kappa, int pre
     P.seg_cell = lists ? seg_cell_dev : nullptr;
     P.seg_len = lists ? seg_len_dev : nullptr;
     P.n_seg = n_seg_dev;
-    P.batch = 16;
+    P.batch = kBatchQueue;
     DeviceBlock blk;
     blk.st = st;
     const bool f32 = precision == MCRT_PREC_FP32;
@@ -1667,7 +1667,7 @@ int peel_off(const mcrt_grid* grid, const void* rho_dev, double kappa, double g,
     P.w = w_dev;
     P.images = images_dev;
     P.work = reinterpret_cast<unsigned long long*>(blk.ptr + off_cnt);
-    P.batch = 16;
+    P.batch = kBatchQueue;
     const int r = f32 ? launch_by_kind<PeelParams, float>(P, st, k_peel<float, kGridRegular>,
                                                           k_peel<float, kGridRect>, k_peel<float, kGridTree>)
                       : launch_by_kind<PeelParams, double>(P, st, k_peel<double, kGridRegular>,
