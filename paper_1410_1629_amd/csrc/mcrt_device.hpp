@@ -260,11 +260,8 @@ MCRT_HD U4 draw_words(uint64_t seed, uint64_t p, uint32_t l, uint32_t c) {
 // Uniform deviate strictly inside (0,1): (w + 1/2) 2^-32, exact in FP64.
 MCRT_HD double u01(uint32_t w) { return ((double)w + 0.5) * 2.3283064365386963e-10; }
 
-MCRT_HD void sincos2pi(double u, double* s, double* c) {
-  const double a = 2.0 * kPi * u;
-  *s = sin(a);
-  *c = cos(a);
-}
+// sin and cos of 2 pi u from one call (one argument reduction for both).
+MCRT_HD void sincos2pi(double u, double* s, double* c) { sincos(2.0 * kPi * u, s, c); }
 
 // ---------------------------------------------------------------------------
 // Henyey-Greenstein phase function and sampling (g sets the phase function,
