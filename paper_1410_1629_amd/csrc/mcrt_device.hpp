@@ -102,7 +102,39 @@ struct GridDev {
   const TreeNode* nodes;
   const double* leaf_box;  // tree grids: per cell lo x y z, hi x y z
   const int* ropes;        // tree grids: per cell and face (-x +x -y +y -z +z) the node across it, -1 outside
+  // Layout of the forward's absorbed-luminosity tally (tally_slot): units of
+  // 2^tb consecutive bricked cells, ntal cells per wavelength.
+  int tb;
+  long long ntal;
 };
+
+// Slot of bricked cell c in the forward's absorbed-luminosity tally.  The
+// tally takes one FP64 atomic per cell crossing, which the memory side
+// executes at the channel holding the address, so the busiest channel sets
+// the rate.  In the bricked order the cells packages cross most (the dense
+// middle of a disk) form short runs at a fixed stride, which can fall on few
+// channels; how few depends on where the tally lands in physical memory
+// (measured on the spiral: 93-115 ms for the forward life kernel over tally
+// offsets of 0-4 MiB).  So units of 2^tb cells -- whole bricks, and at least
+// one 64-byte segment -- are scattered over the array by a multiplicative
+// permutation (an odd multiplier modulo the power-of-two unit count), which
+// spreads any compact region over all channels (80-84 ms at every offset).
+// A unit keeps its cells in order, so neighbouring cells still share a
+// segment.
+constexpr unsigned kTallyMul = 0x9E3779B1u, kTallyMulInv = 0x0E8B2F51u;  // inverses modulo 2^32
+
+MCRT_HD long long tally_slot(const GridDev& G, int c) {
+  const unsigned mask = (unsigned)((G.ntal >> G.tb) - 1);
+  const unsigned u = ((unsigned)c >> G.tb) * kTallyMul & mask;
+  return ((long long)u << G.tb) | (long long)(c & ((1 << G.tb) - 1));
+}
+
+// Bricked cell of tally slot t (0 <= t < ntal): the inverse of tally_slot.
+MCRT_HD long long tally_cell(const GridDev& G, long long t) {
+  const unsigned mask = (unsigned)((G.ntal >> G.tb) - 1);
+  const unsigned u = (unsigned)(t >> G.tb) * kTallyMulInv & mask;
+  return ((long long)u << G.tb) | (t & ((1ll << G.tb) - 1));
+}
 
 // Leaf below node q of a tree grid holding point (px, py, pz), for a ray
 // with direction signs (sx, sy, sz): at each split a point on the plane goes

@@ -270,6 +270,15 @@ inline int check_brick(int brick_shape) {
   return 0;
 }
 
+// Tally layout (tally_slot): units of whole bricks of at least 8 cells (one
+// 64-byte segment of FP64 values), their count rounded up to a power of two.
+inline void set_tally_layout(GridDev& G) {
+  G.tb = std::max(G.lb[0] + G.lb[1] + G.lb[2], 3);
+  long long units = 1;
+  while ((units << G.tb) < (long long)G.ncell_pad) units <<= 1;
+  G.ntal = units << G.tb;
+}
+
 // Device grid description: geometry, row-major strides and the bricked
 // layout.  Fails if the bricked arrays would exceed 2^31 - 1 cells.
 inline int make_grid(const mcrt_grid& g, int elem_bytes, int brick_shape, GridDev& G) {
@@ -298,6 +307,7 @@ inline int make_grid(const mcrt_grid& g, int elem_bytes, int brick_shape, GridDe
     G.bstride[0] = 1;
     G.bstride[1] = G.bstride[2] = nc;
     G.ncell_pad = nc;
+    set_tally_layout(G);
     return 0;
   }
   G.stride[0] = 1;
@@ -318,6 +328,7 @@ inline int make_grid(const mcrt_grid& g, int elem_bytes, int brick_shape, GridDe
   G.bstride[1] = G.nb[0] * cpb;
   G.bstride[2] = G.nb[0] * G.nb[1] * cpb;
   G.ncell_pad = (int)pad;
+  set_tally_layout(G);
   return 0;
 }
 

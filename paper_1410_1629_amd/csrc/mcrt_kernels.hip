@@ -788,9 +788,11 @@ __global__ void k_brick(const R* __restrict__ src, R* __restrict__ dst, const Gr
   }
 }
 
-// Bricked tally [n_lambda][ncell_pad] -> row-major [n_lambda][ncell]; one
-// thread per row-major cell.
-__global__ void k_unbrick(const double* __restrict__ src, double* __restrict__ dst, const GridDev G, int n_lambda) {
+// Library tally -> row-major [n_lambda][ncell]; one thread per row-major
+// cell.  slots: the forward's absorbed tally [n_lambda][ntal], cell c at
+// tally_slot(c); otherwise a bricked array [n_lambda][ncell_pad].
+__global__ void k_unbrick(const double* __restrict__ src, double* __restrict__ dst, const GridDev G, int n_lambda,
+                          bool slots) {
   const long long n = (long long)n_lambda * G.ncell;
   for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
     const long long l = q / G.ncell;
@@ -800,7 +802,8 @@ __global__ void k_unbrick(const double* __restrict__ src, double* __restrict__ d
     const int t = m / G.n[0];
     i[1] = t % G.n[1];
     i[2] = t / G.n[1];
-    dst[q] = src[l * G.ncell_pad + brick_addr(G, i)];
+    const int c = brick_addr(G, i);
+    dst[q] = slots ? src[l * G.ntal + tally_slot(G, c)] : src[l * G.ncell_pad + c];
   }
 }
 
@@ -1016,9 +1019,9 @@ int brick_density(const GridDev& G, const void* rho, void* dst, bool f32, hipStr
   return 0;
 }
 
-int unbrick_tally(const GridDev& G, const double* src, double* dst, int n_lambda, hipStream_t st) {
+int unbrick_tally(const GridDev& G, const double* src, double* dst, int n_lambda, bool slots, hipStream_t st) {
   hipLaunchKernelGGL(k_unbrick, dim3(stream_blocks((long long)n_lambda * G.ncell)), dim3(kBlock), 0, st, src, dst, G,
-                     n_lambda);
+                     n_lambda, slots);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -1309,7 +1312,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const unsigned long long chunk = (P.n_items + n_chunks - 1) / n_chunks;
   // the adjoint's event scratch, then (optics gradients) the pass-B sums
   const size_t n_evs = adjoint ? (size_t)chunk * ((size_t)kEventsKept * ev_k + 1 + (optg ? 4 : 0)) : 0;
-  const long long n_tally = adjoint ? (long long)P.G.ncell_pad : (P.absorbed ? (long long)nl * P.G.ncell_pad : 0);
+  const long long n_tally = adjoint ? (long long)P.G.ncell_pad : (P.absorbed ? (long long)nl * P.G.ntal : 0);
   const size_t off_lam = 0;
   const size_t off_det = align256(sizeof(LamDev) * nl);
   const size_t off_src = off_det + align256(sizeof(DetDev) * pr.det.size());
@@ -1474,7 +1477,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   }
   if (stats) HIPCHK(hipEventRecord(ev.c, st));
   if (tally && user_tally)
-    if (int e = unbrick_tally(P.G, tally, user_tally, adjoint ? 1 : nl, st)) return e;
+    if (int e = unbrick_tally(P.G, tally, user_tally, adjoint ? 1 : nl, !adjoint, st)) return e;
   if (stats) {
     double ds[3];
     unsigned long long xs[7], xq[2] = {0, 0};

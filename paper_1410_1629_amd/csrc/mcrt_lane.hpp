@@ -24,9 +24,10 @@
 //   M.job_slot()  M.store_job(slot, ...)   (peel-ray queue)
 //   M.ev_load(slot, e, k)  M.ev_store(slot, e, k, v)   (adjoint event scratch)
 //   M.opt_store(slot, ga, gg, gl, src)   (pass B sums for the optics gradients)
-// Cells are bricked addresses (GridDev): densities, the absorbed tally
-// (wavelength-major, ncell_pad per wavelength) and the gradient are all in
-// the bricked layout inside the library.
+// Cells are bricked addresses (GridDev): densities, the gradient and dL/dA
+// (wavelength-major, ncell_pad per wavelength) are in the bricked layout
+// inside the library; the forward's absorbed tally is wavelength-major with
+// ntal slots per wavelength, cell c at tally_slot(c).
 //
 // Adjoint (ADJ = true): the detached derivative of C, a peel-off contribution
 // of event e, with respect to the density of cell m is
@@ -137,7 +138,7 @@ struct Lane {
   R kapR, tau_sR, absf, trans, tau_prev, rho_hit, last_t;
   unsigned uw1, uw2;
   int hit_cell, last_cell;
-  long long lam_cell;
+  long long lam_cell;  // the package's wavelength row of the absorbed tally: lam * ntal
   // adjoint replay
   int pass;
   int slot;  // the lane's index in the event scratch
@@ -462,7 +463,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
         L.slot = (int)k;
         L.lam = (int)(item / P.n_pkg);
         L.pkg = P.first + (item - (unsigned long long)L.lam * P.n_pkg);
-        L.lam_cell = (long long)L.lam * G.ncell_pad;
+        L.lam_cell = (long long)L.lam * G.ntal;
         const LamDev& LD = M.lam(L.lam);
         L.kap = LD.kappa;
         L.kapR = (R)L.kap;
@@ -589,7 +590,7 @@ MCRT_HD bool lane_step(Lane<R>& L, const RunParams& P, Mem& M) {
         // absorbed-tally adjoint: deposit dep = W (1 - albedo) e^-tau (1 - e^-dtau) weighted by b;
         // pass B also deposits -kappa l (B - P) + b W (1 - albedo) e^-tau e^-dtau kappa l
         const R em = expm1(-dtau);
-        const double bj = M.adj_abs(L.lam_cell + cell);
+        const double bj = M.adj_abs((long long)L.lam * P.G.ncell_pad + cell);
         const double da = L.wabs * (double)(-L.trans * em);
         if (L.abs_dep) {
           L.Pabs += bj * da;
@@ -609,7 +610,7 @@ MCRT_HD bool lane_step(Lane<R>& L, const RunParams& P, Mem& M) {
         L.trans += L.trans * em;
         L.absf += f;
         if (P.absorbed) {
-          M.template walk_deposit<ADJ>(d, L.lam_cell + cell, L.wabs * (double)f);
+          M.template walk_deposit<ADJ>(d, L.lam_cell + tally_slot(P.G, cell), L.wabs * (double)f);
           put = true;
           ++L.n_dep;
         }

@@ -55,12 +55,15 @@ std::vector<R> brick_copy(const GridDev& G, const R* rho) {
   return out;
 }
 
-// Bricked tally [n][ncell_pad] -> row-major [n][ncell].
-inline void unbrick(const GridDev& G, const std::vector<double>& src, double* dst, int n) {
+// Library tally -> row-major [n][ncell]: the forward's absorbed tally
+// [n][ntal] at tally_slot (slots), or a bricked array [n][ncell_pad].
+inline void unbrick(const GridDev& G, const std::vector<double>& src, double* dst, int n, bool slots) {
   for (int l = 0; l < n; ++l)
     for (int m = 0; m < G.ncell; ++m) {
       int i[3] = {m % G.n[0], (m / G.n[0]) % G.n[1], m / G.n[0] / G.n[1]};
-      dst[(long long)l * G.ncell + m] = src[(size_t)l * G.ncell_pad + brick_addr(G, i)];
+      const int c = brick_addr(G, i);
+      dst[(long long)l * G.ncell + m] =
+          slots ? src[(size_t)l * G.ntal + tally_slot(G, c)] : src[(size_t)l * G.ncell_pad + c];
     }
 }
 
@@ -155,7 +158,8 @@ struct HostLifeMem {
   }
   void add_absorbed(long long i, double v) {
     EMU_CHECK(i >= 0 && i < n_absorbed, "absorbed tally", i, n_absorbed);
-    check_cell(G, i % G.ncell_pad, "absorbed tally");
+    EMU_CHECK(i % G.ntal == tally_slot(G, (int)tally_cell(G, i % G.ntal)), "absorbed tally slot", i, n_absorbed);
+    check_cell(G, tally_cell(G, i % G.ntal), "absorbed tally");
     absorbed[i] += v;
   }
   void add_grad(int i, double v) {
@@ -440,7 +444,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   if (P.absorbed && n_absorbed < (long long)P.n_lambda * P.G.ncell) throw Violation("absorbed buffer too small");
   if (ADJ && grad && n_grad < P.G.ncell) throw Violation("gradient buffer too small");
   const std::vector<R> rho_b = brick_copy(P.G, static_cast<const R*>(rho));
-  std::vector<double> abs_b(P.absorbed ? (size_t)P.n_lambda * P.G.ncell_pad : 0, 0.0);
+  std::vector<double> abs_b(P.absorbed ? (size_t)P.n_lambda * P.G.ntal : 0, 0.0);
   std::vector<double> grad_b(ADJ && grad ? (size_t)P.G.ncell_pad : 0, 0.0);
   HostLifeMem<R, GK, INST> M{rho_b.data(), P.G, pr, images, n_images, P.absorbed ? abs_b.data() : nullptr,
                    (long long)abs_b.size(), adj, n_adj, grad_b.data(), (long long)grad_b.size()};
@@ -560,8 +564,8 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   }
   M.xs[2] += M.x_queue;
   M.xs[6] += M.d_queue;
-  if (P.absorbed) unbrick(P.G, abs_b, absorbed, P.n_lambda);
-  if (ADJ && grad) unbrick(P.G, grad_b, grad, 1);
+  if (P.absorbed) unbrick(P.G, abs_b, absorbed, P.n_lambda, true);
+  if (ADJ && grad) unbrick(P.G, grad_b, grad, 1, false);
   if (stats) {
     stats->emitted = pr.emitted;
     stats->absorbed = sa;
