@@ -49,6 +49,9 @@ class Emu:
         lib.emu_dust_emission.argtypes = [C.POINTER(B.Grid), P, C.c_int, C.c_int, P, C.c_int, P, P, P, d, P, P]
         for f in ("emu_run_photons", "emu_backward_density", "emu_trace_path", "emu_peel_off", "emu_dust_emission"):
             getattr(lib, f).restype = C.c_int
+        lib.emu_tally_layout.argtypes = [C.POINTER(B.Grid), C.c_int, C.c_int, C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_int)]
+        lib.emu_tally_layout.restype = C.c_int
         lib.emu_set_events_kept.argtypes = [C.c_int]
         lib.emu_set_events_kept.restype = None
         lib.emu_set_chunk_items.argtypes = [C.c_int]
@@ -112,6 +115,14 @@ class Emu:
         if optics:
             return g, st.as_dict(), {"albedo": gopt[0], "g": gopt[1], "lum": gopt[2:]}
         return g, st.as_dict()
+
+    def tally_layout(self, box, n, prec, brick_shape=0, planes=None, tree=None):
+        """(slots per wavelength, unit bits) of the absorbed tally, after the
+        harness has checked the layout on every cell."""
+        g = B.make_grid({"box": box, "n": n, "planes": planes, "tree": tree})
+        ntal, tb = C.c_int64(0), C.c_int(0)
+        self._check(self.lib.emu_tally_layout(C.byref(g), int(prec), int(brick_shape), C.byref(ntal), C.byref(tb)))
+        return ntal.value, tb.value
 
     def trace(self, box, n, rho, kappa, prec, origins, dirs, max_seg=0, wave=WAVE, brick_shape=0, planes=None,
               tree=None):

@@ -836,6 +836,40 @@ int emu_backward_density(const mcrt_grid* grid, const void* rho, const mcrt_opti
   }
 }
 
+// Checks the library's absorbed-tally layout on grid (precision, brick
+// shape as in a run): every bricked cell's slot lies in [0, ntal), no two
+// cells share one, tally_cell inverts tally_slot, a cell keeps its place
+// inside its unit, and the unit count is a power of two.  Returns ntal and
+// the unit bits.
+int emu_tally_layout(const mcrt_grid* grid, int precision, int brick_shape, int64_t* ntal, int* tb) {
+  try {
+    g_violation.clear();
+    host::last_error().clear();
+    GridDev G{};
+    if (int e = host::make_grid(*grid, host::elem_bytes(precision), brick_shape, G)) return e;
+    const long long unit = 1ll << G.tb, units = G.ntal / unit;
+    EMU_CHECK(G.tb >= 3 && G.tb >= G.lb[0] + G.lb[1] + G.lb[2], "unit bits", G.tb, 32);
+    EMU_CHECK(units * unit == G.ntal && (units & (units - 1)) == 0, "unit count", units, G.ntal);
+    EMU_CHECK(G.ntal >= G.ncell_pad && G.ntal < 2 * ((long long)G.ncell_pad + unit), "tally slots", G.ntal,
+              2 * ((long long)G.ncell_pad + unit));
+    std::vector<unsigned char> seen((size_t)G.ntal, 0);
+    for (int c = 0; c < G.ncell_pad; ++c) {
+      const long long t = tally_slot(G, c);
+      EMU_CHECK(t >= 0 && t < G.ntal, "tally slot", t, G.ntal);
+      EMU_CHECK(!seen[(size_t)t], "tally slot taken twice", t, G.ntal);
+      seen[(size_t)t] = 1;
+      EMU_CHECK(tally_cell(G, t) == c, "tally_cell of the slot", c, G.ncell_pad);
+      EMU_CHECK((t & (unit - 1)) == (c & (unit - 1)), "place inside the unit", c, unit);
+    }
+    *ntal = G.ntal;
+    *tb = G.tb;
+    return 0;
+  } catch (const Violation& v) {
+    g_violation = std::string("tally layout: ") + v.what();
+    return -100;
+  }
+}
+
 int emu_trace_path(const mcrt_grid* grid, const void* rho, double kappa, int precision, int64_t n_rays,
                    const double* origin, const double* dir, double* tau, int32_t max_seg, int32_t* seg_cell,
                    double* seg_len, int32_t* n_seg, uint64_t* crossings, int brick_shape, int wave) {
