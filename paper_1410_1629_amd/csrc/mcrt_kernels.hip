@@ -204,12 +204,11 @@ struct LifeMem {
     J.r[2] = r[2];
     J.v = v;
     J.ii = ii;
-    J.key = key;
     J.slot = item;
     J.lam = lam;
     J.e = (unsigned short)e;
     J.d = (unsigned char)d;
-    J.sub = (unsigned char)sub;
+    P.keys[slot] = key | (sub << 16);  // the sort reads these words only, not the 56-byte rays
   }
   __device__ void flush_counts(unsigned a, unsigned b, unsigned c, unsigned d) const {
     atomicAdd(P.xstats + 0, (unsigned long long)a);
@@ -308,7 +307,7 @@ __device__ __forceinline__ void life_body(const RunParams& P) {
   if (staged) flush_deposits(staged, tally, dep_idx[wave], dep_val[wave]);
   if (P.jobs) {  // unfilled reserved queue slots
     const unsigned long long lo = M.job_res[0], hi = M.job_res[1] < P.job_cap ? M.job_res[1] : P.job_cap;
-    for (unsigned long long q = lo + __lane_id(); q < hi; q += 64) P.jobs[q].key = kNoKey;
+    for (unsigned long long q = lo + __lane_id(); q < hi; q += 64) P.keys[q] = kNoKey;
   }
   const double s_abs = wave_sum(L.s_abs), s_esc = wave_sum(L.s_esc), s_trunc = wave_sum(L.s_trunc);
   const unsigned long long a0 = wave_sum_u64(L.x_path), a1 = wave_sum_u64(L.x_loc), a2 = wave_sum_u64(L.x_peel),
@@ -416,6 +415,7 @@ __device__ __forceinline__ unsigned long long queued_jobs(const unsigned long lo
 // fill (kNoKey) are skipped.  No global atomics: LDS counters do the
 // ranking; the order of rays with equal keys is arbitrary.
 constexpr int kSortThreads = 1024, kSortBlocks = host::kSortBlocks, kRefineThreads = 256, kSubKeys = 256;
+static_assert(host::kSortKeys <= (1 << 16) && kSubKeys <= 256, "a ray's keys share one word: key | sub << 16");
 
 __device__ __forceinline__ void sort_part(unsigned long long n, unsigned long long& lo, unsigned long long& hi) {
   const unsigned long long per = (n + kSortBlocks - 1) / kSortBlocks;
@@ -423,7 +423,7 @@ __device__ __forceinline__ void sort_part(unsigned long long n, unsigned long lo
   hi = lo + per < n ? lo + per : n;
 }
 
-__global__ void __launch_bounds__(kSortThreads) k_hist(const PeelJob* __restrict__ jobs,
+__global__ void __launch_bounds__(kSortThreads) k_hist(const unsigned* __restrict__ keys,
                                                        const unsigned long long* __restrict__ ctr,
                                                        unsigned long long cap, int n_keys,
                                                        unsigned* __restrict__ counts) {
@@ -433,14 +433,14 @@ __global__ void __launch_bounds__(kSortThreads) k_hist(const PeelJob* __restrict
   unsigned long long lo, hi;
   sort_part(queued_jobs(ctr, cap), lo, hi);
   for (unsigned long long j = lo + threadIdx.x; j < hi; j += kSortThreads) {
-    const unsigned key = jobs[j].key;
-    if (key != kNoKey) atomicAdd(h + key, 1u);
+    const unsigned w = keys[j];
+    if (w != kNoKey) atomicAdd(h + (w & 0xffffu), 1u);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n_keys; i += kSortThreads) counts[(size_t)i * kSortBlocks + blockIdx.x] = h[i];
 }
 
-__global__ void __launch_bounds__(kSortThreads) k_scatter(const PeelJob* __restrict__ jobs,
+__global__ void __launch_bounds__(kSortThreads) k_scatter(const unsigned* __restrict__ keys,
                                                           const unsigned long long* __restrict__ ctr,
                                                           unsigned long long cap, int n_keys,
                                                           const unsigned* __restrict__ starts,
@@ -451,12 +451,11 @@ __global__ void __launch_bounds__(kSortThreads) k_scatter(const PeelJob* __restr
   unsigned long long lo, hi;
   sort_part(queued_jobs(ctr, cap), lo, hi);
   for (unsigned long long j = lo + threadIdx.x; j < hi; j += kSortThreads) {
-    const PeelJob& J = jobs[j];
-    const unsigned key = J.key;
-    if (key != kNoKey) {
-      const unsigned q = atomicAdd(h + key, 1u);
+    const unsigned w = keys[j];
+    if (w != kNoKey) {
+      const unsigned q = atomicAdd(h + (w & 0xffffu), 1u);
       idx[q] = (unsigned)j;
-      subs[q] = J.sub;
+      subs[q] = (unsigned char)(w >> 16);
     }
   }
 }
@@ -1074,14 +1073,14 @@ struct EventPair {
 // Device memory of the peel-ray queue: rays, their sorted order (and the
 // order after the first sort pass with the second keys), the sort's count
 // matrix (keys x kSortBlocks), its scan and the scan's tile totals.
-constexpr size_t kQueueBytesPerRay = sizeof(PeelJob) + 2 * sizeof(unsigned) + 1;
+constexpr size_t kQueueBytesPerRay = sizeof(PeelJob) + 3 * sizeof(unsigned) + 1;
 struct PeelQueue {
   unsigned char* ptr = nullptr;
   hipStream_t st = nullptr;
   unsigned long long cap = 0;
   long long n_keys = 0;
   PeelJob* jobs = nullptr;
-  unsigned *perm = nullptr, *idx = nullptr, *counts = nullptr, *starts = nullptr, *tiles = nullptr;
+  unsigned *keys = nullptr, *perm = nullptr, *idx = nullptr, *counts = nullptr, *starts = nullptr, *tiles = nullptr;
   unsigned char* subs = nullptr;
   ~PeelQueue() {
     if (ptr) (void)hipFreeAsync(ptr, st);
@@ -1108,7 +1107,8 @@ int make_peel_queue(const mcrt_opts& o, const host::Prepared& pr, unsigned long 
     if (cap == 0) return 0;
   }
   const size_t n_cnt = (size_t)q.n_keys * kSortBlocks;
-  const size_t off_perm = align256(sizeof(PeelJob) * cap);
+  const size_t off_keys = align256(sizeof(PeelJob) * cap);
+  const size_t off_perm = off_keys + align256(sizeof(unsigned) * cap);
   const size_t off_idx = off_perm + align256(sizeof(unsigned) * cap);
   const size_t off_subs = off_idx + align256(sizeof(unsigned) * cap);
   const size_t off_cnt = off_subs + align256(cap);
@@ -1118,6 +1118,7 @@ int make_peel_queue(const mcrt_opts& o, const host::Prepared& pr, unsigned long 
   HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&q.ptr), bytes, st));
   q.cap = cap;
   q.jobs = reinterpret_cast<PeelJob*>(q.ptr);
+  q.keys = reinterpret_cast<unsigned*>(q.ptr + off_keys);
   q.perm = reinterpret_cast<unsigned*>(q.ptr + off_perm);
   q.idx = reinterpret_cast<unsigned*>(q.ptr + off_idx);
   q.subs = q.ptr + off_subs;
@@ -1155,14 +1156,14 @@ int walk_peel_jobs(const PeelJobParams& J, hipStream_t st) {
 template <typename R, bool ADJ>
 int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ctr, bool inst, hipStream_t st) {
   const long long n_cnt = q.n_keys * kSortBlocks;
-  hipLaunchKernelGGL(k_hist, dim3(kSortBlocks), dim3(kSortThreads), 0, st, q.jobs, ctr, q.cap, (int)q.n_keys,
+  hipLaunchKernelGGL(k_hist, dim3(kSortBlocks), dim3(kSortThreads), 0, st, q.keys, ctr, q.cap, (int)q.n_keys,
                      q.counts);
   const long long n_tiles = (n_cnt + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, st, q.counts, q.starts, q.tiles,
                      n_cnt);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kTopThreads), 0, st, q.tiles, n_tiles, q.starts, n_cnt);
   hipLaunchKernelGGL(k_scan_add, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, st, q.starts, q.tiles, n_cnt);
-  hipLaunchKernelGGL(k_scatter, dim3(kSortBlocks), dim3(kSortThreads), 0, st, q.jobs, ctr, q.cap, (int)q.n_keys,
+  hipLaunchKernelGGL(k_scatter, dim3(kSortBlocks), dim3(kSortThreads), 0, st, q.keys, ctr, q.cap, (int)q.n_keys,
                      q.starts, q.idx, q.subs);
   hipLaunchKernelGGL(k_refine, dim3((unsigned)q.n_keys), dim3(kRefineThreads), 0, st, q.starts, q.idx, q.subs, q.perm);
   HIPCHK(hipGetLastError());
@@ -1395,6 +1396,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   if (queued) {
     if (int e = make_peel_queue(*opts, pr, chunk, st, queue)) return e;
     P.jobs = queue.cap ? queue.jobs : nullptr;
+    P.keys = queue.cap ? queue.keys : nullptr;
     P.job_cap = queue.cap;
   }
   unsigned long long* const ctr = reinterpret_cast<unsigned long long*>(blk.ptr + off_cnt);

@@ -83,7 +83,7 @@ struct PeelJob {
   double r[3];
   double v;
   long long ii;
-  unsigned key, slot, lam;
+  unsigned key, slot, lam;  // key and sub: sort keys (the device queue holds them in RunParams::keys)
   unsigned short e;
   unsigned char d, sub;
 };
@@ -112,6 +112,7 @@ struct RunParams {
   int split;                   // 1: pass A, 2: pass B
   unsigned long long item0, n_chunk;  // work items [item0, item0 + n_chunk)
   PeelJob* jobs;               // forward run and pass A: queue of peel rays (NULL: walk every peel ray here)
+  unsigned* keys;              // the device queue's sort keys, one word per ray: key | sub << 16
   unsigned long long job_cap;  // its capacity; rays beyond it are walked here
   int ev_max;                  // events kept per package in the event scratch
   int ev_k;                    // doubles per event: T of the leg after it, then q per frame
