@@ -46,7 +46,10 @@
  *    read only during the call.  The library keeps no state between calls.
  *    Each call allocates stream-ordered device memory (hipMallocAsync) for
  *    its tables, a bricked copy of the densities and, where it has one, a
- *    bricked tally, and frees it on the stream when its work ends. 
+ *    tally in the library's own cell order (the forward's absorbed tally
+ *    takes up to twice the cells of the grid per wavelength: its cell units
+ *    are padded to a power of two), the adjoint's event scratch and the
+ *    peel-ray queue, and frees it on the stream when its work ends.
  *  - Errors: 0 on success; MCRT_EINVAL for invalid arguments (nothing is
  *    launched), MCRT_EOVERFLOW when a segment buffer was too small,
  *    MCRT_EHIP for a HIP runtime error.  mcrt_last_error() returns a message
