@@ -373,7 +373,7 @@ def main():
     ap.add_argument("--profiles-dir", default=os.path.join(ROOT, "profiles"), help="where the summaries go")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+        print("bench.py measures one GPU only: the library has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     if args.collect_profiles or args.summarize_profiles:

@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped (not failed) on a machine without a GPU when they
-    # are collected together with CPU tests; `-m gpu` on a GPU machine runs them.
+    # are collected together with CPU tests; `-m gpu` on a machine with an MI355X runs them.
     try:
         import torch
         has_gpu = torch.cuda.is_available()
