@@ -568,8 +568,13 @@ struct PeelJobParams {
   const DetDev* det;
   const LamDev* lam;
   int n_det;
-  PeelJob* jobs;  // the adjoint's optical-depth walks overwrite v with the deposit weight
+  PeelJob* jobs;
   const unsigned* perm;      // sorted order of the queue
+  // the adjoint's deposit weight of sorted ray i, as the low and high words
+  // of a double at wlo[i], whi[i]: the sort's key and index arrays, free once
+  // the order is known, written and read in sorted order
+  unsigned* wlo;
+  unsigned* whi;
   const unsigned* n_sorted;  // number of sorted rays
   double* images;            // forward
   const double* adj;
@@ -632,8 +637,8 @@ __device__ __forceinline__ void flush_images(bool& has, long long ii, double c, 
 // The optical-depth walks of the sorted queue, one ray per lane in a lean
 // persistent loop (no LDS table, so many waves per SIMD hide the density
 // loads).  Forward: C = v e^-tau goes to the ray's pixel (flush_images).
-// Adjoint: q = (dL/dI) v e^-tau goes to the event scratch, and the job's v
-// becomes the deposit weight -q kappa (0: no deposit walk).
+// Adjoint: q = (dL/dI) v e^-tau goes to the event scratch, and the deposit
+// weight -q kappa to the ray's sorted position (wlo, whi; 0: no deposit walk).
 template <typename R, bool ADJ, int GK, bool INST>
 __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2];
@@ -645,7 +650,7 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
   ry.active = false;
   ry.tau = R(0);
   bool done = false, pending = false, has = false;
-  unsigned job = 0;
+  unsigned job = 0, pend_qi = 0;
   R kap = R(0);
   long long out_ii = 0;
   double out_c = 0.0;
@@ -665,7 +670,10 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
             P.evs[((size_t)J.e * P.ev_k + 1 + J.d) * P.n_chunk + J.slot] = q;
           else
             atomic_add_f64(P.evs + (size_t)P.ev_max * P.ev_k * P.n_chunk + J.slot, q);
-          J.v = -q * P.lam[J.lam].kappa;
+          const double w = -q * P.lam[J.lam].kappa;
+          const unsigned long long wb = (unsigned long long)__double_as_longlong(w);
+          P.wlo[pend_qi] = (unsigned)wb;
+          P.whi[pend_qi] = (unsigned)(wb >> 32);
         }
         pending = false;
       }
@@ -675,6 +683,7 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
         break;
       }
       job = P.perm[qi];
+      pend_qi = (unsigned)qi;
       const PeelJob& J = P.jobs[job];
       kap = (R)P.lam[J.lam].kappa;
       if constexpr (INST) {
@@ -735,9 +744,9 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
           done = true;
           break;
         }
-        const PeelJob& J = P.jobs[P.perm[qi]];
-        w = J.v;
+        w = __longlong_as_double((long long)(((unsigned long long)P.whi[qi] << 32) | P.wlo[qi]));
         if (w != 0.0) {
+          const PeelJob& J = P.jobs[P.perm[qi]];
           if constexpr (INST) {
             double kd[3], inv_d2, tmax;
             peel_geometry(P.det[J.d], J.r, kd, inv_d2, tmax);
@@ -1179,6 +1188,8 @@ int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ct
   J.n_det = P.n_det;
   J.jobs = q.jobs;
   J.perm = q.perm;
+  J.wlo = q.keys;
+  J.whi = q.idx;
   J.n_sorted = q.starts + n_cnt;
   J.images = P.images;
   J.adj = P.adj;
