@@ -22,8 +22,11 @@
  *    axis; a point on a wall moving towards lower indices belongs to the
  *    lower cell.
  *  - Densities live on the device.  precision == MCRT_PREC_FP64: double;
- *    precision == MCRT_PREC_FP32: float (traversal in FP32, package state
- *    and every tally in FP64).
+ *    precision == MCRT_PREC_FP32: float (the walk's densities, optical
+ *    depths and exponentials in FP32; package state, every tally, and the
+ *    crossing times of the life-cycle kernel's walks in FP64 -- a segment's
+ *    length is a difference of two crossing times, which FP32 would carry
+ *    with an error proportional to the distance walked).
  *  - Images are FP64 flux per pixel (luminosity / distance^2), laid out as
  *    [comp][lambda][frame pixels], where one wavelength's block is the
  *    frames one after another, each [ny][nx] row-major; comp is 2 with
@@ -200,7 +203,15 @@ typedef struct {
  * kernel (forward: the contribution goes to its pixel); the adjoint walks
  * them again for their deposits in bundles whose deposits are summed in LDS
  * before they reach the gradient.  The results do not depend on the cap up
- * to the order of FP64 additions. */
+ * to the order of FP64 additions -- and, in the FP32 path, up to FP32
+ * rounding of the peel walks (walked inline, a ray keeps the life-cycle
+ * kernel's FP64 times; queued, the queue kernel's FP32 times).
+ * max_chunk caps the packages (work items: packages x wavelengths) of one
+ * chunk of the call: 0 = library choice (chunks as large as the peel-ray
+ * queue and the adjoint's event scratch allow), else at most that many per
+ * chunk; each chunk is a launch of the life-cycle kernel (two in the
+ * adjoint) followed by its queue's sort and walks.  Results do not depend on
+ * it up to the order of FP64 additions. */
 typedef struct {
     uint64_t n_packages, first_package, seed;
     int32_t precision;
@@ -210,6 +221,7 @@ typedef struct {
     int32_t launch_blocks, event_batch;
     int32_t brick_shape;
     int64_t peel_queue;
+    int64_t max_chunk;
 } mcrt_opts;
 
 #define MCRT_BRICK(lx, ly, lz) (0x1000 | (lx) | ((ly) << 4) | ((lz) << 8))
@@ -369,7 +381,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 13
+#define MCRT_ABI_VERSION 14
 
 #ifdef __cplusplus
 }

@@ -60,7 +60,7 @@ class Opts(C.Structure):
     _fields_ = [("n_packages", C.c_uint64), ("first_package", C.c_uint64), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("w_min", C.c_double), ("max_scatter", C.c_int32),
                 ("flags", C.c_uint32), ("launch_blocks", C.c_int32), ("event_batch", C.c_int32),
-                ("brick_shape", C.c_int32), ("peel_queue", C.c_int64)]
+                ("brick_shape", C.c_int32), ("peel_queue", C.c_int64), ("max_chunk", C.c_int64)]
 
 
 def brick(lx, ly, lz):
@@ -87,7 +87,7 @@ class Stats(C.Structure):
 _lib = None
 
 # Exported symbols of include/mcrt.h.
-ABI_VERSION = 13  # MCRT_ABI_VERSION of the header these structs follow
+ABI_VERSION = 14  # MCRT_ABI_VERSION of the header these structs follow
 SYMBOLS = ("run_photons", "trace_path", "peel_off", "backward_density", "backward", "dust_emission",
            "mcrt_last_error", "mcrt_abi_version")
 
@@ -144,6 +144,42 @@ def _ptr(t):
     if not t.is_contiguous():
         raise ValueError("expected a contiguous tensor")
     return C.c_void_p(t.data_ptr())
+
+
+def _need(t, what, numel, dtype=None):
+    """Checks a device tensor before its pointer reaches a kernel: the
+    element count the layout needs and the element type (FP64 unless given).
+    A kernel trusts these, so a mismatch is an error here, before any call."""
+    import torch
+    if t is None:
+        return
+    dt = torch.float64 if dtype is None else dtype
+    if t.dtype != dt:
+        raise ValueError("%s must be %s, got %s" % (what, dt, t.dtype))
+    if t.numel() != numel:
+        raise ValueError("%s has %d elements, the layout needs %d" % (what, t.numel(), numel))
+
+
+def _density_dtype(precision):
+    import torch
+    return torch.float32 if int(precision) == PREC_FP32 else torch.float64
+
+
+def _check_life(prob, rho, images=None, absorbed=None, adj=None, grad=None, overrides=None):
+    """Sizes and types of a life-cycle call's device tensors (run_photons,
+    backward_density, backward): rho float32 for the FP32 path and float64
+    for the FP64 path with one value per cell; images and dL/dI in the image
+    layout; the absorbed tally and dL/dA [n_lambda][ncell]; the density
+    gradient [ncell]; all FP64."""
+    prec = (overrides or {}).get("precision", prob.get("precision", 0))
+    ncell = n_cells(prob)
+    nl = len(np.atleast_1d(prob["kappa"]))
+    _need(rho, "rho", ncell, _density_dtype(prec))
+    npix = int(np.prod(image_shape(prob)))
+    _need(images, "images", npix)
+    _need(adj, "adj_images", npix)
+    _need(absorbed, "absorbed", nl * ncell)
+    _need(grad, "grad_rho", ncell)
 
 
 def _stream(stream):
@@ -248,11 +284,11 @@ class _Problem:
         o = dict(n_packages=prob["n_packages"], first_package=prob.get("first_package", 0),
                  seed=prob.get("seed", 4357), precision=prob.get("precision", 0), w_min=prob.get("w_min", 1e-4),
                  max_scatter=prob.get("max_scatter", 1000), flags=prob.get("flags", 7), launch_blocks=0,
-                 event_batch=0, brick_shape=0, peel_queue=0)
+                 event_batch=0, brick_shape=0, peel_queue=0, max_chunk=0)
         o.update(overrides)
         self.opts = Opts(int(o["n_packages"]), int(o["first_package"]), int(o["seed"]), int(o["precision"]),
                          float(o["w_min"]), int(o["max_scatter"]), int(o["flags"]), int(o["launch_blocks"]),
-                         int(o["event_batch"]), int(o["brick_shape"]), int(o["peel_queue"]))
+                         int(o["event_batch"]), int(o["brick_shape"]), int(o["peel_queue"]), int(o["max_chunk"]))
 
 
 def image_shape(prob):
@@ -273,6 +309,7 @@ def run_photons(prob, rho, images, absorbed=None, stats=True, stream=None, **ove
     tensors (images [comps][n_lambda][pixels] FP64, absorbed [n_lambda][ncell]
     FP64).  Returns the statistics dict (stats=True waits for the kernel)."""
     lib = load()
+    _check_life(prob, rho, images=images, absorbed=absorbed, overrides=overrides)
     pr = _Problem(prob, **overrides)
     st = Stats()
     _check(lib.run_photons(C.byref(pr.grid), _ptr(rho), C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det,
@@ -285,6 +322,7 @@ def backward_density(prob, rho, adj_images, grad_rho, stats=True, stream=None, *
     """backward_density: grad_rho (device FP64 [ncell]) = dL/drho for
     dL/dI = adj_images (device FP64, image layout of run_photons)."""
     lib = load()
+    _check_life(prob, rho, adj=adj_images, grad=grad_rho, overrides=overrides)
     pr = _Problem(prob, **overrides)
     st = Stats()
     _check(lib.backward_density(C.byref(pr.grid), _ptr(rho), C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det,
@@ -301,6 +339,11 @@ def backward(prob, rho, adj_images, grad_rho=None, grad_albedo=None, grad_g=None
     ([n_lambda]) and the source luminosities ([n_src][n_lambda]); each
     output is a device FP64 tensor or None (not computed)."""
     lib = load()
+    _check_life(prob, rho, adj=adj_images, absorbed=adj_absorbed, grad=grad_rho, overrides=overrides)
+    nl = len(np.atleast_1d(prob["kappa"]))
+    _need(grad_albedo, "grad_albedo", nl)
+    _need(grad_g, "grad_g", nl)
+    _need(grad_lum, "grad_lum", len(prob["sources"]) * nl)
     pr = _Problem(prob, **overrides)
     st = Stats()
     g = Grads(_ptr(grad_rho), _ptr(grad_albedo), _ptr(grad_g), _ptr(grad_lum))
@@ -318,6 +361,17 @@ def trace_path(grid, rho, kappa, precision, origins, dirs, tau, max_seg=0, seg_c
     lib = load()
     g = grid if isinstance(grid, Grid) else make_grid(grid)
     n = int(origins.shape[0]) if origins is not None else 0
+    _need(rho, "rho", g.nx * g.ny * g.nz, _density_dtype(precision))
+    _need(origins, "origins", 3 * n)
+    _need(dirs, "dirs", 3 * n)
+    _need(tau, "tau", n)
+    if seg_cell is not None:
+        import torch
+        _need(seg_cell, "seg_cell", n * int(max_seg), torch.int32)
+        _need(seg_len, "seg_len", n * int(max_seg))
+    if n_seg is not None:
+        import torch
+        _need(n_seg, "n_seg", n, torch.int32)
     c = C.c_uint64(0)
     _check(lib.trace_path(C.byref(g), _ptr(rho), float(kappa), int(precision), n, _ptr(origins), _ptr(dirs),
                           _ptr(tau), int(max_seg), _ptr(seg_cell), _ptr(seg_len), _ptr(n_seg),
@@ -332,6 +386,11 @@ def peel_off(grid, rho, kappa, g, precision, pos, dir_in, w, detectors, images, 
     gr = grid if isinstance(grid, Grid) else make_grid(grid)
     dets = make_detectors(detectors)
     n = int(pos.shape[0]) if pos is not None else 0
+    _need(rho, "rho", gr.nx * gr.ny * gr.nz, _density_dtype(precision))
+    _need(pos, "pos", 3 * n)
+    _need(dir_in, "dir_in", 3 * n)
+    _need(w, "w", n)
+    _need(images, "images", int(sum(d["nx"] * d["ny"] for d in detectors)))
     _check(lib.peel_off(C.byref(gr), _ptr(rho), float(kappa), float(g), int(precision), n, _ptr(pos),
                         _ptr(dir_in), _ptr(w), len(detectors), dets, _ptr(images), _stream(stream)))
 
@@ -360,6 +419,11 @@ def dust_emission(grid, rho, precision, absorbed, lam, dlam, kappa_abs, emissivi
     lam, dlam, ka = (np.ascontiguousarray(np.atleast_1d(v), dtype=np.float64) for v in (lam, dlam, kappa_abs))
     dp = C.POINTER(C.c_double)
     n_abs = int(absorbed.shape[0]) if absorbed is not None and absorbed.dim() == 2 else 1
+    ncell = g.nx * g.ny * g.nz
+    _need(rho, "rho", ncell, _density_dtype(precision))
+    _need(absorbed, "absorbed", n_abs * ncell)
+    _need(emission, "emission", lam.size * ncell)
+    _need(temperature, "temperature", ncell)
     _check(lib.dust_emission(C.byref(g), _ptr(rho), int(precision), n_abs, _ptr(absorbed), lam.size,
                              lam.ctypes.data_as(dp), dlam.ctypes.data_as(dp), ka.ctypes.data_as(dp),
                              float(emissivity), _ptr(temperature), _ptr(emission), _stream(stream)))

@@ -598,7 +598,8 @@ MCRT_HD void peel_geometry(const DetDev& D, const double r[3], double kd[3], dou
 }
 
 // ---------------------------------------------------------------------------
-// Grid walk (Amanatides & Woo 1987) in precision R.
+// Grid walk (Amanatides & Woo 1987): times in precision T, densities and
+// optical depths in precision R.
 //
 // Times t of the walk are measured from the point where the ray enters the
 // grid (its origin if that lies inside), so their FP32 rounding is relative
@@ -630,15 +631,27 @@ MCRT_HD void peel_geometry(const DetDev& D, const double r[3], double kd[3], dou
 // the faces' planes exactly, and finds the neighbour through the face's rope
 // (tree_cross).
 
-template <typename R>
+//
+// Times have their own type T, separate from the type R of densities and
+// optical depths.  A segment's length is the difference of two crossing
+// times, and in FP32 each time carries an absolute error of a few units of
+// roundoff times t (the distance from the entry), so a short segment late in
+// a long walk carries a relative error of eps t / length.  Where the walk
+// is the package's path (its optical depth sets the forced-scattering point
+// and every later event inherits that point's error), the life-cycle walks
+// keep times in FP64 and round each segment length to R once; the peel-ray
+// and trace walks, whose optical depths end in one exponential, keep T = R.
+template <typename R, typename T = R>
 struct Ray {
-  R t0[3], dt[3];
-  R tp[3];       // rectilinear grids only
+  using Time = T;
+  T t0[3], dt[3];
+  T tp[3];       // rectilinear grids only
   double e[3];   // rectilinear and tree grids
   double k[3], tc;  // tree grids only
   int j[3], i[3], s[3];
-  R t, tau;
-  R tmax;      // the walk stops here (time from the entry; +inf: at the boundary)
+  T t;
+  R tau;
+  T tmax;      // the walk stops here (time from the entry; +inf: at the boundary)
   double tin;  // FP64 entry time (0 for rays starting inside)
   bool active;
 };
@@ -649,12 +662,12 @@ MCRT_HD double fmaR(double a, double b, double c) { return fma(a, b, c); }
 // Crossing time of the next plane ahead along axis a of a rectilinear grid
 // (+inf for an axis parallel to the ray).  The plane index is clamped to the
 // table: after the walk has left the grid the value is never used.
-template <typename R>
-MCRT_HD R rect_tplane(const Ray<R>& ry, const GridDev& G, int a) {
-  if (ry.s[a] == 0) return R(INFINITY);
+template <typename R, typename T>
+MCRT_HD T rect_tplane(const Ray<R, T>& ry, const GridDev& G, int a) {
+  if (ry.s[a] == 0) return T(INFINITY);
   int p = ry.i[a] + (ry.s[a] > 0 ? 1 : 0);
   p = p < 0 ? 0 : (p > G.n[a] ? G.n[a] : p);
-  return (R)((G.qd[a][p] - ry.e[a]) * (double)ry.dt[a]);
+  return (T)((G.qd[a][p] - ry.e[a]) * (double)ry.dt[a]);
 }
 
 // Sets up the walk of o + t k (0 <= t <= tmax): slab entry for origins
@@ -662,8 +675,8 @@ MCRT_HD R rect_tplane(const Ray<R>& ry, const GridDev& G, int a) {
 // the plane table (rectilinear grids), with the lower cell for a coordinate
 // on a wall while moving down; rays missing the grid (or with non-finite
 // data, or ending before the grid) are left inactive with tau = 0.
-template <typename R, int GK = kGridRegular>
-MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const double k[3],
+template <typename R, int GK = kGridRegular, typename T = R>
+MCRT_HD void ray_begin(Ray<R, T>& ry, const GridDev& G, const double o[3], const double k[3],
                        double tmax = INFINITY) {
   double tin = 0.0, tout = INFINITY;
   int entry = -1;
@@ -692,11 +705,11 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const do
   if (miss || !(tin < tout) || !(tin < tmax)) {
     ry.active = false;
     ry.tau = R(0);
-    ry.t = R(0);
+    ry.t = T(0);
     ry.tin = 0.0;
     return;
   }
-  ry.tmax = (R)(tmax - tin);
+  ry.tmax = (T)(tmax - tin);
   if constexpr (GK == kGridTree) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -708,7 +721,7 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const do
     }
     ry.i[0] = tree_find(G, 0, ry.e[0], ry.e[1], ry.e[2], ry.s[0], ry.s[1], ry.s[2]);
     ry.tc = 0.0;
-    ry.t = R(0);
+    ry.t = T(0);
     ry.tin = tin;
     ry.tau = R(0);
     ry.active = ry.i[0] >= 0;
@@ -737,42 +750,42 @@ MCRT_HD void ray_begin(Ray<R>& ry, const GridDev& G, const double o[3], const do
     if constexpr (GK == kGridRect) {
       ry.s[a] = par[a] ? 0 : (k[a] > 0.0 ? 1 : -1);
       ry.e[a] = o[a] + tin * k[a] - G.pa[a][0];
-      ry.t0[a] = R(0);
-      ry.dt[a] = (R)inv[a];
+      ry.t0[a] = T(0);
+      ry.dt[a] = (T)inv[a];
       ry.tp[a] = rect_tplane(ry, G, a);
     } else if (par[a]) {
-      ry.t0[a] = R(INFINITY);
-      ry.dt[a] = R(0);
+      ry.t0[a] = T(INFINITY);
+      ry.dt[a] = T(0);
       ry.s[a] = 0;
     } else if (k[a] > 0.0) {
-      ry.t0[a] = (R)((G.lo[a] + (double)(i + 1) * G.d[a] - o[a]) * inv[a] - tin);
-      ry.dt[a] = (R)(G.d[a] * inv[a]);
+      ry.t0[a] = (T)((G.lo[a] + (double)(i + 1) * G.d[a] - o[a]) * inv[a] - tin);
+      ry.dt[a] = (T)(G.d[a] * inv[a]);
       ry.s[a] = 1;
     } else {
-      ry.t0[a] = (R)((G.lo[a] + (double)i * G.d[a] - o[a]) * inv[a] - tin);
-      ry.dt[a] = (R)(-G.d[a] * inv[a]);
+      ry.t0[a] = (T)((G.lo[a] + (double)i * G.d[a] - o[a]) * inv[a] - tin);
+      ry.dt[a] = (T)(-G.d[a] * inv[a]);
       ry.s[a] = -1;
     }
   }
-  ry.t = R(0);
+  ry.t = T(0);
   ry.tin = tin;
   ry.tau = R(0);
   ry.active = true;
 }
 
 // Bricked address of the ray's current cell.
-template <typename R>
-MCRT_HD int ray_cell(const Ray<R>& ry, const GridDev& G) {
+template <typename R, typename T>
+MCRT_HD int ray_cell(const Ray<R, T>& ry, const GridDev& G) {
   return brick_addr(G, ry.i);
 }
 
 // Crossing time of the next plane ahead along axis a.
-template <typename R, int GK = kGridRegular>
-MCRT_HD R ray_tplane(const Ray<R>& ry, int a) {
+template <typename R, int GK = kGridRegular, typename T = R>
+MCRT_HD T ray_tplane(const Ray<R, T>& ry, int a) {
   if constexpr (GK == kGridRect)
     return ry.tp[a];
   else
-    return fmaR((R)ry.j[a], ry.dt[a], ry.t0[a]);
+    return fmaR((T)ry.j[a], ry.dt[a], ry.t0[a]);
 }
 
 // The next D cells of the walk, as a block: their bricked addresses, the end
@@ -786,10 +799,10 @@ MCRT_HD R ray_tplane(const Ray<R>& ry, int a) {
 // so no load leaves the grid.  `adv` keeps the axes that advanced at each
 // sub-step (3 bits each) so that a caller stopping inside the block can
 // rewind the ray (ray_rewind).
-template <int D, typename R>
+template <int D, typename R, typename T = R>
 struct WalkBlock {
   int cell[D];
-  R tend[D];
+  T tend[D];  // in the ray's time type
   R rho[D];
   int n;         // valid entries (>= 1 for an active ray)
   unsigned adv;  // axes advanced at sub-step d: bits 3d .. 3d+2
@@ -805,8 +818,8 @@ struct WalkBlock {
 // by descending from the face's rope (the deepest node covering the face),
 // across an edge or corner, from the root.  A non-finite or negative exit
 // time also ends the walk.
-template <typename R>
-MCRT_HD void tree_cross(Ray<R>& ry, const GridDev& G, int& cell, double& tend, bool& out) {
+template <typename R, typename T>
+MCRT_HD void tree_cross(Ray<R, T>& ry, const GridDev& G, int& cell, double& tend, bool& out) {
   const double px = ry.e[0], py = ry.e[1], pz = ry.e[2];
   const int sx = ry.s[0], sy = ry.s[1], sz = ry.s[2];
   int c = ry.i[0];
@@ -853,8 +866,8 @@ MCRT_HD void tree_cross(Ray<R>& ry, const GridDev& G, int& cell, double& tend, b
 // LOAD = false skips the density loads (walks whose work does not depend on
 // the densities, such as the adjoint's peel-ray deposits).  The grid kind
 // comes from the accessor (Mem::kGrid).
-template <int D, typename R, class Mem, bool LOAD = true>
-MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, const GridDev& G, Mem& M) {
+template <int D, typename R, class Mem, bool LOAD = true, typename T = R>
+MCRT_HD void ray_next_block(Ray<R, T>& ry, WalkBlock<D, R, T>& b, const GridDev& G, Mem& M) {
   constexpr int GK = Mem::kGrid;
   b.n = 0;
   b.adv = 0;
@@ -870,7 +883,7 @@ MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, const GridDev& G, Me
         tree_cross(ry, G, cell, te, out);
         b.cell[d] = cell < 0 ? 0 : cell;
         b.tend64[d] = te;
-        b.tend[d] = (R)te;
+        b.tend[d] = (T)te;
         b.n += 1;
         b.out = out;
       } else {
@@ -887,8 +900,8 @@ MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, const GridDev& G, Me
   }
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    const R tx = ray_tplane<R, GK>(ry, 0), ty = ray_tplane<R, GK>(ry, 1), tz = ray_tplane<R, GK>(ry, 2);
-    const R tm = fmin(tx, fmin(ty, tz));
+    const T tx = ray_tplane<R, GK>(ry, 0), ty = ray_tplane<R, GK>(ry, 1), tz = ray_tplane<R, GK>(ry, 2);
+    const T tm = fmin(tx, fmin(ty, tz));
     const bool live = !b.out;
     const bool ax = live && tx == tm, ay = live && ty == tm, az = live && tz == tm;
     b.cell[d] = live ? brick_addr(G, ry.i) : b.cell[d > 0 ? d - 1 : 0];
@@ -918,8 +931,8 @@ MCRT_HD void ray_next_block(Ray<R>& ry, WalkBlock<D, R>& b, const GridDev& G, Me
 
 // Undoes the plane crossings of sub-steps d .. D-1 of the last block, so the
 // ray again describes the walk inside cell b.cell[d].
-template <int D, typename R, int GK = kGridRegular>
-MCRT_HD void ray_rewind(Ray<R>& ry, const WalkBlock<D, R>& b, int d, const GridDev& G) {
+template <int D, typename R, int GK = kGridRegular, typename T = R>
+MCRT_HD void ray_rewind(Ray<R, T>& ry, const WalkBlock<D, R, T>& b, int d, const GridDev& G) {
   if constexpr (GK == kGridTree) {  // back to the start of segment d (only its entry time is used)
     double tc = b.tc0;
     int cell = b.cell[0];
@@ -950,8 +963,8 @@ MCRT_HD void ray_rewind(Ray<R>& ry, const WalkBlock<D, R>& b, int d, const GridD
 // FP64 entry time of the current cell, in the original parametrisation of
 // the ray: the latest plane already crossed, or the ray's entry time.  Moving
 // up into cell i the last plane crossed is plane i; moving down, plane i + 1.
-template <typename R, int GK = kGridRegular>
-MCRT_HD double ray_cell_entry64(const Ray<R>& ry, const GridDev& G, const double o[3], const double k[3]) {
+template <typename R, int GK = kGridRegular, typename T = R>
+MCRT_HD double ray_cell_entry64(const Ray<R, T>& ry, const GridDev& G, const double o[3], const double k[3]) {
   if constexpr (GK == kGridTree) return ry.tin + ry.tc;
   double t = ry.tin;
 #pragma unroll

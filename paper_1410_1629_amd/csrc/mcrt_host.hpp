@@ -575,6 +575,7 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
   if (opts->event_batch < 0 || opts->event_batch > 64) return fail(MCRT_EINVAL, "event_batch outside [0, 64]");
   if (opts->peel_queue < -1 || opts->peel_queue > (1ll << 31))
     return fail(MCRT_EINVAL, "peel_queue outside [-1, 2^31]");
+  if (opts->max_chunk < 0) return fail(MCRT_EINVAL, "max_chunk is negative");
 
   RunParams& P = out.P;
   std::memset(&P, 0, sizeof P);

@@ -1324,6 +1324,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     most = std::min<unsigned long long>(
         most, std::max<size_t>(1 << 16, std::min(kQueueBytes, free_b / 4) /
                                             ((size_t)n_det * 8 * kQueueBytesPerRay)));
+  if (opts->max_chunk > 0) most = std::min<unsigned long long>(most, (unsigned long long)opts->max_chunk);
   const unsigned long long n_chunks = (P.n_items + most - 1) / most;
   const unsigned long long chunk = (P.n_items + n_chunks - 1) / n_chunks;
   // the adjoint's event scratch, then (optics gradients) the pass-B sums

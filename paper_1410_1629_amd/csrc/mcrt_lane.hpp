@@ -126,9 +126,10 @@ struct RunParams {
   const double* adj_abs;
 };
 
+// The life-cycle walks keep their times in FP64 whatever R is (see Ray).
 template <typename R>
 struct Lane {
-  Ray<R> ry;
+  Ray<R, double> ry;
   int phase;
   bool done;
   unsigned long long pkg;
@@ -136,7 +137,9 @@ struct Lane {
   bool is_emit, found;
   double r[3], k[3];
   double W, w0, kap, alb, g, T, tau_s, wabs;
-  R kapR, tau_sR, absf, trans, tau_prev, rho_hit, last_t;
+  R kapR, tau_sR, absf, trans, tau_prev, rho_hit;
+  R tau_c;        // compensation of the walk's optical-depth sum (Kahan)
+  double last_t;  // end of the last absorbing segment of a locate walk (ray time)
   unsigned uw1, uw2;
   int hit_cell, last_cell;
   long long lam_cell;  // the package's wavelength row of the absorbed tally: lam * ntal
@@ -170,7 +173,9 @@ MCRT_HD void lane_init(Lane<R>& L) {
   for (int a = 0; a < 3; ++a) L.r[a] = L.k[a] = 0.0;
   L.k[2] = 1.0;
   L.W = L.w0 = L.kap = L.alb = L.g = L.T = L.tau_s = L.wabs = 0.0;
-  L.kapR = L.tau_sR = L.absf = L.tau_prev = L.rho_hit = L.last_t = R(0);
+  L.kapR = L.tau_sR = L.absf = L.tau_prev = L.rho_hit = R(0);
+  L.last_t = 0.0;
+  L.tau_c = R(0);
   L.trans = R(1);
   L.uw1 = L.uw2 = 0;
   L.hit_cell = L.last_cell = 0;
@@ -359,7 +364,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
           ++L.n_dep;
         }
       } else {  // tau_s reached the total by rounding: end of the last absorbing segment
-        s = L.ry.tin + (double)L.last_t;
+        s = L.ry.tin + L.last_t;
         if (ADJ && L.pass == 1) {
           M.add_grad(L.last_cell, (L.Rtot - L.Gacc) / (double)M.rho(L.last_cell));
           ++L.n_dep;
@@ -541,6 +546,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
       double kd[3], inv_d2, tmax = INFINITY;
       if (to_det) peel_geom<Mem>(M.det(L.det), L.r, kd, inv_d2, tmax);
       ray_begin<R, Mem::kGrid>(L.ry, G, L.r, to_det ? kd : L.k, tmax);
+      L.tau_c = R(0);
       if (L.mode == M_LOCATE) {
         L.last_cell = ray_cell(L.ry, G);
         L.last_t = L.ry.t;
@@ -571,15 +577,15 @@ constexpr int kBlockWalk = 4;
 // made a deposit.
 template <typename R, bool ADJ, class Mem>
 MCRT_HD bool lane_step(Lane<R>& L, const RunParams& P, Mem& M) {
-  Ray<R>& ry = L.ry;
+  auto& ry = L.ry;
   bool put = false;
-  WalkBlock<kBlockWalk, R> b;
+  WalkBlock<kBlockWalk, R, double> b;
   ray_next_block(ry, b, P.G, M);
 #pragma unroll
   for (int d = 0; d < kBlockWalk; ++d) {
     if (d >= b.n) break;
-    const R tm = (Mem::kInst && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];  // a peel walk to a camera stops there
-    R seg = tm - ry.t;
+    const double tm = (Mem::kInst && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];  // a peel walk to a camera stops there
+    R seg = (R)(tm - ry.t);  // one rounding of an FP64 difference
     const bool pos = seg > R(0);
     seg = pos ? seg : R(0);
     const R rs = b.rho[d];
@@ -644,7 +650,14 @@ MCRT_HD bool lane_step(Lane<R>& L, const RunParams& P, Mem& M) {
         ++L.n_dep;
       }
     }
-    ry.tau += dtau;
+    if constexpr (sizeof(R) == sizeof(float)) {  // FP32 sum compensated (Kahan): the leg's optical
+      const R y = dtau - L.tau_c;                   // depth sets the forced-scattering point
+      const R t = ry.tau + y;
+      L.tau_c = (t - ry.tau) - y;
+      ry.tau = t;
+    } else {
+      ry.tau += dtau;
+    }
     if (pos) ry.t = tm;
   }
   if (b.out || (Mem::kInst && ry.t >= ry.tmax)) ry.active = false;
@@ -659,16 +672,16 @@ MCRT_HD bool lane_step(Lane<R>& L, const RunParams& P, Mem& M) {
 // goes through M.deposit(cell, v).  Each advances the ray by one block and
 // returns its positive-length crossings.  INST = false (frames only)
 // compiles out the stop at a camera inside the grid.
-template <typename R, class Mem, bool INST = true>
-MCRT_HD unsigned tau_step(Ray<R>& ry, const GridDev& G, R kap, Mem& M) {
-  WalkBlock<kBlockWalk, R> b;
+template <typename R, class Mem, bool INST = true, typename T = R>
+MCRT_HD unsigned tau_step(Ray<R, T>& ry, const GridDev& G, R kap, Mem& M) {
+  WalkBlock<kBlockWalk, R, T> b;
   ray_next_block(ry, b, G, M);
   unsigned n = 0;
 #pragma unroll
   for (int d = 0; d < kBlockWalk; ++d) {
     if (d >= b.n) break;
-    const R tm = (INST && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];
-    R seg = tm - ry.t;
+    const T tm = (INST && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];
+    R seg = (R)(tm - ry.t);
     const bool pos = seg > R(0);
     seg = pos ? seg : R(0);
     const R dtau = kap * b.rho[d] * seg;
@@ -680,16 +693,16 @@ MCRT_HD unsigned tau_step(Ray<R>& ry, const GridDev& G, R kap, Mem& M) {
   return n;
 }
 
-template <typename R, class Mem, bool INST = true>
-MCRT_HD unsigned bp_step(Ray<R>& ry, const GridDev& G, double w, Mem& M) {
-  WalkBlock<kBlockWalk, R> b;
+template <typename R, class Mem, bool INST = true, typename T = R>
+MCRT_HD unsigned bp_step(Ray<R, T>& ry, const GridDev& G, double w, Mem& M) {
+  WalkBlock<kBlockWalk, R, T> b;
   ray_next_block<kBlockWalk, R, Mem, false>(ry, b, G, M);
   unsigned n = 0;
 #pragma unroll
   for (int d = 0; d < kBlockWalk; ++d) {
     if (d >= b.n) break;
-    const R tm = (INST && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];
-    const R seg = tm - ry.t;
+    const T tm = (INST && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];
+    const R seg = (R)(tm - ry.t);
     if (seg > R(0)) {
       M.deposit(b.cell[d], w * (double)seg);
       ++n;

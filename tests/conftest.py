@@ -6,6 +6,9 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+HELPERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "helpers")
+if HELPERS not in sys.path:
+    sys.path.insert(0, HELPERS)  # parity (element-wise checks), emu (the CPU harness)
 
 
 def pytest_configure(config):

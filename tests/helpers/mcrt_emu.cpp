@@ -497,6 +497,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
       ADJ ? std::min<unsigned long long>(P.n_items, std::max<size_t>(1 << 16, (size_t(1) << 30) / per_item))
           : P.n_items;
   if (g_chunk_items > 0) chunk = std::min<unsigned long long>(chunk, (unsigned long long)g_chunk_items);
+  if (opts->max_chunk > 0) chunk = std::min<unsigned long long>(chunk, (unsigned long long)opts->max_chunk);
   std::vector<PeelJob> jobs;
   if (peel && opts->peel_queue != -1) {
     unsigned long long qcap =

@@ -85,7 +85,7 @@ def _call_run(lib, B, prob, **over):
 
 
 @pytest.mark.parametrize("case", ["n_packages", "precision", "flags", "w_min", "max_scatter", "launch_blocks",
-                                  "event_batch", "brick_shape", "peel_queue", "grid_cells", "grid_extent",
+                                  "event_batch", "brick_shape", "peel_queue", "max_chunk", "grid_cells", "grid_extent",
                                   "planes_order", "planes_ends", "planes_nan", "tree_unreached", "tree_twice",
                                   "tree_split_outside", "tree_cell_twice", "tree_and_planes", "tree_leaf_count",
                                   "albedo", "g", "kappa", "lum", "n_det", "det_pixels", "det_distance",
@@ -111,6 +111,8 @@ def test_invalid_arguments_are_rejected(lib, B, W, case):
         over["brick_shape"] = B.brick(9, 0, 0)
     elif case == "peel_queue":
         over["peel_queue"] = -2
+    elif case == "max_chunk":
+        over["max_chunk"] = -1
     elif case == "grid_cells":
         prob["n"] = (0, 4, 4)
     elif case == "grid_extent":
@@ -313,3 +315,45 @@ def test_null_pointers_are_rejected(lib, B, W):
     assert lib.peel_off(C.byref(g), fake, 1.0, 1.0, 0, 10, fake, None, fake, 1, dets, fake, None) == B.EINVAL
     assert lib.peel_off(C.byref(g), fake, 1.0, 0.5, 0, 10, fake, None, fake, 0, dets, fake, None) == B.EINVAL
     assert lib.mcrt_last_error().decode()
+
+
+@pytest.mark.parametrize("case", ["rho_dtype64", "rho_dtype32", "rho_size", "images_size", "images_dtype",
+                                  "absorbed_size", "adj_size", "grad_size", "grad_albedo_size", "trace_tau",
+                                  "peel_images"])
+def test_binding_rejects_mismatched_tensors(lib, B, W, case):
+    # the binding checks every tensor's element type and count against the
+    # problem before any pointer reaches the library (host-only: the check
+    # fails before the device test, so CPU tensors show it)
+    import torch
+    prob = W.small_problem(n=(4, 3, 2), n_packages=10, detectors=[W.frame(10.0, 0.0, 5, 4, 1.0, 1.0)])
+    f64 = torch.float64
+    rho = torch.ones(24, dtype=f64)
+    images = torch.zeros(B.image_shape(prob), dtype=f64)
+    absorbed = torch.zeros((1, 24), dtype=f64)
+    with pytest.raises(ValueError) as ei:
+        if case == "rho_dtype64":  # FP64 path with float densities
+            B.run_photons(prob, rho.float(), images, absorbed)
+        elif case == "rho_dtype32":  # FP32 path with double densities
+            B.run_photons(dict(prob, precision=1), rho, images, absorbed)
+        elif case == "rho_size":
+            B.run_photons(prob, torch.ones(23, dtype=f64), images, absorbed)
+        elif case == "images_size":
+            B.run_photons(prob, rho, torch.zeros(19, dtype=f64), absorbed)
+        elif case == "images_dtype":
+            B.run_photons(prob, rho, images.float(), absorbed)
+        elif case == "absorbed_size":
+            B.run_photons(prob, rho, images, torch.zeros(23, dtype=f64))
+        elif case == "adj_size":
+            B.backward_density(prob, rho, torch.zeros(21, dtype=f64), torch.zeros(24, dtype=f64))
+        elif case == "grad_size":
+            B.backward_density(prob, rho, images, torch.zeros(12, dtype=f64))
+        elif case == "grad_albedo_size":
+            B.backward(prob, rho, images, grad_albedo=torch.zeros(2, dtype=f64))
+        elif case == "trace_tau":
+            o = torch.zeros((5, 3), dtype=f64)
+            B.trace_path(prob, rho, 1.0, 0, o, o, torch.zeros(4, dtype=f64))
+        elif case == "peel_images":
+            pos = torch.zeros((5, 3), dtype=f64)
+            B.peel_off(prob, rho, 1.0, 0.5, 0, pos, None, torch.zeros(5, dtype=f64), prob["detectors"],
+                       torch.zeros(21, dtype=f64))
+    assert "device tensor" not in str(ei.value), ei.value

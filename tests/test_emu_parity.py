@@ -21,6 +21,16 @@ def rel_l1(a, b):
     return float(np.abs(a - b).sum() / den) if den > 0 else float(np.abs(a).sum())
 
 
+def _same_counts(st, ref, keys, prec):
+    """The life kernel's counts are identical in every queue mode; the
+    peel-ray crossings too in FP64, and in FP32 up to the near-ties that the
+    FP32 times of the queued walks merge or split."""
+    for key in keys:
+        assert st[key] == ref[key], key
+    slack = 0 if prec == 0 else 1e-5 * ref["x_peel"] + 2
+    assert abs(st["x_peel"] - ref["x_peel"]) <= slack, (st["x_peel"], ref["x_peel"])
+
+
 TRACE_CASES = [
     ("uniform32", (-1, 1, -1, 1, -1, 1), (32, 32, 32), None, 1.0),
     ("lognormal_ragged", (-2.0, 1.0, 0.0, 3.0, -1.0, 0.5), (9, 6, 5), 9, 0.7),
@@ -265,9 +275,11 @@ def test_backward_peel_queue_modes(E, orc, W, prec):
         if ref is None:
             ref = (g, st)
             continue
-        assert rel_l1(g, ref[0]) < 1e-12
-        for key in ("x_path", "x_locate", "x_peel", "deposits", "events", "peels"):
-            assert st[key] == ref[1][key], (q, key)
+        # FP32 path: inline peel walks keep their times in FP64 (the life
+        # kernel's walk), queued ones in FP32, so the modes agree to FP32
+        # rounding and a near-tie can merge or split a crossing
+        assert rel_l1(g, ref[0]) < (1e-12 if prec == 0 else 1e-6)
+        _same_counts(st, ref[1], ("x_path", "x_locate", "deposits", "events", "peels"), prec)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -300,9 +312,8 @@ def test_forward_peel_queue_modes(E, orc, W, prec):
         if ref is None:
             ref = (images, st)
             continue
-        assert rel_l1(images, ref[0]) < 1e-12
-        for key in ("x_path", "x_locate", "x_peel", "deposits", "events", "peels", "packages"):
-            assert st[key] == ref[1][key], (q, chunk, key)
+        assert rel_l1(images, ref[0]) < (1e-12 if prec == 0 else 1e-6)
+        _same_counts(st, ref[1], ("x_path", "x_locate", "deposits", "events", "peels", "packages"), prec)
 
 
 def test_backward_events_beyond_the_job_event_field(E, orc, W):
@@ -370,3 +381,43 @@ def test_backward_in_chunks(E, orc, W, queue):
     for key in ("x_path", "x_locate", "x_peel", "deposits", "events", "packages", "peels"):
         assert st[key] == st_full[key], key
     assert st_full["life_launches"] == 2 and st["life_launches"] == 2 * -(-700 // 97)
+
+
+@pytest.mark.parametrize("queue", [-1, 0])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_max_chunk_forward_and_adjoint(E, orc, W, prec, queue):
+    """mcrt_opts.max_chunk: 2 wavelengths x 401 packages in chunks of at most
+    150 items (some straddle the wavelengths) give the oracle's images,
+    tallies and gradients (density, optics, luminosities, absorbed-tally
+    term) and the single chunk's results and counts."""
+    n = (8, 7, 6)
+    prob = W.small_problem(n=n, rho=W.lognormal_density(n, 0.8, seed=61, f32=(prec == 1)), kappa=[0.9, 1.4],
+                           albedo=[0.7, 0.55], g=[0.4, -0.2],
+                           sources=[W.point((0.11, -0.07, 0.05), [1.0, 0.5]), W.expdisk(0.4, 0.15, [2.0, 1.0])],
+                           detectors=[W.frame(10.0, 0.0, 12, 12, 1.2, 1.2), W.frame(10.0, 75.0, 10, 14, 1.3, 1.1,
+                                                                                   azim=20.0)],
+                           n_packages=401, precision=prec,
+                           flags=W.FLAG_PEEL_EMIT | W.FLAG_PEEL_SCAT | W.FLAG_ABSORB | W.FLAG_SPLIT)
+    img_o, abs_o, _ = orc.run(prob)
+    tol = 1e-10 if prec == 0 else 1e-5
+    im, ab, st = E.run(prob, peel_queue=queue, max_chunk=150)
+    assert st["life_launches"] == 6
+    assert rel_l1(im, img_o) < tol and rel_l1(ab, abs_o) < tol
+    im1, ab1, st1 = E.run(prob, peel_queue=queue)
+    assert rel_l1(im, im1) < 1e-12 and rel_l1(ab, ab1) < 1e-12
+    for key in ("x_path", "x_locate", "x_peel", "deposits", "events", "peels", "packages"):
+        assert st[key] == st1[key], key
+    rng = np.random.default_rng(21)
+    adj = rng.standard_normal(img_o.shape)
+    adj_abs = rng.standard_normal(abs_o.shape) * 10.0
+    g_o, _, _, go = orc.grad(prob, adj, optics=True, adj_absorbed=adj_abs)
+    g, st, gopt = E.grad(prob, adj, optics=True, adj_absorbed=adj_abs, peel_queue=queue, max_chunk=150)
+    assert st["life_launches"] == 12
+    tol_g = 1e-9 if prec == 0 else 1e-5
+    assert rel_l1(g, g_o) < tol_g
+    for k in ("albedo", "g", "lum"):
+        assert rel_l1(gopt[k], go[k]) < tol_g, k
+    g1, _, gopt1 = E.grad(prob, adj, optics=True, adj_absorbed=adj_abs, peel_queue=queue)
+    assert rel_l1(g, g1) < 1e-12
+    for k in ("albedo", "g", "lum"):
+        assert rel_l1(gopt[k], gopt1[k]) < 1e-12, k

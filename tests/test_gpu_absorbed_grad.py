@@ -7,16 +7,13 @@ import time
 
 import numpy as np
 import pytest
+from parity import check, rel_l1
 
 from test_emu_absorbed_grad import _setup
 
 pytestmark = pytest.mark.gpu
 
 
-def rel_l1(a, b):
-    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
-    den = np.abs(b).sum()
-    return float(np.abs(a - b).sum() / den) if den > 0 else float(np.abs(a).sum())
 
 
 @pytest.fixture(scope="module")
@@ -48,9 +45,7 @@ def test_absorbed_gradient_matches_oracle(B, orc, W, grid, prec):
     for q in (-1, 0):
         g = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
         B.backward(p, rho, _dev(a), g, adj_absorbed=_dev(b), peel_queue=q)
-        e = rel_l1(g.cpu().numpy(), g_o)
-        _say("  queue %d: rel_L1 grad %.3e" % (q, e))
-        assert e < (1e-9 if prec == 0 else 1e-5)
+        check(g.cpu().numpy(), g_o, 1e-9 if prec == 0 else 1e-5, "queue %d: grad" % q, _say)
 
 
 def test_multiwavelength_absorbed_gradient(B, orc, W):
@@ -66,9 +61,7 @@ def test_multiwavelength_absorbed_gradient(B, orc, W):
     rho = B.density_tensor(p)
     g = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
     B.backward(p, rho, _dev(a), g, adj_absorbed=_dev(b))
-    e = rel_l1(g.cpu().numpy(), g_o)
-    _say("  subset: rel_L1 grad %.3e" % e)
-    assert e < 1e-5
+    check(g.cpu().numpy(), g_o, 1e-5, "subset: grad", _say)
     full = W.multiwavelength(n_packages=1_000_000)
     rho = B.density_tensor(full)
     images = torch.empty(B.image_shape(full), dtype=torch.float64, device="cuda")

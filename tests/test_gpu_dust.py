@@ -9,16 +9,13 @@ import time
 
 import numpy as np
 import pytest
+from parity import check, rel_l1
 
 from test_emu_dust import _cells_problem, absorbed_field, grids, spectrum
 
 pytestmark = pytest.mark.gpu
 
 
-def rel_l1(a, b):
-    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
-    den = np.abs(b).sum()
-    return float(np.abs(a - b).sum() / den) if den > 0 else float(np.abs(a).sum())
 
 
 @pytest.fixture(scope="module")
@@ -124,9 +121,8 @@ def test_cell_source_run_matches_oracle(B, orc, W, grid, prec):
     tol = 1e-10 if prec == 0 else 1e-5
     for q in (-1, 0):
         images, absorbed, st = B.render(p, peel_queue=q)
-        e_i, e_a = rel_l1(images.cpu().numpy(), img_o), rel_l1(absorbed.cpu().numpy(), abs_o)
-        _say("  queue %d: rel_L1 images %.3e absorbed %.3e" % (q, e_i, e_a))
-        assert e_i < tol and e_a < tol
+        check(images.cpu().numpy(), img_o, tol, "queue %d: images" % q, _say)
+        check(absorbed.cpu().numpy(), abs_o, tol, "queue %d: absorbed" % q, _say)
         assert st["packages"] == st_o["packages"]
         assert abs(st["emitted"] - st_o["emitted"]) <= 1e-12 * st_o["emitted"]
         for key in ("events", "x_path", "x_locate", "x_peel"):
@@ -144,9 +140,7 @@ def test_cell_source_adjoint_matches_oracle(B, orc, W, prec):
     rho = B.density_tensor(p)
     grad = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
     B.backward_density(p, rho, _dev(adj), grad)
-    e = rel_l1(grad.cpu().numpy(), g_o)
-    _say("  rel_L1 grad %.3e" % e)
-    assert e < (1e-9 if prec == 0 else 1e-5)
+    check(grad.cpu().numpy(), g_o, 1e-9 if prec == 0 else 1e-5, "grad", _say)
 
 
 def test_cell_cdf_at_scale(B, orc, W):
@@ -170,7 +164,7 @@ def test_cell_cdf_at_scale(B, orc, W):
                         first_package=3_141_592)
     img_o, _, st_o = orc.run(p, threads=8)
     images, _, st = B.render(p)
-    assert rel_l1(images.cpu().numpy(), img_o) < 1e-12
+    check(images.cpu().numpy(), img_o, 1e-12, "images", _say)
     p2 = dict(p, n_packages=4_000_000, first_package=0)
     images, _, st = B.render(p2)
     assert st["packages"] == 8_000_000

@@ -10,16 +10,13 @@ import time
 
 import numpy as np
 import pytest
+from parity import check, rel_l1
 
 from test_emu_instruments import BOX, instruments, problem
 
 pytestmark = pytest.mark.gpu
 
 
-def rel_l1(a, b):
-    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
-    den = np.abs(b).sum()
-    return float(np.abs(a - b).sum() / den) if den > 0 else float(np.abs(a).sum())
 
 
 @pytest.fixture(scope="module")
@@ -49,9 +46,8 @@ def test_run_matches_oracle(B, orc, W, grid, prec):
     tol = 1e-10 if prec == 0 else 1e-5
     for q in (-1, 0, 500):
         images, absorbed, st = B.render(p, peel_queue=q)
-        e_i, e_a = rel_l1(images.cpu().numpy(), img_o), rel_l1(absorbed.cpu().numpy(), abs_o)
-        _say("  queue %d: rel_L1 images %.3e absorbed %.3e" % (q, e_i, e_a))
-        assert e_i < tol and e_a < tol
+        check(images.cpu().numpy(), img_o, tol, "queue %d: images" % q, _say)
+        check(absorbed.cpu().numpy(), abs_o, tol, "queue %d: absorbed" % q, _say)
         for key in ("events", "x_path", "x_locate", "x_peel"):
             assert abs(st[key] - st_o[key]) <= 1e-4 * st_o[key] + 2, (key, st[key], st_o[key])
 
@@ -69,9 +65,7 @@ def test_adjoint_matches_oracle(B, orc, W, grid, prec):
     for q in (-1, 0):
         grad = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
         B.backward_density(p, rho, _dev(adj), grad, peel_queue=q)
-        e = rel_l1(grad.cpu().numpy(), g_o)
-        _say("  queue %d: rel_L1 grad %.3e" % (q, e))
-        assert e < (1e-9 if prec == 0 else 1e-5)
+        check(grad.cpu().numpy(), g_o, 1e-9 if prec == 0 else 1e-5, "queue %d: grad" % q, _say)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -85,7 +79,7 @@ def test_standalone_peel_matches_oracle(B, orc, W, prec):
     img = torch.zeros(ref.size, dtype=torch.float64, device="cuda")
     B.peel_off({"box": BOX, "n": n}, _dev(rho.reshape(-1), torch.float32 if prec else torch.float64), 1.1, 0.6, prec,
                _dev(pos), _dev(din), _dev(w), instruments(W), img)
-    assert rel_l1(img.cpu().numpy(), ref) < (1e-12 if prec == 0 else 1e-6)
+    check(img.cpu().numpy(), ref, 1e-12 if prec == 0 else 1e-6, "images", _say)
 
 
 def _spiral_with_instruments(W, n_packages, precision=1):
@@ -102,9 +96,8 @@ def test_spiral_subset_with_camera_inside_matches_oracle(B, orc, W, prec):
     p["first_package"] = 5_000_003
     img_o, abs_o, _ = orc.run(p, threads=8)
     images, absorbed, _ = B.render(p)
-    e_i, e_a = rel_l1(images.cpu().numpy(), img_o), rel_l1(absorbed.cpu().numpy(), abs_o)
-    _say("  rel_L1 images %.3e absorbed %.3e" % (e_i, e_a))
-    assert e_i < (1e-10 if prec == 0 else 1e-5) and e_a < (1e-10 if prec == 0 else 2e-5)
+    check(images.cpu().numpy(), img_o, 1e-10 if prec == 0 else 1e-5, "images", _say)
+    check(absorbed.cpu().numpy(), abs_o, 1e-10 if prec == 0 else 1e-5, "absorbed", _say)
 
 
 def test_spiral_full_size_with_camera_inside(B, W):

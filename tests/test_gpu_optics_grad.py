@@ -8,16 +8,13 @@ import time
 
 import numpy as np
 import pytest
+from parity import check, rel_l1
 
 from test_emu_optics_grad import problems
 
 pytestmark = pytest.mark.gpu
 
 
-def rel_l1(a, b):
-    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
-    den = np.abs(b).sum()
-    return float(np.abs(a - b).sum() / den) if den > 0 else float(np.abs(a).sum())
 
 
 @pytest.fixture(scope="module")
@@ -59,10 +56,9 @@ def test_optics_gradients_match_oracle(B, orc, W, name, prec):
     for q in (-1, 0):
         gr, ga, gg, gl = _outputs(B, p, rho.numel())
         B.backward(p, rho, _dev(adj), gr, ga, gg, gl, peel_queue=q)
-        errs = [rel_l1(gr.cpu().numpy(), g_o)] + [rel_l1(t.cpu().numpy(), go[k]) for t, k in
-                                                  ((ga, "albedo"), (gg, "g"), (gl, "lum"))]
-        _say("  queue %d: rel_L1 rho %.2e albedo %.2e g %.2e lum %.2e" % ((q,) + tuple(errs)))
-        assert max(errs) < tol
+        check(gr.cpu().numpy(), g_o, tol, "queue %d: rho" % q, _say)
+        for t, k in ((ga, "albedo"), (gg, "g"), (gl, "lum")):
+            check(t.cpu().numpy(), go[k], tol, "queue %d: %s" % (q, k), _say)
 
 
 def test_adjoint_workload_with_optics_gradients(B, W):
@@ -112,13 +108,13 @@ def test_autograd_optics_matches_oracle(B, orc, W):
     loss.backward()
     adj = 2 * (img_o - img_o * 0.7)
     g_o, _, _, go = orc.grad(p, adj, threads=8, optics=True)
-    assert rel_l1(images.detach().cpu().numpy(), img_o) < 1e-10
-    assert rel_l1(rho.grad.cpu().numpy(), g_o) < 1e-9
-    assert rel_l1(albedo.grad.numpy(), go["albedo"]) < 1e-9
-    assert rel_l1(g.grad.numpy(), go["g"]) < 1e-9
-    assert rel_l1(lum.grad.numpy(), go["lum"]) < 1e-9
+    check(images.detach().cpu().numpy(), img_o, 1e-10, "images", _say)
+    check(rho.grad.cpu().numpy(), g_o, 1e-9, "rho", _say)
+    check(albedo.grad.numpy(), go["albedo"], 1e-9, "albedo", _say)
+    check(g.grad.numpy(), go["g"], 1e-9, "g", _say)
+    check(lum.grad.numpy(), go["lum"], 1e-9, "lum", _say)
     # only some inputs requiring gradients
     albedo2 = albedo.detach().requires_grad_(True)
     img2 = autograd.render_optics(p, rho.detach(), albedo2, g.detach(), lum.detach())
     ((img2 - target) ** 2).sum().backward()
-    assert rel_l1(albedo2.grad.numpy(), go["albedo"]) < 1e-9
+    check(albedo2.grad.numpy(), go["albedo"], 1e-9, "albedo", _say)

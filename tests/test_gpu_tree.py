@@ -9,16 +9,13 @@ import time
 
 import numpy as np
 import pytest
+from parity import check, rel_l1
 
 from test_oracle_tree import BOX, _blob, kd_tree, octree
 
 pytestmark = pytest.mark.gpu
 
 
-def rel_l1(a, b):
-    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
-    den = np.abs(b).sum()
-    return float(np.abs(a - b).sum() / den) if den > 0 else float(np.abs(a).sum())
 
 
 @pytest.fixture(scope="module")
@@ -93,7 +90,7 @@ def test_peel_matches_oracle(B, orc, W, prec):
     img = torch.zeros(ref.size, dtype=torch.float64, device="cuda")
     B.peel_off({"box": BOX, "n": n, "tree": T.tree()}, _dev(rho, torch.float32 if prec else torch.float64), 1.1, 0.6,
                prec, _dev(pos), _dev(din), _dev(w), dets, img)
-    assert rel_l1(img.cpu().numpy(), ref) < (1e-12 if prec == 0 else 1e-6)
+    check(img.cpu().numpy(), ref, 1e-12 if prec == 0 else 1e-6, "images", _say)
 
 
 def _tree_problem(W, kind, prec, flags=None, n_packages=3000):
@@ -112,9 +109,8 @@ def test_run_matches_oracle(B, orc, W, kind, prec):
     tol = 1e-10 if prec == 0 else 1e-5
     for q in (-1, 0):
         images, absorbed, st = B.render(p, peel_queue=q)
-        e_i, e_a = rel_l1(images.cpu().numpy(), img_o), rel_l1(absorbed.cpu().numpy(), abs_o)
-        _say("  queue %d: rel_L1 images %.3e absorbed %.3e" % (q, e_i, e_a))
-        assert e_i < tol and e_a < tol
+        check(images.cpu().numpy(), img_o, tol, "queue %d: images" % q, _say)
+        check(absorbed.cpu().numpy(), abs_o, tol, "queue %d: absorbed" % q, _say)
         assert st["packages"] == st_o["packages"]
         for key in ("events", "x_path", "x_locate", "x_peel"):
             assert abs(st[key] - st_o[key]) <= 1e-4 * st_o[key] + 2, (key, st[key], st_o[key])
@@ -133,9 +129,7 @@ def test_backward_matches_oracle(B, orc, W, kind, prec):
     for q in (-1, 0):
         grad = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
         B.backward_density(p, rho, _dev(adj), grad, peel_queue=q)
-        e = rel_l1(grad.cpu().numpy(), g_o)
-        _say("  queue %d: rel_L1 grad %.3e" % (q, e))
-        assert e < (1e-9 if prec == 0 else 1e-5)
+        check(grad.cpu().numpy(), g_o, 1e-9 if prec == 0 else 1e-5, "queue %d: grad" % q, _say)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -150,15 +144,14 @@ def test_kdtree_spiral_subset_matches_oracle(B, orc, W, prec):
     img_o, abs_o, _ = orc.run(p)
     images, absorbed, st = B.render(p)
     tol = 1e-10 if prec == 0 else 1e-5
-    e_i, e_a = rel_l1(images.cpu().numpy(), img_o), rel_l1(absorbed.cpu().numpy(), abs_o)
+    check(images.cpu().numpy(), img_o, tol, "images", _say)
+    check(absorbed.cpu().numpy(), abs_o, tol, "absorbed", _say)
     adj = np.random.default_rng(13).standard_normal(img_o.shape) * 1e9
     g_o, _, _ = orc.grad(p, adj)
     rho = B.density_tensor(p)
     grad = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
     B.backward_density(p, rho, _dev(adj), grad)
-    e_g = rel_l1(grad.cpu().numpy(), g_o)
-    _say("  %s: rel_L1 images %.3e absorbed %.3e gradient %.3e" % (p["name"], e_i, e_a, e_g))
-    assert e_i < tol and e_a < (1e-10 if prec == 0 else 2e-5) and e_g < (1e-9 if prec == 0 else 1e-5)
+    check(grad.cpu().numpy(), g_o, 1e-9 if prec == 0 else 1e-5, "gradient", _say)
 
 
 def test_kdtree_spiral_full_size(B, W):
@@ -188,3 +181,31 @@ def test_kdtree_spiral_full_size(B, W):
     _say("  forward %.1f ms, adjoint %.1f ms, %.3g packages/s per step, %.3g forward crossings/s (%.2f s wall)" % (
         sf["kernel_ms"], sb["kernel_ms"], 1e7 / ((sf["kernel_ms"] + sb["kernel_ms"]) / 1e3),
         x / (sf["kernel_ms"] / 1e3), wall))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_kdtree_spiral_bench_tree_subset_matches_oracle(B, orc, W, prec):
+    # the benchmark's own k-d tree (967 656 leaves, max_mass 3e-4) with its
+    # three 512x512 frames: a few packages from deep inside the run, forward
+    # and adjoint (the oracle's brute-force leaf search scans every leaf per
+    # crossing, about 1 ms each)
+    import os
+    import torch
+    _say("k-d tree spiral, the benchmark's tree, 16 packages, prec=%d" % prec)
+    p = W.kdtree_spiral(n_packages=16, precision=prec)
+    assert p["n"][0] > 900_000
+    p["first_package"] = 7_777_777
+    threads = len(os.sched_getaffinity(0))
+    img_o, abs_o, st_o = orc.run(p, threads=threads)
+    images, absorbed, st = B.render(p)
+    tol = 1e-10 if prec == 0 else 1e-5
+    check(images.cpu().numpy(), img_o, tol, "images", _say)
+    check(absorbed.cpu().numpy(), abs_o, tol, "absorbed", _say)
+    for key in ("events", "x_path", "x_locate", "x_peel"):
+        assert abs(st[key] - st_o[key]) <= 1e-4 * st_o[key] + 2, (key, st[key], st_o[key])
+    adj = np.random.default_rng(14).standard_normal(img_o.shape) * 1e9
+    g_o, _, _ = orc.grad(p, adj, threads=threads)
+    rho = B.density_tensor(p)
+    grad = torch.empty(rho.numel(), dtype=torch.float64, device="cuda")
+    B.backward_density(p, rho, _dev(adj), grad)
+    check(grad.cpu().numpy(), g_o, 1e-9 if prec == 0 else 1e-5, "gradient", _say)
