@@ -285,6 +285,29 @@ int trace_path(const mcrt_grid *grid, const void *rho_dev, double kappa, int pre
                int32_t *seg_cell_dev, double *seg_len_dev, int32_t *n_seg_dev, uint64_t *crossings_host,
                void *hip_stream);
 
+/* trace_path for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, results and errors as trace_path; the call allocates no
+ * device memory (no hipMalloc, hipMallocAsync or hipFree): its counters,
+ * the plane or tree tables of a rectilinear or tree grid and the bricked
+ * copy of the densities live in a library-owned device array of
+ * MCRT_NOALLOC_SCRATCH_BYTES bytes, one per device, which each device that
+ * the library runs on holds until the process ends.  A grid whose tables and
+ * densities need more (about 4 or 8 bytes per cell, FP32 or FP64, plus 256
+ * bytes and the tables) is rejected with MCRT_EINVAL before any device
+ * work.  Every call on one device uses that device's array and leaves its
+ * contents behind: calls that overlap on one device (several streams or
+ * host threads) race, and the caller must serialise them.  The counters are
+ * cleared by a fill kernel on hip_stream; the tables of a rectilinear or
+ * tree grid are copied from host memory the call owns only until it
+ * returns, so a capture into a HIP graph should use a regular grid. */
+#define MCRT_NOALLOC_SCRATCH_BYTES (96u << 20)
+
+int trace_path_noalloc(const mcrt_grid *grid, const void *rho_dev, double kappa, int precision, int64_t n_rays,
+                       const double *origin_dev, const double *dir_dev, double *tau_dev, int32_t max_seg,
+                       int32_t *seg_cell_dev, double *seg_len_dev, int32_t *n_seg_dev, uint64_t *crossings_host,
+                       void *hip_stream);
+
 /* Peel-off (Sect. 1, Yusef-Zadeh et al. 1984) of a list of events into
  * frames of one wavelength: for every event e and frame d whose pixel
  * contains the projection of pos_e, images[d][pixel] +=
@@ -381,7 +404,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 14
+#define MCRT_ABI_VERSION 15
 
 #ifdef __cplusplus
 }

@@ -87,9 +87,10 @@ class Stats(C.Structure):
 _lib = None
 
 # Exported symbols of include/mcrt.h.
-ABI_VERSION = 14  # MCRT_ABI_VERSION of the header these structs follow
-SYMBOLS = ("run_photons", "trace_path", "peel_off", "backward_density", "backward", "dust_emission",
-           "mcrt_last_error", "mcrt_abi_version")
+ABI_VERSION = 15  # MCRT_ABI_VERSION of the header these structs follow
+SYMBOLS = ("run_photons", "trace_path", "trace_path_noalloc", "peel_off", "backward_density", "backward",
+           "dust_emission", "mcrt_last_error", "mcrt_abi_version")
+NOALLOC_SCRATCH_BYTES = 96 << 20  # MCRT_NOALLOC_SCRATCH_BYTES
 
 
 def load():
@@ -111,6 +112,8 @@ def load():
     lib.trace_path.argtypes = [C.POINTER(Grid), P, d, C.c_int, i64, P, P, P, i32, P, P, P,
                                C.POINTER(C.c_uint64), P]
     lib.trace_path.restype = C.c_int
+    lib.trace_path_noalloc.argtypes = lib.trace_path.argtypes
+    lib.trace_path_noalloc.restype = C.c_int
     lib.peel_off.argtypes = [C.POINTER(Grid), P, d, d, C.c_int, i64, P, P, P, C.c_int, C.POINTER(Detector), P, P]
     lib.peel_off.restype = C.c_int
     lib.backward.argtypes = [C.POINTER(Grid), P, C.POINTER(Optics), C.c_int, C.POINTER(Source), C.c_int,
@@ -354,11 +357,14 @@ def backward(prob, rho, adj_images, grad_rho=None, grad_albedo=None, grad_g=None
 
 
 def trace_path(grid, rho, kappa, precision, origins, dirs, tau, max_seg=0, seg_cell=None, seg_len=None,
-               n_seg=None, crossings=True, stream=None):
+               n_seg=None, crossings=True, stream=None, noalloc=False):
     """trace_path for device tensors origins/dirs [n][3] FP64 and tau [n]
     FP64; optional segment lists.  Returns the total crossing count (or
-    None).  `grid` is a problem dict or a Grid."""
+    None).  `grid` is a problem dict or a Grid.  noalloc=True calls
+    trace_path_noalloc instead (the library's per-device scratch array, no
+    device allocation; grids up to NOALLOC_SCRATCH_BYTES)."""
     lib = load()
+    entry = lib.trace_path_noalloc if noalloc else lib.trace_path
     g = grid if isinstance(grid, Grid) else make_grid(grid)
     n = int(origins.shape[0]) if origins is not None else 0
     _need(rho, "rho", g.nx * g.ny * g.nz, _density_dtype(precision))
@@ -373,10 +379,18 @@ def trace_path(grid, rho, kappa, precision, origins, dirs, tau, max_seg=0, seg_c
         import torch
         _need(n_seg, "n_seg", n, torch.int32)
     c = C.c_uint64(0)
-    _check(lib.trace_path(C.byref(g), _ptr(rho), float(kappa), int(precision), n, _ptr(origins), _ptr(dirs),
+    _check(entry(C.byref(g), _ptr(rho), float(kappa), int(precision), n, _ptr(origins), _ptr(dirs),
                           _ptr(tau), int(max_seg), _ptr(seg_cell), _ptr(seg_len), _ptr(n_seg),
                           C.byref(c) if crossings else None, _stream(stream)))
     return c.value if crossings else None
+
+
+def trace_path_noalloc(grid, rho, kappa, precision, origins, dirs, tau, max_seg=0, seg_cell=None, seg_len=None,
+                       n_seg=None, crossings=True, stream=None):
+    """trace_path_noalloc: trace_path without device allocation (the same
+    arguments and results)."""
+    return trace_path(grid, rho, kappa, precision, origins, dirs, tau, max_seg, seg_cell, seg_len, n_seg, crossings,
+                      stream, noalloc=True)
 
 
 def peel_off(grid, rho, kappa, g, precision, pos, dir_in, w, detectors, images, stream=None):

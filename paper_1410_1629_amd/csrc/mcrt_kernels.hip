@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -966,6 +968,10 @@ __global__ void __launch_bounds__(kBlock) k_dust_emission(DustParams P) {
 // ===========================================================================
 // Host side: launches.
 
+// Device block of trace_path_noalloc (see trace_impl): one per device, held
+// until the process ends.
+static __device__ __align__(256) unsigned char scratch[MCRT_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 using namespace mcrt;
@@ -1531,6 +1537,109 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// trace_path and its variant that allocates nothing.
+//
+// The variant's device block (counters, plane or tree tables, bricked
+// densities) is `scratch` (above), a file-scope device array: every device
+// holds its own copy at its own address, taken once per device with
+// hipGetSymbolAddress (in host code the array's name is not a device
+// address).  Calls on one device share it and must not overlap.
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (set up on its first use).
+int scratch_address(unsigned char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MCRT_EINVAL, "device %d beyond the %d the library tracks", dev,
+                                                 kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(MCRT_EHIP, "hipGetSymbolAddress gave no address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
+// trace_path's work.  fixed = false: the device block is allocated on the
+// stream and freed there when the work ends; fixed = true: it is the
+// scratch array (sizes beyond it are rejected before any device work), and
+// the counters are cleared by a fill kernel rather than by the copy of the
+// tables, which only rectilinear and tree grids need.
+int trace_impl(const mcrt_grid* grid, const void* rho_dev, double kappa, int precision, int64_t n_rays,
+               const double* origin_dev, const double* dir_dev, double* tau_dev, int32_t max_seg,
+               int32_t* seg_cell_dev, double* seg_len_dev, int32_t* n_seg_dev, uint64_t* crossings_host,
+               void* hip_stream, bool fixed) {
+  if (int e = host::check_trace(grid, rho_dev, kappa, precision, n_rays, origin_dev, dir_dev, tau_dev, max_seg,
+                                seg_cell_dev, seg_len_dev))
+    return e;
+  const bool lists = seg_cell_dev != nullptr;
+  TraceParams P;
+  std::memset(&P, 0, sizeof P);
+  if (int e = host::make_grid(*grid, host::elem_bytes(precision), 0, P.G)) return e;
+  const bool f32 = precision == MCRT_PREC_FP32;
+  const size_t tables = host::plane_bytes(P.G, *grid);
+  const size_t off_rho = 256 + tables;  // counters, plane tables, densities
+  const size_t bytes = off_rho + (size_t)P.G.ncell_pad * (f32 ? 4 : 8);
+  if (fixed && bytes > (size_t)MCRT_NOALLOC_SCRATCH_BYTES)
+    return fail(MCRT_EINVAL, "trace_path_noalloc: the grid needs %zu bytes of device scratch, the limit is %zu", bytes,
+                (size_t)MCRT_NOALLOC_SCRATCH_BYTES);
+  if (n_rays == 0) {
+    if (crossings_host) *crossings_host = 0;
+    return 0;
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  P.kappa = kappa;
+  P.n_rays = n_rays;
+  P.origin = origin_dev;
+  P.dir = dir_dev;
+  P.tau = tau_dev;
+  P.max_seg = lists ? max_seg : 0;
+  P.seg_cell = lists ? seg_cell_dev : nullptr;
+  P.seg_len = lists ? seg_len_dev : nullptr;
+  P.n_seg = n_seg_dev;
+  P.batch = kBatchQueue;
+  DeviceBlock blk;  // frees only what it allocated
+  blk.st = st;
+  unsigned char* base = nullptr;
+  if (fixed) {
+    if (int e = scratch_address(&base)) return e;
+  } else {
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), bytes, st));
+    base = blk.ptr;
+  }
+  if (tables || !fixed) {
+    std::vector<unsigned char> blob(off_rho, 0);
+    host::put_planes(*grid, P.G, blob.data() + 256, base + 256);
+    HIPCHK(hipMemcpyAsync(base, blob.data(), off_rho, hipMemcpyHostToDevice, st));
+  }
+  if (fixed) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(base), 64ll);
+  if (int e = brick_density(P.G, rho_dev, base + off_rho, f32, st)) return e;
+  P.rho = base + off_rho;
+  P.work = reinterpret_cast<unsigned long long*>(base);
+  P.counters = P.work + 1;
+  const int r = f32 ? launch_by_kind<TraceParams, float>(P, st, k_trace<float, kGridRegular>,
+                                                         k_trace<float, kGridRect>, k_trace<float, kGridTree>)
+                    : launch_by_kind<TraceParams, double>(P, st, k_trace<double, kGridRegular>,
+                                                          k_trace<double, kGridRect>, k_trace<double, kGridTree>);
+  if (r) return r;
+  HIPCHK(hipGetLastError());
+  if (crossings_host || lists) {
+    unsigned long long c[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(c, P.counters, sizeof c, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (crossings_host) *crossings_host = c[0];
+    if (lists && c[1]) return fail(MCRT_EOVERFLOW, "%llu rays had more than max_seg = %d segments", c[1], max_seg);
+  }
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1597,56 +1706,23 @@ int trace_path(const mcrt_grid* grid, const void* rho_dev, double kappa, int pre
                void* hip_stream) {
   try {
     mcrt::host::last_error().clear();
-    if (int e = host::check_trace(grid, rho_dev, kappa, precision, n_rays, origin_dev, dir_dev, tau_dev, max_seg,
-                                  seg_cell_dev, seg_len_dev))
-      return e;
-    const bool lists = seg_cell_dev != nullptr;
-    if (n_rays == 0) {
-      if (crossings_host) *crossings_host = 0;
-      return 0;
-    }
-    hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    TraceParams P;
-    std::memset(&P, 0, sizeof P);
-    if (int e = host::make_grid(*grid, host::elem_bytes(precision), 0, P.G)) return e;
-    P.kappa = kappa;
-    P.n_rays = n_rays;
-    P.origin = origin_dev;
-    P.dir = dir_dev;
-    P.tau = tau_dev;
-    P.max_seg = lists ? max_seg : 0;
-    P.seg_cell = lists ? seg_cell_dev : nullptr;
-    P.seg_len = lists ? seg_len_dev : nullptr;
-    P.n_seg = n_seg_dev;
-    P.batch = kBatchQueue;
-    DeviceBlock blk;
-    blk.st = st;
-    const bool f32 = precision == MCRT_PREC_FP32;
-    const size_t off_rho = 256 + host::plane_bytes(P.G, *grid);  // counters, plane tables, densities
-    std::vector<unsigned char> blob(off_rho, 0);
-    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), off_rho + (size_t)P.G.ncell_pad * (f32 ? 4 : 8), st));
-    host::put_planes(*grid, P.G, blob.data() + 256, blk.ptr + 256);
-    HIPCHK(hipMemcpyAsync(blk.ptr, blob.data(), off_rho, hipMemcpyHostToDevice, st));
-    if (int e = brick_density(P.G, rho_dev, blk.ptr + off_rho, f32, st)) return e;
-    P.rho = blk.ptr + off_rho;
-    P.work = reinterpret_cast<unsigned long long*>(blk.ptr);
-    P.counters = P.work + 1;
-    const int r = f32 ? launch_by_kind<TraceParams, float>(P, st, k_trace<float, kGridRegular>,
-                                                           k_trace<float, kGridRect>, k_trace<float, kGridTree>)
-                      : launch_by_kind<TraceParams, double>(P, st, k_trace<double, kGridRegular>,
-                                                            k_trace<double, kGridRect>, k_trace<double, kGridTree>);
-    if (r) return r;
-    HIPCHK(hipGetLastError());
-    if (crossings_host || lists) {
-      unsigned long long c[2] = {0, 0};
-      HIPCHK(hipMemcpyAsync(c, P.counters, sizeof c, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (crossings_host) *crossings_host = c[0];
-      if (lists && c[1]) return fail(MCRT_EOVERFLOW, "%llu rays had more than max_seg = %d segments", c[1], max_seg);
-    }
-    return 0;
+    return trace_impl(grid, rho_dev, kappa, precision, n_rays, origin_dev, dir_dev, tau_dev, max_seg, seg_cell_dev,
+                      seg_len_dev, n_seg_dev, crossings_host, hip_stream, false);
   } catch (...) {
     return fail(MCRT_EHIP, "trace_path: host exception");
+  }
+}
+
+int trace_path_noalloc(const mcrt_grid* grid, const void* rho_dev, double kappa, int precision, int64_t n_rays,
+                       const double* origin_dev, const double* dir_dev, double* tau_dev, int32_t max_seg,
+                       int32_t* seg_cell_dev, double* seg_len_dev, int32_t* n_seg_dev, uint64_t* crossings_host,
+                       void* hip_stream) {
+  try {
+    mcrt::host::last_error().clear();
+    return trace_impl(grid, rho_dev, kappa, precision, n_rays, origin_dev, dir_dev, tau_dev, max_seg, seg_cell_dev,
+                      seg_len_dev, n_seg_dev, crossings_host, hip_stream, true);
+  } catch (...) {
+    return fail(MCRT_EHIP, "trace_path_noalloc: host exception");
   }
 }
 

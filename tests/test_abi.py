@@ -357,3 +357,17 @@ def test_binding_rejects_mismatched_tensors(lib, B, W, case):
             B.peel_off(prob, rho, 1.0, 0.5, 0, pos, None, torch.zeros(5, dtype=f64), prob["detectors"],
                        torch.zeros(21, dtype=f64))
     assert "device tensor" not in str(ei.value), ei.value
+
+
+def test_noalloc_trace_rejects_grids_beyond_its_scratch(lib, B):
+    # a grid whose bricked densities exceed the scratch array is rejected
+    # before any device work (host-only)
+    g = B.make_grid({"box": (-1, 1, -1, 1, -1, 1), "n": (512, 512, 512)})
+    fake = C.c_void_p(0x1000)
+    for prec, ok_rays in ((0, 0), (1, 0)):
+        rc = lib.trace_path_noalloc(C.byref(g), fake, 1.0, prec, 10, fake, fake, fake, 0, None, None, None, None,
+                                    None)
+        assert rc == B.EINVAL
+        assert b"scratch" in lib.mcrt_last_error()
+    rc = lib.trace_path_noalloc(C.byref(g), fake, -1.0, 0, 10, fake, fake, fake, 0, None, None, None, None, None)
+    assert rc == B.EINVAL
