@@ -241,7 +241,9 @@ typedef struct {
  * the call, life_ms the life-cycle kernel, queue_ms the sort and the walks
  * of the peel-ray queue.  life_launches counts the life-cycle kernel's
  * launches (the call runs its packages in chunks; the adjoint launches the
- * kernel twice per chunk). */
+ * kernel twice per chunk).  life_ms is the sum over those launches; queue_ms
+ * = sort_ms (the peel-ray sort) + peel_ms (the queue's optical-depth walks)
+ * + dep_ms (the adjoint's deposit walks), each summed over the chunks. */
 typedef struct {
     double emitted, absorbed, escaped, truncated;
     uint64_t x_path, x_locate, x_peel, events, packages, peels, deposits;
@@ -250,6 +252,7 @@ typedef struct {
     double life_ms, queue_ms;
     uint64_t d_queue;
     uint64_t life_launches;
+    double sort_ms, peel_ms, dep_ms;
 } mcrt_stats;
 
 /* Photon-package life cycle (Sect. 1 techniques, Sect. 2.2 problem data):
@@ -404,7 +407,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 15
+#define MCRT_ABI_VERSION 16
 
 #ifdef __cplusplus
 }

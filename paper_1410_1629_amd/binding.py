@@ -78,7 +78,8 @@ class Stats(C.Structure):
                 ("x_peel", C.c_uint64), ("events", C.c_uint64), ("packages", C.c_uint64),
                 ("peels", C.c_uint64), ("deposits", C.c_uint64), ("kernel_ms", C.c_double),
                 ("x_queue", C.c_uint64), ("life_ms", C.c_double), ("queue_ms", C.c_double),
-                ("d_queue", C.c_uint64), ("life_launches", C.c_uint64)]
+                ("d_queue", C.c_uint64), ("life_launches", C.c_uint64), ("sort_ms", C.c_double),
+                ("peel_ms", C.c_double), ("dep_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -87,7 +88,7 @@ class Stats(C.Structure):
 _lib = None
 
 # Exported symbols of include/mcrt.h.
-ABI_VERSION = 15  # MCRT_ABI_VERSION of the header these structs follow
+ABI_VERSION = 16  # MCRT_ABI_VERSION of the header these structs follow
 SYMBOLS = ("run_photons", "trace_path", "trace_path_noalloc", "peel_off", "backward_density", "backward",
            "dust_emission", "mcrt_last_error", "mcrt_abi_version")
 NOALLOC_SCRATCH_BYTES = 96 << 20  # MCRT_NOALLOC_SCRATCH_BYTES
@@ -131,6 +132,33 @@ def load():
             lib.mcrt_abi_version(), ABI_VERSION))
     _lib = lib
     return lib
+
+
+PROBES_PATH = os.path.join(HERE, "libmcrt_probes.so")
+PROBE_KINDS = {"stream_read": 0, "gather": 1, "atomic_scattered": 2, "atomic_coalesced": 3}
+_probes = None
+
+
+def probe(kind, buf, n_ops, reps=3, stream=None):
+    """mcrt_probe (include/mcrt_probes.h) on the device tensor buf: the
+    average milliseconds of one run of the memory-system probe `kind`
+    (stream_read, gather, atomic_scattered, atomic_coalesced) over n_ops
+    operations."""
+    global _probes
+    if _probes is None:
+        if not os.path.exists(PROBES_PATH):
+            raise RuntimeError("libmcrt_probes.so is not built (%s)" % PROBES_PATH)
+        lib = C.CDLL(PROBES_PATH)
+        lib.mcrt_probe.argtypes = [C.c_int, C.c_void_p, C.c_uint64, C.c_uint64, C.c_int, C.POINTER(C.c_double),
+                                   C.c_void_p]
+        lib.mcrt_probe.restype = C.c_int
+        _probes = lib
+    ms = C.c_double(0.0)
+    rc = _probes.mcrt_probe(PROBE_KINDS[kind], _ptr(buf), buf.numel() * buf.element_size(), int(n_ops), int(reps),
+                            C.byref(ms), _stream(stream))
+    if rc != 0:
+        raise McrtError(rc, "mcrt_probe %s rejected its arguments or failed" % kind)
+    return {"kind": kind, "ms": ms.value, "n_ops": int(n_ops), "buffer_bytes": buf.numel() * buf.element_size()}
 
 
 def _check(rc):

@@ -18,6 +18,9 @@ LIB = os.path.join(HERE, "libmcrt.so")
 SOURCES = [os.path.join(CSRC, "mcrt_kernels.hip")]
 DEPENDS = SOURCES + [os.path.join(CSRC, h) for h in ("mcrt_device.hpp", "mcrt_lane.hpp", "mcrt_host.hpp")] + [
     os.path.join(INCLUDE, "mcrt.h")]
+# the memory-system probes the roofline is measured against (not the transport path)
+PROBES_LIB = os.path.join(HERE, "libmcrt_probes.so")
+PROBES_SOURCES = [os.path.join(CSRC, "mcrt_probes.hip")]
 ARCH = "gfx950"
 
 
@@ -32,8 +35,8 @@ def flags():
             "-Wall", "-Wno-unused-result", "-I" + INCLUDE, "-I" + CSRC]
 
 
-def build(verbose=False, extra=()):
-    cmd = [hipcc()] + flags() + list(extra) + SOURCES + ["-o", LIB + ".tmp"]
+def _compile(sources, lib, verbose, extra=()):
+    cmd = [hipcc()] + flags() + list(extra) + sources + ["-o", lib + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -43,8 +46,14 @@ def build(verbose=False, extra=()):
         raise RuntimeError("hipcc failed:\n" + msg)
     if verbose and msg.strip():
         print(msg)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
+
+
+def build(verbose=False, extra=()):
+    """Builds libmcrt.so and libmcrt_probes.so; returns the former's path."""
+    _compile(PROBES_SOURCES, PROBES_LIB, verbose, extra)
+    return _compile(SOURCES, LIB, verbose, extra)
 
 
 def needs_build():

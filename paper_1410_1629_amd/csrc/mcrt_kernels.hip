@@ -1089,6 +1089,37 @@ struct EventPair {
   }
 };
 
+// HIP events recorded on the call's stream around the launches of each
+// kind (only when the caller asks for statistics): the life-cycle kernel,
+// the peel-ray sort, the optical-depth walks and the deposit walks.
+enum SpanKind { kSpanLife = 0, kSpanSort, kSpanPeel, kSpanDep, kSpanKinds };
+struct Spans {
+  bool on = false;
+  std::vector<hipEvent_t> ev[kSpanKinds];  // begin, end, begin, end, ...
+  ~Spans() {
+    for (auto& v : ev)
+      for (hipEvent_t e : v) (void)hipEventDestroy(e);
+  }
+  int mark(int kind, hipStream_t st) {
+    if (!on) return 0;
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreate(&e));
+    ev[kind].push_back(e);
+    HIPCHK(hipEventRecord(e, st));
+    return 0;
+  }
+  // total milliseconds of the spans of one kind (after the stream has
+  // finished them)
+  double ms(int kind) const {
+    double t = 0.0;
+    for (size_t i = 0; i + 1 < ev[kind].size(); i += 2) {
+      float x = 0.0f;
+      if (hipEventElapsedTime(&x, ev[kind][i], ev[kind][i + 1]) == hipSuccess) t += x;
+    }
+    return t;
+  }
+};
+
 // Device memory of the peel-ray queue: rays, their sorted order (and the
 // order after the first sort pass with the second keys), the sort's count
 // matrix (keys x kSortBlocks), its scan and the scan's tile totals.
@@ -1155,17 +1186,21 @@ int reset_counters(unsigned long long* ctr, int w, int n, hipStream_t st) {
 // The queue's walks: optical depth (and the image, forward), then the
 // adjoint's deposit walks.
 template <typename R, bool ADJ, int GK, bool INST>
-int walk_peel_jobs(const PeelJobParams& J, hipStream_t st) {
+int walk_peel_jobs(const PeelJobParams& J, hipStream_t st, Spans& sp) {
   int nblk = 0;
   if (int e = persistent_grid(k_peeltau<R, ADJ, GK, INST>, 0, &nblk)) return e;
+  if (int e = sp.mark(kSpanPeel, st)) return e;
   hipLaunchKernelGGL((k_peeltau<R, ADJ, GK, INST>), dim3(nblk), dim3(kBlock), 0, st, J);
+  if (int e = sp.mark(kSpanPeel, st)) return e;
   if (ADJ) {
     int dev = 0, cus = 0, nb = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peeldep<R, GK, INST>, kBundleThreads, 0));
+    if (int e = sp.mark(kSpanDep, st)) return e;
     hipLaunchKernelGGL((k_peeldep<R, GK, INST>), dim3(std::max(1, nb) * std::max(1, cus)), dim3(kBundleThreads), 0,
                        st, J);
+    if (int e = sp.mark(kSpanDep, st)) return e;
   }
   HIPCHK(hipGetLastError());
   return 0;
@@ -1173,8 +1208,10 @@ int walk_peel_jobs(const PeelJobParams& J, hipStream_t st) {
 
 // Sorts the chunk's queued peel rays by key and walks them.
 template <typename R, bool ADJ>
-int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ctr, bool inst, hipStream_t st) {
+int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ctr, bool inst, hipStream_t st,
+                  Spans& sp) {
   const long long n_cnt = q.n_keys * kSortBlocks;
+  if (int e = sp.mark(kSpanSort, st)) return e;
   hipLaunchKernelGGL(k_hist, dim3(kSortBlocks), dim3(kSortThreads), 0, st, q.keys, ctr, q.cap, (int)q.n_keys,
                      q.counts);
   const long long n_tiles = (n_cnt + kScanTile - 1) / kScanTile;
@@ -1186,6 +1223,7 @@ int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ct
                      q.starts, q.idx, q.subs);
   hipLaunchKernelGGL(k_refine, dim3((unsigned)q.n_keys), dim3(kRefineThreads), 0, st, q.starts, q.idx, q.subs, q.perm);
   HIPCHK(hipGetLastError());
+  if (int e = sp.mark(kSpanSort, st)) return e;
   PeelJobParams J;
   J.G = P.G;
   J.rho = P.rho;
@@ -1208,15 +1246,15 @@ int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ct
   J.batch = kBatchQueue;
   if (inst) {  // instruments other than frames: walks that stop at a camera's eye
     switch (P.G.kind) {
-      case kGridRect: return walk_peel_jobs<R, ADJ, kGridRect, true>(J, st);
-      case kGridTree: return walk_peel_jobs<R, ADJ, kGridTree, true>(J, st);
-      default: return walk_peel_jobs<R, ADJ, kGridRegular, true>(J, st);
+      case kGridRect: return walk_peel_jobs<R, ADJ, kGridRect, true>(J, st, sp);
+      case kGridTree: return walk_peel_jobs<R, ADJ, kGridTree, true>(J, st, sp);
+      default: return walk_peel_jobs<R, ADJ, kGridRegular, true>(J, st, sp);
     }
   }
   switch (P.G.kind) {
-    case kGridRect: return walk_peel_jobs<R, ADJ, kGridRect, false>(J, st);
-    case kGridTree: return walk_peel_jobs<R, ADJ, kGridTree, false>(J, st);
-    default: return walk_peel_jobs<R, ADJ, kGridRegular, false>(J, st);
+    case kGridRect: return walk_peel_jobs<R, ADJ, kGridRect, false>(J, st, sp);
+    case kGridTree: return walk_peel_jobs<R, ADJ, kGridTree, false>(J, st, sp);
+    default: return walk_peel_jobs<R, ADJ, kGridRegular, false>(J, st, sp);
   }
 }
 
@@ -1423,37 +1461,28 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   }
   unsigned long long* const ctr = reinterpret_cast<unsigned long long*>(blk.ptr + off_cnt);
   EventPair ev;
-  std::vector<hipEvent_t> qev;  // around each chunk's queue phase
-  struct EventsGuard {
-    std::vector<hipEvent_t>& v;
-    ~EventsGuard() {
-      for (hipEvent_t e : v) (void)hipEventDestroy(e);
-    }
-  } qguard{qev};
+  Spans sp;
+  sp.on = stats != nullptr;
   if (stats) {
     HIPCHK(hipEventCreate(&ev.a));
     HIPCHK(hipEventCreate(&ev.c));
     HIPCHK(hipEventRecord(ev.a, st));
   }
-  int rc = 0;
   unsigned long long launches = 0;  // of the life-cycle kernel
   auto queue_phase = [&](bool adj) -> int {  // sort and walk the chunk's queued peel rays
-    if (stats) {
-      qev.push_back(nullptr);
-      HIPCHK(hipEventCreate(&qev.back()));
-      HIPCHK(hipEventRecord(qev.back(), st));
-    }
-    const int r = adj ? (f32 ? run_peel_jobs<float, true>(queue, P, ctr, inst, st)
-                             : run_peel_jobs<double, true>(queue, P, ctr, inst, st))
-                      : (f32 ? run_peel_jobs<float, false>(queue, P, ctr, inst, st)
-                             : run_peel_jobs<double, false>(queue, P, ctr, inst, st));
+    return adj ? (f32 ? run_peel_jobs<float, true>(queue, P, ctr, inst, st, sp)
+                      : run_peel_jobs<double, true>(queue, P, ctr, inst, st, sp))
+               : (f32 ? run_peel_jobs<float, false>(queue, P, ctr, inst, st, sp)
+                      : run_peel_jobs<double, false>(queue, P, ctr, inst, st, sp));
+  };
+  auto life_launch = [&](bool adj) -> int {
+    if (int e = sp.mark(kSpanLife, st)) return e;
+    const int r = adj ? (f32 ? launch_life<float, true>(P, full, nblk, st) : launch_life<double, true>(P, full, nblk, st))
+                      : (f32 ? launch_life<float, false>(P, full, nblk, st)
+                             : launch_life<double, false>(P, full, nblk, st));
     if (r) return r;
-    if (stats) {
-      qev.push_back(nullptr);
-      HIPCHK(hipEventCreate(&qev.back()));
-      HIPCHK(hipEventRecord(qev.back(), st));
-    }
-    return 0;
+    ++launches;
+    return sp.mark(kSpanLife, st);
   };
   if (!adjoint) {
     for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
@@ -1461,9 +1490,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
       P.n_chunk = std::min(chunk, P.n_items - c0);
       if (int e = reset_counters(ctr, 0, 1, st)) return e;
       if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
-      rc = f32 ? launch_life<float, false>(P, full, nblk, st) : launch_life<double, false>(P, full, nblk, st);
-      if (rc) return rc;
-      ++launches;
+      if (int e = life_launch(false)) return e;
       if (P.jobs)
         if (int e = queue_phase(false)) return e;
     }
@@ -1480,17 +1507,13 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
       if (int e = reset_counters(ctr, kDepCounter, 1, st)) return e;
       P.split = 1;  // pass A
       if (opts->event_batch == 0) P.batch = kBatchPassA;
-      rc = f32 ? launch_life<float, true>(P, full, nblk, st) : launch_life<double, true>(P, full, nblk, st);
-      if (rc) return rc;
-      ++launches;
+      if (int e = life_launch(true)) return e;
       if (P.jobs)
         if (int e = queue_phase(true)) return e;
       if (int e = reset_counters(ctr, 0, 1, st)) return e;
       P.split = 2;  // pass B
       if (opts->event_batch == 0) P.batch = kBatchPassB;
-      rc = f32 ? launch_life<float, true>(P, full, nblk, st) : launch_life<double, true>(P, full, nblk, st);
-      if (rc) return rc;
-      ++launches;
+      if (int e = life_launch(true)) return e;
       if (optg) {
         const unsigned nb = (unsigned)((P.item0 + P.n_chunk - 1) / P.n_pkg - P.item0 / P.n_pkg + 1);
         hipLaunchKernelGGL(k_grad_optics, dim3(nb), dim3(kOptThreads), 0, st, P.gpart, P.item0, P.n_chunk, P.n_pkg,
@@ -1509,13 +1532,9 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     HIPCHK(hipMemcpyAsync(xs, P.xstats, sizeof xs, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(xq, ctr + kQueueCrossings, sizeof xq, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    float ms = 0.0f, ms_queue = 0.0f;
+    float ms = 0.0f;
     if (hipEventElapsedTime(&ms, ev.a, ev.c) != hipSuccess) ms = -1.0f;
-    for (size_t i = 0; i + 1 < qev.size(); i += 2) {
-      float t = 0.0f;
-      if (hipEventElapsedTime(&t, qev[i], qev[i + 1]) == hipSuccess) ms_queue += t;
-    }
-    const float ms_life = ms - ms_queue;
+    const double ms_sort = sp.ms(kSpanSort), ms_peel = sp.ms(kSpanPeel), ms_dep = sp.ms(kSpanDep);
     stats->emitted = pr.emitted;
     stats->absorbed = ds[0];
     stats->escaped = ds[1];
@@ -1529,8 +1548,11 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     stats->deposits = xs[6] + xq[1];
     stats->kernel_ms = ms;
     stats->x_queue = xq[0];
-    stats->life_ms = ms_life;
-    stats->queue_ms = ms_queue;
+    stats->life_ms = sp.ms(kSpanLife);
+    stats->queue_ms = ms_sort + ms_peel + ms_dep;
+    stats->sort_ms = ms_sort;
+    stats->peel_ms = ms_peel;
+    stats->dep_ms = ms_dep;
     stats->d_queue = xq[1];
     stats->life_launches = launches;
   }

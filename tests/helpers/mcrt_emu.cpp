@@ -584,6 +584,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
     stats->life_ms = stats->queue_ms = 0.0;
     stats->d_queue = M.d_queue;
     stats->life_launches = (ADJ ? 2 : 1) * ((P.n_items + chunk - 1) / chunk);
+    stats->sort_ms = stats->peel_ms = stats->dep_ms = 0.0;
   }
   return 0;
 }

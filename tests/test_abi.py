@@ -371,3 +371,26 @@ def test_noalloc_trace_rejects_grids_beyond_its_scratch(lib, B):
         assert b"scratch" in lib.mcrt_last_error()
     rc = lib.trace_path_noalloc(C.byref(g), fake, -1.0, 0, 10, fake, fake, fake, 0, None, None, None, None, None)
     assert rc == B.EINVAL
+
+
+def test_probes_library_exports_its_header(B):
+    # the memory-system probes' header and library: every declared function
+    # is exported, and invalid arguments are rejected before any launch
+    hdr = os.path.join(ROOT, "include", "mcrt_probes.h")
+    text = re.sub(r"/\*.*?\*/", "", open(hdr).read(), flags=re.S)
+    names = re.findall(r"^\s*int\s+(\w+)\s*\(", text, flags=re.M)
+    assert names == ["mcrt_probe"]
+    if not os.path.exists(B.PROBES_PATH):
+        pytest.skip("libmcrt_probes.so is not built")
+    out = subprocess.run(["nm", "-D", "--defined-only", B.PROBES_PATH], check=True, capture_output=True,
+                         text=True).stdout
+    assert "mcrt_probe" in {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    lib = C.CDLL(B.PROBES_PATH)
+    lib.mcrt_probe.argtypes = [C.c_int, C.c_void_p, C.c_uint64, C.c_uint64, C.c_int, C.POINTER(C.c_double),
+                               C.c_void_p]
+    ms = C.c_double(0)
+    fake = C.c_void_p(0x1000)
+    assert lib.mcrt_probe(9, fake, 1 << 20, 1 << 14, 1, C.byref(ms), None) == -1  # unknown kind
+    assert lib.mcrt_probe(1, fake, 3 << 20, 1 << 14, 1, C.byref(ms), None) == -1  # not a power of two
+    assert lib.mcrt_probe(2, fake, 1 << 20, 100, 1, C.byref(ms), None) == -1  # not whole workgroups
+    assert lib.mcrt_probe(0, None, 1 << 20, 1, 1, C.byref(ms), None) == -1
