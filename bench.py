@@ -115,7 +115,9 @@ def kernel_work(st, prec, adjoint):
     dL/dI (adjoint); the adjoint's deposit walk each queued ray again with
     one gradient deposit per crossing and no density loads."""
     cb = BYTES_PER_CROSSING[prec]
-    chunks = st["life_launches"] // (2 if adjoint else 1)
+    # the adjoint launches the life kernel twice per chunk, once when it reads the forward run's tape (then its
+    # queue has no optical-depth walks: peel_ms is 0)
+    chunks = st["life_launches"] // (2 if adjoint and st["peel_ms"] > 0 else 1)
     x_life = st["x_path"] + st["x_locate"] + st["x_peel"] - st["x_queue"]
     x_tau = st["x_queue"] - st["d_queue"]
     out = {"life": (x_life * cb + (st["deposits"] - st["d_queue"]) * BYTES_PER_DEPOSIT, x_life, st["life_launches"],
@@ -278,11 +280,14 @@ def summary(sts, n_pkg):
 
 
 def spiral_step(B, W, dev, steps):
-    """The edge-on spiral, 1e7 packages: one step is the forward run plus
-    the path-replay adjoint of an L2 image loss against a fixed target
-    (rendered once from a perturbed density with another key).  Beside it:
-    the plain FP64 GPU path on the same step with the FP32 step's dL/dI, and
-    the Monte Carlo noise of images and gradient from two more keys."""
+    """The edge-on spiral, 1e7 packages: one step is the forward run (which
+    keeps the adjoint tape: T per leg, C per peel ray) plus the path-replay
+    adjoint of an L2 image loss against a fixed target (rendered once from a
+    perturbed density with another key), which reads the tape and replays
+    each package once.  Beside it: the adjoint without the tape (two replays
+    and the peel rays' optical-depth walks), the plain FP64 GPU path on the
+    same step with the FP32 step's dL/dI, and the Monte Carlo noise of images
+    and gradient from two more keys."""
     import numpy as np
     import torch
     prob = W.spiral(n_packages=10_000_000, precision=1)
@@ -299,23 +304,28 @@ def spiral_step(B, W, dev, steps):
     B.run_photons(dict(prob, seed=4358), rho_t, target, absorbed)
     del rho_t
 
-    def step_fn(p, r, img, g, a):
-        sf = B.run_photons(p, r, img, absorbed)
+    tape = B.new_tape(prob, dev)
+
+    def step_fn(p, r, img, g, a, t):
+        sf = B.run_photons(p, r, img, absorbed, tape=t)
         torch.sub(img, target, out=a)
         a.mul_(2.0)
-        sb = B.backward_density(p, r, a, g)
+        sb = B.backward_density(p, r, a, g, tape=t)
         return sf, sb
 
-    step_fn(prob, rho, images, grad, adj)
+    step_fn(prob, rho, images, grad, adj, tape)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fw, bw = [], []
     for _ in range(steps):
-        sf, sb = step_fn(prob, rho, images, grad, adj)
+        sf, sb = step_fn(prob, rho, images, grad, adj, tape)
         fw.append(sf)
         bw.append(sb)
     torch.cuda.synchronize()
     ms_step = 1e3 * (time.perf_counter() - t0) / steps
+    # the same adjoint without the tape (for comparison; same dL/dI)
+    g_replay = torch.empty_like(grad)
+    sb_replay = B.backward_density(prob, rho, adj, g_replay)
     n_pkg = prob["n_packages"]
     fsum, bsum = summary(fw, n_pkg), summary(bw, n_pkg)
     level = "MALL: the 16 MiB grid and 32 MiB tally fit in the 256 MB MALL behind the 4 MB L2 of each XCD"
@@ -328,6 +338,10 @@ def spiral_step(B, W, dev, steps):
            "packages_per_s": n_pkg / (ms_step / 1e3), "ms_per_step": ms_step,
            "crossings_per_s": (fsum["crossings"] + bsum["crossings"]) / (ms_step / 1e3),
            "forward": fsum, "adjoint": bsum, "rooflines": roof,
+           "tape_gb": (tape.numel() / 1e9) if tape is not None else 0.0,
+           "adjoint_without_tape": {"kernel_ms": sb_replay["kernel_ms"], "life_ms": sb_replay["life_ms"],
+                                    "life_launches": sb_replay["life_launches"], "queue_ms": sb_replay["queue_ms"],
+                                    "gradient_rel_l1_vs_tape": rel_l1(g_replay, grad)},
            "energy_closure": (st_f["absorbed"] + st_f["escaped"] + st_f["truncated"] - st_f["emitted"]) /
                              st_f["emitted"]}
     # the plain FP64 GPU path: the same step, the FP32 step's dL/dI
@@ -336,10 +350,12 @@ def spiral_step(B, W, dev, steps):
     rho64 = B.density_tensor(p64, dev)
     img64 = torch.empty_like(images)
     grad64 = torch.empty_like(grad)
+    del tape
+    tape64 = B.new_tape(p64, dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sf64 = B.run_photons(p64, rho64, img64, absorbed)
-    sb64 = B.backward_density(p64, rho64, adj32, grad64)
+    sf64 = B.run_photons(p64, rho64, img64, absorbed, tape=tape64)
+    sb64 = B.backward_density(p64, rho64, adj32, grad64, tape=tape64)
     torch.cuda.synchronize()
     wall64 = time.perf_counter() - t0
     # Monte Carlo noise: two more Philox keys, the same dL/dI

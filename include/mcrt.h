@@ -211,7 +211,28 @@ typedef struct {
  * queue and the adjoint's event scratch allow), else at most that many per
  * chunk; each chunk is a launch of the life-cycle kernel (two in the
  * adjoint) followed by its queue's sort and walks.  Results do not depend on
- * it up to the order of FP64 additions. */
+ * it up to the order of FP64 additions.
+ *
+ * tape, tape_bytes: the forward run's record for its adjoint (tape NULL:
+ * none).  run_photons fills a device tape of mcrt_tape_bytes bytes with,
+ * per package (work item) and for each of its events, the optical depth T
+ * of the path leg that follows the event and, per frame, the event's
+ * peel-off contribution C and image index.  backward_density and backward,
+ * called with the same arguments and densities and the filled tape, take T
+ * and q = (dL/dI) C from it instead of replaying every package a first
+ * time and walking its peel rays for their optical depth: each package is
+ * replayed once -- its positions, directions and cells are recomputed from
+ * its random numbers, never stored -- and walks only its locate legs, and
+ * its peel rays with q != 0 for their deposits.  The tape records a
+ * fingerprint of the run's arguments (not of the densities or a cell
+ * source's luminosities, which must be the same); an adjoint whose
+ * arguments differ fails with MCRT_EINVAL.  An adjoint with a tape waits
+ * for its fingerprint (a 256-byte copy), so a forward run on another
+ * stream must have finished.  A package with more events than the tape
+ * keeps (impossible when mcrt_tape_bytes is nonzero, but checked) and a
+ * loss on the absorbed tally (adj_absorbed_dev) make the adjoint replay
+ * without the tape.  The forward run ignores tape_bytes and the adjoint
+ * rejects a tape smaller than mcrt_tape_bytes. */
 typedef struct {
     uint64_t n_packages, first_package, seed;
     int32_t precision;
@@ -222,7 +243,23 @@ typedef struct {
     int32_t brick_shape;
     int64_t peel_queue;
     int64_t max_chunk;
+    void *tape;
+    uint64_t tape_bytes;
 } mcrt_opts;
+
+#define MCRT_TAPE_MAX_EVENTS 64
+
+/* Bytes of the adjoint tape of a run with these optics, frames and options
+ * (see mcrt_opts.tape): 256 + items x E x (8 (1 + n_det) + 4 n_det), where
+ * items = n_packages x n_lambda and E is the most events (emission and
+ * scatterings) a package can have -- a package's weight after n
+ * scatterings is at most albedo^n of its initial weight and the package
+ * stops once it is below w_min times that, so E = min(max_scatter, 2 +
+ * floor(ln w_min / ln a)) + 1 with a the largest albedo (max_scatter + 1
+ * when a = 1 or w_min = 0).  Returns 0 when E exceeds MCRT_TAPE_MAX_EVENTS,
+ * when there is nothing to record (no peel-off or no frame), or for
+ * invalid arguments. */
+uint64_t mcrt_tape_bytes(const mcrt_optics *optics, int n_det, const mcrt_opts *opts);
 
 #define MCRT_BRICK(lx, ly, lz) (0x1000 | (lx) | ((ly) << 4) | ((lz) << 8))
 
@@ -407,7 +444,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 16
+#define MCRT_ABI_VERSION 17
 
 #ifdef __cplusplus
 }

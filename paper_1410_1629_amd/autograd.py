@@ -6,12 +6,28 @@ Forward calls run_photons; backward calls backward_density (or backward),
 which replays every package from its random numbers and accumulates the
 detached (score-function) derivative of the images -- the derivative of the
 reweighted estimator whose paths are held fixed.  Both run entirely in the
-HIP kernels.  The absorbed-luminosity tally is not differentiated.
+HIP kernels.  When the run can keep an adjoint tape (binding.tape_bytes)
+and it fits in a quarter of the free device memory, the forward run fills
+one and the backward pass reads T and the peel-off contributions from it,
+replaying each package once instead of twice (prob["adjoint_tape"] = False
+turns this off).  These functions differentiate the images only; a loss on
+the absorbed-luminosity tally goes through binding.backward(adj_absorbed=).
 """
 import numpy as np
 import torch
 
 from . import binding
+
+
+def _tape_for(prob, device):
+    """A tape for the run, or None (not wanted, not possible, or too large)."""
+    if not prob.get("adjoint_tape", True):
+        return None
+    n = binding.tape_bytes(prob)
+    if n == 0:
+        return None
+    free, _ = torch.cuda.mem_get_info(device)
+    return torch.empty(n, dtype=torch.uint8, device=device) if n < free // 4 else None
 
 
 class RTImage(torch.autograd.Function):
@@ -24,8 +40,10 @@ class RTImage(torch.autograd.Function):
     def forward(ctx, rho, prob):
         p = dict(prob, flags=int(prob.get("flags", 7)) & ~binding.ABSORB)
         images = torch.empty(binding.image_shape(p), dtype=torch.float64, device=rho.device)
-        binding.run_photons(p, rho.contiguous(), images, None, stats=False)
+        tape = _tape_for(p, rho.device)
+        binding.run_photons(p, rho.contiguous(), images, None, stats=False, tape=tape)
         ctx.prob = p
+        ctx.tape = tape
         ctx.save_for_backward(rho)
         return images
 
@@ -34,7 +52,8 @@ class RTImage(torch.autograd.Function):
         (rho,) = ctx.saved_tensors
         grad = torch.empty(rho.numel(), dtype=torch.float64, device=rho.device)
         binding.backward_density(ctx.prob, rho.contiguous(), grad_images.contiguous().to(torch.float64), grad,
-                                 stats=False)
+                                 stats=False, tape=ctx.tape)
+        ctx.tape = None
         return grad.to(rho.dtype).view_as(rho), None
 
 
@@ -58,8 +77,10 @@ class RTImageOptics(torch.autograd.Function):
                  g=g.detach().to("cpu", torch.float64).numpy().copy(),
                  sources=[dict(s, lum=np.array(lum_h[i])) for i, s in enumerate(prob["sources"])])
         images = torch.empty(binding.image_shape(p), dtype=torch.float64, device=rho.device)
-        binding.run_photons(p, rho.contiguous(), images, None, stats=False)
+        tape = _tape_for(p, rho.device)
+        binding.run_photons(p, rho.contiguous(), images, None, stats=False, tape=tape)
         ctx.prob = p
+        ctx.tape = tape
         ctx.save_for_backward(rho, albedo, g, lum)
         return images
 
@@ -72,7 +93,9 @@ class RTImageOptics(torch.autograd.Function):
                 for i, t in enumerate((rho, albedo, g, lum))]
         if not any(o is not None for o in outs):
             return None, None, None, None, None
-        binding.backward(ctx.prob, rho.contiguous(), grad_images.contiguous().to(torch.float64), *outs, stats=False)
+        binding.backward(ctx.prob, rho.contiguous(), grad_images.contiguous().to(torch.float64), *outs, stats=False,
+                         tape=ctx.tape)
+        ctx.tape = None
         res = [None if o is None else o.to(t.dtype).view_as(t).to(t.device) for o, t in zip(outs, (rho, albedo, g, lum))]
         return res[0], res[1], res[2], res[3], None
 

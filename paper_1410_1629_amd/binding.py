@@ -60,7 +60,8 @@ class Opts(C.Structure):
     _fields_ = [("n_packages", C.c_uint64), ("first_package", C.c_uint64), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("w_min", C.c_double), ("max_scatter", C.c_int32),
                 ("flags", C.c_uint32), ("launch_blocks", C.c_int32), ("event_batch", C.c_int32),
-                ("brick_shape", C.c_int32), ("peel_queue", C.c_int64), ("max_chunk", C.c_int64)]
+                ("brick_shape", C.c_int32), ("peel_queue", C.c_int64), ("max_chunk", C.c_int64),
+                ("tape", C.c_void_p), ("tape_bytes", C.c_uint64)]
 
 
 def brick(lx, ly, lz):
@@ -88,9 +89,9 @@ class Stats(C.Structure):
 _lib = None
 
 # Exported symbols of include/mcrt.h.
-ABI_VERSION = 16  # MCRT_ABI_VERSION of the header these structs follow
+ABI_VERSION = 17  # MCRT_ABI_VERSION of the header these structs follow
 SYMBOLS = ("run_photons", "trace_path", "trace_path_noalloc", "peel_off", "backward_density", "backward",
-           "dust_emission", "mcrt_last_error", "mcrt_abi_version")
+           "dust_emission", "mcrt_tape_bytes", "mcrt_last_error", "mcrt_abi_version")
 NOALLOC_SCRATCH_BYTES = 96 << 20  # MCRT_NOALLOC_SCRATCH_BYTES
 
 
@@ -125,6 +126,8 @@ def load():
     lib.dust_emission.restype = C.c_int
     lib.mcrt_last_error.argtypes = []
     lib.mcrt_last_error.restype = C.c_char_p
+    lib.mcrt_tape_bytes.argtypes = [C.POINTER(Optics), C.c_int, C.POINTER(Opts)]
+    lib.mcrt_tape_bytes.restype = C.c_uint64
     lib.mcrt_abi_version.argtypes = []
     lib.mcrt_abi_version.restype = C.c_int
     if lib.mcrt_abi_version() != ABI_VERSION:
@@ -315,11 +318,40 @@ class _Problem:
         o = dict(n_packages=prob["n_packages"], first_package=prob.get("first_package", 0),
                  seed=prob.get("seed", 4357), precision=prob.get("precision", 0), w_min=prob.get("w_min", 1e-4),
                  max_scatter=prob.get("max_scatter", 1000), flags=prob.get("flags", 7), launch_blocks=0,
-                 event_batch=0, brick_shape=0, peel_queue=0, max_chunk=0)
+                 event_batch=0, brick_shape=0, peel_queue=0, max_chunk=0, tape=None, tape_bytes=0)
         o.update(overrides)
         self.opts = Opts(int(o["n_packages"]), int(o["first_package"]), int(o["seed"]), int(o["precision"]),
                          float(o["w_min"]), int(o["max_scatter"]), int(o["flags"]), int(o["launch_blocks"]),
-                         int(o["event_batch"]), int(o["brick_shape"]), int(o["peel_queue"]), int(o["max_chunk"]))
+                         int(o["event_batch"]), int(o["brick_shape"]), int(o["peel_queue"]), int(o["max_chunk"]),
+                         o["tape"], int(o["tape_bytes"]))
+
+
+def tape_bytes(prob, **overrides):
+    """mcrt_tape_bytes: the size of the adjoint tape of a run of the problem
+    (0: the run cannot keep one)."""
+    lib = load()
+    pr = _Problem(prob, cells_on_device=False, **overrides)
+    return int(lib.mcrt_tape_bytes(C.byref(pr.optics), pr.n_det, C.byref(pr.opts)))
+
+
+def new_tape(prob, device="cuda", **overrides):
+    """A device byte tensor of the problem's tape size, or None when the run
+    cannot keep a tape."""
+    import torch
+    n = tape_bytes(prob, **overrides)
+    return torch.empty(n, dtype=torch.uint8, device=device) if n else None
+
+
+def _tape_args(prob, tape, overrides):
+    """The tape's pointer and size for the options (after checking it)."""
+    if tape is None:
+        return overrides
+    import torch
+    _need(tape, "tape", tape.numel(), torch.uint8)
+    need = tape_bytes(prob, **overrides)
+    if need == 0 or tape.numel() < need:
+        raise ValueError("tape has %d bytes, the run needs %d (0: it cannot keep one)" % (tape.numel(), need))
+    return dict(overrides, tape=_ptr(tape).value, tape_bytes=tape.numel())
 
 
 def image_shape(prob):
@@ -335,12 +367,15 @@ def density_tensor(prob, device="cuda"):
     return torch.as_tensor(np.ascontiguousarray(prob["rho"]).reshape(-1), dtype=dt).to(device)
 
 
-def run_photons(prob, rho, images, absorbed=None, stats=True, stream=None, **overrides):
+def run_photons(prob, rho, images, absorbed=None, stats=True, stream=None, tape=None, **overrides):
     """run_photons over the problem dict.  rho, images, absorbed: device
     tensors (images [comps][n_lambda][pixels] FP64, absorbed [n_lambda][ncell]
-    FP64).  Returns the statistics dict (stats=True waits for the kernel)."""
+    FP64); tape: a device byte tensor (new_tape) the run fills for its
+    adjoint, or None.  Returns the statistics dict (stats=True waits for the
+    kernel)."""
     lib = load()
     _check_life(prob, rho, images=images, absorbed=absorbed, overrides=overrides)
+    overrides = _tape_args(prob, tape, overrides)
     pr = _Problem(prob, **overrides)
     st = Stats()
     _check(lib.run_photons(C.byref(pr.grid), _ptr(rho), C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det,
@@ -349,11 +384,13 @@ def run_photons(prob, rho, images, absorbed=None, stats=True, stream=None, **ove
     return st.as_dict() if stats else None
 
 
-def backward_density(prob, rho, adj_images, grad_rho, stats=True, stream=None, **overrides):
+def backward_density(prob, rho, adj_images, grad_rho, stats=True, stream=None, tape=None, **overrides):
     """backward_density: grad_rho (device FP64 [ncell]) = dL/drho for
-    dL/dI = adj_images (device FP64, image layout of run_photons)."""
+    dL/dI = adj_images (device FP64, image layout of run_photons); tape: the
+    forward run's tape (same problem and densities), or None."""
     lib = load()
     _check_life(prob, rho, adj=adj_images, grad=grad_rho, overrides=overrides)
+    overrides = _tape_args(prob, tape, overrides)
     pr = _Problem(prob, **overrides)
     st = Stats()
     _check(lib.backward_density(C.byref(pr.grid), _ptr(rho), C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det,
@@ -363,7 +400,7 @@ def backward_density(prob, rho, adj_images, grad_rho, stats=True, stream=None, *
 
 
 def backward(prob, rho, adj_images, grad_rho=None, grad_albedo=None, grad_g=None, grad_lum=None, stats=True,
-             stream=None, adj_absorbed=None, **overrides):
+             stream=None, adj_absorbed=None, tape=None, **overrides):
     """backward: the gradients of the loss with dL/dI = adj_images (and dL/dA
     = adj_absorbed [n_lambda][ncell] on the absorbed tally, if given) with
     respect to the densities (device FP64 [ncell]), the albedo and g
@@ -375,6 +412,7 @@ def backward(prob, rho, adj_images, grad_rho=None, grad_albedo=None, grad_g=None
     _need(grad_albedo, "grad_albedo", nl)
     _need(grad_g, "grad_g", nl)
     _need(grad_lum, "grad_lum", len(prob["sources"]) * nl)
+    overrides = _tape_args(prob, tape, overrides)
     pr = _Problem(prob, **overrides)
     st = Stats()
     g = Grads(_ptr(grad_rho), _ptr(grad_albedo), _ptr(grad_g), _ptr(grad_lum))

@@ -700,5 +700,140 @@ inline void dust_constants(int n_lambda, const double* lambda, const double* dla
   }
 }
 
+// ---------------------------------------------------------------------------
+// The adjoint tape (mcrt_opts.tape): a 256-byte header, then FP64
+// [events][1 + n_det][items] (T of the leg after event e, then C per frame)
+// and uint32 [events][n_det][items] (the image index of each C).
+
+constexpr uint64_t kTapeMagic = 0x3145504154545243ull;  // "CRTTAPE1", little-endian
+constexpr size_t kTapeHeader = 256;
+
+struct TapeHeader {
+  uint64_t magic, fingerprint, n_items;
+  int32_t events, n_det;
+  uint32_t overflow;  // set by the forward run's kernels: a package had more events than the tape keeps
+  uint32_t pad;
+};
+static_assert(sizeof(TapeHeader) <= kTapeHeader, "tape header");
+
+// The most events (emission and scatterings) a package can have: its weight
+// after n scatterings is at most a^n of its initial weight (a the largest
+// albedo; each scattering multiplies it by albedo (1 - e^-T) <= albedo),
+// and a package with weight below w_min times its initial weight stops
+// after that scattering's peel-off, so scattering n + 1 needs a^n >= w_min,
+// n <= ln w_min / ln a; one more is allowed for rounding.  Scattering 1
+// always happens (the first check follows it); max_scatter bounds the rest.
+inline long long tape_events(const mcrt_optics& optics, const mcrt_opts& o) {
+  double a = 0.0;
+  for (int l = 0; l < optics.n_lambda; ++l) a = std::max(a, optics.albedo[l]);
+  long long last = o.max_scatter;  // index of the last possible event
+  if (a < 1.0 && o.w_min > 0.0) {
+    const double r = a > 0.0 ? std::log(o.w_min) / std::log(a) : 0.0;
+    if (r + 2.0 < (double)last) last = std::max(1ll, 2 + (long long)std::floor(r));
+  }
+  return last + 1;
+}
+
+// Bytes of the tape, 0 when the run cannot have one.
+inline uint64_t tape_bytes(const mcrt_optics* optics, int n_det, const mcrt_opts* o) {
+  if (!optics || !o || !optics->albedo || optics->n_lambda < 1 || n_det < 1 || n_det > MCRT_MAX_DETECTORS) return 0;
+  if (!(o->flags & (MCRT_PEEL_EMIT | MCRT_PEEL_SCAT)) || o->n_packages < 1 || o->max_scatter < 1) return 0;
+  for (int l = 0; l < optics->n_lambda; ++l)
+    if (!(optics->albedo[l] >= 0.0 && optics->albedo[l] <= 1.0)) return 0;
+  if (!(o->w_min >= 0.0) || !finite(o->w_min)) return 0;
+  const long long ev = tape_events(*optics, *o);
+  if (ev > MCRT_TAPE_MAX_EVENTS) return 0;
+  const uint64_t items = o->n_packages * (uint64_t)optics->n_lambda;
+  const uint64_t doubles = items * (uint64_t)ev * (1 + n_det), words = items * (uint64_t)ev * n_det;
+  return kTapeHeader + ((8 * doubles + 255) & ~uint64_t(255)) + 4 * words;
+}
+
+inline uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 0x100000001b3ull;
+  return h;
+}
+
+template <typename T>
+inline uint64_t fnv_value(uint64_t h, T v) {
+  return fnv1a(h, &v, sizeof v);
+}
+
+// Fingerprint of everything the tape's contents depend on except the
+// densities and a cell source's luminosities (device arrays): the grid and
+// its planes or tree, the optics, the sources, the frames, the packages,
+// key, precision, termination and peel-off flags.
+inline uint64_t tape_fingerprint(const mcrt_grid& g, const mcrt_optics& op, int n_src, const mcrt_source* src,
+                                 int n_det, const mcrt_detector* det, const mcrt_opts& o) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  const double box[6] = {g.xmin, g.xmax, g.ymin, g.ymax, g.zmin, g.zmax};
+  h = fnv1a(h, box, sizeof box);
+  h = fnv_value(h, g.nx);
+  h = fnv_value(h, g.ny);
+  h = fnv_value(h, g.nz);
+  if (g.planes) h = fnv1a(h, g.planes, sizeof(double) * ((size_t)g.nx + g.ny + g.nz + 3));
+  h = fnv_value(h, g.tree_nodes);
+  if (g.tree_nodes > 0 && g.tree_axis && g.tree_split && g.tree_child) {
+    h = fnv1a(h, g.tree_axis, sizeof(int32_t) * g.tree_nodes);
+    h = fnv1a(h, g.tree_split, sizeof(double) * g.tree_nodes);
+    h = fnv1a(h, g.tree_child, sizeof(int32_t) * g.tree_nodes);
+  }
+  h = fnv_value(h, op.n_lambda);
+  h = fnv1a(h, op.kappa, sizeof(double) * op.n_lambda);
+  h = fnv1a(h, op.albedo, sizeof(double) * op.n_lambda);
+  h = fnv1a(h, op.g, sizeof(double) * op.n_lambda);
+  h = fnv_value(h, n_src);
+  for (int s = 0; s < n_src; ++s) {
+    const double v[5] = {src[s].x, src[s].y, src[s].z, src[s].h_r, src[s].h_z};
+    h = fnv_value(h, src[s].kind);
+    h = fnv1a(h, v, sizeof v);
+    if (src[s].kind != MCRT_SRC_CELLS && src[s].lum) h = fnv1a(h, src[s].lum, sizeof(double) * op.n_lambda);
+  }
+  h = fnv_value(h, n_det);
+  for (int d = 0; d < n_det; ++d) {
+    const mcrt_detector& D = det[d];
+    const double v[15] = {D.distance, D.incl_deg, D.azim_deg, D.pa_deg, D.half_x, D.half_y, D.eye[0], D.eye[1],
+                          D.eye[2], D.target[0], D.target[1], D.target[2], D.up[0], D.up[1], D.up[2]};
+    h = fnv1a(h, v, sizeof v);
+    h = fnv_value(h, D.nx);
+    h = fnv_value(h, D.ny);
+    h = fnv_value(h, D.kind);
+  }
+  h = fnv_value(h, o.n_packages);
+  h = fnv_value(h, o.first_package);
+  h = fnv_value(h, o.seed);
+  h = fnv_value(h, o.precision);
+  h = fnv_value(h, o.w_min);
+  h = fnv_value(h, o.max_scatter);
+  h = fnv_value(h, o.flags & (MCRT_PEEL_EMIT | MCRT_PEEL_SCAT | MCRT_SPLIT));
+  return h;
+}
+
+// The header a forward run writes, and the check an adjoint makes of a
+// tape's header against its own arguments (0, or MCRT_EINVAL with a
+// message; *usable = 0 when the forward run overflowed the tape).
+inline TapeHeader tape_header(uint64_t fingerprint, uint64_t n_items, int events, int n_det) {
+  TapeHeader t;
+  std::memset(&t, 0, sizeof t);
+  t.magic = kTapeMagic;
+  t.fingerprint = fingerprint;
+  t.n_items = n_items;
+  t.events = events;
+  t.n_det = n_det;
+  return t;
+}
+
+inline int check_tape(const TapeHeader& t, uint64_t fingerprint, uint64_t n_items, int events, int n_det,
+                      uint64_t have_bytes, uint64_t need_bytes, bool* usable) {
+  *usable = false;
+  if (t.magic != kTapeMagic) return fail(MCRT_EINVAL, "tape: not written by run_photons");
+  if (t.fingerprint != fingerprint || t.n_items != n_items || t.events != events || t.n_det != n_det)
+    return fail(MCRT_EINVAL, "tape: recorded by a run with other arguments");
+  if (have_bytes < need_bytes) return fail(MCRT_EINVAL, "tape_bytes %llu < %llu", (unsigned long long)have_bytes,
+                                           (unsigned long long)need_bytes);
+  *usable = t.overflow == 0;
+  return 0;
+}
+
 }  // namespace host
 }  // namespace mcrt

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <type_traits>
@@ -211,6 +212,23 @@ struct LifeMem {
     J.e = (unsigned short)e;
     J.d = (unsigned char)d;
     P.keys[slot] = key | (sub << 16);  // the sort reads these words only, not the 56-byte rays
+  }
+  // the forward run's tape: T of the leg after event e, C and the image
+  // index of its peel-off into frame d (work item = item0 + slot)
+  __device__ void tape_leg(int slot, int e, double T) const {
+    if (e < P.tape_ev)
+      P.tape[(size_t)e * (1 + P.n_det) * P.tape_n + P.item0 + slot] = T;
+    else
+      atomicOr(P.tape_over, 1u);
+  }
+  __device__ void tape_peel(int slot, int e, int d, double C, long long ii) const {
+    if (e < P.tape_ev) {
+      const size_t item = P.item0 + slot;
+      P.tape[((size_t)e * (1 + P.n_det) + 1 + d) * P.tape_n + item] = C;
+      P.tape_pix[((size_t)e * P.n_det + d) * P.tape_n + item] = (unsigned)ii;
+    } else {
+      atomicOr(P.tape_over, 1u);
+    }
   }
   __device__ void flush_counts(unsigned a, unsigned b, unsigned c, unsigned d) const {
     atomicAdd(P.xstats + 0, (unsigned long long)a);
@@ -586,6 +604,15 @@ struct PeelJobParams {
   unsigned long long n_chunk;
   unsigned long long* ctr;  // counter block of the call
   int batch;
+  // forward run with a tape: C and the image index of each ray (see RunParams)
+  double* tape;
+  unsigned* tape_pix;
+  unsigned* tape_over;
+  int tape_ev;
+  unsigned long long tape_n, item0;
+  // adjoint from a tape: the deposit weight is the ray's own v (no
+  // optical-depth walk ran)
+  int direct_w;
 };
 
 // Density loads for the optical-depth walk; deposits of the deposit walk go
@@ -666,6 +693,15 @@ __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
           out_ii = J.ii;
           out_c = C;
           has = true;
+          if (P.tape) {
+            if (J.e < P.tape_ev) {
+              const size_t item = P.item0 + J.slot;
+              P.tape[((size_t)J.e * (1 + P.n_det) + 1 + J.d) * P.tape_n + item] = C;
+              P.tape_pix[((size_t)J.e * P.n_det + J.d) * P.tape_n + item] = (unsigned)J.ii;
+            } else {
+              atomicOr(P.tape_over, 1u);
+            }
+          }
         } else {
           const double q = P.adj[J.ii] * C;
           if (J.e < P.ev_max)
@@ -746,7 +782,8 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
           done = true;
           break;
         }
-        w = __longlong_as_double((long long)(((unsigned long long)P.whi[qi] << 32) | P.wlo[qi]));
+        w = P.direct_w ? P.jobs[P.perm[qi]].v
+                       : __longlong_as_double((long long)(((unsigned long long)P.whi[qi] << 32) | P.wlo[qi]));
         if (w != 0.0) {
           const PeelJob& J = P.jobs[P.perm[qi]];
           if constexpr (INST) {
@@ -818,6 +855,29 @@ __global__ void k_unbrick(const double* __restrict__ src, double* __restrict__ d
     i[2] = t / G.n[1];
     const int c = brick_addr(G, i);
     dst[q] = slots ? src[l * G.ntal + tally_slot(G, c)] : src[l * G.ncell_pad + c];
+  }
+}
+
+// The adjoint's event scratch of a chunk from the forward run's tape: per
+// package (slot) and kept event, T of the leg after it and q = (dL/dI) C per
+// frame; nothing lies beyond the kept events.  One thread per package: the
+// tape and the scratch are both [event][entry][package], so neighbouring
+// lanes read and write neighbouring words.
+__global__ void k_tape_q(const double* __restrict__ tape, const unsigned* __restrict__ pix,
+                         const double* __restrict__ adj, double* __restrict__ evs, unsigned long long item0,
+                         unsigned long long n_chunk, unsigned long long tape_n, int ev_max, int n_det) {
+  for (unsigned long long slot = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; slot < n_chunk;
+       slot += (unsigned long long)gridDim.x * blockDim.x) {
+    const unsigned long long item = item0 + slot;
+    for (int e = 0; e < ev_max; ++e) {
+      const size_t b = (size_t)e * (1 + n_det);
+      evs[b * n_chunk + slot] = tape[b * tape_n + item];
+      for (int d = 0; d < n_det; ++d) {
+        const double C = tape[(b + 1 + d) * tape_n + item];
+        evs[(b + 1 + d) * n_chunk + slot] = C != 0.0 ? adj[pix[((size_t)e * n_det + d) * tape_n + item]] * C : 0.0;
+      }
+    }
+    evs[(size_t)ev_max * (1 + n_det) * n_chunk + slot] = 0.0;
   }
 }
 
@@ -1187,11 +1247,13 @@ int reset_counters(unsigned long long* ctr, int w, int n, hipStream_t st) {
 // adjoint's deposit walks.
 template <typename R, bool ADJ, int GK, bool INST>
 int walk_peel_jobs(const PeelJobParams& J, hipStream_t st, Spans& sp) {
-  int nblk = 0;
-  if (int e = persistent_grid(k_peeltau<R, ADJ, GK, INST>, 0, &nblk)) return e;
-  if (int e = sp.mark(kSpanPeel, st)) return e;
-  hipLaunchKernelGGL((k_peeltau<R, ADJ, GK, INST>), dim3(nblk), dim3(kBlock), 0, st, J);
-  if (int e = sp.mark(kSpanPeel, st)) return e;
+  if (!J.direct_w) {  // an adjoint from a tape has every ray's weight already: no optical-depth walk
+    int nblk = 0;
+    if (int e = persistent_grid(k_peeltau<R, ADJ, GK, INST>, 0, &nblk)) return e;
+    if (int e = sp.mark(kSpanPeel, st)) return e;
+    hipLaunchKernelGGL((k_peeltau<R, ADJ, GK, INST>), dim3(nblk), dim3(kBlock), 0, st, J);
+    if (int e = sp.mark(kSpanPeel, st)) return e;
+  }
   if (ADJ) {
     int dev = 0, cus = 0, nb = 0;
     HIPCHK(hipGetDevice(&dev));
@@ -1244,6 +1306,13 @@ int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ct
   J.n_chunk = P.n_chunk;
   J.ctr = ctr;
   J.batch = kBatchQueue;
+  J.tape = P.tape;
+  J.tape_pix = P.tape_pix;
+  J.tape_over = P.tape_over;
+  J.tape_ev = P.tape_ev;
+  J.tape_n = P.tape_n;
+  J.item0 = P.item0;
+  J.direct_w = P.dep_jobs;
   if (inst) {  // instruments other than frames: walks that stop at a camera's eye
     switch (P.G.kind) {
       case kGridRect: return walk_peel_jobs<R, ADJ, kGridRect, true>(J, st, sp);
@@ -1353,11 +1422,41 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
                       : (f32 ? life_grid<float, false>(kind, full, opts->launch_blocks, &nblk)
                              : life_grid<double, false>(kind, full, opts->launch_blocks, &nblk)))
     return e;
+  // the adjoint tape (mcrt_opts.tape): the forward run writes it; an
+  // adjoint with a usable tape fills its event scratch from it and replays
+  // each package once
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const uint64_t tape_need = peel ? host::tape_bytes(optics, n_det, opts) : 0;
+  const int tape_ev = tape_need ? (int)host::tape_events(*optics, *opts) : 0;
+  bool tape_fwd = false, tape_adj = false;
+  uint64_t fprint = 0;
+  if (opts->tape) {
+    if (!tape_need) return fail(MCRT_EINVAL, "tape given, but this run cannot keep one (mcrt_tape_bytes is 0)");
+    fprint = host::tape_fingerprint(*grid, *optics, n_src, sources, n_det, detectors, *opts);
+    if (!adjoint) {
+      if (opts->tape_bytes < tape_need)
+        return fail(MCRT_EINVAL, "tape_bytes %llu < %llu", (unsigned long long)opts->tape_bytes,
+                    (unsigned long long)tape_need);
+      tape_fwd = true;
+    } else {
+      host::TapeHeader hdr;
+      HIPCHK(hipMemcpyAsync(&hdr, opts->tape, sizeof hdr, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      bool usable = false;
+      if (int e = host::check_tape(hdr, fprint, P.n_items, tape_ev, n_det, opts->tape_bytes, tape_need, &usable))
+        return e;
+      tape_adj = usable && !adj_abs_dev;
+    }
+  }
+  const unsigned char* const tape_base = static_cast<const unsigned char*>(opts->tape);
+  const size_t tape_pix_off = host::kTapeHeader + align256(sizeof(double) * (size_t)P.n_items * tape_ev * (1 + n_det));
   // packages run in equal chunks: the adjoint's event scratch holds, per
-  // package, T and q per frame for kEventsKept events plus the sum of q
-  // beyond; the peel-ray queue by default 8 rays per package and frame
+  // package, T and q per frame for ev_max events (the tape's events, else
+  // kEventsKept) plus the sum of q beyond; the peel-ray queue by default 8
+  // rays per package and frame
+  const int ev_max = tape_adj ? tape_ev : kEventsKept;
   const int ev_k = 1 + n_det + (adjoint && adj_abs_dev ? 1 : 0);  // T, q per frame, then B of the path
-  const size_t per_item = sizeof(double) * ((size_t)kEventsKept * ev_k + 1 + (optg ? 4 : 0));
+  const size_t per_item = sizeof(double) * ((size_t)ev_max * ev_k + 1 + (optg ? 4 : 0));
   const bool queued = peel && opts->peel_queue != -1;
   size_t free_b = 0, total_b = 0;
   HIPCHK(hipMemGetInfo(&free_b, &total_b));
@@ -1372,7 +1471,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const unsigned long long n_chunks = (P.n_items + most - 1) / most;
   const unsigned long long chunk = (P.n_items + n_chunks - 1) / n_chunks;
   // the adjoint's event scratch, then (optics gradients) the pass-B sums
-  const size_t n_evs = adjoint ? (size_t)chunk * ((size_t)kEventsKept * ev_k + 1 + (optg ? 4 : 0)) : 0;
+  const size_t n_evs = adjoint ? (size_t)chunk * ((size_t)ev_max * ev_k + 1 + (optg ? 4 : 0)) : 0;
   const long long n_tally = adjoint ? (long long)P.G.ncell_pad : (P.absorbed ? (long long)nl * P.G.ntal : 0);
   const size_t off_lam = 0;
   const size_t off_det = align256(sizeof(LamDev) * nl);
@@ -1396,7 +1495,6 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const bool aabs = adjoint && adj_abs_dev;  // a loss on the absorbed tally: its adjoint, bricked
   const size_t bytes = off_aab + (aabs ? align256(sizeof(double) * (size_t)nl * P.G.ncell_pad) : 0);
 
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
   DeviceBlock blk;
   blk.st = st;
   HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&blk.ptr), bytes, st));
@@ -1424,8 +1522,22 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     P.absorbed = tally;
   if (adjoint) {
     P.evs = reinterpret_cast<double*>(blk.ptr + off_evs);
-    P.ev_max = kEventsKept;
+    P.ev_max = ev_max;
     P.ev_k = ev_k;
+  }
+  if (tape_fwd) {  // header with the run's fingerprint, then every T, C and image index 0
+    unsigned char* t = static_cast<unsigned char*>(opts->tape);
+    const host::TapeHeader hdr = host::tape_header(fprint, P.n_items, tape_ev, n_det);
+    HIPCHK(hipMemcpyAsync(t, &hdr, sizeof hdr, hipMemcpyHostToDevice, st));
+    const long long words = (long long)((tape_need - host::kTapeHeader) / 4);
+    hipLaunchKernelGGL(k_zero_u32, dim3(stream_blocks(words)), dim3(kBlock), 0, st,
+                       reinterpret_cast<unsigned*>(t + host::kTapeHeader), words);
+    HIPCHK(hipGetLastError());
+    P.tape = reinterpret_cast<double*>(t + host::kTapeHeader);
+    P.tape_pix = reinterpret_cast<unsigned*>(t + tape_pix_off);
+    P.tape_over = reinterpret_cast<unsigned*>(t + offsetof(host::TapeHeader, overflow));
+    P.tape_ev = tape_ev;
+    P.tape_n = P.n_items;
   }
   double* const lums = optg ? reinterpret_cast<double*>(blk.ptr + off_lums) : nullptr;
   if (aabs) {
@@ -1498,22 +1610,39 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
       P.item0 = c0;
       P.n_chunk = std::min(chunk, P.n_items - c0);
-      if (int e = zero_fill(P.evs, (long long)(P.n_chunk * ((unsigned long long)kEventsKept * ev_k + 1 + (optg ? 4 : 0))),
-                            st))
-        return e;
-      P.gpart = optg ? P.evs + P.n_chunk * ((unsigned long long)kEventsKept * ev_k + 1) : nullptr;
-      if (int e = reset_counters(ctr, 0, 1, st)) return e;
-      if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
-      if (int e = reset_counters(ctr, kDepCounter, 1, st)) return e;
-      P.split = 1;  // pass A
-      if (opts->event_batch == 0) P.batch = kBatchPassA;
-      if (int e = life_launch(true)) return e;
-      if (P.jobs)
-        if (int e = queue_phase(true)) return e;
-      if (int e = reset_counters(ctr, 0, 1, st)) return e;
-      P.split = 2;  // pass B
-      if (opts->event_batch == 0) P.batch = kBatchPassB;
-      if (int e = life_launch(true)) return e;
+      P.gpart = optg ? P.evs + P.n_chunk * ((unsigned long long)ev_max * ev_k + 1) : nullptr;
+      if (tape_adj) {  // the scratch from the tape, then pass B alone, then the deposit walks
+        if (int e = zero_fill(P.gpart, optg ? 4 * (long long)P.n_chunk : 0, st)) return e;
+        hipLaunchKernelGGL(k_tape_q, dim3(stream_blocks((long long)P.n_chunk)), dim3(kBlock), 0, st,
+                           reinterpret_cast<const double*>(tape_base + host::kTapeHeader),
+                           reinterpret_cast<const unsigned*>(tape_base + tape_pix_off), P.adj, P.evs, P.item0,
+                           P.n_chunk, (unsigned long long)P.n_items, ev_max, n_det);
+        HIPCHK(hipGetLastError());
+        if (int e = reset_counters(ctr, 0, 1, st)) return e;
+        if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
+        if (int e = reset_counters(ctr, kDepCounter, 1, st)) return e;
+        P.split = 2;
+        P.dep_jobs = 1;
+        if (opts->event_batch == 0) P.batch = kBatchPassB;
+        if (int e = life_launch(true)) return e;
+        if (P.jobs)
+          if (int e = queue_phase(true)) return e;
+      } else {  // pass A, the queue's walks, pass B
+        const long long n_scr = (long long)(P.n_chunk * ((unsigned long long)ev_max * ev_k + 1 + (optg ? 4 : 0)));
+        if (int e = zero_fill(P.evs, n_scr, st)) return e;
+        if (int e = reset_counters(ctr, 0, 1, st)) return e;
+        if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
+        if (int e = reset_counters(ctr, kDepCounter, 1, st)) return e;
+        P.split = 1;  // pass A
+        if (opts->event_batch == 0) P.batch = kBatchPassA;
+        if (int e = life_launch(true)) return e;
+        if (P.jobs)
+          if (int e = queue_phase(true)) return e;
+        if (int e = reset_counters(ctr, 0, 1, st)) return e;
+        P.split = 2;  // pass B
+        if (opts->event_batch == 0) P.batch = kBatchPassB;
+        if (int e = life_launch(true)) return e;
+      }
       if (optg) {
         const unsigned nb = (unsigned)((P.item0 + P.n_chunk - 1) / P.n_pkg - P.item0 / P.n_pkg + 1);
         hipLaunchKernelGGL(k_grad_optics, dim3(nb), dim3(kOptThreads), 0, st, P.gpart, P.item0, P.n_chunk, P.n_pkg,
@@ -1667,6 +1796,14 @@ int trace_impl(const mcrt_grid* grid, const void* rho_dev, double kappa, int pre
 extern "C" {
 
 int mcrt_abi_version(void) { return MCRT_ABI_VERSION; }
+
+uint64_t mcrt_tape_bytes(const mcrt_optics* optics, int n_det, const mcrt_opts* opts) {
+  try {
+    return mcrt::host::tape_bytes(optics, n_det, opts);
+  } catch (...) {
+    return 0;
+  }
+}
 
 const char* mcrt_last_error(void) { return mcrt::host::last_error().c_str(); }
 

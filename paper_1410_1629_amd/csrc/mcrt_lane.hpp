@@ -124,6 +124,19 @@ struct RunParams {
   // adjoint of a loss on the absorbed tally: dL/dA, bricked [n_lambda][ncell_pad]
   // (null: none); its path sums B sit in the event scratch's last entry
   const double* adj_abs;
+  // forward run with an adjoint tape (null: none): T of the leg after event
+  // e and C per frame, [tape_ev][1 + n_det][tape_n], and the image index of
+  // each C, [tape_ev][n_det][tape_n], for the call's work items; tape_over
+  // is set when a package has more events than the tape keeps
+  double* tape;
+  unsigned* tape_pix;
+  unsigned* tape_over;
+  int tape_ev;
+  unsigned long long tape_n;
+  // adjoint from a tape: pass B finds every q and T in the event scratch
+  // (filled from the tape) and queues the deposit walks of the event's peel
+  // rays with q != 0 (walked here when the queue is full)
+  int dep_jobs;
 };
 
 // The life-cycle walks keep their times in FP64 whatever R is (see Ray).
@@ -235,7 +248,7 @@ MCRT_HD void event_start(Lane<R>& L, const RunParams& P, Mem& M) {
       L.Ge += q;
       if (Mem::kInst && P.gpart && q != 0.0) optics_add(L, M, d, q);
     }
-    L.det = P.n_det;  // no peel-off walks: PEEL_NEXT goes straight on
+    if (!P.dep_jobs) L.det = P.n_det;  // no peel-off walks: PEEL_NEXT goes straight on
   }
 }
 
@@ -285,6 +298,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
       L.phase = PH_PEEL_NEXT;
       if (!ADJ) {
         M.add_image(ii, C);
+        if (P.tape) M.tape_peel(L.slot, L.n, L.det, C, ii);
         ++L.det;
       } else {
         const double ac = M.adj(ii) * C;
@@ -330,6 +344,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
       } else {
         L.T = (double)L.ry.tau;
         if (ADJ && L.pass == 0 && L.n < P.ev_max) M.ev_store(L.slot, L.n, 0, L.T);
+        if (!ADJ && P.tape) M.tape_leg(L.slot, L.n, L.T);
       }
       if (L.T == 0.0) {  // nothing to interact with: the package leaves
         if (L.pass == 0) L.s_esc += L.W;
@@ -384,8 +399,28 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
 
     // -- the next frame whose pixel the event projects into
     if (L.phase == PH_PEEL_NEXT && !want) {
+      bool dep_inline = false;  // pass B from a tape: a deposit walk the full queue could not take
       while (L.det < P.n_det) {
         const DetDev& D = M.det(L.det);
+        if (ADJ && P.dep_jobs && L.pass == 1 && L.n < P.ev_max) {  // the event's nonzero q: deposit walks
+          const double q = M.ev_load(L.slot, L.n, 1 + L.det);
+          if (q != 0.0) {
+            L.pix = frame_pixel<Mem::kInst>(D, L.r);
+            const unsigned long long slot = P.jobs ? M.job_slot() : P.job_cap;
+            if (slot >= P.job_cap) {
+              L.fac = -q * L.kap;
+              dep_inline = true;
+              break;
+            }
+            const int comp = ((P.flags & kFlagSplit) && !L.is_emit) ? 1 : 0;
+            const long long ii = ((long long)comp * P.n_lambda + L.lam) * P.pix_lambda + D.off + L.pix;
+            const int kp = key_pixel<Mem::kInst>(D, L.r, L.pix);
+            M.store_job(slot, L.r, -q * L.kap, ii, tile_key(D, kp), tile_sub(D, kp), (unsigned)L.slot,
+                        L.n < kEventSat ? L.n : kEventSat, L.det, (unsigned)L.lam);
+          }
+          ++L.det;
+          continue;
+        }
         L.pix = frame_pixel<Mem::kInst>(D, L.r);
         if (L.pix >= 0) {
           if (!P.jobs || L.pass != 0) break;
@@ -408,8 +443,8 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
       }
       if (L.det < P.n_det) {
         want = to_det = true;
-        L.mode = M_PEEL;
-        L.phase = PH_PEEL_END;
+        L.mode = dep_inline ? M_PEEL_DEP : M_PEEL;
+        L.phase = dep_inline ? PH_PEEL_DEP_END : PH_PEEL_END;
       } else {
         if (ADJ) event_done(L, P, M);
         L.phase = L.is_emit ? PH_PATH_START : PH_TERM;

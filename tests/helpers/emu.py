@@ -75,7 +75,19 @@ class Emu:
     def _p(a):
         return None if a is None else a.ctypes.data_as(C.c_void_p)
 
-    def run(self, prob, wave=WAVE, **overrides):
+    @staticmethod
+    def _tape(prob, tape, overrides):
+        """A host byte array as the run's tape (the harness keeps it in host memory)."""
+        if tape is None:
+            return overrides
+        return dict(overrides, tape=tape.ctypes.data, tape_bytes=tape.size)
+
+    def new_tape(self, prob, **overrides):
+        n = B.tape_bytes(prob, **overrides)
+        return np.zeros(n, dtype=np.uint8) if n else None
+
+    def run(self, prob, wave=WAVE, tape=None, **overrides):
+        overrides = self._tape(prob, tape, overrides)
         pr = B._Problem(prob, cells_on_device=False, **overrides)
         rho = self._rho(prob)
         images = np.zeros(B.image_shape(prob))
@@ -96,10 +108,11 @@ class Emu:
         """Packages per adjoint chunk (0: the library's choice)."""
         self.lib.emu_set_chunk_items(int(n))
 
-    def grad(self, prob, adj, wave=WAVE, optics=False, adj_absorbed=None, **overrides):
+    def grad(self, prob, adj, wave=WAVE, optics=False, adj_absorbed=None, tape=None, **overrides):
         """(dL/drho, stats), or with optics=True (dL/drho, stats, {"albedo",
         "g", "lum"}); adj_absorbed [n_lambda][ncell] adds a loss term on the
         absorbed tally."""
+        overrides = self._tape(prob, tape, overrides)
         pr = B._Problem(prob, cells_on_device=False, **overrides)
         rho = self._rho(prob)
         adj = np.ascontiguousarray(adj, dtype=np.float64).reshape(-1)

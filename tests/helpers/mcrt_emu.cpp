@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
+#include <cstring>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -245,6 +247,35 @@ struct HostLifeMem {
     J.d = (unsigned char)d;
     J.sub = (unsigned char)sub;
   }
+  // the forward run's tape (host memory here): every entry bounds-checked
+  double* tape = nullptr;
+  unsigned* tape_pix = nullptr;
+  unsigned* tape_over = nullptr;
+  int tape_ev = 0;
+  unsigned long long tape_n = 0, item0 = 0;
+  void tape_leg(int slot, int e, double T) {
+    EMU_CHECK(tape != nullptr, "tape write without a tape", e, 0);
+    EMU_CHECK(slot >= 0 && slot < n_chunk, "tape package", slot, n_chunk);
+    if (e >= tape_ev) {
+      *tape_over = 1u;
+      return;
+    }
+    tape[(size_t)e * (1 + pr.P.n_det) * tape_n + item0 + slot] = T;
+  }
+  void tape_peel(int slot, int e, int d, double C, long long ii) {
+    EMU_CHECK(tape != nullptr, "tape write without a tape", e, 0);
+    EMU_CHECK(slot >= 0 && slot < n_chunk, "tape package", slot, n_chunk);
+    EMU_CHECK(d >= 0 && d < pr.P.n_det, "tape frame", d, pr.P.n_det);
+    EMU_CHECK(ii >= 0 && ii < n_images, "tape image index", ii, n_images);
+    if (e >= tape_ev) {
+      *tape_over = 1u;
+      return;
+    }
+    const size_t item = item0 + slot;
+    EMU_CHECK(item < tape_n, "tape item", item, tape_n);
+    tape[((size_t)e * (1 + pr.P.n_det) + 1 + d) * tape_n + item] = C;
+    tape_pix[((size_t)e * pr.P.n_det + d) * tape_n + item] = (unsigned)ii;
+  }
   void flush_counts(unsigned a, unsigned b, unsigned c, unsigned d) {
     xs[0] += a;
     xs[1] += b;
@@ -304,7 +335,7 @@ struct HostBundleMem {
 template <typename R, bool ADJ, int GK, bool INST>
 unsigned long long emu_peel_jobs(HostLifeMem<R, GK, INST>& M, const RunParams& P, std::vector<PeelJob>& jobs,
                                  unsigned long long n_jobs, std::vector<double>& grad, unsigned long long& deps,
-                                 long long cap_steps) {
+                                 long long cap_steps, bool direct = false) {
   const long long n_keys = M.n_keys;
   const int nb = host::kSortBlocks;
   const unsigned long long per = (n_jobs + nb - 1) / nb;
@@ -364,29 +395,35 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, GK, INST>& M, const RunParams& P
     while (d + 1 < P.n_det && (unsigned)M.det(d + 1).key_off <= J.key) ++d;
     EMU_CHECK(d == J.d, "job frame against its key", J.d, P.n_det);
     Ray<R> ry;
-    {
-      double kd[3], inv_d2, tmax;
-      peel_geom<HostLifeMem<R, GK, INST>>(M.det(J.d), J.r, kd, inv_d2, tmax);
-      ray_begin<R, GK>(ry, P.G, J.r, kd, tmax);
-    }
-    const R kap = (R)M.lam((int)J.lam).kappa;
     long long steps = 0;
-    while (ry.active) {
-      nx += tau_step<R, HostLifeMem<R, GK, INST>, INST>(ry, P.G, kap, M);
-      if (++steps > cap_steps) throw Violation("a peel-job walk exceeded the grid's crossing bound");
+    double w = J.v;  // an adjoint from a tape: the ray's deposit weight, no optical-depth walk
+    if (!direct) {
+      {
+        double kd[3], inv_d2, tmax;
+        peel_geom<HostLifeMem<R, GK, INST>>(M.det(J.d), J.r, kd, inv_d2, tmax);
+        ray_begin<R, GK>(ry, P.G, J.r, kd, tmax);
+      }
+      const R kap = (R)M.lam((int)J.lam).kappa;
+      while (ry.active) {
+        nx += tau_step<R, HostLifeMem<R, GK, INST>, INST>(ry, P.G, kap, M);
+        if (++steps > cap_steps) throw Violation("a peel-job walk exceeded the grid's crossing bound");
+      }
+      const double C = J.v * exp(-(double)ry.tau);
+      if (!ADJ) {
+        M.add_image(J.ii, C);
+        if (M.tape) M.tape_peel((int)J.slot, J.e, J.d, C, J.ii);
+        continue;
+      }
+      const double q = M.adj(J.ii) * C;
+      if (J.e < P.ev_max)
+        M.ev_store((int)J.slot, J.e, 1 + J.d, q);
+      else
+        M.ev_add_beyond((int)J.slot, q);
+      if (q == 0.0) continue;
+      w = -q * M.lam((int)J.lam).kappa;
+    } else {
+      EMU_CHECK(ADJ && w != 0.0, "a deposit job from a tape without a weight", qi, n_valid);
     }
-    const double C = J.v * exp(-(double)ry.tau);
-    if (!ADJ) {
-      M.add_image(J.ii, C);
-      continue;
-    }
-    const double q = M.adj(J.ii) * C;
-    if (J.e < P.ev_max)
-      M.ev_store((int)J.slot, J.e, 1 + J.d, q);
-    else
-      M.ev_add_beyond((int)J.slot, q);
-    if (q == 0.0) continue;
-    const double w = -q * M.lam((int)J.lam).kappa;
     {
       double kd[3], inv_d2, tmax;
       peel_geom<HostLifeMem<R, GK, INST>>(M.det(J.d), J.r, kd, inv_d2, tmax);
@@ -488,9 +525,40 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
     M.adj_abs_b = &aab;
     P.adj_abs = aab.data();  // only tested against null by the lanes; the loads go through M
   }
+  // the adjoint tape: the forward run writes it (host memory here), an
+  // adjoint with a usable one fills its scratch from it and replays once
+  const uint64_t tape_need = peel ? host::tape_bytes(optics, n_det, opts) : 0;
+  const int tape_ev = tape_need ? (int)host::tape_events(*optics, *opts) : 0;
+  bool tape_adj = false;
+  unsigned char* const tape_base = static_cast<unsigned char*>(opts->tape);
+  const size_t tape_pix_off =
+      host::kTapeHeader + ((sizeof(double) * (size_t)P.n_items * tape_ev * (1 + n_det) + 255) & ~size_t(255));
+  if (opts->tape) {
+    if (!tape_need) return host::fail(MCRT_EINVAL, "tape given, but this run cannot keep one (mcrt_tape_bytes is 0)");
+    const uint64_t fp = host::tape_fingerprint(*grid, *optics, n_src, sources, n_det, detectors, *opts);
+    if (!ADJ) {
+      if (opts->tape_bytes < tape_need) return host::fail(MCRT_EINVAL, "tape_bytes too small");
+      const host::TapeHeader hdr = host::tape_header(fp, P.n_items, tape_ev, n_det);
+      std::memset(tape_base, 0, tape_need);
+      std::memcpy(tape_base, &hdr, sizeof hdr);
+      M.tape = reinterpret_cast<double*>(tape_base + host::kTapeHeader);
+      M.tape_pix = reinterpret_cast<unsigned*>(tape_base + tape_pix_off);
+      M.tape_over = reinterpret_cast<unsigned*>(tape_base + offsetof(host::TapeHeader, overflow));
+      M.tape_ev = tape_ev;
+      M.tape_n = P.n_items;
+      P.tape = M.tape;  // only tested against null by the lanes; the writes go through M
+    } else {
+      host::TapeHeader hdr;
+      std::memcpy(&hdr, tape_base, sizeof hdr);
+      bool usable = false;
+      if (int e = host::check_tape(hdr, fp, P.n_items, tape_ev, n_det, opts->tape_bytes, tape_need, &usable)) return e;
+      tape_adj = usable && !adj_abs;
+    }
+  }
   if (ADJ) {
-    P.ev_max = g_events_kept;
+    P.ev_max = tape_adj ? tape_ev : g_events_kept;
     P.ev_k = 1 + P.n_det + (adj_abs ? 1 : 0);
+    P.dep_jobs = tape_adj ? 1 : 0;
   }
   const size_t per_item = sizeof(double) * ((size_t)P.ev_max * P.ev_k + 1);
   unsigned long long chunk =
@@ -520,8 +588,8 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   M.ev_k = P.ev_k;
   auto queue_phase = [&]() {
     unsigned long long deps = 0;
-    const unsigned long long nx =
-        emu_peel_jobs<R, ADJ, GK, INST>(M, P, jobs, std::min(M.job_next, M.job_cap), grad_b, deps, cap);
+    const unsigned long long nx = emu_peel_jobs<R, ADJ, GK, INST>(M, P, jobs, std::min(M.job_next, M.job_cap),
+                                                                  grad_b, deps, cap, tape_adj);
     M.x_queue += nx;
     M.d_queue += deps;
   };
@@ -529,6 +597,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
     P.item0 = c0;
     P.n_chunk = std::min(chunk, P.n_items - c0);
     M.n_chunk = (int)P.n_chunk;
+    M.item0 = c0;
     M.job_next = 0;
     if (!ADJ) {
       launch(0);
@@ -542,9 +611,28 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
       M.gpart = &gpart;
       P.gpart = gpart.data();  // only tested against null by the lanes; the stores go through M
     }
-    launch(1);  // pass A
-    if (P.jobs) queue_phase();
-    launch(2);  // pass B
+    if (tape_adj) {  // the scratch from the tape (the library's k_tape_q), pass B, the deposit walks
+      const double* tp = reinterpret_cast<const double*>(tape_base + host::kTapeHeader);
+      const unsigned* px = reinterpret_cast<const unsigned*>(tape_base + tape_pix_off);
+      const int nd = P.n_det;
+      for (unsigned long long slot = 0; slot < P.n_chunk; ++slot) {
+        const unsigned long long item = P.item0 + slot;
+        for (int e = 0; e < P.ev_max; ++e) {
+          const size_t b = (size_t)e * (1 + nd);
+          M.ev_store((int)slot, e, 0, tp[b * P.n_items + item]);
+          for (int d = 0; d < nd; ++d) {
+            const double C = tp[(b + 1 + d) * P.n_items + item];
+            M.ev_store((int)slot, e, 1 + d, C != 0.0 ? M.adj(px[((size_t)e * nd + d) * P.n_items + item]) * C : 0.0);
+          }
+        }
+      }
+      launch(2);  // pass B, queueing the deposit walks
+      if (P.jobs) queue_phase();
+    } else {
+      launch(1);  // pass A
+      if (P.jobs) queue_phase();
+      launch(2);  // pass B
+    }
     if (gopt) {  // per wavelength of the chunk: sums over its packages, then the gradients
       const unsigned long long nc = P.n_chunk;
       for (unsigned long long l = P.item0 / P.n_pkg; l <= (P.item0 + nc - 1) / P.n_pkg; ++l) {
@@ -583,7 +671,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
     stats->x_queue = M.x_queue;
     stats->life_ms = stats->queue_ms = 0.0;
     stats->d_queue = M.d_queue;
-    stats->life_launches = (ADJ ? 2 : 1) * ((P.n_items + chunk - 1) / chunk);
+    stats->life_launches = (ADJ && !tape_adj ? 2 : 1) * ((P.n_items + chunk - 1) / chunk);
     stats->sort_ms = stats->peel_ms = stats->dep_ms = 0.0;
   }
   return 0;
