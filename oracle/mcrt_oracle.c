@@ -658,7 +658,7 @@ double oracle_forced_tau(double T, double u) { return -log1p(u * expm1(-T)); }
 /* The simulation. */
 
 enum { FLAG_PEEL_EMIT = 1, FLAG_PEEL_SCAT = 2, FLAG_ABSORB = 4, FLAG_SPLIT = 8 };
-enum { MODE_FORWARD = 0, MODE_GRAD = 1, MODE_REWEIGHT = 2 };
+enum { MODE_FORWARD = 0, MODE_GRAD = 1, MODE_REWEIGHT = 2, MODE_ATTACHED = 3 };
 enum { ST_EMITTED, ST_ABSORBED, ST_ESCAPED, ST_TRUNCATED, ST_XPATH, ST_XLOCATE, ST_XPEEL, ST_EVENTS, ST_PACKAGES, ST_N };
 
 #define MAX_DET 16
@@ -698,8 +698,22 @@ typedef struct {
     double a_c;   /* dL/dI at the pixel times the contribution */
     double dlng;  /* d ln(contribution) / dg: scores of the sampled directions and the peel phase */
     int absorbed; /* 1: the absorbed-tally term of the path after the event (images' optics gradients skip it) */
+    int det;      /* the instrument it goes to */
     size_t beg, end; /* peel segments inside the peel buffer */
 } contrib_t;
+
+/* One event of a package as the attached derivative needs it (ATTACHED
+ * mode): the position and the weight after the event and, when a path leg
+ * follows it, the leg's direction k, optical depth T to the boundary,
+ * forced-scattering depth tau_s, length s to the next event, the density of
+ * the cell where that event lies and the leg's full path (segments up to
+ * the boundary, in the legs buffer). */
+typedef struct {
+    double r[3], w;
+    int leg;
+    double k[3], T, tau_s, s, rho_s;
+    size_t beg, end;
+} att_ev_t;
 
 typedef struct {
     double *images;   /* full image array */
@@ -714,6 +728,8 @@ typedef struct {
     int nleg_cap;
     contrib_t *con;
     int ncon, ncon_cap;
+    att_ev_t *aev; /* ATTACHED: the package's events */
+    int naev, naev_cap;
 } accum_t;
 
 static size_t image_index(const problem_t *P, int comp, int l, int d, int64_t pix)
@@ -776,12 +792,13 @@ static void peel_event(const problem_t *P, accum_t *A, int l, int event, const d
             double tau = seg_tau(&A->peel, P->rho, kappa);
             double c = w * phase * exp(-tau) * inv_d2;
             A->images[ii] += c;
-            if (P->mode == MODE_GRAD) {
+            if (P->mode == MODE_GRAD || P->mode == MODE_ATTACHED) {
                 contrib_t *C = grad_new_contrib(A);
                 C->event = event;
                 C->a_c = P->adj[ii] * c;
                 C->dlng = k_in ? score + hg_dlng(g, k_in[0] * kd[0] + k_in[1] * kd[1] + k_in[2] * kd[2]) : 0.0;
                 C->absorbed = 0;
+                C->det = d;
                 C->beg = A->gpeel.n;
                 for (size_t j = 0; j < A->peel.n; j++)
                     sb_push(&A->gpeel, A->peel.v[j].cell, A->peel.v[j].t0, A->peel.v[j].t1);
@@ -829,6 +846,129 @@ static void grad_flush_package(const problem_t *P, accum_t *A, int l, int src)
         for (size_t j = C->beg; j < C->end; j++) {
             const seg_t *s = &A->gpeel.v[j];
             A->grad[s->cell] -= C->a_c * kappa * (s->t1 - s->t0);
+        }
+    }
+}
+
+/* Appends an event at r with weight w to the package's record (ATTACHED). */
+static void att_push(accum_t *A, const double r[3], double w)
+{
+    if (A->naev == A->naev_cap) {
+        A->naev_cap = A->naev_cap ? 2 * A->naev_cap : 64;
+        A->aev = (att_ev_t *)realloc(A->aev, A->naev_cap * sizeof(att_ev_t));
+    }
+    att_ev_t *E = &A->aev[A->naev++];
+    memset(E, 0, sizeof *E);
+    for (int a = 0; a < 3; a++) E->r[a] = r[a];
+    E->w = w;
+}
+
+/* Derivative of a ray's optical depth with respect to its origin o, for the
+ * segment list b[beg, end) of the ray o + t k (contiguous, up to the grid's
+ * boundary).  Moving the origin by dr moves the crossing of a plane normal
+ * to axis a by dt = -dr_a / k_a, and the optical depth changes there by
+ * kappa (rho_before - rho_after) dt (after the last segment: rho_after = 0,
+ * outside the grid).  The plane of each crossing is the face through which
+ * the ray leaves the cell before it: the axis with the earliest exit time
+ * from that cell's box (on an edge or corner, where the derivative does not
+ * exist, the lowest such axis).  Each crossing's term is weighted by
+ * w_before when it lies before t_cut, else by w_after, and added to out.
+ * Check: finite differences of whole runs with the random numbers held
+ * fixed (the attached derivative it is part of). */
+static void tau_grad_origin(const grid_t *G, const segbuf *b, size_t beg, size_t end, const double o[3],
+                            const double k[3], const double *rho, double kappa, double t_cut, double w_before,
+                            double w_after, double out[3])
+{
+    for (size_t j = beg; j < end; j++) {
+        const seg_t *s = &b->v[j];
+        double after = j + 1 < end ? rho[b->v[j + 1].cell] : 0.0;
+        double jump = kappa * (rho[s->cell] - after);
+        if (jump == 0.0) continue;
+        double lo[3], hi[3];
+        cell_bounds(G, s->cell, lo, hi);
+        int ax = -1;
+        double tm = INFINITY;
+        for (int a = 0; a < 3; a++) {
+            if (k[a] == 0.0) continue;
+            double te = ((k[a] > 0.0 ? hi[a] : lo[a]) - o[a]) / k[a];
+            if (te < tm) {
+                tm = te;
+                ax = a;
+            }
+        }
+        if (ax < 0) continue;
+        out[ax] -= (s->t1 < t_cut ? w_before : w_after) * jump / k[ax];
+    }
+}
+
+/* Gradient of the image loss for one package by the attached (pathwise)
+ * derivative: the random numbers are held fixed and the package's events
+ * move with the densities.  The directions do not depend on the densities
+ * (each is the previous one turned by angles drawn from the random
+ * numbers); the positions do, through the forced-scattering step.  With
+ * event n at r_n, weight w_n and the leg after it along k_n of optical
+ * depth T_n to the boundary:
+ *   tau_s,n = -ln(1 - u (1 - e^-T_n))   (fixed u),
+ *   s_n solves tau(r_n, k_n, s_n) = tau_s,n,   r_{n+1} = r_n + s_n k_n,
+ *   w_{n+1} = w_n albedo (1 - e^-T_n),
+ * and a peel-off contribution of event n is C = w_n Phi e^-tau_peel(r_n) / D^2
+ * (frames and SED instruments: the direction and distance of the observer
+ * do not depend on r_n).  The loss is the sum of a C over the package's
+ * contributions (a = dL/dI of the pixel the event projects into; pixel
+ * choices, the escape test T = 0 and the termination test are held fixed:
+ * the derivative is that of the per-package estimator where it is smooth).
+ * Reverse accumulation over the events, from the last one back, with the
+ * adjoints lbar of ln w_n and rbar of r_n:
+ *   each contribution q = a C of event n: lbar += q, d/drho -= q kappa l
+ *     along its peel ray, rbar -= q dtau_peel/dr_n;
+ *   the leg from event n-1 to event n: sbar = rbar . k,
+ *     taubar = sbar / (kappa rho_s)          (ds/dtau_s = 1/(kappa rho_s)),
+ *     Tbar = taubar dtau_s/dT + lbar dln(1 - e^-T)/dT
+ *          = taubar e^(tau_s - T) (1 - e^-tau_s)/(1 - e^-T) + lbar e^-T/(1 - e^-T),
+ *     d/drho_m += Tbar kappa l_m(leg to the boundary) - (sbar / rho_s) l_m(leg up to s),
+ *     rbar of r_{n-1} = rbar + Tbar dT/dr - taubar dtau(r, k, s)/dr (s fixed);
+ *   lbar carries over unchanged (ln w_n = ln w_{n-1} + ln albedo + ln(1 - e^-T)),
+ *   and the emission point does not move.
+ * Check: finite differences of whole runs at rho (1 +- h v) with the same
+ * random numbers, for instruments without pixel edges (SED) and
+ * termination by count; the detached gradient in expectation; the
+ * detached gradient exactly for a medium that does not scatter. */
+static void attached_flush_package(const problem_t *P, accum_t *A, int l)
+{
+    const grid_t *G = &P->G;
+    const double kappa = P->kappa[l];
+    double lbar = 0.0, rbar[3] = {0.0, 0.0, 0.0};
+    for (int n = A->naev - 1; n >= 0; n--) {
+        const att_ev_t *E = &A->aev[n];
+        for (int q = 0; q < A->ncon; q++) {
+            const contrib_t *C = &A->con[q];
+            if (C->event != n || C->a_c == 0.0) continue;
+            lbar += C->a_c;
+            for (size_t j = C->beg; j < C->end; j++) {
+                const seg_t *s = &A->gpeel.v[j];
+                A->grad[s->cell] -= C->a_c * kappa * (s->t1 - s->t0);
+            }
+            if (n > 0) {
+                double d[3] = {0.0, 0.0, 0.0};
+                tau_grad_origin(G, &A->gpeel, C->beg, C->end, E->r, P->det[C->det].kd, P->rho, kappa, INFINITY, 1.0,
+                                1.0, d);
+                for (int a = 0; a < 3; a++) rbar[a] -= C->a_c * d[a];
+            }
+        }
+        if (n == 0) break;
+        const att_ev_t *L = &A->aev[n - 1];
+        double sbar = rbar[0] * L->k[0] + rbar[1] * L->k[1] + rbar[2] * L->k[2];
+        double taubar = sbar / (kappa * L->rho_s);
+        double Tbar = (taubar * exp(L->tau_s - L->T) * -expm1(-L->tau_s) + lbar * exp(-L->T)) / -expm1(-L->T);
+        for (size_t j = L->beg; j < L->end; j++) {
+            const seg_t *s = &A->legs.v[j];
+            double part = s->t0 < L->s ? fmin(s->t1, L->s) - s->t0 : 0.0;
+            A->grad[s->cell] += Tbar * kappa * (s->t1 - s->t0) - sbar / L->rho_s * part;
+        }
+        if (n - 1 > 0) {
+            double d[3] = {0.0, 0.0, 0.0};
+            tau_grad_origin(G, &A->legs, L->beg, L->end, L->r, L->k, P->rho, kappa, L->s, Tbar - taubar, Tbar, d);
+            for (int a = 0; a < 3; a++) rbar[a] += d[a];
         }
     }
 }
@@ -893,11 +1033,15 @@ static void run_package(const problem_t *P, accum_t *A, uint64_t p, int l)
     A->stats[ST_EMITTED] += w0;
     A->stats[ST_PACKAGES] += 1.0;
 
-    if (P->mode == MODE_GRAD) {
+    if (P->mode == MODE_GRAD || P->mode == MODE_ATTACHED) {
         A->ncon = 0;
         sb_clear(&A->legs);
         sb_clear(&A->gpeel);
         grad_reserve_legs(A, 2);
+    }
+    if (P->mode == MODE_ATTACHED) {
+        A->naev = 0;
+        att_push(A, r, w);
     }
 
     /* 2. peel-off at emission */
@@ -967,6 +1111,7 @@ static void run_package(const problem_t *P, accum_t *A, uint64_t p, int l)
                 C->a_c = B;
                 C->dlng = 0.0;
                 C->absorbed = 1;
+                C->det = -1;
                 C->beg = C->end = A->gpeel.n;
             }
         }
@@ -1017,8 +1162,23 @@ static void run_package(const problem_t *P, accum_t *A, uint64_t p, int l)
                       exp(-dtau_leg);
         }
 
+        if (P->mode == MODE_ATTACHED) { /* the leg after the current event: its whole path to the boundary */
+            att_ev_t *E = &A->aev[A->naev - 1];
+            E->leg = 1;
+            for (int a = 0; a < 3; a++) E->k[a] = k[a];
+            E->T = T;
+            E->tau_s = tau_s;
+            E->s = s_hit;
+            E->rho_s = P->rho[c_hit];
+            E->beg = A->legs.n;
+            for (size_t j = 0; j < A->path.n; j++)
+                sb_push(&A->legs, A->path.v[j].cell, A->path.v[j].t0, A->path.v[j].t1);
+            E->end = A->legs.n;
+        }
+
         for (int a = 0; a < 3; a++) r[a] += s_hit * k[a];
         w *= alb * (-expm1(-T));
+        if (P->mode == MODE_ATTACHED) att_push(A, r, w);
 
         if (P->flags & FLAG_PEEL_SCAT) peel_event(P, A, l, n + 1, r, k, w, w_eval, score);
 
@@ -1039,6 +1199,7 @@ static void run_package(const problem_t *P, accum_t *A, uint64_t p, int l)
     }
 
     if (P->mode == MODE_GRAD) grad_flush_package(P, A, l, sidx);
+    if (P->mode == MODE_ATTACHED) attached_flush_package(P, A, l);
 }
 
 static void accum_free(accum_t *A)
@@ -1051,6 +1212,7 @@ static void accum_free(accum_t *A)
     free(A->leg_end);
     free(A->leg_cell);
     free(A->con);
+    free(A->aev);
 }
 
 static int setup_problem(problem_t *P, const double box[6], const int n[3], const double *rho, int n_lambda,
@@ -1244,6 +1406,32 @@ int oracle_grad(const double box[6], const int n[3], const double *rho, int n_la
     P.adj = adj;
     P.adj_abs = adj_abs;
     int rc = simulate(&P, images, NULL, grad, grad_opt, stats, n_threads);
+    problem_free(&P);
+    return rc;
+}
+
+/* Gradient of the same image loss with respect to every cell density by the
+ * attached (pathwise) derivative (attached_flush_package): the random
+ * numbers are held fixed and the scattering points move with the
+ * densities.  Frames and SED instruments only (-1 with a perspective
+ * instrument).  Also returns the images of the same run. */
+int oracle_grad_attached(const double box[6], const int n[3], const double *rho, int n_lambda, const double *kappa,
+                         const double *albedo, const double *g, int n_src, const int *src_kind,
+                         const double *src_par, const double *src_lum, int n_det, const double *det_par,
+                         const int *det_pix, uint64_t n_pkg, uint64_t first, uint64_t seed, double w_min,
+                         int max_scatter, unsigned flags, const double *adj, double *images, double *grad,
+                         double *stats, int n_threads, const double *planes, const double *tree,
+                         const double *cell_lum)
+{
+    for (int d = 0; d < n_det; d++)
+        if ((int)det_par[16 * d + 6] == DET_PERSPECTIVE) return -1;
+    problem_t P;
+    if (setup_problem(&P, box, n, rho, n_lambda, kappa, albedo, g, n_src, src_kind, src_par, src_lum, n_det,
+                      det_par, det_pix, n_pkg, first, seed, w_min, max_scatter, flags, planes, tree, cell_lum))
+        return -1;
+    P.mode = MODE_ATTACHED;
+    P.adj = adj;
+    int rc = simulate(&P, images, NULL, grad, NULL, stats, n_threads);
     problem_free(&P);
     return rc;
 }

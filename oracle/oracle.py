@@ -57,6 +57,8 @@ def _load():
         _lib.oracle_run.restype = i
         _lib.oracle_grad.argtypes = common + [P, P, P, P, i, P, P, P, P, P]
         _lib.oracle_grad.restype = i
+        _lib.oracle_grad_attached.argtypes = common + [P, P, P, P, i, P, P, P]
+        _lib.oracle_grad_attached.restype = i
         _lib.oracle_reweight.argtypes = [P, P, P, P, i, P, P, P, i, P, P, P, i, P, P, u64, u64, u64, d, i,
                                          C.c_uint, P, P, i, P, P, P, P, P, P, P]
         _lib.oracle_reweight.restype = i
@@ -245,6 +247,23 @@ def grad(prob, adj, threads=1, optics=False, adj_absorbed=None):
         raise ValueError("oracle_grad rejected its arguments")
     if optics:
         return g, images, dict(zip(STAT_NAMES, stats.tolist())), {"albedo": gopt[0], "g": gopt[1], "lum": gopt[2:]}
+    return g, images, dict(zip(STAT_NAMES, stats.tolist()))
+
+
+def grad_attached(prob, adj, threads=1):
+    """Attached (pathwise) gradient dL/drho for dL/dI = adj: the random
+    numbers held fixed, the scattering points moving with the densities.
+    Frames and SED instruments only.  Returns (grad, images, stats)."""
+    args, keep, nl, npix = _marshal(prob)
+    ncell = keep[2].size
+    adj = _f64(adj).reshape(_comps(prob), nl, npix)
+    images = np.zeros((_comps(prob), nl, npix))
+    g = np.zeros(ncell)
+    stats = np.zeros(len(STAT_NAMES))
+    rc = _load().oracle_grad_attached(*args, _ptr(adj), _ptr(images), _ptr(g), _ptr(stats), int(threads),
+                                      _ptr(keep[11]), _ptr(keep[12]), _ptr(keep[13]))
+    if rc != 0:
+        raise ValueError("oracle_grad_attached rejected its arguments")
     return g, images, dict(zip(STAT_NAMES, stats.tolist()))
 
 
