@@ -76,6 +76,11 @@ extern "C" {
 #define MCRT_PEEL_SCAT 2u /* peel-off at every scattering */
 #define MCRT_ABSORB 4u    /* per-cell absorbed-luminosity tally */
 #define MCRT_SPLIT 8u     /* separate direct and scattered images */
+#define MCRT_ATTACHED 16u /* backward_density, backward: the attached (pathwise) gradient */
+
+/* Most events (emission and scatterings) a package may have in a call with
+ * MCRT_ATTACHED; the bound is that of mcrt_tape_bytes. */
+#define MCRT_ATTACHED_MAX_EVENTS 4096
 
 #define MCRT_PREC_FP64 0
 #define MCRT_PREC_FP32 1
@@ -378,6 +383,33 @@ int backward_density(const mcrt_grid *grid, const void *rho_dev, const mcrt_opti
                      const double *adj_images_dev, double *grad_rho_dev, mcrt_stats *stats_host,
                      void *hip_stream);
 
+/* With MCRT_ATTACHED in opts->flags, backward_density (and backward, with
+ * grads->rho alone) computes the attached (pathwise) derivative instead: the
+ * random numbers are held fixed and the scattering points move with the
+ * densities (Sect. 1, forced scattering: the point of each interaction is
+ * where the optical depth from the previous event reaches
+ * tau_s = -ln(1 - u (1 - e^-T)), u fixed), while every direction (drawn from
+ * the random numbers alone) stays.  Each package runs its life cycle once,
+ * keeping its events (position, weight, the leg after it: direction,
+ * optical depth to the boundary, tau_s, length, density at the next event),
+ * then a reverse sweep from the last event back accumulates, for each
+ * peel-off contribution q = (dL/dI) C, -q kappa l along its peel ray and
+ * its pull on the event's position, and for each leg the terms of T, tau_s
+ * and the leg length.  It is the derivative of the per-package estimator
+ * itself, so it omits what changes in steps: a contribution that crosses a
+ * pixel edge, a peel ray parallel to a grid plane whose origin crosses that
+ * plane, a weight that crosses the termination threshold w_min.  Without
+ * those (SED instruments seen along directions that no grid plane
+ * contains, termination by max_scatter) it is an unbiased gradient of the
+ * expected loss, like the detached one, with another variance.
+ * Frames and SED instruments only (a perspective camera: MCRT_EINVAL); no
+ * absorbed-tally term and no optics gradients (MCRT_EINVAL); a package may
+ * have at most MCRT_ATTACHED_MAX_EVENTS events by the bound of
+ * mcrt_tape_bytes (else MCRT_EINVAL: lower max_scatter or raise w_min); the
+ * tape is not used.  The library keeps a workspace of 88 bytes per event per
+ * package of a chunk.  A package that exceeds the bound anyway (not
+ * expected) makes the call return MCRT_EOVERFLOW. */
+
 /* Gradients of the same image loss with respect to the densities and to
  * the optical properties and source luminosities of every wavelength
  * (Sect. 2.3: albedo and g; Sect. 2.2: luminosities), in one replay.  The
@@ -444,7 +476,7 @@ const char *mcrt_last_error(void);
 /* ABI version of this header. */
 int mcrt_abi_version(void);
 
-#define MCRT_ABI_VERSION 17
+#define MCRT_ABI_VERSION 18
 
 #ifdef __cplusplus
 }

@@ -10,8 +10,12 @@ HIP kernels.  When the run can keep an adjoint tape (binding.tape_bytes)
 and it fits in a quarter of the free device memory, the forward run fills
 one and the backward pass reads T and the peel-off contributions from it,
 replaying each package once instead of twice (prob["adjoint_tape"] = False
-turns this off).  These functions differentiate the images only; a loss on
-the absorbed-luminosity tally goes through binding.backward(adj_absorbed=).
+turns this off).  prob["adjoint_estimator"] = "attached" makes RTImage's
+backward pass the attached (pathwise) derivative instead (MCRT_ATTACHED:
+random numbers fixed, scattering points moving with the densities; frames
+and SED instruments; no tape).  These functions differentiate the images
+only; a loss on the absorbed-luminosity tally goes through
+binding.backward(adj_absorbed=).
 """
 import numpy as np
 import torch
@@ -19,9 +23,16 @@ import torch
 from . import binding
 
 
+def _attached(prob):
+    est = prob.get("adjoint_estimator", "detached")
+    if est not in ("detached", "attached"):
+        raise ValueError("adjoint_estimator must be 'detached' or 'attached', not %r" % (est,))
+    return est == "attached"
+
+
 def _tape_for(prob, device):
     """A tape for the run, or None (not wanted, not possible, or too large)."""
-    if not prob.get("adjoint_tape", True):
+    if not prob.get("adjoint_tape", True) or _attached(prob):
         return None
     n = binding.tape_bytes(prob)
     if n == 0:
@@ -52,7 +63,7 @@ class RTImage(torch.autograd.Function):
         (rho,) = ctx.saved_tensors
         grad = torch.empty(rho.numel(), dtype=torch.float64, device=rho.device)
         binding.backward_density(ctx.prob, rho.contiguous(), grad_images.contiguous().to(torch.float64), grad,
-                                 stats=False, tape=ctx.tape)
+                                 stats=False, tape=ctx.tape, attached=_attached(ctx.prob))
         ctx.tape = None
         return grad.to(rho.dtype).view_as(rho), None
 
@@ -71,6 +82,8 @@ class RTImageOptics(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, rho, albedo, g, lum, prob):
+        if _attached(prob):
+            raise ValueError("the attached estimator differentiates the densities only (use RTImage)")
         lum_h = lum.detach().to("cpu", torch.float64).numpy()
         p = dict(prob, flags=int(prob.get("flags", 7)) & ~binding.ABSORB,
                  albedo=albedo.detach().to("cpu", torch.float64).numpy().copy(),

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcrt.so")
 
-PEEL_EMIT, PEEL_SCAT, ABSORB, SPLIT = 1, 2, 4, 8
+PEEL_EMIT, PEEL_SCAT, ABSORB, SPLIT, ATTACHED = 1, 2, 4, 8, 16
 PREC_FP64, PREC_FP32 = 0, 1
 OK, EINVAL, EOVERFLOW, EHIP = 0, -1, -2, -3
 
@@ -89,7 +89,7 @@ class Stats(C.Structure):
 _lib = None
 
 # Exported symbols of include/mcrt.h.
-ABI_VERSION = 17  # MCRT_ABI_VERSION of the header these structs follow
+ABI_VERSION = 18  # MCRT_ABI_VERSION of the header these structs follow
 SYMBOLS = ("run_photons", "trace_path", "trace_path_noalloc", "peel_off", "backward_density", "backward",
            "dust_emission", "mcrt_tape_bytes", "mcrt_last_error", "mcrt_abi_version")
 NOALLOC_SCRATCH_BYTES = 96 << 20  # MCRT_NOALLOC_SCRATCH_BYTES
@@ -384,13 +384,23 @@ def run_photons(prob, rho, images, absorbed=None, stats=True, stream=None, tape=
     return st.as_dict() if stats else None
 
 
-def backward_density(prob, rho, adj_images, grad_rho, stats=True, stream=None, tape=None, **overrides):
+def _attached(prob, attached, overrides):
+    """The options with MCRT_ATTACHED set when the attached gradient is asked for."""
+    if not attached:
+        return overrides
+    return dict(overrides, flags=int(overrides.get("flags", prob.get("flags", 7))) | ATTACHED)
+
+
+def backward_density(prob, rho, adj_images, grad_rho, stats=True, stream=None, tape=None, attached=False,
+                     **overrides):
     """backward_density: grad_rho (device FP64 [ncell]) = dL/drho for
     dL/dI = adj_images (device FP64, image layout of run_photons); tape: the
-    forward run's tape (same problem and densities), or None."""
+    forward run's tape (same problem and densities), or None; attached=True:
+    the attached (pathwise) derivative (MCRT_ATTACHED; the tape is not
+    used)."""
     lib = load()
     _check_life(prob, rho, adj=adj_images, grad=grad_rho, overrides=overrides)
-    overrides = _tape_args(prob, tape, overrides)
+    overrides = _attached(prob, attached, _tape_args(prob, tape, overrides))
     pr = _Problem(prob, **overrides)
     st = Stats()
     _check(lib.backward_density(C.byref(pr.grid), _ptr(rho), C.byref(pr.optics), pr.n_src, pr.sources, pr.n_det,
@@ -400,19 +410,20 @@ def backward_density(prob, rho, adj_images, grad_rho, stats=True, stream=None, t
 
 
 def backward(prob, rho, adj_images, grad_rho=None, grad_albedo=None, grad_g=None, grad_lum=None, stats=True,
-             stream=None, adj_absorbed=None, tape=None, **overrides):
+             stream=None, adj_absorbed=None, tape=None, attached=False, **overrides):
     """backward: the gradients of the loss with dL/dI = adj_images (and dL/dA
     = adj_absorbed [n_lambda][ncell] on the absorbed tally, if given) with
     respect to the densities (device FP64 [ncell]), the albedo and g
     ([n_lambda]) and the source luminosities ([n_src][n_lambda]); each
-    output is a device FP64 tensor or None (not computed)."""
+    output is a device FP64 tensor or None (not computed).  attached=True:
+    the attached density gradient (grad_rho alone)."""
     lib = load()
     _check_life(prob, rho, adj=adj_images, absorbed=adj_absorbed, grad=grad_rho, overrides=overrides)
     nl = len(np.atleast_1d(prob["kappa"]))
     _need(grad_albedo, "grad_albedo", nl)
     _need(grad_g, "grad_g", nl)
     _need(grad_lum, "grad_lum", len(prob["sources"]) * nl)
-    overrides = _tape_args(prob, tape, overrides)
+    overrides = _attached(prob, attached, _tape_args(prob, tape, overrides))
     pr = _Problem(prob, **overrides)
     st = Stats()
     g = Grads(_ptr(grad_rho), _ptr(grad_albedo), _ptr(grad_g), _ptr(grad_lum))

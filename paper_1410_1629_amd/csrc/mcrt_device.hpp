@@ -798,7 +798,8 @@ MCRT_HD T ray_tplane(const Ray<R, T>& ry, int a) {
 // time (non-finite times); sub-steps after that repeat the last valid cell,
 // so no load leaves the grid.  `adv` keeps the axes that advanced at each
 // sub-step (3 bits each) so that a caller stopping inside the block can
-// rewind the ray (ray_rewind).
+// rewind the ray (ray_rewind), and that names the plane of each crossing
+// (on a tree grid: the exit faces of each segment's leaf).
 template <int D, typename R, typename T = R>
 struct WalkBlock {
   int cell[D];
@@ -817,9 +818,11 @@ struct WalkBlock {
 // others advanced along k -- and finds the next leaf: across a single face,
 // by descending from the face's rope (the deepest node covering the face),
 // across an edge or corner, from the root.  A non-finite or negative exit
-// time also ends the walk.
+// time also ends the walk.  `axes` receives the axes of the exit faces (bit
+// a for axis a), as a regular grid's walk block records the axes it
+// advances.
 template <typename R, typename T>
-MCRT_HD void tree_cross(Ray<R, T>& ry, const GridDev& G, int& cell, double& tend, bool& out) {
+MCRT_HD void tree_cross(Ray<R, T>& ry, const GridDev& G, int& cell, double& tend, bool& out, unsigned& axes) {
   const double px = ry.e[0], py = ry.e[1], pz = ry.e[2];
   const int sx = ry.s[0], sy = ry.s[1], sz = ry.s[2];
   int c = ry.i[0];
@@ -849,6 +852,7 @@ MCRT_HD void tree_cross(Ray<R, T>& ry, const GridDev& G, int& cell, double& tend
   const double ny = ey ? fy : py + tm * ry.k[1];
   const double nz = ez ? fz : pz + tm * ry.k[2];
   out = !valid || boundary;
+  axes = valid ? ((unsigned)ex | ((unsigned)ey << 1) | ((unsigned)ez << 2)) : 0u;
   if (valid) {
     ry.e[0] = nx;
     ry.e[1] = ny;
@@ -880,7 +884,9 @@ MCRT_HD void ray_next_block(Ray<R, T>& ry, WalkBlock<D, R, T>& b, const GridDev&
         int cell;
         double te;
         bool out;
-        tree_cross(ry, G, cell, te, out);
+        unsigned axes;
+        tree_cross(ry, G, cell, te, out, axes);
+        b.adv |= axes << (3 * d);
         b.cell[d] = cell < 0 ? 0 : cell;
         b.tend64[d] = te;
         b.tend[d] = (T)te;

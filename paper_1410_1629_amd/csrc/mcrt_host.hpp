@@ -570,7 +570,7 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
   if (!(opts->w_min >= 0.0) || !finite(opts->w_min)) return fail(MCRT_EINVAL, "w_min must be finite and >= 0");
   if (opts->max_scatter < 1 || opts->max_scatter > MCRT_MAX_SCATTER_LIMIT)
     return fail(MCRT_EINVAL, "max_scatter must lie in [1, %d]", MCRT_MAX_SCATTER_LIMIT);
-  if (opts->flags & ~15u) return fail(MCRT_EINVAL, "unknown flag bits 0x%x", opts->flags);
+  if (opts->flags & ~31u) return fail(MCRT_EINVAL, "unknown flag bits 0x%x", opts->flags);
   if (opts->launch_blocks < 0 || opts->launch_blocks > 64) return fail(MCRT_EINVAL, "launch_blocks outside [0, 64]");
   if (opts->event_batch < 0 || opts->event_batch > 64) return fail(MCRT_EINVAL, "event_batch outside [0, 64]");
   if (opts->peel_queue < -1 || opts->peel_queue > (1ll << 31))
@@ -732,6 +732,26 @@ inline long long tape_events(const mcrt_optics& optics, const mcrt_opts& o) {
     if (r + 2.0 < (double)last) last = std::max(1ll, 2 + (long long)std::floor(r));
   }
   return last + 1;
+}
+
+// Checks a call of the attached gradient (MCRT_ATTACHED): frames and SED
+// instruments, no absorbed-tally term, no optics gradients, a bound on a
+// package's events within MCRT_ATTACHED_MAX_EVENTS (returned in *events).
+inline int attached_check(const mcrt_optics& optics, int n_det, const mcrt_detector* detectors,
+                          const mcrt_opts& o, bool absorbed_term, bool optics_grads, int* events) {
+  if (absorbed_term) return fail(MCRT_EINVAL, "MCRT_ATTACHED: the attached gradient has no absorbed-tally term");
+  if (optics_grads) return fail(MCRT_EINVAL, "MCRT_ATTACHED: the attached gradient is that of the densities only");
+  for (int d = 0; d < n_det; ++d)
+    if (detectors[d].kind == MCRT_DET_PERSPECTIVE)
+      return fail(MCRT_EINVAL, "MCRT_ATTACHED: instrument %d is a perspective camera (frames and SED only)", d);
+  const long long ev = tape_events(optics, o);
+  if (ev > MCRT_ATTACHED_MAX_EVENTS)
+    return fail(MCRT_EINVAL,
+                "MCRT_ATTACHED: a package may have %lld events (at most %d): lower max_scatter, or raise w_min "
+                "below an albedo of 1",
+                ev, MCRT_ATTACHED_MAX_EVENTS);
+  *events = (int)ev;
+  return 0;
 }
 
 // Bytes of the tape, 0 when the run cannot have one.

@@ -28,6 +28,7 @@
 
 #include "mcrt.h"
 #include "mcrt_device.hpp"
+#include "mcrt_attached.hpp"
 #include "mcrt_host.hpp"
 #include "mcrt_lane.hpp"
 
@@ -96,7 +97,7 @@ constexpr int kWavesPerBlock = kBlock / 64;
 // [24] next peel-job slot, [25] next sorted job of the optical-depth walks,
 // [26] and [27] crossings and deposits of the queued walks, [28] next chunk
 // of the deposit walks.
-constexpr int kJobCounter = 24, kKeyCounter = 25, kQueueCrossings = 26, kDepCounter = 28;
+constexpr int kJobCounter = 24, kKeyCounter = 25, kQueueCrossings = 26, kDepCounter = 28, kAttOverflow = 29;
 // Deposit-queue slots are reserved per wavefront in chunks (one global
 // atomic per chunk); slots a wavefront reserved but did not fill are marked
 // with kNoKey when it exits, and the sort skips them.
@@ -822,6 +823,59 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
   }
 }
 
+// ---------------------------------------------------------------------------
+// The attached density gradient (mcrt_attached.hpp): one work item per lane,
+// its forward sweep and its reverse sweep back to back.  A plain grid over
+// the chunk's items -- each lane's work is one package's walks, done in
+// order, so there is no state machine to interleave; the workspace keeps
+// each item's events with the items of a chunk side by side, so lanes at the
+// same event of their packages touch adjacent words.  Deposits go straight to
+// the gradient as FP64 atomics.
+
+template <typename R, int GK>
+struct AttMem {
+  static constexpr int kGrid = GK;
+  const R* __restrict__ rho_;
+  const RunParams& P;
+  __device__ R rho(int c) const { return rho_[c]; }
+  __device__ const DetDev& det(int d) const { return P.det[d]; }
+  __device__ const LamDev& lam(int l) const { return P.lam[l]; }
+  __device__ const SrcDev& src(int s) const { return P.src[s]; }
+  __device__ double adj(long long i) const { return P.adj[i]; }
+  __device__ void add_grad(int i, double v) const { atomic_add_f64(P.grad + i, v); }
+  __device__ double att_ld(int slot, int e, int f) const {
+    return P.evs[((size_t)e * kAttF + f) * P.n_chunk + slot];
+  }
+  __device__ void att_st(int slot, int e, int f, double v) const {
+    P.evs[((size_t)e * kAttF + f) * P.n_chunk + slot] = v;
+  }
+  __device__ void att_over() const { atomicOr(P.work + kAttOverflow, 1ull); }
+};
+
+template <typename R, int GK>
+__global__ void __launch_bounds__(kBlock) k_attached(const RunParams P) {
+  AttMem<R, GK> M{static_cast<const R*>(P.rho), P};
+  AttCounts c;
+  const unsigned long long k = (unsigned long long)blockIdx.x * kBlock + threadIdx.x;
+  if (k < P.n_chunk) attached_item<R>(P, M, P.item0 + k, (int)k, c);
+  const double s_abs = wave_sum(c.s_abs), s_esc = wave_sum(c.s_esc), s_trunc = wave_sum(c.s_trunc);
+  const unsigned long long a0 = wave_sum_u64(c.x_path), a1 = wave_sum_u64(c.x_loc), a2 = wave_sum_u64(c.x_peel),
+                           a3 = wave_sum_u64(c.n_ev), a4 = wave_sum_u64(c.n_pk), a5 = wave_sum_u64(c.n_pl),
+                           a6 = wave_sum_u64(c.n_dep);
+  if (__lane_id() == 0) {
+    atomic_add_f64(P.dstats + 0, s_abs);
+    atomic_add_f64(P.dstats + 1, s_esc);
+    atomic_add_f64(P.dstats + 2, s_trunc);
+    atomicAdd(P.xstats + 0, a0);
+    atomicAdd(P.xstats + 1, a1);
+    atomicAdd(P.xstats + 2, a2);
+    atomicAdd(P.xstats + 3, a3);
+    atomicAdd(P.xstats + 4, a4);
+    atomicAdd(P.xstats + 5, a5);
+    atomicAdd(P.xstats + 6, a6);
+  }
+}
+
 __global__ void k_zero(double* __restrict__ p, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = 0.0;
@@ -1368,6 +1422,29 @@ void launch_life_c(const RunParams& P, int nblk, hipStream_t st) {
     launch_life_k<R, ADJ, kGridRegular, INST>(P, nblk, st);
 }
 
+// The attached gradient's kernel over one chunk: one lane per work item.
+int launch_attached(const RunParams& P, bool f32, hipStream_t st) {
+  const unsigned nb = (unsigned)((P.n_chunk + kBlock - 1) / kBlock);
+  const int kind = P.G.kind;
+  if (f32) {
+    if (kind == kGridRect)
+      hipLaunchKernelGGL((k_attached<float, kGridRect>), dim3(nb), dim3(kBlock), 0, st, P);
+    else if (kind == kGridTree)
+      hipLaunchKernelGGL((k_attached<float, kGridTree>), dim3(nb), dim3(kBlock), 0, st, P);
+    else
+      hipLaunchKernelGGL((k_attached<float, kGridRegular>), dim3(nb), dim3(kBlock), 0, st, P);
+  } else {
+    if (kind == kGridRect)
+      hipLaunchKernelGGL((k_attached<double, kGridRect>), dim3(nb), dim3(kBlock), 0, st, P);
+    else if (kind == kGridTree)
+      hipLaunchKernelGGL((k_attached<double, kGridTree>), dim3(nb), dim3(kBlock), 0, st, P);
+    else
+      hipLaunchKernelGGL((k_attached<double, kGridRegular>), dim3(nb), dim3(kBlock), 0, st, P);
+  }
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
 template <typename R, bool ADJ>
 int launch_life(const RunParams& P, bool inst, int nblk, hipStream_t st) {
   if (inst)
@@ -1408,6 +1485,14 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     P.adj = adj_dev;
     P.grad = grads->rho;
   }
+  // the attached gradient: densities of an image loss, frames and SED
+  // instruments, a workspace of every event of a package
+  const bool att = adjoint && (opts->flags & MCRT_ATTACHED);
+  int att_ev = 0;
+  if (att)
+    if (int e = host::attached_check(*optics, n_det, detectors, *opts, adj_abs_dev != nullptr,
+                                     grads->albedo || grads->g || grads->lum || !grads->rho, &att_ev))
+      return e;
   const int nl = P.n_lambda;
   const bool f32 = opts->precision == MCRT_PREC_FP32;
   int nblk = 0;
@@ -1430,7 +1515,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const int tape_ev = tape_need ? (int)host::tape_events(*optics, *opts) : 0;
   bool tape_fwd = false, tape_adj = false;
   uint64_t fprint = 0;
-  if (opts->tape) {
+  if (opts->tape && !att) {
     if (!tape_need) return fail(MCRT_EINVAL, "tape given, but this run cannot keep one (mcrt_tape_bytes is 0)");
     fprint = host::tape_fingerprint(*grid, *optics, n_src, sources, n_det, detectors, *opts);
     if (!adjoint) {
@@ -1454,10 +1539,11 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   // package, T and q per frame for ev_max events (the tape's events, else
   // kEventsKept) plus the sum of q beyond; the peel-ray queue by default 8
   // rays per package and frame
-  const int ev_max = tape_adj ? tape_ev : kEventsKept;
-  const int ev_k = 1 + n_det + (adjoint && adj_abs_dev ? 1 : 0);  // T, q per frame, then B of the path
-  const size_t per_item = sizeof(double) * ((size_t)ev_max * ev_k + 1 + (optg ? 4 : 0));
-  const bool queued = peel && opts->peel_queue != -1;
+  // (the attached gradient: kAttF doubles for each of a package's events)
+  const int ev_max = att ? att_ev : (tape_adj ? tape_ev : kEventsKept);
+  const int ev_k = att ? (int)kAttF : 1 + n_det + (adjoint && adj_abs_dev ? 1 : 0);  // T, q per frame, then B of the path
+  const size_t per_item = sizeof(double) * ((size_t)ev_max * ev_k + (att ? 0 : 1 + (optg ? 4 : 0)));
+  const bool queued = peel && opts->peel_queue != -1 && !att;
   size_t free_b = 0, total_b = 0;
   HIPCHK(hipMemGetInfo(&free_b, &total_b));
   unsigned long long most = P.n_items;
@@ -1471,7 +1557,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const unsigned long long n_chunks = (P.n_items + most - 1) / most;
   const unsigned long long chunk = (P.n_items + n_chunks - 1) / n_chunks;
   // the adjoint's event scratch, then (optics gradients) the pass-B sums
-  const size_t n_evs = adjoint ? (size_t)chunk * ((size_t)ev_max * ev_k + 1 + (optg ? 4 : 0)) : 0;
+  const size_t n_evs = adjoint ? (size_t)chunk * ((size_t)ev_max * ev_k + (att ? 0 : 1 + (optg ? 4 : 0))) : 0;
   const long long n_tally = adjoint ? (long long)P.G.ncell_pad : (P.absorbed ? (long long)nl * P.G.ntal : 0);
   const size_t off_lam = 0;
   const size_t off_det = align256(sizeof(LamDev) * nl);
@@ -1606,6 +1692,16 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
       if (P.jobs)
         if (int e = queue_phase(false)) return e;
     }
+  } else if (att) {
+    if (int e = reset_counters(ctr, kAttOverflow, 1, st)) return e;
+    for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
+      P.item0 = c0;
+      P.n_chunk = std::min(chunk, P.n_items - c0);
+      if (int e = sp.mark(kSpanLife, st)) return e;
+      if (int e = launch_attached(P, f32, st)) return e;
+      ++launches;
+      if (int e = sp.mark(kSpanLife, st)) return e;
+    }
   } else {
     for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
       P.item0 = c0;
@@ -1654,6 +1750,12 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   if (stats) HIPCHK(hipEventRecord(ev.c, st));
   if (tally && user_tally)
     if (int e = unbrick_tally(P.G, tally, user_tally, adjoint ? 1 : nl, !adjoint, st)) return e;
+  if (att) {  // a package beyond the event bound (not expected: the bound holds by construction)
+    unsigned long long over = 0;
+    HIPCHK(hipMemcpyAsync(&over, ctr + kAttOverflow, sizeof over, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (over) return fail(MCRT_EOVERFLOW, "MCRT_ATTACHED: a package had more events than %d", att_ev);
+  }
   if (stats) {
     double ds[3];
     unsigned long long xs[7], xq[2] = {0, 0};

@@ -16,7 +16,7 @@ SRC = os.path.join(HERE, "mcrt_emu.cpp")
 CSRC = os.path.join(ROOT, "paper_1410_1629_amd", "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 DEPS = [SRC, os.path.join(INCLUDE, "mcrt.h")] + [os.path.join(CSRC, h) for h in
-                                                ("mcrt_device.hpp", "mcrt_lane.hpp", "mcrt_host.hpp")]
+                                                ("mcrt_device.hpp", "mcrt_lane.hpp", "mcrt_host.hpp", "mcrt_attached.hpp")]
 WAVE = 64
 
 
@@ -108,11 +108,11 @@ class Emu:
         """Packages per adjoint chunk (0: the library's choice)."""
         self.lib.emu_set_chunk_items(int(n))
 
-    def grad(self, prob, adj, wave=WAVE, optics=False, adj_absorbed=None, tape=None, **overrides):
+    def grad(self, prob, adj, wave=WAVE, optics=False, adj_absorbed=None, tape=None, attached=False, **overrides):
         """(dL/drho, stats), or with optics=True (dL/drho, stats, {"albedo",
         "g", "lum"}); adj_absorbed [n_lambda][ncell] adds a loss term on the
-        absorbed tally."""
-        overrides = self._tape(prob, tape, overrides)
+        absorbed tally; attached=True: the attached gradient."""
+        overrides = B._attached(prob, attached, self._tape(prob, tape, overrides))
         pr = B._Problem(prob, cells_on_device=False, **overrides)
         rho = self._rho(prob)
         adj = np.ascontiguousarray(adj, dtype=np.float64).reshape(-1)

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "mcrt.h"
+#include "mcrt_attached.hpp"
 #include "mcrt_device.hpp"
 #include "mcrt_host.hpp"
 #include "mcrt_lane.hpp"
@@ -821,6 +822,135 @@ int emu_peel(const mcrt_grid* grid, const void* rho, double kappa, double g, int
   return 0;
 }
 
+// The attached gradient's per-item code (mcrt_attached.hpp) on host buffers:
+// items one after another, every access checked, workspace reads checked to
+// follow a write of the same item.
+template <typename R, int GK>
+struct HostAttMem {
+  static constexpr int kGrid = GK;
+  const R* rho_;
+  const GridDev& G;
+  const host::Prepared& pr;
+  const double* adj_;
+  long long n_adj;
+  std::vector<double>& grad;
+  std::vector<double>& ws;
+  std::vector<unsigned char>& ws_set;
+  int ev_max;
+  int n_chunk;
+  bool over = false;
+  R rho(int c) const {
+    check_cell(G, c, "density");
+    return rho_[c];
+  }
+  const DetDev& det(int d) const {
+    EMU_CHECK(d >= 0 && d < pr.P.n_det, "instrument", d, pr.P.n_det);
+    return pr.det[d];
+  }
+  const LamDev& lam(int l) const {
+    EMU_CHECK(l >= 0 && l < pr.P.n_lambda, "wavelength", l, pr.P.n_lambda);
+    return pr.lam[l];
+  }
+  const SrcDev& src(int s) const {
+    EMU_CHECK(s >= 0 && s < pr.P.n_src, "source", s, pr.P.n_src);
+    return pr.src[s];
+  }
+  double adj(long long i) const {
+    EMU_CHECK(i >= 0 && i < n_adj, "adjoint image", i, n_adj);
+    return adj_[i];
+  }
+  void add_grad(int i, double v) {
+    EMU_CHECK(i >= 0 && i < (long long)grad.size(), "gradient", i, (long long)grad.size());
+    check_cell(G, i, "gradient");
+    grad[i] += v;
+  }
+  size_t ws_index(int slot, int e, int f) const {
+    EMU_CHECK(slot >= 0 && slot < n_chunk, "workspace item", slot, n_chunk);
+    EMU_CHECK(e >= 0 && e < ev_max, "workspace event", e, ev_max);
+    EMU_CHECK(f >= 0 && f < kAttF, "workspace field", f, kAttF);
+    return ((size_t)e * kAttF + f) * n_chunk + slot;
+  }
+  double att_ld(int slot, int e, int f) const {
+    const size_t i = ws_index(slot, e, f);
+    EMU_CHECK(ws_set[i], "workspace read before write", e, ev_max);
+    return ws[i];
+  }
+  void att_st(int slot, int e, int f, double v) {
+    const size_t i = ws_index(slot, e, f);
+    ws[i] = v;
+    ws_set[i] = 1;
+  }
+  void att_over() { over = true; }
+};
+
+template <typename R, int GK>
+int emu_attached(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, int n_src,
+                 const mcrt_source* sources, int n_det, const mcrt_detector* detectors, const mcrt_opts* opts,
+                 const double* adj, long long n_adj, double* grad, long long n_grad, mcrt_stats* stats) {
+  host::Prepared pr;
+  if (int e = host::prepare(grid, rho, optics, n_src, sources, n_det, detectors, opts, pr)) return e;
+  int ev = 0;
+  if (int e = host::attached_check(*optics, n_det, detectors, *opts, false, false, &ev)) return e;
+  HostPlanes planes;
+  planes.attach(*grid, pr.P.G);
+  std::vector<double> cum;
+  if (pr.cell_src >= 0) {  // as emu_life: the cell source's prefix sums, NaN-fenced
+    const int nl = pr.P.n_lambda, nc = pr.P.G.ncell;
+    const double* x = sources[pr.cell_src].cell_lum;
+    cum.assign((size_t)nl * (nc + 1) + 2, std::nan(""));
+    std::vector<double> tot(nl);
+    for (int l = 0; l < nl; ++l) {
+      double acc = 0.0;
+      for (int m = 0; m < nc; ++m) {
+        const double v = x[(size_t)l * nc + m];
+        if (!(v >= 0.0 && v < INFINITY)) return host::fail(MCRT_EINVAL, "cell_lum holds a negative or non-finite luminosity");
+        cum[1 + (size_t)l * (nc + 1) + m] = acc;
+        acc += v;
+      }
+      cum[1 + (size_t)l * (nc + 1) + nc] = acc;
+      tot[l] = acc;
+    }
+    host::set_luminosities(pr, n_src, sources, tot.data(), opts->n_packages);
+    pr.src[pr.cell_src].cum = cum.data() + 1;
+  }
+  RunParams P = pr.P;
+  if (n_grad < P.G.ncell) throw Violation("gradient buffer too small");
+  const std::vector<R> rho_b = brick_copy(P.G, static_cast<const R*>(rho));
+  std::vector<double> grad_b((size_t)P.G.ncell_pad, 0.0);
+  const int chunk = g_chunk_items > 0 ? g_chunk_items : (int)std::min<unsigned long long>(P.n_items, 4096);
+  std::vector<double> ws((size_t)ev * kAttF * chunk, std::nan(""));
+  std::vector<unsigned char> ws_set(ws.size(), 0);
+  HostAttMem<R, GK> M{rho_b.data(), P.G, pr, adj, n_adj, grad_b, ws, ws_set, ev, chunk};
+  P.ev_max = ev;
+  AttCounts c;
+  unsigned long long launches = 0;
+  for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
+    const int n = (int)std::min<unsigned long long>(chunk, P.n_items - c0);
+    M.n_chunk = n;
+    std::fill(ws_set.begin(), ws_set.end(), 0);
+    for (int k = 0; k < n; ++k) attached_item<R>(P, M, c0 + k, k, c);
+    ++launches;
+  }
+  if (M.over) return host::fail(MCRT_EOVERFLOW, "MCRT_ATTACHED: a package had more events than %d", ev);
+  unbrick(P.G, grad_b, grad, 1, false);
+  if (stats) {
+    std::memset(stats, 0, sizeof *stats);
+    stats->emitted = pr.emitted;
+    stats->absorbed = c.s_abs;
+    stats->escaped = c.s_esc;
+    stats->truncated = c.s_trunc;
+    stats->x_path = c.x_path;
+    stats->x_locate = c.x_loc;
+    stats->x_peel = c.x_peel;
+    stats->events = c.n_ev;
+    stats->packages = c.n_pk;
+    stats->peels = c.n_pl;
+    stats->deposits = c.n_dep;
+    stats->life_launches = launches;
+  }
+  return 0;
+}
+
 // Precision and grid kind of a call, as the library dispatches its kernels.
 inline int grid_kind(const mcrt_grid* g) {
   return !g ? kGridRegular : (g->tree_nodes > 0 ? kGridTree : (g->planes ? kGridRect : kGridRegular));
@@ -915,6 +1045,26 @@ int emu_backward_density(const mcrt_grid* grid, const void* rho, const mcrt_opti
     if (!opts) return host::fail(MCRT_EINVAL, "opts is NULL");
     mcrt_opts o = *opts;
     o.flags &= ~MCRT_ABSORB;
+    if (o.flags & MCRT_ATTACHED) {
+      if (gopt || adj_abs)
+        return host::fail(MCRT_EINVAL, "MCRT_ATTACHED: the attached gradient is that of the densities only");
+      const int kind = grid_kind(grid);
+      const bool f32 = o.precision == MCRT_PREC_FP32;
+      if (kind == kGridRect)
+        return f32 ? emu_attached<float, kGridRect>(grid, rho, optics, n_src, sources, n_det, detectors, &o, adj, n_adj,
+                                                    grad, n_grad, stats)
+                   : emu_attached<double, kGridRect>(grid, rho, optics, n_src, sources, n_det, detectors, &o, adj,
+                                                     n_adj, grad, n_grad, stats);
+      if (kind == kGridTree)
+        return f32 ? emu_attached<float, kGridTree>(grid, rho, optics, n_src, sources, n_det, detectors, &o, adj, n_adj,
+                                                    grad, n_grad, stats)
+                   : emu_attached<double, kGridTree>(grid, rho, optics, n_src, sources, n_det, detectors, &o, adj,
+                                                     n_adj, grad, n_grad, stats);
+      return f32 ? emu_attached<float, kGridRegular>(grid, rho, optics, n_src, sources, n_det, detectors, &o, adj,
+                                                     n_adj, grad, n_grad, stats)
+                 : emu_attached<double, kGridRegular>(grid, rho, optics, n_src, sources, n_det, detectors, &o, adj,
+                                                      n_adj, grad, n_grad, stats);
+    }
     return life_dispatch<true>(o.precision == MCRT_PREC_FP32, grid_kind(grid), n_det, detectors,
                                gopt != nullptr || adj_abs != nullptr, grid, rho, optics,
                                n_src, sources,

@@ -1,0 +1,104 @@
+"""The attached (pathwise) density gradient (MCRT_ATTACHED) on the CPU
+harness: the library's per-item code (mcrt_attached.hpp) against the
+oracle's attached gradient, for every grid kind, with split images, frames
+and SED instruments, weight termination, a cell source and chunked runs;
+equal to the detached gradient when nothing scatters; the calls it rejects.
+"""
+import numpy as np
+import pytest
+from parity import check
+
+from paper_1410_1629_amd import binding as B
+
+
+def _problem(W, prec, n_packages=500, **kw):
+    n = (8, 7, 6)
+    args = dict(n=n, rho=W.lognormal_density(n, 0.8, seed=31, f32=(prec == 1)), kappa=[1.2, 0.7],
+                albedo=[0.7, 0.5], g=[0.45, -0.1],
+                sources=[W.point((0.13, -0.21, 0.07), [1.0, 0.6]), W.expdisk(0.4, 0.15, [0.5, 1.5])],
+                detectors=[W.frame(10.0, 30.0, 16, 16, 1.0, 1.0, azim=20.0), W.sed(10.0, 95.0, azim=40.0)],
+                n_packages=n_packages, flags=W.FLAG_PEEL_EMIT | W.FLAG_PEEL_SCAT, w_min=1e-3, max_scatter=50,
+                precision=prec)
+    args.update(kw)
+    return W.small_problem(**args)
+
+
+def _grid(W, prob, kind, prec):
+    if kind == "rect":
+        from test_oracle_rectilinear import random_planes
+        rng = np.random.default_rng(4)
+        prob["planes"] = tuple(random_planes(prob["box"][2 * a], prob["box"][2 * a + 1], prob["n"][a], rng)
+                               for a in range(3))
+    elif kind == "tree":
+        from test_oracle_tree import BOX, kd_tree
+        T = kd_tree(W)
+        rho = np.random.default_rng(7).lognormal(0.0, 0.8, T.n_cells)
+        prob = dict(prob, box=BOX, n=(T.n_cells, 1, 1), tree=T.tree(),
+                    rho=rho.astype(np.float32) if prec == 1 else rho)
+    elif kind == "split":
+        prob["flags"] |= W.FLAG_SPLIT
+    return prob
+
+
+TOL = {0: 1e-10, 1: 1e-5}
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind", ["regular", "rect", "tree", "split"])
+def test_attached_matches_the_oracle(E, orc, W, kind, prec):
+    prob = _grid(W, _problem(W, prec), kind, prec)
+    img, _, _ = orc.run(prob)
+    adj = np.random.default_rng(5).standard_normal(img.shape)
+    g_o, _, _ = orc.grad_attached(prob, adj)
+    g, st = E.grad(prob, adj, attached=True)
+    check(g, g_o, TOL[prec], "%s prec %d: attached gradient" % (kind, prec))
+    assert st["life_launches"] == 1 and st["packages"] == 2 * 500
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_attached_in_chunks_with_count_termination_and_a_cell_source(E, orc, W, prec):
+    n = (8, 7, 6)
+    lum = np.random.default_rng(3).lognormal(0.0, 1.0, (2, int(np.prod(n))))
+    prob = _problem(W, prec, n_packages=700, w_min=0.0, max_scatter=7,
+                    sources=[W.point((0.13, -0.21, 0.07), [1.0, 0.6]), W.cells(lum)])
+    img, _, _ = orc.run(prob)
+    adj = np.random.default_rng(8).standard_normal(img.shape)
+    g_o, _, _ = orc.grad_attached(prob, adj)
+    E.set_chunk_items(333)
+    try:
+        g, st = E.grad(prob, adj, attached=True)
+    finally:
+        E.set_chunk_items(0)
+    check(g, g_o, TOL[prec], "chunks of 333: attached gradient")
+    assert st["life_launches"] == -(-1400 // 333)
+
+
+def test_attached_equals_detached_without_scattering(E, W):
+    prob = _problem(W, 0, albedo=[0.0, 0.0])
+    img_shape = B.image_shape(prob)
+    adj = np.random.default_rng(3).standard_normal(img_shape)
+    g_a, _ = E.grad(prob, adj, attached=True)
+    g_d, _ = E.grad(prob, adj)
+    check(g_a, g_d, 1e-12, "albedo 0: attached against detached")
+
+
+def test_attached_rejections(E, W):
+    prob = _problem(W, 0, n_packages=50)
+    adj = np.ones(B.image_shape(prob))
+    cam = W.perspective((0.3, -0.2, 0.1), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 8, 8, 1.0, 1.0)
+    bad = [dict(prob, detectors=[prob["detectors"][0], cam]),          # a camera moves with the event
+           dict(prob, w_min=0.0, max_scatter=B_MAX + 1)]                # no bound within the workspace's
+    for p in bad:
+        with pytest.raises(B.McrtError) as ei:
+            E.grad(p, np.ones(B.image_shape(p)), attached=True)
+        assert ei.value.code == B.EINVAL
+    with pytest.raises(B.McrtError):  # no optics gradients
+        E.grad(prob, adj, attached=True, optics=True)
+    with pytest.raises(B.McrtError):  # no absorbed-tally term
+        E.grad(prob, adj, attached=True, adj_absorbed=np.ones((2, 8 * 7 * 6)))
+    # the most events allowed: max_scatter + 1 = MCRT_ATTACHED_MAX_EVENTS
+    g, _ = E.grad(dict(prob, w_min=0.0, max_scatter=B_MAX - 1, n_packages=5), adj, attached=True)
+    assert np.isfinite(g).all()
+
+
+B_MAX = 4096  # MCRT_ATTACHED_MAX_EVENTS
