@@ -402,6 +402,10 @@ int backward_density(const mcrt_grid *grid, const void *rho_dev, const mcrt_opti
  * those (SED instruments seen along directions that no grid plane
  * contains, termination by max_scatter) it is an unbiased gradient of the
  * expected loss, like the detached one, with another variance.
+ * The attached gradient is computed in FP64 arithmetic in both precisions
+ * (MCRT_PREC_FP32 reads the FP32 densities and widens them): its derivative
+ * amplifies the rounding of a point's position wherever a leg grazes a cell
+ * face, which FP32 walks would not follow on rough media.
  * Frames and SED instruments only (a perspective camera: MCRT_EINVAL); no
  * absorbed-tally term and no optics gradients (MCRT_EINVAL); a package may
  * have at most MCRT_ATTACHED_MAX_EVENTS events by the bound of

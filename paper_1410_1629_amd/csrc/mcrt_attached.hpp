@@ -33,12 +33,16 @@
 // choices, the escape test (T = 0) and the termination test stay fixed: the
 // result is the derivative of the per-package estimator where it is smooth.
 //
-// The forward sweep repeats the life-cycle kernel's arithmetic (the same
-// draws, the same walks with FP64 times and, in FP32, the compensated sum
-// of optical depths, the same locate test), so it follows the forward run's
-// packages.  It keeps, per event, [kAttF] doubles in the workspace
-// [event][field][chunk item]; the host sizes the event dimension by the most
-// events a package can have.
+// The sweeps run in FP64 (R = double) whatever the densities' storage: the
+// derivative amplifies the rounding of a point's position wherever a leg
+// grazes a cell face (a term 1/k_a), and on rough media (neighbouring cells
+// differing by factors of several) a package's derivative changes over
+// density changes of 1e-9 relative -- FP32 walks, which move the points by
+// 1e-7, would not follow it.  The forward sweep repeats the FP64 life
+// cycle's arithmetic (the same draws, walks and locate test), so with FP64
+// densities it follows the forward run's packages exactly.  It keeps, per
+// event, [kAttF] doubles in the workspace [event][field][chunk item]; the
+// host sizes the event dimension by the most events a package can have.
 #pragma once
 
 #include "mcrt_lane.hpp"
@@ -56,8 +60,8 @@ struct AttCounts {
 // Lowest axis in a 3-bit mask, or -1.
 MCRT_HD int att_axis(unsigned m) { return (m & 1u) ? 0 : ((m & 2u) ? 1 : ((m & 4u) ? 2 : -1)); }
 
-// One walk from o along k to the grid's boundary, with FP64 times and the
-// optical-depth sum of the life-cycle walks; returns the optical depth.
+// One walk from o along k to the grid's boundary, with FP64 times, as the
+// life-cycle walks; returns the optical depth.
 // DEP: deposits dep_full l, plus dep_part l for the part of each segment
 // before t_cut (a time from o), into the gradient.  GRAD: adds to g the
 // derivative of the optical depth with respect to o, each crossing's term
@@ -72,7 +76,6 @@ MCRT_HD R att_walk(const GridDev& G, Mem& M, const double o[3], const double k[3
   ray_begin<R, Mem::kGrid>(ry, G, o, k);
   const R kapR = (R)kap;
   const double tc = t_cut - ry.tin;  // in the walk's times (from the grid entry)
-  R tau_c = R(0);
   unsigned pmask = 0;  // planes of the crossing at the end of the last segment
   R prho = R(0);
   double pt = 0.0;
@@ -105,15 +108,7 @@ MCRT_HD R att_walk(const GridDev& G, Mem& M, const double o[3], const double k[3
       } else {
         pmask |= m;
       }
-      const R dtau = kapR * rs * seg;  // the compensated sum also takes the zero steps, as the life cycle's
-      if constexpr (sizeof(R) == sizeof(float)) {
-        const R y = dtau - tau_c;
-        const R t = ry.tau + y;
-        tau_c = (t - ry.tau) - y;
-        ry.tau = t;
-      } else {
-        ry.tau += dtau;
-      }
+      ry.tau += kapR * rs * seg;
       if (pos) ry.t = tm;
     }
     if (b.out) ry.active = false;
@@ -159,7 +154,6 @@ MCRT_HD void att_locate(const GridDev& G, Mem& M, const double o[3], const doubl
   Ray<R, double> ry;
   ray_begin<R, Mem::kGrid>(ry, G, o, k);
   const R kapR = (R)kap, tau_sR = (R)tau_s;
-  R tau_c = R(0);
   double last_t = ry.t;
   int last_cell = ry.active ? ray_cell(ry, G) : 0;
   while (ry.active) {
@@ -186,14 +180,7 @@ MCRT_HD void att_locate(const GridDev& G, Mem& M, const double o[3], const doubl
         last_cell = b.cell[d];
         last_t = tm;
       }
-      if constexpr (sizeof(R) == sizeof(float)) {
-        const R y = dtau - tau_c;
-        const R t = ry.tau + y;
-        tau_c = (t - ry.tau) - y;
-        ry.tau = t;
-      } else {
-        ry.tau += dtau;
-      }
+      ry.tau += dtau;
       if (pos) ry.t = tm;
     }
     if (b.out) ry.active = false;

@@ -825,19 +825,21 @@ __global__ void __launch_bounds__(kBundleThreads) k_peeldep(const PeelJobParams 
 
 // ---------------------------------------------------------------------------
 // The attached density gradient (mcrt_attached.hpp): one work item per lane,
-// its forward sweep and its reverse sweep back to back.  A plain grid over
+// its forward sweep and its reverse sweep back to back, in FP64 arithmetic
+// whatever the densities' storage (the FP32 path's densities are read as
+// FP32 and widened).  A plain grid over
 // the chunk's items -- each lane's work is one package's walks, done in
 // order, so there is no state machine to interleave; the workspace keeps
 // each item's events with the items of a chunk side by side, so lanes at the
 // same event of their packages touch adjacent words.  Deposits go straight to
 // the gradient as FP64 atomics.
 
-template <typename R, int GK>
+template <typename S, int GK>
 struct AttMem {
   static constexpr int kGrid = GK;
-  const R* __restrict__ rho_;
+  const S* __restrict__ rho_;  // the densities as stored (FP32 or FP64), read as FP64
   const RunParams& P;
-  __device__ R rho(int c) const { return rho_[c]; }
+  __device__ double rho(int c) const { return (double)rho_[c]; }
   __device__ const DetDev& det(int d) const { return P.det[d]; }
   __device__ const LamDev& lam(int l) const { return P.lam[l]; }
   __device__ const SrcDev& src(int s) const { return P.src[s]; }
@@ -852,12 +854,12 @@ struct AttMem {
   __device__ void att_over() const { atomicOr(P.work + kAttOverflow, 1ull); }
 };
 
-template <typename R, int GK>
+template <typename S, int GK>
 __global__ void __launch_bounds__(kBlock) k_attached(const RunParams P) {
-  AttMem<R, GK> M{static_cast<const R*>(P.rho), P};
+  AttMem<S, GK> M{static_cast<const S*>(P.rho), P};
   AttCounts c;
   const unsigned long long k = (unsigned long long)blockIdx.x * kBlock + threadIdx.x;
-  if (k < P.n_chunk) attached_item<R>(P, M, P.item0 + k, (int)k, c);
+  if (k < P.n_chunk) attached_item<double>(P, M, P.item0 + k, (int)k, c);
   const double s_abs = wave_sum(c.s_abs), s_esc = wave_sum(c.s_esc), s_trunc = wave_sum(c.s_trunc);
   const unsigned long long a0 = wave_sum_u64(c.x_path), a1 = wave_sum_u64(c.x_loc), a2 = wave_sum_u64(c.x_peel),
                            a3 = wave_sum_u64(c.n_ev), a4 = wave_sum_u64(c.n_pk), a5 = wave_sum_u64(c.n_pl),
@@ -1422,7 +1424,8 @@ void launch_life_c(const RunParams& P, int nblk, hipStream_t st) {
     launch_life_k<R, ADJ, kGridRegular, INST>(P, nblk, st);
 }
 
-// The attached gradient's kernel over one chunk: one lane per work item.
+// The attached gradient's kernel over one chunk: one lane per work item;
+// f32: the densities are stored in FP32.
 int launch_attached(const RunParams& P, bool f32, hipStream_t st) {
   const unsigned nb = (unsigned)((P.n_chunk + kBlock - 1) / kBlock);
   const int kind = P.G.kind;

@@ -823,12 +823,13 @@ int emu_peel(const mcrt_grid* grid, const void* rho, double kappa, double g, int
 }
 
 // The attached gradient's per-item code (mcrt_attached.hpp) on host buffers:
-// items one after another, every access checked, workspace reads checked to
+// items one after another, in FP64 whatever the densities' storage (R), as
+// the library runs it; every access checked, workspace reads checked to
 // follow a write of the same item.
-template <typename R, int GK>
+template <typename S, int GK>
 struct HostAttMem {
   static constexpr int kGrid = GK;
-  const R* rho_;
+  const S* rho_;  // as stored, read as FP64
   const GridDev& G;
   const host::Prepared& pr;
   const double* adj_;
@@ -839,9 +840,9 @@ struct HostAttMem {
   int ev_max;
   int n_chunk;
   bool over = false;
-  R rho(int c) const {
+  double rho(int c) const {
     check_cell(G, c, "density");
-    return rho_[c];
+    return (double)rho_[c];
   }
   const DetDev& det(int d) const {
     EMU_CHECK(d >= 0 && d < pr.P.n_det, "instrument", d, pr.P.n_det);
@@ -928,7 +929,7 @@ int emu_attached(const mcrt_grid* grid, const void* rho, const mcrt_optics* opti
     const int n = (int)std::min<unsigned long long>(chunk, P.n_items - c0);
     M.n_chunk = n;
     std::fill(ws_set.begin(), ws_set.end(), 0);
-    for (int k = 0; k < n; ++k) attached_item<R>(P, M, c0 + k, k, c);
+    for (int k = 0; k < n; ++k) attached_item<double>(P, M, c0 + k, k, c);
     ++launches;
   }
   if (M.over) return host::fail(MCRT_EOVERFLOW, "MCRT_ATTACHED: a package had more events than %d", ev);
