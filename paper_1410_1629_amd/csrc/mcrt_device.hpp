@@ -222,6 +222,9 @@ struct DetDev {
   // of the model box (half_x, half_y and inv_dpx, inv_dpy describe it), so
   // that its rays spread over many keys.
   int kn;
+  // Depth key of a queued ray: the projection of its origin on kd, from dlo
+  // in buckets of 1/dscale over the model box's projection (depth_key).
+  double dlo, dscale;
 };
 
 // Interleaves the low 16 bits of x (even bits) and y (odd bits).
@@ -249,6 +252,27 @@ MCRT_HD unsigned tile_sub(const DetDev& D, int kp) {
   const int iy = kp / D.kn, ix = kp - iy * D.kn;
   const unsigned m = (1u << D.tshift) - 1u;
   return morton2((unsigned)ix & m, (unsigned)iy & m) >> D.sub_shift;
+}
+
+// Depth of a peel ray's origin along kd, in 2^kDepthBits buckets over the
+// model box: the low bits of its second sort key (sort_sub).  The rays of
+// one pixel then run in order of where they start, so the lanes of a
+// wavefront that walk one column of cells start a few cells apart and read
+// the lines each other has just brought in; in any order they start anywhere
+// along the column, and a line is gone from the cache before the next lane
+// comes by.  `drop` coarsens the buckets (the low bits are cleared): the
+// adjoint's deposit walks sum into an LDS table, where lanes that move in
+// step would hit the same entry at once.
+constexpr int kDepthBits = 6;
+MCRT_HD unsigned depth_key(const DetDev& D, const double r[3], int drop = 0) {
+  const double t = ((r[0] * D.kd[0] + r[1] * D.kd[1] + r[2] * D.kd[2]) - D.dlo) * D.dscale;
+  return ((unsigned)fmin(fmax(floor(t), 0.0), (double)((1 << kDepthBits) - 1)) >> drop) << drop;
+}
+
+// Second sort key of a queued ray at r seen in key pixel kp: its place in
+// its tile, then its depth.
+MCRT_HD unsigned sort_sub(const DetDev& D, int kp, const double r[3], int drop = 0) {
+  return (tile_sub(D, kp) << kDepthBits) | depth_key(D, r, drop);
 }
 
 struct SrcDev {

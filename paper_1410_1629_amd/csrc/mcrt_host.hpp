@@ -466,6 +466,20 @@ inline void sed_key_grid(DetDev& D, const GridDev& G) {
   D.inv_dpy = kSedKeys / (2.0 * D.half_y);
 }
 
+// Depth buckets of an instrument's queued rays (depth_key): the projection
+// of the model box's corners on kd, cut into 2^kDepthBits equal parts.
+inline void depth_keys(DetDev& D, const GridDev& G) {
+  double lo = INFINITY, hi = -INFINITY;
+  for (int c = 0; c < 8; ++c) {
+    const double p[3] = {(c & 1) ? G.hi[0] : G.lo[0], (c & 2) ? G.hi[1] : G.lo[1], (c & 4) ? G.hi[2] : G.lo[2]};
+    const double t = p[0] * D.kd[0] + p[1] * D.kd[1] + p[2] * D.kd[2];
+    lo = std::min(lo, t);
+    hi = std::max(hi, t);
+  }
+  D.dlo = lo;
+  D.dscale = hi > lo ? (double)(1 << kDepthBits) / (hi - lo) : 0.0;
+}
+
 // Sort-key ranges of the frames (tile_key): a Morton index over tiles of
 // 2^tshift x 2^tshift pixels, the frames sharing kSortKeys keys (a power of
 // 4 per frame).  Returns the total number of keys.
@@ -612,8 +626,10 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
   }
   P.pix_lambda = off;
   out.n_images = (long long)P.comps * nl * off;
-  for (int d = 0; d < n_det; ++d)
+  for (int d = 0; d < n_det; ++d) {
     if (out.det[d].kind == kDetSed) sed_key_grid(out.det[d], P.G);
+    depth_keys(out.det[d], P.G);
+  }
   out.n_keys = tile_frames(out.det, n_det);
   out.src.assign(n_src, SrcDev{});
   for (int s = 0; s < n_src; ++s) {

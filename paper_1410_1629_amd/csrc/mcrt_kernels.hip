@@ -431,12 +431,15 @@ __device__ __forceinline__ unsigned long long queued_jobs(const unsigned long lo
 // scan of that matrix gives each (key, part) its first sorted position;
 // k_scatter starts an LDS counter per key there and hands positions out to
 // the part's rays, writing each ray's index and second key.  k_refine then
-// sorts each tile's run by the second key (the pixel inside the tile), one
-// workgroup per tile, the same way.  Slots a wavefront reserved but did not
-// fill (kNoKey) are skipped.  No global atomics: LDS counters do the
-// ranking; the order of rays with equal keys is arbitrary.
-constexpr int kSortThreads = 1024, kSortBlocks = host::kSortBlocks, kRefineThreads = 256, kSubKeys = 256;
-static_assert(host::kSortKeys <= (1 << 16) && kSubKeys <= 256, "a ray's keys share one word: key | sub << 16");
+// sorts each tile's run by the second key (the pixel inside the tile, then
+// the depth of the ray's origin), one workgroup per tile, the same way.
+// Slots a wavefront reserved but did not fill (kNoKey) are skipped.  No
+// global atomics: LDS counters do the ranking; the order of rays with equal
+// keys is arbitrary.
+constexpr int kSortThreads = 1024, kSortBlocks = host::kSortBlocks, kRefineThreads = 256,
+              kSubKeys = 256 << kDepthBits;
+
+static_assert(host::kSortKeys <= (1 << 16) && kSubKeys <= (1 << 16), "a ray's keys share one word: key | sub << 16");
 
 __device__ __forceinline__ void sort_part(unsigned long long n, unsigned long long& lo, unsigned long long& hi) {
   const unsigned long long per = (n + kSortBlocks - 1) / kSortBlocks;
@@ -465,7 +468,7 @@ __global__ void __launch_bounds__(kSortThreads) k_scatter(const unsigned* __rest
                                                           const unsigned long long* __restrict__ ctr,
                                                           unsigned long long cap, int n_keys,
                                                           const unsigned* __restrict__ starts,
-                                                          unsigned* __restrict__ idx, unsigned char* __restrict__ subs) {
+                                                          unsigned* __restrict__ idx, unsigned short* __restrict__ subs) {
   __shared__ unsigned h[host::kSortKeys];
   for (int i = threadIdx.x; i < n_keys; i += kSortThreads) h[i] = starts[(size_t)i * kSortBlocks + blockIdx.x];
   __syncthreads();
@@ -476,7 +479,7 @@ __global__ void __launch_bounds__(kSortThreads) k_scatter(const unsigned* __rest
     if (w != kNoKey) {
       const unsigned q = atomicAdd(h + (w & 0xffffu), 1u);
       idx[q] = (unsigned)j;
-      subs[q] = (unsigned char)(w >> 16);
+      subs[q] = (unsigned short)(w >> 16);
     }
   }
 }
@@ -551,26 +554,31 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_add(unsigned* __restrict_
 }
 
 // Workgroup k sorts the run [starts of key k, starts of key k + 1) of idx
-// by subs into perm.
+// by subs (the pixel inside the tile, then the depth) into perm.
 __global__ void __launch_bounds__(kRefineThreads) k_refine(const unsigned* __restrict__ starts,
                                                            const unsigned* __restrict__ idx,
-                                                           const unsigned char* __restrict__ subs,
+                                                           const unsigned short* __restrict__ subs,
                                                            unsigned* __restrict__ perm) {
+  constexpr int kPer = kSubKeys / kRefineThreads;  // counters per thread in the scan
+  static_assert(kSubKeys % kRefineThreads == 0, "whole counters per thread");
   __shared__ unsigned h[kSubKeys], scan[kRefineThreads];
   const unsigned lo = starts[(size_t)blockIdx.x * kSortBlocks], hi = starts[(size_t)(blockIdx.x + 1) * kSortBlocks];
   if (hi - lo <= 1u) {
     if (hi > lo && threadIdx.x == 0) perm[lo] = idx[lo];
     return;
   }
-  static_assert(kSubKeys == kRefineThreads, "one counter per thread");
-  h[threadIdx.x] = 0u;
+  for (int i = threadIdx.x; i < kSubKeys; i += kRefineThreads) h[i] = 0u;
   __syncthreads();
   for (unsigned i = lo + threadIdx.x; i < hi; i += kRefineThreads) atomicAdd(h + subs[i], 1u);
   __syncthreads();
-  unsigned total;
-  const unsigned c = h[threadIdx.x];
-  const unsigned ex = block_exclusive_scan(c, scan, &total);
-  h[threadIdx.x] = lo + ex;
+  unsigned own = 0, total;
+  for (int j = 0; j < kPer; ++j) own += h[threadIdx.x * kPer + j];
+  unsigned run = lo + block_exclusive_scan(own, scan, &total);
+  for (int j = 0; j < kPer; ++j) {
+    const unsigned c = h[threadIdx.x * kPer + j];
+    h[threadIdx.x * kPer + j] = run;
+    run += c;
+  }
   __syncthreads();
   for (unsigned i = lo + threadIdx.x; i < hi; i += kRefineThreads) perm[atomicAdd(h + subs[i], 1u)] = idx[i];
 }
@@ -1239,7 +1247,7 @@ struct Spans {
 // Device memory of the peel-ray queue: rays, their sorted order (and the
 // order after the first sort pass with the second keys), the sort's count
 // matrix (keys x kSortBlocks), its scan and the scan's tile totals.
-constexpr size_t kQueueBytesPerRay = sizeof(PeelJob) + 3 * sizeof(unsigned) + 1;
+constexpr size_t kQueueBytesPerRay = sizeof(PeelJob) + 3 * sizeof(unsigned) + sizeof(unsigned short);
 struct PeelQueue {
   unsigned char* ptr = nullptr;
   hipStream_t st = nullptr;
@@ -1247,7 +1255,7 @@ struct PeelQueue {
   long long n_keys = 0;
   PeelJob* jobs = nullptr;
   unsigned *keys = nullptr, *perm = nullptr, *idx = nullptr, *counts = nullptr, *starts = nullptr, *tiles = nullptr;
-  unsigned char* subs = nullptr;
+  unsigned short* subs = nullptr;
   ~PeelQueue() {
     if (ptr) (void)hipFreeAsync(ptr, st);
   }
@@ -1277,7 +1285,7 @@ int make_peel_queue(const mcrt_opts& o, const host::Prepared& pr, unsigned long 
   const size_t off_perm = off_keys + align256(sizeof(unsigned) * cap);
   const size_t off_idx = off_perm + align256(sizeof(unsigned) * cap);
   const size_t off_subs = off_idx + align256(sizeof(unsigned) * cap);
-  const size_t off_cnt = off_subs + align256(cap);
+  const size_t off_cnt = off_subs + align256(sizeof(unsigned short) * cap);
   const size_t off_start = off_cnt + align256(sizeof(unsigned) * n_cnt);
   const size_t off_tiles = off_start + align256(sizeof(unsigned) * (n_cnt + 1));
   const size_t bytes = off_tiles + align256(sizeof(unsigned) * (n_cnt / kScanTile + 1));
@@ -1287,7 +1295,7 @@ int make_peel_queue(const mcrt_opts& o, const host::Prepared& pr, unsigned long 
   q.keys = reinterpret_cast<unsigned*>(q.ptr + off_keys);
   q.perm = reinterpret_cast<unsigned*>(q.ptr + off_perm);
   q.idx = reinterpret_cast<unsigned*>(q.ptr + off_idx);
-  q.subs = q.ptr + off_subs;
+  q.subs = reinterpret_cast<unsigned short*>(q.ptr + off_subs);
   q.counts = reinterpret_cast<unsigned*>(q.ptr + off_cnt);
   q.starts = reinterpret_cast<unsigned*>(q.ptr + off_start);
   q.tiles = reinterpret_cast<unsigned*>(q.ptr + off_tiles);
@@ -1547,6 +1555,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const int ev_k = att ? (int)kAttF : 1 + n_det + (adjoint && adj_abs_dev ? 1 : 0);  // T, q per frame, then B of the path
   const size_t per_item = sizeof(double) * ((size_t)ev_max * ev_k + (att ? 0 : 1 + (optg ? 4 : 0)));
   const bool queued = peel && opts->peel_queue != -1 && !att;
+  P.depth_drop = adjoint ? kDepthDropAdjoint : 0;
   size_t free_b = 0, total_b = 0;
   HIPCHK(hipMemGetInfo(&free_b, &total_b));
   unsigned long long most = P.n_items;

@@ -77,16 +77,24 @@ enum Phase : int {
 // kEventSat) of chunk package `slot`, with v = W Phi / D^2 (so its
 // contribution is C = v e^-tau), ii its index in the image block (the pixel
 // it adds to, or the dL/dI it is weighted with) and lam its wavelength.
-// key and sub are its sort keys (tile_key, tile_sub).
+// key is its first sort key (tile_key); the device queue keeps both sort
+// keys in RunParams::keys, the second one (sort_sub) outside the ray.
 constexpr int kEventSat = 65535;
 struct PeelJob {
   double r[3];
   double v;
   long long ii;
-  unsigned key, slot, lam;  // key and sub: sort keys (the device queue holds them in RunParams::keys)
+  unsigned key, slot, lam;
   unsigned short e;
-  unsigned char d, sub;
+  unsigned char d;
 };
+
+// Depth bits the adjoint's queued rays drop (RunParams::depth_drop).
+// Measured with the tape (spiral, 1e7 packages): deposit walks 23.6 ms with 4
+// depth bits, 26.0 with 6 and 26.0 with none; the forward's peel walks on
+// the clumpy 512^3 disk (1e8 packages): 1063 ms with none, 716 / 645 / 611 ms
+// with 4 / 5 / 6.
+constexpr int kDepthDropAdjoint = 2;
 
 struct RunParams {
   GridDev G;
@@ -137,6 +145,9 @@ struct RunParams {
   // (filled from the tape) and queues the deposit walks of the event's peel
   // rays with q != 0 (walked here when the queue is full)
   int dep_jobs;
+  // low bits of the queued rays' depth keys cleared (sort_sub): 0 in the
+  // forward run, 2 in the adjoint, whose deposit walks sum into LDS
+  int depth_drop;
 };
 
 // The life-cycle walks keep their times in FP64 whatever R is (see Ray).
@@ -415,7 +426,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
             const int comp = ((P.flags & kFlagSplit) && !L.is_emit) ? 1 : 0;
             const long long ii = ((long long)comp * P.n_lambda + L.lam) * P.pix_lambda + D.off + L.pix;
             const int kp = key_pixel<Mem::kInst>(D, L.r, L.pix);
-            M.store_job(slot, L.r, -q * L.kap, ii, tile_key(D, kp), tile_sub(D, kp), (unsigned)L.slot,
+            M.store_job(slot, L.r, -q * L.kap, ii, tile_key(D, kp), sort_sub(D, kp, L.r, P.depth_drop), (unsigned)L.slot,
                         L.n < kEventSat ? L.n : kEventSat, L.det, (unsigned)L.lam);
           }
           ++L.det;
@@ -434,7 +445,7 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
           const int comp = ((P.flags & kFlagSplit) && !L.is_emit) ? 1 : 0;
           const long long ii = ((long long)comp * P.n_lambda + L.lam) * P.pix_lambda + D.off + L.pix;
           const int kp = key_pixel<Mem::kInst>(D, L.r, L.pix);
-          M.store_job(slot, L.r, L.W * ph * inv_d2, ii, tile_key(D, kp), tile_sub(D, kp), (unsigned)L.slot,
+          M.store_job(slot, L.r, L.W * ph * inv_d2, ii, tile_key(D, kp), sort_sub(D, kp, L.r, P.depth_drop), (unsigned)L.slot,
                       L.n < kEventSat ? L.n : kEventSat, L.det,
                       (unsigned)L.lam);
           ++L.n_pl;

@@ -182,6 +182,7 @@ struct HostLifeMem {
   unsigned long long x_queue = 0, d_queue = 0;
   // adjoint peel-job queue
   std::vector<PeelJob>* jobs = nullptr;
+  std::vector<unsigned short>* job_subs = nullptr;  // each ray's second sort key (the library's keys word)
   unsigned long long job_cap = 0, job_next = 0;
   long long n_keys = 0;
   unsigned long long job_slot() { return job_next++; }
@@ -234,7 +235,7 @@ struct HostLifeMem {
     EMU_CHECK(d >= 0 && d < pr.P.n_det, "job frame", d, pr.P.n_det);
     EMU_CHECK(lam < (unsigned)pr.P.n_lambda, "job wavelength", lam, pr.P.n_lambda);
     EMU_CHECK(e >= 0 && e <= kEventSat, "job event", e, kEventSat);
-    EMU_CHECK(sub < 256u, "second sort key", sub, 256);
+    EMU_CHECK(sub < (256u << kDepthBits), "second sort key", sub, 256 << kDepthBits);
     PeelJob& J = (*jobs)[slot];
     J.r[0] = r[0];
     J.r[1] = r[1];
@@ -246,7 +247,7 @@ struct HostLifeMem {
     J.lam = lam;
     J.e = (unsigned short)e;
     J.d = (unsigned char)d;
-    J.sub = (unsigned char)sub;
+    (*job_subs)[slot] = (unsigned short)sub;
   }
   // the forward run's tape (host memory here): every entry bounds-checked
   double* tape = nullptr;
@@ -351,7 +352,8 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, GK, INST>& M, const RunParams& P
   for (size_t i = 0; i < counts.size(); ++i) starts[i + 1] = starts[i] + counts[i];
   EMU_CHECK(starts.back() == n_valid, "sorted rays", starts.back(), n_valid);
   std::vector<unsigned> idx(n_valid, 0), perm(n_valid, 0);
-  std::vector<unsigned char> subs(n_valid, 0), filled(n_valid, 0);
+  std::vector<unsigned short> subs(n_valid, 0);
+  std::vector<unsigned char> filled(n_valid, 0);
   for (int b = 0; b < nb; ++b) {
     std::vector<unsigned> h(n_keys);
     for (long long k = 0; k < n_keys; ++k) h[k] = starts[(size_t)k * nb + b];
@@ -360,7 +362,7 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, GK, INST>& M, const RunParams& P
       EMU_CHECK(q < n_valid && !filled[q], "sorted position", q, n_valid);
       filled[q] = 1;
       idx[q] = (unsigned)j;
-      subs[q] = jobs[j].sub;
+      subs[q] = (*M.job_subs)[j];
     }
   }
   // second pass: each tile's run by the second key
@@ -368,10 +370,10 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, GK, INST>& M, const RunParams& P
   for (long long k = 0; k < n_keys; ++k) {
     const unsigned lo = starts[(size_t)k * nb], hi = starts[(size_t)(k + 1) * nb];
     EMU_CHECK(lo <= hi && hi <= n_valid, "tile run", hi, n_valid);
-    unsigned h[256] = {0};
+    std::vector<unsigned> h(256 << kDepthBits, 0);
     for (unsigned i = lo; i < hi; ++i) ++h[subs[i]];
     unsigned run = lo;
-    for (int c = 0; c < 256; ++c) {
+    for (int c = 0; c < (256 << kDepthBits); ++c) {
       const unsigned t = h[c];
       h[c] = run;
       run += t;
@@ -390,7 +392,8 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, GK, INST>& M, const RunParams& P
     const PeelJob& J = jobs[perm[qi]];
     if (qi > 0) {
       const PeelJob& Jp = jobs[perm[qi - 1]];
-      EMU_CHECK(Jp.key < J.key || (Jp.key == J.key && Jp.sub <= J.sub), "sorted order", qi, n_valid);
+      const unsigned sp = (*M.job_subs)[perm[qi - 1]], sq = (*M.job_subs)[perm[qi]];
+      EMU_CHECK(Jp.key < J.key || (Jp.key == J.key && sp <= sq), "sorted order", qi, n_valid);
     }
     int d = 0;
     while (d + 1 < P.n_det && (unsigned)M.det(d + 1).key_off <= J.key) ++d;
@@ -473,6 +476,7 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
     pr.src[pr.cell_src].cum = cum.data() + 1;
   }
   RunParams P = pr.P;
+  P.depth_drop = ADJ ? kDepthDropAdjoint : 0;  // as the library
   P.images = images;
   P.absorbed = ((opts->flags & MCRT_ABSORB) && !ADJ) ? absorbed : nullptr;
   P.adj = adj;
@@ -568,12 +572,15 @@ int emu_life(const mcrt_grid* grid, const void* rho, const mcrt_optics* optics, 
   if (g_chunk_items > 0) chunk = std::min<unsigned long long>(chunk, (unsigned long long)g_chunk_items);
   if (opts->max_chunk > 0) chunk = std::min<unsigned long long>(chunk, (unsigned long long)opts->max_chunk);
   std::vector<PeelJob> jobs;
+  std::vector<unsigned short> job_subs;
   if (peel && opts->peel_queue != -1) {
     unsigned long long qcap =
         opts->peel_queue > 0 ? (unsigned long long)opts->peel_queue : chunk * (unsigned long long)P.n_det * 8ull;
     if (opts->peel_queue == 0) qcap = std::min(std::max(qcap, 1ull << 16), 1ull << 28);
     jobs.resize(qcap);
+    job_subs.assign(qcap, 0);
     M.jobs = &jobs;
+    M.job_subs = &job_subs;
     M.job_cap = qcap;
     M.n_keys = pr.n_keys;
     P.jobs = jobs.data();
