@@ -348,8 +348,12 @@ __device__ __forceinline__ void life_body(const RunParams& P) {
   }
 }
 
+// Every variant asks for two wavefronts per SIMD: left free, the compiler
+// took the lean rectilinear adjoint to 256 VGPRs and an AGPR, one wavefront
+// per SIMD (PowCub adjoint life kernel 176 -> 301 ms); with the attribute
+// every variant fits without spills (236-251 VGPRs lean).
 template <typename R, bool ADJ, int GK, bool INST>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(INST ? 2 : 1))) k_life(const RunParams P) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_life(const RunParams P) {
   life_body<R, ADJ, GK, INST>(P);
 }
 
