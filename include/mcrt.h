@@ -194,8 +194,9 @@ typedef struct {
  * brick_shape tune the run without changing its results (0 = library
  * choice): blocks per compute unit of the persistent kernels; how many
  * lanes of a wavefront wait before the wavefront processes events (library
- * choice: 32 in the forward run, 32 and 48 in the adjoint's two replays of
- * each package; a value set here applies to every launch); and the
+ * choice: 32 in the forward run -- 24 when the densities exceed 256 MiB and
+ * are walked from HBM -- and 32 and 48 in the adjoint's two replays of each
+ * package; a value set here applies to every launch); and the
  * brick of the library's internal cell layout, MCRT_BRICK(lx, ly, lz) for
  * bricks of 2^lx x 2^ly x 2^lz cells (each log2 in [0, 7], at most 2^10
  * cells).  The default brick fills one 128-byte cache line with the most

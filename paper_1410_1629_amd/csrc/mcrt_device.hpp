@@ -65,7 +65,12 @@ struct TreeNode {
 // most from a large batch.  Measured on the spiral, PowCub and k-d tree
 // workloads (1e7 packages): forward 32 (PowCub -7%, k-d tree -11%, spiral
 // unchanged against 16); adjoint 32 / 48 (-19% to -28% against 16 / 16).
-constexpr int kBatchForward = 32, kBatchPassA = 32, kBatchPassB = 48;
+// A grid whose densities exceed the 256 MB MALL is walked from HBM, each
+// step waits longer, and idle walkers cost more: there the forward takes
+// 24 (clumpy 512^3 disk, 1e8 packages: life kernel 1436 ms against 1495 at
+// 32, 1432 at 20, 1458 at 28).
+constexpr int kBatchForward = 32, kBatchForwardHbm = 24, kBatchPassA = 32, kBatchPassB = 48;
+constexpr long long kMallBytes = 256ll << 20;
 // The ray kernels -- the peel-queue walks (optical depth, deposit walks) and
 // the trace and peel-off entry points -- refill a lane with the next ray once
 // this many of the wavefront's lanes have finished: measured on the spiral,

@@ -606,7 +606,8 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
   P.w_min = opts->w_min;
   P.max_scatter = opts->max_scatter;
   P.flags = opts->flags;
-  P.batch = opts->event_batch > 0 ? opts->event_batch : kBatchForward;
+  const long long rho_bytes = (long long)P.G.ncell_pad * elem_bytes(opts->precision);
+  P.batch = opts->event_batch > 0 ? opts->event_batch : (rho_bytes > kMallBytes ? kBatchForwardHbm : kBatchForward);
 
   out.lam.assign(nl, LamDev{});
   for (int l = 0; l < nl; ++l) {
