@@ -372,8 +372,10 @@ def spiral_step(B, W, dev, steps):
                         "gradient_max_rel_fp32_vs_fp64": max_rel(grad32.cpu().numpy(), grad64.cpu().numpy()),
                         "images_mc_noise_rel_l1": rel_l1(ia, ib) / 2 ** 0.5,
                         "gradient_mc_noise_rel_l1": rel_l1(ga, gb) / 2 ** 0.5,
+                        "images_mc_noise_max_rel": max_rel(ia.cpu().numpy(), ib.cpu().numpy()),
+                        "gradient_mc_noise_max_rel": max_rel(ga.cpu().numpy(), gb.cpu().numpy()),
                         "note": "both gradients take the FP32 step's dL/dI; noise = rel_L1 of two independent "
-                                "keys / sqrt(2)"}
+                                "keys / sqrt(2); the noise max_rel is that of the two keys' arrays"}
     return out
 
 
