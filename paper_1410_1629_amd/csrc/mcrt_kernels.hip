@@ -1125,19 +1125,30 @@ int persistent_grid(K kernel, int blocks_per_cu, int* grid_out) {
 }
 
 // Launches a persistent kernel with a full-occupancy grid of kBlock threads.
+// (blocks_per_cu > 0: that many workgroups per compute unit instead.)
 template <typename K, typename Params>
-int launch_persistent(K kernel, const Params& P, hipStream_t st) {
+int launch_persistent(K kernel, const Params& P, hipStream_t st, int blocks_per_cu = 0) {
   int nblk = 0;
-  if (int e = persistent_grid(kernel, 0, &nblk)) return e;
+  if (int e = persistent_grid(kernel, blocks_per_cu, &nblk)) return e;
   hipLaunchKernelGGL(kernel, dim3(nblk), dim3(kBlock), 0, st, P);
   return 0;
 }
 
 // Launches the grid kind's variant of a persistent kernel.
 template <typename Params, typename R, typename K>
-int launch_by_kind(const Params& P, hipStream_t st, K regular, K rect, K tree) {
-  return launch_persistent(P.G.kind == kGridRect ? rect : (P.G.kind == kGridTree ? tree : regular), P, st);
+int launch_by_kind(const Params& P, hipStream_t st, K regular, K rect, K tree, int blocks_per_cu = 0) {
+  return launch_persistent(P.G.kind == kGridRect ? rect : (P.G.kind == kGridTree ? tree : regular), P, st,
+                           blocks_per_cu);
 }
+
+// Workgroups per compute unit of the trace kernel.  Its rays are unrelated
+// (no two lanes share lines), so fewer walkers thrash each XCD's 4 MB L2
+// less: 4e6 random rays, 1.82 / 1.77 / 1.67 / 1.58e11 crossings/s on the
+// spiral's grid with 2 / 3 / 4 / all it fits (6), 1.71 / 1.72 / 1.60 /
+// 1.57e11 on the clumpy 512^3 grid.  The sorted peel rays are the opposite
+// case: their lanes share lines, and their walk wants every wavefront it
+// can get (clumpy: 612 ms at 5 workgroups per CU, 982 at 2).
+constexpr int kTraceBlocksPerCu = 2;
 
 unsigned stream_blocks(long long n) { return (unsigned)std::min<long long>((n + kBlock - 1) / kBlock, 16384); }
 
@@ -1894,9 +1905,11 @@ int trace_impl(const mcrt_grid* grid, const void* rho_dev, double kappa, int pre
   P.work = reinterpret_cast<unsigned long long*>(base);
   P.counters = P.work + 1;
   const int r = f32 ? launch_by_kind<TraceParams, float>(P, st, k_trace<float, kGridRegular>,
-                                                         k_trace<float, kGridRect>, k_trace<float, kGridTree>)
+                                                         k_trace<float, kGridRect>, k_trace<float, kGridTree>,
+                                                         kTraceBlocksPerCu)
                     : launch_by_kind<TraceParams, double>(P, st, k_trace<double, kGridRegular>,
-                                                          k_trace<double, kGridRect>, k_trace<double, kGridTree>);
+                                                          k_trace<double, kGridRect>, k_trace<double, kGridTree>,
+                                                          kTraceBlocksPerCu);
   if (r) return r;
   HIPCHK(hipGetLastError());
   if (crossings_host || lists) {

@@ -234,3 +234,25 @@ def test_attached_full_size_adjoint_workload_time(B, W):
     g = out["attached"][0]
     assert np.isfinite(g).all() and np.abs(g).max() > 0
     _say("  rel_L1 attached vs detached: %.3e" % rel_l1(g, out["detached, replay"][0]))
+
+
+def test_autograd_attached_estimator(B, W):
+    # RTImage with adjoint_estimator = "attached": its backward pass is the
+    # attached gradient of the C ABI (no tape), bit for bit up to atomic order
+    import torch
+    from paper_1410_1629_amd import autograd
+    _say("autograd: RTImage with the attached estimator")
+    prob = dict(_problem(W, 1, n_packages=2000), adjoint_estimator="attached")
+    rho = B.density_tensor(prob).clone().requires_grad_(True)
+    images = autograd.render(prob, rho)
+    w = torch.as_tensor(np.random.default_rng(3).standard_normal(tuple(images.shape)), device="cuda")
+    (images * w).sum().backward()
+    g_ref, _ = _attached(B, prob, rho.detach(), w.contiguous())
+    check(rho.grad.double().cpu().numpy(), g_ref.cpu().numpy(), 1e-6, "autograd vs C ABI: attached gradient", _say)
+    with pytest.raises(ValueError):
+        autograd.render(dict(prob, adjoint_estimator="pathwise"), rho)
+    nl = len(prob["kappa"])
+    with pytest.raises(ValueError):
+        autograd.RTImageOptics.apply(rho, torch.tensor(prob["albedo"], device="cuda"),
+                                     torch.tensor(prob["g"], device="cuda"),
+                                     torch.ones((len(prob["sources"]), nl), dtype=torch.float64, device="cuda"), prob)
