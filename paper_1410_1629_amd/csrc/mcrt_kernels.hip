@@ -291,10 +291,9 @@ struct PeelMem {
 // launch it, once per grid kind (GK, kGrid*) and with or without the
 // handling of instruments other than frames -- SED instruments, cameras and
 // their walks to the eye -- and of the adjoint's optics and absorbed-tally
-// gradients (INST).  The FP64 kernel and the full FP32 variants ask for two
-// wavefronts per SIMD, which their register use would otherwise just miss
-// (one accumulation register beyond 256 halves the occupancy); the lean FP32
-// variants fit without the request, and run faster without it.
+// gradients (INST).  Every variant asks for two wavefronts per SIMD, which
+// its register use could otherwise just miss (one accumulation register
+// beyond 256 halves the occupancy).
 template <typename R, bool ADJ, int GK, bool INST>
 __device__ __forceinline__ void life_body(const RunParams& P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2], job_slots[kWavesPerBlock][2];
