@@ -75,7 +75,11 @@ KERNELS = {
     "peel_tau_adjoint": "void mcrt::k_peeltau<float, true, 0, false>(mcrt::PeelJobParams)",
     "peel_deposit": "void mcrt::k_peeldep<float, 0, false>(mcrt::PeelJobParams)",
     "trace": "void mcrt::k_trace<float, 0>(mcrt::TraceParams)",
+    "attached": "void mcrt::k_attached<float, 0>(mcrt::RunParams)",
 }
+# the attached gradient's workspace: 11 FP64 values per event, written in the
+# forward sweep and read back in the reverse sweep
+BYTES_PER_ATTACHED_EVENT = 2 * 11 * 8
 HEADLINE = "clumpy"
 PROFILE_FILES = {"clumpy": "life_and_peel_kernels_clumpy_512cubed_1e8_fp32.md",
                  "spiral": "life_and_peel_kernels_spiral_256x256x64_1e7_fp32.md"}
@@ -414,6 +418,48 @@ def grid_leg(B, prob, dev, note):
     return {"workload": "%s, %s, %d packages" % (prob["name"], note, n_pkg), "cells": int(rho.numel()),
             "packages_per_s": n_pkg / wall, "ms_per_step": wall * 1e3, "forward_ms": sf["kernel_ms"],
             "adjoint_ms": sb["kernel_ms"], "crossings_per_s": x / wall}
+
+
+def attached_leg(B, W, dev):
+    """The attached (pathwise) density gradient of the adjoint workload (64^3
+    lognormal grid, 128^2 face-on frame, 1e7 packages; FP32 densities, FP64
+    sweeps), after one untimed call, beside the detached adjoint of the same
+    dL/dI with and without the forward run's tape.  Roofline of k_attached:
+    4 B per crossing that reads a density (every walk but the peel rays'
+    deposit walks), 8 B per gradient deposit and per dL/dI read, and the
+    workspace's 2 x 88 B per event (emission and scatterings)."""
+    import torch
+    prob = W.adjoint(n_packages=10_000_000, precision=1)
+    rho = B.density_tensor(prob, dev)
+    images = torch.empty(B.image_shape(prob), dtype=torch.float64, device=dev)
+    tape = B.new_tape(prob, dev)
+    B.run_photons(prob, rho, images, None, tape=tape)
+    adj = 2.0 * (images - 0.9 * images)
+    grad = torch.empty(rho.numel(), dtype=torch.float64, device=dev)
+    out = {"workload": "adjoint_lognormal_64: 64^3 i.i.d. lognormal densities, 128x128 face-on frame, "
+                       "10000000 packages; the attached gradient of an image loss"}
+    for name, kw in (("attached", dict(attached=True)), ("detached_replay", {}), ("detached_tape", dict(tape=tape))):
+        B.backward_density(prob, rho, adj, grad, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = B.backward_density(prob, rho, adj, grad, **kw)
+        torch.cuda.synchronize()
+        out[name + "_ms"] = (time.perf_counter() - t0) * 1e3
+        if name == "attached":
+            x_all = st["x_path"] + st["x_locate"] + st["x_peel"]
+            alg = ((x_all - st["d_queue"]) * BYTES_PER_CROSSING[1] + st["deposits"] * BYTES_PER_DEPOSIT +
+                   st["peels"] * BYTES_PER_PIXEL + (st["events"] + st["packages"]) * BYTES_PER_ATTACHED_EVENT)
+            launches = st["life_launches"]
+            launch_s = st["life_ms"] / 1e3 / launches
+            achieved = alg / launches / launch_s / 1e9
+            out["packages_per_s"] = prob["n_packages"] / (st["kernel_ms"] / 1e3)
+            out["crossings_per_s"] = x_all / (st["life_ms"] / 1e3)
+            out["roofline"] = {"kernel": KERNELS["attached"], "bound": "hbm", "achieved": achieved,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                               "traffic": None, "launch_ms": launch_s * 1e3, "launches_per_step": launches,
+                               "algorithmic_bytes_per_launch": alg / launches,
+                               "level": "MALL: the 1 MiB grid fits in the 256 MB MALL"}
+    return out
 
 
 def W_f32(a):
@@ -841,6 +887,7 @@ def main():
         out["kdtree_grid"] = grid_leg(B, W.kdtree_spiral(precision=1), dev,
                                       "leaves halved along their longest side while their dust mass exceeds 3e-4")
         out["panchromatic"] = panchromatic_leg(B, dev)
+        out["attached_gradient"] = attached_leg(B, W, dev)
     print(json.dumps(out), flush=True)
 
 

@@ -286,7 +286,12 @@ uint64_t mcrt_tape_bytes(const mcrt_optics *optics, int n_det, const mcrt_opts *
  * launches (the call runs its packages in chunks; the adjoint launches the
  * kernel twice per chunk).  life_ms is the sum over those launches; queue_ms
  * = sort_ms (the peel-ray sort) + peel_ms (the queue's optical-depth walks)
- * + dep_ms (the adjoint's deposit walks), each summed over the chunks. */
+ * + dep_ms (the adjoint's deposit walks), each summed over the chunks.
+ * With MCRT_ATTACHED: x_path counts the forward sweep's path walks and the
+ * reverse sweep's leg walks, x_locate the locate walks, x_peel both walks of
+ * every peel ray, deposits the gradient deposits; d_queue the crossings of
+ * the peel rays' deposit walks (no density loads); life_ms and
+ * life_launches the attached kernel (one launch per chunk). */
 typedef struct {
     double emitted, absorbed, escaped, truncated;
     uint64_t x_path, x_locate, x_peel, events, packages, peels, deposits;

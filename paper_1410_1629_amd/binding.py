@@ -103,6 +103,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libmcrt.so is not built (%s); run `python -m paper_1410_1629_amd.build` or "
                            "__graft_entry__.build()" % LIB_PATH)
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # one runtime in the process (loaded the other way round, the library's
+    # first HIP call found no device)
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     lib.run_photons.argtypes = [C.POINTER(Grid), P, C.POINTER(Optics), C.c_int, C.POINTER(Source), C.c_int,

@@ -55,6 +55,7 @@ enum AttField : int { AF_RX = 0, AF_RY, AF_RZ, AF_W, AF_KX, AF_KY, AF_KZ, AF_T, 
 struct AttCounts {
   double s_abs = 0.0, s_esc = 0.0, s_trunc = 0.0;
   unsigned long long x_path = 0, x_loc = 0, x_peel = 0, n_ev = 0, n_pk = 0, n_pl = 0, n_dep = 0;
+  unsigned long long x_dep = 0;  // crossings of the peel rays' deposit walks (part of x_peel; no density loads)
 };
 
 // Lowest axis in a 3-bit mask, or -1.
@@ -308,6 +309,7 @@ MCRT_HD void attached_item(const RunParams& P, Mem& M, unsigned long long item, 
         unsigned long long nd = 0;
         att_deposit<R>(G, M, re, D.kd, -q * kap, nd);
         cnt.x_peel += nd;
+        cnt.x_dep += nd;
         cnt.n_dep += nd;
       }
     }

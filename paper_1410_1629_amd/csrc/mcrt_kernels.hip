@@ -96,8 +96,10 @@ constexpr int kWavesPerBlock = kBlock / 64;
 // [8..10] FP64 luminosity stats, [16..22] crossing and event counts,
 // [24] next peel-job slot, [25] next sorted job of the optical-depth walks,
 // [26] and [27] crossings and deposits of the queued walks, [28] next chunk
-// of the deposit walks.
-constexpr int kJobCounter = 24, kKeyCounter = 25, kQueueCrossings = 26, kDepCounter = 28, kAttOverflow = 29;
+// of the deposit walks, [29] a package beyond the attached gradient's
+// workspace, [30] crossings of its peel rays' deposit walks.
+constexpr int kJobCounter = 24, kKeyCounter = 25, kQueueCrossings = 26, kDepCounter = 28, kAttOverflow = 29,
+              kAttDepCrossings = 30;
 // Deposit-queue slots are reserved per wavefront in chunks (one global
 // atomic per chunk); slots a wavefront reserved but did not fill are marked
 // with kNoKey when it exits, and the sort skips them.
@@ -874,8 +876,9 @@ __global__ void __launch_bounds__(kBlock) k_attached(const RunParams P) {
   const double s_abs = wave_sum(c.s_abs), s_esc = wave_sum(c.s_esc), s_trunc = wave_sum(c.s_trunc);
   const unsigned long long a0 = wave_sum_u64(c.x_path), a1 = wave_sum_u64(c.x_loc), a2 = wave_sum_u64(c.x_peel),
                            a3 = wave_sum_u64(c.n_ev), a4 = wave_sum_u64(c.n_pk), a5 = wave_sum_u64(c.n_pl),
-                           a6 = wave_sum_u64(c.n_dep);
+                           a6 = wave_sum_u64(c.n_dep), a7 = wave_sum_u64(c.x_dep);
   if (__lane_id() == 0) {
+    atomicAdd(P.work + kAttDepCrossings, a7);
     atomic_add_f64(P.dstats + 0, s_abs);
     atomic_add_f64(P.dstats + 1, s_esc);
     atomic_add_f64(P.dstats + 2, s_trunc);
@@ -1719,7 +1722,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
         if (int e = queue_phase(false)) return e;
     }
   } else if (att) {
-    if (int e = reset_counters(ctr, kAttOverflow, 1, st)) return e;
+    if (int e = reset_counters(ctr, kAttOverflow, 2, st)) return e;
     for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
       P.item0 = c0;
       P.n_chunk = std::min(chunk, P.n_items - c0);
@@ -1811,6 +1814,10 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     stats->peel_ms = ms_peel;
     stats->dep_ms = ms_dep;
     stats->d_queue = xq[1];
+    if (att) {  // the attached kernel: the crossings of its peel rays' deposit walks
+      HIPCHK(hipMemcpyAsync(&stats->d_queue, ctr + kAttDepCrossings, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
     stats->life_launches = launches;
   }
   return 0;

@@ -954,6 +954,7 @@ int emu_attached(const mcrt_grid* grid, const void* rho, const mcrt_optics* opti
     stats->packages = c.n_pk;
     stats->peels = c.n_pl;
     stats->deposits = c.n_dep;
+    stats->d_queue = c.x_dep;
     stats->life_launches = launches;
   }
   return 0;
