@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmcrt.so")
 SOURCES = [os.path.join(CSRC, "mcrt_kernels.hip")]
-DEPENDS = SOURCES + [os.path.join(CSRC, h) for h in ("mcrt_device.hpp", "mcrt_lane.hpp", "mcrt_host.hpp")] + [
+DEPENDS = SOURCES + [os.path.join(CSRC, h) for h in ("mcrt_device.hpp", "mcrt_lane.hpp", "mcrt_host.hpp", "mcrt_attached.hpp")] + [
     os.path.join(INCLUDE, "mcrt.h")]
 # the memory-system probes the roofline is measured against (not the transport path)
 PROBES_LIB = os.path.join(HERE, "libmcrt_probes.so")
