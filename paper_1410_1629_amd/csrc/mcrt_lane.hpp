@@ -51,8 +51,6 @@
 //     again, without deposits).
 #pragma once
 
-#pragma once
-
 #include "mcrt_device.hpp"
 
 namespace mcrt {
