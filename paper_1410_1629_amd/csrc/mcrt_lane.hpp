@@ -51,6 +51,8 @@
 //     again, without deposits).
 #pragma once
 
+#pragma once
+
 #include "mcrt_device.hpp"
 
 namespace mcrt {
