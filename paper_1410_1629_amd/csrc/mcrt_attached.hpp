@@ -83,14 +83,15 @@ MCRT_HD R att_walk(const GridDev& G, Mem& M, const double o[3], const double k[3
   while (ry.active) {
     WalkBlock<kBlockWalk, R, double> b;
     ray_next_block(ry, b, G, M);
+    // sub-steps past b.n (the last valid cell repeated) are masked rather
+    // than skipped, so that the block's density loads stay in flight together
 #pragma unroll
     for (int d = 0; d < kBlockWalk; ++d) {
-      if (d >= b.n) break;
-      const unsigned m = (b.adv >> (3 * d)) & 7u;
+      const unsigned m = (b.adv >> (3 * d)) & 7u;  // 0 past b.n
       const double tm = b.tend[d];
-      R seg = (R)(tm - ry.t);
-      const bool pos = seg > R(0);
-      seg = pos ? seg : R(0);
+      const R s0 = (R)(tm - ry.t);
+      const bool pos = d < b.n && s0 > R(0);
+      const R seg = pos ? s0 : R(0);
       const R rs = b.rho[d];
       if (pos) {
         if (GRAD) {
@@ -109,7 +110,7 @@ MCRT_HD R att_walk(const GridDev& G, Mem& M, const double o[3], const double k[3
       } else {
         pmask |= m;
       }
-      ry.tau += kapR * rs * seg;
+      ry.tau += pos ? kapR * rs * seg : R(0);
       if (pos) ry.t = tm;
     }
     if (b.out) ry.active = false;
@@ -160,29 +161,56 @@ MCRT_HD void att_locate(const GridDev& G, Mem& M, const double o[3], const doubl
   while (ry.active) {
     WalkBlock<kBlockWalk, R, double> b;
     ray_next_block(ry, b, G, M);
+    // every sub-step's depth first (past b.n: none) and whether the point
+    // lies in this block, a test that needs all of the block's density loads,
+    // so they are in flight together; a block without the point is taken
+    // whole, the block with it step by step
+    R dtau[kBlockWalk];
+    bool pos[kBlockWalk];
+    double t_run = ry.t;
+    R run = ry.tau;
+    bool hit = false;
 #pragma unroll
     for (int d = 0; d < kBlockWalk; ++d) {
-      if (d >= b.n) break;
-      const double tm = b.tend[d];
-      R seg = (R)(tm - ry.t);
-      const bool pos = seg > R(0);
-      seg = pos ? seg : R(0);
-      const R rs = b.rho[d];
-      const R dtau = kapR * rs * seg;
-      nx += pos;
-      if (pos && ry.tau + dtau > tau_sR) {
-        ray_rewind<kBlockWalk, R, Mem::kGrid>(ry, b, d, G);
-        const double tp = ray_cell_entry64<R, Mem::kGrid>(ry, G, o, k);
-        s = tp + (tau_s - (double)ry.tau) / (kap * (double)rs);
-        rho_s = rs;
-        return;
+      const R s0 = (R)(b.tend[d] - t_run);
+      pos[d] = d < b.n && s0 > R(0);
+      dtau[d] = pos[d] ? kapR * b.rho[d] * s0 : R(0);
+      hit = hit || (pos[d] && run + dtau[d] > tau_sR);
+      run += dtau[d];
+      if (pos[d]) t_run = b.tend[d];
+    }
+    if (!hit) {
+#pragma unroll
+      for (int d = 0; d < kBlockWalk; ++d) {
+        nx += pos[d];
+        if (dtau[d] > R(0)) {
+          last_cell = b.cell[d];
+          last_t = b.tend[d];
+        }
       }
-      if (dtau > R(0)) {
-        last_cell = b.cell[d];
-        last_t = tm;
+      ry.tau = run;
+      ry.t = t_run;
+    } else {
+#pragma unroll
+      for (int d = 0; d < kBlockWalk; ++d) {
+        if (d >= b.n) break;
+        const double tm = b.tend[d];
+        const R rs = b.rho[d];
+        nx += pos[d];
+        if (pos[d] && ry.tau + dtau[d] > tau_sR) {
+          ray_rewind<kBlockWalk, R, Mem::kGrid>(ry, b, d, G);
+          const double tp = ray_cell_entry64<R, Mem::kGrid>(ry, G, o, k);
+          s = tp + (tau_s - (double)ry.tau) / (kap * (double)rs);
+          rho_s = rs;
+          return;
+        }
+        if (dtau[d] > R(0)) {
+          last_cell = b.cell[d];
+          last_t = tm;
+        }
+        ry.tau += dtau[d];
+        if (pos[d]) ry.t = tm;
       }
-      ry.tau += dtau;
-      if (pos) ry.t = tm;
     }
     if (b.out) ry.active = false;
   }
