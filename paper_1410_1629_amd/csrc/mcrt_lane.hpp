@@ -362,7 +362,9 @@ MCRT_HD void lane_events(Lane<R>& L, const RunParams& P, Mem& M) {
         L.phase = PH_PKG_END;
       } else {
         if (L.pass == 0) {
-          L.s_abs += L.wabs * (double)L.absf;
+          // the leg's absorbed fraction: the sum of its deposits, which
+          // telescopes to 1 - e^-T, taken so when no tally is kept
+          L.s_abs += L.wabs * ((!ADJ && !P.absorbed) ? -expm1(-L.T) : (double)L.absf);
           L.s_esc += L.W * exp(-L.T);
         }
         const U4 ws = draw_words(P.seed, L.pkg, (unsigned)L.lam, 2u + (unsigned)L.n);
@@ -656,17 +658,16 @@ MCRT_HD bool lane_step(Lane<R>& L, const RunParams& P, Mem& M) {
         }
         L.trans += L.trans * em;
       }
-      if (!ADJ && dtau > R(0)) {
+      if (!ADJ && P.absorbed && dtau > R(0)) {
         // deposit e^-tau (1 - e^-dtau) with e^-tau carried along the walk
+        // (without a tally nothing is summed: the leg's end takes 1 - e^-T)
         const R em = expm1(-dtau);
         const R f = -L.trans * em;
         L.trans += L.trans * em;
         L.absf += f;
-        if (P.absorbed) {
-          M.template walk_deposit<ADJ>(d, L.lam_cell + tally_slot(P.G, cell), L.wabs * (double)f);
-          put = true;
-          ++L.n_dep;
-        }
+        M.template walk_deposit<ADJ>(d, L.lam_cell + tally_slot(P.G, cell), L.wabs * (double)f);
+        put = true;
+        ++L.n_dep;
       }
     } else if (L.mode == M_LOCATE) {
       L.x_loc += pos;
