@@ -445,6 +445,7 @@ def attached_leg(B, W, dev):
         st = B.backward_density(prob, rho, adj, grad, **kw)
         torch.cuda.synchronize()
         out[name + "_ms"] = (time.perf_counter() - t0) * 1e3
+        out[name + "_kernel_ms"] = st["kernel_ms"]  # HIP events on the call's stream (the wall clock includes the host)
         if name == "attached":
             x_all = st["x_path"] + st["x_locate"] + st["x_peel"]
             alg = ((x_all - st["d_queue"]) * BYTES_PER_CROSSING[1] + st["deposits"] * BYTES_PER_DEPOSIT +

@@ -482,8 +482,10 @@ inline void depth_keys(DetDev& D, const GridDev& G) {
 
 // Sort-key ranges of the frames (tile_key): a Morton index over tiles of
 // 2^tshift x 2^tshift pixels, the frames sharing kSortKeys keys (a power of
-// 4 per frame).  Returns the total number of keys.
-inline long long tile_frames(std::vector<DetDev>& det, int n_det) {
+// 4 per frame).  Returns the total number of keys; *sub_bits gets the width
+// of the second keys (sort_sub) over all frames.
+inline long long tile_frames(std::vector<DetDev>& det, int n_det, int* sub_bits) {
+  *sub_bits = 0;
   if (n_det <= 0) return 0;
   int bits = 0;  // key bits per frame: even, with n_det << bits <= kSortKeys
   while ((static_cast<long long>(n_det) << (bits + 2)) <= kSortKeys) bits += 2;
@@ -496,6 +498,7 @@ inline long long tile_frames(std::vector<DetDev>& det, int n_det) {
     while (2 * (k - ts) > bits) ++ts;
     D.tshift = ts;
     D.sub_shift = std::max(0, 2 * ts - 8);
+    *sub_bits = std::max(*sub_bits, 2 * ts - D.sub_shift + kDepthBits);
     D.key_off = (int)keys;
     keys += 1ll << (2 * (k - ts));
   }
@@ -511,6 +514,7 @@ struct Prepared {
   long long n_images = 0;  // comps * n_lambda * pixels of all frames
   double emitted = 0.0;    // sum over wavelengths of n_packages * w0
   long long n_keys = 0;    // image-plane tiles over all frames
+  int sub_bits = 0;        // width of the second sort keys (sort_sub)
   int cell_src = -1;       // index of the cell source, -1 if none
   std::vector<double> lums;  // [n_src][n_lambda] luminosity of each source (a cell source: its total)
 };
@@ -631,7 +635,7 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
     if (out.det[d].kind == kDetSed) sed_key_grid(out.det[d], P.G);
     depth_keys(out.det[d], P.G);
   }
-  out.n_keys = tile_frames(out.det, n_det);
+  out.n_keys = tile_frames(out.det, n_det, &out.sub_bits);
   out.src.assign(n_src, SrcDev{});
   for (int s = 0; s < n_src; ++s) {
     out.src[s].kind = sources[s].kind;

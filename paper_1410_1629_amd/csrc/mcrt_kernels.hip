@@ -469,22 +469,49 @@ __global__ void __launch_bounds__(kSortThreads) k_hist(const unsigned* __restric
   for (int i = threadIdx.x; i < n_keys; i += kSortThreads) counts[(size_t)i * kSortBlocks + blockIdx.x] = h[i];
 }
 
+// Runs of one first key at least this long skip the second level: its one
+// workgroup per run would walk such a run alone, some 3 us per 256 rays (a
+// point source's emission peel-offs all start at one place, one pixel and
+// one depth: 1e7 rays, 33 ms), so k_scatter places their rays in the first
+// level's order itself.  Shorter runs keep the second level, whose order
+// the peel walks need (the clumpy disk's busiest tiles hold a few 1e5 rays
+// per chunk; with a bound of 65536 its peel walks took 1052 ms, not 478).
+// k_hot marks the long runs, one bit per key.
+constexpr unsigned kHotRun = 1u << 21;
+__global__ void __launch_bounds__(kSortThreads) k_hot(const unsigned* __restrict__ starts, int n_keys,
+                                                      unsigned* __restrict__ hot) {
+  const int w = blockIdx.x * kSortThreads + threadIdx.x;
+  if (w >= (n_keys + 31) / 32) return;
+  unsigned bits = 0;
+  for (int b = 0; b < 32; ++b) {
+    const int k = 32 * w + b;
+    if (k < n_keys && starts[(size_t)(k + 1) * kSortBlocks] - starts[(size_t)k * kSortBlocks] >= kHotRun) bits |= 1u << b;
+  }
+  hot[w] = bits;
+}
+
 __global__ void __launch_bounds__(kSortThreads) k_scatter(const unsigned* __restrict__ keys,
                                                           const unsigned long long* __restrict__ ctr,
                                                           unsigned long long cap, int n_keys,
                                                           const unsigned* __restrict__ starts,
-                                                          unsigned* __restrict__ idx, unsigned short* __restrict__ subs) {
-  __shared__ unsigned h[host::kSortKeys];
+                                                          const unsigned* __restrict__ hot,
+                                                          unsigned* __restrict__ idx, unsigned short* __restrict__ subs,
+                                                          unsigned* __restrict__ perm) {
+  __shared__ unsigned h[host::kSortKeys], hb[host::kSortKeys / 32];
   for (int i = threadIdx.x; i < n_keys; i += kSortThreads) h[i] = starts[(size_t)i * kSortBlocks + blockIdx.x];
-  __syncthreads();
+  unsigned any = 0;
+  for (int i = threadIdx.x; i < (n_keys + 31) / 32; i += kSortThreads) any |= hb[i] = hot[i];
+  const bool some_hot = __syncthreads_or(any != 0u);
   unsigned long long lo, hi;
   sort_part(queued_jobs(ctr, cap), lo, hi);
   for (unsigned long long j = lo + threadIdx.x; j < hi; j += kSortThreads) {
     const unsigned w = keys[j];
     if (w != kNoKey) {
-      const unsigned q = atomicAdd(h + (w & 0xffffu), 1u);
+      const unsigned k = w & 0xffffu;
+      const unsigned q = atomicAdd(h + k, 1u);
       idx[q] = (unsigned)j;
       subs[q] = (unsigned short)(w >> 16);
+      if (some_hot && ((hb[k >> 5] >> (k & 31)) & 1u)) perm[q] = (unsigned)j;
     }
   }
 }
@@ -559,29 +586,33 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_add(unsigned* __restrict_
 }
 
 // Workgroup k sorts the run [starts of key k, starts of key k + 1) of idx
-// by subs (the pixel inside the tile, then the depth) into perm.
+// by subs (the pixel inside the tile, then the depth) into perm.  Only the
+// n_sub counters the frames' second keys can reach are cleared and scanned
+// (a 128^2 frame has one-pixel tiles and 6-bit second keys: 64 of 16384).
 __global__ void __launch_bounds__(kRefineThreads) k_refine(const unsigned* __restrict__ starts,
                                                            const unsigned* __restrict__ idx,
                                                            const unsigned short* __restrict__ subs,
-                                                           unsigned* __restrict__ perm) {
-  constexpr int kPer = kSubKeys / kRefineThreads;  // counters per thread in the scan
-  static_assert(kSubKeys % kRefineThreads == 0, "whole counters per thread");
+                                                           unsigned* __restrict__ perm, int n_sub) {
   __shared__ unsigned h[kSubKeys], scan[kRefineThreads];
   const unsigned lo = starts[(size_t)blockIdx.x * kSortBlocks], hi = starts[(size_t)(blockIdx.x + 1) * kSortBlocks];
   if (hi - lo <= 1u) {
     if (hi > lo && threadIdx.x == 0) perm[lo] = idx[lo];
     return;
   }
-  for (int i = threadIdx.x; i < kSubKeys; i += kRefineThreads) h[i] = 0u;
+  if (hi - lo >= kHotRun) return;  // placed by k_scatter
+  for (int i = threadIdx.x; i < n_sub; i += kRefineThreads) h[i] = 0u;
   __syncthreads();
   for (unsigned i = lo + threadIdx.x; i < hi; i += kRefineThreads) atomicAdd(h + subs[i], 1u);
   __syncthreads();
+  // thread t scans counters [t per, (t + 1) per) (n_sub and the threads are powers of two)
+  const int per = n_sub >= kRefineThreads ? n_sub / kRefineThreads : 1;
+  const int c0 = threadIdx.x * per, c1 = c0 + per < n_sub ? c0 + per : n_sub;
   unsigned own = 0, total;
-  for (int j = 0; j < kPer; ++j) own += h[threadIdx.x * kPer + j];
+  for (int j = c0; j < c1; ++j) own += h[j];
   unsigned run = lo + block_exclusive_scan(own, scan, &total);
-  for (int j = 0; j < kPer; ++j) {
-    const unsigned c = h[threadIdx.x * kPer + j];
-    h[threadIdx.x * kPer + j] = run;
+  for (int j = c0; j < c1; ++j) {
+    const unsigned c = h[j];
+    h[j] = run;
     run += c;
   }
   __syncthreads();
@@ -1270,8 +1301,10 @@ struct PeelQueue {
   hipStream_t st = nullptr;
   unsigned long long cap = 0;
   long long n_keys = 0;
+  int n_sub = 0;  // counters of k_refine: 2^(width of the second keys)
   PeelJob* jobs = nullptr;
   unsigned *keys = nullptr, *perm = nullptr, *idx = nullptr, *counts = nullptr, *starts = nullptr, *tiles = nullptr;
+  unsigned* hot = nullptr;  // bit k: key k's run is at least kHotRun rays (not refined)
   unsigned short* subs = nullptr;
   ~PeelQueue() {
     if (ptr) (void)hipFreeAsync(ptr, st);
@@ -1286,6 +1319,8 @@ int make_peel_queue(const mcrt_opts& o, const host::Prepared& pr, unsigned long 
                     PeelQueue& q) {
   q.st = st;
   q.n_keys = pr.n_keys;
+  q.n_sub = 1 << pr.sub_bits;
+  if (q.n_sub > kSubKeys) return fail(MCRT_EINVAL, "second sort keys of %d bits exceed the sort's counters", pr.sub_bits);
   unsigned long long cap;
   if (o.peel_queue > 0) {
     cap = (unsigned long long)o.peel_queue;
@@ -1305,7 +1340,8 @@ int make_peel_queue(const mcrt_opts& o, const host::Prepared& pr, unsigned long 
   const size_t off_cnt = off_subs + align256(sizeof(unsigned short) * cap);
   const size_t off_start = off_cnt + align256(sizeof(unsigned) * n_cnt);
   const size_t off_tiles = off_start + align256(sizeof(unsigned) * (n_cnt + 1));
-  const size_t bytes = off_tiles + align256(sizeof(unsigned) * (n_cnt / kScanTile + 1));
+  const size_t off_hot = off_tiles + align256(sizeof(unsigned) * (n_cnt / kScanTile + 1));
+  const size_t bytes = off_hot + align256(sizeof(unsigned) * (host::kSortKeys / 32));
   HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&q.ptr), bytes, st));
   q.cap = cap;
   q.jobs = reinterpret_cast<PeelJob*>(q.ptr);
@@ -1316,6 +1352,7 @@ int make_peel_queue(const mcrt_opts& o, const host::Prepared& pr, unsigned long 
   q.counts = reinterpret_cast<unsigned*>(q.ptr + off_cnt);
   q.starts = reinterpret_cast<unsigned*>(q.ptr + off_start);
   q.tiles = reinterpret_cast<unsigned*>(q.ptr + off_tiles);
+  q.hot = reinterpret_cast<unsigned*>(q.ptr + off_hot);
   return 0;
 }
 
@@ -1362,9 +1399,12 @@ int run_peel_jobs(const PeelQueue& q, const RunParams& P, unsigned long long* ct
                      n_cnt);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kTopThreads), 0, st, q.tiles, n_tiles, q.starts, n_cnt);
   hipLaunchKernelGGL(k_scan_add, dim3((unsigned)n_tiles), dim3(kScanThreads), 0, st, q.starts, q.tiles, n_cnt);
+  hipLaunchKernelGGL(k_hot, dim3((unsigned)((q.n_keys + 32 * kSortThreads - 1) / (32 * kSortThreads))),
+                     dim3(kSortThreads), 0, st, q.starts, (int)q.n_keys, q.hot);
   hipLaunchKernelGGL(k_scatter, dim3(kSortBlocks), dim3(kSortThreads), 0, st, q.keys, ctr, q.cap, (int)q.n_keys,
-                     q.starts, q.idx, q.subs);
-  hipLaunchKernelGGL(k_refine, dim3((unsigned)q.n_keys), dim3(kRefineThreads), 0, st, q.starts, q.idx, q.subs, q.perm);
+                     q.starts, q.hot, q.idx, q.subs, q.perm);
+  hipLaunchKernelGGL(k_refine, dim3((unsigned)q.n_keys), dim3(kRefineThreads), 0, st, q.starts, q.idx, q.subs, q.perm,
+                     q.n_sub);
   HIPCHK(hipGetLastError());
   if (int e = sp.mark(kSpanSort, st)) return e;
   PeelJobParams J;
