@@ -315,6 +315,32 @@ def test_forward_peel_queue_modes(B, orc, W, prec):
         assert abs(st["x_peel"] - ref["x_peel"]) <= slack, (q, st["x_peel"], ref["x_peel"])
 
 
+def test_forward_peel_queue_long_run(B, orc, W):
+    # a point source's emission peel-offs all start at one place: 2.5e6
+    # packages put more than 2^21 queued rays into one pixel's run, which
+    # the sort's first level places itself (no second level): every ray
+    # still walked once, the same images as the inline walks and the oracle
+    _say("forward peel queue, one run beyond 2^21 rays")
+    n = (6, 6, 6)
+    prob = W.small_problem(n=n, rho=W.lognormal_density(n, 0.5, seed=61), kappa=0.8, albedo=0.5, g=0.3,
+                           sources=[W.point((0.0, 0.0, 0.0))], detectors=[W.frame(10.0, 0.0, 8, 8, 1.2, 1.2)],
+                           n_packages=2_500_000, precision=0, flags=W.FLAG_PEEL_EMIT | W.FLAG_PEEL_SCAT)
+    runs = {}
+    for q in (-1, 0):
+        images, _, st = B.render(prob, peel_queue=q)
+        runs[q] = (images.cpu().numpy(), st)
+    (img_i, st_i), (img_q, st_q) = runs[-1], runs[0]
+    assert st_q["x_queue"] > 0 and st_i["x_queue"] == 0 and st_q["life_launches"] == 1
+    assert st_q["peels"] >= 2_500_000  # the emission peel-offs, all in one pixel
+    for key in ("x_path", "x_locate", "x_peel", "events", "peels", "packages"):
+        assert st_q[key] == st_i[key], (key, st_q[key], st_i[key])
+    # one pixel sums 2.5e6 contributions, in another order on each path:
+    # FP64 rounding of up to n eps (2.8e-10) relative
+    check(img_q, img_i, 1e-10, "queued against inline images", _say)
+    img_o, _, _ = orc.run(prob, threads=16)
+    check(img_q, img_o, 1e-10, "queued images against the oracle", _say)
+
+
 def test_backward_peel_queue_modes(B, orc, W):
     # peel-ray deposits walked inline, queued and bundled, or queued until a
     # tiny queue is full: the same gradient and the same crossing counts
