@@ -898,12 +898,21 @@ struct AttMem {
   __device__ void att_over() const { atomicOr(P.work + kAttOverflow, 1ull); }
 };
 
+// Persistent: a lane that has finished its package takes the next one from
+// the chunk's work counter (packages differ widely in their number of
+// events, and a wavefront of one package per lane lasts as long as its
+// longest one).
 template <typename S, int GK>
 __global__ void __launch_bounds__(kBlock) k_attached(const RunParams P) {
+  __shared__ unsigned long long slots[kWavesPerBlock][2];
+  unsigned long long* const res = wave_reservoir(slots);
   AttMem<S, GK> M{static_cast<const S*>(P.rho), P};
   AttCounts c;
-  const unsigned long long k = (unsigned long long)blockIdx.x * kBlock + threadIdx.x;
-  if (k < P.n_chunk) attached_item<double>(P, M, P.item0 + k, (int)k, c);
+  for (;;) {
+    const unsigned long long k = wave_fetch(P.work, res, 64);
+    if (k >= P.n_chunk) break;
+    attached_item<double>(P, M, P.item0 + k, (int)k, c);
+  }
   const double s_abs = wave_sum(c.s_abs), s_esc = wave_sum(c.s_esc), s_trunc = wave_sum(c.s_trunc);
   const unsigned long long a0 = wave_sum_u64(c.x_path), a1 = wave_sum_u64(c.x_loc), a2 = wave_sum_u64(c.x_peel),
                            a3 = wave_sum_u64(c.n_ev), a4 = wave_sum_u64(c.n_pk), a5 = wave_sum_u64(c.n_pl),
@@ -1489,26 +1498,20 @@ void launch_life_c(const RunParams& P, int nblk, hipStream_t st) {
     launch_life_k<R, ADJ, kGridRegular, INST>(P, nblk, st);
 }
 
-// The attached gradient's kernel over one chunk: one lane per work item;
-// f32: the densities are stored in FP32.
+// The attached gradient's kernel over one chunk (its work counter reset by
+// the caller): a persistent grid; f32: the densities are stored in FP32.
 int launch_attached(const RunParams& P, bool f32, hipStream_t st) {
-  const unsigned nb = (unsigned)((P.n_chunk + kBlock - 1) / kBlock);
   const int kind = P.G.kind;
-  if (f32) {
-    if (kind == kGridRect)
-      hipLaunchKernelGGL((k_attached<float, kGridRect>), dim3(nb), dim3(kBlock), 0, st, P);
-    else if (kind == kGridTree)
-      hipLaunchKernelGGL((k_attached<float, kGridTree>), dim3(nb), dim3(kBlock), 0, st, P);
-    else
-      hipLaunchKernelGGL((k_attached<float, kGridRegular>), dim3(nb), dim3(kBlock), 0, st, P);
-  } else {
-    if (kind == kGridRect)
-      hipLaunchKernelGGL((k_attached<double, kGridRect>), dim3(nb), dim3(kBlock), 0, st, P);
-    else if (kind == kGridTree)
-      hipLaunchKernelGGL((k_attached<double, kGridTree>), dim3(nb), dim3(kBlock), 0, st, P);
-    else
-      hipLaunchKernelGGL((k_attached<double, kGridRegular>), dim3(nb), dim3(kBlock), 0, st, P);
-  }
+  int e;
+  if (f32)
+    e = kind == kGridRect   ? launch_persistent(k_attached<float, kGridRect>, P, st)
+        : kind == kGridTree ? launch_persistent(k_attached<float, kGridTree>, P, st)
+                            : launch_persistent(k_attached<float, kGridRegular>, P, st);
+  else
+    e = kind == kGridRect   ? launch_persistent(k_attached<double, kGridRect>, P, st)
+        : kind == kGridTree ? launch_persistent(k_attached<double, kGridTree>, P, st)
+                            : launch_persistent(k_attached<double, kGridRegular>, P, st);
+  if (e) return e;
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -1766,6 +1769,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
       P.item0 = c0;
       P.n_chunk = std::min(chunk, P.n_items - c0);
+      if (int e = reset_counters(ctr, 0, 1, st)) return e;
       if (int e = sp.mark(kSpanLife, st)) return e;
       if (int e = launch_attached(P, f32, st)) return e;
       ++launches;
