@@ -334,11 +334,15 @@ MCRT_HD void attached_item(const RunParams& P, Mem& M, unsigned long long item, 
         rb[0] -= q * gp[0];
         rb[1] -= q * gp[1];
         rb[2] -= q * gp[2];
-        unsigned long long nd = 0;
-        att_deposit<R>(G, M, re, D.kd, -q * kap, nd);
-        cnt.x_peel += nd;
-        cnt.x_dep += nd;
-        cnt.n_dep += nd;
+        // the deposit walk: queued for the peel-job kernels (sorted, summed
+        // on chip), or walked here when the queue is full or absent
+        if (!M.queue_deposit(D, d, re, pix, -q * kap, ii, (unsigned)slot, e, (unsigned)lam)) {
+          unsigned long long nd = 0;
+          att_deposit<R>(G, M, re, D.kd, -q * kap, nd);
+          cnt.x_peel += nd;
+          cnt.x_dep += nd;
+          cnt.n_dep += nd;
+        }
       }
     }
     if (e == 0) break;

@@ -896,6 +896,29 @@ struct AttMem {
     P.evs[((size_t)e * kAttF + f) * P.n_chunk + slot] = v;
   }
   __device__ void att_over() const { atomicOr(P.work + kAttOverflow, 1ull); }
+  // a peel ray's deposit walk of weight w into the peel-job queue (the
+  // adjoint's sort keys; k_peeldep takes w as the ray's weight); false when
+  // there is no queue or it is full
+  unsigned long long* job_res;
+  __device__ bool queue_deposit(const DetDev& D, int d, const double r[3], int pix, double w, long long ii,
+                                unsigned item, int e, unsigned lam) const {
+    if (!P.jobs) return false;
+    const unsigned long long slot = wave_fetch(P.work + kJobCounter, job_res, kJobChunk);
+    if (slot >= P.job_cap) return false;
+    const int kp = key_pixel<true>(D, r, pix);
+    PeelJob& J = P.jobs[slot];
+    J.r[0] = r[0];
+    J.r[1] = r[1];
+    J.r[2] = r[2];
+    J.v = w;
+    J.ii = ii;
+    J.slot = item;
+    J.lam = lam;
+    J.e = (unsigned short)(e < kEventSat ? e : kEventSat);
+    J.d = (unsigned char)d;
+    P.keys[slot] = tile_key(D, kp) | (sort_sub(D, kp, r, P.depth_drop) << 16);
+    return true;
+  }
 };
 
 // Persistent: a lane that has finished its package takes the next one from
@@ -904,14 +927,18 @@ struct AttMem {
 // longest one).
 template <typename S, int GK>
 __global__ void __launch_bounds__(kBlock) k_attached(const RunParams P) {
-  __shared__ unsigned long long slots[kWavesPerBlock][2];
+  __shared__ unsigned long long slots[kWavesPerBlock][2], job_slots[kWavesPerBlock][2];
   unsigned long long* const res = wave_reservoir(slots);
-  AttMem<S, GK> M{static_cast<const S*>(P.rho), P};
+  AttMem<S, GK> M{static_cast<const S*>(P.rho), P, wave_reservoir(job_slots)};
   AttCounts c;
   for (;;) {
     const unsigned long long k = wave_fetch(P.work, res, 64);
     if (k >= P.n_chunk) break;
     attached_item<double>(P, M, P.item0 + k, (int)k, c);
+  }
+  if (P.jobs) {  // unfilled reserved queue slots
+    const unsigned long long lo = M.job_res[0], hi = M.job_res[1] < P.job_cap ? M.job_res[1] : P.job_cap;
+    for (unsigned long long q = lo + __lane_id(); q < hi; q += 64) P.keys[q] = kNoKey;
   }
   const double s_abs = wave_sum(c.s_abs), s_esc = wave_sum(c.s_esc), s_trunc = wave_sum(c.s_trunc);
   const unsigned long long a0 = wave_sum_u64(c.x_path), a1 = wave_sum_u64(c.x_loc), a2 = wave_sum_u64(c.x_peel),
@@ -1614,7 +1641,7 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
   const int ev_max = att ? att_ev : (tape_adj ? tape_ev : kEventsKept);
   const int ev_k = att ? (int)kAttF : 1 + n_det + (adjoint && adj_abs_dev ? 1 : 0);  // T, q per frame, then B of the path
   const size_t per_item = sizeof(double) * ((size_t)ev_max * ev_k + (att ? 0 : 1 + (optg ? 4 : 0)));
-  const bool queued = peel && opts->peel_queue != -1 && !att;
+  const bool queued = peel && opts->peel_queue != -1;  // the attached gradient queues its deposit walks only
   P.depth_drop = adjoint ? kDepthDropAdjoint : 0;
   size_t free_b = 0, total_b = 0;
   HIPCHK(hipMemGetInfo(&free_b, &total_b));
@@ -1770,10 +1797,16 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
       P.item0 = c0;
       P.n_chunk = std::min(chunk, P.n_items - c0);
       if (int e = reset_counters(ctr, 0, 1, st)) return e;
+      if (int e = reset_counters(ctr, kJobCounter, 2, st)) return e;
+      if (int e = reset_counters(ctr, kDepCounter, 1, st)) return e;
+      P.dep_jobs = 1;  // the queued rays carry their weights
       if (int e = sp.mark(kSpanLife, st)) return e;
       if (int e = launch_attached(P, f32, st)) return e;
       ++launches;
       if (int e = sp.mark(kSpanLife, st)) return e;
+      // the queued deposit walks, in FP64 like the sweeps' own walks
+      if (P.jobs)
+        if (int e = run_peel_jobs<double, true>(queue, P, ctr, inst, st, sp)) return e;
     }
   } else {
     for (unsigned long long c0 = 0; c0 < P.n_items; c0 += chunk) {
@@ -1858,9 +1891,11 @@ int life(bool adjoint, const mcrt_grid* grid, const void* rho_dev, const mcrt_op
     stats->peel_ms = ms_peel;
     stats->dep_ms = ms_dep;
     stats->d_queue = xq[1];
-    if (att) {  // the attached kernel: the crossings of its peel rays' deposit walks
-      HIPCHK(hipMemcpyAsync(&stats->d_queue, ctr + kAttDepCrossings, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    if (att) {  // the crossings of the peel rays' deposit walks: those the attached kernel walked, then the queue's
+      uint64_t inline_dep = 0;
+      HIPCHK(hipMemcpyAsync(&inline_dep, ctr + kAttDepCrossings, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
+      stats->d_queue = inline_dep + xq[1];
     }
     stats->life_launches = launches;
   }

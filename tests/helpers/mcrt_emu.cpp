@@ -889,6 +889,12 @@ struct HostAttMem {
     ws_set[i] = 1;
   }
   void att_over() { over = true; }
+  // the library queues the peel rays' deposit walks for its peel-job kernels
+  // when it can; the harness walks them in place (the same deposits, summed
+  // in another order)
+  bool queue_deposit(const DetDev&, int, const double*, int, double, long long, unsigned, int, unsigned) {
+    return false;
+  }
 };
 
 template <typename R, int GK>
