@@ -424,10 +424,12 @@ def attached_leg(B, W, dev):
     """The attached (pathwise) density gradient of the adjoint workload (64^3
     lognormal grid, 128^2 face-on frame, 1e7 packages; FP32 densities, FP64
     sweeps), after one untimed call, beside the detached adjoint of the same
-    dL/dI with and without the forward run's tape.  Roofline of k_attached:
-    4 B per crossing that reads a density (every walk but the peel rays'
-    deposit walks), 8 B per gradient deposit and per dL/dI read, and the
-    workspace's 2 x 88 B per event (emission and scatterings)."""
+    dL/dI with and without the forward run's tape.  The peel rays' deposit
+    walks go through the peel-job queue (sort, k_peeldep).  Roofline of
+    k_attached: 4 B per crossing that reads a density (every walk but the
+    deposit walks), 8 B per gradient deposit it makes itself and per dL/dI
+    read, and the workspace's 2 x 88 B per event (emission and
+    scatterings)."""
     import torch
     prob = W.adjoint(n_packages=10_000_000, precision=1)
     rho = B.density_tensor(prob, dev)
@@ -447,14 +449,18 @@ def attached_leg(B, W, dev):
         out[name + "_ms"] = (time.perf_counter() - t0) * 1e3
         out[name + "_kernel_ms"] = st["kernel_ms"]  # HIP events on the call's stream (the wall clock includes the host)
         if name == "attached":
+            # k_attached's own work: every walk but the deposit walks reads densities (d_queue counts all
+            # deposit-walk crossings); its deposits exclude those of the queued deposit walks (x_queue,
+            # one deposit per crossing), which the peel-job kernels make
             x_all = st["x_path"] + st["x_locate"] + st["x_peel"]
-            alg = ((x_all - st["d_queue"]) * BYTES_PER_CROSSING[1] + st["deposits"] * BYTES_PER_DEPOSIT +
+            alg = ((x_all - st["d_queue"]) * BYTES_PER_CROSSING[1] + (st["deposits"] - st["x_queue"]) * BYTES_PER_DEPOSIT +
                    st["peels"] * BYTES_PER_PIXEL + (st["events"] + st["packages"]) * BYTES_PER_ATTACHED_EVENT)
             launches = st["life_launches"]
             launch_s = st["life_ms"] / 1e3 / launches
             achieved = alg / launches / launch_s / 1e9
             out["packages_per_s"] = prob["n_packages"] / (st["kernel_ms"] / 1e3)
-            out["crossings_per_s"] = x_all / (st["life_ms"] / 1e3)
+            out["crossings_per_s"] = x_all / (st["kernel_ms"] / 1e3)
+            out["queue_ms"] = st["queue_ms"]  # the queued deposit walks and their sort
             out["roofline"] = {"kernel": KERNELS["attached"], "bound": "hbm", "achieved": achieved,
                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                                "traffic": None, "launch_ms": launch_s * 1e3, "launches_per_step": launches,

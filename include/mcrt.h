@@ -290,8 +290,11 @@ uint64_t mcrt_tape_bytes(const mcrt_optics *optics, int n_det, const mcrt_opts *
  * With MCRT_ATTACHED: x_path counts the forward sweep's path walks and the
  * reverse sweep's leg walks, x_locate the locate walks, x_peel both walks of
  * every peel ray, deposits the gradient deposits; d_queue the crossings of
- * the peel rays' deposit walks (no density loads); life_ms and
- * life_launches the attached kernel (one launch per chunk). */
+ * the peel rays' deposit walks (no density loads), x_queue the part of
+ * them walked by the queue kernels (the rest, with the queue full, by the
+ * attached kernel); life_ms and life_launches the attached kernel (one
+ * launch per chunk), queue_ms the sort and walks of the queued deposit
+ * walks. */
 typedef struct {
     double emitted, absorbed, escaped, truncated;
     uint64_t x_path, x_locate, x_peel, events, packages, peels, deposits;
@@ -417,7 +420,8 @@ int backward_density(const mcrt_grid *grid, const void *rho_dev, const mcrt_opti
  * have at most MCRT_ATTACHED_MAX_EVENTS events by the bound of
  * mcrt_tape_bytes (else MCRT_EINVAL: lower max_scatter or raise w_min); the
  * tape is not used.  The library keeps a workspace of 88 bytes per event per
- * package of a chunk.  A package that exceeds the bound anyway (not
+ * package of a chunk, and queues the peel rays' deposit walks like the
+ * detached gradient (mcrt_opts.peel_queue; -1: every walk inline).  A package that exceeds the bound anyway (not
  * expected) makes the call return MCRT_EOVERFLOW. */
 
 /* Gradients of the same image loss with respect to the densities and to

@@ -94,6 +94,33 @@ def test_attached_matches_the_oracle(B, orc, W, kind, prec):
         assert st["packages"] == 2 * 3000
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_attached_deposit_walks_queued_inline_or_both(B, orc, W, prec):
+    # the peel rays' deposit walks: all through the peel-job queue (the
+    # default), all inline (no queue), or queued until a small queue is full
+    _say("attached gradient: deposit walks by queue mode, precision %d" % prec)
+    prob = _grid(W, _problem(W, prec), "regular", prec)
+    img, _, _ = orc.run(prob)
+    adj = np.random.default_rng(9).standard_normal(img.shape)
+    g_o, _, _ = orc.grad_attached(prob, adj)
+    rho = B.density_tensor(prob)
+    tol = 1e-10 if prec == 0 else TOL32
+    ref = None
+    for q in (0, -1, 300):
+        grad, st = _attached(B, prob, rho, _dev(adj), peel_queue=q)
+        check(grad.cpu().numpy(), g_o, tol, "queue %d: attached gradient" % q, _say)
+        if q == -1:
+            assert st["x_queue"] == 0
+        else:
+            assert 0 < st["x_queue"] <= st["d_queue"]
+        if q == 300:
+            assert st["x_queue"] < st["d_queue"]  # the rest walked inline
+        if ref is None:
+            ref = st
+        for key in ("x_path", "x_locate", "x_peel", "deposits", "d_queue", "events", "peels", "packages"):
+            assert st[key] == ref[key], (q, key, st[key], ref[key])
+
+
 def test_attached_rejects_what_it_cannot_differentiate(B, W):
     import torch
     prob = _problem(W, 0, n_packages=100)
