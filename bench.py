@@ -199,7 +199,7 @@ def oracle_rate(prob, seconds, threads, forward_only=True, adj=None, n0=None):
 
     n = n0 or max(100, 25 * threads)
     t, img, st = timed(n)
-    while t < 0.25 * seconds and n < 50_000_000:
+    while t < 0.6 * seconds and n < 50_000_000:  # the last sample takes 0.6-1.5x `seconds`
         n = int(n * min(max(seconds / max(t, 1e-3), 1.5), 16))
         t, img, st = timed(n)
     return n, t, img, st
