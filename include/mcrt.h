@@ -26,7 +26,10 @@
  *    depths and exponentials in FP32; package state, every tally, and the
  *    crossing times of the life-cycle kernel's walks in FP64 -- a segment's
  *    length is a difference of two crossing times, which FP32 would carry
- *    with an error proportional to the distance walked).
+ *    with an error proportional to the distance walked).  FP32 calls on
+ *    regular and rectilinear grids take at most 2^24 - 1 cells along each
+ *    axis (the FP32 walks count crossed planes in FP32); larger grids fail
+ *    with MCRT_EINVAL.
  *  - Images are FP64 flux per pixel (luminosity / distance^2), laid out as
  *    [comp][lambda][frame pixels], where one wavelength's block is the
  *    frames one after another, each [ny][nx] row-major; comp is 2 with

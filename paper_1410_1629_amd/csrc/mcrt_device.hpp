@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #include <cmath>
+#include <type_traits>
 
 #define MCRT_HD __host__ __device__ __forceinline__
 
@@ -670,6 +671,19 @@ MCRT_HD void peel_geometry(const DetDev& D, const double r[3], double kd[3], dou
 // and every later event inherits that point's error), the life-cycle walks
 // keep times in FP64 and round each segment length to R once; the peel-ray
 // and trace walks, whose optical depths end in one exponential, keep T = R.
+//
+// FP32-time walks count planes in FP32 (the plane time fma(j, dt, t0) then
+// needs no integer conversion per crossing; exact while j < 2^24, and the
+// library rejects FP32 walks of grids with 2^24 or more cells along an axis)
+// and, on regular grids, leave the grid by time: texit is the earliest
+// boundary-plane time over the axes, the same fma at the axis's last plane.
+// A walk first reaches that time at the crossing that leaves the grid (an
+// index leaves its range there, or all later segments inside have zero
+// length), so one comparison replaces three index tests.
+template <typename T>
+using PlaneCount = std::conditional_t<sizeof(T) == sizeof(float), float, int>;
+template <int GK, typename T>
+constexpr bool kExitByTime = GK == kGridRegular && sizeof(T) == sizeof(float);
 template <typename R, typename T = R>
 struct Ray {
   using Time = T;
@@ -677,7 +691,9 @@ struct Ray {
   T tp[3];       // rectilinear grids only
   double e[3];   // rectilinear and tree grids
   double k[3], tc;  // tree grids only
-  int j[3], i[3], s[3];
+  PlaneCount<T> j[3];
+  int i[3], s[3];
+  T texit;  // kExitByTime walks only
   T t;
   R tau;
   T tmax;      // the walk stops here (time from the entry; +inf: at the boundary)
@@ -795,6 +811,16 @@ MCRT_HD void ray_begin(Ray<R, T>& ry, const GridDev& G, const double o[3], const
       ry.dt[a] = (T)(-G.d[a] * inv[a]);
       ry.s[a] = -1;
     }
+  }
+  if constexpr (kExitByTime<GK, T>) {
+    T te = T(INFINITY);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (ry.s[a] == 0) continue;
+      const int last = ry.s[a] > 0 ? G.n[a] - 1 - ry.i[a] : ry.i[a];  // planes crossed before the boundary's
+      te = fmin(te, fmaR((T)last, ry.dt[a], ry.t0[a]));
+    }
+    ry.texit = te;
   }
   ry.t = T(0);
   ry.tin = tin;
@@ -944,9 +970,9 @@ MCRT_HD void ray_next_block(Ray<R, T>& ry, WalkBlock<D, R, T>& b, const GridDev&
     ry.i[0] += ax ? ry.s[0] : 0;
     ry.i[1] += ay ? ry.s[1] : 0;
     ry.i[2] += az ? ry.s[2] : 0;
-    ry.j[0] += ax;
-    ry.j[1] += ay;
-    ry.j[2] += az;
+    ry.j[0] += (PlaneCount<T>)ax;
+    ry.j[1] += (PlaneCount<T>)ay;
+    ry.j[2] += (PlaneCount<T>)az;
     if constexpr (GK == kGridRect) {
       if (ax) ry.tp[0] = rect_tplane(ry, G, 0);
       if (ay) ry.tp[1] = rect_tplane(ry, G, 1);
@@ -954,8 +980,12 @@ MCRT_HD void ray_next_block(Ray<R, T>& ry, WalkBlock<D, R, T>& b, const GridDev&
     }
     b.adv |= ((unsigned)ax | ((unsigned)ay << 1) | ((unsigned)az << 2)) << (3 * d);
     b.n += live;
-    const bool outside = (unsigned)ry.i[0] >= (unsigned)G.n[0] || (unsigned)ry.i[1] >= (unsigned)G.n[1] ||
-                         (unsigned)ry.i[2] >= (unsigned)G.n[2];
+    bool outside;
+    if constexpr (kExitByTime<GK, T>)
+      outside = tm >= ry.texit;
+    else
+      outside = (unsigned)ry.i[0] >= (unsigned)G.n[0] || (unsigned)ry.i[1] >= (unsigned)G.n[1] ||
+                (unsigned)ry.i[2] >= (unsigned)G.n[2];
     b.out = b.out || outside || !(ax || ay || az);
   }
   if constexpr (LOAD) {
@@ -985,7 +1015,7 @@ MCRT_HD void ray_rewind(Ray<R, T>& ry, const WalkBlock<D, R, T>& b, int d, const
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int x = (int)((m >> a) & 1u);
-      ry.j[a] -= x;
+      ry.j[a] -= (PlaneCount<T>)x;
       ry.i[a] -= x * ry.s[a];
     }
   }

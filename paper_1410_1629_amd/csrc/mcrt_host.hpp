@@ -120,6 +120,16 @@ inline int check_grid(const mcrt_grid* g) {
   return 0;
 }
 
+// FP32 walks on regular and rectilinear grids count crossed planes in FP32,
+// exact below 2^24 (FP32 plane times of farther planes would be inexact too).
+inline int check_fp32_axes(const mcrt_grid& g, int precision) {
+  if (precision != MCRT_PREC_FP32 || g.tree_nodes != 0) return 0;
+  if (g.nx >= (1 << 24) || g.ny >= (1 << 24) || g.nz >= (1 << 24))
+    return fail(MCRT_EINVAL, "FP32 precision: at most 2^24 - 1 cells along each axis (grid %d x %d x %d)", g.nx,
+                g.ny, g.nz);
+  return 0;
+}
+
 inline size_t align_up256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Leaf tables of a tree grid (checked by check_tree): the box of each cell
@@ -625,6 +635,7 @@ inline int prepare(const mcrt_grid* grid, const void* rho_dev, const mcrt_optics
   if (opts->n_packages * (unsigned long long)nl > (1ull << 62)) return fail(MCRT_EINVAL, "too many work items");
   if (opts->precision != MCRT_PREC_FP64 && opts->precision != MCRT_PREC_FP32)
     return fail(MCRT_EINVAL, "unknown precision %d", opts->precision);
+  if (int e = check_fp32_axes(*grid, opts->precision)) return e;
   if (!(opts->w_min >= 0.0) || !finite(opts->w_min)) return fail(MCRT_EINVAL, "w_min must be finite and >= 0");
   if (opts->max_scatter < 1 || opts->max_scatter > MCRT_MAX_SCATTER_LIMIT)
     return fail(MCRT_EINVAL, "max_scatter must lie in [1, %d]", MCRT_MAX_SCATTER_LIMIT);
@@ -695,6 +706,7 @@ inline int check_trace(const mcrt_grid* grid, const void* rho_dev, double kappa,
   if (!rho_dev) return fail(MCRT_EINVAL, "rho_dev is NULL");
   if (!(kappa >= 0.0) || !std::isfinite(kappa)) return fail(MCRT_EINVAL, "kappa must be finite and >= 0");
   if (precision != MCRT_PREC_FP64 && precision != MCRT_PREC_FP32) return fail(MCRT_EINVAL, "unknown precision");
+  if (int e = check_fp32_axes(*grid, precision)) return e;
   if (n_rays < 0) return fail(MCRT_EINVAL, "n_rays < 0");
   if (n_rays > 0 && (!origin_dev || !dir_dev || !tau_dev)) return fail(MCRT_EINVAL, "ray arrays are NULL");
   const bool lists = seg_cell_dev || seg_len_dev;
@@ -712,6 +724,7 @@ inline int check_peel(const mcrt_grid* grid, const void* rho_dev, double kappa, 
   if (!(kappa >= 0.0) || !std::isfinite(kappa)) return fail(MCRT_EINVAL, "kappa must be finite and >= 0");
   if (!(std::fabs(g) < 1.0)) return fail(MCRT_EINVAL, "|g| must be < 1");
   if (precision != MCRT_PREC_FP64 && precision != MCRT_PREC_FP32) return fail(MCRT_EINVAL, "unknown precision");
+  if (int e = check_fp32_axes(*grid, precision)) return e;
   if (n_events < 0) return fail(MCRT_EINVAL, "n_events < 0");
   if (int e = check_detectors(n_det, detectors, false)) return e;
   if (!images_dev) return fail(MCRT_EINVAL, "images_dev is NULL");

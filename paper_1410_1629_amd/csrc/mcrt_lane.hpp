@@ -732,15 +732,16 @@ MCRT_HD unsigned tau_step(Ray<R, T>& ry, const GridDev& G, R kap, Mem& M) {
   WalkBlock<D, R, T> b;
   ray_next_block(ry, b, G, M);
   unsigned n = 0;
-  // Every sub-step is evaluated, those past b.n masked (they repeat the last
-  // valid cell and add nothing): with a branch per sub-step the compiler
+  // Every sub-step is evaluated: with a branch per sub-step the compiler
   // moves each density load into its branch, and the block's loads then wait
-  // for one another instead of being in flight together.
+  // for one another instead of being in flight together.  Sub-steps past b.n
+  // repeat the last valid cell and end time, so their segments have no
+  // positive length and add nothing.
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     const T tm = (INST && b.tend[d] > ry.tmax) ? ry.tmax : b.tend[d];
     const R seg = (R)(tm - ry.t);
-    const bool pos = d < b.n && seg > R(0);
+    const bool pos = seg > R(0);
     const R dtau = pos ? kap * b.rho[d] * seg : R(0);
     n += pos;
     ry.tau += dtau;

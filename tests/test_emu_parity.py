@@ -79,6 +79,18 @@ def test_trace_edge_cases(E, orc):
     assert rc == 0 and tot == 0
 
 
+def test_fp32_axis_limit(E):
+    """FP32 walks count crossed planes in FP32, exact below 2^24: a grid
+    with 2^24 cells along an axis is rejected in FP32 (before any walk) and
+    accepted in FP64; 2^24 - 1 cells pass the check."""
+    box = (-1, 1, -1, 1, -1, 1)
+    o, k = np.zeros((0, 3)), np.zeros((0, 3))
+    for n in ((1, 1, 1 << 24), (1 << 24, 1, 1), (1, 1 << 24, 1)):
+        assert E.trace(box, n, np.ones(1), 1.0, 1, o, k)[0] == -1
+        assert E.trace(box, n, np.ones(1), 1.0, 0, o, k)[0] == 0
+    assert E.trace(box, (1, 1, (1 << 24) - 1), np.ones(1), 1.0, 1, o, k)[0] == 0
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("iso", [True, False])
 def test_peel(E, orc, W, prec, iso):
