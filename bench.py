@@ -67,12 +67,13 @@ BYTES_PER_DEPOSIT = 8
 BYTES_PER_PIXEL = 8
 BYTES_PER_RAY = 56
 COPY_BYTES = 1 << 30
-# kernels as rocprofv3 names them (FP32 path, regular grid, frames only)
+# kernels as rocprofv3 names them (FP32 path, regular grid, frames only; the
+# peel-ray walk with its LDS table of address terms)
 KERNELS = {
     "life_forward": "void mcrt::k_life<float, false, 0, false>(mcrt::RunParams)",
-    "peel_tau_forward": "void mcrt::k_peeltau<float, false, 0, false>(mcrt::PeelJobParams)",
+    "peel_tau_forward": "void mcrt::k_peeltau<float, false, 0, false, true>(mcrt::PeelJobParams)",
     "life_adjoint": "void mcrt::k_life<float, true, 0, false>(mcrt::RunParams)",
-    "peel_tau_adjoint": "void mcrt::k_peeltau<float, true, 0, false>(mcrt::PeelJobParams)",
+    "peel_tau_adjoint": "void mcrt::k_peeltau<float, true, 0, false, true>(mcrt::PeelJobParams)",
     "peel_deposit": "void mcrt::k_peeldep<float, 0, false>(mcrt::PeelJobParams)",
     "trace": "void mcrt::k_trace<float, 0>(mcrt::TraceParams)",
     "attached": "void mcrt::k_attached<float, 0>(mcrt::RunParams)",

@@ -184,6 +184,28 @@ MCRT_HD int brick_addr(const GridDev& G, const int i[3]) {
          ((i[0] & m0) | ((i[1] & m1) << G.lb[0]) | ((i[2] & m2) << (G.lb[0] + G.lb[1])));
 }
 
+// The bricked address is a sum of one term per axis (the fine parts occupy
+// disjoint bits): term a of index i.  Walk kernels on regular grids keep the
+// terms of every index in LDS and add three table entries per cell.
+MCRT_HD int brick_axis_term(const GridDev& G, int a, int i) {
+  const int sh = a == 0 ? 0 : (a == 1 ? G.lb[0] : G.lb[0] + G.lb[1]);
+  return (i >> G.lb[a]) * G.bstride[a] + ((i & ((1 << G.lb[a]) - 1)) << sh);
+}
+
+// The terms of a regular grid's three axes in one table (kept in LDS by the
+// peel-ray walk kernel): indices -1 .. n[0] of axis 0, then -1 .. n[1] of
+// axis 1 and -1 .. n[2] of axis 2, the outer two of each clamped to the edge
+// cells (a walk's indices leave their range by at most one, at its last
+// crossing, whose address is not used).
+constexpr int kLutCells = 4096;
+MCRT_HD int lut_cells(const GridDev& G) { return G.n[0] + G.n[1] + G.n[2] + 6; }
+MCRT_HD int lut_first(const GridDev& G, int a) { return a == 0 ? 0 : (a == 1 ? G.n[0] + 2 : G.n[0] + G.n[1] + 4); }
+MCRT_HD int lut_entry(const GridDev& G, int t) {
+  const int a = t < lut_first(G, 1) ? 0 : (t < lut_first(G, 2) ? 1 : 2);
+  const int i = t - lut_first(G, a) - 1;
+  return brick_axis_term(G, a, i < 0 ? 0 : (i >= G.n[a] ? G.n[a] - 1 : i));
+}
+
 // Cell indices of bricked address c; false for padding cells.
 MCRT_HD bool brick_cell(const GridDev& G, int c, int i[3]) {
   const int cb = G.lb[0] + G.lb[1] + G.lb[2];
@@ -922,6 +944,13 @@ MCRT_HD void tree_cross(Ray<R, T>& ry, const GridDev& G, int& cell, double& tend
   ry.i[0] = tree_find(G, r < 0 ? 0 : r, nx, ny, nz, sx, sy, sz);
 }
 
+// Whether an accessor brings the per-axis address terms of a regular grid
+// (Mem::kLut, with Mem::lut_addr(i): the bricked address of cell i).
+template <class M, class = void>
+struct HasLut : std::false_type {};
+template <class M>
+struct HasLut<M, std::void_t<decltype(M::kLut)>> : std::bool_constant<M::kLut> {};
+
 // LOAD = false skips the density loads (walks whose work does not depend on
 // the densities, such as the adjoint's peel-ray deposits).  The grid kind
 // comes from the accessor (Mem::kGrid).
@@ -965,7 +994,12 @@ MCRT_HD void ray_next_block(Ray<R, T>& ry, WalkBlock<D, R, T>& b, const GridDev&
     const T tm = fmin(tx, fmin(ty, tz));
     const bool live = !b.out;
     const bool ax = live && tx == tm, ay = live && ty == tm, az = live && tz == tm;
-    b.cell[d] = live ? brick_addr(G, ry.i) : b.cell[d > 0 ? d - 1 : 0];
+    if constexpr (GK == kGridRegular && HasLut<Mem>::value) {
+      const int c = M.lut_addr(ry.i);
+      b.cell[d] = live ? c : b.cell[d > 0 ? d - 1 : 0];
+    } else {
+      b.cell[d] = live ? brick_addr(G, ry.i) : b.cell[d > 0 ? d - 1 : 0];
+    }
     b.tend[d] = live ? tm : b.tend[d > 0 ? d - 1 : 0];
     ry.i[0] += ax ? ry.s[0] : 0;
     ry.i[1] += ay ? ry.s[1] : 0;

@@ -663,15 +663,20 @@ struct PeelJobParams {
 // Density loads for the optical-depth walk; deposits of the deposit walk go
 // into the workgroup's LDS table (open addressing, linear probing over at
 // most kProbes slots); a deposit that finds no slot goes straight to the
-// global tally.
-template <typename R, int GK>
+// global tally.  LUT: cell addresses from the per-axis address terms in LDS
+// (k_peeltau on regular grids whose three axes fit kLutCells entries).
+template <typename R, int GK, bool LUT = false>
 struct PeelJobMem {
   static constexpr int kGrid = GK;
+  static constexpr bool kLut = LUT;
   const R* __restrict__ rho_;
   int* tk;
   double* tv;
   double* grad;
+  const int* lut = nullptr;  // the table of lut_entry; axis a's index i at lut_first(G, a) + 1 + i
+  int o1 = 0, o2 = 0;        // lut_first(G, 1) + 1, lut_first(G, 2) + 1
   __device__ R rho(int c) const { return rho_[c]; }
+  __device__ int lut_addr(const int i[3]) const { return lut[i[0] + 1] + lut[o1 + i[1]] + lut[o2 + i[2]]; }
   __device__ void deposit(int cell, double v) const {
     const unsigned h = ((unsigned)cell * 2654435761u) >> (32 - kTableBits);
     for (int p = 0; p < kProbes; ++p) {
@@ -713,11 +718,25 @@ __device__ __forceinline__ void flush_images(bool& has, long long ii, double c, 
 // loads).  Forward: C = v e^-tau goes to the ray's pixel (flush_images).
 // Adjoint: q = (dL/dI) v e^-tau goes to the event scratch, and the deposit
 // weight -q kappa to the ray's sorted position (wlo, whi; 0: no deposit walk).
-template <typename R, bool ADJ, int GK, bool INST>
+//
+// LUT (regular grids): the workgroup first writes the table of per-axis
+// address terms (lut_entry) into LDS; the walk then adds three entries per
+// cell, a few vector instructions against the dozen of the shifts and
+// multiplies, in a kernel whose walk is bound by instruction issue.
+template <typename R, bool ADJ, int GK, bool INST, bool LUT>
 __global__ void __launch_bounds__(kBlock) k_peeltau(const PeelJobParams P) {
   __shared__ unsigned long long slots[kWavesPerBlock][2];
+  __shared__ int lut[LUT ? kLutCells : 1];
   unsigned long long* res = wave_reservoir(slots);
-  const PeelJobMem<R, GK> M{static_cast<const R*>(P.rho), nullptr, nullptr, P.grad};
+  PeelJobMem<R, GK, LUT> M{static_cast<const R*>(P.rho), nullptr, nullptr, P.grad};
+  if constexpr (LUT) {
+    const int tot = lut_cells(P.G);  // the launch checks tot <= kLutCells
+    for (int t = (int)threadIdx.x; t < tot; t += (int)blockDim.x) lut[t] = lut_entry(P.G, t);
+    __syncthreads();
+    M.lut = lut;
+    M.o1 = lut_first(P.G, 1) + 1;
+    M.o2 = lut_first(P.G, 2) + 1;
+  }
   const unsigned n_jobs = *P.n_sorted;
   unsigned long long nx = 0;
   Ray<R> ry;
@@ -1403,9 +1422,12 @@ template <typename R, bool ADJ, int GK, bool INST>
 int walk_peel_jobs(const PeelJobParams& J, hipStream_t st, Spans& sp) {
   if (!J.direct_w) {  // an adjoint from a tape has every ray's weight already: no optical-depth walk
     int nblk = 0;
-    if (int e = persistent_grid(k_peeltau<R, ADJ, GK, INST>, 0, &nblk)) return e;
+    void (*kern)(PeelJobParams) = k_peeltau<R, ADJ, GK, INST, false>;
+    if constexpr (GK == kGridRegular)
+      if (lut_cells(J.G) <= kLutCells) kern = k_peeltau<R, ADJ, GK, INST, true>;
+    if (int e = persistent_grid(kern, 0, &nblk)) return e;
     if (int e = sp.mark(kSpanPeel, st)) return e;
-    hipLaunchKernelGGL((k_peeltau<R, ADJ, GK, INST>), dim3(nblk), dim3(kBlock), 0, st, J);
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(kBlock), 0, st, J);
     if (int e = sp.mark(kSpanPeel, st)) return e;
   }
   if (ADJ) {

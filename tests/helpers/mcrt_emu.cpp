@@ -286,6 +286,38 @@ struct HostLifeMem {
   }
 };
 
+// The queued peel walk's accessor on regular grids: densities through the
+// life-cycle accessor, cell addresses from the table of per-axis address
+// terms that the peel-ray walk kernel keeps in LDS (lut_entry), every table
+// index checked; brick_addr where the table would not fit, as the library
+// then launches the kernel without it.
+template <typename R, int GK, bool INST>
+struct HostLutMem {
+  static constexpr int kGrid = GK;
+  static constexpr bool kLut = GK == kGridRegular;
+  const HostLifeMem<R, GK, INST>& M;
+  const GridDev& G;
+  std::vector<int> lut;
+  HostLutMem(const HostLifeMem<R, GK, INST>& m, const GridDev& g) : M(m), G(g) {
+    if (kLut && lut_cells(G) <= kLutCells) {
+      lut.resize(lut_cells(G));
+      for (int t = 0; t < lut_cells(G); ++t) lut[t] = lut_entry(G, t);
+    }
+  }
+  R rho(int c) const { return M.rho(c); }
+  int lut_addr(const int i[3]) const {
+    if (lut.empty()) return brick_addr(G, i);
+    int c = 0;
+    for (int a = 0; a < 3; ++a) {
+      EMU_CHECK(i[a] >= -1 && i[a] <= G.n[a], "axis index for the address table", i[a], G.n[a] + 1);
+      const int t = lut_first(G, a) + 1 + i[a];
+      EMU_CHECK(t >= 0 && t < (int)lut.size(), "address table", t, lut.size());
+      c += lut[t];
+    }
+    return c;
+  }
+};
+
 // The kernels' outer loop for one wavefront of `wave` lanes: events for
 // every waiting lane, then lockstep crossings until `batch` lanes wait.
 template <class LaneT, class Events, class Step, class Ncell>
@@ -386,6 +418,7 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, GK, INST>& M, const RunParams& P
     }
   }
   HostBundleMem<GK> D{P.G, grad};
+  HostLutMem<R, GK, INST> LM(M, P.G);
   unsigned long long nx = 0;
   deps = 0;
   for (unsigned long long qi = 0; qi < n_valid; ++qi) {
@@ -409,7 +442,7 @@ unsigned long long emu_peel_jobs(HostLifeMem<R, GK, INST>& M, const RunParams& P
       }
       const R kap = (R)M.lam((int)J.lam).kappa;
       while (ry.active) {
-        nx += tau_step<R, HostLifeMem<R, GK, INST>, INST>(ry, P.G, kap, M);
+        nx += tau_step<R, HostLutMem<R, GK, INST>, INST>(ry, P.G, kap, LM);
         if (++steps > cap_steps) throw Violation("a peel-job walk exceeded the grid's crossing bound");
       }
       const double C = J.v * exp(-(double)ry.tau);

@@ -341,6 +341,37 @@ def test_forward_peel_queue_long_run(B, orc, W):
     check(img_q, img_o, 1e-10, "queued images against the oracle", _say)
 
 
+@pytest.mark.parametrize("nx", [4084, 4085])
+def test_peel_queue_address_table_edge(B, orc, W, nx):
+    # the queued peel walk adds per-axis address terms from an LDS table when
+    # the three axes fit it (nx + 2 + 2 + 6 <= 4096 entries: nx = 4084) and
+    # computes addresses otherwise (4085): both against the inline walks,
+    # which never use the table, and the oracle, FP64 and FP32.  A thin slab
+    # seen along +x and -x: every peel ray walks about half of the long axis
+    # (tau about 5 from the centre to either end)
+    _say("queued peel walk, address table edge, nx = %d" % nx)
+    n = (nx, 2, 2)
+    frames = [W.frame(10.0, 90.0, 8, 8, 0.012, 0.012, azim=az) for az in (0.0, 180.0)]
+    for prec in (0, 1):
+        prob = W.small_problem(n=n, box=(-1.0, 1.0, -0.01, 0.01, -0.01, 0.01),
+                               rho=W.lognormal_density(n, 0.5, seed=67), kappa=5.0, albedo=0.6, g=0.4,
+                               sources=[W.point((0.0, 0.0, 0.0))], detectors=frames, n_packages=20_000,
+                               precision=prec, flags=W.FLAG_PEEL_EMIT | W.FLAG_PEEL_SCAT)
+        runs = {}
+        for q in (-1, 0):
+            images, _, st = B.render(prob, peel_queue=q)
+            runs[q] = (images.cpu().numpy(), st)
+        (img_i, st_i), (img_q, st_q) = runs[-1], runs[0]
+        assert st_q["x_queue"] > 0 and st_i["x_queue"] == 0
+        for key in ("x_path", "x_locate", "events", "peels", "packages"):
+            assert st_q[key] == st_i[key], (key, st_q[key], st_i[key])
+        slack = 0 if prec == 0 else 1e-5 * st_i["x_peel"] + 2
+        assert abs(st_q["x_peel"] - st_i["x_peel"]) <= slack, (st_q["x_peel"], st_i["x_peel"])
+        check(img_q, img_i, 1e-12 if prec == 0 else 2e-5, "queued against inline images", _say)
+        img_o, _, _ = orc.run(prob, threads=16)
+        check(img_q, img_o, 1e-12 if prec == 0 else 2e-5, "queued images against the oracle", _say)
+
+
 def test_backward_peel_queue_modes(B, orc, W):
     # peel-ray deposits walked inline, queued and bundled, or queued until a
     # tiny queue is full: the same gradient and the same crossing counts
