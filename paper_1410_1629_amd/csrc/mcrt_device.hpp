@@ -76,8 +76,11 @@ constexpr long long kMallBytes = 256ll << 20;
 // the trace and peel-off entry points -- refill a lane with the next ray once
 // this many of the wavefront's lanes have finished: measured on the spiral,
 // 48 against 16 saves 4 ms of the forward's queue kernels, 6 ms of the
-// adjoint's, and 6% of a trace over 4e6 random rays.
-constexpr int kBatchQueue = 48;
+// adjoint's, and 6% of a trace over 4e6 random rays.  The optical-depth
+// walk over a grid whose densities exceed the MALL takes 24 (clumpy 512^3
+// disk: 423.5 ms at 16, 20 and 24 against 435.7 at 48; on the spiral 48
+// stays best, 30.8 against 31.9 ms at 24).
+constexpr int kBatchQueue = 48, kBatchQueueHbm = 24;
 
 // ---------------------------------------------------------------------------
 // Problem data, prepared by the host in FP64.

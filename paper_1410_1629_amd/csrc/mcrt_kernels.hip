@@ -1425,9 +1425,11 @@ int walk_peel_jobs(const PeelJobParams& J, hipStream_t st, Spans& sp) {
     void (*kern)(PeelJobParams) = k_peeltau<R, ADJ, GK, INST, false>;
     if constexpr (GK == kGridRegular)
       if (lut_cells(J.G) <= kLutCells) kern = k_peeltau<R, ADJ, GK, INST, true>;
+    PeelJobParams Jt = J;
+    if ((long long)J.G.ncell_pad * (long long)sizeof(R) > kMallBytes) Jt.batch = kBatchQueueHbm;
     if (int e = persistent_grid(kern, 0, &nblk)) return e;
     if (int e = sp.mark(kSpanPeel, st)) return e;
-    hipLaunchKernelGGL(kern, dim3(nblk), dim3(kBlock), 0, st, J);
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(kBlock), 0, st, Jt);
     if (int e = sp.mark(kSpanPeel, st)) return e;
   }
   if (ADJ) {
