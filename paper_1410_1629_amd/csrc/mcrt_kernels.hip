@@ -1583,11 +1583,12 @@ int launch_life(const RunParams& P, bool inst, int nblk, hipStream_t st) {
 // memory).  Every chunk costs its launches' tails (a persistent kernel ends
 // with few waves busy), so the budgets are large: the 1e7-package spiral
 // runs in one chunk of each.  A larger chunk also puts more rays into each
-// pixel's run of the sorted queue, where the peel walks share more cells:
-// the clumpy 512^3 forward (1e8 packages) takes 1920 / 1829 / 1799 / 1786 ms
-// with a queue of 8 / 16 / 24 / 32 GiB (14 / 7 / 5 / 4 chunks; peel walks
-// 482 / 422 / 401 / 391 ms), while with 48 and 64 GiB the life kernel's
-// queue stores slow it from 1322 to 1716 and 2216 ms.
+// pixel's run of the sorted queue, where the peel walks share more cells,
+// but spreads the jobs that the walks read in sorted order over a larger
+// array: the clumpy 512^3 forward (1e8 packages) takes 1920 / 1829 / 1799 /
+// 1786 ms with a queue of 8 / 16 / 24 / 32 GiB (14 / 7 / 5 / 4 chunks; peel
+// walks 482 / 422 / 401 / 391 ms), and 1829 / 1863 ms in 3 / 2 chunks (peel
+// walks 444 / 496 ms, measured with the capacity limit below raised).
 constexpr int kEventsKept = 32;
 constexpr size_t kScratchBytes = size_t(1) << 34, kQueueBytes = size_t(1) << 35;
 
