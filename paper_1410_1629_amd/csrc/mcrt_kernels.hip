@@ -716,7 +716,7 @@ __device__ __forceinline__ void flush_images(bool& has, long long ii, double c, 
 }
 
 // The optical-depth walks of the sorted queue, one ray per lane in a lean
-// persistent loop (no LDS table, so many waves per SIMD hide the density
+// persistent loop (no deposit table, so many waves per SIMD hide the density
 // loads).  Forward: C = v e^-tau goes to the ray's pixel (flush_images).
 // Adjoint: q = (dL/dI) v e^-tau goes to the event scratch, and the deposit
 // weight -q kappa to the ray's sorted position (wlo, whi; 0: no deposit walk).
