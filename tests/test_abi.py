@@ -89,7 +89,7 @@ def _call_run(lib, B, prob, **over):
                                   "planes_order", "planes_ends", "planes_nan", "tree_unreached", "tree_twice",
                                   "tree_split_outside", "tree_cell_twice", "tree_and_planes", "tree_leaf_count",
                                   "albedo", "g", "kappa", "lum", "n_det", "det_pixels", "det_distance",
-                                  "n_src", "src_kind", "src_scale"])
+                                  "n_src", "src_kind", "src_scale", "fp32_axis"])
 def test_invalid_arguments_are_rejected(lib, B, W, case):
     prob = W.small_problem(n=(4, 4, 4), n_packages=100)
     over = {}
@@ -166,6 +166,10 @@ def test_invalid_arguments_are_rejected(lib, B, W, case):
         prob["sources"] = [dict(W.point(), kind="ring")]
     elif case == "src_scale":
         prob["sources"] = [W.expdisk(0.0, 0.1)]
+    elif case == "fp32_axis":
+        # FP32 walks count crossed planes in FP32: 2^24 cells along an axis are refused
+        prob["n"] = (1, 1, 1 << 24)
+        over["precision"] = 1
     if case == "src_kind":
         # the binding maps kinds to the enum; pass an unknown value directly
         pr = B._Problem(dict(prob, sources=[W.point()]))
@@ -178,6 +182,8 @@ def test_invalid_arguments_are_rejected(lib, B, W, case):
         rc = _call_run(lib, B, prob, **over)
     assert rc == B.EINVAL, (case, rc)
     assert lib.mcrt_last_error().decode(), case
+    if case == "fp32_axis":
+        assert "2^24" in lib.mcrt_last_error().decode()
 
 
 def test_backward_rejects_missing_gradients(lib, B, W):
