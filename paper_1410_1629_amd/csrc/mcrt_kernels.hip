@@ -1370,8 +1370,10 @@ struct PeelQueue {
 
 // Capacity per chunk of `chunk` packages: mcrt_opts.peel_queue, or by
 // default 8 peel rays per package and frame (the typical package has fewer
-// events; rays beyond the capacity are walked inline), at most 2^28 and a
-// quarter of the free device memory.
+// events; rays beyond the capacity are walked inline), at most 2^31 (the
+// sort's positions are 32-bit) and a quarter of the free device memory.  The
+// chunk follows the queue's byte budget, so the default capacity keeps its 8
+// rays per package and frame.
 int make_peel_queue(const mcrt_opts& o, const host::Prepared& pr, unsigned long long chunk, hipStream_t st,
                     PeelQueue& q) {
   q.st = st;
@@ -1383,7 +1385,7 @@ int make_peel_queue(const mcrt_opts& o, const host::Prepared& pr, unsigned long 
     cap = (unsigned long long)o.peel_queue;
   } else {
     cap = chunk * (unsigned long long)pr.P.n_det * 8ull;
-    cap = std::min(std::max(cap, 1ull << 16), 1ull << 28);
+    cap = std::min(std::max(cap, 1ull << 16), 1ull << 31);
     size_t free_b = 0, total_b = 0;
     HIPCHK(hipMemGetInfo(&free_b, &total_b));
     cap = std::min<unsigned long long>(cap, free_b / 4 / kQueueBytesPerRay);
@@ -1590,7 +1592,7 @@ int launch_life(const RunParams& P, bool inst, int nblk, hipStream_t st) {
 // array: the clumpy 512^3 forward (1e8 packages) takes 1920 / 1829 / 1799 /
 // 1786 ms with a queue of 8 / 16 / 24 / 32 GiB (14 / 7 / 5 / 4 chunks; peel
 // walks 482 / 422 / 401 / 391 ms), and 1829 / 1863 ms in 3 / 2 chunks (peel
-// walks 444 / 496 ms, measured with the capacity limit below raised).
+// walks 444 / 496 ms).
 constexpr int kEventsKept = 32;
 constexpr size_t kScratchBytes = size_t(1) << 34, kQueueBytes = size_t(1) << 35;
 
